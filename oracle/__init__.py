@@ -1,0 +1,14 @@
+"""TEST INFRASTRUCTURE — the CPU oracle (complex128, single-threaded).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It is an independent statevector
+simulator written from the definitions in the paper (Sec. "Foundations
+Recap": gates as local contractions, E = <psi|H|psi> with H a Pauli sum,
+reverse-mode gradient / parameter-shift rule); it shares no code with the HIP
+library.  Pins that tie it to the mathematics live in tests/test_oracle_pins.py.
+
+Parity status: every function here is pinned (closed forms, brute-force
+Kronecker products for n <= 6, exact diagonalisation against the free-fermion
+closed form, parameter shift vs adjoint, finite differences).
+"""
+from .api import *  # noqa: F401,F403

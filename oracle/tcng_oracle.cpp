@@ -1,0 +1,524 @@
+// TEST INFRASTRUCTURE — the CPU oracle.  Only the test-suite, the smoke check
+// and the benchmark's CPU-baseline leg may call this code; the product path
+// never does.  It shares no code, header or table with the HIP library.
+//
+// A plain, single-threaded complex128 statevector simulator written from the
+// definitions (TensorCircuit-NG paper, Sec. "Foundations Recap"):
+//   * a circuit prepares |psi(theta)> = U_D ... U_1 |psi_0>, every gate being a
+//     local contraction of a 2^k x 2^k matrix with k legs of the state;
+//   * the VQE objective is E(theta) = <psi(theta)| H |psi(theta)> with
+//     H = sum_k c_k P_k a sum of Pauli strings (expectation_ps, real part);
+//   * the gradient is the reverse-mode derivative of E (the paper's AD), here
+//     written out as the textbook adjoint recursion, and independently as the
+//     parameter-shift rule that the paper quotes as the 2k-evaluation
+//     alternative.
+// Every 2^n-term sum is pairwise (recursive halving), never a running sum.
+// Compiled with -O2 and no fast-math: IEEE round-to-nearest throughout.
+//
+// Conventions (readings where the paper is silent):
+//   * amplitude index bit q <-> qubit q (qubit 0 is the least significant bit);
+//   * for a k-qubit gate on qubits (q_0 .. q_{k-1}) the local matrix index is
+//     a = sum_t bit_{q_t} * 2^(k-1-t), i.e. q_0 is the most significant bit;
+//   * R_P(theta) = exp(-i theta P / 2); RZZ = exp(-i theta Z(x)Z / 2);
+//   * fSim(theta, phi) = [[1,0,0,0],[0,cos,-i sin,0],[0,-i sin,cos,0],[0,0,0,e^{-i phi}]];
+//   * Pauli codes 0=I, 1=X, 2=Y, 3=Z.
+#include <complex>
+#include <vector>
+#include <cstdint>
+#include <cmath>
+#include <cstring>
+
+namespace {
+
+using cplx = std::complex<double>;
+const cplx I1(0.0, 1.0);
+
+enum Kind { RX = 0, RY, RZ, H, X, Y, Z, S, CNOT, CZ, RZZ, FSIM, U1, U2, N_KINDS };
+
+struct Gate { int kind, q0, q1, p0, p1, mat; };
+
+int arity(int kind) {
+    switch (kind) {
+        case CNOT: case CZ: case RZZ: case FSIM: case U2: return 2;
+        default: return 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pairwise summation over an index range [lo, hi)
+// ---------------------------------------------------------------------------
+template <class F>
+cplx pairwise_sum(const F& f, uint64_t lo, uint64_t hi) {
+    if (hi - lo <= 16) {
+        cplx s = 0.0;
+        for (uint64_t i = lo; i < hi; ++i) s += f(i);
+        return s;
+    }
+    uint64_t mid = lo + (hi - lo) / 2;
+    return pairwise_sum(f, lo, mid) + pairwise_sum(f, mid, hi);
+}
+
+// ---------------------------------------------------------------------------
+// gate matrices, written from their definitions
+// ---------------------------------------------------------------------------
+struct Mat4 { cplx m[4][4]; };   // k = 1 uses the top-left 2x2 block
+
+Mat4 zero4() { Mat4 a; for (auto& r : a.m) for (auto& v : r) v = 0.0; return a; }
+
+// exp(-i t P/2) for P in {X, Y, Z}
+Mat4 rot1(int pauli, double t) {
+    Mat4 a = zero4();
+    double c = std::cos(t / 2), s = std::sin(t / 2);
+    if (pauli == 1) { a.m[0][0] = c; a.m[0][1] = -I1 * s; a.m[1][0] = -I1 * s; a.m[1][1] = c; }
+    if (pauli == 2) { a.m[0][0] = c; a.m[0][1] = -s;      a.m[1][0] = s;       a.m[1][1] = c; }
+    if (pauli == 3) { a.m[0][0] = std::exp(-I1 * (t / 2)); a.m[1][1] = std::exp(I1 * (t / 2)); }
+    return a;
+}
+
+Mat4 gate_matrix(const Gate& g, const double* params, const cplx* mats) {
+    Mat4 a = zero4();
+    const double r2 = 1.0 / std::sqrt(2.0);
+    switch (g.kind) {
+        case RX: return rot1(1, params[g.p0]);
+        case RY: return rot1(2, params[g.p0]);
+        case RZ: return rot1(3, params[g.p0]);
+        case H:  a.m[0][0] = r2; a.m[0][1] = r2; a.m[1][0] = r2; a.m[1][1] = -r2; return a;
+        case X:  a.m[0][1] = 1.0; a.m[1][0] = 1.0; return a;
+        case Y:  a.m[0][1] = -I1; a.m[1][0] = I1; return a;
+        case Z:  a.m[0][0] = 1.0; a.m[1][1] = -1.0; return a;
+        case S:  a.m[0][0] = 1.0; a.m[1][1] = I1; return a;
+        case CNOT:  // control = q0 (MSB), target = q1
+            a.m[0][0] = 1.0; a.m[1][1] = 1.0; a.m[2][3] = 1.0; a.m[3][2] = 1.0; return a;
+        case CZ: a.m[0][0] = 1.0; a.m[1][1] = 1.0; a.m[2][2] = 1.0; a.m[3][3] = -1.0; return a;
+        case RZZ: {
+            double t = params[g.p0];
+            cplx em = std::exp(-I1 * (t / 2)), ep = std::exp(I1 * (t / 2));
+            a.m[0][0] = em; a.m[1][1] = ep; a.m[2][2] = ep; a.m[3][3] = em; return a;
+        }
+        case FSIM: {
+            double t = params[g.p0], p = params[g.p1];
+            a.m[0][0] = 1.0;
+            a.m[1][1] = std::cos(t); a.m[1][2] = -I1 * std::sin(t);
+            a.m[2][1] = -I1 * std::sin(t); a.m[2][2] = std::cos(t);
+            a.m[3][3] = std::exp(-I1 * p);
+            return a;
+        }
+        case U1: case U2:
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) a.m[i][j] = mats[16 * g.mat + 4 * i + j];
+            return a;
+    }
+    return a;
+}
+
+// d U / d(param role r) for the parameterised kinds, differentiated by hand
+// from the closed forms above (r = 0: params[p0], r = 1: params[p1]).
+Mat4 gate_matrix_derivative(const Gate& g, int r, const double* params) {
+    Mat4 a = zero4();
+    switch (g.kind) {
+        case RX: { double t = params[g.p0], c = std::cos(t / 2), s = std::sin(t / 2);
+            a.m[0][0] = -s / 2; a.m[0][1] = -I1 * (c / 2); a.m[1][0] = -I1 * (c / 2); a.m[1][1] = -s / 2;
+            return a; }
+        case RY: { double t = params[g.p0], c = std::cos(t / 2), s = std::sin(t / 2);
+            a.m[0][0] = -s / 2; a.m[0][1] = -c / 2; a.m[1][0] = c / 2; a.m[1][1] = -s / 2;
+            return a; }
+        case RZ: { double t = params[g.p0];
+            a.m[0][0] = (-I1 / 2.0) * std::exp(-I1 * (t / 2));
+            a.m[1][1] = (I1 / 2.0) * std::exp(I1 * (t / 2));
+            return a; }
+        case RZZ: { double t = params[g.p0];
+            cplx dm = (-I1 / 2.0) * std::exp(-I1 * (t / 2)), dp = (I1 / 2.0) * std::exp(I1 * (t / 2));
+            a.m[0][0] = dm; a.m[1][1] = dp; a.m[2][2] = dp; a.m[3][3] = dm;
+            return a; }
+        case FSIM: {
+            double t = params[g.p0], p = params[g.p1];
+            if (r == 0) {
+                a.m[1][1] = -std::sin(t); a.m[1][2] = -I1 * std::cos(t);
+                a.m[2][1] = -I1 * std::cos(t); a.m[2][2] = -std::sin(t);
+            } else {
+                a.m[3][3] = -I1 * std::exp(-I1 * p);
+            }
+            return a;
+        }
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// gate application: psi'_j = sum_b U[a(j)][b] psi_{j with gate bits := b}
+// ---------------------------------------------------------------------------
+void apply_matrix(int n, std::vector<cplx>& psi, const int* q, int k, const Mat4& U) {
+    const uint64_t dim = uint64_t(1) << n;
+    const int kdim = 1 << k;
+    std::vector<cplx> out(dim);
+    for (uint64_t j = 0; j < dim; ++j) {
+        int a = 0;
+        for (int t = 0; t < k; ++t) a |= int((j >> q[t]) & 1) << (k - 1 - t);
+        uint64_t rest = j;
+        for (int t = 0; t < k; ++t) rest &= ~(uint64_t(1) << q[t]);
+        cplx s = 0.0;
+        for (int b = 0; b < kdim; ++b) {
+            uint64_t src = rest;
+            for (int t = 0; t < k; ++t) src |= uint64_t((b >> (k - 1 - t)) & 1) << q[t];
+            s += U.m[a][b] * psi[src];
+        }
+        out[j] = s;
+    }
+    psi.swap(out);
+}
+
+Mat4 dagger(const Mat4& U) {
+    Mat4 a;
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) a.m[i][j] = std::conj(U.m[j][i]);
+    return a;
+}
+
+Mat4 matmul(const Mat4& A, const Mat4& B, int kdim) {
+    Mat4 c = zero4();
+    for (int i = 0; i < kdim; ++i)
+        for (int j = 0; j < kdim; ++j)
+            for (int l = 0; l < kdim; ++l) c.m[i][j] += A.m[i][l] * B.m[l][j];
+    return c;
+}
+
+void apply_gate(int n, std::vector<cplx>& psi, const Gate& g, const Mat4& U) {
+    int q[2] = {g.q0, g.q1};
+    apply_matrix(n, psi, q, arity(g.kind), U);
+}
+
+// ---------------------------------------------------------------------------
+// Pauli strings, applied qubit by qubit from the single-qubit actions
+//   X|b> = |1-b>,  Y|b> = i (-1)^b |1-b>,  Z|b> = (-1)^b |b>.
+// P|k> = phase(k) |image(k)>.
+// ---------------------------------------------------------------------------
+struct PauliTerm { std::vector<std::pair<int, int>> ops; double coeff; };  // (qubit, code)
+
+void pauli_on_basis(const PauliTerm& t, uint64_t k, uint64_t& image, cplx& phase) {
+    image = k;
+    phase = 1.0;
+    for (auto& op : t.ops) {
+        int b = int((k >> op.first) & 1);
+        if (op.second == 1) { image ^= uint64_t(1) << op.first; }
+        else if (op.second == 2) { image ^= uint64_t(1) << op.first; phase *= (b ? -I1 : I1); }
+        else if (op.second == 3) { if (b) phase = -phase; }
+    }
+}
+
+std::vector<PauliTerm> read_terms(int n, const uint8_t* codes, const double* coeffs, int T) {
+    std::vector<PauliTerm> terms(T);
+    for (int t = 0; t < T; ++t) {
+        terms[t].coeff = coeffs[t];
+        for (int q = 0; q < n; ++q)
+            if (codes[size_t(t) * n + q]) terms[t].ops.push_back({q, int(codes[size_t(t) * n + q])});
+    }
+    return terms;
+}
+
+// <psi|H|psi> (complex; its imaginary part is a check that should vanish)
+cplx expectation(int n, const std::vector<cplx>& psi, const std::vector<PauliTerm>& terms) {
+    const uint64_t dim = uint64_t(1) << n;
+    cplx e = 0.0;
+    for (auto& t : terms) {
+        auto f = [&](uint64_t k) {
+            uint64_t img; cplx ph;
+            pauli_on_basis(t, k, img, ph);
+            return std::conj(psi[img]) * ph * psi[k];
+        };
+        e += t.coeff * pairwise_sum(f, 0, dim);
+    }
+    return e;
+}
+
+// lambda = H psi
+std::vector<cplx> apply_hamiltonian(int n, const std::vector<cplx>& psi, const std::vector<PauliTerm>& terms) {
+    const uint64_t dim = uint64_t(1) << n;
+    std::vector<cplx> lam(dim, 0.0);
+    for (auto& t : terms)
+        for (uint64_t k = 0; k < dim; ++k) {
+            uint64_t img; cplx ph;
+            pauli_on_basis(t, k, img, ph);
+            lam[img] += t.coeff * ph * psi[k];
+        }
+    return lam;
+}
+
+cplx inner(const std::vector<cplx>& a, const std::vector<cplx>& b) {   // <a|b>
+    auto f = [&](uint64_t k) { return std::conj(a[k]) * b[k]; };
+    return pairwise_sum(f, 0, a.size());
+}
+
+std::vector<Gate> read_gates(const int32_t* g, int G) {
+    std::vector<Gate> out(G);
+    for (int i = 0; i < G; ++i)
+        out[i] = Gate{g[6 * i], g[6 * i + 1], g[6 * i + 2], g[6 * i + 3], g[6 * i + 4], g[6 * i + 5]};
+    return out;
+}
+
+std::vector<cplx> read_mats(const double* mats, int n_mats) {
+    std::vector<cplx> m(size_t(n_mats) * 16);
+    for (size_t i = 0; i < m.size(); ++i) m[i] = cplx(mats[2 * i], mats[2 * i + 1]);
+    return m;
+}
+
+std::vector<cplx> initial_state(int n, const double* init) {
+    const uint64_t dim = uint64_t(1) << n;
+    std::vector<cplx> psi(dim, 0.0);
+    if (init) for (uint64_t k = 0; k < dim; ++k) psi[k] = cplx(init[2 * k], init[2 * k + 1]);
+    else psi[0] = 1.0;
+    return psi;
+}
+
+void write_state(const std::vector<cplx>& psi, double* out) {
+    for (size_t k = 0; k < psi.size(); ++k) { out[2 * k] = psi[k].real(); out[2 * k + 1] = psi[k].imag(); }
+}
+
+std::vector<cplx> forward(int n, const std::vector<Gate>& gates, const double* params,
+                          const std::vector<cplx>& mats, const double* init) {
+    std::vector<cplx> psi = initial_state(n, init);
+    for (auto& g : gates) apply_gate(n, psi, g, gate_matrix(g, params, mats.data()));
+    return psi;
+}
+
+// two-qubit Pauli sigma_a (x) sigma_b in the local basis (a on the MSB)
+Mat4 pauli2(int a, int b) {
+    Mat4 s[4];
+    for (auto& m : s) m = zero4();
+    s[0].m[0][0] = 1.0; s[0].m[1][1] = 1.0;
+    s[1].m[0][1] = 1.0; s[1].m[1][0] = 1.0;
+    s[2].m[0][1] = -I1; s[2].m[1][0] = I1;
+    s[3].m[0][0] = 1.0; s[3].m[1][1] = -1.0;
+    Mat4 r = zero4();
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.m[i][j] = s[a].m[i >> 1][j >> 1] * s[b].m[i & 1][j & 1];
+    return r;
+}
+
+// exp(-i t P/2) for a two-qubit Pauli P (P^2 = I): cos(t/2) I - i sin(t/2) P
+Mat4 pauli2_rotation(int a, int b, double t) {
+    Mat4 P = pauli2(a, b), r = zero4();
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.m[i][j] = (i == j ? std::cos(t / 2) : 0.0) - I1 * std::sin(t / 2) * P.m[i][j];
+    return r;
+}
+
+// E for the circuit with gate `which` replaced by L * U_which (L a 4x4 / 2x2 matrix)
+double energy_with_left_factor(int n, const std::vector<Gate>& gates, const double* params,
+                               const std::vector<cplx>& mats, const double* init,
+                               const std::vector<PauliTerm>& terms, int which, const Mat4& L) {
+    std::vector<cplx> psi = initial_state(n, init);
+    for (int i = 0; i < int(gates.size()); ++i) {
+        Mat4 U = gate_matrix(gates[i], params, mats.data());
+        if (i == which) U = matmul(L, U, 1 << arity(gates[i].kind));
+        apply_gate(n, psi, gates[i], U);
+    }
+    return expectation(n, psi, terms).real();
+}
+
+double energy_with_param(int n, const std::vector<Gate>& gates, std::vector<double> params_shifted,
+                         const std::vector<cplx>& mats, const double* init,
+                         const std::vector<PauliTerm>& terms, int which, int role, double shift) {
+    // shift only the angle of gate `which` (role 0: p0, role 1: p1), even if
+    // other gates share the same parameter: copy it into a private slot
+    std::vector<Gate> g2 = gates;
+    int p = role == 0 ? gates[which].p0 : gates[which].p1;
+    params_shifted.push_back(params_shifted[p] + shift);
+    if (role == 0) g2[which].p0 = int(params_shifted.size()) - 1;
+    else g2[which].p1 = int(params_shifted.size()) - 1;
+    std::vector<cplx> psi = forward(n, g2, params_shifted.data(), mats, init);
+    return expectation(n, psi, terms).real();
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_version() { return 1; }
+
+// State after the circuit.  init: nullable interleaved complex [2^n] (else |0..0>).
+int orc_run(int n, const int32_t* gates, int G, const double* params, const double* mats, int n_mats,
+            const double* init, double* out) {
+    auto g = read_gates(gates, G);
+    auto m = read_mats(mats, n_mats);
+    write_state(forward(n, g, params, m, init), out);
+    return 0;
+}
+
+// Apply one k-qubit matrix (row-major 2^k x 2^k, interleaved complex) in place.
+int orc_apply_matrix(int n, double* state, const int32_t* qubits, int k, const double* U) {
+    if (k < 1 || k > 2) return 1;
+    std::vector<cplx> psi = initial_state(n, state);
+    Mat4 M = zero4();
+    int kd = 1 << k;
+    for (int i = 0; i < kd; ++i)
+        for (int j = 0; j < kd; ++j) M.m[i][j] = cplx(U[2 * (kd * i + j)], U[2 * (kd * i + j) + 1]);
+    apply_matrix(n, psi, qubits, k, M);
+    write_state(psi, state);
+    return 0;
+}
+
+// Matrix of one gate record (4x4 interleaved; one-qubit gates fill the top-left 2x2).
+int orc_gate_matrix(const int32_t* gate, const double* params, const double* mats, int n_mats, double* out) {
+    Gate g{gate[0], gate[1], gate[2], gate[3], gate[4], gate[5]};
+    auto m = read_mats(mats, n_mats);
+    Mat4 U = gate_matrix(g, params, m.data());
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) { out[2 * (4 * i + j)] = U.m[i][j].real(); out[2 * (4 * i + j) + 1] = U.m[i][j].imag(); }
+    return 0;
+}
+
+// E = <psi|H|psi>; out[0] = Re, out[1] = Im (should be ~0).
+int orc_expect(int n, const double* state, const uint8_t* codes, const double* coeffs, int T, double* out) {
+    std::vector<cplx> psi = initial_state(n, state);
+    cplx e = expectation(n, psi, read_terms(n, codes, coeffs, T));
+    out[0] = e.real(); out[1] = e.imag();
+    return 0;
+}
+
+// lambda = H psi
+int orc_apply_hamiltonian(int n, const double* state, const uint8_t* codes, const double* coeffs, int T, double* out) {
+    std::vector<cplx> psi = initial_state(n, state);
+    write_state(apply_hamiltonian(n, psi, read_terms(n, codes, coeffs, T)), out);
+    return 0;
+}
+
+double orc_norm2(int n, const double* state) {
+    std::vector<cplx> psi = initial_state(n, state);
+    return inner(psi, psi).real();
+}
+
+// Adjoint-method value and gradient.
+//   energy[0] = Re E, energy[1] = Im E
+//   grad[n_params]       : dE/dtheta_p summed over every gate using theta_p
+//   gate_cot (nullable)  : per gate the 4x4 cotangent G_g = sum_rest lambda_g phi_{g-1}^dagger
+//                          (lambda_g = U_{g+1}^dag..U_D^dag H psi_D, phi_{g-1} the state before
+//                          gate g), so that dE = 2 Re tr(G_g^dag dU_g); one-qubit gates fill 2x2
+//   lie (nullable)       : per gate 15 values dE/dalpha_k for U_g -> exp(-i alpha_k P_k/2) U_g,
+//                          P_k = sigma_a (x) sigma_b, k = 4a + b - 1 (two-qubit gates only)
+//   final_state (nullable): psi_D
+int orc_expect_grad(int n, const int32_t* gates, int G, const double* params, int n_params,
+                    const double* mats, int n_mats, const uint8_t* codes, const double* coeffs, int T,
+                    const double* init, double* energy, double* grad, double* gate_cot, double* lie,
+                    double* final_state) {
+    auto g = read_gates(gates, G);
+    auto m = read_mats(mats, n_mats);
+    auto terms = read_terms(n, codes, coeffs, T);
+    std::vector<cplx> psi = forward(n, g, params, m, init);
+    if (final_state) write_state(psi, final_state);
+    std::vector<cplx> lam = apply_hamiltonian(n, psi, terms);
+    cplx e = inner(psi, lam);
+    energy[0] = e.real(); energy[1] = e.imag();
+    for (int p = 0; p < n_params; ++p) grad[p] = 0.0;
+    const uint64_t dim = uint64_t(1) << n;
+    for (int i = G - 1; i >= 0; --i) {
+        const Gate& gi = g[i];
+        const int k = arity(gi.kind), kd = 1 << k;
+        Mat4 U = gate_matrix(gi, params, m.data());
+        Mat4 Ud = dagger(U);
+        std::vector<cplx> phi = psi;          // state before gate i
+        apply_gate(n, phi, gi, Ud);
+        const int roles = (gi.kind == FSIM) ? 2 : ((gi.kind == RX || gi.kind == RY || gi.kind == RZ || gi.kind == RZZ) ? 1 : 0);
+        for (int r = 0; r < roles; ++r) {
+            std::vector<cplx> t = phi;
+            apply_gate(n, t, gi, gate_matrix_derivative(gi, r, params));
+            grad[r == 0 ? gi.p0 : gi.p1] += 2.0 * inner(lam, t).real();
+        }
+        if (gate_cot || lie) {
+            Mat4 Gc = zero4();
+            int q[2] = {gi.q0, gi.q1};
+            for (int a = 0; a < kd; ++a)
+                for (int b = 0; b < kd; ++b) {
+                    auto f = [&](uint64_t j) {
+                        // j runs over the 2^(n-k) indices with the gate bits cleared,
+                        // enumerated by inserting zero bits at the gate positions
+                        uint64_t base = 0, jj = j;
+                        for (int bit = 0, used = 0; bit < n; ++bit) {
+                            bool isg = false;
+                            for (int t = 0; t < k; ++t) isg |= (q[t] == bit);
+                            if (isg) continue;
+                            base |= ((jj >> used) & 1) << bit;
+                            ++used;
+                        }
+                        uint64_t ia = base, ib = base;
+                        for (int t = 0; t < k; ++t) {
+                            ia |= uint64_t((a >> (k - 1 - t)) & 1) << q[t];
+                            ib |= uint64_t((b >> (k - 1 - t)) & 1) << q[t];
+                        }
+                        return lam[ia] * std::conj(phi[ib]);
+                    };
+                    Gc.m[a][b] = pairwise_sum(f, 0, dim >> k);
+                }
+            if (gate_cot)
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) {
+                        gate_cot[32 * i + 2 * (4 * a + b)] = Gc.m[a][b].real();
+                        gate_cot[32 * i + 2 * (4 * a + b) + 1] = Gc.m[a][b].imag();
+                    }
+            if (lie) {
+                for (int kk = 0; kk < 15; ++kk) lie[15 * i + kk] = 0.0;
+                if (k == 2) {
+                    // dE/dalpha = 2 Re tr(G^dag dU), dU = -i (P/2) U  =>  Im tr(G^dag P U)
+                    for (int kk = 0; kk < 15; ++kk) {
+                        int a = (kk + 1) >> 2, b = (kk + 1) & 3;
+                        Mat4 PU = matmul(pauli2(a, b), U, 4);
+                        cplx tr = 0.0;
+                        for (int x = 0; x < 4; ++x)
+                            for (int y = 0; y < 4; ++y) tr += std::conj(Gc.m[y][x]) * PU.m[y][x];
+                        lie[15 * i + kk] = tr.imag();
+                    }
+                }
+            }
+        }
+        apply_gate(n, lam, gi, Ud);
+        psi.swap(phi);
+    }
+    return 0;
+}
+
+// Parameter-shift gradient (exact for these gates): for a gate generated by
+// P/2 with P^2 = I, dE/dtheta = (E(theta + pi/2) - E(theta - pi/2)) / 2.
+// fSim's phi generator |11><11| has eigenvalues {0, 1}: same two-term rule.
+// fSim's theta generator (XX + YY)/2 has three eigenvalues; because XX and YY
+// commute, exp(-i theta (XX+YY)/2) = exp(-i theta XX/2) exp(-i theta YY/2) and
+// the rule is applied to each factor; a shift of one factor equals a left
+// factor exp(-i s XX/2) (resp. YY) on the whole gate.
+// lie (nullable): per two-qubit gate the 15 shifted-generator derivatives.
+int orc_param_shift(int n, const int32_t* gates, int G, const double* params, int n_params,
+                    const double* mats, int n_mats, const uint8_t* codes, const double* coeffs, int T,
+                    const double* init, double* grad, double* lie) {
+    auto g = read_gates(gates, G);
+    auto m = read_mats(mats, n_mats);
+    auto terms = read_terms(n, codes, coeffs, T);
+    std::vector<double> pv(params, params + n_params);
+    const double h = M_PI / 2;
+    for (int p = 0; p < n_params; ++p) grad[p] = 0.0;
+    for (int i = 0; i < G; ++i) {
+        const Gate& gi = g[i];
+        switch (gi.kind) {
+            case RX: case RY: case RZ: case RZZ:
+                grad[gi.p0] += 0.5 * (energy_with_param(n, g, pv, m, init, terms, i, 0, h) -
+                                      energy_with_param(n, g, pv, m, init, terms, i, 0, -h));
+                break;
+            case FSIM:
+                grad[gi.p0] += 0.5 * (energy_with_left_factor(n, g, params, m, init, terms, i, pauli2_rotation(1, 1, h)) -
+                                      energy_with_left_factor(n, g, params, m, init, terms, i, pauli2_rotation(1, 1, -h)));
+                grad[gi.p0] += 0.5 * (energy_with_left_factor(n, g, params, m, init, terms, i, pauli2_rotation(2, 2, h)) -
+                                      energy_with_left_factor(n, g, params, m, init, terms, i, pauli2_rotation(2, 2, -h)));
+                grad[gi.p1] += 0.5 * (energy_with_param(n, g, pv, m, init, terms, i, 1, h) -
+                                      energy_with_param(n, g, pv, m, init, terms, i, 1, -h));
+                break;
+            default: break;
+        }
+        if (lie) {
+            for (int kk = 0; kk < 15; ++kk) lie[15 * i + kk] = 0.0;
+            if (arity(gi.kind) == 2)
+                for (int kk = 0; kk < 15; ++kk) {
+                    int a = (kk + 1) >> 2, b = (kk + 1) & 3;
+                    lie[15 * i + kk] = 0.5 * (energy_with_left_factor(n, g, params, m, init, terms, i, pauli2_rotation(a, b, h)) -
+                                              energy_with_left_factor(n, g, params, m, init, terms, i, pauli2_rotation(a, b, -h)));
+                }
+        }
+    }
+    return 0;
+}
+
+}  // extern "C"
