@@ -1,0 +1,185 @@
+/*
+ * tcng.h — C ABI of the MI355X statevector hot path.
+ *
+ * What is computed (TensorCircuit-NG paper, Sec. "Foundations Recap" and
+ * Sec. "Data Parallelism"):
+ *   |psi(theta)> = U_D(theta) ... U_1(theta) |psi_0>      gates as local contractions
+ *   E(theta)     = Re <psi(theta)| H |psi(theta)>,  H = sum_k c_k P_k   (expectation_ps)
+ *   dE/dtheta                                          (value_and_grad; here by the adjoint method)
+ * batched over many parameter sets (the VMAP paradigm, "parameter parallelism")
+ * and over many different circuits (uneven batches).
+ *
+ * Conventions (readings where the paper is silent):
+ *   - amplitudes are interleaved complex, the memory layout of torch.complex64 /
+ *     torch.complex128; amplitude index bit q <-> qubit q (qubit 0 = LSB);
+ *   - a k-qubit matrix acting on qubits (q_0, ..., q_{k-1}) is row-major
+ *     2^k x 2^k with q_0 the most significant bit of its local index;
+ *   - R_P(theta) = exp(-i theta P / 2) for RX/RY/RZ, RZZ = exp(-i theta ZZ/2),
+ *     FSIM(theta, phi) = [[1,0,0,0],[0,c,-is,0],[0,-is,c,0],[0,0,0,e^{-i phi}]]
+ *     with c = cos theta, s = sin theta;
+ *   - Pauli codes 0 = I, 1 = X, 2 = Y, 3 = Z (the paper's shadow encoding).
+ *
+ * General rules for every call:
+ *   - returns TCNG_OK or an error code; tcng_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread);
+ *   - device pointers are caller-owned (e.g. torch tensors) and must stay
+ *     valid until the stream reaches the work; host pointers are read before
+ *     the call returns;
+ *   - work is enqueued on `stream` (a hipStream_t, NULL = default stream) and
+ *     is asynchronous; outputs are valid once the stream reaches them;
+ *   - no call allocates device memory after tcng_circuit_create /
+ *     tcng_pauli_sum_create (which upload their own small descriptor tables);
+ *     scratch space comes from the caller's workspace (tcng_workspace_size);
+ *   - a workspace must not be used by two calls that may overlap in time.
+ */
+#ifndef TCNG_ABI_H_
+#define TCNG_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tcng_status;
+enum {
+    TCNG_OK = 0,
+    TCNG_E_INVALID = 1,     /* bad argument: null pointer, qubit out of range, duplicate qubits, ... */
+    TCNG_E_UNSUPPORTED = 2, /* valid request this library does not implement (e.g. n too large)      */
+    TCNG_E_WORKSPACE = 3,   /* workspace smaller than tcng_workspace_size() says                     */
+    TCNG_E_HIP = 4,         /* HIP runtime error (launch failure, or an earlier asynchronous error)  */
+    TCNG_E_ALLOC = 5        /* host or device allocation failed at create time                       */
+};
+
+enum { TCNG_C64 = 0, TCNG_C128 = 1 };
+
+/* Execution strategy of the circuit passes.
+ *   TCNG_MODE_TILED: gates are scheduled into passes over 2^m-amplitude tiles
+ *     held in registers and LDS; one HBM round trip applies many gates.
+ *   TCNG_MODE_PLAIN: one streaming kernel per gate (and per Pauli x-group);
+ *     the unfused baseline. */
+enum { TCNG_MODE_TILED = 0, TCNG_MODE_PLAIN = 1 };
+
+/* gate kinds of tcng_gate.kind */
+enum {
+    TCNG_RX = 0, TCNG_RY = 1, TCNG_RZ = 2, TCNG_H = 3, TCNG_X = 4, TCNG_Y = 5, TCNG_Z = 6,
+    TCNG_S = 7, TCNG_CNOT = 8, TCNG_CZ = 9, TCNG_RZZ = 10, TCNG_FSIM = 11,
+    TCNG_U1 = 12, /* constant 2x2 matrix: top-left block of const_mats[mat] */
+    TCNG_U2 = 13  /* constant 4x4 matrix const_mats[mat]                    */
+};
+
+/* A batch of statevectors: a NON-OWNING view of device memory.
+ * Member b occupies amps + b*stride*(8 or 16 bytes), 2^n_qubits amplitudes. */
+typedef struct tcng_state {
+    void* amps;        /* device, interleaved complex in `dtype`                 */
+    int32_t n_qubits;  /* 1 .. 34                                                */
+    int32_t dtype;     /* TCNG_C64 or TCNG_C128                                  */
+    int64_t batch;     /* >= 1                                                   */
+    int64_t stride;    /* amplitudes between batch members, >= 2^n_qubits        */
+} tcng_state;
+
+/* One gate of a circuit.  q1 = -1 for one-qubit kinds; for CNOT q0 is the
+ * control.  p0/p1 index the parameter vector (-1 = unused; FSIM uses p0 = theta,
+ * p1 = phi); mat indexes the circuit's constant matrices (U1/U2 only). */
+typedef struct tcng_gate {
+    int32_t kind, q0, q1, p0, p1, mat;
+} tcng_gate;
+
+typedef struct tcng_circuit tcng_circuit;     /* immutable host handle + device tables */
+typedef struct tcng_pauli_sum tcng_pauli_sum; /* immutable host handle + device tables */
+
+const char* tcng_last_error(void);
+int32_t tcng_version(void);
+
+/* psi := |basis_index> (amps_in == NULL) or a copy of amps_in (device, same
+ * dtype, 2^n amplitudes, copied into every batch member).  Paper: Circuit(n)
+ * starts from |0...0>; Circuit(n, inputs=x) from given amplitudes (Sec.
+ * "End-to-End Pure QML for Computer Vision", amplitude encoding). */
+tcng_status tcng_state_init(const tcng_state* s, const void* amps_in, int64_t basis_index, void* stream);
+
+/* Apply one k-qubit matrix (1 <= k <= 5) to every batch member in place.
+ * unitary: DEVICE pointer, row-major 2^k x 2^k complex in the state's dtype,
+ * qubits[0] = most significant local bit (Sec. "Foundations Recap": a gate is
+ * a local tensor contraction).  qubits: host array of k distinct qubits. */
+tcng_status tcng_apply_gate(const tcng_state* s, const int32_t* qubits, int32_t k, const void* unitary,
+                            void* stream);
+
+/* Build a circuit handle on the current device.  gates: host [n_gates];
+ * const_mats: host complex128 [n_mats][4][4] interleaved (NULL if n_mats = 0).
+ * Errors: TCNG_E_INVALID for out-of-range / duplicate qubits, bad kinds,
+ * parameter or matrix indices out of range. */
+tcng_status tcng_circuit_create(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
+                                const double* const_mats, int32_t n_mats, tcng_circuit** out);
+/* Waits for the device (enqueued work may still read the tables), then frees. */
+tcng_status tcng_circuit_destroy(tcng_circuit* c);
+/* Number of tiled passes the planner produced for `dtype` (forward sweep). */
+tcng_status tcng_circuit_num_passes(const tcng_circuit* c, int32_t dtype, int32_t* passes);
+
+/* Build a Pauli-sum handle: codes host uint8 [n_terms][n_qubits] (0=I,1=X,2=Y,3=Z),
+ * coeffs host float64 [n_terms] (Sec. "Data Parallelism": H = sum_i c_i P_i). */
+tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const double* coeffs, int32_t n_terms,
+                                  tcng_pauli_sum** out);
+tcng_status tcng_pauli_sum_destroy(tcng_pauli_sum* h);
+
+/* Bytes of workspace needed by tcng_run_circuit / tcng_expect_pauli /
+ * tcng_expect_grad for this shape (c or h may be NULL when not used). */
+tcng_status tcng_workspace_size(const tcng_circuit* c, const tcng_pauli_sum* h, int32_t dtype, int64_t batch,
+                                int32_t mode, size_t* bytes);
+
+/* Apply the circuit in place to every batch member of s.
+ * params: DEVICE [batch][n_params], float32 for TCNG_C64, float64 for TCNG_C128
+ * (may be NULL when n_params == 0). */
+tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tcng_state* s, int32_t mode,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* out[b] = Re <psi_b| H |psi_b> accumulated in float64 (DEVICE float64 [batch]). */
+tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, double* out, int32_t mode, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Value and adjoint gradient.
+ *   psi   : in  = initial states |psi_0> (batch members);
+ *           out = the initial states recomputed by the reverse sweep (equal to
+ *                 the input up to rounding);
+ *   lam   : scratch state of the same shape (holds H psi, then the costates);
+ *   energy: DEVICE float64 [batch], E_b;
+ *   grad  : DEVICE float64 [batch][n_params], dE_b/dtheta summed over every use;
+ *   gate_grad (nullable): DEVICE float64 [batch][n_gates][15]: for each
+ *           two-qubit gate, dE/dalpha_k for U -> exp(-i alpha_k P_k / 2) U,
+ *           P_k = sigma_a (x) sigma_b, k = 4a + b - 1 (zero rows for other gates).
+ * The reverse sweep recomputes states by applying inverse gates; nothing is
+ * stored per gate. */
+tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,
+                             const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
+                             double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel-family timing with HIP events recorded on the launch stream around
+ * every launch (instrumentation for benchmarks; off by default).
+ * tcng_profile_begin allocates up to max_launches event pairs and starts
+ * recording; tcng_profile_query synchronises the recorded events and returns
+ * the launch count and summed duration (ms) of one family:
+ *   0 forward tile pass   1 reverse tile pass   2 Pauli tile pass
+ *   3 one-qubit gate      4 two-qubit gate      5 k-qubit gate
+ *   6 reverse one-qubit   7 reverse two-qubit   8 Pauli X-group
+ *   9 final reduction     10 state init
+ * tcng_profile_end stops recording and frees the events. */
+enum { TCNG_PROF_FAMILIES = 11 };
+tcng_status tcng_profile_begin(int32_t max_launches);
+tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
+tcng_status tcng_profile_end(void);
+
+/* Host-only inspection of the tiled planner (no device is touched): the
+ * schedule tcng_circuit_create would build for `dtype`.  Outputs (host):
+ *   order[n_gates]      gate indices in execution order of the forward sweep;
+ *   pass_of[n_gates]    pass in which gate order[i] runs;
+ *   tile_mask[n_gates]  qubit mask of pass p's tile in entry p (p < *n_passes);
+ *   n_passes            number of passes (0 if the tiled path does not apply).
+ * Any output pointer may be NULL. */
+tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
+                              int32_t dtype, int32_t* order, int32_t* pass_of, uint64_t* tile_mask,
+                              int32_t* n_passes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCNG_ABI_H_ */

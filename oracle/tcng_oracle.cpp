@@ -167,6 +167,27 @@ void apply_matrix(int n, std::vector<cplx>& psi, const int* q, int k, const Mat4
     psi.swap(out);
 }
 
+// the same definition for a general k-qubit matrix (row-major 2^k x 2^k)
+void apply_dense(int n, std::vector<cplx>& psi, const int* q, int k, const std::vector<cplx>& U) {
+    const uint64_t dim = uint64_t(1) << n;
+    const int kdim = 1 << k;
+    std::vector<cplx> out(dim);
+    for (uint64_t j = 0; j < dim; ++j) {
+        int a = 0;
+        for (int t = 0; t < k; ++t) a |= int((j >> q[t]) & 1) << (k - 1 - t);
+        uint64_t rest = j;
+        for (int t = 0; t < k; ++t) rest &= ~(uint64_t(1) << q[t]);
+        cplx s = 0.0;
+        for (int b = 0; b < kdim; ++b) {
+            uint64_t src = rest;
+            for (int t = 0; t < k; ++t) src |= uint64_t((b >> (k - 1 - t)) & 1) << q[t];
+            s += U[size_t(a) * kdim + b] * psi[src];
+        }
+        out[j] = s;
+    }
+    psi.swap(out);
+}
+
 Mat4 dagger(const Mat4& U) {
     Mat4 a;
     for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) a.m[i][j] = std::conj(U.m[j][i]);
@@ -343,15 +364,14 @@ int orc_run(int n, const int32_t* gates, int G, const double* params, const doub
     return 0;
 }
 
-// Apply one k-qubit matrix (row-major 2^k x 2^k, interleaved complex) in place.
+// Apply one k-qubit matrix (1 <= k <= 6, row-major 2^k x 2^k, interleaved complex) in place.
 int orc_apply_matrix(int n, double* state, const int32_t* qubits, int k, const double* U) {
-    if (k < 1 || k > 2) return 1;
+    if (k < 1 || k > 6 || k > n) return 1;
     std::vector<cplx> psi = initial_state(n, state);
-    Mat4 M = zero4();
-    int kd = 1 << k;
-    for (int i = 0; i < kd; ++i)
-        for (int j = 0; j < kd; ++j) M.m[i][j] = cplx(U[2 * (kd * i + j)], U[2 * (kd * i + j) + 1]);
-    apply_matrix(n, psi, qubits, k, M);
+    const int kd = 1 << k;
+    std::vector<cplx> M(size_t(kd) * kd);
+    for (size_t i = 0; i < M.size(); ++i) M[i] = cplx(U[2 * i], U[2 * i + 1]);
+    apply_dense(n, psi, qubits, k, M);
     write_state(psi, state);
     return 0;
 }

@@ -1,0 +1,254 @@
+"""MI355X statevector hot path: gates, Pauli-sum <H> and adjoint gradients.
+
+Python face of the C ABI (include/tcng.h).  PyTorch supplies device memory
+and the stream; the computation runs in the HIP kernels of libtcng.so.
+Following the paper's problem statement (Sec. "Foundations Recap"):
+
+    circ = Circuit(n, gates, n_params)            # tc.Circuit + gate calls
+    H = PauliSum(n, codes, coeffs)                # expectation_ps terms
+    E, g = expect_grad(circ, params, H)           # jit(vmap(value_and_grad(...)))
+    E = TcngEnergy.apply(params, circ, H)         # torch autograd op
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TcngError, TcngGate,  # noqa: F401
+                   TcngState, check, lib)
+
+__all__ = ["plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
+           "TcngEnergy", "new_state", "TcngError", "MODES"]
+
+MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN}
+
+
+def _mode(mode):
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor):
+    if t.dtype == torch.complex64:
+        return TCNG_C64
+    if t.dtype == torch.complex128:
+        return TCNG_C128
+    raise TypeError(f"state must be complex64 or complex128, got {t.dtype}")
+
+
+def _state(t: torch.Tensor, n: int) -> TcngState:
+    if not t.is_cuda:
+        raise ValueError("state must be a device tensor")
+    if t.dim() == 1:
+        t2 = t.view(1, -1)
+    else:
+        t2 = t
+    if t2.dim() != 2 or t2.shape[1] != 2 ** n or t2.stride(1) != 1:
+        raise ValueError(f"state must be [batch, 2^{n}] with unit inner stride")
+    return TcngState(t2.data_ptr(), n, _dtype_code(t2), t2.shape[0], t2.stride(0))
+
+
+def _nqubits(t: torch.Tensor) -> int:
+    d = t.shape[-1]
+    n = int(d).bit_length() - 1
+    if d != 2 ** n:
+        raise ValueError("last dimension must be a power of two")
+    return n
+
+
+def new_state(n, batch=1, dtype=torch.complex64, device="cuda"):
+    """|0...0> for every batch member, shape [batch, 2^n]."""
+    psi = torch.empty((batch, 2 ** n), dtype=dtype, device=device)
+    state_init(psi)
+    return psi
+
+
+def state_init(psi: torch.Tensor, amps: torch.Tensor | None = None, basis: int = 0):
+    n = _nqubits(psi)
+    s = _state(psi, n)
+    ptr = None
+    if amps is not None:
+        amps = amps.to(device=psi.device, dtype=psi.dtype).contiguous().view(-1)
+        if amps.numel() != 2 ** n:
+            raise ValueError("amps must have 2^n entries")
+        ptr = amps.data_ptr()
+    check(lib().tcng_state_init(ctypes.byref(s), ptr, int(basis), _stream()))
+    return psi
+
+
+def apply_gate(psi: torch.Tensor, qubits, U: torch.Tensor):
+    """Apply a k-qubit matrix (qubits[0] = most significant local bit) in place."""
+    n = _nqubits(psi)
+    s = _state(psi, n)
+    q = np.ascontiguousarray(np.asarray(qubits, dtype=np.int32).reshape(-1))
+    U = U.to(device=psi.device, dtype=psi.dtype).contiguous()
+    if U.numel() != 4 ** len(q):
+        raise ValueError("U must be 2^k x 2^k")
+    check(lib().tcng_apply_gate(ctypes.byref(s), q.ctypes.data_as(ctypes.c_void_p), len(q),
+                                ctypes.c_void_p(U.data_ptr()), _stream()))
+    return psi
+
+
+class Circuit:
+    """Immutable circuit handle: gate records int32 [G][6] = (kind, q0, q1, p0, p1, mat)."""
+
+    def __init__(self, n: int, gates, n_params: int, mats=None):
+        g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 6))
+        m = np.zeros((0, 4, 4), np.complex128) if mats is None else np.asarray(mats, dtype=np.complex128)
+        m = np.ascontiguousarray(m.reshape(-1, 4, 4))
+        h = ctypes.c_void_p()
+        check(lib().tcng_circuit_create(int(n), g.ctypes.data_as(ctypes.c_void_p), g.shape[0], int(n_params),
+                                        m.ctypes.data_as(ctypes.c_void_p) if m.shape[0] else None, m.shape[0],
+                                        ctypes.byref(h)))
+        self.handle = h
+        self.n, self.n_params, self.n_gates = int(n), int(n_params), g.shape[0]
+        self.gates = g
+
+    def num_passes(self, dtype=torch.complex64):
+        out = ctypes.c_int32()
+        check(lib().tcng_circuit_num_passes(self.handle, TCNG_C64 if dtype == torch.complex64 else TCNG_C128,
+                                            ctypes.byref(out)))
+        return out.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.tcng_circuit_destroy(h)
+            self.handle = None
+
+
+class PauliSum:
+    """Immutable Hamiltonian handle: codes uint8 [T][n] (0=I,1=X,2=Y,3=Z), coefficients float64 [T]."""
+
+    def __init__(self, n: int, codes, coeffs):
+        c = np.ascontiguousarray(np.asarray(codes, dtype=np.uint8).reshape(-1, n))
+        w = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(-1))
+        if c.shape[0] != w.shape[0]:
+            raise ValueError("codes and coeffs disagree in length")
+        h = ctypes.c_void_p()
+        check(lib().tcng_pauli_sum_create(int(n), c.ctypes.data_as(ctypes.c_void_p),
+                                          w.ctypes.data_as(ctypes.c_void_p), c.shape[0], ctypes.byref(h)))
+        self.handle = h
+        self.n, self.n_terms = int(n), c.shape[0]
+        self.abs_sum = float(np.abs(w).sum())
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.tcng_pauli_sum_destroy(h)
+            self.handle = None
+
+
+def _workspace(circ, H, dtype_code, batch, mode, device):
+    nbytes = ctypes.c_size_t()
+    check(lib().tcng_workspace_size(circ.handle if circ is not None else None, H.handle if H is not None else None,
+                                    dtype_code, int(batch), mode, ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+    return ws
+
+
+def _params(circ, params, psi, batch):
+    if circ.n_params == 0:
+        return None, None
+    rdt = torch.float32 if psi.dtype == torch.complex64 else torch.float64
+    p = params.to(device=psi.device, dtype=rdt).reshape(batch, circ.n_params).contiguous()
+    return p, ctypes.c_void_p(p.data_ptr())
+
+
+def run_circuit(circ: Circuit, params, psi: torch.Tensor, mode="tiled"):
+    """Apply the circuit in place to every batch member (params [batch][n_params])."""
+    s = _state(psi, circ.n)
+    p, pp = _params(circ, params, psi, s.batch)
+    check(lib().tcng_run_circuit(circ.handle, pp, ctypes.byref(s), _mode(mode), None, 0, _stream()))
+    return psi
+
+
+def expect_pauli(psi: torch.Tensor, H: PauliSum, mode="tiled", out=None):
+    """float64 [batch] of Re <psi|H|psi>."""
+    s = _state(psi, H.n)
+    m = _mode(mode)
+    ws = _workspace(None, H, s.dtype, s.batch, m, psi.device)
+    if out is None:
+        out = torch.empty(s.batch, dtype=torch.float64, device=psi.device)
+    check(lib().tcng_expect_pauli(ctypes.byref(s), H.handle, ctypes.c_void_p(out.data_ptr()), m,
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
+
+
+def expect_grad(circ: Circuit, params, H: PauliSum, psi=None, lam=None, batch=None, dtype=torch.complex64,
+                want_gate_grad=False, mode="tiled", ws=None):
+    """E and dE/dtheta (float64) for every parameter set.
+
+    psi: initial states [batch, 2^n] (default |0...0>); it holds the
+    recomputed initial states on return.  lam: scratch state of the same shape.
+    """
+    if psi is None:
+        if batch is None:
+            batch = 1 if params is None or circ.n_params == 0 else params.numel() // circ.n_params
+        psi = new_state(circ.n, batch, dtype)
+    s = _state(psi, circ.n)
+    if lam is None:
+        lam = torch.empty_like(psi)
+    sl = _state(lam, circ.n)
+    m = _mode(mode)
+    if ws is None:
+        ws = _workspace(circ, H, s.dtype, s.batch, m, psi.device)
+    p, pp = _params(circ, params, psi, s.batch)
+    energy = torch.empty(s.batch, dtype=torch.float64, device=psi.device)
+    grad = torch.empty((s.batch, max(circ.n_params, 0)), dtype=torch.float64, device=psi.device)
+    gg = torch.empty((s.batch, circ.n_gates, 15), dtype=torch.float64, device=psi.device) if want_gate_grad else None
+    check(lib().tcng_expect_grad(circ.handle, pp, H.handle, ctypes.byref(s), ctypes.byref(sl),
+                                 ctypes.c_void_p(energy.data_ptr()),
+                                 ctypes.c_void_p(grad.data_ptr()) if circ.n_params else None,
+                                 ctypes.c_void_p(gg.data_ptr()) if gg is not None else None, m,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    if want_gate_grad:
+        return energy, grad, gg
+    return energy, grad
+
+
+class TcngEnergy(torch.autograd.Function):
+    """E(theta) = <psi(theta)|H|psi(theta)> as a differentiable torch op.
+
+    forward runs the whole adjoint sweep once (value and gradient together,
+    like the paper's value_and_grad); backward scales the stored gradient.
+    params: [batch, n_params] (or [n_params]) float tensor on the device.
+    """
+
+    @staticmethod
+    def forward(ctx, params, circ, H, dtype=torch.complex64, mode="tiled"):
+        p2 = params.detach().reshape(-1, circ.n_params)
+        energy, grad = expect_grad(circ, p2, H, batch=p2.shape[0], dtype=dtype, mode=mode)
+        ctx.save_for_backward(grad)
+        ctx.shape = params.shape
+        ctx.pdtype = params.dtype
+        out = energy if params.dim() > 1 else energy[0]
+        return out.to(params.dtype) if params.dtype != torch.float64 else out
+
+    @staticmethod
+    def backward(ctx, gE):
+        (grad,) = ctx.saved_tensors
+        g = gE.to(torch.float64).reshape(-1, 1) * grad
+        return g.reshape(ctx.shape).to(ctx.pdtype), None, None, None, None
+
+
+def plan_inspect(n, gates, n_params, dtype=torch.complex64):
+    """Host-only view of the tiled schedule: (order, pass_of, tile_masks)."""
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 6))
+    G = g.shape[0]
+    order = np.zeros(max(G, 1), np.int32)
+    pass_of = np.zeros(max(G, 1), np.int32)
+    masks = np.zeros(max(G, 1), np.uint64)
+    npass = ctypes.c_int32()
+    check(lib().tcng_plan_inspect(int(n), g.ctypes.data_as(ctypes.c_void_p), G, int(n_params),
+                                  TCNG_C64 if dtype == torch.complex64 else TCNG_C128,
+                                  order.ctypes.data_as(ctypes.c_void_p), pass_of.ctypes.data_as(ctypes.c_void_p),
+                                  masks.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass)))
+    k = npass.value
+    return order[:G] if k else None, pass_of[:G] if k else None, masks[:k]

@@ -1,0 +1,143 @@
+// Shared definitions of the HIP library: complex arithmetic on interleaved
+// (re, im) pairs, the gate-kind enum of the C ABI, and the plan descriptors
+// the host planner writes for the tiled kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tcng.h"
+
+namespace tcng {
+
+// ---------------------------------------------------------------------------
+// complex numbers in the layout of torch.complex64 / complex128
+// ---------------------------------------------------------------------------
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+__host__ __device__ __forceinline__ float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmaR(double a, double b, double c) { return fma(a, b, c); }
+// a*b + c
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> c) {
+    return {fmaR(a.re, b.re, fmaR(-a.im, b.im, c.re)), fmaR(a.re, b.im, fmaR(a.im, b.re, c.im))};
+}
+
+// gate kinds (values of the C ABI)
+enum Kind : int {
+    K_RX = TCNG_RX, K_RY = TCNG_RY, K_RZ = TCNG_RZ, K_H = TCNG_H, K_X = TCNG_X, K_Y = TCNG_Y,
+    K_Z = TCNG_Z, K_S = TCNG_S, K_CNOT = TCNG_CNOT, K_CZ = TCNG_CZ, K_RZZ = TCNG_RZZ,
+    K_FSIM = TCNG_FSIM, K_U1 = TCNG_U1, K_U2 = TCNG_U2, K_COUNT
+};
+
+__host__ __device__ inline int kind_arity(int k) {
+    return (k == K_CNOT || k == K_CZ || k == K_RZZ || k == K_FSIM || k == K_U2) ? 2 : 1;
+}
+__host__ __device__ inline int kind_nparams(int k) {
+    return (k == K_RX || k == K_RY || k == K_RZ || k == K_RZZ) ? 1 : (k == K_FSIM ? 2 : 0);
+}
+__host__ __device__ inline bool kind_diagonal(int k) {
+    return k == K_RZ || k == K_Z || k == K_S || k == K_CZ || k == K_RZZ;
+}
+// gradient slots (float64 accumulators) one gate needs in the reverse sweep:
+// one per angle, 32 for the 4x4 complex cotangent of a constant U2
+__host__ __device__ inline int kind_slots(int k) {
+    return k == K_U2 ? 32 : kind_nparams(k);
+}
+
+// ---------------------------------------------------------------------------
+// tiled-pass plan (written on the host, read by the kernels)
+// ---------------------------------------------------------------------------
+constexpr int MAX_TILE_BITS = 14;
+constexpr int MAX_RB = 5;
+constexpr int RED_SLOTS = 512;   // float64 gradient accumulators per wave and reverse pass
+
+enum OpType : int8_t {
+    OP_DENSE1 = 0,  // 2x2 matrix, operand in register bit r0
+    OP_DIAG1 = 1,   // diagonal 2x2 on bit (r0 | lb0)
+    OP_CX = 2,      // CNOT: target in register bit r1, control bit (r0 | lb0)
+    OP_DENSE2 = 3,  // 4x4 matrix, operands in register bits r0 (MSB) and r1
+    OP_DIAG2 = 4,   // diagonal 4x4 on bits (r0 | lb0), (r1 | lb1)
+};
+
+// One gate inside a phase.  A qubit operand is either a register bit
+// (r >= 0: bit r of the register index j) or a thread bit (r < 0: bit lb of
+// the thread's part of the local index).
+struct Op {
+    int8_t type, kind, r0, r1, lb0, lb1, pad0, pad1;
+    int32_t p0, p1, mat;
+    int32_t slot;   // first gradient slot of this gate inside its reverse pass, -1 none
+    int32_t gate;   // gate index in the circuit
+    int32_t pad2;
+};
+
+// A run of ops that all act on the same RB local bits held in registers.
+struct Phase {
+    int32_t op_begin, op_end;
+    int8_t R[8];     // local bit position of register bit i (i < RB)
+};
+
+// One HBM round trip: tiles of 2^m amplitudes over the qubits in tile_mask.
+// Local bits 0..lo-1 are qubits 0..lo-1 (contiguous in memory); local bit
+// i >= lo is qubit local_qubit[i].
+struct Pass {
+    int32_t phase_begin, phase_end;
+    int32_t m, lo;
+    int32_t n_slots, slot_base;   // reverse sweep: gradient slots [slot_base, slot_base + n_slots)
+    uint64_t tile_mask;
+    int8_t local_qubit[16];
+};
+
+// Pauli sum, grouped by X-mask, for the tiled H|psi> / <H> passes.  Inside a
+// group the terms are split into classes of equal coefficient c_k i^{#Y_k},
+// so the kernels count sign parities with integer adds per class.
+struct PTerm {
+    int32_t z_local;     // Z/Y bits inside the tile, as local bit positions
+    int32_t pad;
+    uint64_t z_out;      // Z/Y qubits outside the tile
+};
+struct PClass {
+    int32_t term_begin, term_end;
+    double cre, cim;     // common coefficient c * i^{#Y}
+};
+struct PGroup {
+    int32_t x_local;     // X/Y bits (all inside the tile), local positions
+    int32_t class_begin, class_end;
+    int32_t pad;
+};
+struct PPass {
+    int32_t group_begin, group_end;
+    int32_t m, lo;
+    uint64_t tile_mask;
+    int8_t local_qubit[16];
+};
+
+// Pauli sum grouped by X-mask over the full index space (plain path).
+struct PTermFull {
+    uint64_t z;
+};
+struct PClassFull {
+    int32_t term_begin, term_end;
+    double cre, cim;
+};
+struct PGroupFull {
+    uint64_t x;
+    int32_t class_begin, class_end;
+};
+
+}  // namespace tcng

@@ -1,0 +1,259 @@
+// Device-side gate matrices, built from the gate kind and its angles, and
+// the register-resident gate application / adjoint-gradient primitives used
+// by the tiled kernels.
+//
+// Matrices (rows = output local index, q0 = most significant local bit):
+//   RX(t) = [[c, -is], [-is, c]],  RY(t) = [[c, -s], [s, c]],  c = cos t/2, s = sin t/2
+//   RZ(t) = diag(e^{-it/2}, e^{it/2}),  RZZ(t) = diag(e^{-it/2}, e^{it/2}, e^{it/2}, e^{-it/2})
+//   FSIM(t, p): |01>,|10> block [[cos t, -i sin t], [-i sin t, cos t]], |11> -> e^{-ip}
+// Gradient of E with respect to an angle of U = exp(-i t G) V is
+//   dE/dt = 2 Im <lambda| G |psi>   (psi, lambda: state and costate after the gate)
+// with G = P/2 for the Pauli rotations, (XX+YY)/2 and |11><11| for FSIM.
+#pragma once
+
+#include "common.h"
+
+namespace tcng {
+
+__device__ __forceinline__ void sc_half(float t, float& c, float& s) { sincosf(0.5f * t, &s, &c); }
+__device__ __forceinline__ void sc_half(double t, double& c, double& s) { sincos(0.5 * t, &s, &c); }
+__device__ __forceinline__ void sc_full(float t, float& c, float& s) { sincosf(t, &s, &c); }
+__device__ __forceinline__ void sc_full(double t, double& c, double& s) { sincos(t, &s, &c); }
+
+// 2x2 matrix of a one-qubit non-diagonal kind
+template <typename R>
+__device__ __forceinline__ void mat1(int kind, const R* prm, int p0, const cx<R>* cm, int mat, cx<R>* u) {
+    const R z = R(0), o = R(1);
+    switch (kind) {
+        case K_RX: { R c, s; sc_half(prm[p0], c, s); u[0] = {c, z}; u[1] = {z, -s}; u[2] = {z, -s}; u[3] = {c, z}; break; }
+        case K_RY: { R c, s; sc_half(prm[p0], c, s); u[0] = {c, z}; u[1] = {-s, z}; u[2] = {s, z}; u[3] = {c, z}; break; }
+        case K_H: { const R r = R(0.70710678118654752440); u[0] = {r, z}; u[1] = {r, z}; u[2] = {r, z}; u[3] = {-r, z}; break; }
+        case K_X: u[0] = {z, z}; u[1] = {o, z}; u[2] = {o, z}; u[3] = {z, z}; break;
+        case K_Y: u[0] = {z, z}; u[1] = {z, -o}; u[2] = {z, o}; u[3] = {z, z}; break;
+        default:  // K_U1
+            u[0] = cm[16 * mat + 0]; u[1] = cm[16 * mat + 1]; u[2] = cm[16 * mat + 4]; u[3] = cm[16 * mat + 5];
+            break;
+    }
+}
+
+// diagonal of a one-qubit diagonal kind
+template <typename R>
+__device__ __forceinline__ void diag1(int kind, const R* prm, int p0, cx<R>* d) {
+    const R z = R(0), o = R(1);
+    switch (kind) {
+        case K_RZ: { R c, s; sc_half(prm[p0], c, s); d[0] = {c, -s}; d[1] = {c, s}; break; }
+        case K_Z: d[0] = {o, z}; d[1] = {-o, z}; break;
+        default:  // K_S
+            d[0] = {o, z}; d[1] = {z, o}; break;
+    }
+}
+
+// diagonal of a two-qubit diagonal kind
+template <typename R>
+__device__ __forceinline__ void diag2(int kind, const R* prm, int p0, cx<R>* d) {
+    const R z = R(0), o = R(1);
+    if (kind == K_RZZ) {
+        R c, s; sc_half(prm[p0], c, s);
+        d[0] = {c, -s}; d[1] = {c, s}; d[2] = {c, s}; d[3] = {c, -s};
+    } else {  // K_CZ
+        d[0] = {o, z}; d[1] = {o, z}; d[2] = {o, z}; d[3] = {-o, z};
+    }
+}
+
+// 4x4 matrix of a dense two-qubit kind (FSIM, U2)
+template <typename R>
+__device__ __forceinline__ void mat2(int kind, const R* prm, int p0, int p1, const cx<R>* cm, int mat, cx<R>* u) {
+    if (kind == K_FSIM) {
+        const R z = R(0), o = R(1);
+        R c, s, cp, sp;
+        sc_full(prm[p0], c, s);
+        sc_full(prm[p1], cp, sp);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = {z, z};
+        u[0] = {o, z};
+        u[5] = {c, z}; u[6] = {z, -s};
+        u[9] = {z, -s}; u[10] = {c, z};
+        u[15] = {cp, -sp};
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = cm[16 * mat + i];
+    }
+}
+
+template <typename R, int K>
+__device__ __forceinline__ void dagger_inplace(cx<R>* u) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        u[i * K + i] = conj(u[i * K + i]);
+#pragma unroll
+        for (int j = i + 1; j < K; ++j) {
+            cx<R> a = u[i * K + j], b = u[j * K + i];
+            u[i * K + j] = conj(b);
+            u[j * K + i] = conj(a);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// register-resident application: a register block holds NB = 2^RB amplitudes
+// whose local index bits R[0..RB-1] are the bits of the register index j.
+// Blocks and matrices are passed and returned by value: with pointer
+// arguments the compiler keeps the block in scratch memory.
+// ---------------------------------------------------------------------------
+template <typename R, int NB>
+struct Regs {
+    cx<R> v[NB];
+};
+template <typename R>
+struct M2 {
+    cx<R> e[4];
+};
+template <typename R>
+struct M4 {
+    cx<R> e[16];
+};
+template <typename R>
+struct D4 {
+    cx<R> e[4];
+};
+
+// per-element selects on named values (no indexed access to a private array)
+template <typename R>
+__device__ __forceinline__ cx<R> sel(bool c, cx<R> x, cx<R> y) {
+    return {c ? x.re : y.re, c ? x.im : y.im};
+}
+
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_dense1(Regs<R, NB> a, M2<R> u) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        const cx<R> x0 = a.v[j], x1 = a.v[j | (1 << B)];
+        a.v[j] = cfma(u.e[1], x1, u.e[0] * x0);
+        a.v[j | (1 << B)] = cfma(u.e[3], x1, u.e[2] * x0);
+    }
+    return a;
+}
+
+template <typename R, int NB, int B0, int B1>
+__device__ __forceinline__ Regs<R, NB> app_dense2(Regs<R, NB> a, M4<R> u) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & ((1 << B0) | (1 << B1))) continue;
+        const int i1 = j | (1 << B1), i2 = j | (1 << B0), i3 = j | (1 << B0) | (1 << B1);
+        const cx<R> x0 = a.v[j], x1 = a.v[i1], x2 = a.v[i2], x3 = a.v[i3];
+        a.v[j]  = cfma(u.e[3], x3, cfma(u.e[2], x2, cfma(u.e[1], x1, u.e[0] * x0)));
+        a.v[i1] = cfma(u.e[7], x3, cfma(u.e[6], x2, cfma(u.e[5], x1, u.e[4] * x0)));
+        a.v[i2] = cfma(u.e[11], x3, cfma(u.e[10], x2, cfma(u.e[9], x1, u.e[8] * x0)));
+        a.v[i3] = cfma(u.e[15], x3, cfma(u.e[14], x2, cfma(u.e[13], x1, u.e[12] * x0)));
+    }
+    return a;
+}
+
+// CNOT with the target in register bit B; control either register bit rc
+// (rc >= 0) or the thread-constant bit value tb.
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_cx(Regs<R, NB> a, int rc, int tb) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        const bool c = (rc >= 0 ? ((j >> rc) & 1) : tb) != 0;
+        const cx<R> x0 = a.v[j], x1 = a.v[j | (1 << B)];
+        a.v[j] = sel(c, x1, x0);
+        a.v[j | (1 << B)] = sel(c, x0, x1);
+    }
+    return a;
+}
+
+// diagonal on one bit (d.e[0], d.e[1]) or two bits (d.e[2 b0 + b1])
+template <typename R, int NB>
+__device__ __forceinline__ Regs<R, NB> app_diag(Regs<R, NB> a, int r0, int tb0, int r1, int tb1, bool two, D4<R> d) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int b0 = r0 >= 0 ? ((j >> r0) & 1) : tb0;
+        const int b1 = r1 >= 0 ? ((j >> r1) & 1) : tb1;
+        cx<R> f;
+        if (two) {
+            const cx<R> lo = sel(b1 != 0, d.e[1], d.e[0]), hi = sel(b1 != 0, d.e[3], d.e[2]);
+            f = sel(b0 != 0, hi, lo);
+        } else {
+            f = sel(b0 != 0, d.e[1], d.e[0]);
+        }
+        a.v[j] = a.v[j] * f;
+    }
+    return a;
+}
+
+// Im(conj(l) * p) and Re(conj(l) * p) in float64 (exact products for float inputs)
+template <typename R>
+__device__ __forceinline__ double im_conj_mul(cx<R> l, cx<R> p) {
+    return fma(double(l.re), double(p.im), -double(l.im) * double(p.re));
+}
+template <typename R>
+__device__ __forceinline__ double re_conj_mul(cx<R> l, cx<R> p) {
+    return fma(double(l.re), double(p.re), double(l.im) * double(p.im));
+}
+
+// dE/dt contribution of RX / RY on register bit B:  Im <l| P |p>
+template <typename R, int NB, int B>
+__device__ __forceinline__ double grad_rot1(int kind, Regs<R, NB> l, Regs<R, NB> p) {
+    double g = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        const int j1 = j | (1 << B);
+        if (kind == K_RX) {   // X: (Xp)_0 = p_1, (Xp)_1 = p_0
+            g += im_conj_mul(l.v[j], p.v[j1]) + im_conj_mul(l.v[j1], p.v[j]);
+        } else {              // Y: (Yp)_0 = -i p_1, (Yp)_1 = i p_0;  Im(-i z) = -Re z
+            g += re_conj_mul(l.v[j1], p.v[j]) - re_conj_mul(l.v[j], p.v[j1]);
+        }
+    }
+    return g;
+}
+
+// RZ / RZZ: sum_j sign_j Im(conj(l_j) p_j), sign = (-1)^{bit} resp. (-1)^{b0 ^ b1}
+template <typename R, int NB>
+__device__ __forceinline__ double grad_zdiag(Regs<R, NB> l, Regs<R, NB> p, int r0, int tb0, int r1, int tb1) {
+    double g = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int b0 = r0 >= 0 ? ((j >> r0) & 1) : tb0;
+        const int b1 = r1 >= 0 ? ((j >> r1) & 1) : tb1;
+        const double v = im_conj_mul(l.v[j], p.v[j]);
+        g += (b0 ^ b1) ? -v : v;
+    }
+    return g;
+}
+
+// FSIM: theta -> 2 Im(conj(l01) p10 + conj(l10) p01), phi -> 2 Im(conj(l11) p11)
+template <typename R, int NB, int B0, int B1>
+__device__ __forceinline__ double2 grad_fsim(Regs<R, NB> l, Regs<R, NB> p) {
+    double gt = 0.0, gp = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & ((1 << B0) | (1 << B1))) continue;
+        const int i1 = j | (1 << B1), i2 = j | (1 << B0), i3 = j | (1 << B0) | (1 << B1);
+        gt += 2.0 * (im_conj_mul(l.v[i1], p.v[i2]) + im_conj_mul(l.v[i2], p.v[i1]));
+        gp += 2.0 * im_conj_mul(l.v[i3], p.v[i3]);
+    }
+    return make_double2(gt, gp);
+}
+
+// U2 cotangent entry (a, b): sum over quads of lambda_a conj(phi_b)
+// (phi = state before the gate), real and imaginary part
+template <typename R, int NB, int B0, int B1>
+__device__ __forceinline__ double2 cot_u2(Regs<R, NB> l, Regs<R, NB> f, int a, int b) {
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & ((1 << B0) | (1 << B1))) continue;
+        const int i1 = j | (1 << B1), i2 = j | (1 << B0), i3 = j | (1 << B0) | (1 << B1);
+        const cx<R> la = sel(a == 0, l.v[j], sel(a == 1, l.v[i1], sel(a == 2, l.v[i2], l.v[i3])));
+        const cx<R> fb = sel(b == 0, f.v[j], sel(b == 1, f.v[i1], sel(b == 2, f.v[i2], f.v[i3])));
+        re += fma(double(la.re), double(fb.re), double(la.im) * double(fb.im));
+        im += fma(double(la.im), double(fb.re), -double(la.re) * double(fb.im));
+    }
+    return make_double2(re, im);
+}
+
+}  // namespace tcng

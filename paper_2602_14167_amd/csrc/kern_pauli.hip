@@ -1,0 +1,222 @@
+// Pauli-sum kernels: lambda = H psi and E = <psi|H|psi>.
+//
+// For a Pauli string P with X-mask x (qubits carrying X or Y) and Z-mask z
+// (qubits carrying Z or Y),  (P psi)_j = i^{#Y} (-1)^{popcount((j^x) & z)} psi_{j^x}
+// (from X|b> = |b^1>, Z|b> = (-1)^b |b>, Y = i X Z).  Terms sharing an X-mask
+// read the same partner amplitude psi_{j^x}, so H is applied group by group:
+//   (H psi)_j = psi_{j^x} * sum_{k in group} c_k i^{#Y_k} (-1)^{popcount((j^x) & z_k)}.
+// Inside a group, terms of equal coefficient form a class whose signed sum is
+// c * (n_terms - 2 * #odd parities): integer counting, no float adds per term.
+// E is accumulated in float64 (exact products of the float32 amplitudes),
+// reduced per wave by butterfly shuffles and per workgroup in a fixed order
+// (deterministic); the partial sums go to `epart` for a final fixed-order sum.
+// Measurement parallelism over terms (Sec. "Data Parallelism") is realised on
+// one GPU as parallelism over amplitudes with all terms of a group fused.
+#include "kernels.h"
+
+namespace tcng {
+
+namespace {
+
+constexpr int NTHREADS = 256;
+
+template <typename R>
+struct PTile {
+    static constexpr int ELEMS = (sizeof(R) == 4) ? (1 << 13) : (1 << 12);
+};
+
+__device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int8_t* lq) {
+    uint64_t g = l & ((1u << lo) - 1);
+    for (int i = lo; i < m; ++i) g |= uint64_t((l >> i) & 1) << lq[i];
+    return g;
+}
+
+__device__ __forceinline__ uint64_t tile_base(uint64_t tile, uint64_t tmask, int n) {
+    uint64_t base = 0;
+    int k = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((tmask >> q) & 1) continue;
+        base |= ((tile >> k) & 1) << q;
+        ++k;
+    }
+    return base;
+}
+
+__device__ __forceinline__ double wave_sum(double v, int width) {
+    for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+    return v;
+}
+
+// fixed-order workgroup sum of one double per thread (result valid in thread 0)
+__device__ double block_sum(double v, double* sh, int nthreads) {
+    const int width = nthreads < 64 ? nthreads : 64;
+    v = wave_sum(v, width);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (nthreads + 63) / 64; ++w) s += sh[w];
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// tiled: one pass handles every X-group whose mask lies inside its tile
+// ---------------------------------------------------------------------------
+template <typename R, int RB>
+__global__ void __launch_bounds__(NTHREADS)
+k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups, const PClass* __restrict__ classes,
+             const PTerm* __restrict__ terms, int pass_idx, int n_passes, const cx<R>* __restrict__ state,
+             cx<R>* __restrict__ costate, int accumulate, int64_t stride, int n, int64_t tiles_per_state, int wgs,
+             double* __restrict__ epart) {
+    __shared__ cx<R> lds[PTile<R>::ELEMS];
+    __shared__ double sh[NTHREADS / 64];
+    constexpr int NB = 1 << RB;
+    const PPass& P = passes[pass_idx];
+    const int m = P.m, lo = P.lo;
+    const uint64_t tmask = P.tile_mask;
+    const int8_t* lq = P.local_qubit;
+    const int nt = 1 << (m - RB);
+    const int t = threadIdx.x;
+    const int64_t b = blockIdx.x / wgs;
+    const int wg = int(blockIdx.x - b * wgs);
+    const cx<R>* psi = state + b * stride;
+    cx<R>* lam = costate ? costate + b * stride : nullptr;
+    double e_acc = 0.0;
+
+    for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
+        const uint64_t base = tile_base(uint64_t(tile), tmask, n);
+        __syncthreads();
+        // psi tile -> LDS; element l = it*nt + t (lane-consecutive, coalesced)
+#pragma unroll
+        for (int it = 0; it < NB; ++it) {
+            const uint32_t l = uint32_t(it * nt + t);
+            lds[l] = psi[base + loc2glob(l, lo, m, lq)];
+        }
+        __syncthreads();
+        // elements l = it*nt + t, CH at a time (few live registers per thread)
+        constexpr int CH = 4;
+        for (int c0 = 0; c0 < NB; c0 += CH) {
+            cx<R> acc[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const uint32_t l = uint32_t((c0 + i) * nt + t);
+                acc[i] = (lam && accumulate) ? lam[base + loc2glob(l, lo, m, lq)] : cx<R>{R(0), R(0)};
+            }
+            for (int g = P.group_begin; g < P.group_end; ++g) {
+                const PGroup G = groups[g];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) {
+                    const uint32_t l = uint32_t((c0 + i) * nt + t);
+                    const uint32_t lp = l ^ uint32_t(G.x_local);
+                    const cx<R> pp = lds[lp], own = lds[l];
+                    double cre = 0.0, cim = 0.0;
+                    for (int c = G.class_begin; c < G.class_end; ++c) {
+                        const PClass C = classes[c];
+                        int odd = 0;
+                        for (int k = C.term_begin; k < C.term_end; ++k) {
+                            const PTerm T = terms[k];
+                            const int tp = __popcll(base & T.z_out) & 1;   // tile-constant part
+                            odd += (__popc(lp & uint32_t(T.z_local)) + tp) & 1;
+                        }
+                        const double sgn = double(C.term_end - C.term_begin - 2 * odd);
+                        cre = fma(C.cre, sgn, cre);
+                        cim = fma(C.cim, sgn, cim);
+                    }
+                    // contribution = (cre + i cim) * psi_{l^x}
+                    const cx<R> cc = {R(cre), R(cim)};
+                    acc[i] = cfma(cc, pp, acc[i]);
+                    // E += Re(conj(psi_l) * contribution), float64
+                    const double rr = fma(double(own.re), double(pp.re), double(own.im) * double(pp.im));
+                    const double ri = fma(double(own.re), double(pp.im), -double(own.im) * double(pp.re));
+                    e_acc += cre * rr - cim * ri;
+                }
+            }
+            if (lam) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    lam[base + loc2glob(uint32_t((c0 + i) * nt + t), lo, m, lq)] = acc[i];
+            }
+        }
+    }
+    const double s = block_sum(e_acc, sh, nt);
+    if (t == 0) epart[(size_t(b) * n_passes + pass_idx) * wgs + wg] = s;
+}
+
+// ---------------------------------------------------------------------------
+// plain: one X-group over the whole state
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_pauli_group(const cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int accumulate, int64_t stride, int n,
+              uint64_t x, const PClassFull* __restrict__ classes, int class_begin, int class_end,
+              const PTermFull* __restrict__ terms, int wgs, double* __restrict__ epart, int row, int n_rows) {
+    __shared__ double sh[NTHREADS / 64];
+    const int64_t b = blockIdx.x / wgs;
+    const int wg = int(blockIdx.x - b * wgs);
+    const cx<R>* psi = state + b * stride;
+    cx<R>* lam = costate ? costate + b * stride : nullptr;
+    const uint64_t dim = uint64_t(1) << n;
+    double e_acc = 0.0;
+    for (uint64_t j = uint64_t(wg) * blockDim.x + threadIdx.x; j < dim; j += uint64_t(wgs) * blockDim.x) {
+        const uint64_t jp = j ^ x;
+        const cx<R> pp = psi[jp], pj = psi[j];
+        double cre = 0.0, cim = 0.0;
+        for (int c = class_begin; c < class_end; ++c) {
+            const PClassFull C = classes[c];
+            int odd = 0;
+            for (int k = C.term_begin; k < C.term_end; ++k) odd += __popcll(jp & terms[k].z) & 1;
+            const double s = double(C.term_end - C.term_begin - 2 * odd);
+            cre = fma(C.cre, s, cre);
+            cim = fma(C.cim, s, cim);
+        }
+        const cx<R> cc = {R(cre), R(cim)};
+        if (lam) {
+            const cx<R> prev = accumulate ? lam[j] : cx<R>{R(0), R(0)};
+            lam[j] = cfma(cc, pp, prev);
+        }
+        const double rr = fma(double(pj.re), double(pp.re), double(pj.im) * double(pp.im));
+        const double ri = fma(double(pj.re), double(pp.im), -double(pj.im) * double(pp.re));
+        e_acc += cre * rr - cim * ri;
+    }
+    const double s = block_sum(e_acc, sh, blockDim.x);
+    if (threadIdx.x == 0) epart[(size_t(b) * n_rows + row) * wgs + wg] = s;
+}
+
+}  // namespace
+
+template <typename R, int RB>
+hipError_t launch_pauli_tile(const DevPauliPlan& dp, int pass_idx, int n_passes, int m, const void* state,
+                             void* costate, bool accumulate, int64_t stride, int n, int64_t batch, int wgs,
+                             double* epart, hipStream_t st) {
+    const int64_t tiles = int64_t(1) << (n - m);
+    const int nt = 1 << (m - RB);
+    hipLaunchKernelGGL((k_pauli_tile<R, RB>), dim3(unsigned(wgs * batch)), dim3(nt), 0, st, dp.passes, dp.groups,
+                       dp.classes, dp.terms, pass_idx, n_passes, static_cast<const cx<R>*>(state),
+                       static_cast<cx<R>*>(costate), int(accumulate), stride, n, tiles, wgs, epart);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_pauli_group(const void* state, void* costate, bool accumulate, int64_t stride, int n, int64_t batch,
+                              uint64_t x, const PClassFull* classes, int class_begin, int class_end,
+                              const PTermFull* terms, int wgs, double* epart, int row, int n_rows, hipStream_t st) {
+    hipLaunchKernelGGL((k_pauli_group<R>), dim3(unsigned(wgs * batch)), dim3(NTHREADS), 0, st,
+                       static_cast<const cx<R>*>(state), static_cast<cx<R>*>(costate), int(accumulate), stride, n, x,
+                       classes, class_begin, class_end, terms, wgs, epart, row, n_rows);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pauli_tile<float, 5>(const DevPauliPlan&, int, int, int, const void*, void*, bool, int64_t,
+                                                int, int64_t, int, double*, hipStream_t);
+template hipError_t launch_pauli_tile<double, 4>(const DevPauliPlan&, int, int, int, const void*, void*, bool,
+                                                 int64_t, int, int64_t, int, double*, hipStream_t);
+template hipError_t launch_pauli_group<float>(const void*, void*, bool, int64_t, int, int64_t, uint64_t,
+                                              const PClassFull*, int, int, const PTermFull*, int, double*, int, int,
+                                              hipStream_t);
+template hipError_t launch_pauli_group<double>(const void*, void*, bool, int64_t, int, int64_t, uint64_t,
+                                               const PClassFull*, int, int, const PTermFull*, int, double*, int, int,
+                                               hipStream_t);
+
+}  // namespace tcng

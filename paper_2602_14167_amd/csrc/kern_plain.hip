@@ -1,0 +1,493 @@
+// Streaming per-gate kernels (the unfused path and tcng_apply_gate), state
+// initialisation, and the final fixed-order reductions.
+//
+// One-qubit gate on qubit q: every amplitude pair (j, j | 2^q) with bit q of
+// j clear is multiplied by the 2x2 matrix.  For q >= 1 a thread owns two
+// neighbouring pairs, so both halves are read as 16-byte vectors of
+// consecutive amplitudes (fully coalesced for every q, including the low
+// qubits whose partners sit in the same 64-byte run); for q = 0 the pair is
+// itself one 16-byte vector.  Two-qubit gates work on quads the same way.
+// Gate matrices are rebuilt per batch member from the device angles, so one
+// launch serves every parameter set of a batch (blockIdx.y = member).
+#include "gates.h"
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace tcng {
+
+namespace {
+
+constexpr int NTHREADS = 256;
+
+__device__ __forceinline__ uint64_t insert0(uint64_t v, int q) {
+    const uint64_t lowm = (uint64_t(1) << q) - 1;
+    return ((v & ~lowm) << 1) | (v & lowm);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NTHREADS / 64; ++w) s += sh[w];
+    return s;
+}
+
+// build the (possibly inverted) 2x2 / 4x4 matrix of a gate for batch member b
+template <typename R>
+__device__ __forceinline__ void gate_mat1(int kind, const R* prm, int p0, const cx<R>* cm, int mat,
+                                          const cx<R>* umat, bool inv, cx<R> u[4]) {
+    if (umat) {
+        u[0] = umat[0]; u[1] = umat[1]; u[2] = umat[2]; u[3] = umat[3];
+    } else if (kind_diagonal(kind)) {
+        cx<R> d[2];
+        diag1<R>(kind, prm, p0, d);
+        u[0] = d[0]; u[1] = {R(0), R(0)}; u[2] = {R(0), R(0)}; u[3] = d[1];
+    } else {
+        mat1<R>(kind, prm, p0, cm, mat, u);
+    }
+    if (inv) dagger_inplace<R, 2>(u);
+}
+
+template <typename R>
+__device__ __forceinline__ void gate_mat2(int kind, const R* prm, int p0, int p1, const cx<R>* cm, int mat,
+                                          const cx<R>* umat, bool inv, cx<R> u[16]) {
+    if (umat) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = umat[i];
+    } else if (kind == K_FSIM || kind == K_U2) {
+        mat2<R>(kind, prm, p0, p1, cm, mat, u);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = {R(0), R(0)};
+        if (kind == K_CNOT) {
+            u[0] = {R(1), R(0)}; u[5] = {R(1), R(0)}; u[11] = {R(1), R(0)}; u[14] = {R(1), R(0)};
+        } else {
+            cx<R> d[4];
+            diag2<R>(kind, prm, p0, d);
+            u[0] = d[0]; u[5] = d[1]; u[10] = d[2]; u[15] = d[3];
+        }
+    }
+    if (inv) dagger_inplace<R, 4>(u);
+}
+
+template <typename R>
+__device__ __forceinline__ void mv2(const cx<R>* u, cx<R>& a0, cx<R>& a1) {
+    const cx<R> x0 = a0, x1 = a1;
+    a0 = cfma(u[1], x1, u[0] * x0);
+    a1 = cfma(u[3], x1, u[2] * x0);
+}
+
+template <typename R>
+__device__ __forceinline__ void mv4(const cx<R>* u, cx<R>* x) {
+    const cx<R> x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = cfma(u[4 * a + 3], x3, cfma(u[4 * a + 2], x2, cfma(u[4 * a + 1], x1, u[4 * a] * x0)));
+}
+
+// ---------------------------------------------------------------------------
+// forward one-qubit gate
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_gate1(cx<R>* __restrict__ state, int64_t stride, int n, int q, int kind, int p0, int mat,
+        const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm, const cx<R>* __restrict__ umat,
+        int inv) {
+    const int64_t b = blockIdx.y;
+    cx<R>* psi = state + b * stride;
+    cx<R> u[4];
+    gate_mat1<R>(kind, params ? params + b * pstride : nullptr, p0, cm, mat, umat, inv != 0, u);
+    const uint64_t npairs = uint64_t(1) << (n - 1);
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    if (sizeof(R) == 4 && n >= 2) {
+        // two pairs per thread, 16-byte accesses
+        const uint64_t nunits = npairs >> 1;
+        for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nunits; w += step) {
+            if (q == 0) {
+                cx<R>* p = psi + 4 * w;
+                cx<R> a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
+                mv2(u, a0, a1);
+                mv2(u, a2, a3);
+                p[0] = a0; p[1] = a1; p[2] = a2; p[3] = a3;
+            } else {
+                const uint64_t i0 = insert0(2 * w, q);
+                cx<R>* p0p = psi + i0;
+                cx<R>* p1p = psi + i0 + (uint64_t(1) << q);
+                cx<R> a0 = p0p[0], a1 = p0p[1], c0 = p1p[0], c1 = p1p[1];
+                mv2(u, a0, c0);
+                mv2(u, a1, c1);
+                p0p[0] = a0; p0p[1] = a1; p1p[0] = c0; p1p[1] = c1;
+            }
+        }
+    } else {
+        for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < npairs; w += step) {
+            const uint64_t i0 = insert0(w, q), i1 = i0 | (uint64_t(1) << q);
+            cx<R> a0 = psi[i0], a1 = psi[i1];
+            mv2(u, a0, a1);
+            psi[i0] = a0;
+            psi[i1] = a1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward two-qubit gate on (q0 = MSB of the local index, q1)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_gate2(cx<R>* __restrict__ state, int64_t stride, int n, int q0, int q1, int kind, int p0, int p1, int mat,
+        const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm, const cx<R>* __restrict__ umat,
+        int inv) {
+    const int64_t b = blockIdx.y;
+    cx<R>* psi = state + b * stride;
+    cx<R> u[16];
+    gate_mat2<R>(kind, params ? params + b * pstride : nullptr, p0, p1, cm, mat, umat, inv != 0, u);
+    const int qa = q0 < q1 ? q0 : q1, qb = q0 < q1 ? q1 : q0;
+    const uint64_t m0 = uint64_t(1) << q0, m1 = uint64_t(1) << q1;
+    const uint64_t nquads = uint64_t(1) << (n - 2);
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nquads; w += step) {
+        const uint64_t i = insert0(insert0(w, qa), qb);
+        cx<R> x[4] = {psi[i], psi[i | m1], psi[i | m0], psi[i | m0 | m1]};
+        mv4(u, x);
+        psi[i] = x[0]; psi[i | m1] = x[1]; psi[i | m0] = x[2]; psi[i | m0 | m1] = x[3];
+    }
+}
+
+// generic k-qubit dense matrix (k <= 5), matrix staged in LDS
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_gatek(cx<R>* __restrict__ state, int64_t stride, int n, int k, uint64_t qpack, const cx<R>* __restrict__ umat) {
+    __shared__ cx<R> U[32 * 32];
+    const int kd = 1 << k;
+    for (int i = threadIdx.x; i < kd * kd; i += blockDim.x) U[i] = umat[i];
+    __syncthreads();
+    int q[5], qs[5];
+    for (int t = 0; t < k; ++t) q[t] = int((qpack >> (6 * t)) & 63);
+    for (int t = 0; t < k; ++t) qs[t] = q[t];
+    for (int a = 0; a < k; ++a)          // ascending order for the zero-bit insertion
+        for (int c = a + 1; c < k; ++c)
+            if (qs[c] < qs[a]) { int tmp = qs[a]; qs[a] = qs[c]; qs[c] = tmp; }
+    const int64_t b = blockIdx.y;
+    cx<R>* psi = state + b * stride;
+    const uint64_t ngroups = uint64_t(1) << (n - k);
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < ngroups; w += step) {
+        uint64_t base = w;
+        for (int t = 0; t < k; ++t) base = insert0(base, qs[t]);
+        cx<R> x[32], y[32];
+        for (int a = 0; a < kd; ++a) {
+            uint64_t idx = base;
+            for (int t = 0; t < k; ++t) idx |= uint64_t((a >> (k - 1 - t)) & 1) << q[t];
+            x[a] = psi[idx];
+        }
+        for (int a = 0; a < kd; ++a) {
+            cx<R> s = {R(0), R(0)};
+            for (int c = 0; c < kd; ++c) s = cfma(U[a * kd + c], x[c], s);
+            y[a] = s;
+        }
+        for (int a = 0; a < kd; ++a) {
+            uint64_t idx = base;
+            for (int t = 0; t < k; ++t) idx |= uint64_t((a >> (k - 1 - t)) & 1) << q[t];
+            psi[idx] = y[a];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse sweep, one gate: gradient then un-compute psi and lambda
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_rev1(cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int64_t stride, int n, int q, int kind, int p0,
+       int mat, const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm, int slot, int wgs,
+       double* __restrict__ part, int total_slots) {
+    __shared__ double sh[NTHREADS / 64];
+    const int64_t b = blockIdx.x / wgs;
+    const int wg = int(blockIdx.x - b * wgs);
+    cx<R>* psi = state + b * stride;
+    cx<R>* lam = costate + b * stride;
+    cx<R> u[4];
+    gate_mat1<R>(kind, params ? params + b * pstride : nullptr, p0, cm, mat, nullptr, true, u);
+    const uint64_t npairs = uint64_t(1) << (n - 1);
+    double g = 0.0;
+    for (uint64_t w = uint64_t(wg) * blockDim.x + threadIdx.x; w < npairs; w += uint64_t(wgs) * blockDim.x) {
+        const uint64_t i0 = insert0(w, q), i1 = i0 | (uint64_t(1) << q);
+        cx<R> a0 = psi[i0], a1 = psi[i1], l0 = lam[i0], l1 = lam[i1];
+        if (slot >= 0) {
+            if (kind == K_RX) g += im_conj_mul(l0, a1) + im_conj_mul(l1, a0);
+            else if (kind == K_RY) g += re_conj_mul(l1, a0) - re_conj_mul(l0, a1);
+            else g += im_conj_mul(l0, a0) - im_conj_mul(l1, a1);   // RZ
+        }
+        mv2(u, a0, a1);
+        mv2(u, l0, l1);
+        psi[i0] = a0; psi[i1] = a1; lam[i0] = l0; lam[i1] = l1;
+    }
+    if (slot >= 0) {
+        const double s = block_sum(g, sh);
+        if (threadIdx.x == 0) part[(size_t(b) * total_slots + slot) * wgs + wg] = s;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_rev2(cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int64_t stride, int n, int q0, int q1, int kind,
+       int p0, int p1, int mat, const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm, int slot,
+       int wgs, double* __restrict__ part, int total_slots) {
+    __shared__ double sh[NTHREADS / 64];
+    const int64_t b = blockIdx.x / wgs;
+    const int wg = int(blockIdx.x - b * wgs);
+    cx<R>* psi = state + b * stride;
+    cx<R>* lam = costate + b * stride;
+    cx<R> u[16];
+    gate_mat2<R>(kind, params ? params + b * pstride : nullptr, p0, p1, cm, mat, nullptr, true, u);
+    const int qa = q0 < q1 ? q0 : q1, qb = q0 < q1 ? q1 : q0;
+    const uint64_t m0 = uint64_t(1) << q0, m1 = uint64_t(1) << q1;
+    const uint64_t nquads = uint64_t(1) << (n - 2);
+    const int nacc = (kind == K_U2) ? 32 : (kind == K_FSIM ? 2 : 1);
+    double G[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) G[i] = 0.0;
+    for (uint64_t w = uint64_t(wg) * blockDim.x + threadIdx.x; w < nquads; w += uint64_t(wgs) * blockDim.x) {
+        const uint64_t i = insert0(insert0(w, qa), qb);
+        const uint64_t idx[4] = {i, i | m1, i | m0, i | m0 | m1};
+        cx<R> x[4], l[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) { x[a] = psi[idx[a]]; l[a] = lam[idx[a]]; }
+        if (slot >= 0) {
+            if (kind == K_RZZ) {
+                G[0] += im_conj_mul(l[0], x[0]) - im_conj_mul(l[1], x[1]) - im_conj_mul(l[2], x[2]) +
+                        im_conj_mul(l[3], x[3]);
+            } else if (kind == K_FSIM) {
+                G[0] += 2.0 * (im_conj_mul(l[1], x[2]) + im_conj_mul(l[2], x[1]));
+                G[1] += 2.0 * im_conj_mul(l[3], x[3]);
+            }
+        }
+        mv4(u, x);
+        if (slot >= 0 && kind == K_U2) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    G[2 * (4 * a + c)] += fma(double(l[a].re), double(x[c].re), double(l[a].im) * double(x[c].im));
+                    G[2 * (4 * a + c) + 1] += fma(double(l[a].im), double(x[c].re), -double(l[a].re) * double(x[c].im));
+                }
+        }
+        mv4(u, l);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) { psi[idx[a]] = x[a]; lam[idx[a]] = l[a]; }
+    }
+    if (slot >= 0) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            if (i >= nacc) break;
+            const double s = block_sum(G[i], sh);
+            if (threadIdx.x == 0) part[(size_t(b) * total_slots + slot + i) * wgs + wg] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NTHREADS)
+k_init(cx<R>* __restrict__ state, int64_t stride, int n, const cx<R>* __restrict__ amps, int64_t basis) {
+    const int64_t b = blockIdx.y;
+    cx<R>* psi = state + b * stride;
+    const uint64_t dim = uint64_t(1) << n;
+    for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < dim; j += uint64_t(gridDim.x) * blockDim.x)
+        psi[j] = amps ? amps[j] : cx<R>{R(j == uint64_t(basis) ? 1 : 0), R(0)};
+}
+
+__global__ void k_zero(double* __restrict__ p, size_t count) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x)
+        p[i] = 0.0;
+}
+
+// final sums: one thread per (member, output), fixed order everywhere
+__global__ void k_finish(const double* __restrict__ part, int total_slots, int wgs, const int32_t* __restrict__ slot_ptr,
+                         const int32_t* __restrict__ slot_idx, int n_params, const double* __restrict__ epart,
+                         int erows, int ewgs, int64_t batch, double* __restrict__ energy, double* __restrict__ grad,
+                         double* __restrict__ gate_grad, const int32_t* __restrict__ gate_slot,
+                         const double* __restrict__ u2m, const int32_t* __restrict__ gate_mat, int n_gates) {
+    const int64_t per = int64_t(1) + n_params + (gate_grad ? int64_t(n_gates) : 0);
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= per * batch) return;
+    const int64_t b = tid / per;
+    const int64_t k = tid - b * per;
+    auto slot_sum = [&](int s) {
+        double v = 0.0;
+        const double* p = part + (size_t(b) * total_slots + s) * wgs;
+        for (int w = 0; w < wgs; ++w) v += p[w];
+        return v;
+    };
+    if (k == 0) {
+        double e = 0.0;
+        const double* p = epart + size_t(b) * erows * ewgs;
+        for (int i = 0; i < erows * ewgs; ++i) e += p[i];
+        energy[b] = e;
+    } else if (k <= n_params) {
+        const int p = int(k - 1);
+        double g = 0.0;
+        for (int i = slot_ptr[p]; i < slot_ptr[p + 1]; ++i) g += slot_sum(slot_idx[i]);
+        grad[size_t(b) * n_params + p] = g;
+    } else {
+        // per U2 gate: dE/dalpha_k = Im tr(G^dag P_k U), P_k = sigma_a (x) sigma_b, k = 4a + b - 1
+        const int gi = int(k - 1 - n_params);
+        double* out = gate_grad + (size_t(b) * n_gates + gi) * 15;
+        const int s0 = gate_slot[gi];
+        if (s0 < 0) {
+            for (int i = 0; i < 15; ++i) out[i] = 0.0;
+            return;
+        }
+        double Gr[16], Gi[16];
+        for (int i = 0; i < 16; ++i) { Gr[i] = slot_sum(s0 + 2 * i); Gi[i] = slot_sum(s0 + 2 * i + 1); }
+        const double* U = u2m + size_t(gate_mat[gi]) * 32;
+        // single-qubit Paulis: entry (r, c) of sigma_a as (re, im)
+        auto sig = [](int a, int r, int c, double& re, double& im) {
+            re = 0.0; im = 0.0;
+            if (a == 0) re = (r == c) ? 1.0 : 0.0;
+            else if (a == 1) re = (r != c) ? 1.0 : 0.0;
+            else if (a == 2) im = (r == c) ? 0.0 : (r == 0 ? -1.0 : 1.0);
+            else re = (r == c) ? (r == 0 ? 1.0 : -1.0) : 0.0;
+        };
+        for (int kk = 0; kk < 15; ++kk) {
+            const int a = (kk + 1) >> 2, c = (kk + 1) & 3;
+            double tr_im = 0.0;
+            for (int x = 0; x < 4; ++x)
+                for (int y = 0; y < 4; ++y) {
+                    // (P U)[y][x] = sum_z P[y][z] U[z][x]
+                    double pur = 0.0, pui = 0.0;
+                    for (int z = 0; z < 4; ++z) {
+                        double s1r, s1i, s2r, s2i;
+                        sig(a, y >> 1, z >> 1, s1r, s1i);
+                        sig(c, y & 1, z & 1, s2r, s2i);
+                        const double pr = s1r * s2r - s1i * s2i, pi = s1r * s2i + s1i * s2r;
+                        const double ur = U[2 * (4 * z + x)], ui = U[2 * (4 * z + x) + 1];
+                        pur += pr * ur - pi * ui;
+                        pui += pr * ui + pi * ur;
+                    }
+                    // conj(G[y][x]) * (PU)[y][x]
+                    const double gr = Gr[4 * y + x], gim = Gi[4 * y + x];
+                    tr_im += gr * pui - gim * pur;
+                }
+            out[kk] = tr_im;
+        }
+    }
+}
+
+}  // namespace
+
+template <typename R>
+static unsigned grid_for(uint64_t work) {
+    uint64_t blocks = (work + NTHREADS - 1) / NTHREADS;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    return unsigned(blocks);
+}
+
+template <typename R>
+hipError_t launch_gate1(void* state, int64_t stride, int n, int64_t batch, int q, int kind, int p0, int mat,
+                        const void* params, int64_t pstride, const void* cmats, const void* umat, bool inv,
+                        hipStream_t st) {
+    const uint64_t work = (sizeof(R) == 4 && n >= 2) ? (uint64_t(1) << (n - 2)) : (uint64_t(1) << (n - 1));
+    hipLaunchKernelGGL((k_gate1<R>), dim3(grid_for<R>(work), unsigned(batch)), dim3(NTHREADS), 0, st,
+                       static_cast<cx<R>*>(state), stride, n, q, kind, p0, mat, static_cast<const R*>(params), pstride,
+                       static_cast<const cx<R>*>(cmats), static_cast<const cx<R>*>(umat), int(inv));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gate2(void* state, int64_t stride, int n, int64_t batch, int q0, int q1, int kind, int p0, int p1,
+                        int mat, const void* params, int64_t pstride, const void* cmats, const void* umat, bool inv,
+                        hipStream_t st) {
+    hipLaunchKernelGGL((k_gate2<R>), dim3(grid_for<R>(uint64_t(1) << (n - 2)), unsigned(batch)), dim3(NTHREADS), 0,
+                       st, static_cast<cx<R>*>(state), stride, n, q0, q1, kind, p0, p1, mat,
+                       static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats),
+                       static_cast<const cx<R>*>(umat), int(inv));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gatek(void* state, int64_t stride, int n, int64_t batch, const int32_t* qubits, int k,
+                        const void* umat, hipStream_t st) {
+    uint64_t qpack = 0;
+    for (int t = 0; t < k; ++t) qpack |= uint64_t(qubits[t]) << (6 * t);
+    hipLaunchKernelGGL((k_gatek<R>), dim3(grid_for<R>(uint64_t(1) << (n - k)), unsigned(batch)), dim3(NTHREADS), 0,
+                       st, static_cast<cx<R>*>(state), stride, n, k, qpack, static_cast<const cx<R>*>(umat));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_rev1(void* state, void* costate, int64_t stride, int n, int64_t batch, int q, int kind, int p0,
+                       int mat, const void* params, int64_t pstride, const void* cmats, int slot, int wgs,
+                       double* part, int total_slots, hipStream_t st) {
+    hipLaunchKernelGGL((k_rev1<R>), dim3(unsigned(wgs * batch)), dim3(NTHREADS), 0, st, static_cast<cx<R>*>(state),
+                       static_cast<cx<R>*>(costate), stride, n, q, kind, p0, mat, static_cast<const R*>(params),
+                       pstride, static_cast<const cx<R>*>(cmats), slot, wgs, part, total_slots);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_rev2(void* state, void* costate, int64_t stride, int n, int64_t batch, int q0, int q1, int kind,
+                       int p0, int p1, int mat, const void* params, int64_t pstride, const void* cmats, int slot,
+                       int wgs, double* part, int total_slots, hipStream_t st) {
+    hipLaunchKernelGGL((k_rev2<R>), dim3(unsigned(wgs * batch)), dim3(NTHREADS), 0, st, static_cast<cx<R>*>(state),
+                       static_cast<cx<R>*>(costate), stride, n, q0, q1, kind, p0, p1, mat,
+                       static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats), slot, wgs, part,
+                       total_slots);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_init(void* state, int64_t stride, int n, int64_t batch, const void* amps_in, int64_t basis,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((k_init<R>), dim3(grid_for<R>(uint64_t(1) << n), unsigned(batch)), dim3(NTHREADS), 0, st,
+                       static_cast<cx<R>*>(state), stride, n, static_cast<const cx<R>*>(amps_in), basis);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, size_t count, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero, dim3(unsigned(blocks)), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const double* part, int total_slots, int wgs, const int32_t* slot_ptr,
+                         const int32_t* slot_idx, int n_params, const double* epart, int erows, int ewgs,
+                         int64_t batch, double* energy, double* grad, double* gate_grad, const int32_t* gate_slot,
+                         const double* u2_mats_c128, const int32_t* gate_mat, int n_gates, hipStream_t st) {
+    const int64_t per = 1 + n_params + (gate_grad ? n_gates : 0);
+    const int64_t work = per * batch;
+    hipLaunchKernelGGL(k_finish, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, part, total_slots, wgs,
+                       slot_ptr, slot_idx, n_params, epart, erows, ewgs, batch, energy, grad, gate_grad, gate_slot,
+                       u2_mats_c128, gate_mat, n_gates);
+    return hipGetLastError();
+}
+
+#define TCNG_INST(R)                                                                                              \
+    template hipError_t launch_gate1<R>(void*, int64_t, int, int64_t, int, int, int, int, const void*, int64_t,    \
+                                        const void*, const void*, bool, hipStream_t);                             \
+    template hipError_t launch_gate2<R>(void*, int64_t, int, int64_t, int, int, int, int, int, int, const void*,   \
+                                        int64_t, const void*, const void*, bool, hipStream_t);                    \
+    template hipError_t launch_gatek<R>(void*, int64_t, int, int64_t, const int32_t*, int, const void*,            \
+                                        hipStream_t);                                                             \
+    template hipError_t launch_rev1<R>(void*, void*, int64_t, int, int64_t, int, int, int, int, const void*,       \
+                                       int64_t, const void*, int, int, double*, int, hipStream_t);                \
+    template hipError_t launch_rev2<R>(void*, void*, int64_t, int, int64_t, int, int, int, int, int, int,          \
+                                       const void*, int64_t, const void*, int, int, double*, int, hipStream_t);   \
+    template hipError_t launch_init<R>(void*, int64_t, int, int64_t, const void*, int64_t, hipStream_t);
+TCNG_INST(float)
+TCNG_INST(double)
+
+}  // namespace tcng

@@ -1,0 +1,488 @@
+// Tiled circuit passes (forward sweep and adjoint reverse sweep).
+//
+// One workgroup owns a tile: the 2^m amplitudes whose index bits outside the
+// pass's qubit set T are fixed.  The tile is streamed HBM -> LDS with 16-byte
+// coalesced accesses (T always contains the low `lo` qubits, so every tile is
+// a set of contiguous 2^lo-amplitude runs), then processed in register
+// phases: each thread holds 2^RB amplitudes whose local index bits are the
+// phase's register bits, applies the phase's gates without any exchange, and
+// hands the tile back to LDS for the next phase's bit assignment.  One pass
+// thus applies many gates per HBM round trip (the paper's "operator fusion"
+// under JIT, Sec. "Foundations Recap", done here in space rather than by
+// multiplying matrices).
+//
+// The reverse sweep holds the state psi and the costate lambda = H psi pushed
+// back through the circuit, evaluates each angle's derivative
+// 2 Im <lambda|G|psi> in float64 and un-computes both by applying inverse
+// gates (adjoint method: nothing is stored per gate).
+#include "gates.h"
+#include "kernels.h"
+
+namespace tcng {
+
+namespace {
+
+constexpr int NTHREADS = 256;
+
+template <typename R>
+struct Tile {
+    static constexpr int ELEMS = (sizeof(R) == 4) ? (1 << 13) : (1 << 12);   // 64 KiB of LDS
+};
+
+// amplitude index offset of a local index l (disjoint bit sets add)
+__device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int8_t* lq) {
+    uint64_t g = l & ((1u << lo) - 1);
+    for (int i = lo; i < m; ++i) g |= uint64_t((l >> i) & 1) << lq[i];
+    return g;
+}
+
+// tile base: the tile index's bits deposited into the qubits outside the tile
+__device__ __forceinline__ uint64_t tile_base(uint64_t tile, uint64_t tmask, int n) {
+    uint64_t base = 0;
+    int k = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((tmask >> q) & 1) continue;
+        base |= ((tile >> k) & 1) << q;
+        ++k;
+    }
+    return base;
+}
+
+// LDS position of local index l: XOR-swizzle bits 1..3 with bits 5..7 so that
+// strided register reads spread over banks; bit 0 is untouched so 16-byte
+// pairs of complex64 stay adjacent.
+__device__ __forceinline__ uint32_t swz(uint32_t l) { return l ^ (((l >> 5) & 7u) << 1); }
+
+// 16-byte vector access of the state
+template <typename R>
+struct V16;
+template <>
+struct V16<float> {
+    static constexpr int N = 2;
+    __device__ static void load(const cx<float>* p, cx<float>* o) {
+        float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = {v.x, v.y};
+        o[1] = {v.z, v.w};
+    }
+    __device__ static void store(cx<float>* p, const cx<float>* o) {
+        *reinterpret_cast<float4*>(p) = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
+    }
+};
+template <>
+struct V16<double> {
+    static constexpr int N = 1;
+    __device__ static void load(const cx<double>* p, cx<double>* o) {
+        double2 v = *reinterpret_cast<const double2*>(p);
+        o[0] = {v.x, v.y};
+    }
+    __device__ static void store(cx<double>* p, const cx<double>* o) {
+        *reinterpret_cast<double2*>(p) = make_double2(o[0].re, o[0].im);
+    }
+};
+
+struct PassInfo {
+    int m, lo;
+    uint64_t tmask;
+    const int8_t* lq;   // local bit -> qubit, read from the plan in global memory
+};
+
+__device__ __forceinline__ PassInfo read_pass(const Pass& P) {
+    PassInfo pi;
+    pi.m = P.m;
+    pi.lo = P.lo;
+    pi.tmask = P.tile_mask;
+    pi.lq = P.local_qubit;
+    return pi;
+}
+
+// HBM -> LDS (coalesced: lane-consecutive 16-byte chunks of local index space)
+template <typename R, int RB>
+__device__ __forceinline__ void tile_load(cx<R>* lds, const cx<R>* psi, uint64_t base, const PassInfo& pi, int t,
+                                          int nt) {
+    constexpr int VN = V16<R>::N;
+    const int iters = (1 << RB) / VN;
+    const uint64_t off_t = loc2glob(uint32_t(t * VN), pi.lo, pi.m, pi.lq);
+    cx<R> v[(1 << RB)];
+#pragma unroll
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t e0 = uint32_t(it * nt * VN);
+        const uint64_t g = base + loc2glob(e0, pi.lo, pi.m, pi.lq) + off_t;
+        V16<R>::load(psi + g, &v[it * VN]);
+    }
+#pragma unroll
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t e = uint32_t((it * nt + t) * VN);
+#pragma unroll
+        for (int k = 0; k < VN; ++k) lds[swz(e + k)] = v[it * VN + k];
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void tile_store(const cx<R>* lds, cx<R>* psi, uint64_t base, const PassInfo& pi, int t,
+                                           int nt) {
+    constexpr int VN = V16<R>::N;
+    const int iters = (1 << RB) / VN;
+    const uint64_t off_t = loc2glob(uint32_t(t * VN), pi.lo, pi.m, pi.lq);
+#pragma unroll
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t e = uint32_t((it * nt + t) * VN);
+        cx<R> v[VN];
+#pragma unroll
+        for (int k = 0; k < VN; ++k) v[k] = lds[swz(e + k)];
+        const uint64_t g = base + loc2glob(uint32_t(it * nt * VN), pi.lo, pi.m, pi.lq) + off_t;
+        V16<R>::store(psi + g, v);
+    }
+}
+
+// register <-> LDS for a phase
+struct PhaseMap {
+    uint32_t tpart;
+    uint32_t rbit[MAX_RB];
+};
+
+template <int RB>
+__device__ __forceinline__ PhaseMap phase_map(const Phase& F, int t, int m) {
+    PhaseMap pm;
+    uint32_t rmask = 0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        pm.rbit[i] = 1u << F.R[i];
+        rmask |= pm.rbit[i];
+    }
+    // deposit the thread index into the non-register local bits
+    uint32_t tp = 0;
+    int k = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((rmask >> b) & 1) continue;
+        tp |= uint32_t((t >> k) & 1) << b;
+        ++k;
+    }
+    pm.tpart = tp;
+    return pm;
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t jpart(const PhaseMap& pm, int j) {
+    uint32_t p = 0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+        if ((j >> i) & 1) p |= pm.rbit[i];
+    return p;
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> regs_from_lds(const cx<R>* lds, const PhaseMap& pm) {
+    Regs<R, (1 << RB)> a;
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) a.v[j] = lds[swz(pm.tpart | jpart<RB>(pm, j))];
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ void regs_to_lds(Regs<R, (1 << RB)> a, cx<R>* lds, const PhaseMap& pm) {
+#pragma unroll
+    for (int j = 0; j < (1 << RB); ++j) lds[swz(pm.tpart | jpart<RB>(pm, j))] = a.v[j];
+}
+
+// ---------------------------------------------------------------------------
+// dispatch on the register bit positions (compile-time register indices)
+// ---------------------------------------------------------------------------
+#define TCNG_PAIRS(X) X(0, 1) X(0, 2) X(0, 3) X(0, 4) X(1, 0) X(1, 2) X(1, 3) X(1, 4) X(2, 0) X(2, 1) \
+    X(2, 3) X(2, 4) X(3, 0) X(3, 1) X(3, 2) X(3, 4) X(4, 0) X(4, 1) X(4, 2) X(4, 3)
+#define TCNG_SINGLES(X) X(0) X(1) X(2) X(3) X(4)
+
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> dense1_at(Regs<R, (1 << RB)> a, int r, M2<R> u) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_dense1<R, (1 << RB), B>(a, u); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> cx_at(Regs<R, (1 << RB)> a, int rt, int rc, int tb) {
+    switch (rt) {
+#define C1(B) case B: if constexpr (B < RB) a = app_cx<R, (1 << RB), B>(a, rc, tb); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> dense2_at(Regs<R, (1 << RB)> a, int r0, int r1, M4<R> u) {
+    switch (r0 * 8 + r1) {
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) a = app_dense2<R, (1 << RB), B0, B1>(a, u); break;
+        TCNG_PAIRS(C2)
+#undef C2
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ double grad_rot1_at(int kind, int r, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
+    double g = 0.0;
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) g = grad_rot1<R, (1 << RB), B>(kind, l, p); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return g;
+}
+template <typename R, int RB>
+__device__ __forceinline__ double2 grad_fsim_at(int r0, int r1, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
+    double2 g = make_double2(0.0, 0.0);
+    switch (r0 * 8 + r1) {
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) g = grad_fsim<R, (1 << RB), B0, B1>(l, p); break;
+        TCNG_PAIRS(C2)
+#undef C2
+        default: break;
+    }
+    return g;
+}
+template <typename R, int RB>
+__device__ __forceinline__ double2 cot_u2_at(int r0, int r1, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> f, int a, int b) {
+    double2 g = make_double2(0.0, 0.0);
+    switch (r0 * 8 + r1) {
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) g = cot_u2<R, (1 << RB), B0, B1>(l, f, a, b); break;
+        TCNG_PAIRS(C2)
+#undef C2
+        default: break;
+    }
+    return g;
+}
+
+// apply one op (forward, or its inverse when INV) to the register block
+template <typename R, int RB, bool INV>
+__device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, const Op& op, uint32_t tpart,
+                                                      const R* prm, const cx<R>* cm) {
+    const int tb0 = op.lb0 >= 0 ? int((tpart >> op.lb0) & 1) : 0;
+    const int tb1 = op.lb1 >= 0 ? int((tpart >> op.lb1) & 1) : 0;
+    switch (op.type) {
+        case OP_DENSE1: {
+            M2<R> u;
+            mat1<R>(op.kind, prm, op.p0, cm, op.mat, u.e);
+            if (INV) dagger_inplace<R, 2>(u.e);
+            a = dense1_at<R, RB>(a, op.r0, u);
+            break;
+        }
+        case OP_DIAG1: {
+            D4<R> d;
+            diag1<R>(op.kind, prm, op.p0, d.e);
+            if (INV) { d.e[0] = conj(d.e[0]); d.e[1] = conj(d.e[1]); }
+            a = app_diag<R, (1 << RB)>(a, op.r0, tb0, -1, 0, false, d);
+            break;
+        }
+        case OP_CX:
+            a = cx_at<R, RB>(a, op.r1, op.r0, tb0);
+            break;
+        case OP_DENSE2: {
+            M4<R> u;
+            mat2<R>(op.kind, prm, op.p0, op.p1, cm, op.mat, u.e);
+            if (INV) dagger_inplace<R, 4>(u.e);
+            a = dense2_at<R, RB>(a, op.r0, op.r1, u);
+            break;
+        }
+        default: {   // OP_DIAG2
+            D4<R> d;
+            diag2<R>(op.kind, prm, op.p0, d.e);
+            if (INV) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d.e[i] = conj(d.e[i]);
+            }
+            a = app_diag<R, (1 << RB)>(a, op.r0, tb0, op.r1, tb1, true, d);
+            break;
+        }
+    }
+    return a;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// forward pass: one tile per workgroup
+// ---------------------------------------------------------------------------
+template <typename R, int RB>
+__global__ void __launch_bounds__(NTHREADS)
+k_tile_fwd(const Pass* __restrict__ passes, const Phase* __restrict__ phases, const Op* __restrict__ ops, int pass_idx,
+           cx<R>* __restrict__ state, int64_t stride, int n, const R* __restrict__ params, int64_t pstride,
+           const cx<R>* __restrict__ cmats, int64_t tiles_per_state) {
+    __shared__ cx<R> lds[Tile<R>::ELEMS];
+    const Pass& P = passes[pass_idx];
+    const PassInfo pi = read_pass(P);
+    const int nt = 1 << (pi.m - RB);
+    const int t = threadIdx.x;
+    const int64_t gid = blockIdx.x;
+    const int64_t b = gid / tiles_per_state;
+    const uint64_t tile = uint64_t(gid - b * tiles_per_state);
+    cx<R>* psi = state + b * stride;
+    const R* prm = params ? params + b * pstride : nullptr;
+    const uint64_t base = tile_base(tile, pi.tmask, n);
+
+    tile_load<R, RB>(lds, psi, base, pi, t, nt);
+    __syncthreads();
+    for (int f = P.phase_begin; f < P.phase_end; ++f) {
+        const Phase& F = phases[f];
+        const PhaseMap pm = phase_map<RB>(F, t, pi.m);
+        Regs<R, (1 << RB)> a = regs_from_lds<R, RB>(lds, pm);
+        for (int o = F.op_begin; o < F.op_end; ++o) a = apply_op<R, RB, false>(a, ops[o], pm.tpart, prm, cmats);
+        regs_to_lds<R, RB>(a, lds, pm);
+        __syncthreads();
+    }
+    tile_store<R, RB>(lds, psi, base, pi, t, nt);
+}
+
+// ---------------------------------------------------------------------------
+// reverse pass: psi and lambda, gradient slots accumulated per wave in LDS,
+// `wgs` workgroups per batch member loop over the tiles
+// ---------------------------------------------------------------------------
+template <typename R, int RB>
+__global__ void __launch_bounds__(NTHREADS)
+k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, const Op* __restrict__ ops, int pass_idx,
+           cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int64_t stride, int n,
+           const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cmats, int64_t tiles_per_state,
+           int wgs, double* __restrict__ part, int total_slots) {
+    __shared__ cx<R> lds[Tile<R>::ELEMS];
+    __shared__ double red[RED_SLOTS * (NTHREADS / 64)];
+    using Blk = Regs<R, (1 << RB)>;
+    const Pass& P = passes[pass_idx];
+    const PassInfo pi = read_pass(P);
+    const int nt = 1 << (pi.m - RB);
+    const int nwaves = (nt + 63) / 64;
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int64_t b = blockIdx.x / wgs;
+    const int wg = int(blockIdx.x - b * wgs);
+    cx<R>* psi = state + b * stride;
+    cx<R>* lam = costate + b * stride;
+    const R* prm = params ? params + b * pstride : nullptr;
+    const int nslots = P.n_slots;
+
+    for (int i = t; i < nslots * nwaves; i += nt) red[i] = 0.0;
+    // (the first __syncthreads below orders these writes before any accumulation)
+
+    for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
+        const uint64_t base = tile_base(uint64_t(tile), pi.tmask, n);
+        // phases run backwards; psi and lambda take turns in the one LDS tile
+        __syncthreads();
+        tile_load<R, RB>(lds, psi, base, pi, t, nt);
+        __syncthreads();
+        int f = P.phase_end - 1;
+        PhaseMap pm = phase_map<RB>(phases[f], t, pi.m);
+        Blk ps = regs_from_lds<R, RB>(lds, pm);
+        __syncthreads();
+        tile_load<R, RB>(lds, lam, base, pi, t, nt);
+        __syncthreads();
+        Blk la = regs_from_lds<R, RB>(lds, pm);
+        for (;;) {
+            const Phase& F = phases[f];
+            for (int o = F.op_end - 1; o >= F.op_begin; --o) {
+                const Op op = ops[o];
+                if (op.slot >= 0 && op.kind != K_U2) {
+                    double g0 = 0.0, g1 = 0.0;
+                    if (op.type == OP_DENSE1) {
+                        g0 = grad_rot1_at<R, RB>(op.kind, op.r0, la, ps);
+                    } else if (op.type == OP_DENSE2) {   // FSIM
+                        const double2 g = grad_fsim_at<R, RB>(op.r0, op.r1, la, ps);
+                        g0 = g.x;
+                        g1 = g.y;
+                    } else {                            // RZ, RZZ
+                        const int tb0 = op.lb0 >= 0 ? int((pm.tpart >> op.lb0) & 1) : 0;
+                        const int tb1 = op.lb1 >= 0 ? int((pm.tpart >> op.lb1) & 1) : 0;
+                        g0 = grad_zdiag<R, (1 << RB)>(la, ps, op.r0, tb0, op.type == OP_DIAG2 ? op.r1 : -1,
+                                                      op.type == OP_DIAG2 ? tb1 : 0);
+                    }
+                    g0 = wave_sum(g0);
+                    if (lane == 0) red[op.slot * nwaves + wave] += g0;
+                    if (op.kind == K_FSIM) {
+                        g1 = wave_sum(g1);
+                        if (lane == 0) red[(op.slot + 1) * nwaves + wave] += g1;
+                    }
+                }
+                ps = apply_op<R, RB, true>(ps, op, pm.tpart, prm, cmats);
+                if (op.kind == K_U2 && op.slot >= 0) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const double2 g = cot_u2_at<R, RB>(op.r0, op.r1, la, ps, e >> 2, e & 3);
+                        const double gr = wave_sum(g.x), gi = wave_sum(g.y);
+                        if (lane == 0) {
+                            red[(op.slot + 2 * e) * nwaves + wave] += gr;
+                            red[(op.slot + 2 * e + 1) * nwaves + wave] += gi;
+                        }
+                    }
+                }
+                la = apply_op<R, RB, true>(la, op, pm.tpart, prm, cmats);
+            }
+            if (f == P.phase_begin) break;
+            // hand both blocks to the previous phase's register assignment
+            const PhaseMap pn = phase_map<RB>(phases[f - 1], t, pi.m);
+            __syncthreads();
+            regs_to_lds<R, RB>(ps, lds, pm);
+            __syncthreads();
+            ps = regs_from_lds<R, RB>(lds, pn);
+            __syncthreads();
+            regs_to_lds<R, RB>(la, lds, pm);
+            __syncthreads();
+            la = regs_from_lds<R, RB>(lds, pn);
+            pm = pn;
+            --f;
+        }
+        __syncthreads();
+        regs_to_lds<R, RB>(ps, lds, pm);
+        __syncthreads();
+        tile_store<R, RB>(lds, psi, base, pi, t, nt);
+        __syncthreads();
+        regs_to_lds<R, RB>(la, lds, pm);
+        __syncthreads();
+        tile_store<R, RB>(lds, lam, base, pi, t, nt);
+    }
+    __syncthreads();
+    for (int s = t; s < nslots; s += nt) {
+        double v = 0.0;
+        for (int w = 0; w < nwaves; ++w) v += red[s * nwaves + w];
+        part[(size_t(b) * total_slots + P.slot_base + s) * wgs + wg] = v;
+    }
+}
+
+}  // namespace
+
+template <typename R, int RB>
+hipError_t launch_tile_fwd(const DevPlan& dp, int pass_idx, int m, void* state, int64_t stride, int n, int64_t batch,
+                           const void* params, int64_t pstride, const void* cmats, hipStream_t st) {
+    const int64_t tiles = int64_t(1) << (n - m);
+    const int nt = 1 << (m - RB);
+    hipLaunchKernelGGL((k_tile_fwd<R, RB>), dim3(unsigned(tiles * batch)), dim3(nt), 0, st, dp.passes, dp.phases,
+                       dp.ops, pass_idx, static_cast<cx<R>*>(state), stride, n, static_cast<const R*>(params), pstride,
+                       static_cast<const cx<R>*>(cmats), tiles);
+    return hipGetLastError();
+}
+
+template <typename R, int RB>
+hipError_t launch_tile_rev(const DevPlan& dp, int pass_idx, int m, void* state, void* costate, int64_t stride, int n,
+                           int64_t batch, const void* params, int64_t pstride, const void* cmats, int wgs,
+                           double* part, int total_slots, hipStream_t st) {
+    const int64_t tiles = int64_t(1) << (n - m);
+    const int nt = 1 << (m - RB);
+    hipLaunchKernelGGL((k_tile_rev<R, RB>), dim3(unsigned(wgs * batch)), dim3(nt), 0, st, dp.passes, dp.phases,
+                       dp.ops, pass_idx, static_cast<cx<R>*>(state), static_cast<cx<R>*>(costate), stride, n,
+                       static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats), tiles, wgs, part,
+                       total_slots);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile_fwd<float, 5>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*,
+                                              int64_t, const void*, hipStream_t);
+template hipError_t launch_tile_fwd<double, 4>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*,
+                                               int64_t, const void*, hipStream_t);
+template hipError_t launch_tile_rev<float, 5>(const DevPlan&, int, int, void*, void*, int64_t, int, int64_t,
+                                              const void*, int64_t, const void*, int, double*, int, hipStream_t);
+template hipError_t launch_tile_rev<double, 4>(const DevPlan&, int, int, void*, void*, int64_t, int, int64_t,
+                                               const void*, int64_t, const void*, int, double*, int, hipStream_t);
+
+}  // namespace tcng

@@ -1,0 +1,342 @@
+// Host-side planner for the tiled passes.
+//
+// A pass streams the state through the GPU once: every tile of 2^m
+// amplitudes whose index bits outside the tile's qubit set T are fixed is
+// loaded, has a run of gates applied in registers/LDS, and is written back.
+// Gates are scheduled greedily in circuit order: a gate joins the pass when
+// all its qubits lie in T and no earlier, not yet applied gate shares a qubit
+// with it (gates on disjoint qubits commute, so the result is that of the
+// original order).  Inside a pass, register phases are formed the same way:
+// a phase holds rb local bits in registers, and a gate joins it when the bits
+// it needs in registers fit.
+#include "plan.h"
+
+#include <algorithm>
+#include <map>
+
+namespace tcng {
+
+namespace {
+
+int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+uint64_t gate_qmask(const tcng_gate& g) {
+    uint64_t m = uint64_t(1) << g.q0;
+    if (kind_arity(g.kind) == 2) m |= uint64_t(1) << g.q1;
+    return m;
+}
+
+// Greedy schedule of `rem` (gate indices in order) into tile T.
+// Fills `taken` (flags per position in rem) and returns the number taken.
+int schedule_into_tile(const std::vector<tcng_gate>& gates, const std::vector<int>& rem, uint64_t T,
+                       int slot_budget, std::vector<char>* taken) {
+    uint64_t blocked = 0;
+    int count = 0, slots = 0;
+    for (size_t i = 0; i < rem.size(); ++i) {
+        const tcng_gate& g = gates[rem[i]];
+        uint64_t qm = gate_qmask(g);
+        int s = kind_slots(g.kind);
+        bool ok = !(qm & blocked) && ((qm & ~T) == 0) && (slots + s <= slot_budget);
+        if (ok) {
+            ++count;
+            slots += s;
+            if (taken) (*taken)[i] = 1;
+        } else {
+            blocked |= qm;
+        }
+        if (taken == nullptr && blocked == ~uint64_t(0)) break;
+    }
+    return count;
+}
+
+// terms of one X-group split by their coefficient c * i^{#Y} (order of first appearance)
+std::vector<std::pair<std::pair<double, double>, std::vector<int>>> coefficient_classes(
+    const std::vector<PauliTermHost>& terms, const std::vector<int>& idx) {
+    std::vector<std::pair<std::pair<double, double>, std::vector<int>>> out;
+    for (int t : idx) {
+        const PauliTermHost& h = terms[t];
+        const int r = h.ny & 3;
+        const double re = (r == 0) ? h.c : (r == 2 ? -h.c : 0.0);
+        const double im = (r == 1) ? h.c : (r == 3 ? -h.c : 0.0);
+        bool found = false;
+        for (auto& cls : out)
+            if (cls.first.first == re && cls.first.second == im) { cls.second.push_back(t); found = true; break; }
+        if (!found) out.push_back({{re, im}, {t}});
+    }
+    return out;
+}
+
+uint64_t fill_tile(uint64_t T, int n, int m) {
+    for (int q = 0; q < n && popc(T) < m; ++q) T |= uint64_t(1) << q;
+    return T;
+}
+
+}  // namespace
+
+std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_params, const TileConfig& cfg,
+                         CircuitPlan& out) {
+    out = CircuitPlan();
+    out.cfg = cfg;
+    const int m = std::min(n, cfg.m_max);
+    const int lo = std::min(cfg.lo, m);
+    if (m < cfg.rb) return "tile smaller than the register block";
+    const uint64_t lo_mask = (lo >= 64) ? ~uint64_t(0) : ((uint64_t(1) << lo) - 1);
+    const uint64_t all_mask = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+
+    std::vector<int> rem(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
+
+    // per-gate slot assignment (global, in reverse-sweep order is not needed:
+    // slots are contiguous per pass, assigned as passes are formed)
+    std::vector<int32_t> gate_slot_first(gates.size(), -1);
+    out.gate_slot.assign(gates.size(), -1);
+
+    while (!rem.empty()) {
+        // ---- choose the tile
+        std::vector<uint64_t> cands;
+        if (n <= m) {
+            cands.push_back(all_mask);
+        } else {
+            const int h = m - lo;
+            for (int a = lo; a + h <= n; ++a) {
+                uint64_t w = lo_mask;
+                for (int q = a; q < a + h; ++q) w |= uint64_t(1) << q;
+                cands.push_back(w);
+            }
+            // frontier candidate: qubits of the earliest unblocked gates
+            uint64_t T = lo_mask, blocked = 0;
+            for (int gi : rem) {
+                uint64_t qm = gate_qmask(gates[gi]);
+                if (!(qm & blocked) && popc(T | qm) <= m) T |= qm;
+                else blocked |= qm;
+            }
+            cands.push_back(fill_tile(T, n, m));
+        }
+        int best = -1, best_count = -1;
+        for (size_t c = 0; c < cands.size(); ++c) {
+            int cnt = schedule_into_tile(gates, rem, cands[c], RED_SLOTS, nullptr);
+            if (cnt > best_count) { best_count = cnt; best = int(c); }
+        }
+        if (best_count <= 0) return "planner made no progress (gate needs more than the tile's qubits)";
+        const uint64_t T = cands[best];
+        std::vector<char> taken(rem.size(), 0);
+        schedule_into_tile(gates, rem, T, RED_SLOTS, &taken);
+        std::vector<int> sel, rest;
+        for (size_t i = 0; i < rem.size(); ++i) (taken[i] ? sel : rest).push_back(rem[i]);
+        rem.swap(rest);
+
+        // ---- local bit map
+        Pass P{};
+        P.m = m;
+        P.lo = lo;
+        P.tile_mask = T;
+        int qubit_to_local[64];
+        for (int q = 0; q < 64; ++q) qubit_to_local[q] = -1;
+        for (int i = 0; i < 16; ++i) P.local_qubit[i] = -1;
+        int li = 0;
+        for (int q = 0; q < n; ++q)
+            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = int8_t(q); ++li; }
+        if (li != m) return "internal: tile size mismatch";
+        for (int q = 0; q < lo; ++q)
+            if (qubit_to_local[q] != q) return "internal: low qubits not contiguous";
+
+        // ---- slots of this pass
+        P.slot_base = out.total_slots;
+        int pass_slots = 0;
+        for (int gi : sel) {
+            int s = kind_slots(gates[gi].kind);
+            if (s) { gate_slot_first[gi] = pass_slots; pass_slots += s; }
+        }
+        P.n_slots = pass_slots;
+        out.total_slots += pass_slots;
+
+        // ---- register phases
+        P.phase_begin = int(out.phases.size());
+        std::vector<int> prem = sel;
+        while (!prem.empty()) {
+            uint32_t R = 0;   // local bits in registers
+            uint64_t blocked = 0;
+            std::vector<int> ph, rest2;
+            for (int gi : prem) {
+                const tcng_gate& g = gates[gi];
+                uint64_t qm = gate_qmask(g);
+                uint32_t need = 0;
+                const int l0 = qubit_to_local[g.q0];
+                const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
+                if (g.kind == K_CNOT) need = 1u << l1;
+                else if (g.kind == K_CZ || g.kind == K_RZZ || kind_diagonal(g.kind)) need = 0;
+                else need = (1u << l0) | (l1 >= 0 ? (1u << l1) : 0u);
+                if (!(qm & blocked) && popc(R | need) <= cfg.rb) {
+                    R |= need;
+                    ph.push_back(gi);
+                } else {
+                    blocked |= qm;
+                    rest2.push_back(gi);
+                }
+            }
+            prem.swap(rest2);
+            // fill the register set to exactly rb bits, preferring high local bits
+            // (keeps consecutive lanes on consecutive LDS addresses)
+            for (int b = m - 1; b >= 0 && popc(R) < cfg.rb; --b) R |= 1u << b;
+            Phase F{};
+            for (int i = 0; i < 8; ++i) F.R[i] = -1;
+            int ri = 0, reg_of_local[MAX_TILE_BITS];
+            for (int b = 0; b < MAX_TILE_BITS; ++b) reg_of_local[b] = -1;
+            for (int b = 0; b < m; ++b)
+                if ((R >> b) & 1) { F.R[ri] = int8_t(b); reg_of_local[b] = ri; ++ri; }
+            F.op_begin = int(out.ops.size());
+            for (int gi : ph) {
+                const tcng_gate& g = gates[gi];
+                Op o{};
+                o.kind = int8_t(g.kind);
+                o.p0 = g.p0;
+                o.p1 = g.p1;
+                o.mat = g.mat;
+                o.gate = gi;
+                o.slot = gate_slot_first[gi];
+                const int l0 = qubit_to_local[g.q0];
+                const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
+                o.lb0 = int8_t(l0);
+                o.lb1 = int8_t(l1);
+                o.r0 = int8_t(reg_of_local[l0]);
+                o.r1 = int8_t(l1 >= 0 ? reg_of_local[l1] : -1);
+                switch (g.kind) {
+                    case K_RZ: case K_Z: case K_S: o.type = OP_DIAG1; break;
+                    case K_CZ: case K_RZZ: o.type = OP_DIAG2; break;
+                    case K_CNOT: o.type = OP_CX; break;
+                    case K_FSIM: case K_U2: o.type = OP_DENSE2; break;
+                    default: o.type = OP_DENSE1; break;
+                }
+                if ((o.type == OP_DENSE1 && o.r0 < 0) || (o.type == OP_CX && o.r1 < 0) ||
+                    (o.type == OP_DENSE2 && (o.r0 < 0 || o.r1 < 0)))
+                    return "internal: register operand missing";
+                out.ops.push_back(o);
+            }
+            F.op_end = int(out.ops.size());
+            out.phases.push_back(F);
+        }
+        P.phase_end = int(out.phases.size());
+        out.passes.push_back(P);
+    }
+
+    // ---- gradient assembly tables
+    std::vector<std::vector<int32_t>> per_param(std::max(n_params, 0));
+    for (const Pass& P : out.passes)
+        for (int f = P.phase_begin; f < P.phase_end; ++f)
+            for (int o = out.phases[f].op_begin; o < out.phases[f].op_end; ++o) {
+                const Op& op = out.ops[o];
+                if (op.slot < 0) continue;
+                const int gslot = P.slot_base + op.slot;
+                const tcng_gate& g = gates[op.gate];
+                if (g.kind == K_U2) {
+                    out.gate_slot[op.gate] = gslot;
+                } else {
+                    if (g.p0 >= 0) per_param[g.p0].push_back(gslot);
+                    if (kind_nparams(g.kind) == 2 && g.p1 >= 0) per_param[g.p1].push_back(gslot + 1);
+                }
+            }
+    out.slot_ptr.assign(1, 0);
+    for (auto& v : per_param) {
+        std::sort(v.begin(), v.end());
+        out.slot_idx.insert(out.slot_idx.end(), v.begin(), v.end());
+        out.slot_ptr.push_back(int32_t(out.slot_idx.size()));
+    }
+    return "";
+}
+
+std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const TileConfig& cfg, PauliPlan& out) {
+    out = PauliPlan();
+    out.cfg = cfg;
+    const int m = std::min(n, cfg.m_max);
+    const int lo = std::min(cfg.lo, m);
+    const uint64_t lo_mask = (lo >= 64) ? ~uint64_t(0) : ((uint64_t(1) << lo) - 1);
+    const uint64_t all_mask = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+
+    std::map<uint64_t, std::vector<int>> by_x;   // ordered: x = 0 (diagonal) first
+    for (size_t t = 0; t < terms.size(); ++t) by_x[terms[t].x].push_back(int(t));
+    std::vector<uint64_t> xs;
+    for (auto& kv : by_x) {
+        if (popc(kv.first & ~lo_mask) > m - lo) return "Pauli term flips more qubits than a tile holds";
+        xs.push_back(kv.first);
+    }
+    std::vector<char> done(xs.size(), 0);
+    size_t left = xs.size();
+    while (left) {
+        uint64_t T = (n <= m) ? all_mask : lo_mask;
+        for (size_t i = 0; i < xs.size(); ++i)
+            if (!done[i] && popc((T | xs[i]) & all_mask) <= m) T |= xs[i];
+        T = fill_tile(T, n, m);
+        PPass P{};
+        P.m = m;
+        P.lo = lo;
+        P.tile_mask = T;
+        int qubit_to_local[64];
+        for (int q = 0; q < 64; ++q) qubit_to_local[q] = -1;
+        for (int i = 0; i < 16; ++i) P.local_qubit[i] = -1;
+        int li = 0;
+        for (int q = 0; q < n; ++q)
+            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = int8_t(q); ++li; }
+        auto to_local = [&](uint64_t mask) {
+            int32_t r = 0;
+            for (int q = 0; q < n; ++q)
+                if (((mask & T) >> q) & 1) r |= 1 << qubit_to_local[q];
+            return r;
+        };
+        P.group_begin = int(out.groups.size());
+        for (size_t i = 0; i < xs.size(); ++i) {
+            if (done[i] || (xs[i] & ~T)) continue;
+            done[i] = 1;
+            --left;
+            PGroup G{};
+            G.x_local = to_local(xs[i]);
+            G.class_begin = int(out.classes.size());
+            for (auto& cls : coefficient_classes(terms, by_x[xs[i]])) {
+                PClass pc{};
+                pc.cre = cls.first.first;
+                pc.cim = cls.first.second;
+                pc.term_begin = int(out.terms.size());
+                for (int t : cls.second) {
+                    PTerm pt{};
+                    pt.z_local = to_local(terms[t].z);
+                    pt.z_out = terms[t].z & ~T;
+                    out.terms.push_back(pt);
+                }
+                pc.term_end = int(out.terms.size());
+                out.classes.push_back(pc);
+            }
+            G.class_end = int(out.classes.size());
+            out.groups.push_back(G);
+        }
+        P.group_end = int(out.groups.size());
+        if (P.group_end == P.group_begin) return "internal: Pauli planner made no progress";
+        out.passes.push_back(P);
+    }
+    return "";
+}
+
+void group_pauli_full(const std::vector<PauliTermHost>& terms, std::vector<PGroupFull>& groups,
+                      std::vector<PClassFull>& classes, std::vector<PTermFull>& out_terms) {
+    std::map<uint64_t, std::vector<int>> by_x;
+    for (size_t t = 0; t < terms.size(); ++t) by_x[terms[t].x].push_back(int(t));
+    groups.clear();
+    classes.clear();
+    out_terms.clear();
+    for (auto& kv : by_x) {
+        PGroupFull G{};
+        G.x = kv.first;
+        G.class_begin = int(classes.size());
+        for (auto& cls : coefficient_classes(terms, kv.second)) {
+            PClassFull pc{};
+            pc.cre = cls.first.first;
+            pc.cim = cls.first.second;
+            pc.term_begin = int(out_terms.size());
+            for (int t : cls.second) out_terms.push_back(PTermFull{terms[t].z});
+            pc.term_end = int(out_terms.size());
+            classes.push_back(pc);
+        }
+        G.class_end = int(classes.size());
+        groups.push_back(G);
+    }
+}
+
+}  // namespace tcng

@@ -1,0 +1,53 @@
+// Host-side planner: schedules a circuit's gates into tiled passes and
+// register phases, and groups a Pauli sum by X-mask into tiled passes.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace tcng {
+
+struct TileConfig {
+    int m_max;   // tile bits (2^m amplitudes per tile)
+    int rb;      // register bits per thread (2^rb amplitudes per thread and state)
+    int lo;      // low qubits always in the tile (memory-contiguous runs of 2^lo amplitudes)
+};
+
+struct CircuitPlan {
+    TileConfig cfg{};
+    std::vector<Pass> passes;
+    std::vector<Phase> phases;
+    std::vector<Op> ops;
+    int total_slots = 0;
+    // gradient assembly: slots of parameter p are slot_idx[slot_ptr[p] .. slot_ptr[p+1])
+    std::vector<int32_t> slot_ptr, slot_idx;
+    // U2 gates: gate index -> first of its 32 cotangent slots (-1 otherwise)
+    std::vector<int32_t> gate_slot;
+};
+
+struct PauliPlan {
+    TileConfig cfg{};
+    std::vector<PPass> passes;
+    std::vector<PGroup> groups;
+    std::vector<PClass> classes;
+    std::vector<PTerm> terms;
+};
+
+struct PauliTermHost {
+    uint64_t x, z;
+    int ny;
+    double c;
+};
+
+// Returns an empty string on success, else the reason the plan is impossible.
+std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_params, const TileConfig& cfg,
+                         CircuitPlan& out);
+std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const TileConfig& cfg, PauliPlan& out);
+
+// Plain path: terms grouped by full X-mask.
+void group_pauli_full(const std::vector<PauliTermHost>& terms, std::vector<PGroupFull>& groups,
+                      std::vector<PClassFull>& classes, std::vector<PTermFull>& out_terms);
+
+}  // namespace tcng

@@ -1,0 +1,127 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library loads and exports every symbol include/tcng.h declares; argument
+validation rejects bad input before any device call; and the tiled planner's
+schedule is a legal reordering of the circuit whose every gate fits its pass's
+tile (checked by running the CPU oracle in the planned order).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2602_14167_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "tcng.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tcng_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(P):
+    names = header_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(P.lib(), name), name
+    assert set(names) == set(P._lib.EXPORTS)
+    assert P.lib().tcng_version() == 1
+
+
+def test_validation_errors_without_device(P):
+    L = P.lib()
+    h = ctypes.c_void_p()
+    bad = np.array([[W.CNOT, 0, 0, -1, -1, -1]], np.int32)           # duplicate qubit
+    assert L.tcng_circuit_create(3, bad.ctypes.data_as(ctypes.c_void_p), 1, 0, None, 0, ctypes.byref(h)) == P._lib.TCNG_E_INVALID
+    assert b"duplicate" in L.tcng_last_error()
+    bad = np.array([[W.RY, 5, -1, 0, -1, -1]], np.int32)             # qubit out of range
+    assert L.tcng_circuit_create(3, bad.ctypes.data_as(ctypes.c_void_p), 1, 1, None, 0, ctypes.byref(h)) == P._lib.TCNG_E_INVALID
+    bad = np.array([[W.RY, 1, -1, 3, -1, -1]], np.int32)             # parameter index out of range
+    assert L.tcng_circuit_create(3, bad.ctypes.data_as(ctypes.c_void_p), 1, 2, None, 0, ctypes.byref(h)) == P._lib.TCNG_E_INVALID
+    bad = np.array([[W.U2, 1, 0, -1, -1, 0]], np.int32)              # matrix index out of range
+    assert L.tcng_circuit_create(3, bad.ctypes.data_as(ctypes.c_void_p), 1, 0, None, 0, ctypes.byref(h)) == P._lib.TCNG_E_INVALID
+    bad = np.array([[17, 1, -1, -1, -1, -1]], np.int32)              # unknown kind
+    assert L.tcng_circuit_create(3, bad.ctypes.data_as(ctypes.c_void_p), 1, 0, None, 0, ctypes.byref(h)) == P._lib.TCNG_E_INVALID
+    assert L.tcng_circuit_create(40, None, 0, 0, None, 0, ctypes.byref(h)) == P._lib.TCNG_E_UNSUPPORTED
+    codes = np.array([[4, 0]], np.uint8)
+    coeffs = np.array([1.0])
+    assert L.tcng_pauli_sum_create(2, codes.ctypes.data_as(ctypes.c_void_p), coeffs.ctypes.data_as(ctypes.c_void_p), 1,
+                                   ctypes.byref(h)) == P._lib.TCNG_E_INVALID
+    assert L.tcng_state_init(None, None, 0, None) == P._lib.TCNG_E_INVALID
+    s = P.TcngState(0, 4, 0, 1, 16)
+    assert L.tcng_state_init(ctypes.byref(s), None, 0, None) == P._lib.TCNG_E_INVALID   # null amplitudes
+    s = P.TcngState(256, 4, 0, 1, 8)
+    assert L.tcng_state_init(ctypes.byref(s), None, 0, None) == P._lib.TCNG_E_INVALID   # stride < 2^n
+    s = P.TcngState(256, 4, 7, 1, 16)
+    assert L.tcng_state_init(ctypes.byref(s), None, 0, None) == P._lib.TCNG_E_INVALID   # dtype
+    s = P.TcngState(256, 4, 0, 1, 16)
+    q = np.array([1, 1], np.int32)
+    assert L.tcng_apply_gate(ctypes.byref(s), q.ctypes.data_as(ctypes.c_void_p), 2, ctypes.c_void_p(256), None) == P._lib.TCNG_E_INVALID
+    q = np.array([0, 1, 2, 3, 0, 1], np.int32)
+    assert L.tcng_apply_gate(ctypes.byref(s), q.ctypes.data_as(ctypes.c_void_p), 6, ctypes.c_void_p(256), None) == P._lib.TCNG_E_INVALID
+
+
+def _check_schedule(P, oracle_mod, n, gates, n_params, params, mats, dtype):
+    import torch
+    order, pass_of, masks = P.plan_inspect(n, gates, n_params, dtype=dtype)
+    assert order is not None
+    G = len(gates)
+    assert sorted(order.tolist()) == list(range(G))
+    pos = np.empty(G, int)
+    pos[order] = np.arange(G)
+    qsets = [{int(g[1])} | ({int(g[2])} if g[2] >= 0 else set()) for g in gates]
+    # gates sharing a qubit keep their relative order
+    last = {}
+    for i in range(G):
+        for q in qsets[i]:
+            if q in last:
+                assert pos[last[q]] < pos[i]
+            last[q] = i
+    # every gate's qubits lie in its pass's tile; passes are non-decreasing in execution order
+    assert np.all(np.diff(pass_of) >= 0)
+    m_max = 13 if dtype == torch.complex64 else 12
+    for k, gi in enumerate(order):
+        mask = int(masks[pass_of[k]])
+        assert bin(mask).count("1") == min(n, m_max)
+        for q in qsets[gi]:
+            assert (mask >> q) & 1
+    # the reordered circuit computes the same state (CPU oracle)
+    if n <= 14:
+        a = oracle_mod.run(n, gates, params, mats)
+        b = oracle_mod.run(n, gates[order], params, mats)
+        np.testing.assert_allclose(a, b, atol=1e-12)
+    return len(masks)
+
+
+@pytest.mark.parametrize("n", [11, 12, 14])
+def test_planner_random_circuits(P, oracle_mod, n):
+    import torch
+    r = np.random.default_rng(40 + n)
+    gates, params, mats = W.random_circuit(n, 150, r)
+    for dt in (torch.complex64, torch.complex128):
+        _check_schedule(P, oracle_mod, n, gates, len(params), params, mats, dt)
+
+
+def test_planner_workloads(P, oracle_mod):
+    import torch
+    c = W.cfg2(n=14, layers=3)
+    _check_schedule(P, oracle_mod, 14, c["gates"], c["n_params"], c["params"], None, torch.complex64)
+    c = W.cfg2()
+    npass = _check_schedule(P, oracle_mod, 28, c["gates"], c["n_params"], c["params"], None, torch.complex64)
+    assert npass <= 20          # 996 gates in a handful of HBM round trips
+    c = W.cfg5()
+    _check_schedule(P, oracle_mod, 32, c["gates"], c["n_params"], c["params"], None, torch.complex64)
+    c = W.cfg4(count=4)
+    for cc in c["circuits"]:
+        _check_schedule(P, oracle_mod, cc["n"], cc["gates"], 0, None, cc["mats"], torch.complex64)

@@ -1,0 +1,152 @@
+"""Checks at the measured sizes (n = 28, 30, 32), where the oracle cannot run
+the whole workload: closed forms, invariants and exact identities that hold
+at any size, evaluated on the HIP path in the launch configuration the
+benchmark times (tiled passes, complex64).
+
+* product states (one HEA layer without CNOTs): <H> and the gradient in
+  closed form from the Bloch vectors;
+* GHZ amplitudes, and a single rotation on |0..0> (sampled amplitudes);
+* the n=28 HEA workload in complex64 against the same run in complex128
+  (self-consistency of the two precisions, not oracle parity), norm, and the
+  reverse sweep's recomputed initial state;
+* the n=32 fSim / 2D TFIM workload: phi-derivatives against the exact
+  two-term shift rule, theta-derivatives against a fourth-order central
+  difference, computed with GPU forward evaluations.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2602_14167_amd as pkg
+    assert torch.cuda.is_available()
+    pkg.lib()
+    return pkg
+
+
+def product_state_reference(params, n, J, h):
+    t, f = params[:n], params[n:]
+    bz = np.cos(t)
+    bx = np.sin(t) * np.cos(f)
+    E = J * np.sum(bz[:-1] * bz[1:]) + h * np.sum(bx)
+    gt = np.zeros(n)
+    gf = np.zeros(n)
+    for i in range(n):
+        nb = (bz[i - 1] if i > 0 else 0.0) + (bz[i + 1] if i < n - 1 else 0.0)
+        gt[i] = J * (-np.sin(t[i])) * nb + h * np.cos(t[i]) * np.cos(f[i])
+        gf[i] = h * (-np.sin(t[i]) * np.sin(f[i]))
+    return E, np.concatenate([gt, gf])
+
+
+@pytest.mark.parametrize("n", [28, 30])
+def test_product_state_closed_form(P, n):
+    gates, npar = W.hea_gates(n, 1, cnot=False)
+    params = np.random.default_rng(n).uniform(0, 2 * np.pi, npar)
+    p32 = W.round_params(params, "c64")
+    J, h = -1.0, -0.5
+    codes, coeffs = W.tfim_1d(n, J, h)
+    circ = P.Circuit(n, gates, npar)
+    H = P.PauliSum(n, codes, coeffs)
+    E, g = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float32, device="cuda"), H)
+    Er, gr = product_state_reference(p32, n, J, h)
+    S = np.abs(coeffs).sum()
+    assert abs(E.item() - Er) <= 1e-5 * S
+    assert np.max(np.abs(g.cpu().numpy()[0] - gr)) <= 1e-4 * S
+    del circ, H
+    torch.cuda.empty_cache()
+
+
+def test_ghz_and_single_rotation_n30(P):
+    n = 30
+    psi = P.new_state(n, 1, torch.complex64)
+    g = [W.gate(W.H, 0)] + [W.gate(W.CNOT, i, i + 1) for i in range(n - 1)]
+    P.run_circuit(P.Circuit(n, g, 0), None, psi)
+    r2 = 2 ** -0.5
+    assert abs(psi[0, 0].item() - r2) < 1e-6 and abs(psi[0, -1].item() - r2) < 1e-6
+    idx = torch.randint(1, 2 ** n - 1, (4096,), device="cuda")
+    assert torch.max(torch.abs(psi[0, idx])).item() == 0.0
+    assert abs(torch.sum(torch.abs(psi) ** 2).item() - 1) < 1e-5
+    # RY(theta) on qubit 29 of |0..0> on the per-gate path (high target qubit)
+    P.state_init(psi)
+    th = 1.234
+    P.run_circuit(P.Circuit(n, [W.gate(W.RY, 29, p0=0)], 1), torch.tensor([[th]], device="cuda"), psi, mode="plain")
+    assert abs(psi[0, 0].item() - np.cos(th / 2)) < 1e-6
+    assert abs(psi[0, 2 ** 29].item() - np.sin(th / 2)) < 1e-6
+    del psi
+    torch.cuda.empty_cache()
+
+
+def test_hea28_c64_vs_c128_and_invariants(P):
+    c = W.cfg2()
+    n = c["n"]
+    circ = P.Circuit(n, c["gates"], c["n_params"])
+    H = P.PauliSum(n, c["codes"], c["coeffs"])
+    S = np.abs(c["coeffs"]).sum()
+    p32 = W.round_params(c["params"], "c64")
+    psi = P.new_state(n, 1, torch.complex64)
+    E32, g32 = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float32, device="cuda"), H, psi=psi)
+    # reverse sweep recomputed |0..0>
+    assert abs(psi[0, 0].item() - 1) < 1e-4
+    assert torch.max(torch.abs(psi[0, 1:])).item() < 1e-4
+    E32, g32 = E32.item(), g32.cpu().numpy()[0]
+    del psi
+    torch.cuda.empty_cache()
+    psi = P.new_state(n, 1, torch.complex128)
+    E64, g64 = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float64, device="cuda"), H, psi=psi)
+    E64, g64 = E64.item(), g64.cpu().numpy()[0]
+    # the final state's norm and <H> by the standalone expectation kernel
+    P.state_init(psi)
+    P.run_circuit(circ, torch.tensor(p32, dtype=torch.float64, device="cuda"), psi)
+    norm = P.PauliSum(n, np.zeros((1, n), np.uint8), [1.0])
+    assert abs(P.expect_pauli(psi, norm).item() - 1) < 1e-12
+    assert abs(P.expect_pauli(psi, H).item() - E64) < 1e-12 * S
+    del psi
+    torch.cuda.empty_cache()
+    assert abs(E32 - E64) <= 1e-5 * S
+    assert np.max(np.abs(g32 - g64)) <= 1e-4 * S
+
+
+def test_fsim32_shift_rule_and_finite_differences(P):
+    c = W.cfg5()
+    n = c["n"]
+    circ = P.Circuit(n, c["gates"], c["n_params"])
+    H = P.PauliSum(n, c["codes"], c["coeffs"])
+    S = np.abs(c["coeffs"]).sum()
+    p = W.round_params(c["params"], "c64")
+    psi = P.new_state(n, 1, torch.complex64)
+    lam = torch.empty_like(psi)
+    E, g = P.expect_grad(circ, torch.tensor(p, dtype=torch.float32, device="cuda"), H, psi=psi, lam=lam)
+    E, g = E.item(), g.cpu().numpy()[0]
+    assert abs(psi[0, 0].item() - 1) < 1e-3
+
+    def energy(pp):
+        P.state_init(psi)
+        P.run_circuit(circ, torch.tensor(pp, dtype=torch.float32, device="cuda"), psi)
+        return P.expect_pauli(psi, H).item()
+
+    assert abs(energy(p) - E) <= 1e-5 * S
+    rng = np.random.default_rng(7)
+    for gi in rng.choice(len(c["gates"]), size=2, replace=False):
+        k_phi = int(c["gates"][gi][4])
+        pp, pm = p.copy(), p.copy()
+        pp[k_phi] += np.pi / 2
+        pm[k_phi] -= np.pi / 2
+        shift = 0.5 * (energy(pp) - energy(pm))
+        assert abs(shift - g[k_phi]) <= 1e-4 * S
+        k_th = int(c["gates"][gi][3])
+        hstep = 0.05
+        vals = []
+        for m in (2, 1, -1, -2):
+            q = p.copy()
+            q[k_th] += m * hstep
+            vals.append(energy(q))
+        fd = (-vals[0] + 8 * vals[1] - 8 * vals[2] + vals[3]) / (12 * hstep)
+        assert abs(fd - g[k_th]) <= 1e-4 * S
+    del psi, lam
+    torch.cuda.empty_cache()

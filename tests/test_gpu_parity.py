@@ -1,0 +1,261 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (the accuracy targets of the build):
+  complex128: 1e-12 on <H> and on every gradient component;
+  complex64 : 1e-5 on <H>, 1e-4 on the gradient;
+all relative to S = sum_k |c_k|, the a-priori bound on |<H>| and on each
+gradient component of a generator with norm <= 1 (a relative error of a value
+that concentrates near 0 is undefined).  For complex64 the oracle receives the
+float32-rounded angles and complex64-rounded matrices widened exactly, so the
+comparison measures the kernels, not input rounding.  Amplitudes: absolute
+1e-12 (c128) / 2e-5 (c64).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": dict(E=1e-5, g=1e-4, amp=2e-5), "c128": dict(E=1e-12, g=1e-12, amp=1e-12)}
+TDT = {"c64": torch.complex64, "c128": torch.complex128}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2602_14167_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.lib()
+    return pkg
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.asarray(x)).to(device="cuda", dtype=dtype)
+
+
+def rdt(dtype):
+    return torch.float32 if dtype == "c64" else torch.float64
+
+
+def run_gpu(P, n, gates, params, mats, dtype, mode, batch_params=None, init=None):
+    circ = P.Circuit(n, gates, 0 if params is None else len(params), W.round_mats(mats, dtype) if mats is not None else None)
+    pb = np.atleast_2d(params if batch_params is None else batch_params)
+    B = pb.shape[0]
+    psi = torch.empty((B, 2 ** n), dtype=TDT[dtype], device="cuda")
+    if init is None:
+        P.state_init(psi)
+    else:
+        psi.copy_(dev(init, TDT[dtype]))
+    p = dev(pb, rdt(dtype)) if circ.n_params else None
+    P.run_circuit(circ, p, psi, mode=mode)
+    return psi.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# state initialisation and single gates
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_state_init(P, dtype):
+    n = 9
+    psi = torch.full((3, 2 ** n), 7.0, dtype=TDT[dtype], device="cuda")
+    P.state_init(psi, basis=37)
+    ref = np.zeros((3, 2 ** n))
+    ref[:, 37] = 1
+    np.testing.assert_array_equal(psi.cpu().numpy(), ref)
+    amps = W.random_state(n, np.random.default_rng(1))
+    P.state_init(psi, amps=dev(amps, TDT[dtype]))
+    np.testing.assert_allclose(psi.cpu().numpy(), np.tile(amps, (3, 1)), atol=TOL[dtype]["amp"])
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_apply_gate_matches_oracle(P, oracle_mod, dtype, k):
+    n = 9
+    r = np.random.default_rng(10 + k)
+    init = W.random_state(n, r)
+    psi = dev(init, TDT[dtype]).reshape(1, -1).contiguous()
+    for trial in range(3):
+        qs = [int(v) for v in r.choice(n, size=k, replace=False)]
+        A = r.standard_normal((2 ** k, 2 ** k)) + 1j * r.standard_normal((2 ** k, 2 ** k))
+        A /= np.linalg.norm(A, 2)
+        A = W.round_mats(A, dtype)
+        P.apply_gate(psi, qs, dev(A, TDT[dtype]))
+        init = oracle_mod.apply_matrix(n, init, qs, A)
+    np.testing.assert_allclose(psi.cpu().numpy()[0], init, atol=TOL[dtype]["amp"])
+
+
+# ---------------------------------------------------------------------------
+# circuits
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("n", [1, 2, 5, 9, 10, 11, 12, 13, 14, 16])
+def test_run_circuit_random_all_kinds(P, oracle_mod, dtype, mode, n):
+    r = np.random.default_rng(100 + n)
+    gates, params, mats = W.random_circuit(n, 120, r)
+    B = 2
+    bp = np.stack([params, r.uniform(0, 2 * np.pi, params.shape)])
+    init = W.random_state(n, r)
+    got = run_gpu(P, n, gates, params, mats, dtype, mode, batch_params=bp, init=np.tile(init, (B, 1)))
+    for b in range(B):
+        ref = oracle_mod.run(n, gates, W.round_params(bp[b], dtype), W.round_mats(mats, dtype), init=init if dtype == "c128" else init.astype(np.complex64))
+        np.testing.assert_allclose(got[b], ref, atol=TOL[dtype]["amp"] * (5 if dtype == "c64" else 1))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_tiled_and_plain_agree_on_hea(P, dtype):
+    c = W.cfg2(n=15, layers=4)
+    a = run_gpu(P, 15, c["gates"], c["params"], None, dtype, "tiled")
+    b = run_gpu(P, 15, c["gates"], c["params"], None, dtype, "plain")
+    np.testing.assert_allclose(a, b, atol=TOL[dtype]["amp"])
+
+
+# ---------------------------------------------------------------------------
+# Pauli expectations
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("n,kind", [(3, "random"), (11, "random"), (12, "tfim"), (15, "xxz"), (16, "2local"),
+                                    (16, "random")])
+def test_expect_pauli_matches_oracle(P, oracle_mod, dtype, mode, n, kind):
+    r = np.random.default_rng(300 + n)
+    if kind == "random":
+        codes, coeffs = W.random_pauli_sum(n, 20, r, max_weight=4 if n > 12 else None)
+    elif kind == "tfim":
+        codes, coeffs = W.tfim_1d(n, -1.0, -0.5)
+    elif kind == "xxz":
+        codes, coeffs = W.xxz_1d(n, 0.5)
+    else:
+        codes, coeffs = W.random_2local(n, 3 * n, r)
+    B = 2
+    states = np.stack([W.random_state(n, r) for _ in range(B)])
+    if dtype == "c64":
+        states = states.astype(np.complex64).astype(np.complex128)
+    H = P.PauliSum(n, codes, coeffs)
+    psi = dev(states, TDT[dtype])
+    e = P.expect_pauli(psi, H, mode=mode).cpu().numpy()
+    S = np.abs(coeffs).sum()
+    for b in range(B):
+        ref = oracle_mod.expect(n, states[b], codes, coeffs).real
+        assert abs(e[b] - ref) <= TOL[dtype]["E"] * S, (e[b], ref)
+
+
+# ---------------------------------------------------------------------------
+# value and adjoint gradient
+# ---------------------------------------------------------------------------
+
+def check_expect_grad(P, oracle_mod, n, gates, params_b, mats, codes, coeffs, dtype, mode, lie=False, init=None):
+    """params_b: [B][P] float64 (rounded per dtype here)."""
+    B = params_b.shape[0]
+    circ = P.Circuit(n, gates, params_b.shape[1], W.round_mats(mats, dtype) if mats is not None else None)
+    H = P.PauliSum(n, codes, coeffs)
+    psi = torch.empty((B, 2 ** n), dtype=TDT[dtype], device="cuda")
+    if init is None:
+        P.state_init(psi)
+    else:
+        psi.copy_(dev(np.tile(init, (B, 1)), TDT[dtype]))
+    psi0 = psi.clone()
+    p = dev(params_b, rdt(dtype)) if params_b.shape[1] else None
+    out = P.expect_grad(circ, p, H, psi=psi, want_gate_grad=lie, mode=mode)
+    E, g = out[0].cpu().numpy(), out[1].cpu().numpy()
+    S = np.abs(coeffs).sum()
+    tol = TOL[dtype]
+    for b in range(B):
+        ref = oracle_mod.expect_grad(n, gates, W.round_params(params_b[b], dtype), codes, coeffs,
+                                     W.round_mats(mats, dtype) if mats is not None else None,
+                                     init=init, want_lie=lie)
+        assert abs(E[b] - ref["E"]) <= tol["E"] * S, (b, E[b], ref["E"])
+        if params_b.shape[1]:
+            err = np.max(np.abs(g[b] - ref["grad"]))
+            assert err <= tol["g"] * S, (b, err)
+        if lie:
+            gl = out[2].cpu().numpy()[b]
+            err = np.max(np.abs(gl - ref["lie"]))
+            assert err <= tol["g"] * S, (b, err)
+    # the reverse sweep recomputes the initial states
+    np.testing.assert_allclose(psi.cpu().numpy(), psi0.cpu().numpy(), atol=(1e-11 if dtype == "c128" else 1e-4))
+    return E, g
+
+
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+def test_cfg1_state_energy_gradient_c128(P, oracle_mod, mode):
+    """n=10 complex128 HEA L=4, TFIM +ZZ +X: final state, <H>, gradient at 1e-12."""
+    c = W.cfg1()
+    st = run_gpu(P, 10, c["gates"], c["params"], None, "c128", mode)[0]
+    ref = oracle_mod.expect_grad(10, c["gates"], c["params"], c["codes"], c["coeffs"], want_state=True)
+    np.testing.assert_allclose(st, ref["state"], atol=1e-13)
+    check_expect_grad(P, oracle_mod, 10, c["gates"], c["params"][None, :], None, c["codes"], c["coeffs"], "c128", mode)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+def test_hea_tfim_batched(P, oracle_mod, dtype, mode):
+    """Reduced-size instance of the n=28 HEA/TFIM workload (same generator), batch 3."""
+    c = W.cfg2(n=16, layers=3)
+    r = np.random.default_rng(5)
+    pb = np.stack([c["params"], r.uniform(0, 2 * np.pi, c["n_params"]), r.uniform(0, 2 * np.pi, c["n_params"])])
+    check_expect_grad(P, oracle_mod, 16, c["gates"], pb, None, c["codes"], c["coeffs"], dtype, mode)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+def test_xxz_batched(P, oracle_mod, dtype, mode):
+    """Batched XXZ workload (n=16, L=8) on a subset of parameter sets."""
+    c = W.cfg3(batch=4)
+    check_expect_grad(P, oracle_mod, 16, c["gates"], c["params"], None, c["codes"], c["coeffs"], dtype, mode)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("n", [5, 11, 12, 14])
+def test_random_circuits_all_kinds_with_gate_gradients(P, oracle_mod, dtype, mode, n):
+    r = np.random.default_rng(500 + n)
+    gates, params, mats = W.random_circuit(n, 80, r)
+    codes, coeffs = W.random_pauli_sum(n, 10, r, max_weight=4)
+    init = W.random_state(n, r)
+    if dtype == "c64":
+        init = init.astype(np.complex64).astype(np.complex128)
+    pb = np.stack([params, r.uniform(0, 2 * np.pi, params.shape)])
+    check_expect_grad(P, oracle_mod, n, gates, pb, mats, codes, coeffs, dtype, mode, lie=True, init=init)
+
+
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+def test_fsim_brickwork_2d_tfim(P, oracle_mod, mode):
+    """Reduced-size instance of the n=32 fSim / 2D TFIM workload: 4x4 lattice, depth 8."""
+    c = W.cfg5(rows=4, cols=4, depth=8)
+    check_expect_grad(P, oracle_mod, 16, c["gates"], c["params"][None, :], None, c["codes"], c["coeffs"], "c64", mode)
+
+
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+def test_haar_brickwork_lie_gradients(P, oracle_mod, mode):
+    """Haar brick-wall circuits with random 2-local H (the uneven-batch generator, small n)."""
+    c = W.cfg4(count=3, n_lo=11, n_hi=14, d_lo=2, d_hi=6, seed=44)
+    for cc in c["circuits"]:
+        check_expect_grad(P, oracle_mod, cc["n"], cc["gates"], np.zeros((1, 0)), cc["mats"], cc["codes"],
+                          cc["coeffs"], "c64", mode, lie=True)
+
+
+def test_autograd_function(P, oracle_mod):
+    c = W.cfg2(n=12, layers=2)
+    circ = P.Circuit(12, c["gates"], c["n_params"])
+    H = P.PauliSum(12, c["codes"], c["coeffs"])
+    theta = torch.tensor(c["params"], dtype=torch.float64, device="cuda", requires_grad=True)
+    E = P.TcngEnergy.apply(theta, circ, H, torch.complex128)
+    (2.0 * E).backward()
+    ref = oracle_mod.expect_grad(12, c["gates"], c["params"], c["codes"], c["coeffs"])
+    assert abs(E.item() - ref["E"]) < 1e-12 * 20
+    np.testing.assert_allclose(theta.grad.cpu().numpy(), 2.0 * ref["grad"], atol=1e-11)
+
+
+def test_results_are_deterministic(P):
+    c = W.cfg3(batch=8)
+    circ = P.Circuit(16, c["gates"], c["n_params"])
+    H = P.PauliSum(16, c["codes"], c["coeffs"])
+    p = dev(c["params"], torch.float32)
+    e1, g1 = P.expect_grad(circ, p, H, batch=8)
+    e2, g2 = P.expect_grad(circ, p, H, batch=8)
+    assert torch.equal(e1, e2) and torch.equal(g1, g2)

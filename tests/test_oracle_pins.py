@@ -332,3 +332,14 @@ def test_product_state_gradient_closed_form(oracle_mod):
         gf[i] = h * dbx_df[i]
     a = oracle_mod.expect_grad(n, gates, params, codes, coeffs)
     np.testing.assert_allclose(a["grad"], np.concatenate([gt, gf]), atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_k_qubit_matrix_matches_tensor_contraction(oracle_mod, k):
+    n = 7
+    r = rng(900 + k)
+    qs = [int(v) for v in r.choice(n, size=k, replace=False)]
+    A = r.standard_normal((2 ** k, 2 ** k)) + 1j * r.standard_normal((2 ** k, 2 ** k))
+    psi = W.random_state(n, r)
+    got = oracle_mod.apply_matrix(n, psi, qs, A)
+    np.testing.assert_allclose(got, B.apply_tn(psi, n, A, qs), atol=1e-12)
