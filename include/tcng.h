@@ -145,8 +145,9 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
  *   energy: DEVICE float64 [batch], E_b;
  *   grad  : DEVICE float64 [batch][n_params], dE_b/dtheta summed over every use;
  *   gate_grad (nullable): DEVICE float64 [batch][n_gates][15]: for each
- *           two-qubit gate, dE/dalpha_k for U -> exp(-i alpha_k P_k / 2) U,
- *           P_k = sigma_a (x) sigma_b, k = 4a + b - 1 (zero rows for other gates).
+ *           constant two-qubit gate (TCNG_U2), dE/dalpha_k for
+ *           U -> exp(-i alpha_k P_k / 2) U, P_k = sigma_a (x) sigma_b acting on
+ *           (q0, q1), k = 4a + b - 1; rows of all other gates are zero.
  * The reverse sweep recomputes states by applying inverse gates; nothing is
  * stored per gate. */
 tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,

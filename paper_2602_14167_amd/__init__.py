@@ -161,11 +161,15 @@ def _params(circ, params, psi, batch):
     return p, ctypes.c_void_p(p.data_ptr())
 
 
-def run_circuit(circ: Circuit, params, psi: torch.Tensor, mode="tiled"):
+def run_circuit(circ: Circuit, params, psi: torch.Tensor, mode="tiled", ws=None):
     """Apply the circuit in place to every batch member (params [batch][n_params])."""
     s = _state(psi, circ.n)
+    m = _mode(mode)
     p, pp = _params(circ, params, psi, s.batch)
-    check(lib().tcng_run_circuit(circ.handle, pp, ctypes.byref(s), _mode(mode), None, 0, _stream()))
+    if ws is None:
+        ws = _workspace(circ, None, s.dtype, s.batch, m, psi.device)
+    check(lib().tcng_run_circuit(circ.handle, pp, ctypes.byref(s), m, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 _stream()))
     return psi
 
 

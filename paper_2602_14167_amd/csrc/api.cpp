@@ -184,11 +184,22 @@ int pauli_wgs_plain(int n, int64_t batch) {
 struct WsLayout {
     size_t part_off = 0, part_bytes = 0;
     size_t epart_off = 0, epart_bytes = 0;
+    size_t red_off = 0, red_bytes = 0;     // row sums of the partials
+    size_t opm_off = 0, opm_bytes = 0;     // matrix entries of the plan's ops per batch member
     size_t total = 0;
     int rev_wgs = 0, e_wgs = 0, e_rows = 0, total_slots = 0;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+void finish_layout(WsLayout& L, int64_t batch) {
+    L.part_off = 0;
+    L.epart_off = align256(L.part_bytes);
+    L.red_off = L.epart_off + align256(L.epart_bytes);
+    L.red_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1) + std::max(L.e_rows, 1)) * sizeof(double);
+    L.opm_off = L.red_off + align256(L.red_bytes);
+    L.total = L.opm_off + align256(L.opm_bytes);
+}
 
 bool use_tiled(int mode, int n, int dtype) { return mode == TCNG_MODE_TILED && tiled_ok(n, dtype); }
 
@@ -196,6 +207,8 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
     WsLayout L;
     const bool tiled = use_tiled(mode, n, dtype);
     if (c) {
+        if (tiled)
+            L.opm_bytes = size_t(batch) * c->tiled[dtype].host.ops.size() * 16 * (dtype == TCNG_C64 ? 8 : 16);
         L.total_slots = tiled ? c->tiled[dtype].host.total_slots : c->plain.total;
         L.rev_wgs = tiled ? rev_wgs_tiled(n, dtype, batch) : rev_wgs_plain(n, batch);
         L.part_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1)) * size_t(L.rev_wgs) * sizeof(double);
@@ -211,23 +224,30 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
         L.e_rows = std::max(L.e_rows, 1);
         L.epart_bytes = size_t(batch) * size_t(L.e_rows) * size_t(L.e_wgs) * sizeof(double);
     }
-    L.part_off = 0;
-    L.epart_off = align256(L.part_bytes);
-    L.total = L.epart_off + align256(L.epart_bytes);
-    if (L.total == 0) L.total = 256;
+    finish_layout(L, batch);
     return L;
 }
 
+// op matrix entries for the tiled passes (once per evaluation)
+template <typename R>
+tcng_status build_ops(const tcng_circuit* c, const void* params, int64_t batch, int dt, void* opm, hipStream_t st) {
+    const DevCircuitPlan& P = c->tiled[dt];
+    DevPlan dp{P.passes, P.phases, P.ops};
+    PROF_TRY(F_FINISH, launch_build_ops<R>(dp, int(P.host.ops.size()), params, c->n_params, c->cm[dt], batch, opm, st));
+    return TCNG_OK;
+}
+
 template <typename R, int RB>
-tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_state* s, int mode, hipStream_t st) {
+tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_state* s, int mode, const void* opm,
+                        hipStream_t st) {
     const int dt = s->dtype;
     const int n = s->n_qubits;
     if (use_tiled(mode, n, dt)) {
         const DevCircuitPlan& P = c->tiled[dt];
         DevPlan dp{P.passes, P.phases, P.ops};
         for (size_t p = 0; p < P.host.passes.size(); ++p)
-            PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(dp, int(p), P.host.passes[p].m, s->amps, s->stride, n, s->batch, params,
-                                             c->n_params, c->cm[dt], st)));
+            PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(dp, int(p), P.host.passes[p].m, s->amps, s->stride, n, s->batch,
+                                                          opm, int(P.host.ops.size()), st)));
     } else {
         for (const tcng_gate& g : c->gates) {
             if (kind_arity(g.kind) == 1)
@@ -271,7 +291,7 @@ tcng_status run_pauli(const tcng_pauli_sum* h, const tcng_state* s, void* lam, c
 
 template <typename R, int RB>
 tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_state* psi, void* lam,
-                        const WsLayout& L, double* part, int mode, hipStream_t st) {
+                        const WsLayout& L, double* part, int mode, const void* opm, hipStream_t st) {
     const int dt = psi->dtype;
     const int n = psi->n_qubits;
     if (use_tiled(mode, n, dt)) {
@@ -279,7 +299,8 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
         DevPlan dp{P.passes, P.phases, P.ops};
         for (int p = int(P.host.passes.size()) - 1; p >= 0; --p)
             PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(dp, p, P.host.passes[p].m, psi->amps, lam, psi->stride, n, psi->batch,
-                                             params, c->n_params, c->cm[dt], L.rev_wgs, part, L.total_slots, st)));
+                                                          opm, int(P.host.ops.size()), L.rev_wgs, part, L.total_slots,
+                                                          st)));
     } else {
         for (int gi = int(c->gates.size()) - 1; gi >= 0; --gi) {
             const tcng_gate& g = c->gates[gi];
@@ -555,14 +576,23 @@ tcng_status tcng_workspace_size(const tcng_circuit* c, const tcng_pauli_sum* h, 
 
 tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tcng_state* s, int32_t mode, void* ws,
                              size_t ws_bytes, void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (tcng_status e = check_state(s, "tcng_run_circuit")) return e;
     if (tcng_status e = check_circuit_state(c, s, params)) return e;
     if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN) return fail(TCNG_E_INVALID, "bad mode");
+    const WsLayout L = layout(c, nullptr, s->n_qubits, s->dtype, s->batch, mode);
+    const bool tiled = use_tiled(mode, s->n_qubits, s->dtype);
+    if (tiled && (!ws || ws_bytes < L.total))
+        return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    tcng_status e = s->dtype == TCNG_C64 ? run_forward<float, 5>(c, params, s, mode, st)
-                                         : run_forward<double, 4>(c, params, s, mode, st);
+    void* opm = tiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
+    tcng_status e;
+    if (s->dtype == TCNG_C64) {
+        e = tiled ? build_ops<float>(c, params, s->batch, s->dtype, opm, st) : TCNG_OK;
+        if (!e) e = run_forward<float, 5>(c, params, s, mode, opm, st);
+    } else {
+        e = tiled ? build_ops<double>(c, params, s->batch, s->dtype, opm, st) : TCNG_OK;
+        if (!e) e = run_forward<double, 4>(c, params, s, mode, opm, st);
+    }
     return e ? e : ok();
 }
 
@@ -580,8 +610,9 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
     tcng_status e = s->dtype == TCNG_C64 ? run_pauli<float, 5>(h, s, nullptr, L, epart, mode, st)
                                          : run_pauli<double, 4>(h, s, nullptr, L, epart, mode, st);
     if (e) return e;
+    double* red = reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off);
     PROF_TRY(F_FINISH, launch_finish(nullptr, 0, 1, nullptr, nullptr, 0, epart, L.e_rows, L.e_wgs, s->batch, out, nullptr,
-                          nullptr, nullptr, nullptr, nullptr, 0, st));
+                          nullptr, nullptr, nullptr, nullptr, 0, red, st));
     return ok();
 }
 
@@ -609,28 +640,31 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     L.e_rows = Lh.e_rows;
     L.e_wgs = Lh.e_wgs;
     L.epart_bytes = Lh.epart_bytes;
-    L.epart_off = align256(L.part_bytes);
-    L.total = L.epart_off + align256(L.epart_bytes);
+    finish_layout(L, psi->batch);
     if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part_off);
     double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
+    const bool ctiled = use_tiled(mode, psi->n_qubits, dt);
+    void* opm = ctiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
     tcng_status e;
     if (dt == TCNG_C64) {
-        e = run_forward<float, 5>(c, params, psi, mode, st);
+        e = ctiled ? build_ops<float>(c, params, psi->batch, dt, opm, st) : TCNG_OK;
+        if (!e) e = run_forward<float, 5>(c, params, psi, mode, opm, st);
         if (!e) e = run_pauli<float, 5>(h, psi, lam->amps, L, epart, pmode, st);
-        if (!e) e = run_reverse<float, 5>(c, params, psi, lam->amps, L, part, mode, st);
+        if (!e) e = run_reverse<float, 5>(c, params, psi, lam->amps, L, part, mode, opm, st);
     } else {
-        e = run_forward<double, 4>(c, params, psi, mode, st);
+        e = ctiled ? build_ops<double>(c, params, psi->batch, dt, opm, st) : TCNG_OK;
+        if (!e) e = run_forward<double, 4>(c, params, psi, mode, opm, st);
         if (!e) e = run_pauli<double, 4>(h, psi, lam->amps, L, epart, pmode, st);
-        if (!e) e = run_reverse<double, 4>(c, params, psi, lam->amps, L, part, mode, st);
+        if (!e) e = run_reverse<double, 4>(c, params, psi, lam->amps, L, part, mode, opm, st);
     }
     if (e) return e;
     const bool tiled = use_tiled(mode, psi->n_qubits, dt);
     const SlotTables& S = tiled ? c->tiled[dt].slots : c->plain;
     PROF_TRY(F_FINISH, launch_finish(part, std::max(L.total_slots, 1), L.rev_wgs, S.ptr, S.idx, c->n_params, epart, L.e_rows,
                           L.e_wgs, psi->batch, energy, grad, gate_grad, S.gate_slot, c->u2m[dt], c->gate_mat,
-                          int(c->gates.size()), st));
+                          int(c->gates.size()), reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off), st));
     return ok();
 }
 

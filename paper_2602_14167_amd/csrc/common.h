@@ -73,23 +73,30 @@ enum OpType : int8_t {
     OP_CX = 2,      // CNOT: target in register bit r1, control bit (r0 | lb0)
     OP_DENSE2 = 3,  // 4x4 matrix, operands in register bits r0 (MSB) and r1
     OP_DIAG2 = 4,   // diagonal 4x4 on bits (r0 | lb0), (r1 | lb1)
+    OP_REAL1 = 5,   // real 2x2 matrix (RY, H, X), operand in register bit r0
+    OP_RX = 6,      // [[c, -is], [-is, c]], operand in register bit r0
+    OP_FSIM = 7,    // fSim: |01>,|10> block [[c, -is], [-is, c]], |11> phase; register bits r0, r1
 };
+
+// Descriptor fields are 32-bit: the kernels read them with scalar loads
+// (gfx9 has no scalar sub-dword loads; byte fields become per-lane vector
+// loads whose waits serialise the amplitude traffic).
 
 // One gate inside a phase.  A qubit operand is either a register bit
 // (r >= 0: bit r of the register index j) or a thread bit (r < 0: bit lb of
 // the thread's part of the local index).
 struct Op {
-    int8_t type, kind, r0, r1, lb0, lb1, pad0, pad1;
+    int32_t type, kind, r0, r1, lb0, lb1;
     int32_t p0, p1, mat;
     int32_t slot;   // first gradient slot of this gate inside its reverse pass, -1 none
     int32_t gate;   // gate index in the circuit
-    int32_t pad2;
+    int32_t pad;
 };
 
 // A run of ops that all act on the same RB local bits held in registers.
 struct Phase {
     int32_t op_begin, op_end;
-    int8_t R[8];     // local bit position of register bit i (i < RB)
+    int32_t R[6];    // local bit position of register bit i (i < RB)
 };
 
 // One HBM round trip: tiles of 2^m amplitudes over the qubits in tile_mask.
@@ -100,7 +107,7 @@ struct Pass {
     int32_t m, lo;
     int32_t n_slots, slot_base;   // reverse sweep: gradient slots [slot_base, slot_base + n_slots)
     uint64_t tile_mask;
-    int8_t local_qubit[16];
+    int32_t local_qubit[16];
 };
 
 // Pauli sum, grouped by X-mask, for the tiled H|psi> / <H> passes.  Inside a
@@ -124,7 +131,7 @@ struct PPass {
     int32_t group_begin, group_end;
     int32_t m, lo;
     uint64_t tile_mask;
-    int8_t local_qubit[16];
+    int32_t local_qubit[16];
 };
 
 // Pauli sum grouped by X-mask over the full index space (plain path).

@@ -150,6 +150,69 @@ __device__ __forceinline__ Regs<R, NB> app_dense2(Regs<R, NB> a, M4<R> u) {
     return a;
 }
 
+// real 2x2 matrix (u0 u1; u2 u3) on register bit B: RY, H, X
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_real1(Regs<R, NB> a, R u0, R u1, R u2, R u3) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        const cx<R> x0 = a.v[j], x1 = a.v[j | (1 << B)];
+        a.v[j] = {fmaR(u1, x1.re, u0 * x0.re), fmaR(u1, x1.im, u0 * x0.im)};
+        a.v[j | (1 << B)] = {fmaR(u3, x1.re, u2 * x0.re), fmaR(u3, x1.im, u2 * x0.im)};
+    }
+    return a;
+}
+
+// [[c, -i s], [-i s, c]] on register bit B (RX with c = cos t/2, s = sin t/2)
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_rx(Regs<R, NB> a, R c, R s) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        const cx<R> x0 = a.v[j], x1 = a.v[j | (1 << B)];
+        a.v[j] = {fmaR(s, x1.im, c * x0.re), fmaR(-s, x1.re, c * x0.im)};
+        a.v[j | (1 << B)] = {fmaR(s, x0.im, c * x1.re), fmaR(-s, x0.re, c * x1.im)};
+    }
+    return a;
+}
+
+// diagonal (d0, d1) on register bit B (compile-time selection)
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_diag1r(Regs<R, NB> a, cx<R> d0, cx<R> d1) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a.v[j] = a.v[j] * ((j & (1 << B)) ? d1 : d0);
+    return a;
+}
+
+// CNOT with target register bit BT and control register bit BC: a renaming
+template <typename R, int NB, int BT, int BC>
+__device__ __forceinline__ Regs<R, NB> app_cxr(Regs<R, NB> a) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if ((j & (1 << BT)) || !(j & (1 << BC))) continue;
+        const cx<R> t = a.v[j];
+        a.v[j] = a.v[j | (1 << BT)];
+        a.v[j | (1 << BT)] = t;
+    }
+    return a;
+}
+
+// fSim on register bits (B0 = q0, B1 = q1): |01>,|10> block [[c, -is], [-is, c]],
+// |11> multiplied by ph
+template <typename R, int NB, int B0, int B1>
+__device__ __forceinline__ Regs<R, NB> app_fsim(Regs<R, NB> a, R c, R s, cx<R> ph) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & ((1 << B0) | (1 << B1))) continue;
+        const int i1 = j | (1 << B1), i2 = j | (1 << B0), i3 = j | (1 << B0) | (1 << B1);
+        const cx<R> x1 = a.v[i1], x2 = a.v[i2];
+        a.v[i1] = {fmaR(s, x2.im, c * x1.re), fmaR(-s, x2.re, c * x1.im)};
+        a.v[i2] = {fmaR(s, x1.im, c * x2.re), fmaR(-s, x1.re, c * x2.im)};
+        a.v[i3] = a.v[i3] * ph;
+    }
+    return a;
+}
+
 // CNOT with the target in register bit B; control either register bit rc
 // (rc >= 0) or the thread-constant bit value tb.
 template <typename R, int NB, int B>

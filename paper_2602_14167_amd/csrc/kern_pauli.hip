@@ -25,9 +25,11 @@ struct PTile {
     static constexpr int ELEMS = (sizeof(R) == 4) ? (1 << 13) : (1 << 12);
 };
 
-__device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int8_t* lq) {
+__device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int* lq) {
     uint64_t g = l & ((1u << lo) - 1);
-    for (int i = lo; i < m; ++i) g |= uint64_t((l >> i) & 1) << lq[i];
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_BITS; ++i)
+        if (i >= lo && i < m) g |= uint64_t((l >> i) & 1) << lq[i];
     return g;
 }
 
@@ -76,7 +78,9 @@ k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups
     const PPass& P = passes[pass_idx];
     const int m = P.m, lo = P.lo;
     const uint64_t tmask = P.tile_mask;
-    const int8_t* lq = P.local_qubit;
+    int lq[MAX_TILE_BITS];
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_BITS; ++i) lq[i] = P.local_qubit[i];
     const int nt = 1 << (m - RB);
     const int t = threadIdx.x;
     const int64_t b = blockIdx.x / wgs;
@@ -95,8 +99,9 @@ k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups
             lds[l] = psi[base + loc2glob(l, lo, m, lq)];
         }
         __syncthreads();
-        // elements l = it*nt + t, CH at a time (few live registers per thread)
-        constexpr int CH = 4;
+        // elements l = it*nt + t, CH at a time; the term loop is outside the
+        // element loop so every scalar load of a term serves CH elements
+        constexpr int CH = (NB < 8) ? NB : 8;
         for (int c0 = 0; c0 < NB; c0 += CH) {
             cx<R> acc[CH];
 #pragma unroll
@@ -106,31 +111,44 @@ k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups
             }
             for (int g = P.group_begin; g < P.group_end; ++g) {
                 const PGroup G = groups[g];
+                double cre[CH], cim[CH];
+#pragma unroll
+                for (int i = 0; i < CH; ++i) { cre[i] = 0.0; cim[i] = 0.0; }
+                for (int c = G.class_begin; c < G.class_end; ++c) {
+                    const PClass C = classes[c];
+                    int odd[CH];
+#pragma unroll
+                    for (int i = 0; i < CH; ++i) odd[i] = 0;
+                    for (int k = C.term_begin; k < C.term_end; ++k) {
+                        const PTerm T = terms[k];
+                        const uint32_t zl = uint32_t(T.z_local);
+                        const uint32_t tp = uint32_t(__popcll(base & T.z_out) & 1);   // tile-constant part
+#pragma unroll
+                        for (int i = 0; i < CH; ++i) {
+                            const uint32_t lp = uint32_t((c0 + i) * nt + t) ^ uint32_t(G.x_local);
+                            odd[i] += int((__popc(lp & zl) + tp) & 1u);
+                        }
+                    }
+                    const int nterm = C.term_end - C.term_begin;
+#pragma unroll
+                    for (int i = 0; i < CH; ++i) {
+                        const double sgn = double(nterm - 2 * odd[i]);
+                        cre[i] = fma(C.cre, sgn, cre[i]);
+                        cim[i] = fma(C.cim, sgn, cim[i]);
+                    }
+                }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
                     const uint32_t l = uint32_t((c0 + i) * nt + t);
                     const uint32_t lp = l ^ uint32_t(G.x_local);
                     const cx<R> pp = lds[lp], own = lds[l];
-                    double cre = 0.0, cim = 0.0;
-                    for (int c = G.class_begin; c < G.class_end; ++c) {
-                        const PClass C = classes[c];
-                        int odd = 0;
-                        for (int k = C.term_begin; k < C.term_end; ++k) {
-                            const PTerm T = terms[k];
-                            const int tp = __popcll(base & T.z_out) & 1;   // tile-constant part
-                            odd += (__popc(lp & uint32_t(T.z_local)) + tp) & 1;
-                        }
-                        const double sgn = double(C.term_end - C.term_begin - 2 * odd);
-                        cre = fma(C.cre, sgn, cre);
-                        cim = fma(C.cim, sgn, cim);
-                    }
                     // contribution = (cre + i cim) * psi_{l^x}
-                    const cx<R> cc = {R(cre), R(cim)};
+                    const cx<R> cc = {R(cre[i]), R(cim[i])};
                     acc[i] = cfma(cc, pp, acc[i]);
                     // E += Re(conj(psi_l) * contribution), float64
                     const double rr = fma(double(own.re), double(pp.re), double(own.im) * double(pp.im));
                     const double ri = fma(double(own.re), double(pp.im), -double(own.im) * double(pp.re));
-                    e_acc += cre * rr - cim * ri;
+                    e_acc += cre[i] * rr - cim[i] * ri;
                 }
             }
             if (lam) {

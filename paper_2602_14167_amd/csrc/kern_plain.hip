@@ -313,10 +313,24 @@ __global__ void k_zero(double* __restrict__ p, size_t count) {
         p[i] = 0.0;
 }
 
+// row sums of the per-workgroup partials: one wave per row, lanes stride the
+// row, then a butterfly (fixed order: deterministic)
+__global__ void __launch_bounds__(256) k_rowsum(const double* __restrict__ in, int64_t rows, int len,
+                                                double* __restrict__ out) {
+    const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;   // whole wave leaves together
+    const double* p = in + size_t(row) * len;
+    double v = 0.0;
+    for (int i = lane; i < len; i += 64) v += p[i];
+    v = wave_sum(v);
+    if (lane == 0) out[row] = v;
+}
+
 // final sums: one thread per (member, output), fixed order everywhere
-__global__ void k_finish(const double* __restrict__ part, int total_slots, int wgs, const int32_t* __restrict__ slot_ptr,
-                         const int32_t* __restrict__ slot_idx, int n_params, const double* __restrict__ epart,
-                         int erows, int ewgs, int64_t batch, double* __restrict__ energy, double* __restrict__ grad,
+__global__ void k_finish(const double* __restrict__ slots, int total_slots, const int32_t* __restrict__ slot_ptr,
+                         const int32_t* __restrict__ slot_idx, int n_params, const double* __restrict__ erow,
+                         int erows, int64_t batch, double* __restrict__ energy, double* __restrict__ grad,
                          double* __restrict__ gate_grad, const int32_t* __restrict__ gate_slot,
                          const double* __restrict__ u2m, const int32_t* __restrict__ gate_mat, int n_gates) {
     const int64_t per = int64_t(1) + n_params + (gate_grad ? int64_t(n_gates) : 0);
@@ -324,21 +338,15 @@ __global__ void k_finish(const double* __restrict__ part, int total_slots, int w
     if (tid >= per * batch) return;
     const int64_t b = tid / per;
     const int64_t k = tid - b * per;
-    auto slot_sum = [&](int s) {
-        double v = 0.0;
-        const double* p = part + (size_t(b) * total_slots + s) * wgs;
-        for (int w = 0; w < wgs; ++w) v += p[w];
-        return v;
-    };
+    const double* sl = slots + size_t(b) * total_slots;
     if (k == 0) {
         double e = 0.0;
-        const double* p = epart + size_t(b) * erows * ewgs;
-        for (int i = 0; i < erows * ewgs; ++i) e += p[i];
+        for (int i = 0; i < erows; ++i) e += erow[size_t(b) * erows + i];
         energy[b] = e;
     } else if (k <= n_params) {
         const int p = int(k - 1);
         double g = 0.0;
-        for (int i = slot_ptr[p]; i < slot_ptr[p + 1]; ++i) g += slot_sum(slot_idx[i]);
+        for (int i = slot_ptr[p]; i < slot_ptr[p + 1]; ++i) g += sl[slot_idx[i]];
         grad[size_t(b) * n_params + p] = g;
     } else {
         // per U2 gate: dE/dalpha_k = Im tr(G^dag P_k U), P_k = sigma_a (x) sigma_b, k = 4a + b - 1
@@ -349,8 +357,6 @@ __global__ void k_finish(const double* __restrict__ part, int total_slots, int w
             for (int i = 0; i < 15; ++i) out[i] = 0.0;
             return;
         }
-        double Gr[16], Gi[16];
-        for (int i = 0; i < 16; ++i) { Gr[i] = slot_sum(s0 + 2 * i); Gi[i] = slot_sum(s0 + 2 * i + 1); }
         const double* U = u2m + size_t(gate_mat[gi]) * 32;
         // single-qubit Paulis: entry (r, c) of sigma_a as (re, im)
         auto sig = [](int a, int r, int c, double& re, double& im) {
@@ -377,7 +383,7 @@ __global__ void k_finish(const double* __restrict__ part, int total_slots, int w
                         pui += pr * ui + pi * ur;
                     }
                     // conj(G[y][x]) * (PU)[y][x]
-                    const double gr = Gr[4 * y + x], gim = Gi[4 * y + x];
+                    const double gr = sl[s0 + 2 * (4 * y + x)], gim = sl[s0 + 2 * (4 * y + x) + 1];
                     tr_im += gr * pui - gim * pur;
                 }
             out[kk] = tr_im;
@@ -466,12 +472,25 @@ hipError_t launch_zero(double* p, size_t count, hipStream_t st) {
 hipError_t launch_finish(const double* part, int total_slots, int wgs, const int32_t* slot_ptr,
                          const int32_t* slot_idx, int n_params, const double* epart, int erows, int ewgs,
                          int64_t batch, double* energy, double* grad, double* gate_grad, const int32_t* gate_slot,
-                         const double* u2_mats_c128, const int32_t* gate_mat, int n_gates, hipStream_t st) {
+                         const double* u2_mats_c128, const int32_t* gate_mat, int n_gates, double* scratch,
+                         hipStream_t st) {
+    // scratch: [batch][total_slots] slot sums, then [batch][erows] energy row sums
+    double* slots = scratch;
+    double* erow = scratch + size_t(batch) * total_slots;
+    const int64_t srows = batch * int64_t(total_slots), er = batch * int64_t(erows);
+    if (srows > 0 && part) {
+        hipLaunchKernelGGL(k_rowsum, dim3(unsigned((srows + 3) / 4)), dim3(256), 0, st, part, srows, wgs, slots);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_rowsum, dim3(unsigned((er + 3) / 4)), dim3(256), 0, st, epart, er, ewgs, erow);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int64_t per = 1 + n_params + (gate_grad ? n_gates : 0);
     const int64_t work = per * batch;
-    hipLaunchKernelGGL(k_finish, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, part, total_slots, wgs,
-                       slot_ptr, slot_idx, n_params, epart, erows, ewgs, batch, energy, grad, gate_grad, gate_slot,
-                       u2_mats_c128, gate_mat, n_gates);
+    hipLaunchKernelGGL(k_finish, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, slots, total_slots, slot_ptr,
+                       slot_idx, n_params, erow, erows, batch, energy, grad, gate_grad, gate_slot, u2_mats_c128,
+                       gate_mat, n_gates);
     return hipGetLastError();
 }
 

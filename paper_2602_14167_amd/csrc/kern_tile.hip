@@ -29,10 +29,13 @@ struct Tile {
     static constexpr int ELEMS = (sizeof(R) == 4) ? (1 << 13) : (1 << 12);   // 64 KiB of LDS
 };
 
-// amplitude index offset of a local index l (disjoint bit sets add)
-__device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int8_t* lq) {
+// amplitude index offset of a local index l (disjoint bit sets add);
+// lq[] holds the qubit of every local bit (identity below lo)
+__device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int* lq) {
     uint64_t g = l & ((1u << lo) - 1);
-    for (int i = lo; i < m; ++i) g |= uint64_t((l >> i) & 1) << lq[i];
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_BITS; ++i)
+        if (i >= lo && i < m) g |= uint64_t((l >> i) & 1) << lq[i];
     return g;
 }
 
@@ -83,7 +86,7 @@ struct V16<double> {
 struct PassInfo {
     int m, lo;
     uint64_t tmask;
-    const int8_t* lq;   // local bit -> qubit, read from the plan in global memory
+    int lq[MAX_TILE_BITS];   // local bit -> qubit (uniform: scalar registers)
 };
 
 __device__ __forceinline__ PassInfo read_pass(const Pass& P) {
@@ -91,7 +94,8 @@ __device__ __forceinline__ PassInfo read_pass(const Pass& P) {
     pi.m = P.m;
     pi.lo = P.lo;
     pi.tmask = P.tile_mask;
-    pi.lq = P.local_qubit;
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_BITS; ++i) pi.lq[i] = P.local_qubit[i];
     return pi;
 }
 
@@ -149,6 +153,7 @@ __device__ __forceinline__ PhaseMap phase_map(const Phase& F, int t, int m) {
         pm.rbit[i] = 1u << F.R[i];
         rmask |= pm.rbit[i];
     }
+    // (F.R is read with scalar loads: 32-bit fields)
     // deposit the thread index into the non-register local bits
     uint32_t tp = 0;
     int k = 0;
@@ -221,6 +226,56 @@ __device__ __forceinline__ Regs<R, (1 << RB)> dense2_at(Regs<R, (1 << RB)> a, in
     return a;
 }
 template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> real1_at(Regs<R, (1 << RB)> a, int r, R u0, R u1, R u2, R u3) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_real1<R, (1 << RB), B>(a, u0, u1, u2, u3); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> rx_at(Regs<R, (1 << RB)> a, int r, R c, R s) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_rx<R, (1 << RB), B>(a, c, s); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> diag1r_at(Regs<R, (1 << RB)> a, int r, cx<R> d0, cx<R> d1) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_diag1r<R, (1 << RB), B>(a, d0, d1); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> cxr_at(Regs<R, (1 << RB)> a, int rt, int rc) {
+    switch (rt * 8 + rc) {
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) a = app_cxr<R, (1 << RB), B0, B1>(a); break;
+        TCNG_PAIRS(C2)
+#undef C2
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> fsim_at(Regs<R, (1 << RB)> a, int r0, int r1, R c, R s, cx<R> ph) {
+    switch (r0 * 8 + r1) {
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) a = app_fsim<R, (1 << RB), B0, B1>(a, c, s, ph); break;
+        TCNG_PAIRS(C2)
+#undef C2
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
 __device__ __forceinline__ double grad_rot1_at(int kind, int r, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
     double g = 0.0;
     switch (r) {
@@ -254,49 +309,100 @@ __device__ __forceinline__ double2 cot_u2_at(int r0, int r1, Regs<R, (1 << RB)> 
     return g;
 }
 
-// apply one op (forward, or its inverse when INV) to the register block
+// apply one op (forward, or its inverse when INV) to the register block;
+// om: the op's matrix entries for this batch member (k_build_ops)
 template <typename R, int RB, bool INV>
 __device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, const Op& op, uint32_t tpart,
-                                                      const R* prm, const cx<R>* cm) {
+                                                      const cx<R>* __restrict__ om) {
     const int tb0 = op.lb0 >= 0 ? int((tpart >> op.lb0) & 1) : 0;
     const int tb1 = op.lb1 >= 0 ? int((tpart >> op.lb1) & 1) : 0;
     switch (op.type) {
         case OP_DENSE1: {
             M2<R> u;
-            mat1<R>(op.kind, prm, op.p0, cm, op.mat, u.e);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) u.e[i] = om[i];
             if (INV) dagger_inplace<R, 2>(u.e);
             a = dense1_at<R, RB>(a, op.r0, u);
             break;
         }
+        case OP_REAL1: {
+            // real orthogonal: the inverse is the transpose
+            const R u0 = om[0].re, u1 = om[1].re, u2 = om[2].re, u3 = om[3].re;
+            a = INV ? real1_at<R, RB>(a, op.r0, u0, u2, u1, u3) : real1_at<R, RB>(a, op.r0, u0, u1, u2, u3);
+            break;
+        }
+        case OP_RX: {
+            const R c = om[0].re, s = -om[1].im;
+            a = rx_at<R, RB>(a, op.r0, c, INV ? -s : s);
+            break;
+        }
+        case OP_FSIM: {
+            const R c = om[5].re, s = -om[6].im;
+            const cx<R> ph = INV ? conj(om[15]) : om[15];
+            a = fsim_at<R, RB>(a, op.r0, op.r1, c, INV ? -s : s, ph);
+            break;
+        }
         case OP_DIAG1: {
-            D4<R> d;
-            diag1<R>(op.kind, prm, op.p0, d.e);
-            if (INV) { d.e[0] = conj(d.e[0]); d.e[1] = conj(d.e[1]); }
-            a = app_diag<R, (1 << RB)>(a, op.r0, tb0, -1, 0, false, d);
+            const cx<R> d0 = INV ? conj(om[0]) : om[0];
+            const cx<R> d1 = INV ? conj(om[1]) : om[1];
+            if (op.r0 >= 0) {
+                a = diag1r_at<R, RB>(a, op.r0, d0, d1);
+            } else {
+                D4<R> d;
+                d.e[0] = d0;
+                d.e[1] = d1;
+                d.e[2] = d.e[3] = d0;
+                a = app_diag<R, (1 << RB)>(a, -1, tb0, -1, 0, false, d);
+            }
             break;
         }
         case OP_CX:
-            a = cx_at<R, RB>(a, op.r1, op.r0, tb0);
+            if (op.r0 >= 0) a = cxr_at<R, RB>(a, op.r1, op.r0);
+            else a = cx_at<R, RB>(a, op.r1, -1, tb0);
             break;
         case OP_DENSE2: {
             M4<R> u;
-            mat2<R>(op.kind, prm, op.p0, op.p1, cm, op.mat, u.e);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) u.e[i] = om[i];
             if (INV) dagger_inplace<R, 4>(u.e);
             a = dense2_at<R, RB>(a, op.r0, op.r1, u);
             break;
         }
         default: {   // OP_DIAG2
             D4<R> d;
-            diag2<R>(op.kind, prm, op.p0, d.e);
-            if (INV) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) d.e[i] = conj(d.e[i]);
-            }
+            for (int i = 0; i < 4; ++i) d.e[i] = INV ? conj(om[i]) : om[i];
             a = app_diag<R, (1 << RB)>(a, op.r0, tb0, op.r1, tb1, true, d);
             break;
         }
     }
     return a;
+}
+
+// matrix entries of every op of a plan for every batch member, computed once
+// per evaluation: dense 2x2 (4 entries), diagonals (2 or 4), dense 4x4 (16)
+template <typename R>
+__global__ void k_build_ops(const Op* __restrict__ ops, int n_ops, const R* __restrict__ params, int64_t pstride,
+                            const cx<R>* __restrict__ cm, int64_t batch, cx<R>* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(n_ops) * batch) return;
+    const int64_t b = i / n_ops;
+    const int o = int(i - b * n_ops);
+    const Op op = ops[o];
+    const R* prm = params ? params + b * pstride : nullptr;
+    cx<R>* dst = out + size_t(i) * 16;
+    cx<R> u[16];
+    switch (op.type) {
+        case OP_DENSE1: case OP_REAL1: case OP_RX: mat1<R>(op.kind, prm, op.p0, cm, op.mat, u); break;
+        case OP_DIAG1: diag1<R>(op.kind, prm, op.p0, u); break;
+        case OP_DIAG2: diag2<R>(op.kind, prm, op.p0, u); break;
+        case OP_DENSE2: case OP_FSIM: mat2<R>(op.kind, prm, op.p0, op.p1, cm, op.mat, u); break;
+        default: break;
+    }
+    const int cnt = (op.type == OP_DENSE2 || op.type == OP_FSIM) ? 16 : (op.type == OP_CX ? 0 : 4);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (k < cnt) dst[k] = u[k];
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -311,8 +417,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename R, int RB>
 __global__ void __launch_bounds__(NTHREADS)
 k_tile_fwd(const Pass* __restrict__ passes, const Phase* __restrict__ phases, const Op* __restrict__ ops, int pass_idx,
-           cx<R>* __restrict__ state, int64_t stride, int n, const R* __restrict__ params, int64_t pstride,
-           const cx<R>* __restrict__ cmats, int64_t tiles_per_state) {
+           cx<R>* __restrict__ state, int64_t stride, int n, const cx<R>* __restrict__ opm, int n_ops,
+           int64_t tiles_per_state) {
     __shared__ cx<R> lds[Tile<R>::ELEMS];
     const Pass& P = passes[pass_idx];
     const PassInfo pi = read_pass(P);
@@ -322,7 +428,7 @@ k_tile_fwd(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
     const int64_t b = gid / tiles_per_state;
     const uint64_t tile = uint64_t(gid - b * tiles_per_state);
     cx<R>* psi = state + b * stride;
-    const R* prm = params ? params + b * pstride : nullptr;
+    const cx<R>* om = opm + size_t(b) * n_ops * 16;
     const uint64_t base = tile_base(tile, pi.tmask, n);
 
     tile_load<R, RB>(lds, psi, base, pi, t, nt);
@@ -331,7 +437,7 @@ k_tile_fwd(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
         const Phase& F = phases[f];
         const PhaseMap pm = phase_map<RB>(F, t, pi.m);
         Regs<R, (1 << RB)> a = regs_from_lds<R, RB>(lds, pm);
-        for (int o = F.op_begin; o < F.op_end; ++o) a = apply_op<R, RB, false>(a, ops[o], pm.tpart, prm, cmats);
+        for (int o = F.op_begin; o < F.op_end; ++o) a = apply_op<R, RB, false>(a, ops[o], pm.tpart, om + 16 * o);
         regs_to_lds<R, RB>(a, lds, pm);
         __syncthreads();
     }
@@ -346,8 +452,8 @@ template <typename R, int RB>
 __global__ void __launch_bounds__(NTHREADS)
 k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, const Op* __restrict__ ops, int pass_idx,
            cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int64_t stride, int n,
-           const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cmats, int64_t tiles_per_state,
-           int wgs, double* __restrict__ part, int total_slots) {
+           const cx<R>* __restrict__ opm, int n_ops, int64_t tiles_per_state, int wgs, double* __restrict__ part,
+           int total_slots) {
     __shared__ cx<R> lds[Tile<R>::ELEMS];
     __shared__ double red[RED_SLOTS * (NTHREADS / 64)];
     using Blk = Regs<R, (1 << RB)>;
@@ -361,7 +467,7 @@ k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
     const int wg = int(blockIdx.x - b * wgs);
     cx<R>* psi = state + b * stride;
     cx<R>* lam = costate + b * stride;
-    const R* prm = params ? params + b * pstride : nullptr;
+    const cx<R>* om = opm + size_t(b) * n_ops * 16;
     const int nslots = P.n_slots;
 
     for (int i = t; i < nslots * nwaves; i += nt) red[i] = 0.0;
@@ -386,9 +492,9 @@ k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
                 const Op op = ops[o];
                 if (op.slot >= 0 && op.kind != K_U2) {
                     double g0 = 0.0, g1 = 0.0;
-                    if (op.type == OP_DENSE1) {
+                    if (op.kind == K_RX || op.kind == K_RY) {
                         g0 = grad_rot1_at<R, RB>(op.kind, op.r0, la, ps);
-                    } else if (op.type == OP_DENSE2) {   // FSIM
+                    } else if (op.kind == K_FSIM) {
                         const double2 g = grad_fsim_at<R, RB>(op.r0, op.r1, la, ps);
                         g0 = g.x;
                         g1 = g.y;
@@ -405,7 +511,7 @@ k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
                         if (lane == 0) red[(op.slot + 1) * nwaves + wave] += g1;
                     }
                 }
-                ps = apply_op<R, RB, true>(ps, op, pm.tpart, prm, cmats);
+                ps = apply_op<R, RB, true>(ps, op, pm.tpart, om + 16 * o);
                 if (op.kind == K_U2 && op.slot >= 0) {
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
@@ -417,7 +523,7 @@ k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
                         }
                     }
                 }
-                la = apply_op<R, RB, true>(la, op, pm.tpart, prm, cmats);
+                la = apply_op<R, RB, true>(la, op, pm.tpart, om + 16 * o);
             }
             if (f == P.phase_begin) break;
             // hand both blocks to the previous phase's register assignment
@@ -452,37 +558,51 @@ k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, co
 
 }  // namespace
 
+template <typename R>
+hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, int64_t pstride, const void* cmats,
+                            int64_t batch, void* opm, hipStream_t st) {
+    const int64_t work = int64_t(n_ops) * batch;
+    if (work == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_build_ops<R>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, dp.ops, n_ops,
+                       static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats), batch,
+                       static_cast<cx<R>*>(opm));
+    return hipGetLastError();
+}
+
 template <typename R, int RB>
 hipError_t launch_tile_fwd(const DevPlan& dp, int pass_idx, int m, void* state, int64_t stride, int n, int64_t batch,
-                           const void* params, int64_t pstride, const void* cmats, hipStream_t st) {
+                           const void* opm, int n_ops, hipStream_t st) {
     const int64_t tiles = int64_t(1) << (n - m);
     const int nt = 1 << (m - RB);
     hipLaunchKernelGGL((k_tile_fwd<R, RB>), dim3(unsigned(tiles * batch)), dim3(nt), 0, st, dp.passes, dp.phases,
-                       dp.ops, pass_idx, static_cast<cx<R>*>(state), stride, n, static_cast<const R*>(params), pstride,
-                       static_cast<const cx<R>*>(cmats), tiles);
+                       dp.ops, pass_idx, static_cast<cx<R>*>(state), stride, n, static_cast<const cx<R>*>(opm), n_ops,
+                       tiles);
     return hipGetLastError();
 }
 
 template <typename R, int RB>
 hipError_t launch_tile_rev(const DevPlan& dp, int pass_idx, int m, void* state, void* costate, int64_t stride, int n,
-                           int64_t batch, const void* params, int64_t pstride, const void* cmats, int wgs,
-                           double* part, int total_slots, hipStream_t st) {
+                           int64_t batch, const void* opm, int n_ops, int wgs, double* part, int total_slots,
+                           hipStream_t st) {
     const int64_t tiles = int64_t(1) << (n - m);
     const int nt = 1 << (m - RB);
     hipLaunchKernelGGL((k_tile_rev<R, RB>), dim3(unsigned(wgs * batch)), dim3(nt), 0, st, dp.passes, dp.phases,
                        dp.ops, pass_idx, static_cast<cx<R>*>(state), static_cast<cx<R>*>(costate), stride, n,
-                       static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats), tiles, wgs, part,
-                       total_slots);
+                       static_cast<const cx<R>*>(opm), n_ops, tiles, wgs, part, total_slots);
     return hipGetLastError();
 }
 
-template hipError_t launch_tile_fwd<float, 5>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*,
-                                              int64_t, const void*, hipStream_t);
+template hipError_t launch_build_ops<float>(const DevPlan&, int, const void*, int64_t, const void*, int64_t, void*,
+                                            hipStream_t);
+template hipError_t launch_build_ops<double>(const DevPlan&, int, const void*, int64_t, const void*, int64_t, void*,
+                                             hipStream_t);
+template hipError_t launch_tile_fwd<float, 5>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*, int,
+                                              hipStream_t);
 template hipError_t launch_tile_fwd<double, 4>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*,
-                                               int64_t, const void*, hipStream_t);
+                                               int, hipStream_t);
 template hipError_t launch_tile_rev<float, 5>(const DevPlan&, int, int, void*, void*, int64_t, int, int64_t,
-                                              const void*, int64_t, const void*, int, double*, int, hipStream_t);
+                                              const void*, int, int, double*, int, hipStream_t);
 template hipError_t launch_tile_rev<double, 4>(const DevPlan&, int, int, void*, void*, int64_t, int, int64_t,
-                                               const void*, int64_t, const void*, int, double*, int, hipStream_t);
+                                               const void*, int, int, double*, int, hipStream_t);
 
 }  // namespace tcng

@@ -20,13 +20,17 @@ struct DevPauliPlan {
 };
 
 // ---- tiled passes
+// opm: [batch][n_ops][16] matrix entries of the plan's ops, written by launch_build_ops
+template <typename R>
+hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, int64_t pstride, const void* cmats,
+                            int64_t batch, void* opm, hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_tile_fwd(const DevPlan& dp, int pass_idx, int m, void* state, int64_t stride, int n, int64_t batch,
-                           const void* params, int64_t pstride, const void* cmats, hipStream_t st);
+                           const void* opm, int n_ops, hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_tile_rev(const DevPlan& dp, int pass_idx, int m, void* state, void* costate, int64_t stride, int n,
-                           int64_t batch, const void* params, int64_t pstride, const void* cmats, int wgs,
-                           double* part, int total_slots, hipStream_t st);
+                           int64_t batch, const void* opm, int n_ops, int wgs, double* part, int total_slots,
+                           hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_pauli_tile(const DevPauliPlan& dp, int pass_idx, int n_passes, int m, const void* state,
                              void* costate, bool accumulate, int64_t stride, int n, int64_t batch, int wgs,
@@ -64,10 +68,12 @@ hipError_t launch_init(void* state, int64_t stride, int n, int64_t batch, const 
 
 hipError_t launch_zero(double* p, size_t count, hipStream_t st);
 
-// grad[b][p] = sum over slots of p of sum_wg part; energy[b] = sum of erows; lie from U2 cotangents
+// grad[b][p] = sum over slots of p of sum_wg part; energy[b] = sum of erows; lie from U2 cotangents.
+// scratch: batch * (total_slots + erows) doubles.
 hipError_t launch_finish(const double* part, int total_slots, int wgs, const int32_t* slot_ptr,
                          const int32_t* slot_idx, int n_params, const double* epart, int erows, int ewgs,
                          int64_t batch, double* energy, double* grad, double* gate_grad, const int32_t* gate_slot,
-                         const double* u2_mats_c128, const int32_t* gate_mat, int n_gates, hipStream_t st);
+                         const double* u2_mats_c128, const int32_t* gate_mat, int n_gates, double* scratch,
+                         hipStream_t st);
 
 }  // namespace tcng

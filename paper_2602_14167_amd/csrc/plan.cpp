@@ -135,7 +135,7 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
         for (int i = 0; i < 16; ++i) P.local_qubit[i] = -1;
         int li = 0;
         for (int q = 0; q < n; ++q)
-            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = int8_t(q); ++li; }
+            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = q; ++li; }
         if (li != m) return "internal: tile size mismatch";
         for (int q = 0; q < lo; ++q)
             if (qubit_to_local[q] != q) return "internal: low qubits not contiguous";
@@ -179,16 +179,16 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
             // (keeps consecutive lanes on consecutive LDS addresses)
             for (int b = m - 1; b >= 0 && popc(R) < cfg.rb; --b) R |= 1u << b;
             Phase F{};
-            for (int i = 0; i < 8; ++i) F.R[i] = -1;
+            for (int i = 0; i < 6; ++i) F.R[i] = -1;
             int ri = 0, reg_of_local[MAX_TILE_BITS];
             for (int b = 0; b < MAX_TILE_BITS; ++b) reg_of_local[b] = -1;
             for (int b = 0; b < m; ++b)
-                if ((R >> b) & 1) { F.R[ri] = int8_t(b); reg_of_local[b] = ri; ++ri; }
+                if ((R >> b) & 1) { F.R[ri] = b; reg_of_local[b] = ri; ++ri; }
             F.op_begin = int(out.ops.size());
             for (int gi : ph) {
                 const tcng_gate& g = gates[gi];
                 Op o{};
-                o.kind = int8_t(g.kind);
+                o.kind = g.kind;
                 o.p0 = g.p0;
                 o.p1 = g.p1;
                 o.mat = g.mat;
@@ -196,19 +196,23 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
                 o.slot = gate_slot_first[gi];
                 const int l0 = qubit_to_local[g.q0];
                 const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
-                o.lb0 = int8_t(l0);
-                o.lb1 = int8_t(l1);
-                o.r0 = int8_t(reg_of_local[l0]);
-                o.r1 = int8_t(l1 >= 0 ? reg_of_local[l1] : -1);
+                o.lb0 = l0;
+                o.lb1 = l1;
+                o.r0 = reg_of_local[l0];
+                o.r1 = l1 >= 0 ? reg_of_local[l1] : -1;
                 switch (g.kind) {
                     case K_RZ: case K_Z: case K_S: o.type = OP_DIAG1; break;
                     case K_CZ: case K_RZZ: o.type = OP_DIAG2; break;
                     case K_CNOT: o.type = OP_CX; break;
-                    case K_FSIM: case K_U2: o.type = OP_DENSE2; break;
-                    default: o.type = OP_DENSE1; break;
+                    case K_FSIM: o.type = OP_FSIM; break;
+                    case K_U2: o.type = OP_DENSE2; break;
+                    case K_RY: case K_H: case K_X: o.type = OP_REAL1; break;
+                    case K_RX: o.type = OP_RX; break;
+                    default: o.type = OP_DENSE1; break;   // Y, U1
                 }
-                if ((o.type == OP_DENSE1 && o.r0 < 0) || (o.type == OP_CX && o.r1 < 0) ||
-                    (o.type == OP_DENSE2 && (o.r0 < 0 || o.r1 < 0)))
+                const bool one = o.type == OP_DENSE1 || o.type == OP_REAL1 || o.type == OP_RX;
+                const bool two = o.type == OP_DENSE2 || o.type == OP_FSIM;
+                if ((one && o.r0 < 0) || (o.type == OP_CX && o.r1 < 0) || (two && (o.r0 < 0 || o.r1 < 0)))
                     return "internal: register operand missing";
                 out.ops.push_back(o);
             }
@@ -275,7 +279,7 @@ std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const Til
         for (int i = 0; i < 16; ++i) P.local_qubit[i] = -1;
         int li = 0;
         for (int q = 0; q < n; ++q)
-            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = int8_t(q); ++li; }
+            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = q; ++li; }
         auto to_local = [&](uint64_t mask) {
             int32_t r = 0;
             for (int q = 0; q < n; ++q)
