@@ -35,6 +35,8 @@ FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "re
 
 def workload(name):
     import workloads as W
+    if name.startswith("gates"):
+        return None
     if name == "hea28":
         w = W.cfg2()
         w["batch"] = 1
@@ -47,6 +49,8 @@ def workload(name):
         return w
     if name == "xxz16_b2048":
         return W.cfg3()
+    if name == "haar_uneven":
+        return W.cfg4()
     if name == "fsim32":
         w = W.cfg5()
         w["batch"] = 1
@@ -66,6 +70,121 @@ def algorithmic_bytes(family, n, s, batch, n_pauli_passes):
         # first pass: read psi, write lambda; later passes also read lambda
         return None if n_pauli_passes == 0 else (2 * amp + 3 * amp * (n_pauli_passes - 1)) / n_pauli_passes
     return None
+
+
+def run_uneven(args, w, P, torch):
+    """The uneven batch (1024 Haar brick-wall circuits of 12..22 qubits): one
+    step = value and Lie-algebra gate gradients of every circuit."""
+    cs = w["circuits"]
+    circs = [P.Circuit(c["n"], c["gates"], 0, c["mats"]) for c in cs]
+    hams = [P.PauliSum(c["n"], c["codes"], c["coeffs"]) for c in cs]
+    cdt = torch.complex64
+    psis = [torch.empty((1, 2 ** c["n"]), dtype=cdt, device="cuda") for c in cs]
+    count = len(cs)
+    nbytes = ctypes.c_size_t()
+    ch = (ctypes.c_void_p * count)(*[c.handle.value for c in circs])
+    hh = (ctypes.c_void_p * count)(*[h.handle.value for h in hams])
+    P.check(P.lib().tcng_workspace_size_multi(ch, hh, count, 0, ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+
+    def step():
+        for p in psis:
+            P.state_init(p)
+        return P.expect_grad_multi(circs, hams, [None] * count, dtype=cdt, psis=psis, want_gate_grad=True, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prof = not args.no_profile
+    if prof:
+        P.check(P.lib().tcng_profile_begin(200000))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, _, _ = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fam = {}
+    if prof:
+        for i, name in enumerate(FAMILIES):
+            cnt, tot = ctypes.c_int32(), ctypes.c_double()
+            P.check(P.lib().tcng_profile_query(i, ctypes.byref(cnt), ctypes.byref(tot)))
+            if cnt.value:
+                fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
+        P.check(P.lib().tcng_profile_end())
+    G = sum(len(c["gates"]) for c in cs)
+    amp = sum(3.0 * len(c["gates"]) * 2 ** c["n"] for c in cs)
+    # algorithmic bytes of the reverse sweep (dominant) over one step: 4 * 2^n * 8 per pass per circuit
+    rev_bytes = sum(c2.num_passes() * 4 * 8 * 2 ** c["n"] for c, c2 in zip(cs, circs))
+    roofline = None
+    if "rev_tile" in fam:
+        achieved = rev_bytes * args.steps / (fam["rev_tile"]["total_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "rev_tile",
+                    "bytes_per_step": rev_bytes, "launches_per_step": fam["rev_tile"]["launches"] / args.steps}
+    return {
+        "metric": "amplitude-updates/s", "value": amp / dt, "unit": "amplitude-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (f32 state, f64 reductions)", "data": "synthetic",
+        "config": {"workload": w["name"], "circuits": count, "gates": G, "mode": "tiled, uneven batch",
+                   "parallelism": "single GPU"},
+        "evals_per_s": count / dt, "roofline": roofline,
+        "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}
+                    for k, v in fam.items()},
+    }
+
+
+def run_gate_sweep(args, P, torch, n):
+    """Per-gate HBM bandwidth of the streaming gate kernels (the unfused path)
+    for low and high target qubits: RY (dense real 2x2), RZ (diagonal), CNOT
+    (q, q+1) and a Haar 4x4 on (q, q') with q' low or high; complex64."""
+    import workloads as W
+    rng = np.random.default_rng(7)
+    psi = torch.empty((1, 2 ** n), dtype=torch.complex64, device="cuda")
+    P.state_init(psi)
+    cases = []
+    targets = [0, 1, 2, 3, 4, 6, 8, 12, 16, 20, 24, n - 2]
+    for q in targets:
+        cases.append(("RY", [W.gate(W.RY, q, p0=0)], None))
+        cases.append(("RZ", [W.gate(W.RZ, q, p0=0)], None))
+        cases.append(("CNOT", [W.gate(W.CNOT, q, q + 1)], None))
+        mats = W.haar_u4(rng)[None]
+        cases.append(("U2low", [W.gate(W.U2, q + 1, 0 if q > 0 else 1, mat=0)], mats))
+        cases.append(("U2high", [W.gate(W.U2, q, n - 1 if q != n - 1 else n - 2, mat=0)], mats))
+    theta = torch.tensor([[0.37]], dtype=torch.float32, device="cuda")
+    res = []
+    for name, g, mats in cases:
+        circ = P.Circuit(n, g, 1 if name in ("RY", "RZ") else 0, mats)
+        prm = theta if circ.n_params else None
+        for _ in range(2):
+            P.run_circuit(circ, prm, psi, mode="plain")
+        torch.cuda.synchronize()
+        reps = 10
+        P.check(P.lib().tcng_profile_begin(64))
+        for _ in range(reps):
+            P.run_circuit(circ, prm, psi, mode="plain")
+        torch.cuda.synchronize()
+        fam = 3 if len(g) and g[0][2] < 0 else 4
+        cnt, tot = ctypes.c_int32(), ctypes.c_double()
+        P.check(P.lib().tcng_profile_query(fam, ctypes.byref(cnt), ctypes.byref(tot)))
+        P.check(P.lib().tcng_profile_end())
+        ms = tot.value / max(cnt.value, 1)
+        gbs = 2 * 8 * 2 ** n / (ms * 1e-3) / 1e9
+        res.append({"gate": name, "q": [int(g[0][1])] + ([int(g[0][2])] if g[0][2] >= 0 else []),
+                    "ms": round(ms, 4), "GB_s": round(gbs, 1)})
+    gb = sorted(r["GB_s"] for r in res)
+    med = gb[len(gb) // 2]
+    ms_med = 2 * 8 * 2 ** n / (med * 1e9) * 1e3
+    return {
+        "metric": "amplitude-updates/s", "value": 2 ** n / (ms_med * 1e-3), "unit": "amplitude-updates/s",
+        "n_gpus": 1, "steps": 10, "warmup": 2, "ms_per_step": ms_med, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"single_gate_sweep_n{n}", "n_qubits": n, "cases": len(res),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": med, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(med / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "gate1/gate2 (median case)",
+                     "min_GB_s": gb[0], "max_GB_s": gb[-1]},
+        "gate_sweep": res,
+    }
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -98,6 +217,8 @@ def main():
     ap.add_argument("--mode", default="tiled", choices=["tiled", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiling", default=None, help="m,rb,rb_rev (skips the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
@@ -110,6 +231,14 @@ def main():
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
     w = workload(args.workload)
+    if args.workload in ("gates28", "gates30"):
+        out = run_gate_sweep(args, P, torch, int(args.workload[-2:]))
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "haar_uneven":
+        out = run_uneven(args, w, P, torch)
+        print(json.dumps(out), flush=True)
+        return
     n, G, B = w["n"], len(w["gates"]), int(w.get("batch", 1))
     cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
     rdt = torch.float32 if args.dtype == "c64" else torch.float64
@@ -120,6 +249,15 @@ def main():
     psi = torch.empty((B, 2 ** n), dtype=cdt, device="cuda")
     lam = torch.empty_like(psi)
     mode = P.MODES[args.mode]
+    tuned = None
+    if args.mode == "tiled" and args.tiling:
+        circ.configure(cdt, *[int(v) for v in args.tiling.split(",")])
+    elif args.mode == "tiled" and not args.no_autotune:
+        P.state_init(psi)
+        cfg, tms = P.autotune(circ, params, H, psi, lam, repeats=3,
+                              cache_path=os.path.join(os.environ.get("TMPDIR", "/tmp"), "tcng_autotune.txt"))
+        tuned = {"tiling": list(cfg), "median_ms": round(tms, 3)}
+    # workspace for the chosen tiling
     nbytes = ctypes.c_size_t()
     P.check(P.lib().tcng_workspace_size(circ.handle, H.handle, 0 if args.dtype == "c64" else 1, B, mode,
                                         ctypes.byref(nbytes)))
@@ -183,6 +321,8 @@ def main():
         "config": {"workload": w["name"], "n_qubits": n, "gates": G, "params": w["n_params"], "batch": B,
                    "pauli_terms": len(w["coeffs"]), "mode": args.mode, "parallelism": "single GPU"},
         "evals_per_s": B / dt,
+        "tiling": list(circ.config(cdt)) if args.mode == "tiled" else None,
+        "autotune": tuned,
         "energy0": float(E[0].item()),
         "roofline": roofline,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}

@@ -116,6 +116,53 @@ tcng_status tcng_circuit_destroy(tcng_circuit* c);
 /* Number of tiled passes the planner produced for `dtype` (forward sweep). */
 tcng_status tcng_circuit_num_passes(const tcng_circuit* c, int32_t dtype, int32_t* passes);
 
+/* Uneven batch (the VMAP paradigm over circuits that differ in qubit count,
+ * depth and Hamiltonian, Sec. "Data Parallelism"): value and adjoint gradient
+ * of `count` circuits, each with its own Pauli sum, angles and single state,
+ * in shared launches -- the k-th pass of every circuit that has one runs in
+ * one launch, so the number of launches follows the deepest circuit, not the
+ * number of circuits.  Every circuit must have the tiled path for the dtype
+ * (n >= 11 for complex64, >= 10 for complex128) with the same register block
+ * sizes, and its Pauli sum a tiled plan; else TCNG_E_UNSUPPORTED.
+ *   circs, hams : host arrays [count] of handles
+ *   params      : host array [count] of DEVICE pointers to the angles (NULL when
+ *                 the circuit has none), float32 / float64 as the dtype
+ *   psi, lam    : host arrays [count] of states (batch 1, dtype as the first)
+ *   energy      : DEVICE float64 [count]
+ *   grad        : host array [count] of DEVICE float64 [n_params] (entries may be NULL
+ *                 only for circuits without angles); NULL if no circuit has angles
+ *   gate_grad   : NULL, or host array [count] of DEVICE float64 [n_gates][15]
+ * The workspace holds every circuit's scratch and the launch tables. */
+tcng_status tcng_workspace_size_multi(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams,
+                                      int32_t count, int32_t dtype, size_t* bytes);
+tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                                   const void* const* params, const tcng_state* psi, const tcng_state* lam,
+                                   double* energy, double* const* grad, double* const* gate_grad, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* Tiling of the tiled path for `dtype`: tile bits m_max (at most 13 for
+ * TCNG_C64, 12 for TCNG_C128), register bits per thread in the forward sweep
+ * rb and per thread and state in the reverse sweep rb_rev (4 or 5 for C64,
+ * 3 or 4 for C128), with 6 <= m_max - rb, m_max - rb_rev <= 9.  Rebuilds and
+ * uploads the plan (synchronises the device).  TCNG_E_UNSUPPORTED if the
+ * shape is not available or the circuit is too small for the tiled path. */
+tcng_status tcng_circuit_configure(tcng_circuit* c, int32_t dtype, int32_t m_max, int32_t rb, int32_t rb_rev);
+tcng_status tcng_circuit_get_config(const tcng_circuit* c, int32_t dtype, int32_t* m_max, int32_t* rb,
+                                    int32_t* rb_rev);
+
+/* Autotuner: times tcng_expect_grad (TCNG_MODE_TILED) for every available
+ * tiling of c for this dtype and batch, on the given initial states psi
+ * (restored afterwards up to rounding) and scratch lam, keeps the fastest
+ * (median of `repeats` runs, ties to the earlier candidate) and configures c
+ * with it.  Allocates and frees its own workspace and synchronises; not for
+ * the hot path.  params as for tcng_expect_grad.  best_ms (nullable) receives
+ * the winner's median time.  If cache_path is not NULL, the choice is looked
+ * up in / appended to that text file, keyed by the circuit's structure, dtype,
+ * batch and device architecture; a cached choice is applied without timing. */
+tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* params, const tcng_state* psi,
+                          const tcng_state* lam, int32_t repeats, const char* cache_path, double* best_ms,
+                          void* stream);
+
 /* Build a Pauli-sum handle: codes host uint8 [n_terms][n_qubits] (0=I,1=X,2=Y,3=Z),
  * coeffs host float64 [n_terms] (Sec. "Data Parallelism": H = sum_i c_i P_i). */
 tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const double* coeffs, int32_t n_terms,

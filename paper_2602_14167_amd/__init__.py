@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TcngError, TcngGate,  # noqa: F401
                    TcngState, check, lib)
 
-__all__ = ["plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
+__all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
            "TcngEnergy", "new_state", "TcngError", "MODES"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN}
@@ -116,11 +116,36 @@ class Circuit:
                                             ctypes.byref(out)))
         return out.value
 
+    def configure(self, dtype, m_max, rb, rb_rev):
+        check(lib().tcng_circuit_configure(self.handle, _dt(dtype), int(m_max), int(rb), int(rb_rev)))
+
+    def config(self, dtype=torch.complex64):
+        v = [ctypes.c_int32() for _ in range(3)]
+        check(lib().tcng_circuit_get_config(self.handle, _dt(dtype), *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib._lib is not None:
             _lib._lib.tcng_circuit_destroy(h)
             self.handle = None
+
+
+def _dt(dtype):
+    return TCNG_C64 if dtype in (torch.complex64, "c64", TCNG_C64) else TCNG_C128
+
+
+def autotune(circ, params, H, psi, lam=None, repeats=3, cache_path=None):
+    """Pick the fastest tiling for this circuit, dtype and batch (see tcng_autotune)."""
+    s = _state(psi, circ.n)
+    if lam is None:
+        lam = torch.empty_like(psi)
+    sl = _state(lam, circ.n)
+    p, pp = _params(circ, params, psi, s.batch)
+    best = ctypes.c_double()
+    check(lib().tcng_autotune(circ.handle, H.handle, pp, ctypes.byref(s), ctypes.byref(sl), int(repeats),
+                              cache_path.encode() if cache_path else None, ctypes.byref(best), _stream()))
+    return circ.config(psi.dtype), best.value
 
 
 class PauliSum:
@@ -215,6 +240,51 @@ def expect_grad(circ: Circuit, params, H: PauliSum, psi=None, lam=None, batch=No
     if want_gate_grad:
         return energy, grad, gg
     return energy, grad
+
+
+def expect_grad_multi(circs, hams, params_list, dtype=torch.complex64, psis=None, want_gate_grad=False, ws=None):
+    """Uneven batch: E and gradients of many different circuits in shared launches.
+
+    params_list[i]: device tensor of circuit i's angles (or None); psis: optional
+    list of initial states [1, 2^n_i] (default |0...0>).  Returns (energy [count]
+    float64, list of gradients, list of gate gradients or None)."""
+    count = len(circs)
+    dev = torch.device("cuda")
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    if psis is None:
+        psis = [new_state(c.n, 1, dtype) for c in circs]
+    lams = [torch.empty_like(p) for p in psis]
+    st_psi = (TcngState * count)(*[_state(p, c.n) for p, c in zip(psis, circs)])
+    st_lam = (TcngState * count)(*[_state(l, c.n) for l, c in zip(lams, circs)])
+    ch = (ctypes.c_void_p * count)(*[c.handle.value for c in circs])
+    hh = (ctypes.c_void_p * count)(*[h.handle.value for h in hams])
+    keep = []
+    pp = (ctypes.c_void_p * count)()
+    grads, ggs = [], []
+    gp = (ctypes.c_void_p * count)()
+    ggp = (ctypes.c_void_p * count)()
+    for i, c in enumerate(circs):
+        if c.n_params:
+            t = params_list[i].to(device=dev, dtype=rdt).contiguous()
+            keep.append(t)
+            pp[i] = t.data_ptr()
+        g = torch.empty(max(c.n_params, 1), dtype=torch.float64, device=dev)
+        grads.append(g[: c.n_params])
+        gp[i] = g.data_ptr()
+        if want_gate_grad:
+            gg = torch.empty((c.n_gates, 15), dtype=torch.float64, device=dev)
+            ggs.append(gg)
+            ggp[i] = gg.data_ptr()
+    dcode = _dt(dtype)
+    if ws is None:
+        nbytes = ctypes.c_size_t()
+        check(lib().tcng_workspace_size_multi(ch, hh, count, dcode, ctypes.byref(nbytes)))
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+    energy = torch.empty(count, dtype=torch.float64, device=dev)
+    check(lib().tcng_expect_grad_multi(ch, hh, count, pp, st_psi, st_lam, ctypes.c_void_p(energy.data_ptr()), gp,
+                                       ggp if want_gate_grad else None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream()))
+    return energy, grads, (ggs if want_gate_grad else None)
 
 
 class TcngEnergy(torch.autograd.Function):

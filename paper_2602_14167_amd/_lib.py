@@ -21,7 +21,8 @@ EXPORTS = [
     "tcng_last_error", "tcng_version", "tcng_state_init", "tcng_apply_gate", "tcng_circuit_create",
     "tcng_circuit_destroy", "tcng_circuit_num_passes", "tcng_pauli_sum_create", "tcng_pauli_sum_destroy",
     "tcng_workspace_size", "tcng_run_circuit", "tcng_expect_pauli", "tcng_expect_grad", "tcng_plan_inspect",
-    "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end",
+    "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end", "tcng_circuit_configure",
+    "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
 ]
 
 
@@ -68,6 +69,11 @@ def lib():
     L.tcng_run_circuit.argtypes = [P, P, PS, i32, P, sz, P]
     L.tcng_expect_pauli.argtypes = [PS, P, P, i32, P, sz, P]
     L.tcng_expect_grad.argtypes = [P, P, P, PS, PS, P, P, P, i32, P, sz, P]
+    L.tcng_workspace_size_multi.argtypes = [P, P, i32, i32, ctypes.POINTER(sz)]
+    L.tcng_expect_grad_multi.argtypes = [P, P, i32, P, PS, PS, P, P, P, P, sz, P]
+    L.tcng_circuit_configure.argtypes = [P, i32, i32, i32, i32]
+    L.tcng_circuit_get_config.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.tcng_autotune.argtypes = [P, P, P, PS, PS, i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), P]
     L.tcng_profile_begin.argtypes = [i32]
     L.tcng_profile_query.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     L.tcng_profile_end.argtypes = []

@@ -3,7 +3,11 @@
 // computation runs in the HIP kernels; this file only orders launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -69,13 +73,25 @@ struct ProfScope {
     }
 };
 
+// default tiling: 64 KiB tiles; forward blocks of 32 (c64) / 16 (c128)
+// amplitudes per thread, reverse blocks of 16 / 8 per state (psi and lambda)
 TileConfig tile_config(int dtype) {
-    return dtype == TCNG_C64 ? TileConfig{13, 5, 4} : TileConfig{12, 4, 4};
+    return dtype == TCNG_C64 ? TileConfig{13, 5, 4, 4} : TileConfig{12, 4, 4, 3};
 }
 // the tiled kernels need at least one full wave per tile
 bool tiled_ok(int n, int dtype) {
     const TileConfig c = tile_config(dtype);
-    return n >= c.rb + 6;
+    return n >= std::max(c.rb, c.rb_rev) + 6;
+}
+bool config_ok(const TileConfig& c, int dtype) {
+    const int mmax = dtype == TCNG_C64 ? 13 : 12;
+    const int rbs[2] = {c.rb, c.rb_rev};
+    for (int rb : rbs) {
+        if (dtype == TCNG_C64 && rb != 4 && rb != 5) return false;
+        if (dtype == TCNG_C128 && rb != 3 && rb != 4) return false;
+        if (c.m_max - rb > 9 || c.m_max - rb < 6) return false;   // 64..512 threads
+    }
+    return c.m_max <= mmax && c.lo >= 1 && c.lo <= c.m_max;
 }
 
 template <typename T>
@@ -100,8 +116,24 @@ struct DevCircuitPlan {
     Pass* passes = nullptr;
     Phase* phases = nullptr;
     Op* ops = nullptr;
+    Pass* rpasses = nullptr;
+    Phase* rphases = nullptr;
+    Op* rops = nullptr;
     SlotTables slots;
 };
+
+void free_plan(DevCircuitPlan& P) {
+    (void)hipFree(P.passes);
+    (void)hipFree(P.phases);
+    (void)hipFree(P.ops);
+    (void)hipFree(P.rpasses);
+    (void)hipFree(P.rphases);
+    (void)hipFree(P.rops);
+    (void)hipFree(P.slots.ptr);
+    (void)hipFree(P.slots.idx);
+    (void)hipFree(P.slots.gate_slot);
+    P = DevCircuitPlan();
+}
 
 }  // namespace
 
@@ -146,6 +178,27 @@ tcng_status build_slot_tables(const std::vector<tcng_gate>& gates, int n_params,
     return TCNG_OK;
 }
 
+tcng_status make_plan(tcng_circuit* c, int dt, const TileConfig& cfg) {
+    DevCircuitPlan P;
+    std::string why = plan_circuit(c->n, c->gates, c->n_params, cfg, P.host);
+    if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "planner: " + why);
+    if (upload(P.host.passes, &P.passes) != hipSuccess || upload(P.host.phases, &P.phases) != hipSuccess ||
+        upload(P.host.ops, &P.ops) != hipSuccess || upload(P.host.rpasses, &P.rpasses) != hipSuccess ||
+        upload(P.host.rphases, &P.rphases) != hipSuccess || upload(P.host.rops, &P.rops) != hipSuccess) {
+        free_plan(P);
+        return fail(TCNG_E_ALLOC, "device allocation failed");
+    }
+    if (tcng_status e = build_slot_tables(c->gates, c->n_params, P.host.slot_ptr, P.host.slot_idx, P.host.gate_slot,
+                                          P.host.total_slots, P.slots)) {
+        free_plan(P);
+        return e;
+    }
+    P.valid = true;
+    free_plan(c->tiled[dt]);
+    c->tiled[dt] = P;
+    return TCNG_OK;
+}
+
 tcng_status check_state(const tcng_state* s, const char* what) {
     if (!s) return fail(TCNG_E_INVALID, std::string(what) + ": null state");
     if (!s->amps) return fail(TCNG_E_INVALID, std::string(what) + ": null amplitude pointer");
@@ -164,8 +217,8 @@ tcng_status check_state(const tcng_state* s, const char* what) {
 int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
 // workgroups per batch member of the reduction-carrying launches
-int rev_wgs_tiled(int n, int dtype, int64_t batch) {
-    const int m = std::min(n, tile_config(dtype).m_max);
+int rev_wgs_tiled(int n, int m_max, int64_t batch) {
+    const int m = std::min(n, m_max);
     const int64_t tiles = int64_t(1) << (n - m);
     const int64_t cap = std::max<int64_t>(1, ceil_div(8192, batch));
     return int(std::min(tiles, cap));
@@ -208,15 +261,15 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
     const bool tiled = use_tiled(mode, n, dtype);
     if (c) {
         if (tiled)
-            L.opm_bytes = size_t(batch) * c->tiled[dtype].host.ops.size() * 16 * (dtype == TCNG_C64 ? 8 : 16);
+            L.opm_bytes = size_t(batch) * c->gates.size() * 16 * (dtype == TCNG_C64 ? 8 : 16);
         L.total_slots = tiled ? c->tiled[dtype].host.total_slots : c->plain.total;
-        L.rev_wgs = tiled ? rev_wgs_tiled(n, dtype, batch) : rev_wgs_plain(n, batch);
+        L.rev_wgs = tiled ? rev_wgs_tiled(n, c->tiled[dtype].host.cfg.m_max, batch) : rev_wgs_plain(n, batch);
         L.part_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1)) * size_t(L.rev_wgs) * sizeof(double);
     }
     if (h) {
         if (tiled) {
             L.e_rows = int(h->tplan[dtype].passes.size());
-            L.e_wgs = rev_wgs_tiled(n, dtype, batch);
+            L.e_wgs = rev_wgs_tiled(n, h->tplan[dtype].cfg.m_max, batch);
         } else {
             L.e_rows = int(h->groups_full.size());
             L.e_wgs = pauli_wgs_plain(n, batch);
@@ -234,20 +287,67 @@ tcng_status build_ops(const tcng_circuit* c, const void* params, int64_t batch, 
     const DevCircuitPlan& P = c->tiled[dt];
     DevPlan dp{P.passes, P.phases, P.ops};
     PROF_TRY(F_FINISH, launch_build_ops<R>(dp, int(P.host.ops.size()), params, c->n_params, c->cm[dt], batch, opm, st));
+    // (the forward plan lists every gate exactly once: the table is indexed by gate)
     return TCNG_OK;
 }
 
+// the job descriptor of a single circuit (shared by `batch` parameter sets)
+Job make_job(const tcng_circuit* c, const tcng_pauli_sum* h, const tcng_state* s, void* lam, const void* opm,
+             double* part, double* epart, const WsLayout& L) {
+    Job J{};
+    const int dt = s->dtype;
+    if (c && c->tiled[dt].valid) {
+        const DevCircuitPlan& P = c->tiled[dt];
+        J.passes = P.passes;
+        J.phases = P.phases;
+        J.ops = P.ops;
+        J.rpasses = P.rpasses;
+        J.rphases = P.rphases;
+        J.rops = P.rops;
+        J.n_passes = int32_t(P.host.passes.size());
+        J.n_gates = int32_t(c->gates.size());
+        J.tiles = int64_t(1) << (s->n_qubits - std::min(s->n_qubits, P.host.cfg.m_max));
+    }
+    if (h && h->tiled_valid[dt]) {
+        J.ppasses = h->dplan[dt].passes;
+        J.pgroups = h->dplan[dt].groups;
+        J.pclasses = h->dplan[dt].classes;
+        J.pterms = h->dplan[dt].terms;
+        J.n_ppasses = int32_t(h->tplan[dt].passes.size());
+        if (!J.tiles) J.tiles = int64_t(1) << (s->n_qubits - std::min(s->n_qubits, h->tplan[dt].cfg.m_max));
+    }
+    J.state = s->amps;
+    J.costate = lam;
+    J.opm = opm;
+    J.part = part;
+    J.epart = epart;
+    J.stride = s->stride;
+    J.batch = s->batch;
+    J.n = s->n_qubits;
+    J.total_slots = L.total_slots;
+    J.wgs = L.rev_wgs;
+    J.e_rows = L.e_rows;
+    J.e_wgs = L.e_wgs;
+    return J;
+}
+
 template <typename R, int RB>
-tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_state* s, int mode, const void* opm,
+tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_state* s, int mode, const Job& J,
                         hipStream_t st) {
     const int dt = s->dtype;
     const int n = s->n_qubits;
     if (use_tiled(mode, n, dt)) {
         const DevCircuitPlan& P = c->tiled[dt];
-        DevPlan dp{P.passes, P.phases, P.ops};
-        for (size_t p = 0; p < P.host.passes.size(); ++p)
-            PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(dp, int(p), P.host.passes[p].m, s->amps, s->stride, n, s->batch,
-                                                          opm, int(P.host.ops.size()), st)));
+        const int rb = P.host.cfg.rb;
+        for (size_t p = 0; p < P.host.passes.size(); ++p) {
+            const int m = P.host.passes[p].m;
+            const JobList jl{nullptr, nullptr, 0, int32_t(p)};
+            const int64_t blocks = J.tiles * J.batch;
+            if (rb == RB)
+                PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
+            else
+                PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB - 1>(jl, J, blocks, 1 << (m - RB + 1), st)));
+        }
     } else {
         for (const tcng_gate& g : c->gates) {
             if (kind_arity(g.kind) == 1)
@@ -264,14 +364,18 @@ tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_st
 // H psi into lam (if lam) and energy partial sums into epart
 template <typename R, int RB>
 tcng_status run_pauli(const tcng_pauli_sum* h, const tcng_state* s, void* lam, const WsLayout& L, double* epart,
-                      int mode, hipStream_t st) {
+                      int mode, const Job& job, hipStream_t st) {
     const int dt = s->dtype;
     const int n = s->n_qubits;
     if (use_tiled(mode, n, dt)) {
         const PauliPlan& P = h->tplan[dt];
-        for (size_t p = 0; p < P.passes.size(); ++p)
-            PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<R, RB>(h->dplan[dt], int(p), L.e_rows, P.passes[p].m, s->amps, lam, p > 0,
-                                               s->stride, n, s->batch, L.e_wgs, epart, st)));
+        Job J = job;
+        J.costate = lam;
+        for (size_t p = 0; p < P.passes.size(); ++p) {
+            const JobList jl{nullptr, nullptr, 0, int32_t(p)};
+            PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<R, RB>(jl, J, int64_t(L.e_wgs) * s->batch,
+                                                              1 << (P.passes[p].m - RB), st)));
+        }
         if (P.passes.empty()) HIP_TRY(launch_zero(epart, L.epart_bytes / sizeof(double), st));
     } else {
         for (size_t g = 0; g < h->groups_full.size(); ++g) {
@@ -291,16 +395,22 @@ tcng_status run_pauli(const tcng_pauli_sum* h, const tcng_state* s, void* lam, c
 
 template <typename R, int RB>
 tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_state* psi, void* lam,
-                        const WsLayout& L, double* part, int mode, const void* opm, hipStream_t st) {
+                        const WsLayout& L, double* part, int mode, const Job& J, hipStream_t st) {
     const int dt = psi->dtype;
     const int n = psi->n_qubits;
     if (use_tiled(mode, n, dt)) {
         const DevCircuitPlan& P = c->tiled[dt];
-        DevPlan dp{P.passes, P.phases, P.ops};
-        for (int p = int(P.host.passes.size()) - 1; p >= 0; --p)
-            PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(dp, p, P.host.passes[p].m, psi->amps, lam, psi->stride, n, psi->batch,
-                                                          opm, int(P.host.ops.size()), L.rev_wgs, part, L.total_slots,
-                                                          st)));
+        const int rb = P.host.cfg.rb_rev;
+        const int np = int(P.host.rpasses.size());
+        for (int k = 0; k < np; ++k) {
+            const int m = P.host.rpasses[np - 1 - k].m;
+            const JobList jl{nullptr, nullptr, 0, int32_t(k)};
+            const int64_t blocks = int64_t(J.wgs) * J.batch;
+            if (rb == RB)
+                PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
+            else
+                PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB - 1>(jl, J, blocks, 1 << (m - RB + 1), st)));
+        }
     } else {
         for (int gi = int(c->gates.size()) - 1; gi >= 0; --gi) {
             const tcng_gate& g = c->gates[gi];
@@ -448,16 +558,7 @@ tcng_status tcng_circuit_create(int32_t n_qubits, const tcng_gate* gates, int32_
     // tiled plans
     for (int dt = 0; dt < 2; ++dt) {
         if (!tiled_ok(n_qubits, dt)) continue;
-        DevCircuitPlan& P = c->tiled[dt];
-        std::string why = plan_circuit(n_qubits, c->gates, n_params, tile_config(dt), P.host);
-        if (!why.empty()) return cleanup(fail(TCNG_E_UNSUPPORTED, "planner: " + why));
-        if (upload(P.host.passes, &P.passes) != hipSuccess || upload(P.host.phases, &P.phases) != hipSuccess ||
-            upload(P.host.ops, &P.ops) != hipSuccess)
-            return cleanup(fail(TCNG_E_ALLOC, "device allocation failed"));
-        if (tcng_status e = build_slot_tables(c->gates, n_params, P.host.slot_ptr, P.host.slot_idx, P.host.gate_slot,
-                                              P.host.total_slots, P.slots))
-            return cleanup(e);
-        P.valid = true;
+        if (tcng_status e = make_plan(c, dt, tile_config(dt))) return cleanup(e);
     }
     *out = c;
     return ok();
@@ -475,14 +576,7 @@ tcng_status tcng_circuit_destroy(tcng_circuit* c) {
     (void)hipFree(c->plain.ptr);
     (void)hipFree(c->plain.idx);
     (void)hipFree(c->plain.gate_slot);
-    for (auto& P : c->tiled) {
-        (void)hipFree(P.passes);
-        (void)hipFree(P.phases);
-        (void)hipFree(P.ops);
-        (void)hipFree(P.slots.ptr);
-        (void)hipFree(P.slots.idx);
-        (void)hipFree(P.slots.gate_slot);
-    }
+    for (auto& P : c->tiled) free_plan(P);
     delete c;
     return ok();
 }
@@ -585,13 +679,14 @@ tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tc
         return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
     void* opm = tiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
+    const Job J = make_job(c, nullptr, s, nullptr, opm, nullptr, nullptr, L);
     tcng_status e;
     if (s->dtype == TCNG_C64) {
         e = tiled ? build_ops<float>(c, params, s->batch, s->dtype, opm, st) : TCNG_OK;
-        if (!e) e = run_forward<float, 5>(c, params, s, mode, opm, st);
+        if (!e) e = run_forward<float, 5>(c, params, s, mode, J, st);
     } else {
         e = tiled ? build_ops<double>(c, params, s->batch, s->dtype, opm, st) : TCNG_OK;
-        if (!e) e = run_forward<double, 4>(c, params, s, mode, opm, st);
+        if (!e) e = run_forward<double, 4>(c, params, s, mode, J, st);
     }
     return e ? e : ok();
 }
@@ -607,8 +702,9 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
     if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
     double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
-    tcng_status e = s->dtype == TCNG_C64 ? run_pauli<float, 5>(h, s, nullptr, L, epart, mode, st)
-                                         : run_pauli<double, 4>(h, s, nullptr, L, epart, mode, st);
+    const Job J = make_job(nullptr, h, s, nullptr, nullptr, nullptr, epart, L);
+    tcng_status e = s->dtype == TCNG_C64 ? run_pauli<float, 5>(h, s, nullptr, L, epart, mode, J, st)
+                                         : run_pauli<double, 4>(h, s, nullptr, L, epart, mode, J, st);
     if (e) return e;
     double* red = reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off);
     PROF_TRY(F_FINISH, launch_finish(nullptr, 0, 1, nullptr, nullptr, 0, epart, L.e_rows, L.e_wgs, s->batch, out, nullptr,
@@ -647,17 +743,18 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
     const bool ctiled = use_tiled(mode, psi->n_qubits, dt);
     void* opm = ctiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
+    const Job J = make_job(c, h, psi, lam->amps, opm, part, epart, L);
     tcng_status e;
     if (dt == TCNG_C64) {
         e = ctiled ? build_ops<float>(c, params, psi->batch, dt, opm, st) : TCNG_OK;
-        if (!e) e = run_forward<float, 5>(c, params, psi, mode, opm, st);
-        if (!e) e = run_pauli<float, 5>(h, psi, lam->amps, L, epart, pmode, st);
-        if (!e) e = run_reverse<float, 5>(c, params, psi, lam->amps, L, part, mode, opm, st);
+        if (!e) e = run_forward<float, 5>(c, params, psi, mode, J, st);
+        if (!e) e = run_pauli<float, 5>(h, psi, lam->amps, L, epart, pmode, J, st);
+        if (!e) e = run_reverse<float, 5>(c, params, psi, lam->amps, L, part, mode, J, st);
     } else {
         e = ctiled ? build_ops<double>(c, params, psi->batch, dt, opm, st) : TCNG_OK;
-        if (!e) e = run_forward<double, 4>(c, params, psi, mode, opm, st);
-        if (!e) e = run_pauli<double, 4>(h, psi, lam->amps, L, epart, pmode, st);
-        if (!e) e = run_reverse<double, 4>(c, params, psi, lam->amps, L, part, mode, opm, st);
+        if (!e) e = run_forward<double, 4>(c, params, psi, mode, J, st);
+        if (!e) e = run_pauli<double, 4>(h, psi, lam->amps, L, epart, pmode, J, st);
+        if (!e) e = run_reverse<double, 4>(c, params, psi, lam->amps, L, part, mode, J, st);
     }
     if (e) return e;
     const bool tiled = use_tiled(mode, psi->n_qubits, dt);
@@ -665,6 +762,400 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     PROF_TRY(F_FINISH, launch_finish(part, std::max(L.total_slots, 1), L.rev_wgs, S.ptr, S.idx, c->n_params, epart, L.e_rows,
                           L.e_wgs, psi->batch, energy, grad, gate_grad, S.gate_slot, c->u2m[dt], c->gate_mat,
                           int(c->gates.size()), reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off), st));
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// uneven batch
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int MULTI_WGS = 16;   // workgroups per circuit in the reverse and Pauli sweeps
+
+struct MultiLayout {
+    // per circuit offsets (bytes) into the workspace and row offsets
+    std::vector<size_t> opm_off;
+    std::vector<int64_t> slot_row, erow_row;
+    size_t part_off = 0, epart_off = 0, ssum_off = 0, esum_off = 0;
+    size_t jobs_off[3] = {0, 0, 0}, prefix_off[3] = {0, 0, 0};
+    size_t build_off = 0, build_prefix_off = 0, fin_off = 0, fin_prefix_off = 0;
+    int64_t slot_rows = 0, e_rows = 0;
+    size_t total = 0;
+};
+
+tcng_status multi_check(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                        int32_t dtype) {
+    if (!circs || !hams || count < 1) return fail(TCNG_E_INVALID, "empty uneven batch");
+    if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
+    int rb = -1, rr = -1;
+    for (int i = 0; i < count; ++i) {
+        const tcng_circuit* c = circs[i];
+        const tcng_pauli_sum* h = hams[i];
+        if (!c || !h) return fail(TCNG_E_INVALID, "null handle in uneven batch");
+        if (c->n != h->n) return fail(TCNG_E_INVALID, "circuit and Pauli sum differ in qubit count");
+        if (!c->tiled[dtype].valid || !h->tiled_valid[dtype])
+            return fail(TCNG_E_UNSUPPORTED, "uneven batch member without a tiled plan");
+        const TileConfig& cfg = c->tiled[dtype].host.cfg;
+        if (rb < 0) { rb = cfg.rb; rr = cfg.rb_rev; }
+        if (cfg.rb != rb || cfg.rb_rev != rr) return fail(TCNG_E_UNSUPPORTED, "uneven batch with mixed register blocks");
+    }
+    return TCNG_OK;
+}
+
+MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                         int32_t dtype) {
+    MultiLayout L;
+    const size_t s = dtype == TCNG_C64 ? 8 : 16;
+    size_t off = 0;
+    L.opm_off.resize(count);
+    L.slot_row.resize(count);
+    L.erow_row.resize(count);
+    for (int i = 0; i < count; ++i) {
+        L.opm_off[i] = off;
+        off = align256(off + circs[i]->gates.size() * 16 * s);
+        L.slot_row[i] = L.slot_rows;
+        L.slot_rows += std::max(circs[i]->tiled[dtype].host.total_slots, 1);
+        L.erow_row[i] = L.e_rows;
+        L.e_rows += std::max<int64_t>(int64_t(hams[i]->tplan[dtype].passes.size()), 1);
+    }
+    L.part_off = off;
+    off = align256(off + size_t(L.slot_rows) * MULTI_WGS * sizeof(double));
+    L.epart_off = off;
+    off = align256(off + size_t(L.e_rows) * MULTI_WGS * sizeof(double));
+    L.ssum_off = off;
+    off = align256(off + size_t(L.slot_rows) * sizeof(double));
+    L.esum_off = off;
+    off = align256(off + size_t(L.e_rows) * sizeof(double));
+    for (int k = 0; k < 3; ++k) {
+        L.jobs_off[k] = off;
+        off = align256(off + size_t(count) * sizeof(Job));
+        L.prefix_off[k] = off;
+        off = align256(off + size_t(count + 1) * sizeof(int64_t));
+    }
+    L.build_off = off;
+    off = align256(off + size_t(count) * sizeof(BuildJob));
+    L.build_prefix_off = off;
+    off = align256(off + size_t(count + 1) * sizeof(int64_t));
+    L.fin_off = off;
+    off = align256(off + size_t(count) * sizeof(FinishJob));
+    L.fin_prefix_off = off;
+    off = align256(off + size_t(count + 1) * sizeof(int64_t));
+    L.total = off;
+    return L;
+}
+
+template <typename R, int RB, int RBR, int RBP = (sizeof(R) == 4 ? 5 : 4)>
+tcng_status run_multi(const std::vector<Job>& jobs, const tcng_circuit* const* circs,
+                      const tcng_pauli_sum* const* hams, int count, int dt, const MultiLayout& L, char* ws,
+                      hipStream_t st) {
+    // order per sweep: circuits with more passes first, so launch k covers a prefix of the order
+    std::vector<int> ord_c(count), ord_p(count);
+    for (int i = 0; i < count; ++i) ord_c[i] = ord_p[i] = i;
+    std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) { return jobs[x].n_passes > jobs[y].n_passes; });
+    std::stable_sort(ord_p.begin(), ord_p.end(), [&](int x, int y) { return jobs[x].n_ppasses > jobs[y].n_ppasses; });
+    const int* orders[3] = {ord_c.data(), ord_p.data(), ord_c.data()};
+    int nt_max[3] = {64, 64, 64};
+    int max_steps[3] = {0, 0, 0};
+    std::vector<int64_t> prefix_host[3];
+    for (int k = 0; k < 3; ++k) {
+        std::vector<Job> sorted(count);
+        prefix_host[k].assign(count + 1, 0);
+        for (int i = 0; i < count; ++i) {
+            const Job& J = jobs[orders[k][i]];
+            sorted[i] = J;
+            const int64_t per = (k == 0) ? J.tiles : (k == 1 ? J.e_wgs : J.wgs);
+            prefix_host[k][i + 1] = prefix_host[k][i] + per * J.batch;
+            const int m = (k == 1) ? hams[orders[k][i]]->tplan[dt].passes[0].m
+                                   : circs[orders[k][i]]->tiled[dt].host.passes[0].m;
+            const int rbk = (k == 2) ? RBR : (k == 1 ? RBP : RB);
+            nt_max[k] = std::max(nt_max[k], 1 << (m - rbk));
+            max_steps[k] = std::max(max_steps[k], k == 1 ? J.n_ppasses : J.n_passes);
+        }
+        HIP_TRY(hipMemcpyAsync(ws + L.jobs_off[k], sorted.data(), sizeof(Job) * count, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(ws + L.prefix_off[k], prefix_host[k].data(), sizeof(int64_t) * (count + 1),
+                               hipMemcpyHostToDevice, st));
+    }
+    // number of jobs of each sweep taking part in step k
+    auto active = [&](int sweep, int k) {
+        int c = 0;
+        for (int i = 0; i < count; ++i) {
+            const Job& J = jobs[orders[sweep][i]];
+            if ((sweep == 1 ? J.n_ppasses : J.n_passes) > k) ++c;
+        }
+        return c;
+    };
+    for (int k = 0; k < max_steps[0]; ++k) {
+        const int na = active(0, k);
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[0]),
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[0]), na, k};
+        PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, jobs[0], prefix_host[0][na], nt_max[0], st)));
+    }
+    for (int k = 0; k < max_steps[1]; ++k) {
+        const int na = active(1, k);
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[1]),
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[1]), na, k};
+        PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<R, RBP>(jl, jobs[0], prefix_host[1][na], nt_max[1], st)));
+    }
+    for (int k = 0; k < max_steps[2]; ++k) {
+        const int na = active(2, k);
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[2]),
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[2]), na, k};
+        PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RBR>(jl, jobs[0], prefix_host[2][na], nt_max[2], st)));
+    }
+    (void)circs;
+    return TCNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tcng_status tcng_workspace_size_multi(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams,
+                                      int32_t count, int32_t dtype, size_t* bytes) {
+    if (!bytes) return fail(TCNG_E_INVALID, "null output");
+    if (tcng_status e = multi_check(circs, hams, count, dtype)) return e;
+    *bytes = multi_layout(circs, hams, count, dtype).total;
+    return ok();
+}
+
+tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                                   const void* const* params, const tcng_state* psi, const tcng_state* lam,
+                                   double* energy, double* const* grad, double* const* gate_grad, void* ws,
+                                   size_t ws_bytes, void* stream) {
+    if (!psi || !lam || !energy) return fail(TCNG_E_INVALID, "null argument");
+    const int dt = psi[0].dtype;
+    if (tcng_status e = multi_check(circs, hams, count, dt)) return e;
+    for (int i = 0; i < count; ++i) {
+        if (tcng_status e = check_state(&psi[i], "tcng_expect_grad_multi(psi)")) return e;
+        if (tcng_status e = check_state(&lam[i], "tcng_expect_grad_multi(lam)")) return e;
+        if (psi[i].dtype != dt || lam[i].dtype != dt || psi[i].batch != 1 || lam[i].batch != 1 ||
+            psi[i].n_qubits != circs[i]->n || lam[i].n_qubits != circs[i]->n || psi[i].amps == lam[i].amps)
+            return fail(TCNG_E_INVALID, "uneven batch: states must be single, distinct and match their circuits");
+        if (circs[i]->n_params > 0 && (!params || !params[i] || !grad || !grad[i]))
+            return fail(TCNG_E_INVALID, "uneven batch: missing angles or gradient output");
+    }
+    const MultiLayout L = multi_layout(circs, hams, count, dt);
+    if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+    char* w = static_cast<char*>(ws);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<Job> jobs(count);
+    std::vector<BuildJob> builds(count);
+    std::vector<FinishJob> fins(count);
+    std::vector<int64_t> bprefix(count + 1, 0), fprefix(count + 1, 0);
+    double* part = reinterpret_cast<double*>(w + L.part_off);
+    double* epart = reinterpret_cast<double*>(w + L.epart_off);
+    double* ssum = reinterpret_cast<double*>(w + L.ssum_off);
+    double* esum = reinterpret_cast<double*>(w + L.esum_off);
+    for (int i = 0; i < count; ++i) {
+        const tcng_circuit* c = circs[i];
+        const tcng_pauli_sum* h = hams[i];
+        WsLayout Li;
+        Li.total_slots = std::max(c->tiled[dt].host.total_slots, 1);
+        Li.rev_wgs = MULTI_WGS;
+        Li.e_rows = std::max<int>(int(h->tplan[dt].passes.size()), 1);
+        Li.e_wgs = MULTI_WGS;
+        jobs[i] = make_job(c, h, &psi[i], lam[i].amps, w + L.opm_off[i], part + L.slot_row[i] * MULTI_WGS,
+                           epart + L.erow_row[i] * MULTI_WGS, Li);
+        builds[i] = BuildJob{c->tiled[dt].ops, params ? params[i] : nullptr, c->cm[dt], w + L.opm_off[i],
+                             int32_t(c->gates.size()), 0};
+        bprefix[i + 1] = bprefix[i] + int64_t(c->gates.size());
+        const SlotTables& S = c->tiled[dt].slots;
+        FinishJob F{};
+        F.slots = ssum + L.slot_row[i];
+        F.erow = esum + L.erow_row[i];
+        F.slot_ptr = S.ptr;
+        F.slot_idx = S.idx;
+        F.gate_slot = S.gate_slot;
+        F.u2m = c->u2m[dt];
+        F.gate_mat = c->gate_mat;
+        F.energy = energy + i;
+        F.grad = (grad && c->n_params) ? grad[i] : nullptr;
+        F.gate_grad = gate_grad ? gate_grad[i] : nullptr;
+        F.n_params = c->n_params;
+        F.n_gates = int32_t(c->gates.size());
+        F.erows = Li.e_rows;
+        fins[i] = F;
+        fprefix[i + 1] = fprefix[i] + 1 + c->n_params + (F.gate_grad ? int64_t(c->gates.size()) : 0);
+    }
+    HIP_TRY(hipMemcpyAsync(w + L.build_off, builds.data(), sizeof(BuildJob) * count, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + L.build_prefix_off, bprefix.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipMemcpyAsync(w + L.fin_off, fins.data(), sizeof(FinishJob) * count, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w + L.fin_prefix_off, fprefix.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
+                           st));
+    // every Pauli pass writes its rows; circuits with fewer passes leave rows unwritten: clear
+    HIP_TRY(launch_zero(epart, size_t(L.e_rows) * MULTI_WGS, st));
+    HIP_TRY(launch_zero(part, size_t(L.slot_rows) * MULTI_WGS, st));
+    const TileConfig& cfg = circs[0]->tiled[dt].host.cfg;
+    tcng_status e = TCNG_OK;
+    if (dt == TCNG_C64) {
+        HIP_TRY(launch_build_ops_multi<float>(reinterpret_cast<const BuildJob*>(w + L.build_off),
+                                              reinterpret_cast<const int64_t*>(w + L.build_prefix_off), count,
+                                              bprefix[count], st));
+        if (cfg.rb == 5 && cfg.rb_rev == 4) e = run_multi<float, 5, 4>(jobs, circs, hams, count, dt, L, w, st);
+        else if (cfg.rb == 5 && cfg.rb_rev == 5) e = run_multi<float, 5, 5>(jobs, circs, hams, count, dt, L, w, st);
+        else if (cfg.rb == 4 && cfg.rb_rev == 4) e = run_multi<float, 4, 4>(jobs, circs, hams, count, dt, L, w, st);
+        else e = run_multi<float, 4, 5>(jobs, circs, hams, count, dt, L, w, st);
+    } else {
+        HIP_TRY(launch_build_ops_multi<double>(reinterpret_cast<const BuildJob*>(w + L.build_off),
+                                               reinterpret_cast<const int64_t*>(w + L.build_prefix_off), count,
+                                               bprefix[count], st));
+        if (cfg.rb == 4 && cfg.rb_rev == 3) e = run_multi<double, 4, 3>(jobs, circs, hams, count, dt, L, w, st);
+        else if (cfg.rb == 4 && cfg.rb_rev == 4) e = run_multi<double, 4, 4>(jobs, circs, hams, count, dt, L, w, st);
+        else if (cfg.rb == 3 && cfg.rb_rev == 3) e = run_multi<double, 3, 3>(jobs, circs, hams, count, dt, L, w, st);
+        else e = run_multi<double, 3, 4>(jobs, circs, hams, count, dt, L, w, st);
+    }
+    if (e) return e;
+    PROF_TRY(F_FINISH, launch_finish_multi(part, L.slot_rows, MULTI_WGS, epart, L.e_rows, MULTI_WGS, ssum, esum,
+                                           reinterpret_cast<const FinishJob*>(w + L.fin_off),
+                                           reinterpret_cast<const int64_t*>(w + L.fin_prefix_off), count,
+                                           fprefix[count], st));
+    return ok();
+}
+
+tcng_status tcng_circuit_configure(tcng_circuit* c, int32_t dtype, int32_t m_max, int32_t rb, int32_t rb_rev) {
+    if (!c) return fail(TCNG_E_INVALID, "null circuit");
+    if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
+    if (!c->tiled[dtype].valid) return fail(TCNG_E_UNSUPPORTED, "circuit too small for the tiled path");
+    TileConfig cfg = tile_config(dtype);
+    cfg.m_max = m_max;
+    cfg.rb = rb;
+    cfg.rb_rev = rb_rev;
+    if (!config_ok(cfg, dtype) || std::min(c->n, m_max) < std::max(rb, rb_rev) + 6)
+        return fail(TCNG_E_UNSUPPORTED, "tiling not available");
+    HIP_TRY(hipDeviceSynchronize());
+    if (tcng_status e = make_plan(c, dtype, cfg)) return e;
+    return ok();
+}
+
+tcng_status tcng_circuit_get_config(const tcng_circuit* c, int32_t dtype, int32_t* m_max, int32_t* rb,
+                                    int32_t* rb_rev) {
+    if (!c || !m_max || !rb || !rb_rev) return fail(TCNG_E_INVALID, "null argument");
+    if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
+    if (!c->tiled[dtype].valid) {
+        *m_max = *rb = *rb_rev = 0;
+        return ok();
+    }
+    const TileConfig& cfg = c->tiled[dtype].host.cfg;
+    *m_max = cfg.m_max;
+    *rb = cfg.rb;
+    *rb_rev = cfg.rb_rev;
+    return ok();
+}
+
+namespace {
+
+// structural key of a circuit (gate records, not angle values) for the autotune cache
+std::string circuit_key(const tcng_circuit* c, int dtype, int64_t batch) {
+    uint64_t h = 1469598103934665603ull;   // FNV-1a
+    auto mix = [&](int32_t v) {
+        for (int i = 0; i < 4; ++i) { h ^= uint64_t((v >> (8 * i)) & 0xff); h *= 1099511628211ull; }
+    };
+    mix(c->n);
+    for (const tcng_gate& g : c->gates) { mix(g.kind); mix(g.q0); mix(g.q1); }
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::ostringstream os;
+    os << std::hex << h << std::dec << " n" << c->n << " g" << c->gates.size() << " dt" << dtype << " b" << batch
+       << " " << prop.gcnArchName;
+    return os.str();
+}
+
+}  // namespace
+
+tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* params, const tcng_state* psi,
+                          const tcng_state* lam, int32_t repeats, const char* cache_path, double* best_ms,
+                          void* stream) {
+    if (!c || !h || !psi || !lam) return fail(TCNG_E_INVALID, "null argument");
+    if (tcng_status e = check_state(psi, "tcng_autotune(psi)")) return e;
+    const int dt = psi->dtype;
+    if (!c->tiled[dt].valid) return ok();   // plain path only: nothing to tune
+    if (repeats < 1) repeats = 1;
+    const std::string key = circuit_key(c, dt, psi->batch);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.find(" | ");
+            if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+            int m = 0, rb = 0, rr = 0;
+            double ms = 0;
+            if (std::sscanf(line.c_str() + bar + 3, "%d %d %d %lf", &m, &rb, &rr, &ms) == 4) {
+                if (best_ms) *best_ms = ms;
+                return tcng_circuit_configure(c, dt, m, rb, rr);
+            }
+        }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const TileConfig def = tile_config(dt);
+    std::vector<TileConfig> cands;
+    const int rbs64[2] = {5, 4}, rbs128[2] = {4, 3};
+    const int* rbs = dt == TCNG_C64 ? rbs64 : rbs128;
+    for (int dm = 0; dm <= 1; ++dm)
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                TileConfig t = def;
+                t.m_max = def.m_max - dm;
+                t.rb = rbs[i];
+                t.rb_rev = rbs[j];
+                if (config_ok(t, dt) && std::min(c->n, t.m_max) >= std::max(t.rb, t.rb_rev) + 6) cands.push_back(t);
+            }
+    // the initial states are overwritten by each run's reverse sweep: keep a copy
+    const size_t state_bytes = size_t(psi->batch) * psi->stride * (dt == TCNG_C64 ? 8 : 16);
+    void* save = nullptr;
+    HIP_TRY(hipMalloc(&save, state_bytes));
+    HIP_TRY(hipMemcpyAsync(save, psi->amps, state_bytes, hipMemcpyDeviceToDevice, st));
+    double* energy = nullptr;
+    double* grad = nullptr;
+    HIP_TRY(hipMalloc(&energy, sizeof(double) * psi->batch));
+    HIP_TRY(hipMalloc(&grad, sizeof(double) * psi->batch * std::max(c->n_params, 1)));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    TileConfig best_cfg = c->tiled[dt].host.cfg;
+    tcng_status err = TCNG_OK;
+    for (const TileConfig& t : cands) {
+        if ((err = tcng_circuit_configure(c, dt, t.m_max, t.rb, t.rb_rev))) break;
+        size_t wsb = 0;
+        if ((err = tcng_workspace_size(c, h, dt, psi->batch, TCNG_MODE_TILED, &wsb))) break;
+        void* ws = nullptr;
+        if (hipMalloc(&ws, wsb) != hipSuccess) { err = fail(TCNG_E_ALLOC, "autotune workspace"); break; }
+        std::vector<double> times;
+        for (int r = 0; r <= repeats && !err; ++r) {   // run 0 is a warm-up
+            (void)hipMemcpyAsync(psi->amps, save, state_bytes, hipMemcpyDeviceToDevice, st);
+            (void)hipEventRecord(e0, st);
+            err = tcng_expect_grad(c, params, h, psi, lam, energy, grad, nullptr, TCNG_MODE_TILED, ws, wsb, stream);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) times.push_back(ms);
+        }
+        (void)hipFree(ws);
+        if (err) break;
+        std::sort(times.begin(), times.end());
+        const double med = times[times.size() / 2];
+        if (med < best) { best = med; best_cfg = t; }
+    }
+    (void)hipMemcpyAsync(psi->amps, save, state_bytes, hipMemcpyDeviceToDevice, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(save);
+    (void)hipFree(energy);
+    (void)hipFree(grad);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err) return err;
+    if (tcng_status e = tcng_circuit_configure(c, dt, best_cfg.m_max, best_cfg.rb, best_cfg.rb_rev)) return e;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        out << key << " | " << best_cfg.m_max << " " << best_cfg.rb << " " << best_cfg.rb_rev << " " << best << "\n";
+    }
     return ok();
 }
 

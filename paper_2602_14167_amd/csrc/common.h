@@ -65,7 +65,8 @@ __host__ __device__ inline int kind_slots(int k) {
 // ---------------------------------------------------------------------------
 constexpr int MAX_TILE_BITS = 14;
 constexpr int MAX_RB = 5;
-constexpr int RED_SLOTS = 512;   // float64 gradient accumulators per wave and reverse pass
+constexpr int RED_SLOTS = 256;   // float64 gradient accumulators per wave and reverse pass
+constexpr int MAX_THREADS = 512; // threads per tile workgroup (2^(m - rb))
 
 enum OpType : int8_t {
     OP_DENSE1 = 0,  // 2x2 matrix, operand in register bit r0

@@ -66,15 +66,39 @@ __device__ double block_sum(double v, double* sh, int nthreads) {
 // ---------------------------------------------------------------------------
 // tiled: one pass handles every X-group whose mask lies inside its tile
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ const Job& find_job(const JobList& jl, const Job& single, int64_t blk, int64_t& local) {
+    if (!jl.jobs) {
+        local = blk;
+        return single;
+    }
+    int lo = 0, hi = jl.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jl.prefix[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    local = blk - jl.prefix[lo];
+    return jl.jobs[lo];
+}
+
 template <typename R, int RB>
 __global__ void __launch_bounds__(NTHREADS)
-k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups, const PClass* __restrict__ classes,
-             const PTerm* __restrict__ terms, int pass_idx, int n_passes, const cx<R>* __restrict__ state,
-             cx<R>* __restrict__ costate, int accumulate, int64_t stride, int n, int64_t tiles_per_state, int wgs,
-             double* __restrict__ epart) {
+k_pauli_tile(const JobList jl, const Job single) {
     __shared__ cx<R> lds[PTile<R>::ELEMS];
     __shared__ double sh[NTHREADS / 64];
     constexpr int NB = 1 << RB;
+    int64_t local;
+    const Job& J = find_job(jl, single, blockIdx.x, local);
+    const int pass_idx = jl.step;
+    const PPass* passes = J.ppasses;
+    const PGroup* __restrict__ groups = J.pgroups;
+    const PClass* __restrict__ classes = J.pclasses;
+    const PTerm* __restrict__ terms = J.pterms;
+    const int accumulate = pass_idx > 0;
+    const int wgs = J.e_wgs;
+    const int n = J.n;
+    const int64_t b = local / wgs;
+    const int wg = int(local - b * wgs);
     const PPass& P = passes[pass_idx];
     const int m = P.m, lo = P.lo;
     const uint64_t tmask = P.tile_mask;
@@ -82,23 +106,26 @@ k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups
 #pragma unroll
     for (int i = 0; i < MAX_TILE_BITS; ++i) lq[i] = P.local_qubit[i];
     const int nt = 1 << (m - RB);
+    const int64_t tiles_per_state = int64_t(1) << (n - m);
     const int t = threadIdx.x;
-    const int64_t b = blockIdx.x / wgs;
-    const int wg = int(blockIdx.x - b * wgs);
-    const cx<R>* psi = state + b * stride;
-    cx<R>* lam = costate ? costate + b * stride : nullptr;
+    const bool active = t < nt;
+    const cx<R>* psi = static_cast<const cx<R>*>(J.state) + b * J.stride;
+    cx<R>* lam = J.costate ? static_cast<cx<R>*>(J.costate) + b * J.stride : nullptr;
     double e_acc = 0.0;
 
     for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), tmask, n);
         __syncthreads();
         // psi tile -> LDS; element l = it*nt + t (lane-consecutive, coalesced)
+        if (active) {
 #pragma unroll
-        for (int it = 0; it < NB; ++it) {
-            const uint32_t l = uint32_t(it * nt + t);
-            lds[l] = psi[base + loc2glob(l, lo, m, lq)];
+            for (int it = 0; it < NB; ++it) {
+                const uint32_t l = uint32_t(it * nt + t);
+                lds[l] = psi[base + loc2glob(l, lo, m, lq)];
+            }
         }
         __syncthreads();
+        if (!active) continue;
         // elements l = it*nt + t, CH at a time; the term loop is outside the
         // element loop so every scalar load of a term serves CH elements
         constexpr int CH = (NB < 8) ? NB : 8;
@@ -158,8 +185,8 @@ k_pauli_tile(const PPass* __restrict__ passes, const PGroup* __restrict__ groups
             }
         }
     }
-    const double s = block_sum(e_acc, sh, nt);
-    if (t == 0) epart[(size_t(b) * n_passes + pass_idx) * wgs + wg] = s;
+    const double s = block_sum(e_acc, sh, blockDim.x);
+    if (t == 0) J.epart[(size_t(b) * J.e_rows + pass_idx) * wgs + wg] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -205,14 +232,9 @@ k_pauli_group(const cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int 
 }  // namespace
 
 template <typename R, int RB>
-hipError_t launch_pauli_tile(const DevPauliPlan& dp, int pass_idx, int n_passes, int m, const void* state,
-                             void* costate, bool accumulate, int64_t stride, int n, int64_t batch, int wgs,
-                             double* epart, hipStream_t st) {
-    const int64_t tiles = int64_t(1) << (n - m);
-    const int nt = 1 << (m - RB);
-    hipLaunchKernelGGL((k_pauli_tile<R, RB>), dim3(unsigned(wgs * batch)), dim3(nt), 0, st, dp.passes, dp.groups,
-                       dp.classes, dp.terms, pass_idx, n_passes, static_cast<const cx<R>*>(state),
-                       static_cast<cx<R>*>(costate), int(accumulate), stride, n, tiles, wgs, epart);
+hipError_t launch_pauli_tile(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pauli_tile<R, RB>), dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
     return hipGetLastError();
 }
 
@@ -226,10 +248,8 @@ hipError_t launch_pauli_group(const void* state, void* costate, bool accumulate,
     return hipGetLastError();
 }
 
-template hipError_t launch_pauli_tile<float, 5>(const DevPauliPlan&, int, int, int, const void*, void*, bool, int64_t,
-                                                int, int64_t, int, double*, hipStream_t);
-template hipError_t launch_pauli_tile<double, 4>(const DevPauliPlan&, int, int, int, const void*, void*, bool,
-                                                 int64_t, int, int64_t, int, double*, hipStream_t);
+template hipError_t launch_pauli_tile<float, 5>(const JobList&, const Job&, int64_t, int, hipStream_t);
+template hipError_t launch_pauli_tile<double, 4>(const JobList&, const Job&, int64_t, int, hipStream_t);
 template hipError_t launch_pauli_group<float>(const void*, void*, bool, int64_t, int, int64_t, uint64_t,
                                               const PClassFull*, int, int, const PTermFull*, int, double*, int, int,
                                               hipStream_t);

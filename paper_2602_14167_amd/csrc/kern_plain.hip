@@ -95,9 +95,64 @@ __device__ __forceinline__ void mv4(const cx<R>* u, cx<R>* x) {
     for (int a = 0; a < 4; ++a) x[a] = cfma(u[4 * a + 3], x3, cfma(u[4 * a + 2], x2, cfma(u[4 * a + 1], x1, u[4 * a] * x0)));
 }
 
+// 16-byte streaming access: two complex64 or one complex128 amplitude per
+// vector, non-temporal (each amplitude is touched once per gate pass)
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void ld2(const cx<float>* p, cx<float>& a, cx<float>& b) {
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    a = {v.x, v.y};
+    b = {v.z, v.w};
+}
+__device__ __forceinline__ void st2(cx<float>* p, cx<float> a, cx<float> b) {
+    f4v v;
+    v.x = a.re; v.y = a.im; v.z = b.re; v.w = b.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<f4v*>(p));
+}
+__device__ __forceinline__ cx<double> ld1(const cx<double>* p) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void st1(cx<double>* p, cx<double> a) {
+    d2v v;
+    v.x = a.re; v.y = a.im;
+    __builtin_nontemporal_store(v, reinterpret_cast<d2v*>(p));
+}
+
 // ---------------------------------------------------------------------------
-// forward one-qubit gate
+// forward one-qubit gate.  complex64: a thread owns two neighbouring pairs,
+// i.e. one 16-byte vector from each half (q >= 1) or two vectors holding two
+// pairs (q = 0); complex128: one pair = two 16-byte vectors.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void gate1_unit(cx<float>* psi, uint64_t w, int q, const cx<float>* u) {
+    if (q == 0) {
+        cx<float> a0, a1, a2, a3;
+        ld2(psi + 4 * w, a0, a1);
+        ld2(psi + 4 * w + 2, a2, a3);
+        mv2(u, a0, a1);
+        mv2(u, a2, a3);
+        st2(psi + 4 * w, a0, a1);
+        st2(psi + 4 * w + 2, a2, a3);
+    } else {
+        const uint64_t i0 = insert0(2 * w, q);
+        cx<float> a0, a1, c0, c1;
+        ld2(psi + i0, a0, a1);
+        ld2(psi + i0 + (uint64_t(1) << q), c0, c1);
+        mv2(u, a0, c0);
+        mv2(u, a1, c1);
+        st2(psi + i0, a0, a1);
+        st2(psi + i0 + (uint64_t(1) << q), c0, c1);
+    }
+}
+__device__ __forceinline__ void gate1_unit(cx<double>* psi, uint64_t w, int q, const cx<double>* u) {
+    const uint64_t i0 = insert0(w, q), i1 = i0 | (uint64_t(1) << q);
+    cx<double> a0 = ld1(psi + i0), a1 = ld1(psi + i1);
+    mv2(u, a0, a1);
+    st1(psi + i0, a0);
+    st1(psi + i1, a1);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(NTHREADS)
 k_gate1(cx<R>* __restrict__ state, int64_t stride, int n, int q, int kind, int p0, int mat,
@@ -107,42 +162,48 @@ k_gate1(cx<R>* __restrict__ state, int64_t stride, int n, int q, int kind, int p
     cx<R>* psi = state + b * stride;
     cx<R> u[4];
     gate_mat1<R>(kind, params ? params + b * pstride : nullptr, p0, cm, mat, umat, inv != 0, u);
-    const uint64_t npairs = uint64_t(1) << (n - 1);
+    const uint64_t nunits = (sizeof(R) == 4) ? (uint64_t(1) << (n - 2)) : (uint64_t(1) << (n - 1));
     const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
-    if (sizeof(R) == 4 && n >= 2) {
-        // two pairs per thread, 16-byte accesses
-        const uint64_t nunits = npairs >> 1;
-        for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nunits; w += step) {
-            if (q == 0) {
-                cx<R>* p = psi + 4 * w;
-                cx<R> a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
-                mv2(u, a0, a1);
-                mv2(u, a2, a3);
-                p[0] = a0; p[1] = a1; p[2] = a2; p[3] = a3;
-            } else {
-                const uint64_t i0 = insert0(2 * w, q);
-                cx<R>* p0p = psi + i0;
-                cx<R>* p1p = psi + i0 + (uint64_t(1) << q);
-                cx<R> a0 = p0p[0], a1 = p0p[1], c0 = p1p[0], c1 = p1p[1];
-                mv2(u, a0, c0);
-                mv2(u, a1, c1);
-                p0p[0] = a0; p0p[1] = a1; p1p[0] = c0; p1p[1] = c1;
-            }
-        }
-    } else {
-        for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < npairs; w += step) {
-            const uint64_t i0 = insert0(w, q), i1 = i0 | (uint64_t(1) << q);
-            cx<R> a0 = psi[i0], a1 = psi[i1];
-            mv2(u, a0, a1);
-            psi[i0] = a0;
-            psi[i1] = a1;
-        }
+    uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    // two units in flight per thread
+    for (; w + step < nunits; w += 2 * step) {
+        gate1_unit(psi, w, q, u);
+        gate1_unit(psi, w + step, q, u);
     }
+    if (w < nunits) gate1_unit(psi, w, q, u);
+}
+
+// one-qubit gates on n = 1 complex64 states (a single pair)
+template <typename R>
+__global__ void k_gate1_tiny(cx<R>* __restrict__ state, int64_t stride, int q, int kind, int p0, int mat,
+                             const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm,
+                             const cx<R>* __restrict__ umat, int inv) {
+    const int64_t b = blockIdx.y;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    cx<R>* psi = state + b * stride;
+    cx<R> u[4];
+    gate_mat1<R>(kind, params ? params + b * pstride : nullptr, p0, cm, mat, umat, inv != 0, u);
+    (void)q;
+    cx<R> a0 = psi[0], a1 = psi[1];
+    mv2(u, a0, a1);
+    psi[0] = a0;
+    psi[1] = a1;
 }
 
 // ---------------------------------------------------------------------------
-// forward two-qubit gate on (q0 = MSB of the local index, q1)
+// forward two-qubit gate on (q0 = MSB of the local index, q1).  complex64 with
+// both qubits >= 1: a thread owns two neighbouring quads (four 16-byte
+// vectors); otherwise one quad.
 // ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void quad_load(const cx<R>* psi, uint64_t i, uint64_t m0, uint64_t m1, cx<R>* x) {
+    x[0] = psi[i]; x[1] = psi[i | m1]; x[2] = psi[i | m0]; x[3] = psi[i | m0 | m1];
+}
+template <typename R>
+__device__ __forceinline__ void quad_store(cx<R>* psi, uint64_t i, uint64_t m0, uint64_t m1, const cx<R>* x) {
+    psi[i] = x[0]; psi[i | m1] = x[1]; psi[i | m0] = x[2]; psi[i | m0 | m1] = x[3];
+}
+
 template <typename R>
 __global__ void __launch_bounds__(NTHREADS)
 k_gate2(cx<R>* __restrict__ state, int64_t stride, int n, int q0, int q1, int kind, int p0, int p1, int mat,
@@ -156,11 +217,32 @@ k_gate2(cx<R>* __restrict__ state, int64_t stride, int n, int q0, int q1, int ki
     const uint64_t m0 = uint64_t(1) << q0, m1 = uint64_t(1) << q1;
     const uint64_t nquads = uint64_t(1) << (n - 2);
     const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    if constexpr (sizeof(R) == 4) {
+        if (qa >= 1 && n >= 3) {
+            const uint64_t nunits = nquads >> 1;
+            for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nunits; w += step) {
+                const uint64_t i = insert0(insert0(2 * w, qa), qb);   // even: quads i and i + 1
+                cx<R> x[4], y[4];
+                ld2(psi + i, x[0], y[0]);
+                ld2(psi + (i | m1), x[1], y[1]);
+                ld2(psi + (i | m0), x[2], y[2]);
+                ld2(psi + (i | m0 | m1), x[3], y[3]);
+                mv4(u, x);
+                mv4(u, y);
+                st2(psi + i, x[0], y[0]);
+                st2(psi + (i | m1), x[1], y[1]);
+                st2(psi + (i | m0), x[2], y[2]);
+                st2(psi + (i | m0 | m1), x[3], y[3]);
+            }
+            return;
+        }
+    }
     for (uint64_t w = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; w < nquads; w += step) {
         const uint64_t i = insert0(insert0(w, qa), qb);
-        cx<R> x[4] = {psi[i], psi[i | m1], psi[i | m0], psi[i | m0 | m1]};
+        cx<R> x[4];
+        quad_load(psi, i, m0, m1, x);
         mv4(u, x);
-        psi[i] = x[0]; psi[i | m1] = x[1]; psi[i | m0] = x[2]; psi[i | m0 | m1] = x[3];
+        quad_store(psi, i, m0, m1, x);
     }
 }
 
@@ -328,36 +410,29 @@ __global__ void __launch_bounds__(256) k_rowsum(const double* __restrict__ in, i
 }
 
 // final sums: one thread per (member, output), fixed order everywhere
-__global__ void k_finish(const double* __restrict__ slots, int total_slots, const int32_t* __restrict__ slot_ptr,
-                         const int32_t* __restrict__ slot_idx, int n_params, const double* __restrict__ erow,
-                         int erows, int64_t batch, double* __restrict__ energy, double* __restrict__ grad,
-                         double* __restrict__ gate_grad, const int32_t* __restrict__ gate_slot,
-                         const double* __restrict__ u2m, const int32_t* __restrict__ gate_mat, int n_gates) {
-    const int64_t per = int64_t(1) + n_params + (gate_grad ? int64_t(n_gates) : 0);
-    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (tid >= per * batch) return;
-    const int64_t b = tid / per;
-    const int64_t k = tid - b * per;
-    const double* sl = slots + size_t(b) * total_slots;
+// output k of one circuit: k = 0 energy, 1..n_params gradient, then one
+// 15-vector of Lie-algebra derivatives per gate (when gate_grad is wanted)
+__device__ void finish_one(const FinishJob& F, int64_t k) {
+    const double* sl = F.slots;
     if (k == 0) {
         double e = 0.0;
-        for (int i = 0; i < erows; ++i) e += erow[size_t(b) * erows + i];
-        energy[b] = e;
-    } else if (k <= n_params) {
+        for (int i = 0; i < F.erows; ++i) e += F.erow[i];
+        F.energy[0] = e;
+    } else if (k <= F.n_params) {
         const int p = int(k - 1);
         double g = 0.0;
-        for (int i = slot_ptr[p]; i < slot_ptr[p + 1]; ++i) g += sl[slot_idx[i]];
-        grad[size_t(b) * n_params + p] = g;
+        for (int i = F.slot_ptr[p]; i < F.slot_ptr[p + 1]; ++i) g += sl[F.slot_idx[i]];
+        F.grad[p] = g;
     } else {
         // per U2 gate: dE/dalpha_k = Im tr(G^dag P_k U), P_k = sigma_a (x) sigma_b, k = 4a + b - 1
-        const int gi = int(k - 1 - n_params);
-        double* out = gate_grad + (size_t(b) * n_gates + gi) * 15;
-        const int s0 = gate_slot[gi];
+        const int gi = int(k - 1 - F.n_params);
+        double* out = F.gate_grad + size_t(gi) * 15;
+        const int s0 = F.gate_slot[gi];
         if (s0 < 0) {
             for (int i = 0; i < 15; ++i) out[i] = 0.0;
             return;
         }
-        const double* U = u2m + size_t(gate_mat[gi]) * 32;
+        const double* U = F.u2m + size_t(F.gate_mat[gi]) * 32;
         // single-qubit Paulis: entry (r, c) of sigma_a as (re, im)
         auto sig = [](int a, int r, int c, double& re, double& im) {
             re = 0.0; im = 0.0;
@@ -391,6 +466,45 @@ __global__ void k_finish(const double* __restrict__ slots, int total_slots, cons
     }
 }
 
+__global__ void k_finish(const double* __restrict__ slots, int total_slots, const int32_t* __restrict__ slot_ptr,
+                         const int32_t* __restrict__ slot_idx, int n_params, const double* __restrict__ erow,
+                         int erows, int64_t batch, double* __restrict__ energy, double* __restrict__ grad,
+                         double* __restrict__ gate_grad, const int32_t* __restrict__ gate_slot,
+                         const double* __restrict__ u2m, const int32_t* __restrict__ gate_mat, int n_gates) {
+    const int64_t per = int64_t(1) + n_params + (gate_grad ? int64_t(n_gates) : 0);
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= per * batch) return;
+    const int64_t b = tid / per;
+    FinishJob F{};
+    F.slots = slots + size_t(b) * total_slots;
+    F.erow = erow + size_t(b) * erows;
+    F.slot_ptr = slot_ptr;
+    F.slot_idx = slot_idx;
+    F.gate_slot = gate_slot;
+    F.u2m = u2m;
+    F.gate_mat = gate_mat;
+    F.energy = energy + b;
+    F.grad = grad ? grad + size_t(b) * n_params : nullptr;
+    F.gate_grad = gate_grad ? gate_grad + size_t(b) * n_gates * 15 : nullptr;
+    F.n_params = n_params;
+    F.n_gates = n_gates;
+    F.erows = erows;
+    finish_one(F, tid - b * per);
+}
+
+__global__ void k_finish_multi(const FinishJob* __restrict__ jobs, const int64_t* __restrict__ prefix, int njobs,
+                               int64_t total) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    finish_one(jobs[lo], i - prefix[lo]);
+}
+
 }  // namespace
 
 template <typename R>
@@ -401,12 +515,28 @@ static unsigned grid_for(uint64_t work) {
     return unsigned(blocks);
 }
 
+// streaming launches: a persistent-style grid of at most 1024 workgroups per
+// batch member (about four per compute unit), each thread looping over units
+static unsigned stream_grid(uint64_t units, int64_t batch) {
+    uint64_t blocks = (units + NTHREADS - 1) / NTHREADS;
+    uint64_t cap = 1024;
+    if (batch > 1) cap = std::max<uint64_t>(1, 4096 / uint64_t(batch));
+    blocks = std::min(blocks, cap);
+    return unsigned(std::max<uint64_t>(blocks, 1));
+}
+
 template <typename R>
 hipError_t launch_gate1(void* state, int64_t stride, int n, int64_t batch, int q, int kind, int p0, int mat,
                         const void* params, int64_t pstride, const void* cmats, const void* umat, bool inv,
                         hipStream_t st) {
-    const uint64_t work = (sizeof(R) == 4 && n >= 2) ? (uint64_t(1) << (n - 2)) : (uint64_t(1) << (n - 1));
-    hipLaunchKernelGGL((k_gate1<R>), dim3(grid_for<R>(work), unsigned(batch)), dim3(NTHREADS), 0, st,
+    if (sizeof(R) == 4 && n < 2) {
+        hipLaunchKernelGGL((k_gate1_tiny<R>), dim3(1, unsigned(batch)), dim3(64), 0, st, static_cast<cx<R>*>(state),
+                           stride, q, kind, p0, mat, static_cast<const R*>(params), pstride,
+                           static_cast<const cx<R>*>(cmats), static_cast<const cx<R>*>(umat), int(inv));
+        return hipGetLastError();
+    }
+    const uint64_t units = (sizeof(R) == 4) ? (uint64_t(1) << (n - 2)) : (uint64_t(1) << (n - 1));
+    hipLaunchKernelGGL((k_gate1<R>), dim3(stream_grid(units, batch), unsigned(batch)), dim3(NTHREADS), 0, st,
                        static_cast<cx<R>*>(state), stride, n, q, kind, p0, mat, static_cast<const R*>(params), pstride,
                        static_cast<const cx<R>*>(cmats), static_cast<const cx<R>*>(umat), int(inv));
     return hipGetLastError();
@@ -416,7 +546,7 @@ template <typename R>
 hipError_t launch_gate2(void* state, int64_t stride, int n, int64_t batch, int q0, int q1, int kind, int p0, int p1,
                         int mat, const void* params, int64_t pstride, const void* cmats, const void* umat, bool inv,
                         hipStream_t st) {
-    hipLaunchKernelGGL((k_gate2<R>), dim3(grid_for<R>(uint64_t(1) << (n - 2)), unsigned(batch)), dim3(NTHREADS), 0,
+    hipLaunchKernelGGL((k_gate2<R>), dim3(stream_grid(uint64_t(1) << (n - 2), batch), unsigned(batch)), dim3(NTHREADS), 0,
                        st, static_cast<cx<R>*>(state), stride, n, q0, q1, kind, p0, p1, mat,
                        static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats),
                        static_cast<const cx<R>*>(umat), int(inv));
@@ -491,6 +621,26 @@ hipError_t launch_finish(const double* part, int total_slots, int wgs, const int
     hipLaunchKernelGGL(k_finish, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, slots, total_slots, slot_ptr,
                        slot_idx, n_params, erow, erows, batch, energy, grad, gate_grad, gate_slot, u2_mats_c128,
                        gate_mat, n_gates);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_multi(const double* part, int64_t prows, int wgs, const double* epart, int64_t erows_total,
+                               int ewgs, double* slot_sums, double* erow_sums, const FinishJob* jobs,
+                               const int64_t* prefix, int njobs, int64_t total, hipStream_t st) {
+    if (prows > 0) {
+        hipLaunchKernelGGL(k_rowsum, dim3(unsigned((prows + 3) / 4)), dim3(256), 0, st, part, prows, wgs, slot_sums);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (erows_total > 0) {
+        hipLaunchKernelGGL(k_rowsum, dim3(unsigned((erows_total + 3) / 4)), dim3(256), 0, st, epart, erows_total, ewgs,
+                           erow_sums);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finish_multi, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, jobs, prefix, njobs,
+                       total);
     return hipGetLastError();
 }
 

@@ -22,7 +22,14 @@ namespace tcng {
 
 namespace {
 
-constexpr int NTHREADS = 256;
+constexpr int NTHREADS = MAX_THREADS;
+
+// largest workgroup of a (precision, register block) instantiation: a full
+// 64 KiB tile, 2^(m_max - RB) threads
+template <typename R, int RB>
+struct MaxThreads {
+    static constexpr int value = 1 << ((sizeof(R) == 4 ? 13 : 12) - RB);
+};
 
 template <typename R>
 struct Tile {
@@ -379,18 +386,10 @@ __device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, con
     return a;
 }
 
-// matrix entries of every op of a plan for every batch member, computed once
-// per evaluation: dense 2x2 (4 entries), diagonals (2 or 4), dense 4x4 (16)
+// matrix entries of one op (table indexed by gate)
 template <typename R>
-__global__ void k_build_ops(const Op* __restrict__ ops, int n_ops, const R* __restrict__ params, int64_t pstride,
-                            const cx<R>* __restrict__ cm, int64_t batch, cx<R>* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= int64_t(n_ops) * batch) return;
-    const int64_t b = i / n_ops;
-    const int o = int(i - b * n_ops);
-    const Op op = ops[o];
-    const R* prm = params ? params + b * pstride : nullptr;
-    cx<R>* dst = out + size_t(i) * 16;
+__device__ __forceinline__ void build_op(const Op& op, const R* prm, const cx<R>* cm, cx<R>* table) {
+    cx<R>* dst = table + size_t(op.gate) * 16;
     cx<R> u[16];
     switch (op.type) {
         case OP_DENSE1: case OP_REAL1: case OP_RX: mat1<R>(op.kind, prm, op.p0, cm, op.mat, u); break;
@@ -405,6 +404,36 @@ __global__ void k_build_ops(const Op* __restrict__ ops, int n_ops, const R* __re
         if (k < cnt) dst[k] = u[k];
 }
 
+// matrix entries of every op of a plan for every batch member, computed once
+// per evaluation: dense 2x2 (4 entries), diagonals (2 or 4), dense 4x4 (16)
+template <typename R>
+__global__ void k_build_ops(const Op* __restrict__ ops, int n_ops, const R* __restrict__ params, int64_t pstride,
+                            const cx<R>* __restrict__ cm, int64_t batch, cx<R>* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(n_ops) * batch) return;
+    const int64_t b = i / n_ops;
+    const int o = int(i - b * n_ops);
+    build_op<R>(ops[o], params ? params + b * pstride : nullptr, cm, out + size_t(b) * n_ops * 16);
+}
+
+// the same for an uneven batch: job j covers threads [prefix[j], prefix[j+1])
+template <typename R>
+__global__ void k_build_ops_multi(const BuildJob* __restrict__ jobs, const int64_t* __restrict__ prefix, int njobs,
+                                  int64_t total) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const BuildJob& B = jobs[lo];
+    const int o = int(i - prefix[lo]);
+    build_op<R>(B.ops[o], static_cast<const R*>(B.params), static_cast<const cx<R>*>(B.cmats),
+                static_cast<cx<R>*>(B.opm));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -412,147 +441,181 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// forward pass: one tile per workgroup
+// job lookup: block -> (job, member, tile or workgroup index)
 // ---------------------------------------------------------------------------
-template <typename R, int RB>
-__global__ void __launch_bounds__(NTHREADS)
-k_tile_fwd(const Pass* __restrict__ passes, const Phase* __restrict__ phases, const Op* __restrict__ ops, int pass_idx,
-           cx<R>* __restrict__ state, int64_t stride, int n, const cx<R>* __restrict__ opm, int n_ops,
-           int64_t tiles_per_state) {
-    __shared__ cx<R> lds[Tile<R>::ELEMS];
-    const Pass& P = passes[pass_idx];
-    const PassInfo pi = read_pass(P);
-    const int nt = 1 << (pi.m - RB);
-    const int t = threadIdx.x;
-    const int64_t gid = blockIdx.x;
-    const int64_t b = gid / tiles_per_state;
-    const uint64_t tile = uint64_t(gid - b * tiles_per_state);
-    cx<R>* psi = state + b * stride;
-    const cx<R>* om = opm + size_t(b) * n_ops * 16;
-    const uint64_t base = tile_base(tile, pi.tmask, n);
-
-    tile_load<R, RB>(lds, psi, base, pi, t, nt);
-    __syncthreads();
-    for (int f = P.phase_begin; f < P.phase_end; ++f) {
-        const Phase& F = phases[f];
-        const PhaseMap pm = phase_map<RB>(F, t, pi.m);
-        Regs<R, (1 << RB)> a = regs_from_lds<R, RB>(lds, pm);
-        for (int o = F.op_begin; o < F.op_end; ++o) a = apply_op<R, RB, false>(a, ops[o], pm.tpart, om + 16 * o);
-        regs_to_lds<R, RB>(a, lds, pm);
-        __syncthreads();
+__device__ __forceinline__ const Job& find_job(const JobList& jl, const Job& single, int64_t blk, int64_t& local) {
+    if (!jl.jobs) {
+        local = blk;
+        return single;
     }
-    tile_store<R, RB>(lds, psi, base, pi, t, nt);
+    int lo = 0, hi = jl.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jl.prefix[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    local = blk - jl.prefix[lo];
+    return jl.jobs[lo];
 }
 
 // ---------------------------------------------------------------------------
-// reverse pass: psi and lambda, gradient slots accumulated per wave in LDS,
-// `wgs` workgroups per batch member loop over the tiles
+// forward pass: one tile per workgroup.  Waves beyond the job's tile size
+// (2^(m - RB) threads; jobs of one launch may differ in m) take part in the
+// barriers only.
 // ---------------------------------------------------------------------------
 template <typename R, int RB>
-__global__ void __launch_bounds__(NTHREADS)
-k_tile_rev(const Pass* __restrict__ passes, const Phase* __restrict__ phases, const Op* __restrict__ ops, int pass_idx,
-           cx<R>* __restrict__ state, cx<R>* __restrict__ costate, int64_t stride, int n,
-           const cx<R>* __restrict__ opm, int n_ops, int64_t tiles_per_state, int wgs, double* __restrict__ part,
-           int total_slots) {
+__global__ void __launch_bounds__((MaxThreads<R, RB>::value))
+k_tile_fwd(const JobList jl, const Job single) {
+    __shared__ cx<R> lds[Tile<R>::ELEMS];
+    int64_t local;
+    const Job& J = find_job(jl, single, blockIdx.x, local);
+    const Pass& P = J.passes[jl.step];
+    const PassInfo pi = read_pass(P);
+    const int nt = 1 << (pi.m - RB);
+    const int t = threadIdx.x;
+    const bool active = t < nt;
+    const int64_t b = local / J.tiles;
+    const uint64_t tile = uint64_t(local - b * J.tiles);
+    const int n = J.n;
+    cx<R>* psi = static_cast<cx<R>*>(J.state) + b * J.stride;
+    const cx<R>* om = static_cast<const cx<R>*>(J.opm) + size_t(b) * J.n_gates * 16;
+    const uint64_t base = tile_base(tile, pi.tmask, n);
+
+    if (active) tile_load<R, RB>(lds, psi, base, pi, t, nt);
+    __syncthreads();
+    for (int f = P.phase_begin; f < P.phase_end; ++f) {
+        if (active) {
+            const Phase& F = J.phases[f];
+            const PhaseMap pm = phase_map<RB>(F, t, pi.m);
+            Regs<R, (1 << RB)> a = regs_from_lds<R, RB>(lds, pm);
+            for (int o = F.op_begin; o < F.op_end; ++o) {
+                const Op& op = J.ops[o];
+                a = apply_op<R, RB, false>(a, op, pm.tpart, om + 16 * op.gate);
+            }
+            regs_to_lds<R, RB>(a, lds, pm);
+        }
+        __syncthreads();
+    }
+    if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt);
+}
+
+// ---------------------------------------------------------------------------
+// reverse pass (pass n_passes - 1 - step): psi and lambda, gradient slots
+// accumulated per wave in LDS; `wgs` workgroups per member loop over the tiles
+// ---------------------------------------------------------------------------
+template <typename R, int RB>
+__global__ void __launch_bounds__((MaxThreads<R, RB>::value))
+k_tile_rev(const JobList jl, const Job single) {
     __shared__ cx<R> lds[Tile<R>::ELEMS];
     __shared__ double red[RED_SLOTS * (NTHREADS / 64)];
     using Blk = Regs<R, (1 << RB)>;
-    const Pass& P = passes[pass_idx];
+    int64_t local;
+    const Job& J = find_job(jl, single, blockIdx.x, local);
+    const int pidx = J.n_passes - 1 - jl.step;
+    const Pass& P = J.rpasses[pidx];
     const PassInfo pi = read_pass(P);
     const int nt = 1 << (pi.m - RB);
     const int nwaves = (nt + 63) / 64;
     const int t = threadIdx.x;
+    const bool active = t < nt;
     const int wave = t >> 6, lane = t & 63;
-    const int64_t b = blockIdx.x / wgs;
-    const int wg = int(blockIdx.x - b * wgs);
-    cx<R>* psi = state + b * stride;
-    cx<R>* lam = costate + b * stride;
-    const cx<R>* om = opm + size_t(b) * n_ops * 16;
+    const int wgs = J.wgs;
+    const int64_t b = local / wgs;
+    const int wg = int(local - b * wgs);
+    const int n = J.n;
+    cx<R>* psi = static_cast<cx<R>*>(J.state) + b * J.stride;
+    cx<R>* lam = static_cast<cx<R>*>(J.costate) + b * J.stride;
+    const cx<R>* om = static_cast<const cx<R>*>(J.opm) + size_t(b) * J.n_gates * 16;
     const int nslots = P.n_slots;
 
-    for (int i = t; i < nslots * nwaves; i += nt) red[i] = 0.0;
+    for (int i = t; i < nslots * nwaves; i += blockDim.x) red[i] = 0.0;
     // (the first __syncthreads below orders these writes before any accumulation)
 
-    for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
+    for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), pi.tmask, n);
         // phases run backwards; psi and lambda take turns in the one LDS tile
-        __syncthreads();
-        tile_load<R, RB>(lds, psi, base, pi, t, nt);
-        __syncthreads();
         int f = P.phase_end - 1;
-        PhaseMap pm = phase_map<RB>(phases[f], t, pi.m);
-        Blk ps = regs_from_lds<R, RB>(lds, pm);
+        PhaseMap pm = phase_map<RB>(J.rphases[f], t, pi.m);
+        Blk ps, la;
         __syncthreads();
-        tile_load<R, RB>(lds, lam, base, pi, t, nt);
+        if (active) tile_load<R, RB>(lds, psi, base, pi, t, nt);
         __syncthreads();
-        Blk la = regs_from_lds<R, RB>(lds, pm);
+        if (active) ps = regs_from_lds<R, RB>(lds, pm);
+        __syncthreads();
+        if (active) tile_load<R, RB>(lds, lam, base, pi, t, nt);
+        __syncthreads();
+        if (active) la = regs_from_lds<R, RB>(lds, pm);
         for (;;) {
-            const Phase& F = phases[f];
-            for (int o = F.op_end - 1; o >= F.op_begin; --o) {
-                const Op op = ops[o];
-                if (op.slot >= 0 && op.kind != K_U2) {
-                    double g0 = 0.0, g1 = 0.0;
-                    if (op.kind == K_RX || op.kind == K_RY) {
-                        g0 = grad_rot1_at<R, RB>(op.kind, op.r0, la, ps);
-                    } else if (op.kind == K_FSIM) {
-                        const double2 g = grad_fsim_at<R, RB>(op.r0, op.r1, la, ps);
-                        g0 = g.x;
-                        g1 = g.y;
-                    } else {                            // RZ, RZZ
-                        const int tb0 = op.lb0 >= 0 ? int((pm.tpart >> op.lb0) & 1) : 0;
-                        const int tb1 = op.lb1 >= 0 ? int((pm.tpart >> op.lb1) & 1) : 0;
-                        g0 = grad_zdiag<R, (1 << RB)>(la, ps, op.r0, tb0, op.type == OP_DIAG2 ? op.r1 : -1,
-                                                      op.type == OP_DIAG2 ? tb1 : 0);
-                    }
-                    g0 = wave_sum(g0);
-                    if (lane == 0) red[op.slot * nwaves + wave] += g0;
-                    if (op.kind == K_FSIM) {
-                        g1 = wave_sum(g1);
-                        if (lane == 0) red[(op.slot + 1) * nwaves + wave] += g1;
-                    }
-                }
-                ps = apply_op<R, RB, true>(ps, op, pm.tpart, om + 16 * o);
-                if (op.kind == K_U2 && op.slot >= 0) {
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const double2 g = cot_u2_at<R, RB>(op.r0, op.r1, la, ps, e >> 2, e & 3);
-                        const double gr = wave_sum(g.x), gi = wave_sum(g.y);
-                        if (lane == 0) {
-                            red[(op.slot + 2 * e) * nwaves + wave] += gr;
-                            red[(op.slot + 2 * e + 1) * nwaves + wave] += gi;
+            const Phase& F = J.rphases[f];
+            if (active) {
+                for (int o = F.op_end - 1; o >= F.op_begin; --o) {
+                    const Op op = J.rops[o];
+                    const cx<R>* m16 = om + 16 * op.gate;
+                    if (op.slot >= 0 && op.kind != K_U2) {
+                        double g0 = 0.0, g1 = 0.0;
+                        if (op.kind == K_RX || op.kind == K_RY) {
+                            g0 = grad_rot1_at<R, RB>(op.kind, op.r0, la, ps);
+                        } else if (op.kind == K_FSIM) {
+                            const double2 g = grad_fsim_at<R, RB>(op.r0, op.r1, la, ps);
+                            g0 = g.x;
+                            g1 = g.y;
+                        } else {                            // RZ, RZZ
+                            const int tb0 = op.lb0 >= 0 ? int((pm.tpart >> op.lb0) & 1) : 0;
+                            const int tb1 = op.lb1 >= 0 ? int((pm.tpart >> op.lb1) & 1) : 0;
+                            g0 = grad_zdiag<R, (1 << RB)>(la, ps, op.r0, tb0, op.type == OP_DIAG2 ? op.r1 : -1,
+                                                          op.type == OP_DIAG2 ? tb1 : 0);
+                        }
+                        g0 = wave_sum(g0);
+                        if (lane == 0) red[op.slot * nwaves + wave] += g0;
+                        if (op.kind == K_FSIM) {
+                            g1 = wave_sum(g1);
+                            if (lane == 0) red[(op.slot + 1) * nwaves + wave] += g1;
                         }
                     }
+                    ps = apply_op<R, RB, true>(ps, op, pm.tpart, m16);
+                    if (op.kind == K_U2 && op.slot >= 0) {
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) {
+                            const double2 g = cot_u2_at<R, RB>(op.r0, op.r1, la, ps, e >> 2, e & 3);
+                            const double gr = wave_sum(g.x), gi = wave_sum(g.y);
+                            if (lane == 0) {
+                                red[(op.slot + 2 * e) * nwaves + wave] += gr;
+                                red[(op.slot + 2 * e + 1) * nwaves + wave] += gi;
+                            }
+                        }
+                    }
+                    la = apply_op<R, RB, true>(la, op, pm.tpart, m16);
                 }
-                la = apply_op<R, RB, true>(la, op, pm.tpart, om + 16 * o);
             }
             if (f == P.phase_begin) break;
             // hand both blocks to the previous phase's register assignment
-            const PhaseMap pn = phase_map<RB>(phases[f - 1], t, pi.m);
+            const PhaseMap pn = phase_map<RB>(J.rphases[f - 1], t, pi.m);
             __syncthreads();
-            regs_to_lds<R, RB>(ps, lds, pm);
+            if (active) regs_to_lds<R, RB>(ps, lds, pm);
             __syncthreads();
-            ps = regs_from_lds<R, RB>(lds, pn);
+            if (active) ps = regs_from_lds<R, RB>(lds, pn);
             __syncthreads();
-            regs_to_lds<R, RB>(la, lds, pm);
+            if (active) regs_to_lds<R, RB>(la, lds, pm);
             __syncthreads();
-            la = regs_from_lds<R, RB>(lds, pn);
+            if (active) la = regs_from_lds<R, RB>(lds, pn);
             pm = pn;
             --f;
         }
         __syncthreads();
-        regs_to_lds<R, RB>(ps, lds, pm);
+        if (active) regs_to_lds<R, RB>(ps, lds, pm);
         __syncthreads();
-        tile_store<R, RB>(lds, psi, base, pi, t, nt);
+        if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt);
         __syncthreads();
-        regs_to_lds<R, RB>(la, lds, pm);
+        if (active) regs_to_lds<R, RB>(la, lds, pm);
         __syncthreads();
-        tile_store<R, RB>(lds, lam, base, pi, t, nt);
+        if (active) tile_store<R, RB>(lds, lam, base, pi, t, nt);
     }
     __syncthreads();
-    for (int s = t; s < nslots; s += nt) {
+    double* part = J.part + size_t(b) * J.total_slots * wgs;
+    for (int s = t; s < nslots; s += blockDim.x) {
         double v = 0.0;
         for (int w = 0; w < nwaves; ++w) v += red[s * nwaves + w];
-        part[(size_t(b) * total_slots + P.slot_base + s) * wgs + wg] = v;
+        part[size_t(P.slot_base + s) * wgs + wg] = v;
     }
 }
 
@@ -570,39 +633,40 @@ hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, in
 }
 
 template <typename R, int RB>
-hipError_t launch_tile_fwd(const DevPlan& dp, int pass_idx, int m, void* state, int64_t stride, int n, int64_t batch,
-                           const void* opm, int n_ops, hipStream_t st) {
-    const int64_t tiles = int64_t(1) << (n - m);
-    const int nt = 1 << (m - RB);
-    hipLaunchKernelGGL((k_tile_fwd<R, RB>), dim3(unsigned(tiles * batch)), dim3(nt), 0, st, dp.passes, dp.phases,
-                       dp.ops, pass_idx, static_cast<cx<R>*>(state), stride, n, static_cast<const cx<R>*>(opm), n_ops,
-                       tiles);
+hipError_t launch_tile_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_tile_fwd<R, RB>), dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
     return hipGetLastError();
 }
 
 template <typename R, int RB>
-hipError_t launch_tile_rev(const DevPlan& dp, int pass_idx, int m, void* state, void* costate, int64_t stride, int n,
-                           int64_t batch, const void* opm, int n_ops, int wgs, double* part, int total_slots,
-                           hipStream_t st) {
-    const int64_t tiles = int64_t(1) << (n - m);
-    const int nt = 1 << (m - RB);
-    hipLaunchKernelGGL((k_tile_rev<R, RB>), dim3(unsigned(wgs * batch)), dim3(nt), 0, st, dp.passes, dp.phases,
-                       dp.ops, pass_idx, static_cast<cx<R>*>(state), static_cast<cx<R>*>(costate), stride, n,
-                       static_cast<const cx<R>*>(opm), n_ops, tiles, wgs, part, total_slots);
+hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_tile_rev<R, RB>), dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
     return hipGetLastError();
 }
+
+template <typename R>
+hipError_t launch_build_ops_multi(const BuildJob* jobs, const int64_t* prefix, int njobs, int64_t total,
+                                  hipStream_t st) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_build_ops_multi<R>), dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, jobs, prefix,
+                       njobs, total);
+    return hipGetLastError();
+}
+template hipError_t launch_build_ops_multi<float>(const BuildJob*, const int64_t*, int, int64_t, hipStream_t);
+template hipError_t launch_build_ops_multi<double>(const BuildJob*, const int64_t*, int, int64_t, hipStream_t);
 
 template hipError_t launch_build_ops<float>(const DevPlan&, int, const void*, int64_t, const void*, int64_t, void*,
                                             hipStream_t);
 template hipError_t launch_build_ops<double>(const DevPlan&, int, const void*, int64_t, const void*, int64_t, void*,
                                              hipStream_t);
-template hipError_t launch_tile_fwd<float, 5>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*, int,
-                                              hipStream_t);
-template hipError_t launch_tile_fwd<double, 4>(const DevPlan&, int, int, void*, int64_t, int, int64_t, const void*,
-                                               int, hipStream_t);
-template hipError_t launch_tile_rev<float, 5>(const DevPlan&, int, int, void*, void*, int64_t, int, int64_t,
-                                              const void*, int, int, double*, int, hipStream_t);
-template hipError_t launch_tile_rev<double, 4>(const DevPlan&, int, int, void*, void*, int64_t, int, int64_t,
-                                               const void*, int, int, double*, int, hipStream_t);
+#define TCNG_INST_TILE(R, RB)                                                                                     \
+    template hipError_t launch_tile_fwd<R, RB>(const JobList&, const Job&, int64_t, int, hipStream_t);           \
+    template hipError_t launch_tile_rev<R, RB>(const JobList&, const Job&, int64_t, int, hipStream_t);
+TCNG_INST_TILE(float, 4)
+TCNG_INST_TILE(float, 5)
+TCNG_INST_TILE(double, 3)
+TCNG_INST_TILE(double, 4)
 
 }  // namespace tcng

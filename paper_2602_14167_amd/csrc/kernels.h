@@ -12,6 +12,39 @@ struct DevPlan {
     const Op* ops = nullptr;
 };
 
+// One unit of a tiled launch: a circuit with `batch` members sharing its plan
+// (parameter sets), or one circuit of an uneven batch.  A launch covers a
+// list of jobs; job j owns blocks [prefix[j], prefix[j+1]) and each member
+// `per` consecutive blocks (tiles in the forward sweep, `wgs` workgroups in
+// the reverse and Pauli sweeps).  All fields are 32/64-bit (scalar loads).
+struct Job {
+    const Pass* passes;
+    const Phase* phases;
+    const Op* ops;            // forward plan
+    const Pass* rpasses;
+    const Phase* rphases;
+    const Op* rops;           // reverse plan
+    const PPass* ppasses;
+    const PGroup* pgroups;
+    const PClass* pclasses;
+    const PTerm* pterms;      // Pauli plan
+    void* state;              // member b at + b * stride amplitudes
+    void* costate;
+    const void* opm;          // member b at + b * n_gates * 16 entries
+    double* part;             // member b at + b * total_slots * wgs
+    double* epart;            // member b at + b * e_rows * e_wgs
+    int64_t stride, batch, tiles;
+    int32_t n, n_gates, n_passes, n_ppasses;
+    int32_t total_slots, wgs, e_rows, e_wgs;
+};
+
+// job list of a launch; a single job may be passed by value (jobs == nullptr)
+struct JobList {
+    const Job* jobs;
+    const int64_t* prefix;    // [njobs + 1] block offsets
+    int32_t njobs, step;
+};
+
 struct DevPauliPlan {
     const PPass* passes = nullptr;
     const PGroup* groups = nullptr;
@@ -24,17 +57,14 @@ struct DevPauliPlan {
 template <typename R>
 hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, int64_t pstride, const void* cmats,
                             int64_t batch, void* opm, hipStream_t st);
+// step: forward pass index, reverse step (pass n_passes - 1 - step) or Pauli pass index;
+// nthreads: workgroup size (2^(m - RB) of the largest tile among the jobs)
 template <typename R, int RB>
-hipError_t launch_tile_fwd(const DevPlan& dp, int pass_idx, int m, void* state, int64_t stride, int n, int64_t batch,
-                           const void* opm, int n_ops, hipStream_t st);
+hipError_t launch_tile_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 template <typename R, int RB>
-hipError_t launch_tile_rev(const DevPlan& dp, int pass_idx, int m, void* state, void* costate, int64_t stride, int n,
-                           int64_t batch, const void* opm, int n_ops, int wgs, double* part, int total_slots,
-                           hipStream_t st);
+hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 template <typename R, int RB>
-hipError_t launch_pauli_tile(const DevPauliPlan& dp, int pass_idx, int n_passes, int m, const void* state,
-                             void* costate, bool accumulate, int64_t stride, int n, int64_t batch, int wgs,
-                             double* epart, hipStream_t st);
+hipError_t launch_pauli_tile(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 
 // ---- plain (one kernel per gate / per Pauli X-group)
 template <typename R>
@@ -67,6 +97,35 @@ hipError_t launch_init(void* state, int64_t stride, int n, int64_t batch, const 
                        hipStream_t st);
 
 hipError_t launch_zero(double* p, size_t count, hipStream_t st);
+
+// ---- uneven batch: per-circuit descriptors for the op-matrix build and the final sums
+struct BuildJob {
+    const Op* ops;            // forward plan (every gate once)
+    const void* params;
+    const void* cmats;
+    void* opm;
+    int32_t n_ops, pad;
+};
+struct FinishJob {
+    const double* slots;      // row sums of this circuit's gradient partials
+    const double* erow;       // row sums of its energy partials
+    const int32_t* slot_ptr;
+    const int32_t* slot_idx;
+    const int32_t* gate_slot;
+    const double* u2m;
+    const int32_t* gate_mat;
+    double* energy;           // one value
+    double* grad;             // [n_params] or null
+    double* gate_grad;        // [n_gates][15] or null
+    int32_t n_params, n_gates, erows, pad;
+};
+template <typename R>
+hipError_t launch_build_ops_multi(const BuildJob* jobs, const int64_t* prefix, int njobs, int64_t total,
+                                  hipStream_t st);
+// prefix[j]: first output thread of job j (outputs: energy, n_params gradients, n_gates gate rows if gate_grad)
+hipError_t launch_finish_multi(const double* part, int64_t prows, int wgs, const double* epart, int64_t erows_total,
+                               int ewgs, double* slot_sums, double* erow_sums, const FinishJob* jobs,
+                               const int64_t* prefix, int njobs, int64_t total, hipStream_t st);
 
 // grad[b][p] = sum over slots of p of sum_wg part; energy[b] = sum of erows; lie from U2 cotangents.
 // scratch: batch * (total_slots + erows) doubles.

@@ -71,6 +71,84 @@ uint64_t fill_tile(uint64_t T, int n, int m) {
     return T;
 }
 
+// Register phases of one pass: a phase holds rb local bits in registers; a
+// gate joins it when no earlier unapplied gate of the pass shares a qubit and
+// the bits it needs in registers fit.
+std::string plan_phases(const std::vector<tcng_gate>& gates, const std::vector<int>& sel, const int* qubit_to_local,
+                        int m, int rb, const std::vector<int32_t>& gate_slot_first, Pass& P,
+                        std::vector<Phase>& phases, std::vector<Op>& ops) {
+    P.phase_begin = int(phases.size());
+    std::vector<int> prem = sel;
+    while (!prem.empty()) {
+        uint32_t R = 0;   // local bits in registers
+        uint64_t blocked = 0;
+        std::vector<int> ph, rest2;
+        for (int gi : prem) {
+            const tcng_gate& g = gates[gi];
+            uint64_t qm = gate_qmask(g);
+            uint32_t need = 0;
+            const int l0 = qubit_to_local[g.q0];
+            const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
+            if (g.kind == K_CNOT) need = 1u << l1;
+            else if (g.kind == K_CZ || g.kind == K_RZZ || kind_diagonal(g.kind)) need = 0;
+            else need = (1u << l0) | (l1 >= 0 ? (1u << l1) : 0u);
+            if (!(qm & blocked) && popc(R | need) <= rb) {
+                R |= need;
+                ph.push_back(gi);
+            } else {
+                blocked |= qm;
+                rest2.push_back(gi);
+            }
+        }
+        prem.swap(rest2);
+        // fill the register set to exactly rb bits, preferring high local bits
+        // (keeps consecutive lanes on consecutive LDS addresses)
+        for (int b = m - 1; b >= 0 && popc(R) < rb; --b) R |= 1u << b;
+        Phase F{};
+        for (int i = 0; i < 6; ++i) F.R[i] = -1;
+        int ri = 0, reg_of_local[MAX_TILE_BITS];
+        for (int b = 0; b < MAX_TILE_BITS; ++b) reg_of_local[b] = -1;
+        for (int b = 0; b < m; ++b)
+            if ((R >> b) & 1) { F.R[ri] = b; reg_of_local[b] = ri; ++ri; }
+        F.op_begin = int(ops.size());
+        for (int gi : ph) {
+            const tcng_gate& g = gates[gi];
+            Op o{};
+            o.kind = g.kind;
+            o.p0 = g.p0;
+            o.p1 = g.p1;
+            o.mat = g.mat;
+            o.gate = gi;
+            o.slot = gate_slot_first[gi];
+            const int l0 = qubit_to_local[g.q0];
+            const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
+            o.lb0 = l0;
+            o.lb1 = l1;
+            o.r0 = reg_of_local[l0];
+            o.r1 = l1 >= 0 ? reg_of_local[l1] : -1;
+            switch (g.kind) {
+                case K_RZ: case K_Z: case K_S: o.type = OP_DIAG1; break;
+                case K_CZ: case K_RZZ: o.type = OP_DIAG2; break;
+                case K_CNOT: o.type = OP_CX; break;
+                case K_FSIM: o.type = OP_FSIM; break;
+                case K_U2: o.type = OP_DENSE2; break;
+                case K_RY: case K_H: case K_X: o.type = OP_REAL1; break;
+                case K_RX: o.type = OP_RX; break;
+                default: o.type = OP_DENSE1; break;   // Y, U1
+            }
+            const bool one = o.type == OP_DENSE1 || o.type == OP_REAL1 || o.type == OP_RX;
+            const bool two = o.type == OP_DENSE2 || o.type == OP_FSIM;
+            if ((one && o.r0 < 0) || (o.type == OP_CX && o.r1 < 0) || (two && (o.r0 < 0 || o.r1 < 0)))
+                return "internal: register operand missing";
+            ops.push_back(o);
+        }
+        F.op_end = int(ops.size());
+        phases.push_back(F);
+    }
+    P.phase_end = int(phases.size());
+    return "";
+}
+
 }  // namespace
 
 std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_params, const TileConfig& cfg,
@@ -79,7 +157,8 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
     out.cfg = cfg;
     const int m = std::min(n, cfg.m_max);
     const int lo = std::min(cfg.lo, m);
-    if (m < cfg.rb) return "tile smaller than the register block";
+    if (m < cfg.rb || m < cfg.rb_rev) return "tile smaller than the register block";
+    if (cfg.rb < 1 || cfg.rb > MAX_RB || cfg.rb_rev < 1 || cfg.rb_rev > MAX_RB) return "register block out of range";
     const uint64_t lo_mask = (lo >= 64) ? ~uint64_t(0) : ((uint64_t(1) << lo) - 1);
     const uint64_t all_mask = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
 
@@ -150,77 +229,14 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
         P.n_slots = pass_slots;
         out.total_slots += pass_slots;
 
-        // ---- register phases
-        P.phase_begin = int(out.phases.size());
-        std::vector<int> prem = sel;
-        while (!prem.empty()) {
-            uint32_t R = 0;   // local bits in registers
-            uint64_t blocked = 0;
-            std::vector<int> ph, rest2;
-            for (int gi : prem) {
-                const tcng_gate& g = gates[gi];
-                uint64_t qm = gate_qmask(g);
-                uint32_t need = 0;
-                const int l0 = qubit_to_local[g.q0];
-                const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
-                if (g.kind == K_CNOT) need = 1u << l1;
-                else if (g.kind == K_CZ || g.kind == K_RZZ || kind_diagonal(g.kind)) need = 0;
-                else need = (1u << l0) | (l1 >= 0 ? (1u << l1) : 0u);
-                if (!(qm & blocked) && popc(R | need) <= cfg.rb) {
-                    R |= need;
-                    ph.push_back(gi);
-                } else {
-                    blocked |= qm;
-                    rest2.push_back(gi);
-                }
-            }
-            prem.swap(rest2);
-            // fill the register set to exactly rb bits, preferring high local bits
-            // (keeps consecutive lanes on consecutive LDS addresses)
-            for (int b = m - 1; b >= 0 && popc(R) < cfg.rb; --b) R |= 1u << b;
-            Phase F{};
-            for (int i = 0; i < 6; ++i) F.R[i] = -1;
-            int ri = 0, reg_of_local[MAX_TILE_BITS];
-            for (int b = 0; b < MAX_TILE_BITS; ++b) reg_of_local[b] = -1;
-            for (int b = 0; b < m; ++b)
-                if ((R >> b) & 1) { F.R[ri] = b; reg_of_local[b] = ri; ++ri; }
-            F.op_begin = int(out.ops.size());
-            for (int gi : ph) {
-                const tcng_gate& g = gates[gi];
-                Op o{};
-                o.kind = g.kind;
-                o.p0 = g.p0;
-                o.p1 = g.p1;
-                o.mat = g.mat;
-                o.gate = gi;
-                o.slot = gate_slot_first[gi];
-                const int l0 = qubit_to_local[g.q0];
-                const int l1 = kind_arity(g.kind) == 2 ? qubit_to_local[g.q1] : -1;
-                o.lb0 = l0;
-                o.lb1 = l1;
-                o.r0 = reg_of_local[l0];
-                o.r1 = l1 >= 0 ? reg_of_local[l1] : -1;
-                switch (g.kind) {
-                    case K_RZ: case K_Z: case K_S: o.type = OP_DIAG1; break;
-                    case K_CZ: case K_RZZ: o.type = OP_DIAG2; break;
-                    case K_CNOT: o.type = OP_CX; break;
-                    case K_FSIM: o.type = OP_FSIM; break;
-                    case K_U2: o.type = OP_DENSE2; break;
-                    case K_RY: case K_H: case K_X: o.type = OP_REAL1; break;
-                    case K_RX: o.type = OP_RX; break;
-                    default: o.type = OP_DENSE1; break;   // Y, U1
-                }
-                const bool one = o.type == OP_DENSE1 || o.type == OP_REAL1 || o.type == OP_RX;
-                const bool two = o.type == OP_DENSE2 || o.type == OP_FSIM;
-                if ((one && o.r0 < 0) || (o.type == OP_CX && o.r1 < 0) || (two && (o.r0 < 0 || o.r1 < 0)))
-                    return "internal: register operand missing";
-                out.ops.push_back(o);
-            }
-            F.op_end = int(out.ops.size());
-            out.phases.push_back(F);
-        }
-        P.phase_end = int(out.phases.size());
+        // ---- register phases, forward and reverse block sizes
+        Pass R = P;
+        std::string why = plan_phases(gates, sel, qubit_to_local, m, cfg.rb, gate_slot_first, P, out.phases, out.ops);
+        if (!why.empty()) return why;
+        why = plan_phases(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, R, out.rphases, out.rops);
+        if (!why.empty()) return why;
         out.passes.push_back(P);
+        out.rpasses.push_back(R);
     }
 
     // ---- gradient assembly tables

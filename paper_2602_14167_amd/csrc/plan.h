@@ -11,15 +11,18 @@ namespace tcng {
 
 struct TileConfig {
     int m_max;   // tile bits (2^m amplitudes per tile)
-    int rb;      // register bits per thread (2^rb amplitudes per thread and state)
+    int rb;      // register bits per thread in the forward sweep (2^rb amplitudes per thread)
     int lo;      // low qubits always in the tile (memory-contiguous runs of 2^lo amplitudes)
+    int rb_rev;  // register bits per thread and state in the reverse sweep
 };
 
 struct CircuitPlan {
     TileConfig cfg{};
-    std::vector<Pass> passes;
-    std::vector<Phase> phases;
-    std::vector<Op> ops;
+    // forward sweep (register blocks of 2^rb) and reverse sweep (2^rb_rev):
+    // the same passes (tiles, gates, gradient slots), phased separately
+    std::vector<Pass> passes, rpasses;
+    std::vector<Phase> phases, rphases;
+    std::vector<Op> ops, rops;
     int total_slots = 0;
     // gradient assembly: slots of parameter p are slot_idx[slot_ptr[p] .. slot_ptr[p+1])
     std::vector<int32_t> slot_ptr, slot_idx;

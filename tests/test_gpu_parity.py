@@ -262,3 +262,91 @@ def test_results_are_deterministic(P):
     e1, g1 = P.expect_grad(circ, p, H, batch=8)
     e2, g2 = P.expect_grad(circ, p, H, batch=8)
     assert torch.equal(e1, e2) and torch.equal(g1, g2)
+
+
+def tilings(dtype, n):
+    """Every tiling the library offers for this precision and qubit count."""
+    mmax = 13 if dtype == "c64" else 12
+    rbs = (4, 5) if dtype == "c64" else (3, 4)
+    out = []
+    for m in (mmax - 1, mmax):
+        for rb in rbs:
+            for rr in rbs:
+                if 6 <= m - rb <= 9 and 6 <= m - rr <= 9 and min(n, m) >= max(rb, rr) + 6:
+                    out.append((m, rb, rr))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_every_tiling_matches_oracle(P, oracle_mod, dtype):
+    n = 14
+    r = np.random.default_rng(77)
+    gates, params, mats = W.random_circuit(n, 90, r)
+    codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=3)
+    circ = P.Circuit(n, gates, len(params), W.round_mats(mats, dtype))
+    H = P.PauliSum(n, codes, coeffs)
+    ref = oracle_mod.expect_grad(n, gates, W.round_params(params, dtype), codes, coeffs, W.round_mats(mats, dtype),
+                                 want_lie=True)
+    S = np.abs(coeffs).sum()
+    u2 = np.asarray(gates)[:, 0] == W.U2
+    cfgs = tilings(dtype, n)
+    assert len(cfgs) >= 4
+    for cfg in cfgs:
+        circ.configure(TDT[dtype], *cfg)
+        assert circ.config(TDT[dtype]) == cfg
+        E, g, gl = P.expect_grad(circ, dev(params[None, :], rdt(dtype)), H, dtype=TDT[dtype], want_gate_grad=True)
+        assert abs(E.item() - ref["E"]) <= TOL[dtype]["E"] * S, cfg
+        assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= TOL[dtype]["g"] * S, cfg
+        assert np.max(np.abs(gl.cpu().numpy()[0][u2] - ref["lie"][u2])) <= TOL[dtype]["g"] * S, cfg
+
+
+def test_autotune_picks_an_available_tiling_and_keeps_results(P, oracle_mod, tmp_path):
+    c = W.cfg2(n=15, layers=2)
+    circ = P.Circuit(15, c["gates"], c["n_params"])
+    H = P.PauliSum(15, c["codes"], c["coeffs"])
+    p = dev(c["params"][None, :], torch.float32)
+    psi = P.new_state(15, 1, torch.complex64)
+    cache = str(tmp_path / "tune.txt")
+    cfg, ms = P.autotune(circ, p, H, psi, repeats=2, cache_path=cache)
+    assert cfg in tilings("c64", 15) and ms > 0
+    assert abs(psi[0, 0].item() - 1) < 1e-4          # initial state restored
+    # a second call is answered from the cache file
+    circ2 = P.Circuit(15, c["gates"], c["n_params"])
+    cfg2, ms2 = P.autotune(circ2, p, H, psi, repeats=2, cache_path=cache)
+    assert cfg2 == cfg and ms2 == pytest.approx(ms)
+    ref = oracle_mod.expect_grad(15, c["gates"], W.round_params(c["params"], "c64"), c["codes"], c["coeffs"])
+    E, g = P.expect_grad(circ, p, H)
+    S = np.abs(c["coeffs"]).sum()
+    assert abs(E.item() - ref["E"]) <= 1e-5 * S
+    assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= 1e-4 * S
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_uneven_batch_matches_oracle(P, oracle_mod, dtype):
+    """Different circuits (qubit counts, depths, Hamiltonians; Haar brick-walls
+    and parameterised ansatzes) in one uneven-batch evaluation."""
+    r = np.random.default_rng(90)
+    cs, hs, ps, refs = [], [], [], []
+    c4 = W.cfg4(count=5, n_lo=11, n_hi=15, d_lo=2, d_hi=9, seed=91)
+    for cc in c4["circuits"]:
+        cs.append(P.Circuit(cc["n"], cc["gates"], 0, W.round_mats(cc["mats"], dtype)))
+        hs.append(P.PauliSum(cc["n"], cc["codes"], cc["coeffs"]))
+        ps.append(None)
+        refs.append((cc["n"], cc["gates"], None, cc["codes"], cc["coeffs"], W.round_mats(cc["mats"], dtype)))
+    for n, L in ((12, 2), (15, 3)):
+        w = W.cfg2(n=n, layers=L)
+        cs.append(P.Circuit(n, w["gates"], w["n_params"]))
+        hs.append(P.PauliSum(n, w["codes"], w["coeffs"]))
+        ps.append(dev(w["params"], rdt(dtype)))
+        refs.append((n, w["gates"], W.round_params(w["params"], dtype), w["codes"], w["coeffs"], None))
+    E, grads, ggs = P.expect_grad_multi(cs, hs, ps, dtype=TDT[dtype], want_gate_grad=True)
+    E = E.cpu().numpy()
+    for i, (n, g, pr, codes, coeffs, mats) in enumerate(refs):
+        ref = oracle_mod.expect_grad(n, g, pr, codes, coeffs, mats, want_lie=True)
+        S = np.abs(coeffs).sum()
+        assert abs(E[i] - ref["E"]) <= TOL[dtype]["E"] * S, i
+        if pr is not None:
+            assert np.max(np.abs(grads[i].cpu().numpy() - ref["grad"])) <= TOL[dtype]["g"] * S, i
+        u2 = np.asarray(g)[:, 0] == W.U2
+        if u2.any():
+            assert np.max(np.abs(ggs[i].cpu().numpy()[u2] - ref["lie"][u2])) <= TOL[dtype]["g"] * S, i
