@@ -148,7 +148,7 @@ def run_gate_sweep(args, P, torch, n):
         cases.append(("RZ", [W.gate(W.RZ, q, p0=0)], None))
         cases.append(("CNOT", [W.gate(W.CNOT, q, q + 1)], None))
         mats = W.haar_u4(rng)[None]
-        cases.append(("U2low", [W.gate(W.U2, q + 1, 0 if q > 0 else 1, mat=0)], mats))
+        cases.append(("U2low", [W.gate(W.U2, max(q, 1), 0, mat=0)], mats))
         cases.append(("U2high", [W.gate(W.U2, q, n - 1 if q != n - 1 else n - 2, mat=0)], mats))
     theta = torch.tensor([[0.37]], dtype=torch.float32, device="cuda")
     res = []
