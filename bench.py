@@ -29,6 +29,20 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# FP32 / FP64 vector peak without packed-FP32 instructions (not used by this
+# build): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
+
+# algorithmic flops per amplitude of one gate application (complex
+# arithmetic: multiply 6, add 2; real x complex 2) and of one gradient term
+KIND = {n: i for i, n in enumerate(["RX", "RY", "RZ", "H", "X", "Y", "Z", "S", "CNOT", "CZ", "RZZ", "FSIM", "U1",
+                                    "U2"])}
+APPLY_FLOPS = {"RX": 6, "RY": 6, "RZ": 6, "H": 4, "X": 0, "Y": 0, "Z": 0, "S": 0, "CNOT": 0, "CZ": 0, "RZZ": 6,
+               "FSIM": 4.5, "U1": 14, "U2": 30}
+# Im<l|G|p> per amplitude: RX/RY/RZ/RZZ 4; FSIM theta on half and phi on a
+# quarter of the amplitudes; U2: the 16-entry cotangent, 4 complex MACs per amplitude
+GRAD_FLOPS = {"RX": 4, "RY": 4, "RZ": 4, "RZZ": 4, "FSIM": 3, "U2": 32}
+KIND_NAME = {v: k for k, v in KIND.items()}
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
             "finish", "init"]
 
@@ -72,6 +86,60 @@ def algorithmic_bytes(family, n, s, batch, n_pauli_passes):
     return None
 
 
+def sweep_flops(gates, n, batch, with_u2_grad=False):
+    """(forward, reverse) algorithmic flops of one evaluation: every gate
+    applied once forward; in reverse applied to psi and lambda plus its
+    gradient term."""
+    fwd = rev = 0.0
+    for g in gates:
+        k = KIND_NAME[int(g[0])]
+        a = APPLY_FLOPS[k]
+        grad = GRAD_FLOPS.get(k, 0) if (k != "U2" or with_u2_grad) else 0
+        fwd += a
+        rev += 2 * a + grad
+    amp = float(2 ** n) * batch
+    return fwd * amp, rev * amp
+
+
+def roofline_entry(kernel, flops_per_launch, bytes_per_launch, avg_ms):
+    """Roofline of one kernel family from its average launch: ALU-bound when
+    its arithmetic intensity exceeds the ridge point, HBM-bound otherwise."""
+    t = avg_ms * 1e-3
+    ai = flops_per_launch / bytes_per_launch
+    ridge = ALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    gbs = bytes_per_launch / t / 1e9
+    tfl = flops_per_launch / t / 1e12
+    hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    alu = {"achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(tfl / ALU_PEAK_TFLOPS, 4)}
+    main, other = (alu, hbm) if ai > ridge else (hbm, alu)
+    out = {"bound": "alu" if ai > ridge else "hbm", **main, "traffic": None, "kernel": kernel,
+           "flops_per_launch": flops_per_launch, "bytes_per_launch": bytes_per_launch,
+           "avg_launch_ms": round(avg_ms, 4), "intensity_flop_per_byte": round(ai, 2),
+           "ridge_flop_per_byte": round(ridge, 2), "other_roof": other}
+    return out
+
+
+def copy_ceiling(torch, nbytes):
+    """Measured device-to-device copy rate (read + write bytes per second) of
+    torch's copy kernel on a buffer of the state's size."""
+    n = max(nbytes // 4, 1)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes": 2 * n * 4, "avg_ms": round(ms, 4), "GB_s": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
+
+
 def run_uneven(args, w, P, torch):
     """The uneven batch (1024 Haar brick-wall circuits of 12..22 qubits): one
     step = value and Lie-algebra gate gradients of every circuit."""
@@ -113,14 +181,13 @@ def run_uneven(args, w, P, torch):
         P.check(P.lib().tcng_profile_end())
     G = sum(len(c["gates"]) for c in cs)
     amp = sum(3.0 * len(c["gates"]) * 2 ** c["n"] for c in cs)
-    # algorithmic bytes of the reverse sweep (dominant) over one step: 4 * 2^n * 8 per pass per circuit
+    # algorithmic bytes and flops of the reverse sweep (dominant) over one step
     rev_bytes = sum(c2.num_passes() * 4 * 8 * 2 ** c["n"] for c, c2 in zip(cs, circs))
+    rev_flops = sum(sweep_flops(c["gates"], c["n"], 1, with_u2_grad=True)[1] for c in cs)
     roofline = None
     if "rev_tile" in fam:
-        achieved = rev_bytes * args.steps / (fam["rev_tile"]["total_ms"] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "rev_tile",
-                    "bytes_per_step": rev_bytes, "launches_per_step": fam["rev_tile"]["launches"] / args.steps}
+        L = fam["rev_tile"]["launches"] / args.steps
+        roofline = roofline_entry("rev_tile", rev_flops / L, rev_bytes / L, fam["rev_tile"]["avg_ms"])
     return {
         "metric": "amplitude-updates/s", "value": amp / dt, "unit": "amplitude-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -217,7 +284,7 @@ def main():
     ap.add_argument("--mode", default="tiled", choices=["tiled", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick the tiling by timed search first")
     ap.add_argument("--tiling", default=None, help="m,rb,rb_rev (skips the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -240,9 +307,10 @@ def main():
         print(json.dumps(out), flush=True)
         return
     n, G, B = w["n"], len(w["gates"]), int(w.get("batch", 1))
+    s = 8 if args.dtype == "c64" else 16
+    copy = copy_ceiling(torch, (2 ** n) * s * B)
     cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
     rdt = torch.float32 if args.dtype == "c64" else torch.float64
-    s = 8 if args.dtype == "c64" else 16
     circ = P.Circuit(n, w["gates"], w["n_params"], w.get("mats"))
     H = P.PauliSum(n, w["codes"], w["coeffs"])
     params = torch.tensor(np.asarray(w["params"]).reshape(B, -1), dtype=rdt, device="cuda")
@@ -252,7 +320,7 @@ def main():
     tuned = None
     if args.mode == "tiled" and args.tiling:
         circ.configure(cdt, *[int(v) for v in args.tiling.split(",")])
-    elif args.mode == "tiled" and not args.no_autotune:
+    elif args.mode == "tiled" and args.autotune:
         P.state_init(psi)
         cfg, tms = P.autotune(circ, params, H, psi, lam, repeats=3,
                               cache_path=os.path.join(os.environ.get("TMPDIR", "/tmp"), "tcng_autotune.txt"))
@@ -291,19 +359,17 @@ def main():
 
     amp_updates = 3.0 * G * (2 ** n) * B
     value = amp_updates / dt
-    n_pauli = 0
-    if "pauli_tile" in fam_stats:
-        n_pauli = fam_stats["pauli_tile"]["launches"] // args.steps
+    fwd_flops, rev_flops = sweep_flops(w["gates"], n, B)
     roofline = None
-    if fam_stats:
-        dom = max((k for k in fam_stats if algorithmic_bytes(k, n, s, B, n_pauli) is not None),
-                  key=lambda k: fam_stats[k]["total_ms"], default=None)
-        if dom is not None:
-            ab = algorithmic_bytes(dom, n, s, B, n_pauli)
-            achieved = ab / (fam_stats[dom]["avg_ms"] * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                        "bytes_per_launch": ab, "avg_launch_ms": round(fam_stats[dom]["avg_ms"], 4)}
+    if args.mode == "tiled" and "rev_tile" in fam_stats:
+        dom = max(("fwd_tile", "rev_tile"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
+        L = fam_stats[dom]["launches"] / args.steps
+        flops = (rev_flops if dom == "rev_tile" else fwd_flops) / L
+        nbytes = algorithmic_bytes(dom, n, s, B, 0)
+        roofline = roofline_entry(dom, flops, nbytes, fam_stats[dom]["avg_ms"])
+    elif fam_stats:
+        dom = max(fam_stats, key=lambda k: fam_stats[k]["total_ms"])
+        roofline = {"bound": "hbm", "kernel": dom, "note": "plain per-gate path"}
 
     out = {
         "metric": "amplitude-updates/s",
@@ -325,6 +391,7 @@ def main():
         "autotune": tuned,
         "energy0": float(E[0].item()),
         "roofline": roofline,
+        "copy_ceiling": copy,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}
                     for k, v in fam_stats.items()},
     }

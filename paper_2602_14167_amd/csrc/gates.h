@@ -257,18 +257,31 @@ __device__ __forceinline__ double re_conj_mul(cx<R> l, cx<R> p) {
     return fma(double(l.re), double(p.re), double(l.im) * double(p.im));
 }
 
+// Gradient partial sums of one thread (2^RB products) are accumulated in the
+// state's precision R and widened to float64 for the wave / workgroup / tile
+// sums.  For complex64 the relative rounding of a thread's partial is at most
+// about 2^RB * 2^-24 of the sum of its terms' magnitudes (< 2e-6), far below
+// the float32 state's own error.
+
 // dE/dt contribution of RX / RY on register bit B:  Im <l| P |p>
 template <typename R, int NB, int B>
-__device__ __forceinline__ double grad_rot1(int kind, Regs<R, NB> l, Regs<R, NB> p) {
-    double g = 0.0;
+__device__ __forceinline__ R grad_rot1(int kind, Regs<R, NB> l, Regs<R, NB> p) {
+    R g = R(0);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         if (j & (1 << B)) continue;
         const int j1 = j | (1 << B);
-        if (kind == K_RX) {   // X: (Xp)_0 = p_1, (Xp)_1 = p_0
-            g += im_conj_mul(l.v[j], p.v[j1]) + im_conj_mul(l.v[j1], p.v[j]);
-        } else {              // Y: (Yp)_0 = -i p_1, (Yp)_1 = i p_0;  Im(-i z) = -Re z
-            g += re_conj_mul(l.v[j1], p.v[j]) - re_conj_mul(l.v[j], p.v[j1]);
+        const cx<R> l0 = l.v[j], l1 = l.v[j1], p0 = p.v[j], p1 = p.v[j1];
+        if (kind == K_RX) {   // X: (Xp)_0 = p_1, (Xp)_1 = p_0:  Im(conj(l0) p1) + Im(conj(l1) p0)
+            g = fmaR(l0.re, p1.im, g);
+            g = fmaR(-l0.im, p1.re, g);
+            g = fmaR(l1.re, p0.im, g);
+            g = fmaR(-l1.im, p0.re, g);
+        } else {              // Y: (Yp)_0 = -i p_1, (Yp)_1 = i p_0:  Re(conj(l1) p0) - Re(conj(l0) p1)
+            g = fmaR(l1.re, p0.re, g);
+            g = fmaR(l1.im, p0.im, g);
+            g = fmaR(-l0.re, p1.re, g);
+            g = fmaR(-l0.im, p1.im, g);
         }
     }
     return g;
@@ -276,47 +289,56 @@ __device__ __forceinline__ double grad_rot1(int kind, Regs<R, NB> l, Regs<R, NB>
 
 // RZ / RZZ: sum_j sign_j Im(conj(l_j) p_j), sign = (-1)^{bit} resp. (-1)^{b0 ^ b1}
 template <typename R, int NB>
-__device__ __forceinline__ double grad_zdiag(Regs<R, NB> l, Regs<R, NB> p, int r0, int tb0, int r1, int tb1) {
-    double g = 0.0;
+__device__ __forceinline__ R grad_zdiag(Regs<R, NB> l, Regs<R, NB> p, int r0, int tb0, int r1, int tb1) {
+    R gp = R(0), gm = R(0);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int b0 = r0 >= 0 ? ((j >> r0) & 1) : tb0;
         const int b1 = r1 >= 0 ? ((j >> r1) & 1) : tb1;
-        const double v = im_conj_mul(l.v[j], p.v[j]);
-        g += (b0 ^ b1) ? -v : v;
+        const R v = fmaR(l.v[j].re, p.v[j].im, -l.v[j].im * p.v[j].re);
+        if (b0 ^ b1) gm += v;
+        else gp += v;
     }
-    return g;
+    return gp - gm;
 }
 
 // FSIM: theta -> 2 Im(conj(l01) p10 + conj(l10) p01), phi -> 2 Im(conj(l11) p11)
 template <typename R, int NB, int B0, int B1>
-__device__ __forceinline__ double2 grad_fsim(Regs<R, NB> l, Regs<R, NB> p) {
-    double gt = 0.0, gp = 0.0;
+__device__ __forceinline__ void grad_fsim(Regs<R, NB> l, Regs<R, NB> p, R& gt, R& gp) {
+    gt = R(0);
+    gp = R(0);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
         const int i1 = j | (1 << B1), i2 = j | (1 << B0), i3 = j | (1 << B0) | (1 << B1);
-        gt += 2.0 * (im_conj_mul(l.v[i1], p.v[i2]) + im_conj_mul(l.v[i2], p.v[i1]));
-        gp += 2.0 * im_conj_mul(l.v[i3], p.v[i3]);
+        gt = fmaR(l.v[i1].re, p.v[i2].im, gt);
+        gt = fmaR(-l.v[i1].im, p.v[i2].re, gt);
+        gt = fmaR(l.v[i2].re, p.v[i1].im, gt);
+        gt = fmaR(-l.v[i2].im, p.v[i1].re, gt);
+        gp = fmaR(l.v[i3].re, p.v[i3].im, gp);
+        gp = fmaR(-l.v[i3].im, p.v[i3].re, gp);
     }
-    return make_double2(gt, gp);
+    gt *= R(2);
+    gp *= R(2);
 }
 
 // U2 cotangent entry (a, b): sum over quads of lambda_a conj(phi_b)
 // (phi = state before the gate), real and imaginary part
 template <typename R, int NB, int B0, int B1>
-__device__ __forceinline__ double2 cot_u2(Regs<R, NB> l, Regs<R, NB> f, int a, int b) {
-    double re = 0.0, im = 0.0;
+__device__ __forceinline__ void cot_u2(Regs<R, NB> l, Regs<R, NB> f, int a, int b, R& re, R& im) {
+    re = R(0);
+    im = R(0);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
         const int i1 = j | (1 << B1), i2 = j | (1 << B0), i3 = j | (1 << B0) | (1 << B1);
         const cx<R> la = sel(a == 0, l.v[j], sel(a == 1, l.v[i1], sel(a == 2, l.v[i2], l.v[i3])));
         const cx<R> fb = sel(b == 0, f.v[j], sel(b == 1, f.v[i1], sel(b == 2, f.v[i2], f.v[i3])));
-        re += fma(double(la.re), double(fb.re), double(la.im) * double(fb.im));
-        im += fma(double(la.im), double(fb.re), -double(la.re) * double(fb.im));
+        re = fmaR(la.re, fb.re, re);
+        re = fmaR(la.im, fb.im, re);
+        im = fmaR(la.im, fb.re, im);
+        im = fmaR(-la.re, fb.im, im);
     }
-    return make_double2(re, im);
 }
 
 }  // namespace tcng

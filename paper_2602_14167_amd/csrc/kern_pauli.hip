@@ -12,7 +12,7 @@
 // (deterministic); the partial sums go to `epart` for a final fixed-order sum.
 // Measurement parallelism over terms (Sec. "Data Parallelism") is realised on
 // one GPU as parallelism over amplitudes with all terms of a group fused.
-#include "kernels.h"
+#include "devutil.h"
 
 namespace tcng {
 
@@ -44,7 +44,7 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t tile, uint64_t tmask, int
     return base;
 }
 
-__device__ __forceinline__ double wave_sum(double v, int width) {
+__device__ __forceinline__ double shfl_sum(double v, int width) {
     for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
     return v;
 }
@@ -52,7 +52,7 @@ __device__ __forceinline__ double wave_sum(double v, int width) {
 // fixed-order workgroup sum of one double per thread (result valid in thread 0)
 __device__ double block_sum(double v, double* sh, int nthreads) {
     const int width = nthreads < 64 ? nthreads : 64;
-    v = wave_sum(v, width);
+    v = width == 64 ? wave_sum(v) : shfl_sum(v, width);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
     if (lane == 0) sh[wave] = v;
@@ -66,21 +66,6 @@ __device__ double block_sum(double v, double* sh, int nthreads) {
 // ---------------------------------------------------------------------------
 // tiled: one pass handles every X-group whose mask lies inside its tile
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ const Job& find_job(const JobList& jl, const Job& single, int64_t blk, int64_t& local) {
-    if (!jl.jobs) {
-        local = blk;
-        return single;
-    }
-    int lo = 0, hi = jl.njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jl.prefix[mid] <= blk) lo = mid;
-        else hi = mid - 1;
-    }
-    local = blk - jl.prefix[lo];
-    return jl.jobs[lo];
-}
-
 template <typename R, int RB>
 __global__ void __launch_bounds__(NTHREADS)
 k_pauli_tile(const JobList jl, const Job single) {
@@ -88,29 +73,30 @@ k_pauli_tile(const JobList jl, const Job single) {
     __shared__ double sh[NTHREADS / 64];
     constexpr int NB = 1 << RB;
     int64_t local;
-    const Job& J = find_job(jl, single, blockIdx.x, local);
+    const Job J = load_job(jl, single, blockIdx.x, local);
     const int pass_idx = jl.step;
-    const PPass* passes = J.ppasses;
-    const PGroup* __restrict__ groups = J.pgroups;
-    const PClass* __restrict__ classes = J.pclasses;
-    const PTerm* __restrict__ terms = J.pterms;
+    cptr<PGroup> groups = as_const(J.pgroups);
+    cptr<PClass> classes = as_const(J.pclasses);
+    cptr<PTerm> terms = as_const(J.pterms);
     const int accumulate = pass_idx > 0;
     const int wgs = J.e_wgs;
     const int n = J.n;
     const int64_t b = local / wgs;
     const int wg = int(local - b * wgs);
-    const PPass& P = passes[pass_idx];
-    const int m = P.m, lo = P.lo;
-    const uint64_t tmask = P.tile_mask;
+    cptr<PPass> P = as_const(J.ppasses) + pass_idx;
+    const int m = P->m, lo = P->lo;
+    const uint64_t tmask = P->tile_mask;
     int lq[MAX_TILE_BITS];
 #pragma unroll
-    for (int i = 0; i < MAX_TILE_BITS; ++i) lq[i] = P.local_qubit[i];
+    for (int i = 0; i < MAX_TILE_BITS; ++i) lq[i] = P->local_qubit[i];
     const int nt = 1 << (m - RB);
     const int64_t tiles_per_state = int64_t(1) << (n - m);
     const int t = threadIdx.x;
-    const bool active = t < nt;
-    const cx<R>* psi = static_cast<const cx<R>*>(J.state) + b * J.stride;
-    cx<R>* lam = J.costate ? static_cast<cx<R>*>(J.costate) + b * J.stride : nullptr;
+    // nt is a multiple of 64: whole waves are active or idle
+    const bool active = uniform(t >> 6) < (nt >> 6);
+    gptr<const cx<R>> psi = as_global(static_cast<const cx<R>*>(J.state)) + b * J.stride;
+    gptr<cx<R>> lam = as_global(J.costate ? static_cast<cx<R>*>(J.costate) : nullptr) + (J.costate ? b * J.stride : 0);
+    const bool has_lam = J.costate != nullptr;
     double e_acc = 0.0;
 
     for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
@@ -134,9 +120,10 @@ k_pauli_tile(const JobList jl, const Job single) {
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const uint32_t l = uint32_t((c0 + i) * nt + t);
-                acc[i] = (lam && accumulate) ? lam[base + loc2glob(l, lo, m, lq)] : cx<R>{R(0), R(0)};
+                acc[i] = (has_lam && accumulate) ? lam[base + loc2glob(l, lo, m, lq)] : cx<R>{R(0), R(0)};
             }
-            for (int g = P.group_begin; g < P.group_end; ++g) {
+            const int g_end = P->group_end;
+            for (int g = P->group_begin; g < g_end; ++g) {
                 const PGroup G = groups[g];
                 double cre[CH], cim[CH];
 #pragma unroll
@@ -178,7 +165,7 @@ k_pauli_tile(const JobList jl, const Job single) {
                     e_acc += cre[i] * rr - cim[i] * ri;
                 }
             }
-            if (lam) {
+            if (has_lam) {
 #pragma unroll
                 for (int i = 0; i < CH; ++i)
                     lam[base + loc2glob(uint32_t((c0 + i) * nt + t), lo, m, lq)] = acc[i];

@@ -15,8 +15,8 @@
 // back through the circuit, evaluates each angle's derivative
 // 2 Im <lambda|G|psi> in float64 and un-computes both by applying inverse
 // gates (adjoint method: nothing is stored per gate).
+#include "devutil.h"
 #include "gates.h"
-#include "kernels.h"
 
 namespace tcng {
 
@@ -69,24 +69,24 @@ struct V16;
 template <>
 struct V16<float> {
     static constexpr int N = 2;
-    __device__ static void load(const cx<float>* p, cx<float>* o) {
-        float4 v = *reinterpret_cast<const float4*>(p);
+    __device__ static void load(gptr<const cx<float>> p, cx<float>* o) {
+        float4 v = *reinterpret_cast<gptr<const float4>>(p);
         o[0] = {v.x, v.y};
         o[1] = {v.z, v.w};
     }
-    __device__ static void store(cx<float>* p, const cx<float>* o) {
-        *reinterpret_cast<float4*>(p) = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
+    __device__ static void store(gptr<cx<float>> p, const cx<float>* o) {
+        *reinterpret_cast<gptr<float4>>(p) = make_float4(o[0].re, o[0].im, o[1].re, o[1].im);
     }
 };
 template <>
 struct V16<double> {
     static constexpr int N = 1;
-    __device__ static void load(const cx<double>* p, cx<double>* o) {
-        double2 v = *reinterpret_cast<const double2*>(p);
+    __device__ static void load(gptr<const cx<double>> p, cx<double>* o) {
+        double2 v = *reinterpret_cast<gptr<const double2>>(p);
         o[0] = {v.x, v.y};
     }
-    __device__ static void store(cx<double>* p, const cx<double>* o) {
-        *reinterpret_cast<double2*>(p) = make_double2(o[0].re, o[0].im);
+    __device__ static void store(gptr<cx<double>> p, const cx<double>* o) {
+        *reinterpret_cast<gptr<double2>>(p) = make_double2(o[0].re, o[0].im);
     }
 };
 
@@ -96,19 +96,19 @@ struct PassInfo {
     int lq[MAX_TILE_BITS];   // local bit -> qubit (uniform: scalar registers)
 };
 
-__device__ __forceinline__ PassInfo read_pass(const Pass& P) {
+__device__ __forceinline__ PassInfo read_pass(cptr<Pass> P) {
     PassInfo pi;
-    pi.m = P.m;
-    pi.lo = P.lo;
-    pi.tmask = P.tile_mask;
+    pi.m = P->m;
+    pi.lo = P->lo;
+    pi.tmask = P->tile_mask;
 #pragma unroll
-    for (int i = 0; i < MAX_TILE_BITS; ++i) pi.lq[i] = P.local_qubit[i];
+    for (int i = 0; i < MAX_TILE_BITS; ++i) pi.lq[i] = P->local_qubit[i];
     return pi;
 }
 
 // HBM -> LDS (coalesced: lane-consecutive 16-byte chunks of local index space)
 template <typename R, int RB>
-__device__ __forceinline__ void tile_load(cx<R>* lds, const cx<R>* psi, uint64_t base, const PassInfo& pi, int t,
+__device__ __forceinline__ void tile_load(cx<R>* lds, gptr<const cx<R>> psi, uint64_t base, const PassInfo& pi, int t,
                                           int nt) {
     constexpr int VN = V16<R>::N;
     const int iters = (1 << RB) / VN;
@@ -129,7 +129,7 @@ __device__ __forceinline__ void tile_load(cx<R>* lds, const cx<R>* psi, uint64_t
 }
 
 template <typename R, int RB>
-__device__ __forceinline__ void tile_store(const cx<R>* lds, cx<R>* psi, uint64_t base, const PassInfo& pi, int t,
+__device__ __forceinline__ void tile_store(const cx<R>* lds, gptr<cx<R>> psi, uint64_t base, const PassInfo& pi, int t,
                                            int nt) {
     constexpr int VN = V16<R>::N;
     const int iters = (1 << RB) / VN;
@@ -145,22 +145,25 @@ __device__ __forceinline__ void tile_store(const cx<R>* lds, cx<R>* psi, uint64_
     }
 }
 
-// register <-> LDS for a phase
+// register <-> LDS for a phase.  The swizzle is linear over XOR and the
+// thread part and register part of a local index have disjoint bits, so
+// swz(tpart | jpart) = swz(tpart) ^ swz(jpart): one per-lane term and one
+// uniform term per register.
 struct PhaseMap {
-    uint32_t tpart;
+    uint32_t tpart;   // thread's bits of the local index (per lane)
+    uint32_t tsw;     // swz(tpart)
     uint32_t rbit[MAX_RB];
 };
 
 template <int RB>
-__device__ __forceinline__ PhaseMap phase_map(const Phase& F, int t, int m) {
+__device__ __forceinline__ PhaseMap phase_map(cptr<Phase> F, int t, int m) {
     PhaseMap pm;
     uint32_t rmask = 0;
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-        pm.rbit[i] = 1u << F.R[i];
+        pm.rbit[i] = 1u << F->R[i];
         rmask |= pm.rbit[i];
     }
-    // (F.R is read with scalar loads: 32-bit fields)
     // deposit the thread index into the non-register local bits
     uint32_t tp = 0;
     int k = 0;
@@ -170,6 +173,7 @@ __device__ __forceinline__ PhaseMap phase_map(const Phase& F, int t, int m) {
         ++k;
     }
     pm.tpart = tp;
+    pm.tsw = swz(tp);
     return pm;
 }
 
@@ -186,13 +190,13 @@ template <typename R, int RB>
 __device__ __forceinline__ Regs<R, (1 << RB)> regs_from_lds(const cx<R>* lds, const PhaseMap& pm) {
     Regs<R, (1 << RB)> a;
 #pragma unroll
-    for (int j = 0; j < (1 << RB); ++j) a.v[j] = lds[swz(pm.tpart | jpart<RB>(pm, j))];
+    for (int j = 0; j < (1 << RB); ++j) a.v[j] = lds[pm.tsw ^ swz(jpart<RB>(pm, j))];
     return a;
 }
 template <typename R, int RB>
 __device__ __forceinline__ void regs_to_lds(Regs<R, (1 << RB)> a, cx<R>* lds, const PhaseMap& pm) {
 #pragma unroll
-    for (int j = 0; j < (1 << RB); ++j) lds[swz(pm.tpart | jpart<RB>(pm, j))] = a.v[j];
+    for (int j = 0; j < (1 << RB); ++j) lds[pm.tsw ^ swz(jpart<RB>(pm, j))] = a.v[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -283,8 +287,8 @@ __device__ __forceinline__ Regs<R, (1 << RB)> fsim_at(Regs<R, (1 << RB)> a, int 
     return a;
 }
 template <typename R, int RB>
-__device__ __forceinline__ double grad_rot1_at(int kind, int r, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
-    double g = 0.0;
+__device__ __forceinline__ R grad_rot1_at(int kind, int r, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
+    R g = R(0);
     switch (r) {
 #define C1(B) case B: if constexpr (B < RB) g = grad_rot1<R, (1 << RB), B>(kind, l, p); break;
         TCNG_SINGLES(C1)
@@ -294,33 +298,35 @@ __device__ __forceinline__ double grad_rot1_at(int kind, int r, Regs<R, (1 << RB
     return g;
 }
 template <typename R, int RB>
-__device__ __forceinline__ double2 grad_fsim_at(int r0, int r1, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
-    double2 g = make_double2(0.0, 0.0);
+__device__ __forceinline__ void grad_fsim_at(int r0, int r1, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p, R& gt,
+                                             R& gp) {
+    gt = R(0);
+    gp = R(0);
     switch (r0 * 8 + r1) {
-#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) g = grad_fsim<R, (1 << RB), B0, B1>(l, p); break;
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) grad_fsim<R, (1 << RB), B0, B1>(l, p, gt, gp); break;
         TCNG_PAIRS(C2)
 #undef C2
         default: break;
     }
-    return g;
 }
 template <typename R, int RB>
-__device__ __forceinline__ double2 cot_u2_at(int r0, int r1, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> f, int a, int b) {
-    double2 g = make_double2(0.0, 0.0);
+__device__ __forceinline__ void cot_u2_at(int r0, int r1, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> f, int a, int b,
+                                          R& re, R& im) {
+    re = R(0);
+    im = R(0);
     switch (r0 * 8 + r1) {
-#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) g = cot_u2<R, (1 << RB), B0, B1>(l, f, a, b); break;
+#define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) cot_u2<R, (1 << RB), B0, B1>(l, f, a, b, re, im); break;
         TCNG_PAIRS(C2)
 #undef C2
         default: break;
     }
-    return g;
 }
 
 // apply one op (forward, or its inverse when INV) to the register block;
 // om: the op's matrix entries for this batch member (k_build_ops)
 template <typename R, int RB, bool INV>
 __device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, const Op& op, uint32_t tpart,
-                                                      const cx<R>* __restrict__ om) {
+                                                      cptr<cx<R>> om) {
     const int tb0 = op.lb0 >= 0 ? int((tpart >> op.lb0) & 1) : 0;
     const int tb1 = op.lb1 >= 0 ? int((tpart >> op.lb1) & 1) : 0;
     switch (op.type) {
@@ -345,13 +351,15 @@ __device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, con
         }
         case OP_FSIM: {
             const R c = om[5].re, s = -om[6].im;
-            const cx<R> ph = INV ? conj(om[15]) : om[15];
+            const cx<R> w = om[15];
+            const cx<R> ph = INV ? conj(w) : w;
             a = fsim_at<R, RB>(a, op.r0, op.r1, c, INV ? -s : s, ph);
             break;
         }
         case OP_DIAG1: {
-            const cx<R> d0 = INV ? conj(om[0]) : om[0];
-            const cx<R> d1 = INV ? conj(om[1]) : om[1];
+            const cx<R> w0 = om[0], w1 = om[1];
+            const cx<R> d0 = INV ? conj(w0) : w0;
+            const cx<R> d1 = INV ? conj(w1) : w1;
             if (op.r0 >= 0) {
                 a = diag1r_at<R, RB>(a, op.r0, d0, d1);
             } else {
@@ -378,7 +386,10 @@ __device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, con
         default: {   // OP_DIAG2
             D4<R> d;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) d.e[i] = INV ? conj(om[i]) : om[i];
+            for (int i = 0; i < 4; ++i) {
+                const cx<R> w = om[i];
+                d.e[i] = INV ? conj(w) : w;
+            }
             a = app_diag<R, (1 << RB)>(a, op.r0, tb0, op.r1, tb1, true, d);
             break;
         }
@@ -434,30 +445,6 @@ __global__ void k_build_ops_multi(const BuildJob* __restrict__ jobs, const int64
                 static_cast<cx<R>*>(B.opm));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// ---------------------------------------------------------------------------
-// job lookup: block -> (job, member, tile or workgroup index)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ const Job& find_job(const JobList& jl, const Job& single, int64_t blk, int64_t& local) {
-    if (!jl.jobs) {
-        local = blk;
-        return single;
-    }
-    int lo = 0, hi = jl.njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jl.prefix[mid] <= blk) lo = mid;
-        else hi = mid - 1;
-    }
-    local = blk - jl.prefix[lo];
-    return jl.jobs[lo];
-}
-
 // ---------------------------------------------------------------------------
 // forward pass: one tile per workgroup.  Waves beyond the job's tile size
 // (2^(m - RB) threads; jobs of one launch may differ in m) take part in the
@@ -468,28 +455,32 @@ __global__ void __launch_bounds__((MaxThreads<R, RB>::value))
 k_tile_fwd(const JobList jl, const Job single) {
     __shared__ cx<R> lds[Tile<R>::ELEMS];
     int64_t local;
-    const Job& J = find_job(jl, single, blockIdx.x, local);
-    const Pass& P = J.passes[jl.step];
+    const Job J = load_job(jl, single, blockIdx.x, local);
+    cptr<Pass> P = as_const(J.passes) + jl.step;
     const PassInfo pi = read_pass(P);
     const int nt = 1 << (pi.m - RB);
     const int t = threadIdx.x;
-    const bool active = t < nt;
+    // nt is a multiple of 64: whole waves are active or idle
+    const bool active = uniform(t >> 6) < (nt >> 6);
     const int64_t b = local / J.tiles;
     const uint64_t tile = uint64_t(local - b * J.tiles);
     const int n = J.n;
-    cx<R>* psi = static_cast<cx<R>*>(J.state) + b * J.stride;
-    const cx<R>* om = static_cast<const cx<R>*>(J.opm) + size_t(b) * J.n_gates * 16;
+    gptr<cx<R>> psi = as_global(static_cast<cx<R>*>(J.state)) + b * J.stride;
+    cptr<cx<R>> om = as_const(static_cast<const cx<R>*>(J.opm)) + size_t(b) * J.n_gates * 16;
+    cptr<Phase> phases = as_const(J.phases);
+    cptr<Op> ops = as_const(J.ops);
     const uint64_t base = tile_base(tile, pi.tmask, n);
+    const int f_end = P->phase_end;
 
     if (active) tile_load<R, RB>(lds, psi, base, pi, t, nt);
     __syncthreads();
-    for (int f = P.phase_begin; f < P.phase_end; ++f) {
+    for (int f = P->phase_begin; f < f_end; ++f) {
         if (active) {
-            const Phase& F = J.phases[f];
-            const PhaseMap pm = phase_map<RB>(F, t, pi.m);
+            const PhaseMap pm = phase_map<RB>(phases + f, t, pi.m);
             Regs<R, (1 << RB)> a = regs_from_lds<R, RB>(lds, pm);
-            for (int o = F.op_begin; o < F.op_end; ++o) {
-                const Op& op = J.ops[o];
+            const int o_end = phases[f].op_end;
+            for (int o = phases[f].op_begin; o < o_end; ++o) {
+                const Op op = ops[o];
                 a = apply_op<R, RB, false>(a, op, pm.tpart, om + 16 * op.gate);
             }
             regs_to_lds<R, RB>(a, lds, pm);
@@ -497,6 +488,13 @@ k_tile_fwd(const JobList jl, const Job single) {
         __syncthreads();
     }
     if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt);
+}
+
+// accumulate a thread's gradient partial into the wave's slot (float64)
+template <typename R>
+__device__ __forceinline__ void red_add(double* red, int idx, R v, int lane) {
+    const double s = wave_sum(double(v));
+    if (lane == 0) red[idx] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -510,23 +508,26 @@ k_tile_rev(const JobList jl, const Job single) {
     __shared__ double red[RED_SLOTS * (NTHREADS / 64)];
     using Blk = Regs<R, (1 << RB)>;
     int64_t local;
-    const Job& J = find_job(jl, single, blockIdx.x, local);
+    const Job J = load_job(jl, single, blockIdx.x, local);
     const int pidx = J.n_passes - 1 - jl.step;
-    const Pass& P = J.rpasses[pidx];
+    cptr<Pass> P = as_const(J.rpasses) + pidx;
     const PassInfo pi = read_pass(P);
     const int nt = 1 << (pi.m - RB);
-    const int nwaves = (nt + 63) / 64;
+    const int nwaves = nt >> 6;
     const int t = threadIdx.x;
-    const bool active = t < nt;
-    const int wave = t >> 6, lane = t & 63;
+    const int wave = uniform(t >> 6), lane = t & 63;
+    const bool active = wave < nwaves;
     const int wgs = J.wgs;
     const int64_t b = local / wgs;
     const int wg = int(local - b * wgs);
     const int n = J.n;
-    cx<R>* psi = static_cast<cx<R>*>(J.state) + b * J.stride;
-    cx<R>* lam = static_cast<cx<R>*>(J.costate) + b * J.stride;
-    const cx<R>* om = static_cast<const cx<R>*>(J.opm) + size_t(b) * J.n_gates * 16;
-    const int nslots = P.n_slots;
+    gptr<cx<R>> psi = as_global(static_cast<cx<R>*>(J.state)) + b * J.stride;
+    gptr<cx<R>> lam = as_global(static_cast<cx<R>*>(J.costate)) + b * J.stride;
+    cptr<cx<R>> om = as_const(static_cast<const cx<R>*>(J.opm)) + size_t(b) * J.n_gates * 16;
+    cptr<Phase> rphases = as_const(J.rphases);
+    cptr<Op> rops = as_const(J.rops);
+    const int nslots = P->n_slots;
+    const int f_begin = P->phase_begin, f_last = P->phase_end - 1;
 
     for (int i = t; i < nslots * nwaves; i += blockDim.x) red[i] = 0.0;
     // (the first __syncthreads below orders these writes before any accumulation)
@@ -534,8 +535,8 @@ k_tile_rev(const JobList jl, const Job single) {
     for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), pi.tmask, n);
         // phases run backwards; psi and lambda take turns in the one LDS tile
-        int f = P.phase_end - 1;
-        PhaseMap pm = phase_map<RB>(J.rphases[f], t, pi.m);
+        int f = f_last;
+        PhaseMap pm = phase_map<RB>(rphases + f, t, pi.m);
         Blk ps, la;
         __syncthreads();
         if (active) tile_load<R, RB>(lds, psi, base, pi, t, nt);
@@ -546,50 +547,45 @@ k_tile_rev(const JobList jl, const Job single) {
         __syncthreads();
         if (active) la = regs_from_lds<R, RB>(lds, pm);
         for (;;) {
-            const Phase& F = J.rphases[f];
             if (active) {
-                for (int o = F.op_end - 1; o >= F.op_begin; --o) {
-                    const Op op = J.rops[o];
-                    const cx<R>* m16 = om + 16 * op.gate;
+                const int o_begin = rphases[f].op_begin;
+                for (int o = rphases[f].op_end - 1; o >= o_begin; --o) {
+                    const Op op = rops[o];
+                    cptr<cx<R>> m16 = om + 16 * op.gate;
+                    const int slot = op.slot * nwaves + wave;
                     if (op.slot >= 0 && op.kind != K_U2) {
-                        double g0 = 0.0, g1 = 0.0;
                         if (op.kind == K_RX || op.kind == K_RY) {
-                            g0 = grad_rot1_at<R, RB>(op.kind, op.r0, la, ps);
+                            red_add(red, slot, grad_rot1_at<R, RB>(op.kind, op.r0, la, ps), lane);
                         } else if (op.kind == K_FSIM) {
-                            const double2 g = grad_fsim_at<R, RB>(op.r0, op.r1, la, ps);
-                            g0 = g.x;
-                            g1 = g.y;
+                            R gt, gp;
+                            grad_fsim_at<R, RB>(op.r0, op.r1, la, ps, gt, gp);
+                            red_add(red, slot, gt, lane);
+                            red_add(red, slot + nwaves, gp, lane);
                         } else {                            // RZ, RZZ
                             const int tb0 = op.lb0 >= 0 ? int((pm.tpart >> op.lb0) & 1) : 0;
                             const int tb1 = op.lb1 >= 0 ? int((pm.tpart >> op.lb1) & 1) : 0;
-                            g0 = grad_zdiag<R, (1 << RB)>(la, ps, op.r0, tb0, op.type == OP_DIAG2 ? op.r1 : -1,
-                                                          op.type == OP_DIAG2 ? tb1 : 0);
-                        }
-                        g0 = wave_sum(g0);
-                        if (lane == 0) red[op.slot * nwaves + wave] += g0;
-                        if (op.kind == K_FSIM) {
-                            g1 = wave_sum(g1);
-                            if (lane == 0) red[(op.slot + 1) * nwaves + wave] += g1;
+                            red_add(red, slot,
+                                    grad_zdiag<R, (1 << RB)>(la, ps, op.r0, tb0, op.type == OP_DIAG2 ? op.r1 : -1,
+                                                             op.type == OP_DIAG2 ? tb1 : 0),
+                                    lane);
                         }
                     }
                     ps = apply_op<R, RB, true>(ps, op, pm.tpart, m16);
                     if (op.kind == K_U2 && op.slot >= 0) {
 #pragma unroll
                         for (int e = 0; e < 16; ++e) {
-                            const double2 g = cot_u2_at<R, RB>(op.r0, op.r1, la, ps, e >> 2, e & 3);
-                            const double gr = wave_sum(g.x), gi = wave_sum(g.y);
-                            if (lane == 0) {
-                                red[(op.slot + 2 * e) * nwaves + wave] += gr;
-                                red[(op.slot + 2 * e + 1) * nwaves + wave] += gi;
-                            }
+                            R gr, gi;
+                            cot_u2_at<R, RB>(op.r0, op.r1, la, ps, e >> 2, e & 3, gr, gi);
+                            red_add(red, slot + 2 * e * nwaves, gr, lane);
+                            red_add(red, slot + (2 * e + 1) * nwaves, gi, lane);
                         }
                     }
                     la = apply_op<R, RB, true>(la, op, pm.tpart, m16);
                 }
             }
-            if (f == P.phase_begin) break;
+            if (f == f_begin) break;
             // hand both blocks to the previous phase's register assignment
-            const PhaseMap pn = phase_map<RB>(J.rphases[f - 1], t, pi.m);
+            const PhaseMap pn = phase_map<RB>(rphases + (f - 1), t, pi.m);
             __syncthreads();
             if (active) regs_to_lds<R, RB>(ps, lds, pm);
             __syncthreads();
@@ -615,7 +611,7 @@ k_tile_rev(const JobList jl, const Job single) {
     for (int s = t; s < nslots; s += blockDim.x) {
         double v = 0.0;
         for (int w = 0; w < nwaves; ++w) v += red[s * nwaves + w];
-        part[size_t(P.slot_base + s) * wgs + wg] = v;
+        part[size_t(P->slot_base + s) * wgs + wg] = v;
     }
 }
 
