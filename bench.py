@@ -43,6 +43,34 @@ APPLY_FLOPS = {"RX": 6, "RY": 6, "RZ": 6, "H": 4, "X": 0, "Y": 0, "Z": 0, "S": 0
 # quarter of the amplitudes; U2: the 16-entry cotangent, 4 complex MACs per amplitude
 GRAD_FLOPS = {"RX": 4, "RY": 4, "RZ": 4, "RZZ": 4, "FSIM": 3, "U2": 32}
 KIND_NAME = {v: k for k, v in KIND.items()}
+
+# HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE in separate runs, scaled by what each reads for a 2 GiB device
+# copy: x1.99993 and x1.0), keyed by workload and kernel family, valid only
+# for the kernel sources they were taken with (hash below).
+TILE_SOURCES = ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_tile.hip", "plan.cpp", "plan.h"]
+TRAFFIC = {
+    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "f906f1d349c202dd"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "f906f1d349c202dd"),
+}
+
+
+def tile_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_2602_14167_amd", "csrc")
+    for f in TILE_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, kernel):
+    """Counter-measured bytes per launch, or None if not taken for these sources."""
+    rec = TRAFFIC.get((workload_name, kernel))
+    if rec is None or rec[1] != tile_source_hash():
+        return None
+    return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
             "finish", "init"]
 
@@ -367,6 +395,7 @@ def main():
         flops = (rev_flops if dom == "rev_tile" else fwd_flops) / L
         nbytes = algorithmic_bytes(dom, n, s, B, 0)
         roofline = roofline_entry(dom, flops, nbytes, fam_stats[dom]["avg_ms"])
+        roofline["traffic"] = measured_traffic(w["name"], dom) if args.dtype == "c64" else None
     elif fam_stats:
         dom = max(fam_stats, key=lambda k: fam_stats[k]["total_ms"])
         roofline = {"bound": "hbm", "kernel": dom, "note": "plain per-gate path"}
