@@ -72,7 +72,8 @@ def measured_traffic(workload_name, kernel):
         return None
     return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
-            "finish", "init"]
+            "finish", "init", "fused_fwd", "fused_rev", "fused_grad"]
+MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
 
 def workload(name):
@@ -106,8 +107,10 @@ def algorithmic_bytes(family, n, s, batch, n_pauli_passes):
     amp = (2 ** n) * s * batch
     if family == "fwd_tile":
         return 2 * amp                      # read + write psi
-    if family == "rev_tile":
+    if family in ("rev_tile", "fused_rev"):
         return 4 * amp                      # read + write psi and lambda
+    if family == "fused_fwd":
+        return 2 * amp
     if family == "pauli_tile":
         # first pass: read psi, write lambda; later passes also read lambda
         return None if n_pauli_passes == 0 else (2 * amp + 3 * amp * (n_pauli_passes - 1)) / n_pauli_passes
@@ -129,19 +132,20 @@ def sweep_flops(gates, n, batch, with_u2_grad=False):
     return fwd * amp, rev * amp
 
 
-def roofline_entry(kernel, flops_per_launch, bytes_per_launch, avg_ms):
-    """Roofline of one kernel family from its average launch: ALU-bound when
-    its arithmetic intensity exceeds the ridge point, HBM-bound otherwise."""
+def roofline_entry(kernel, flops_per_launch, bytes_per_launch, avg_ms, compute="alu"):
+    """Roofline of one kernel family from its average launch: compute-bound
+    (vector ALU, or matrix cores for the fused passes) when its arithmetic
+    intensity exceeds the ridge point, HBM-bound otherwise."""
     t = avg_ms * 1e-3
     ai = flops_per_launch / bytes_per_launch
-    ridge = ALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    peak = MFMA_F32_PEAK_TFLOPS if compute == "mfma" else ALU_PEAK_TFLOPS
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
     gbs = bytes_per_launch / t / 1e9
     tfl = flops_per_launch / t / 1e12
     hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    alu = {"achieved": round(tfl, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-           "frac": round(tfl / ALU_PEAK_TFLOPS, 4)}
+    alu = {"achieved": round(tfl, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(tfl / peak, 4)}
     main, other = (alu, hbm) if ai > ridge else (hbm, alu)
-    out = {"bound": "alu" if ai > ridge else "hbm", **main, "traffic": None, "kernel": kernel,
+    out = {"bound": compute if ai > ridge else "hbm", **main, "traffic": None, "kernel": kernel,
            "flops_per_launch": flops_per_launch, "bytes_per_launch": bytes_per_launch,
            "avg_launch_ms": round(avg_ms, 4), "intensity_flop_per_byte": round(ai, 2),
            "ridge_flop_per_byte": round(ridge, 2), "other_roof": other}
@@ -309,7 +313,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hea28")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--mode", default="tiled", choices=["tiled", "plain"])
+    ap.add_argument("--mode", default="tiled", choices=["tiled", "plain", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick the tiling by timed search first")
@@ -389,7 +393,17 @@ def main():
     value = amp_updates / dt
     fwd_flops, rev_flops = sweep_flops(w["gates"], n, B)
     roofline = None
-    if args.mode == "tiled" and "rev_tile" in fam_stats:
+    if args.mode == "fused" and "fused_rev" in fam_stats:
+        # matrix-core work of the block formulation: 8 * 16 flops per amplitude
+        # and block (16 x 16 complex product), three products per block in reverse
+        nblk = P.fused_plan_inspect(n, w["gates"], w["n_params"])[4]
+        blk_flops = 8.0 * 16 * (2 ** n) * B * nblk
+        dom = max(("fused_fwd", "fused_rev"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
+        L = fam_stats[dom]["launches"] / args.steps
+        flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
+        roofline = roofline_entry(dom, flops, algorithmic_bytes(dom, n, s, B, 0), fam_stats[dom]["avg_ms"], "mfma")
+        roofline["gate_level_flops_per_launch"] = (rev_flops if dom == "fused_rev" else fwd_flops) / L
+    elif args.mode == "tiled" and "rev_tile" in fam_stats:
         dom = max(("fwd_tile", "rev_tile"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
         L = fam_stats[dom]["launches"] / args.steps
         flops = (rev_flops if dom == "rev_tile" else fwd_flops) / L

@@ -58,8 +58,14 @@ enum { TCNG_C64 = 0, TCNG_C128 = 1 };
  *   TCNG_MODE_TILED: gates are scheduled into passes over 2^m-amplitude tiles
  *     held in registers and LDS; one HBM round trip applies many gates.
  *   TCNG_MODE_PLAIN: one streaming kernel per gate (and per Pauli x-group);
- *     the unfused baseline. */
-enum { TCNG_MODE_TILED = 0, TCNG_MODE_PLAIN = 1 };
+ *     the unfused baseline.
+ *   TCNG_MODE_FUSED: the tiled passes with every register phase multiplied
+ *     out into one 16 x 16 block matrix (float64 product, rounded once to
+ *     float32) applied on the matrix cores; the adjoint sweep accumulates each
+ *     block's outer product sum(lambda psi^dagger) and derives every gate
+ *     derivative from it.  complex64 states with n >= 9 only; otherwise the
+ *     call runs as TCNG_MODE_TILED. */
+enum { TCNG_MODE_TILED = 0, TCNG_MODE_PLAIN = 1, TCNG_MODE_FUSED = 2 };
 
 /* gate kinds of tcng_gate.kind */
 enum {
@@ -210,8 +216,9 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
  *   3 one-qubit gate      4 two-qubit gate      5 k-qubit gate
  *   6 reverse one-qubit   7 reverse two-qubit   8 Pauli X-group
  *   9 final reduction     10 state init
+ *   11 fused forward pass  12 fused reverse pass  13 fused block matrices and gradients
  * tcng_profile_end stops recording and frees the events. */
-enum { TCNG_PROF_FAMILIES = 11 };
+enum { TCNG_PROF_FAMILIES = 14 };
 tcng_status tcng_profile_begin(int32_t max_launches);
 tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
 tcng_status tcng_profile_end(void);
@@ -226,6 +233,19 @@ tcng_status tcng_profile_end(void);
 tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                               int32_t dtype, int32_t* order, int32_t* pass_of, uint64_t* tile_mask,
                               int32_t* n_passes);
+
+/* Host-only inspection of the fused planner (TCNG_MODE_FUSED, complex64).
+ * Outputs (host, any may be NULL):
+ *   order[n_gates], pass_of[n_gates]  as for tcng_plan_inspect;
+ *   block_of[n_gates]                 block (16 x 16 matrix) of gate order[i];
+ *   n_passes, n_blocks;
+ *   bad_layouts  number of LDS layouts of the plan that are not bijections of
+ *                the tile or that put two lanes of a 32-lane access of the
+ *                phases that write or read them on one bank (0 expected).
+ * Returns TCNG_E_UNSUPPORTED when the fused path does not apply (n < 9). */
+tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
+                                    int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
+                                    int32_t* n_blocks, int32_t* bad_layouts);
 
 #ifdef __cplusplus
 }

@@ -17,13 +17,13 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TcngError, TcngGate,  # noqa: F401
+from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TcngError, TcngGate,  # noqa: F401
                    TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
-           "TcngEnergy", "new_state", "TcngError", "MODES"]
+           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect"]
 
-MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN}
+MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
 
 
 def _mode(mode):
@@ -326,3 +326,19 @@ def plan_inspect(n, gates, n_params, dtype=torch.complex64):
                                   masks.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass)))
     k = npass.value
     return order[:G] if k else None, pass_of[:G] if k else None, masks[:k]
+
+
+def fused_plan_inspect(n, gates, n_params):
+    """Host-only view of the fused schedule (complex64 matrix-core blocks):
+    (order, pass_of, block_of, n_passes, n_blocks, bad_layouts)."""
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 6))
+    G = g.shape[0]
+    order = np.zeros(max(G, 1), np.int32)
+    pass_of = np.zeros(max(G, 1), np.int32)
+    block_of = np.zeros(max(G, 1), np.int32)
+    npass, nblk, bad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().tcng_fused_plan_inspect(int(n), g.ctypes.data_as(ctypes.c_void_p), G, int(n_params),
+                                        order.ctypes.data_as(ctypes.c_void_p), pass_of.ctypes.data_as(ctypes.c_void_p),
+                                        block_of.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass),
+                                        ctypes.byref(nblk), ctypes.byref(bad)))
+    return order[:G], pass_of[:G], block_of[:G], npass.value, nblk.value, bad.value

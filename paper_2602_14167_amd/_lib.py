@@ -14,13 +14,14 @@ LIB_PATH = os.path.join(HERE, "libtcng.so")
 
 TCNG_OK, TCNG_E_INVALID, TCNG_E_UNSUPPORTED, TCNG_E_WORKSPACE, TCNG_E_HIP, TCNG_E_ALLOC = range(6)
 TCNG_C64, TCNG_C128 = 0, 1
-TCNG_MODE_TILED, TCNG_MODE_PLAIN = 0, 1
+TCNG_MODE_TILED, TCNG_MODE_PLAIN, TCNG_MODE_FUSED = 0, 1, 2
 
 # every function include/tcng.h declares
 EXPORTS = [
     "tcng_last_error", "tcng_version", "tcng_state_init", "tcng_apply_gate", "tcng_circuit_create",
     "tcng_circuit_destroy", "tcng_circuit_num_passes", "tcng_pauli_sum_create", "tcng_pauli_sum_destroy",
     "tcng_workspace_size", "tcng_run_circuit", "tcng_expect_pauli", "tcng_expect_grad", "tcng_plan_inspect",
+    "tcng_fused_plan_inspect",
     "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end", "tcng_circuit_configure",
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
 ]
@@ -78,6 +79,8 @@ def lib():
     L.tcng_profile_query.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     L.tcng_profile_end.argtypes = []
     L.tcng_plan_inspect.argtypes = [i32, P, i32, i32, i32, P, P, P, ctypes.POINTER(i32)]
+    L.tcng_fused_plan_inspect.argtypes = [i32, P, i32, i32, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32)]
     for name in EXPORTS:
         if name != "tcng_last_error" and name != "tcng_version":
             getattr(L, name).restype = i32

@@ -49,7 +49,8 @@ constexpr int MAX_QUBITS = 34;
 // optional per-launch timing (events on the launch stream)
 // ---------------------------------------------------------------------------
 enum Family { F_FWD_TILE, F_REV_TILE, F_PAULI_TILE, F_GATE1, F_GATE2, F_GATEK, F_REV1, F_REV2, F_PAULI_GROUP,
-              F_FINISH, F_INIT, F_COUNT };
+              F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_COUNT };
+static_assert(F_COUNT == TCNG_PROF_FAMILIES, "profiler families");
 
 struct Profiler {
     bool on = false;
@@ -122,6 +123,33 @@ struct DevCircuitPlan {
     SlotTables slots;
 };
 
+struct DevFusedPlan {
+    bool valid = false;
+    FusedPlan host;
+    FPass* passes = nullptr;
+    FPhase* phases = nullptr;
+    FPass* rpasses = nullptr;
+    FPhase* rphases = nullptr;
+    Op* ops = nullptr;
+    SlotTables slots;
+};
+
+void free_fused(DevFusedPlan& P) {
+    (void)hipFree(P.passes);
+    (void)hipFree(P.phases);
+    (void)hipFree(P.rpasses);
+    (void)hipFree(P.rphases);
+    (void)hipFree(P.ops);
+    (void)hipFree(P.slots.ptr);
+    (void)hipFree(P.slots.idx);
+    (void)hipFree(P.slots.gate_slot);
+    P = DevFusedPlan();
+}
+
+// fused passes: tile bits and low qubits (complex64 only)
+constexpr int FUSED_M = 12, FUSED_LO = 4;
+bool fused_ok(int n, int dtype) { return dtype == TCNG_C64 && n >= FUSED_K + 5; }
+
 void free_plan(DevCircuitPlan& P) {
     (void)hipFree(P.passes);
     (void)hipFree(P.phases);
@@ -148,6 +176,7 @@ struct tcng_circuit {
     std::vector<int> plain_slot;               // first slot per gate (plain path), -1 none
     SlotTables plain;
     DevCircuitPlan tiled[2];
+    DevFusedPlan fused;              // complex64 matrix-core plan
 };
 
 struct tcng_pauli_sum {
@@ -199,6 +228,27 @@ tcng_status make_plan(tcng_circuit* c, int dt, const TileConfig& cfg) {
     return TCNG_OK;
 }
 
+tcng_status make_fused(tcng_circuit* c) {
+    DevFusedPlan P;
+    std::string why = plan_fused(c->n, c->gates, c->n_params, FUSED_M, FUSED_LO, P.host);
+    if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "fused planner: " + why);
+    if (upload(P.host.passes, &P.passes) != hipSuccess || upload(P.host.phases, &P.phases) != hipSuccess ||
+        upload(P.host.rpasses, &P.rpasses) != hipSuccess || upload(P.host.rphases, &P.rphases) != hipSuccess ||
+        upload(P.host.ops, &P.ops) != hipSuccess) {
+        free_fused(P);
+        return fail(TCNG_E_ALLOC, "device allocation failed");
+    }
+    if (tcng_status e = build_slot_tables(c->gates, c->n_params, P.host.slot_ptr, P.host.slot_idx, P.host.gate_slot,
+                                          P.host.total_slots, P.slots)) {
+        free_fused(P);
+        return e;
+    }
+    P.valid = true;
+    free_fused(c->fused);
+    c->fused = P;
+    return TCNG_OK;
+}
+
 tcng_status check_state(const tcng_state* s, const char* what) {
     if (!s) return fail(TCNG_E_INVALID, std::string(what) + ": null state");
     if (!s->amps) return fail(TCNG_E_INVALID, std::string(what) + ": null amplitude pointer");
@@ -235,6 +285,10 @@ int pauli_wgs_plain(int n, int64_t batch) {
 }
 
 struct WsLayout {
+    bool fused = false;
+    size_t fmats_off = 0, fmats_bytes = 0;   // fused: block matrices
+    size_t opart_off = 0, opart_bytes = 0;   // fused: outer products per workgroup
+    size_t osum_off = 0, osum_bytes = 0;     // fused: outer products summed
     size_t part_off = 0, part_bytes = 0;
     size_t epart_off = 0, epart_bytes = 0;
     size_t red_off = 0, red_bytes = 0;     // row sums of the partials
@@ -251,15 +305,40 @@ void finish_layout(WsLayout& L, int64_t batch) {
     L.red_off = L.epart_off + align256(L.epart_bytes);
     L.red_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1) + std::max(L.e_rows, 1)) * sizeof(double);
     L.opm_off = L.red_off + align256(L.red_bytes);
-    L.total = L.opm_off + align256(L.opm_bytes);
+    L.fmats_off = L.opm_off + align256(L.opm_bytes);
+    L.opart_off = L.fmats_off + align256(L.fmats_bytes);
+    L.osum_off = L.opart_off + align256(L.opart_bytes);
+    L.total = L.osum_off + align256(L.osum_bytes);
 }
 
 bool use_tiled(int mode, int n, int dtype) { return mode == TCNG_MODE_TILED && tiled_ok(n, dtype); }
 
+// the mode a call runs in: FUSED needs a complex64 circuit with a fused plan
+int run_mode(int mode, const tcng_circuit* c, int dtype) {
+    if (mode != TCNG_MODE_FUSED) return mode;
+    return (c && dtype == TCNG_C64 && c->fused.valid) ? TCNG_MODE_FUSED : TCNG_MODE_TILED;
+}
+
+// fused reverse: one 512-thread workgroup per CU, looping over tiles
+int fused_wgs(int n, int m, int64_t batch) {
+    const int64_t tiles = int64_t(1) << (n - m);
+    const int64_t cap = std::max<int64_t>(1, ceil_div(512, batch));
+    return int(std::min(tiles, cap));
+}
+
 WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype, int64_t batch, int mode) {
     WsLayout L;
     const bool tiled = use_tiled(mode, n, dtype);
-    if (c) {
+    if (c && mode == TCNG_MODE_FUSED) {
+        const FusedPlan& F = c->fused.host;
+        L.fused = true;
+        L.total_slots = F.total_slots;
+        L.rev_wgs = fused_wgs(n, F.m, batch);
+        L.fmats_bytes = size_t(batch) * F.n_blocks * 2048 * sizeof(float);
+        L.opart_bytes = size_t(batch) * F.n_blocks * size_t(L.rev_wgs) * 512 * sizeof(double);
+        L.osum_bytes = size_t(batch) * F.n_blocks * 512 * sizeof(double);
+        L.part_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1)) * sizeof(double);
+    } else if (c) {
         if (tiled)
             L.opm_bytes = size_t(batch) * c->gates.size() * 16 * (dtype == TCNG_C64 ? 8 : 16);
         L.total_slots = tiled ? c->tiled[dtype].host.total_slots : c->plain.total;
@@ -277,6 +356,24 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
         L.e_rows = std::max(L.e_rows, 1);
         L.epart_bytes = size_t(batch) * size_t(L.e_rows) * size_t(L.e_wgs) * sizeof(double);
     }
+    finish_layout(L, batch);
+    return L;
+}
+
+// the Pauli passes run tiled unless the mode is plain or the tiled Pauli plan is impossible
+int pauli_mode(int mode, const tcng_pauli_sum* h, int n, int dt) {
+    const int m = mode == TCNG_MODE_FUSED ? TCNG_MODE_TILED : mode;
+    return (use_tiled(m, n, dt) && !h->tiled_valid[dt]) ? TCNG_MODE_PLAIN : m;
+}
+
+// workspace of a value-and-gradient evaluation (mode already passed through run_mode)
+WsLayout grad_layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dt, int64_t batch, int mode) {
+    WsLayout Lc = layout(c, nullptr, n, dt, batch, mode);
+    WsLayout Lh = layout(nullptr, h, n, dt, batch, pauli_mode(mode, h, n, dt));
+    WsLayout L = Lc;
+    L.e_rows = Lh.e_rows;
+    L.e_wgs = Lh.e_wgs;
+    L.epart_bytes = Lh.epart_bytes;
     finish_layout(L, batch);
     return L;
 }
@@ -307,6 +404,17 @@ Job make_job(const tcng_circuit* c, const tcng_pauli_sum* h, const tcng_state* s
         J.n_passes = int32_t(P.host.passes.size());
         J.n_gates = int32_t(c->gates.size());
         J.tiles = int64_t(1) << (s->n_qubits - std::min(s->n_qubits, P.host.cfg.m_max));
+    }
+    if (c && L.fused) {
+        const DevFusedPlan& F = c->fused;
+        J.fpasses = F.passes;
+        J.fphases = F.phases;
+        J.frpasses = F.rpasses;
+        J.frphases = F.rphases;
+        J.n_passes = int32_t(F.host.passes.size());
+        J.n_blocks = F.host.n_blocks;
+        J.n_gates = int32_t(c->gates.size());
+        J.tiles = int64_t(1) << (s->n_qubits - F.host.m);
     }
     if (h && h->tiled_valid[dt]) {
         J.ppasses = h->dplan[dt].passes;
@@ -424,6 +532,35 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
                                        st));
         }
     }
+    return TCNG_OK;
+}
+
+// fused: block matrices (forward operand order, and the reverse one when
+// gradients follow), then the forward passes
+tcng_status run_forward_fused(const tcng_circuit* c, const void* params, const tcng_state* s, const Job& J,
+                              bool want_rev, hipStream_t st) {
+    const DevFusedPlan& F = c->fused;
+    PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, params, c->n_params, c->cm[0],
+                                             s->batch, const_cast<void*>(J.fmats), want_rev, st));
+    for (size_t p = 0; p < F.host.passes.size(); ++p) {
+        const JobList jl{nullptr, nullptr, 0, int32_t(p)};
+        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st));
+    }
+    return TCNG_OK;
+}
+
+// fused adjoint sweep: passes in reverse, then gradient slots from the block outer products
+tcng_status run_reverse_fused(const tcng_circuit* c, const void* params, const tcng_state* psi, const WsLayout& L,
+                              double* part, double* osum, const Job& J, hipStream_t st) {
+    const DevFusedPlan& F = c->fused;
+    const int np = int(F.host.passes.size());
+    for (int k = 0; k < np; ++k) {
+        const JobList jl{nullptr, nullptr, 0, int32_t(k)};
+        PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, J, F.host.m, int64_t(J.wgs) * J.batch, st));
+    }
+    if (L.total_slots > 0)
+        PROF_TRY(F_FUSED_GRAD, launch_fused_grad(F.phases, F.ops, F.host.n_blocks, params, c->n_params, c->cm[0],
+                                                 psi->batch, J.opart, J.wgs, osum, L.total_slots, part, st));
     return TCNG_OK;
 }
 
@@ -560,6 +697,8 @@ tcng_status tcng_circuit_create(int32_t n_qubits, const tcng_gate* gates, int32_
         if (!tiled_ok(n_qubits, dt)) continue;
         if (tcng_status e = make_plan(c, dt, tile_config(dt))) return cleanup(e);
     }
+    if (fused_ok(n_qubits, TCNG_C64))
+        if (tcng_status e = make_fused(c)) return cleanup(e);
     *out = c;
     return ok();
 }
@@ -577,6 +716,7 @@ tcng_status tcng_circuit_destroy(tcng_circuit* c) {
     (void)hipFree(c->plain.idx);
     (void)hipFree(c->plain.gate_slot);
     for (auto& P : c->tiled) free_plan(P);
+    free_fused(c->fused);
     delete c;
     return ok();
 }
@@ -659,12 +799,19 @@ tcng_status tcng_workspace_size(const tcng_circuit* c, const tcng_pauli_sum* h, 
     if (!bytes) return fail(TCNG_E_INVALID, "null output");
     if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
     if (batch < 1) return fail(TCNG_E_INVALID, "batch < 1");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN) return fail(TCNG_E_INVALID, "bad mode");
+    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
+        return fail(TCNG_E_INVALID, "bad mode");
     const int n = c ? c->n : (h ? h->n : 0);
     if (!n) return fail(TCNG_E_INVALID, "need a circuit or a Pauli sum");
     if (c && h && c->n != h->n) return fail(TCNG_E_INVALID, "circuit and Pauli sum differ in qubit count");
-    if (h && use_tiled(mode, n, dtype) && !h->tiled_valid[dtype]) mode = TCNG_MODE_PLAIN;
-    *bytes = layout(c, h, n, dtype, batch, mode).total;
+    mode = run_mode(mode, c, dtype);
+    if (!c || !h) {
+        if (h && use_tiled(mode == TCNG_MODE_FUSED ? TCNG_MODE_TILED : mode, n, dtype) && !h->tiled_valid[dtype])
+            mode = TCNG_MODE_PLAIN;
+        *bytes = layout(c, h, n, dtype, batch, (!c && mode == TCNG_MODE_FUSED) ? TCNG_MODE_TILED : mode).total;
+        return ok();
+    }
+    *bytes = grad_layout(c, h, n, dtype, batch, mode).total;
     return ok();
 }
 
@@ -672,12 +819,20 @@ tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tc
                              size_t ws_bytes, void* stream) {
     if (tcng_status e = check_state(s, "tcng_run_circuit")) return e;
     if (tcng_status e = check_circuit_state(c, s, params)) return e;
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN) return fail(TCNG_E_INVALID, "bad mode");
+    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
+        return fail(TCNG_E_INVALID, "bad mode");
+    mode = run_mode(mode, c, s->dtype);
     const WsLayout L = layout(c, nullptr, s->n_qubits, s->dtype, s->batch, mode);
     const bool tiled = use_tiled(mode, s->n_qubits, s->dtype);
-    if (tiled && (!ws || ws_bytes < L.total))
+    if ((tiled || L.fused) && (!ws || ws_bytes < L.total))
         return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (L.fused) {
+        Job J = make_job(c, nullptr, s, nullptr, nullptr, nullptr, nullptr, L);
+        J.fmats = static_cast<char*>(ws) + L.fmats_off;
+        const tcng_status e = run_forward_fused(c, params, s, J, false, st);
+        return e ? e : ok();
+    }
     void* opm = tiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
     const Job J = make_job(c, nullptr, s, nullptr, opm, nullptr, nullptr, L);
     tcng_status e;
@@ -696,8 +851,9 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
     if (tcng_status e = check_state(s, "tcng_expect_pauli")) return e;
     if (!h || !out) return fail(TCNG_E_INVALID, "null Pauli sum or output");
     if (h->n != s->n_qubits) return fail(TCNG_E_INVALID, "Pauli sum and state differ in qubit count");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN) return fail(TCNG_E_INVALID, "bad mode");
-    if (use_tiled(mode, h->n, s->dtype) && !h->tiled_valid[s->dtype]) mode = TCNG_MODE_PLAIN;
+    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
+        return fail(TCNG_E_INVALID, "bad mode");
+    mode = pauli_mode(mode, h, h->n, s->dtype);
     const WsLayout L = layout(nullptr, h, s->n_qubits, s->dtype, s->batch, mode);
     if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -726,23 +882,35 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     if (lam->amps == psi->amps) return fail(TCNG_E_INVALID, "psi and lam must not alias");
     if (!energy) return fail(TCNG_E_INVALID, "null energy output");
     if (c->n_params > 0 && !grad) return fail(TCNG_E_INVALID, "null gradient output");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN) return fail(TCNG_E_INVALID, "bad mode");
+    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
+        return fail(TCNG_E_INVALID, "bad mode");
     const int dt = psi->dtype;
-    // the Pauli passes follow the circuit's mode unless the tiled Pauli plan is impossible
-    const int pmode = (use_tiled(mode, h->n, dt) && !h->tiled_valid[dt]) ? TCNG_MODE_PLAIN : mode;
-    WsLayout Lc = layout(c, nullptr, psi->n_qubits, dt, psi->batch, mode);
-    WsLayout Lh = layout(nullptr, h, psi->n_qubits, dt, psi->batch, pmode);
-    WsLayout L = Lc;
-    L.e_rows = Lh.e_rows;
-    L.e_wgs = Lh.e_wgs;
-    L.epart_bytes = Lh.epart_bytes;
-    finish_layout(L, psi->batch);
+    mode = run_mode(mode, c, dt);
+    const int pmode = pauli_mode(mode, h, h->n, dt);
+    const WsLayout L = grad_layout(c, h, psi->n_qubits, dt, psi->batch, mode);
     if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + L.part_off);
-    double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
+    char* w = static_cast<char*>(ws);
+    double* part = reinterpret_cast<double*>(w + L.part_off);
+    double* epart = reinterpret_cast<double*>(w + L.epart_off);
+    double* red = reinterpret_cast<double*>(w + L.red_off);
+    if (L.fused) {
+        Job J = make_job(c, h, psi, lam->amps, nullptr, part, epart, L);
+        J.fmats = w + L.fmats_off;
+        J.opart = reinterpret_cast<double*>(w + L.opart_off);
+        tcng_status e = run_forward_fused(c, params, psi, J, true, st);
+        if (!e) e = run_pauli<float, 5>(h, psi, lam->amps, L, epart, pmode, J, st);
+        if (!e) e = run_reverse_fused(c, params, psi, L, part, reinterpret_cast<double*>(w + L.osum_off), J, st);
+        if (e) return e;
+        const SlotTables& S = c->fused.slots;
+        PROF_TRY(F_FINISH, launch_finish(L.total_slots > 0 ? part : nullptr, std::max(L.total_slots, 1), 1, S.ptr,
+                                         S.idx, c->n_params, epart, L.e_rows, L.e_wgs, psi->batch, energy, grad,
+                                         gate_grad, S.gate_slot, c->u2m[dt], c->gate_mat, int(c->gates.size()), red,
+                                         st));
+        return ok();
+    }
     const bool ctiled = use_tiled(mode, psi->n_qubits, dt);
-    void* opm = ctiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
+    void* opm = ctiled ? w + L.opm_off : nullptr;
     const Job J = make_job(c, h, psi, lam->amps, opm, part, epart, L);
     tcng_status e;
     if (dt == TCNG_C64) {
@@ -757,11 +925,44 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
         if (!e) e = run_reverse<double, 4>(c, params, psi, lam->amps, L, part, mode, J, st);
     }
     if (e) return e;
-    const bool tiled = use_tiled(mode, psi->n_qubits, dt);
-    const SlotTables& S = tiled ? c->tiled[dt].slots : c->plain;
+    const SlotTables& S = ctiled ? c->tiled[dt].slots : c->plain;
     PROF_TRY(F_FINISH, launch_finish(part, std::max(L.total_slots, 1), L.rev_wgs, S.ptr, S.idx, c->n_params, epart, L.e_rows,
                           L.e_wgs, psi->batch, energy, grad, gate_grad, S.gate_slot, c->u2m[dt], c->gate_mat,
-                          int(c->gates.size()), reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off), st));
+                          int(c->gates.size()), red, st));
+    return ok();
+}
+
+tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
+                                    int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
+                                    int32_t* n_blocks, int32_t* bad_layouts) {
+    if (n_qubits < 1 || n_qubits > MAX_QUBITS) return fail(TCNG_E_UNSUPPORTED, "n_qubits out of range");
+    if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(TCNG_E_INVALID, "bad gate list");
+    for (int i = 0; i < n_gates; ++i) {
+        const tcng_gate& g = gates[i];
+        if (g.kind < 0 || g.kind >= K_COUNT || g.q0 < 0 || g.q0 >= n_qubits ||
+            (kind_arity(g.kind) == 2 && (g.q1 < 0 || g.q1 >= n_qubits || g.q1 == g.q0)))
+            return fail(TCNG_E_INVALID, "gate " + std::to_string(i) + ": bad kind or qubits");
+        const int np = kind_nparams(g.kind);
+        if ((np >= 1 && (g.p0 < 0 || g.p0 >= n_params)) || (np >= 2 && (g.p1 < 0 || g.p1 >= n_params)))
+            return fail(TCNG_E_INVALID, "gate " + std::to_string(i) + ": parameter index out of range");
+    }
+    if (!fused_ok(n_qubits, TCNG_C64)) return fail(TCNG_E_UNSUPPORTED, "fused path needs n >= 9");
+    FusedPlan P;
+    std::vector<tcng_gate> g(gates, gates + n_gates);
+    std::string why = plan_fused(n_qubits, g, n_params, FUSED_M, FUSED_LO, P);
+    if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "fused planner: " + why);
+    int k = 0;
+    for (size_t p = 0; p < P.passes.size(); ++p)
+        for (int f = P.passes[p].phase_begin; f < P.passes[p].phase_end; ++f)
+            for (int o = P.phases[f].op_begin; o < P.phases[f].op_end; ++o) {
+                if (order) order[k] = P.ops[o].gate;
+                if (pass_of) pass_of[k] = int32_t(p);
+                if (block_of) block_of[k] = P.phases[f].block;
+                ++k;
+            }
+    if (n_passes) *n_passes = int32_t(P.passes.size());
+    if (n_blocks) *n_blocks = P.n_blocks;
+    if (bad_layouts) *bad_layouts = check_fused_layouts(P);
     return ok();
 }
 

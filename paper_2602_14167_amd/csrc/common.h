@@ -111,6 +111,38 @@ struct Pass {
     int32_t local_qubit[16];
 };
 
+// ---------------------------------------------------------------------------
+// fused passes: each phase applies one 2^FUSED_K x 2^FUSED_K block matrix on
+// matrix cores.  A tile's local index splits, per phase, into the block index
+// j (local bits R[0..3], R[t] = bit t of j) and the column index (the other
+// local bits in increasing order).  The LDS address of local index l under a
+// layout is the XOR of img[b] over the set bits b of l (a linear bijection
+// chosen by the planner so that the 32-lane accesses of both the phase that
+// writes a layout and the phase that reads it hit distinct banks).
+// ---------------------------------------------------------------------------
+constexpr int FUSED_K = 4;
+constexpr int FUSED_MAX_BLOCKS = 8;    // blocks per fused pass (outer-product accumulators in LDS)
+
+struct FPhase {
+    int32_t op_begin, op_end;      // gates of the block, circuit order (Op.r0/r1 = bit of j)
+    int32_t R[FUSED_K];
+    int32_t C[9];                  // local bit of column bit k (-1 beyond the tile)
+    int32_t rd[MAX_TILE_BITS];     // layout this phase reads
+    int32_t wr[MAX_TILE_BITS];     // layout this phase writes
+    int32_t block;                 // index of the block (matrix table, outer-product sums)
+    int32_t pad;
+};
+
+struct FPass {
+    int32_t phase_begin, phase_end;
+    int32_t m, lo;
+    int32_t n_slots, slot_base;
+    uint64_t tile_mask;
+    int32_t local_qubit[16];
+    int32_t ld[MAX_TILE_BITS];     // layout the tile load writes
+    int32_t st[MAX_TILE_BITS];     // layout the tile store reads
+};
+
 // Pauli sum, grouped by X-mask, for the tiled H|psi> / <H> passes.  Inside a
 // group the terms are split into classes of equal coefficient c_k i^{#Y_k},
 // so the kernels count sign parities with integer adds per class.

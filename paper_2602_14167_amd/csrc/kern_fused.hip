@@ -1,0 +1,726 @@
+// Fused block passes on matrix cores (complex64 state, float32 MFMA).
+//
+// A pass streams each tile of 2^m amplitudes through LDS once, as the tiled
+// passes do; inside the tile every phase applies ONE block matrix M (the
+// product of the phase's gates on its FUSED_K = 4 local bits, formed in
+// float64 and rounded once) to all 2^(m-4) columns.  Splitting complex
+// numbers into real and imaginary parts turns y = M x into a real 32 x 32
+// product, which v_mfma_f32_32x32x2f32 evaluates 32 columns at a time
+// (the paper's JIT "operator fusion", done here as explicit block matrices).
+//
+// Reverse sweep (adjoint): psi and lambda are un-computed block by block
+// (psi_in = M^dagger psi_out, lambda_in = M^dagger lambda_out) and the block's
+// outer product O = sum over columns of lambda_in psi_in^dagger (16 x 16) is
+// accumulated with a third matrix-core product, float32 within a tile and
+// float64 across tiles.  Every gate derivative of the block then follows from
+// O by 16 x 16 algebra (k_fused_grad): with X_1 = G_1 O and
+// X_{g+1} = G_{g+1} X_g G_g^dagger, X_g = sum lambda_after_g phi_before_g^dagger,
+// so dE/dtheta = 2 Im sum_ab Gen_ab conj((X_g G_g^dagger)_ab) and the U2
+// cotangent is the partial trace of X_g over the block's other bits.
+//
+// MFMA operand / result layouts (lane l, h = l / 32, v = accumulator index):
+//   A[i][k]: lane supplies A[l % 32][2 s + h] in step s
+//   B[k][n]: lane supplies B[2 s + h][l % 32]
+//   D[i][n]: lane holds D[8 (v / 4) + 4 h + v % 4][l % 32] in register v
+#include "devutil.h"
+#include "gates.h"
+
+namespace tcng {
+
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int FTHREADS = 256;            // 4 waves; 32-column tiles dealt round-robin (<= 2 per wave)
+constexpr int CT_MAX = 2;
+constexpr int FMAX_M = 12;               // tile bits of the fused kernels
+constexpr int OSTRIDE = 512;             // doubles per block outer product (16 x 16 complex)
+
+__device__ __forceinline__ uint64_t loc2glob_f(uint32_t l, int lo, int m, cptr<FPass> P) {
+    uint64_t g = l & ((1u << lo) - 1);
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_BITS; ++i)
+        if (i >= lo && i < m) g |= uint64_t((l >> i) & 1) << P->local_qubit[i];
+    return g;
+}
+
+__device__ __forceinline__ uint64_t tile_base_f(uint64_t tile, uint64_t tmask, int n) {
+    uint64_t base = 0;
+    int k = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((tmask >> q) & 1) continue;
+        base |= ((tile >> k) & 1) << q;
+        ++k;
+    }
+    return base;
+}
+
+// address of local index l under a layout (XOR of the images of its bits;
+// masks instead of branches: l differs per lane)
+__device__ __forceinline__ uint32_t lay_c(uint32_t l, cptr<int32_t> img, int m) {
+    uint32_t a = 0;
+#pragma unroll
+    for (int b = 0; b < MAX_TILE_BITS; ++b)
+        if (b < m) a ^= uint32_t(img[b]) & (0u - ((l >> b) & 1u));
+    return a;
+}
+
+// tile HBM <-> LDS: thread t moves 16-byte chunks c = it * nthr + t (local
+// indices 2c, 2c + 1), each amplitude to its address under `img`.  Layouts and
+// the local -> global map are linear in the bits, so the thread's part
+// (bits 1..log2(2 nthr)) and the iteration's part (higher bits) combine by XOR
+// / addition: one per-lane term, uniform terms per iteration.
+// Per-kernel addressing of the tile load and store (IT chunks per thread):
+// the pass's maps are the same for every tile, so the lane's terms and the
+// iterations' uniform terms are formed once.
+template <int IT>
+struct TileIO {
+    uint64_t gt;                 // lane: global offset of local index 2t
+    uint32_t at_ld, at_st;       // lane: LDS address of 2t in the load / store layout
+    uint64_t gi[IT];             // uniform: global offset of 2 it nthr
+    uint32_t ai_ld[IT], ai_st[IT];
+    uint32_t a1_ld, a1_st;       // images of local bit 0
+};
+
+template <int IT>
+__device__ __forceinline__ TileIO<IT> tile_io(cptr<FPass> P, int t, int nthr) {
+    TileIO<IT> io;
+    const int m = P->m, lo = P->lo;
+    const uint32_t lt = 2u * uint32_t(t);
+    io.gt = loc2glob_f(lt, lo, m, P);
+    io.at_ld = lay_c(lt, as_const(P->ld), m);
+    io.at_st = lay_c(lt, as_const(P->st), m);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint32_t li = 2u * uint32_t(it * nthr);
+        io.gi[it] = loc2glob_f(li, lo, m, P);
+        io.ai_ld[it] = lay_c(li, as_const(P->ld), m);
+        io.ai_st[it] = lay_c(li, as_const(P->st), m);
+    }
+    io.a1_ld = uint32_t(P->ld[0]);
+    io.a1_st = uint32_t(P->st[0]);
+    return io;
+}
+
+// NS states (psi, and lambda in the reverse sweep): every load in flight
+// before the first LDS write
+template <int IT, int NS>
+__device__ __forceinline__ void ftile_load(float2* const* lds, const gptr<cx<float>>* st, uint64_t base,
+                                           const TileIO<IT>& io) {
+    float4 v[NS][IT];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+            v[k][it] = *reinterpret_cast<gptr<const float4>>(st[k] + base + io.gt + io.gi[it]);
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const uint32_t a = io.at_ld ^ io.ai_ld[it];
+            lds[k][a] = make_float2(v[k][it].x, v[k][it].y);
+            lds[k][a ^ io.a1_ld] = make_float2(v[k][it].z, v[k][it].w);
+        }
+}
+template <int IT, int NS>
+__device__ __forceinline__ void ftile_store(float2* const* lds, const gptr<cx<float>>* st, uint64_t base,
+                                            const TileIO<IT>& io) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const uint32_t a = io.at_st ^ io.ai_st[it];
+            const float2 x = lds[k][a], y = lds[k][a ^ io.a1_st];
+            *reinterpret_cast<gptr<float4>>(st[k] + base + io.gt + io.gi[it]) = make_float4(x.x, x.y, y.x, y.y);
+        }
+}
+
+// per-lane view of one phase: addresses of the lane's column (block bits
+// zero) and the uniform images of the block bits and of column bits 0..4
+struct FView {
+    uint32_t rd_col, wr_col;   // column ct * 32 + lane % 32
+    uint32_t wr_tile;          // column ct * 32 (write layout)
+    uint32_t rdR[FUSED_K], wrR[FUSED_K], wrC[5];
+};
+
+__device__ __forceinline__ FView fview(cptr<FPhase> F, int ct, int lane) {
+    FView v;
+    uint32_t rl = 0, wl = 0, rw = 0, ww = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cb = F->C[k];
+        if (cb < 0) continue;
+        const uint32_t ir = uint32_t(F->rd[cb]), iw = uint32_t(F->wr[cb]);
+        if (k < 5) {
+            v.wrC[k] = iw;
+            const uint32_t msk = 0u - ((uint32_t(lane) >> k) & 1u);
+            rl ^= ir & msk;
+            wl ^= iw & msk;
+        } else if ((ct >> (k - 5)) & 1) {
+            rw ^= ir;
+            ww ^= iw;
+        }
+    }
+    v.rd_col = rl ^ rw;
+    v.wr_col = wl ^ ww;
+    v.wr_tile = ww;
+#pragma unroll
+    for (int t = 0; t < FUSED_K; ++t) {
+        v.rdR[t] = uint32_t(F->rd[F->R[t]]);
+        v.wrR[t] = uint32_t(F->wr[F->R[t]]);
+    }
+    return v;
+}
+
+// the lane's MFMA input: components 2 s + h (s = 0..15) of its column,
+// i.e. the 8 amplitudes with block index j = 2 s' + h (re for s < 8, im after)
+__device__ __forceinline__ void read_cols(const float2* lds, const FView& v, int h, float* x) {
+    const uint32_t base = v.rd_col ^ (v.rdR[0] & (0u - uint32_t(h)));
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const uint32_t a = base ^ ((s & 1) ? v.rdR[1] : 0u) ^ ((s & 2) ? v.rdR[2] : 0u) ^ ((s & 4) ? v.rdR[3] : 0u);
+        const float2 z = lds[a];
+        x[s] = z.x;
+        x[s + 8] = z.y;
+    }
+}
+
+// 16 floats of this lane's matrix operand (lane-major table)
+__device__ __forceinline__ void read_mat(gptr<const float> tbl, int lane, float* w) {
+    gptr<const float4> p = reinterpret_cast<gptr<const float4>>(tbl + lane * 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 q = p[i];
+        w[4 * i] = q.x;
+        w[4 * i + 1] = q.y;
+        w[4 * i + 2] = q.z;
+        w[4 * i + 3] = q.w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward pass: one tile per workgroup
+// ---------------------------------------------------------------------------
+// waves and column tiles of a tile of 2^m amplitudes: 2^(m - 9) column tiles
+// of 32 columns over min(4, 2^(m - 9)) waves
+struct FWork {
+    int nwv, ctw, nthr;
+};
+__device__ __forceinline__ FWork fwork(int m) {
+    FWork k;
+    const int ct = 1 << (m - 9);
+    k.nwv = ct < 4 ? ct : 4;
+    k.ctw = ct / k.nwv;
+    k.nthr = 64 * k.nwv;
+    return k;
+}
+
+template <int IT>
+__global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const Job single) {
+    __shared__ float2 lds[1 << FMAX_M];
+    int64_t local;
+    const Job J = load_job(jl, single, blockIdx.x, local);
+    cptr<FPass> P = as_const(J.fpasses) + jl.step;
+    const int m = P->m;
+    const FWork K = fwork(m);
+    const int t = threadIdx.x;
+    const int wave = uniform(t >> 6), lane = t & 63, h = lane >> 5;
+    const bool active = wave < K.nwv;
+    const int64_t b = local / J.tiles;
+    const uint64_t tile = uint64_t(local - b * J.tiles);
+    gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
+    gptr<const float> mats = as_global(static_cast<const float*>(J.fmats)) + size_t(b) * J.n_blocks * 2048;
+    cptr<FPhase> phases = as_const(J.fphases);
+    const uint64_t base = tile_base_f(tile, P->tile_mask, J.n);
+    float2* const bufs[1] = {lds};
+    const gptr<cx<float>> sts[1] = {psi};
+    const TileIO<IT> io = tile_io<IT>(P, t, K.nthr);
+
+    if (active) ftile_load<IT, 1>(bufs, sts, base, io);
+    __syncthreads();
+    const int f_end = P->phase_end;
+    for (int f = P->phase_begin; f < f_end; ++f) {
+        cptr<FPhase> F = phases + f;
+        float x[CT_MAX][16], w[16];
+        FView v[CT_MAX];
+        if (active) {
+            read_mat(mats + size_t(F->block) * 2048, lane, w);
+#pragma unroll
+            for (int k = 0; k < CT_MAX; ++k) {
+                if (k >= K.ctw) break;
+                v[k] = fview(F, wave + K.nwv * k, lane);
+                read_cols(lds, v[k], h, x[k]);
+            }
+        }
+        __syncthreads();   // the phase writes another layout: all reads first
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < CT_MAX; ++k) {
+                if (k >= K.ctw) break;
+                f16v acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w[s], x[k][s], acc, 0, 0, 0);
+                // register q (< 8): re of y[j], q + 8: im, j = 8 (q / 4) + 4 h + q % 4
+                const uint32_t wb = v[k].wr_col ^ (v[k].wrR[2] & (0u - uint32_t(h)));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t a = wb ^ ((q & 1) ? v[k].wrR[0] : 0u) ^ ((q & 2) ? v[k].wrR[1] : 0u) ^
+                                       ((q & 4) ? v[k].wrR[3] : 0u);
+                    lds[a] = make_float2(acc[q], acc[q + 8]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active) ftile_store<IT, 1>(bufs, sts, base, io);
+}
+
+// ---------------------------------------------------------------------------
+// reverse pass (pass n_passes - 1 - step): psi and lambda tiles in LDS; `wgs`
+// workgroups per member loop over the tiles (two workgroups per CU).
+//
+// Outer product of a block, O[a][b] = sum_col lambda_in[a] conj(psi_in[b]),
+// straight from the un-apply results (lane l, register q: component l % 32 of
+// column 8 (q / 4) + 4 h + q % 4): as the A / B operands of
+// v_mfma_f32_16x16x4f32 (K index 4 s + l / 16) a register supplies
+// (re, im, re, im) of one block index at two columns, so
+//   O_re += A(lambda) B(psi),  O_im += A(lambda) B'(psi),
+// B' = psi with re and im exchanged across the two 16-lane halves and the
+// new re negated.  Per tile the 8 outputs per lane go to float32 LDS sums;
+// every FLUSH_TILES tiles those are added into this workgroup's float64
+// partials in global memory (no atomics: the slice is the workgroup's own).
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int FLUSH_TILES = 16;
+
+// B' operand for the imaginary part: the value of lane l ^ 16 (the other
+// 16-lane half holds the other component of the same amplitude), negated on
+// even 16-lane rows.  v_permlane16_swap with both operands equal leaves the
+// rows of the other half in its two results.
+__device__ __forceinline__ float swap16(float v, bool odd_row) {
+    const unsigned u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return odd_row ? __uint_as_float(r[0]) : -__uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void flush_osum(float* osum, int nblk, gptr<double> dst, int wgs, bool first) {
+    // dst: this workgroup's slice of block 0; block k at + k * wgs * OSTRIDE
+    for (int i = threadIdx.x; i < nblk * OSTRIDE; i += blockDim.x) {
+        const int k = i / OSTRIDE, e = i - k * OSTRIDE;
+        gptr<double> d = dst + size_t(k) * wgs * OSTRIDE + e;
+        const double v = double(osum[i]);
+        *d = first ? v : *d + v;
+        osum[i] = 0.f;
+    }
+}
+
+template <int IT>
+__global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, const Job single) {
+    __shared__ float2 lps[1 << FMAX_M];
+    __shared__ float2 llm[1 << FMAX_M];
+    __shared__ float osum[FUSED_MAX_BLOCKS * OSTRIDE];
+    int64_t local;
+    const Job J = load_job(jl, single, blockIdx.x, local);
+    cptr<FPass> P = as_const(J.frpasses) + (J.n_passes - 1 - jl.step);
+    const int m = P->m;
+    const FWork K = fwork(m);
+    const int t = threadIdx.x;
+    const int wave = uniform(t >> 6), lane = t & 63, h = lane >> 5;
+    const bool active = wave < K.nwv;
+    const int wgs = J.wgs;
+    const int64_t b = local / wgs;
+    const int wg = int(local - b * wgs);
+    gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
+    gptr<cx<float>> lam = as_global(static_cast<cx<float>*>(J.costate)) + b * J.stride;
+    gptr<const float> mats = as_global(static_cast<const float*>(J.fmats)) + size_t(b) * J.n_blocks * 2048 + 1024;
+    cptr<FPhase> phases = as_const(J.frphases);
+    const int f_begin = P->phase_begin, f_end = P->phase_end;
+    const int nblk = f_end - f_begin;
+    // blocks of a pass are numbered consecutively (visited in reverse)
+    const int blk0 = phases[f_end - 1].block;
+    gptr<double> odst = as_global(J.opart) + ((size_t(b) * J.n_blocks + blk0) * wgs + wg) * OSTRIDE;
+
+    for (int i = t; i < nblk * OSTRIDE; i += blockDim.x) osum[i] = 0.f;
+
+    const int n_c = lane & 31;
+    const bool odd_row = (lane & 16) != 0;
+    const int g4 = lane >> 4, bcol = lane & 15;
+    float* fp = reinterpret_cast<float*>(lps);
+    float* fl = reinterpret_cast<float*>(llm);
+    const int part = n_c >> 4;
+    float2* const bufs[2] = {lps, llm};
+    const gptr<cx<float>> sts[2] = {psi, lam};
+    const TileIO<IT> io = tile_io<IT>(P, t, K.nthr);
+    int pending = 0;
+    bool first = true;
+    for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
+        const uint64_t base = tile_base_f(uint64_t(tile), P->tile_mask, J.n);
+        __syncthreads();
+        if (active) ftile_load<IT, 2>(bufs, sts, base, io);
+        __syncthreads();
+        for (int f = f_begin; f < f_end; ++f) {
+            cptr<FPhase> F = phases + f;
+            float xp[CT_MAX][16], xl[CT_MAX][16], w[16];
+            FView v[CT_MAX];
+            if (active) {
+                read_mat(mats + size_t(F->block) * 2048, lane, w);
+#pragma unroll
+                for (int k = 0; k < CT_MAX; ++k) {
+                    if (k >= K.ctw) break;
+                    v[k] = fview(F, wave + K.nwv * k, lane);
+                    read_cols(lps, v[k], h, xp[k]);
+                    read_cols(llm, v[k], h, xl[k]);
+                }
+            }
+            __syncthreads();
+            if (active) {
+                const f16v z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+                f4v ore = z4, oim = z4, ore1 = z4, oim1 = z4;
+#pragma unroll
+                for (int k = 0; k < CT_MAX; ++k) {
+                    if (k >= K.ctw) break;
+                    f16v ap = z, al = z;
+#pragma unroll
+                    for (int s = 0; s < 16; ++s) {
+                        ap = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[k][s], w[s], ap, 0, 0, 0);
+                        al = __builtin_amdgcn_mfma_f32_32x32x2f32(xl[k][s], w[s], al, 0, 0, 0);
+                    }
+                    // two independent accumulator pairs (shorter dependency chains)
+#pragma unroll
+                    for (int q = 0; q < 16; q += 2) {
+                        const float s0 = swap16(ap[q], odd_row), s1 = swap16(ap[q + 1], odd_row);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q], ap[q], ore, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q], s0, oim, 0, 0, 0);
+                        ore1 = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q + 1], ap[q + 1], ore1, 0, 0, 0);
+                        oim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q + 1], s1, oim1, 0, 0, 0);
+                    }
+                    // write back: float component n_c (re if < 16) of block index n_c % 16
+                    const uint32_t jb = (v[k].wrR[0] & (0u - uint32_t(n_c & 1))) ^
+                                        (v[k].wrR[1] & (0u - uint32_t((n_c >> 1) & 1))) ^
+                                        (v[k].wrR[2] & (0u - uint32_t((n_c >> 2) & 1))) ^
+                                        (v[k].wrR[3] & (0u - uint32_t((n_c >> 3) & 1)));
+                    const uint32_t wb = v[k].wr_tile ^ jb ^ (v[k].wrC[2] & (0u - uint32_t(h)));
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        // column ct * 32 + 8 (q / 4) + 4 h + q % 4: bits 0, 1 <- q, bit 2 <- h, bits 3, 4 <- q / 4
+                        const uint32_t a = wb ^ ((q & 1) ? v[k].wrC[0] : 0u) ^ ((q & 2) ? v[k].wrC[1] : 0u) ^
+                                           ((q & 4) ? v[k].wrC[3] : 0u) ^ ((q & 8) ? v[k].wrC[4] : 0u);
+                        fp[2 * a + part] = ap[q];
+                        fl[2 * a + part] = al[q];
+                    }
+                    // one column tile at a time (register pressure)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // O[a = 4 (l / 16) + r][b = l % 16]
+                float* ob = osum + (F->block - blk0) * OSTRIDE;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = ((4 * g4 + r) * 16 + bcol) * 2;
+                    atomicAdd(ob + e, ore[r] + ore1[r]);
+                    atomicAdd(ob + e + 1, oim[r] + oim1[r]);
+                }
+            }
+            __syncthreads();
+        }
+        if (active) ftile_store<IT, 2>(bufs, sts, base, io);
+        if (++pending == FLUSH_TILES) {
+            __syncthreads();
+            flush_osum(osum, nblk, odst, wgs, first);
+            first = false;
+            pending = 0;
+        }
+    }
+    if (pending || first) {
+        __syncthreads();
+        flush_osum(osum, nblk, odst, wgs, first);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block matrices: M = G_L ... G_1 in float64 on the block's 4 bits, rounded
+// to float32 in the two lane-major operand orders (forward: A = M~, reverse:
+// B = M~, M~ = [[Re M, -Im M], [Im M, Re M]])
+// ---------------------------------------------------------------------------
+struct c64d {
+    double re, im;
+};
+__device__ __forceinline__ c64d cmul(c64d a, c64d b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// gate matrix in float64 (dim 2 or 4), rows = output, q0 = most significant bit
+__device__ int gate_u64(const Op& op, const float* prm, const cx<float>* cm, c64d* u) {
+    const int k = op.kind;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) u[i] = {0.0, 0.0};
+    double c = 0.0, s = 0.0;
+    if (k == K_RX || k == K_RY || k == K_RZ || k == K_RZZ) sincos(0.5 * double(prm[op.p0]), &s, &c);
+    const double r = 0.70710678118654752440;
+    switch (k) {
+        case K_RX: u[0] = {c, 0}; u[1] = {0, -s}; u[2] = {0, -s}; u[3] = {c, 0}; return 2;
+        case K_RY: u[0] = {c, 0}; u[1] = {-s, 0}; u[2] = {s, 0}; u[3] = {c, 0}; return 2;
+        case K_RZ: u[0] = {c, -s}; u[3] = {c, s}; return 2;
+        case K_H: u[0] = {r, 0}; u[1] = {r, 0}; u[2] = {r, 0}; u[3] = {-r, 0}; return 2;
+        case K_X: u[1] = {1, 0}; u[2] = {1, 0}; return 2;
+        case K_Y: u[1] = {0, -1}; u[2] = {0, 1}; return 2;
+        case K_Z: u[0] = {1, 0}; u[3] = {-1, 0}; return 2;
+        case K_S: u[0] = {1, 0}; u[3] = {0, 1}; return 2;
+        case K_U1: {
+            const int ix[4] = {0, 1, 4, 5};
+            for (int i = 0; i < 4; ++i) u[i] = {double(cm[16 * op.mat + ix[i]].re), double(cm[16 * op.mat + ix[i]].im)};
+            return 2;
+        }
+        case K_CNOT: u[0] = {1, 0}; u[5] = {1, 0}; u[11] = {1, 0}; u[14] = {1, 0}; return 4;
+        case K_CZ: u[0] = {1, 0}; u[5] = {1, 0}; u[10] = {1, 0}; u[15] = {-1, 0}; return 4;
+        case K_RZZ: u[0] = {c, -s}; u[5] = {c, s}; u[10] = {c, s}; u[15] = {c, -s}; return 4;
+        case K_FSIM: {
+            double ct, st, cp, sp;
+            sincos(double(prm[op.p0]), &st, &ct);
+            sincos(double(prm[op.p1]), &sp, &cp);
+            u[0] = {1, 0};
+            u[5] = {ct, 0}; u[6] = {0, -st};
+            u[9] = {0, -st}; u[10] = {ct, 0};
+            u[15] = {cp, -sp};
+            return 4;
+        }
+        default:   // K_U2
+            for (int i = 0; i < 16; ++i) u[i] = {double(cm[16 * op.mat + i].re), double(cm[16 * op.mat + i].im)};
+            return 4;
+    }
+}
+
+// gate-local index of block index a, and block index a with the gate bits set to beta
+__device__ __forceinline__ int gidx(const Op& op, int a, int dim) {
+    return dim == 2 ? ((a >> op.r0) & 1) : ((((a >> op.r0) & 1) << 1) | ((a >> op.r1) & 1));
+}
+__device__ __forceinline__ int gset(const Op& op, int a, int dim, int beta) {
+    if (dim == 2) return (a & ~(1 << op.r0)) | (beta << op.r0);
+    return (a & ~((1 << op.r0) | (1 << op.r1))) | ((beta >> 1) << op.r0) | ((beta & 1) << op.r1);
+}
+
+// one workgroup of 256 threads per (block, member): thread (row a, column c)
+__global__ void __launch_bounds__(256)
+k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
+             int64_t pstride, const cx<float>* __restrict__ cm, float* __restrict__ out, int want_rev) {
+    __shared__ c64d M[256];
+    const int f = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int t = threadIdx.x, a = t >> 4, c = t & 15;
+    const FPhase F = phases[f];
+    const float* prm = params ? params + b * pstride : nullptr;
+    M[t] = {a == c ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+    for (int o = F.op_begin; o < F.op_end; ++o) {
+        const Op op = ops[o];
+        c64d u[16];
+        const int dim = gate_u64(op, prm, cm, u);
+        const int al = gidx(op, a, dim);
+        c64d acc = {0.0, 0.0};
+        for (int be = 0; be < dim; ++be) {
+            const c64d x = M[gset(op, a, dim, be) * 16 + c];
+            const c64d p = cmul(u[al * dim + be], x);
+            acc.re += p.re;
+            acc.im += p.im;
+        }
+        __syncthreads();
+        M[t] = acc;
+        __syncthreads();
+    }
+    // real embedding entry (i, k), i, k < 32
+    auto emb = [&](int i, int k) -> float {
+        const c64d z = M[(i & 15) * 16 + (k & 15)];
+        if ((i < 16) == (k < 16)) return float(z.re);
+        return (i < 16) ? float(-z.im) : float(z.im);
+    };
+    float* dst = out + (size_t(b) * n_blocks + F.block) * 2048;
+    for (int e = t; e < 1024; e += 256) {
+        const int l = e >> 4, s = e & 15;
+        const int kk = 2 * s + (l >> 5), ll = l & 31;
+        dst[e] = emb(ll, kk);                     // forward: A[l % 32][2 s + h]
+        if (want_rev) dst[1024 + e] = emb(kk, ll);   // reverse: B[2 s + h][l % 32]
+    }
+}
+
+// ---------------------------------------------------------------------------
+// outer products: fixed-order sum over workgroups
+// ---------------------------------------------------------------------------
+__global__ void k_fused_osum(const double* __restrict__ opart, int64_t rows, int wgs, double* __restrict__ osum) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows * OSTRIDE) return;
+    const int64_t r = i / OSTRIDE, e = i - r * OSTRIDE;
+    const double* p = opart + size_t(r) * wgs * OSTRIDE + e;
+    double s = 0.0;
+    for (int w = 0; w < wgs; ++w) s += p[size_t(w) * OSTRIDE];
+    osum[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// gate gradients of a block from its outer product (float64 16 x 16 algebra);
+// writes slot values slots[b][slot] (the gradient slots of the tiled plan)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256)
+k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
+             int64_t pstride, const cx<float>* __restrict__ cm, const double* __restrict__ osum, int total_slots,
+             double* __restrict__ slots) {
+    __shared__ c64d X[256];
+    __shared__ double red[4];
+    const int f = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int t = threadIdx.x, a = t >> 4, c = t & 15;
+    const FPhase F = phases[f];
+    if (F.op_end == F.op_begin) return;
+    const float* prm = params ? params + b * pstride : nullptr;
+    const double* O = osum + (size_t(b) * n_blocks + F.block) * OSTRIDE;
+    double* sl = slots + size_t(b) * total_slots;
+    c64d u[16];
+    // X_1 = G_1 O
+    {
+        const Op op = ops[F.op_begin];
+        const int dim = gate_u64(op, prm, cm, u);
+        const int al = gidx(op, a, dim);
+        c64d acc = {0.0, 0.0};
+        for (int be = 0; be < dim; ++be) {
+            const int r = gset(op, a, dim, be);
+            const c64d p = cmul(u[al * dim + be], c64d{O[(r * 16 + c) * 2], O[(r * 16 + c) * 2 + 1]});
+            acc.re += p.re;
+            acc.im += p.im;
+        }
+        X[t] = acc;
+        __syncthreads();
+    }
+    for (int o = F.op_begin; o < F.op_end; ++o) {
+        const Op op = ops[o];
+        const int dim = gate_u64(op, prm, cm, u);
+        // U2 cotangent: partial trace of X over the block's other bits
+        if (op.kind == K_U2 && op.slot >= 0) {
+            // thread (a, c): contributes X[a][c] to entry (gidx a, gidx c) when the other bits agree
+            const int mask = (1 << op.r0) | (1 << op.r1);
+            const bool diag = (a & ~mask) == (c & ~mask);
+            const int e = gidx(op, a, 4) * 4 + gidx(op, c, 4);
+            for (int ee = 0; ee < 16; ++ee) {
+                const double vr = (diag && e == ee) ? X[t].re : 0.0;
+                const double vi = (diag && e == ee) ? X[t].im : 0.0;
+                const double sr = block_sum256(vr, red);
+                const double si = block_sum256(vi, red);
+                if (t == 0) {
+                    sl[op.slot + 2 * ee] = sr;
+                    sl[op.slot + 2 * ee + 1] = si;
+                }
+            }
+        }
+        // Y = X G^dagger
+        const int cl = gidx(op, c, dim);
+        c64d y = {0.0, 0.0};
+        for (int de = 0; de < dim; ++de) {
+            const c64d x = X[a * 16 + gset(op, c, dim, de)];
+            const c64d g = u[cl * dim + de];   // (G^dagger)[d][c] = conj(G[c][d])
+            y.re += x.re * g.re + x.im * g.im;
+            y.im += x.im * g.re - x.re * g.im;
+        }
+        __syncthreads();
+        X[t] = y;
+        __syncthreads();
+        // angle derivatives: 2 Im sum_ab Gen_ab conj(Y_ab)
+        if (op.slot >= 0 && op.kind != K_U2) {
+            const int al = gidx(op, a, dim), clc = gidx(op, c, dim);
+            const int mask = dim == 2 ? (1 << op.r0) : ((1 << op.r0) | (1 << op.r1));
+            const bool same_rest = (a & ~mask) == (c & ~mask);
+            double g0 = 0.0, g1 = 0.0;
+            if (same_rest) {
+                // conj(Y) = (y.re, -y.im); Gen entries per kind (times 2 for the derivative)
+                const double yr = y.re, yi = -y.im;
+                switch (op.kind) {
+                    case K_RX:   // X/2: Gen_01 = Gen_10 = 1/2
+                        if (al != clc) g0 = yi;   // 2 Im(0.5 * conj Y) = Im conj Y
+                        break;
+                    case K_RY:   // Y/2: Gen_01 = -i/2, Gen_10 = i/2
+                        if (al == 0 && clc == 1) g0 = -yr;   // 2 Im(-i/2 z) = -Re z
+                        if (al == 1 && clc == 0) g0 = yr;
+                        break;
+                    case K_RZ:   // Z/2
+                        if (al == clc) g0 = al == 0 ? yi : -yi;
+                        break;
+                    case K_RZZ:  // ZZ/2
+                        if (al == clc) g0 = (al == 0 || al == 3) ? yi : -yi;
+                        break;
+                    default:     // FSIM: theta (XX+YY)/2 couples 01 and 10 (weight 1); phi |11><11|
+                        if ((al == 1 && clc == 2) || (al == 2 && clc == 1)) g0 = 2.0 * yi;
+                        if (al == 3 && clc == 3) g1 = 2.0 * yi;
+                        break;
+                }
+            }
+            const double s0 = block_sum256(g0, red);
+            if (t == 0) sl[op.slot] = s0;
+            if (op.kind == K_FSIM) {
+                const double s1 = block_sum256(g1, red);
+                if (t == 0) sl[op.slot + 1] = s1;
+            }
+        }
+        // X_{next} = G_next Y
+        if (o + 1 < F.op_end) {
+            const Op nx = ops[o + 1];
+            const int nd = gate_u64(nx, prm, cm, u);
+            const int al = gidx(nx, a, nd);
+            c64d acc = {0.0, 0.0};
+            for (int be = 0; be < nd; ++be) {
+                const c64d p = cmul(u[al * nd + be], X[gset(nx, a, nd, be) * 16 + c]);
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            __syncthreads();
+            X[t] = acc;
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
+                             const void* cmats, int64_t batch, void* out, bool want_rev, hipStream_t st) {
+    if (n_blocks == 0 || batch == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fused_mats, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
+                       n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
+                       static_cast<float*>(out), int(want_rev));
+    return hipGetLastError();
+}
+
+// chunks per thread of the tile load: 8 at m = 12 (256 threads), 4 for m = 9..11
+hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (m == 12) hipLaunchKernelGGL((k_fused_fwd<8>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    else hipLaunchKernelGGL((k_fused_fwd<4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (m == 12) hipLaunchKernelGGL((k_fused_rev<8>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    else hipLaunchKernelGGL((k_fused_rev<4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_grad(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
+                             const void* cmats, int64_t batch, const double* opart, int wgs, double* osum,
+                             int total_slots, double* slots, hipStream_t st) {
+    if (n_blocks == 0 || batch == 0) return hipSuccess;
+    const int64_t rows = batch * int64_t(n_blocks);
+    hipLaunchKernelGGL(k_fused_osum, dim3(unsigned((rows * OSTRIDE + 255) / 256)), dim3(256), 0, st, opart, rows, wgs,
+                       osum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fused_grad, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
+                       n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
+                       osum, total_slots, slots);
+    return hipGetLastError();
+}
+
+}  // namespace tcng

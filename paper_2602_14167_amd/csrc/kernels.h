@@ -33,9 +33,16 @@ struct Job {
     const void* opm;          // member b at + b * n_gates * 16 entries
     double* part;             // member b at + b * total_slots * wgs
     double* epart;            // member b at + b * e_rows * e_wgs
+    const FPass* fpasses;     // fused plan (matrix-core blocks)
+    const FPhase* fphases;
+    const FPass* frpasses;
+    const FPhase* frphases;
+    const void* fmats;        // member b at + b * n_blocks * 2048 floats (forward and reverse operand orders)
+    double* opart;            // member b at + b * n_blocks * wgs * 512 (block outer products per workgroup)
     int64_t stride, batch, tiles;
     int32_t n, n_gates, n_passes, n_ppasses;
     int32_t total_slots, wgs, e_rows, e_wgs;
+    int32_t n_blocks, pad;
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
@@ -65,6 +72,20 @@ template <typename R, int RB>
 hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_pauli_tile(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
+
+// ---- fused passes (complex64, matrix cores)
+// block matrices of every forward phase for every member (float64 products rounded to float32)
+hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
+                             const void* cmats, int64_t batch, void* out, bool want_rev, hipStream_t st);
+// blocks: tiles * batch (forward), wgs * batch (reverse)
+// m: tile bits of the plan (9..12)
+hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st);
+hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st);
+// outer products summed over workgroups (osum: batch * n_blocks * 512), then the
+// gate gradient slots slots[b][slot] (total_slots per member)
+hipError_t launch_fused_grad(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
+                             const void* cmats, int64_t batch, const double* opart, int wgs, double* osum,
+                             int total_slots, double* slots, hipStream_t st);
 
 // ---- plain (one kernel per gate / per Pauli X-group)
 template <typename R>

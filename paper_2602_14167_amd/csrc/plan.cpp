@@ -264,6 +264,319 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
     return "";
 }
 
+void lds_layout(int m, uint32_t v_read, uint32_t v_write, int32_t* img) {
+    for (int b = 0; b < MAX_TILE_BITS; ++b) img[b] = 0;
+    int pos[MAX_TILE_BITS];
+    int k = 0;
+    for (int b = 0; b < m; ++b)
+        if ((v_read >> b) & 1) pos[b] = k++;
+    for (int b = 0; b < m; ++b)
+        if (!((v_read >> b) & 1)) pos[b] = k++;
+    for (int b = 0; b < m; ++b) img[b] = 1 << pos[b];
+    // bits written but not read in the low positions are folded onto the low
+    // positions of bits read but not written (XOR: the map stays a bijection)
+    int extra[MAX_TILE_BITS], free_pos[MAX_TILE_BITS], ne = 0, nf = 0;
+    for (int b = 0; b < m; ++b) {
+        const bool r = (v_read >> b) & 1, w = (v_write >> b) & 1;
+        if (w && !r) extra[ne++] = b;
+        if (r && !w) free_pos[nf++] = pos[b];
+    }
+    for (int i = 0; i < ne && i < nf; ++i) img[extra[i]] |= 1 << free_pos[i];
+}
+
+namespace {
+
+// the 5 lowest column bits of a phase (the bits 32 consecutive columns vary)
+uint32_t low_columns(int m, uint32_t rmask) {
+    uint32_t v = 0;
+    int k = 0;
+    for (int b = 0; b < m && k < 5; ++b)
+        if (!((rmask >> b) & 1)) { v |= 1u << b; ++k; }
+    return v;
+}
+
+// column bit c (in increasing order of the non-block bits) of a phase
+int column_bit(int m, uint32_t rmask, int c) {
+    for (int b = 0; b < m; ++b)
+        if (!((rmask >> b) & 1) && c-- == 0) return b;
+    return -1;
+}
+
+}  // namespace
+
+std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params, int m_max, int lo_cfg,
+                       FusedPlan& out) {
+    out = FusedPlan();
+    const int m = std::min(n, m_max);
+    const int lo = std::min(lo_cfg, m);
+    if (m < FUSED_K + 5) return "tile too small for fused blocks (needs 2^(K+5) amplitudes)";
+    out.m = m;
+    const uint64_t lo_mask = (lo >= 64) ? ~uint64_t(0) : ((uint64_t(1) << lo) - 1);
+    const uint64_t all_mask = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    const uint32_t ldst = 0x3Eu;   // tile load / store: 32 lanes vary local bits 1..5
+
+    std::vector<int> rem(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
+    out.gate_slot.assign(gates.size(), -1);
+
+    while (!rem.empty()) {
+        // ---- the tile (same choice as the tiled plan)
+        std::vector<uint64_t> cands;
+        if (n <= m) {
+            cands.push_back(all_mask);
+        } else {
+            const int h = m - lo;
+            for (int a = lo; a + h <= n; ++a) {
+                uint64_t w = lo_mask;
+                for (int q = a; q < a + h; ++q) w |= uint64_t(1) << q;
+                cands.push_back(w);
+            }
+            uint64_t T = lo_mask, blocked = 0;
+            for (int gi : rem) {
+                uint64_t qm = gate_qmask(gates[gi]);
+                if (!(qm & blocked) && popc(T | qm) <= m) T |= qm;
+                else blocked |= qm;
+            }
+            cands.push_back(fill_tile(T, n, m));
+        }
+        int best = -1, best_count = -1;
+        for (size_t c = 0; c < cands.size(); ++c) {
+            int cnt = schedule_into_tile(gates, rem, cands[c], RED_SLOTS, nullptr);
+            if (cnt > best_count) { best_count = cnt; best = int(c); }
+        }
+        if (best_count <= 0) return "planner made no progress";
+        const uint64_t T = cands[best];
+        std::vector<char> taken(rem.size(), 0);
+        schedule_into_tile(gates, rem, T, RED_SLOTS, &taken);
+        std::vector<int> sel, rest;
+        for (size_t i = 0; i < rem.size(); ++i) (taken[i] ? sel : rest).push_back(rem[i]);
+        rem.swap(rest);
+
+        FPass P{};
+        P.m = m;
+        P.lo = lo;
+        P.tile_mask = T;
+        int qubit_to_local[64];
+        for (int q = 0; q < 64; ++q) qubit_to_local[q] = -1;
+        for (int i = 0; i < 16; ++i) P.local_qubit[i] = -1;
+        int li = 0;
+        for (int q = 0; q < n; ++q)
+            if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = q; ++li; }
+        if (li != m) return "internal: tile size mismatch";
+
+        // ---- blocks: a gate joins while its qubits fit in FUSED_K local bits
+        // and no earlier gate of the pass left out shares a qubit with it
+        std::vector<uint32_t> rmasks;
+        const int first = int(out.phases.size());
+        std::vector<int> prem = sel;
+        while (!prem.empty()) {
+            if (int(out.phases.size()) - first == FUSED_MAX_BLOCKS) {
+                // the rest of the pass goes back to the queue (disjoint from
+                // everything it overtakes, so order is preserved)
+                std::vector<int> back = prem;
+                back.insert(back.end(), rem.begin(), rem.end());
+                std::sort(back.begin(), back.end());
+                rem.swap(back);
+                break;
+            }
+            uint32_t R = 0;
+            uint64_t blocked = 0;
+            std::vector<int> ph, rest2;
+            for (int gi : prem) {
+                const tcng_gate& g = gates[gi];
+                const uint64_t qm = gate_qmask(g);
+                uint32_t need = 1u << qubit_to_local[g.q0];
+                if (kind_arity(g.kind) == 2) need |= 1u << qubit_to_local[g.q1];
+                if (!(qm & blocked) && popc(R | need) <= FUSED_K) {
+                    R |= need;
+                    ph.push_back(gi);
+                } else {
+                    blocked |= qm;
+                    rest2.push_back(gi);
+                }
+            }
+            prem.swap(rest2);
+            for (int b = m - 1; b >= 0 && popc(R) < FUSED_K; --b) R |= 1u << b;
+            FPhase F{};
+            int reg_of_local[MAX_TILE_BITS];
+            for (int b = 0; b < MAX_TILE_BITS; ++b) reg_of_local[b] = -1;
+            int t = 0, kc = 0;
+            for (int i = 0; i < 9; ++i) F.C[i] = -1;
+            for (int b = 0; b < m; ++b) {
+                if ((R >> b) & 1) { F.R[t] = b; reg_of_local[b] = t; ++t; }
+                else if (kc < 9) F.C[kc++] = b;
+            }
+            F.block = out.n_blocks++;
+            F.op_begin = int(out.ops.size());
+            for (int gi : ph) {
+                const tcng_gate& g = gates[gi];
+                Op o{};
+                o.kind = g.kind;
+                o.p0 = g.p0;
+                o.p1 = g.p1;
+                o.mat = g.mat;
+                o.gate = gi;
+                o.slot = -1;
+                o.r0 = reg_of_local[qubit_to_local[g.q0]];
+                o.r1 = kind_arity(g.kind) == 2 ? reg_of_local[qubit_to_local[g.q1]] : -1;
+                o.lb0 = o.lb1 = -1;
+                o.type = kind_arity(g.kind);
+                out.ops.push_back(o);
+            }
+            F.op_end = int(out.ops.size());
+            out.phases.push_back(F);
+            rmasks.push_back(R);
+        }
+        const int last = int(out.phases.size());
+        P.phase_begin = first;
+        P.phase_end = last;
+        // gradient slots of the gates this pass applies (global numbering)
+        P.slot_base = out.total_slots;
+        int pass_slots = 0;
+        for (size_t o = size_t(out.phases[first].op_begin); o < out.ops.size(); ++o) {
+            const int sl = kind_slots(out.ops[o].kind);
+            if (sl) { out.ops[o].slot = P.slot_base + pass_slots; pass_slots += sl; }
+        }
+        P.n_slots = pass_slots;
+        out.total_slots += pass_slots;
+
+        // ---- layouts.  Forward: the load writes bits 1..5, phase f reads and
+        // writes its 5 lowest column bits, the store reads bits 1..5.
+        // Reverse (phases visited last to first): phase f writes its block
+        // bits plus column bit 2 (one float per lane, 32 components of two
+        // columns per 64 lanes).
+        const int F = last - first;
+        auto lowc = [&](int i) { return low_columns(m, rmasks[i]); };
+        lds_layout(m, lowc(0), ldst, P.ld);
+        for (int i = 0; i < F; ++i) {
+            FPhase& Ph = out.phases[first + i];
+            const uint32_t vw_prev = i == 0 ? ldst : lowc(i - 1);
+            lds_layout(m, lowc(i), vw_prev, Ph.rd);
+            if (i + 1 < F) lds_layout(m, lowc(i + 1), lowc(i), Ph.wr);
+            else lds_layout(m, ldst, lowc(i), Ph.wr);
+        }
+        lds_layout(m, ldst, lowc(F - 1), P.st);
+        out.passes.push_back(P);
+
+        FPass Q = P;
+        Q.phase_begin = int(out.rphases.size());
+        auto rev_w = [&](int i) { return rmasks[i] | (1u << column_bit(m, rmasks[i], 2)); };
+        lds_layout(m, lowc(F - 1), ldst, Q.ld);
+        for (int i = F - 1; i >= 0; --i) {
+            FPhase Ph = out.phases[first + i];
+            const uint32_t vw_prev = (i == F - 1) ? ldst : rev_w(i + 1);
+            lds_layout(m, lowc(i), vw_prev, Ph.rd);
+            if (i > 0) lds_layout(m, lowc(i - 1), rev_w(i), Ph.wr);
+            else lds_layout(m, ldst, rev_w(i), Ph.wr);
+            out.rphases.push_back(Ph);
+        }
+        lds_layout(m, ldst, rev_w(0), Q.st);
+        Q.phase_end = int(out.rphases.size());
+        out.rpasses.push_back(Q);
+    }
+
+    // ---- gradient assembly tables
+    std::vector<std::vector<int32_t>> per_param(std::max(n_params, 0));
+    for (const FPass& P : out.passes)
+        for (int f = P.phase_begin; f < P.phase_end; ++f)
+            for (int o = out.phases[f].op_begin; o < out.phases[f].op_end; ++o) {
+                const Op& op = out.ops[o];
+                if (op.slot < 0) continue;
+                const int gslot = op.slot;
+                const tcng_gate& g = gates[op.gate];
+                if (g.kind == K_U2) {
+                    out.gate_slot[op.gate] = gslot;
+                } else {
+                    if (g.p0 >= 0) per_param[g.p0].push_back(gslot);
+                    if (kind_nparams(g.kind) == 2 && g.p1 >= 0) per_param[g.p1].push_back(gslot + 1);
+                }
+            }
+    out.slot_ptr.assign(1, 0);
+    for (auto& v : per_param) {
+        std::sort(v.begin(), v.end());
+        out.slot_idx.insert(out.slot_idx.end(), v.begin(), v.end());
+        out.slot_ptr.push_back(int32_t(out.slot_idx.size()));
+    }
+    return "";
+}
+
+namespace {
+
+// rank over GF(2) of the vectors v[0..k)
+int gf2_rank(std::vector<uint32_t> v) {
+    int r = 0;
+    for (int bit = 31; bit >= 0; --bit) {
+        int piv = -1;
+        for (size_t i = r; i < v.size(); ++i)
+            if ((v[i] >> bit) & 1) { piv = int(i); break; }
+        if (piv < 0) continue;
+        std::swap(v[r], v[piv]);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (int(i) != r && ((v[i] >> bit) & 1)) v[i] ^= v[r];
+        ++r;
+    }
+    return r;
+}
+
+// layout img over m bits: a bijection, and 32-lane accesses varying the bits
+// of each pattern in `pats` spread over 32 distinct 8-byte bank pairs
+bool layout_ok(const int32_t* img, int m, std::initializer_list<uint32_t> pats) {
+    std::vector<uint32_t> all;
+    for (int b = 0; b < m; ++b) {
+        if (img[b] < 0 || img[b] >= (1 << m)) return false;
+        all.push_back(uint32_t(img[b]));
+    }
+    if (gf2_rank(all) != m) return false;
+    for (uint32_t p : pats) {
+        std::vector<uint32_t> low;
+        for (int b = 0; b < m; ++b)
+            if ((p >> b) & 1) low.push_back(uint32_t(img[b]) & 31u);
+        if (low.size() != 5 || gf2_rank(low) != 5) return false;
+    }
+    return true;
+}
+
+uint32_t phase_rmask(const FPhase& F) {
+    uint32_t r = 0;
+    for (int t = 0; t < FUSED_K; ++t) r |= 1u << F.R[t];
+    return r;
+}
+
+}  // namespace
+
+int check_fused_layouts(const FusedPlan& P) {
+    const int m = P.m;
+    const uint32_t ldst = 0x3Eu;
+    int bad = 0;
+    for (const FPass& Q : P.passes) {
+        const int F = Q.phase_end - Q.phase_begin;
+        auto low = [&](int i) { return low_columns(m, phase_rmask(P.phases[Q.phase_begin + i])); };
+        bad += !layout_ok(Q.ld, m, {ldst, low(0)});
+        for (int i = 0; i < F; ++i) {
+            const FPhase& Ph = P.phases[Q.phase_begin + i];
+            bad += !layout_ok(Ph.rd, m, {low(i)});
+            bad += !layout_ok(Ph.wr, m, {low(i), i + 1 < F ? low(i + 1) : ldst});
+        }
+        bad += !layout_ok(Q.st, m, {ldst, low(F - 1)});
+    }
+    for (const FPass& Q : P.rpasses) {
+        const int F = Q.phase_end - Q.phase_begin;   // visiting order
+        auto low = [&](int i) { return low_columns(m, phase_rmask(P.rphases[Q.phase_begin + i])); };
+        auto wpat = [&](int i) {
+            const FPhase& Ph = P.rphases[Q.phase_begin + i];
+            return phase_rmask(Ph) | (1u << Ph.C[2]);
+        };
+        bad += !layout_ok(Q.ld, m, {ldst, low(0)});
+        for (int i = 0; i < F; ++i) {
+            const FPhase& Ph = P.rphases[Q.phase_begin + i];
+            bad += !layout_ok(Ph.rd, m, {low(i)});
+            bad += !layout_ok(Ph.wr, m, {wpat(i), i + 1 < F ? low(i + 1) : ldst});
+        }
+        bad += !layout_ok(Q.st, m, {ldst, wpat(F - 1)});
+    }
+    return bad;
+}
+
 std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const TileConfig& cfg, PauliPlan& out) {
     out = PauliPlan();
     out.cfg = cfg;

@@ -30,6 +30,17 @@ struct CircuitPlan {
     std::vector<int32_t> gate_slot;
 };
 
+// Fused passes: the same tiles as the tiled plan, phases of FUSED_K bits that
+// hold every qubit of their gates, one block matrix per phase.
+struct FusedPlan {
+    int m = 0;
+    std::vector<FPass> passes, rpasses;     // reverse: phases listed in the order the reverse sweep visits them
+    std::vector<FPhase> phases, rphases;
+    std::vector<Op> ops;                    // gates of the forward phases (r0/r1 = bit of the block index)
+    int n_blocks = 0, total_slots = 0;
+    std::vector<int32_t> slot_ptr, slot_idx, gate_slot;
+};
+
 struct PauliPlan {
     TileConfig cfg{};
     std::vector<PPass> passes;
@@ -47,6 +58,14 @@ struct PauliTermHost {
 // Returns an empty string on success, else the reason the plan is impossible.
 std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_params, const TileConfig& cfg,
                          CircuitPlan& out);
+std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params, int m_max, int lo,
+                       FusedPlan& out);
+// LDS layout of a tile of 2^m amplitudes: img[b] = address of local bit b
+// alone; 32-lane accesses varying the local bits of v_read (5 bits), or of
+// v_write, map to 32 distinct 8-byte bank pairs.
+void lds_layout(int m, uint32_t v_read, uint32_t v_write, int32_t* img);
+// number of layouts of a fused plan that are not bank-conflict-free bijections
+int check_fused_layouts(const FusedPlan& P);
 std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const TileConfig& cfg, PauliPlan& out);
 
 // Plain path: terms grouped by full X-mask.

@@ -125,3 +125,54 @@ def test_planner_workloads(P, oracle_mod):
     c = W.cfg4(count=4)
     for cc in c["circuits"]:
         _check_schedule(P, oracle_mod, cc["n"], cc["gates"], 0, None, cc["mats"], torch.complex64)
+
+
+def _check_fused_schedule(P, oracle_mod, n, gates, n_params, params, mats):
+    order, pass_of, block_of, npass, nblk, bad = P.fused_plan_inspect(n, gates, n_params)
+    G = len(gates)
+    assert bad == 0                                   # every LDS layout a bank-conflict-free bijection
+    assert sorted(order.tolist()) == list(range(G))
+    pos = np.empty(G, int)
+    pos[order] = np.arange(G)
+    qsets = [{int(g[1])} | ({int(g[2])} if g[2] >= 0 else set()) for g in gates]
+    last = {}
+    for i in range(G):
+        for q in qsets[i]:
+            if q in last:
+                assert pos[last[q]] < pos[i]
+            last[q] = i
+    assert np.all(np.diff(pass_of) >= 0) and np.all(np.diff(block_of) >= 0)
+    # a block touches at most 4 qubits
+    for b in range(nblk):
+        qs = set().union(*[qsets[gi] for gi in order[block_of == b]])
+        assert 1 <= len(qs) <= 4
+    if n <= 14:
+        a = oracle_mod.run(n, gates, params, mats)
+        b = oracle_mod.run(n, gates[order], params, mats)
+        np.testing.assert_allclose(a, b, atol=1e-12)
+    return npass, nblk
+
+
+@pytest.mark.parametrize("n", [9, 12, 14])
+def test_fused_planner_random_circuits(P, oracle_mod, n):
+    r = np.random.default_rng(60 + n)
+    gates, params, mats = W.random_circuit(n, 200, r)
+    _check_fused_schedule(P, oracle_mod, n, gates, len(params), params, mats)
+
+
+def test_fused_planner_workloads(P, oracle_mod):
+    c = W.cfg2()
+    npass, nblk = _check_fused_schedule(P, oracle_mod, 28, c["gates"], c["n_params"], c["params"], None)
+    assert nblk < len(c["gates"]) // 5          # blocks hold many gates each
+    c = W.cfg5()
+    _check_fused_schedule(P, oracle_mod, 32, c["gates"], c["n_params"], c["params"], None)
+    c = W.cfg3(batch=2)
+    _check_fused_schedule(P, oracle_mod, 16, c["gates"], c["n_params"], c["params"][0], None)
+    for cc in W.cfg4(count=4)["circuits"]:
+        _check_fused_schedule(P, oracle_mod, cc["n"], cc["gates"], 0, None, cc["mats"])
+
+
+def test_fused_planner_rejects_small_tiles(P):
+    gates = np.array([W.gate(W.RY, 0, p0=0)], np.int32)
+    with pytest.raises(P.TcngError):
+        P.fused_plan_inspect(8, gates, 1)

@@ -1,7 +1,7 @@
 """Checks at the measured sizes (n = 28, 30, 32), where the oracle cannot run
 the whole workload: closed forms, invariants and exact identities that hold
-at any size, evaluated on the HIP path in the launch configuration the
-benchmark times (tiled passes, complex64).
+at any size, evaluated on the HIP path in the launch configurations the
+benchmark times (tiled and fused passes, complex64).
 
 * product states (one HEA layer without CNOTs): <H> and the gradient in
   closed form from the Bloch vectors;
@@ -44,8 +44,9 @@ def product_state_reference(params, n, J, h):
     return E, np.concatenate([gt, gf])
 
 
+@pytest.mark.parametrize("mode", ["tiled", "fused"])
 @pytest.mark.parametrize("n", [28, 30])
-def test_product_state_closed_form(P, n):
+def test_product_state_closed_form(P, n, mode):
     gates, npar = W.hea_gates(n, 1, cnot=False)
     params = np.random.default_rng(n).uniform(0, 2 * np.pi, npar)
     p32 = W.round_params(params, "c64")
@@ -53,7 +54,7 @@ def test_product_state_closed_form(P, n):
     codes, coeffs = W.tfim_1d(n, J, h)
     circ = P.Circuit(n, gates, npar)
     H = P.PauliSum(n, codes, coeffs)
-    E, g = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float32, device="cuda"), H)
+    E, g = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float32, device="cuda"), H, mode=mode)
     Er, gr = product_state_reference(p32, n, J, h)
     S = np.abs(coeffs).sum()
     assert abs(E.item() - Er) <= 1e-5 * S
@@ -82,7 +83,8 @@ def test_ghz_and_single_rotation_n30(P):
     torch.cuda.empty_cache()
 
 
-def test_hea28_c64_vs_c128_and_invariants(P):
+@pytest.mark.parametrize("mode", ["tiled", "fused"])
+def test_hea28_c64_vs_c128_and_invariants(P, mode):
     c = W.cfg2()
     n = c["n"]
     circ = P.Circuit(n, c["gates"], c["n_params"])
@@ -90,7 +92,7 @@ def test_hea28_c64_vs_c128_and_invariants(P):
     S = np.abs(c["coeffs"]).sum()
     p32 = W.round_params(c["params"], "c64")
     psi = P.new_state(n, 1, torch.complex64)
-    E32, g32 = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float32, device="cuda"), H, psi=psi)
+    E32, g32 = P.expect_grad(circ, torch.tensor(p32, dtype=torch.float32, device="cuda"), H, psi=psi, mode=mode)
     # reverse sweep recomputed |0..0>
     assert abs(psi[0, 0].item() - 1) < 1e-4
     assert torch.max(torch.abs(psi[0, 1:])).item() < 1e-4
@@ -112,7 +114,8 @@ def test_hea28_c64_vs_c128_and_invariants(P):
     assert np.max(np.abs(g32 - g64)) <= 1e-4 * S
 
 
-def test_fsim32_shift_rule_and_finite_differences(P):
+@pytest.mark.parametrize("mode", ["tiled", "fused"])
+def test_fsim32_shift_rule_and_finite_differences(P, mode):
     c = W.cfg5()
     n = c["n"]
     circ = P.Circuit(n, c["gates"], c["n_params"])
@@ -121,13 +124,13 @@ def test_fsim32_shift_rule_and_finite_differences(P):
     p = W.round_params(c["params"], "c64")
     psi = P.new_state(n, 1, torch.complex64)
     lam = torch.empty_like(psi)
-    E, g = P.expect_grad(circ, torch.tensor(p, dtype=torch.float32, device="cuda"), H, psi=psi, lam=lam)
+    E, g = P.expect_grad(circ, torch.tensor(p, dtype=torch.float32, device="cuda"), H, psi=psi, lam=lam, mode=mode)
     E, g = E.item(), g.cpu().numpy()[0]
     assert abs(psi[0, 0].item() - 1) < 1e-3
 
     def energy(pp):
         P.state_init(psi)
-        P.run_circuit(circ, torch.tensor(pp, dtype=torch.float32, device="cuda"), psi)
+        P.run_circuit(circ, torch.tensor(pp, dtype=torch.float32, device="cuda"), psi, mode=mode)
         return P.expect_pauli(psi, H).item()
 
     assert abs(energy(p) - E) <= 1e-5 * S

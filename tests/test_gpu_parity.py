@@ -91,7 +91,7 @@ def test_apply_gate_matches_oracle(P, oracle_mod, dtype, k):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 @pytest.mark.parametrize("n", [1, 2, 5, 9, 10, 11, 12, 13, 14, 16])
 def test_run_circuit_random_all_kinds(P, oracle_mod, dtype, mode, n):
     r = np.random.default_rng(100 + n)
@@ -118,7 +118,7 @@ def test_tiled_and_plain_agree_on_hea(P, dtype):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 @pytest.mark.parametrize("n,kind", [(3, "random"), (11, "random"), (12, "tfim"), (15, "xxz"), (16, "2local"),
                                     (16, "random")])
 def test_expect_pauli_matches_oracle(P, oracle_mod, dtype, mode, n, kind):
@@ -184,7 +184,7 @@ def check_expect_grad(P, oracle_mod, n, gates, params_b, mats, codes, coeffs, dt
     return E, g
 
 
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 def test_cfg1_state_energy_gradient_c128(P, oracle_mod, mode):
     """n=10 complex128 HEA L=4, TFIM +ZZ +X: final state, <H>, gradient at 1e-12."""
     c = W.cfg1()
@@ -195,7 +195,7 @@ def test_cfg1_state_energy_gradient_c128(P, oracle_mod, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 def test_hea_tfim_batched(P, oracle_mod, dtype, mode):
     """Reduced-size instance of the n=28 HEA/TFIM workload (same generator), batch 3."""
     c = W.cfg2(n=16, layers=3)
@@ -205,7 +205,7 @@ def test_hea_tfim_batched(P, oracle_mod, dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 def test_xxz_batched(P, oracle_mod, dtype, mode):
     """Batched XXZ workload (n=16, L=8) on a subset of parameter sets."""
     c = W.cfg3(batch=4)
@@ -213,7 +213,7 @@ def test_xxz_batched(P, oracle_mod, dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 @pytest.mark.parametrize("n", [5, 11, 12, 14])
 def test_random_circuits_all_kinds_with_gate_gradients(P, oracle_mod, dtype, mode, n):
     r = np.random.default_rng(500 + n)
@@ -226,14 +226,14 @@ def test_random_circuits_all_kinds_with_gate_gradients(P, oracle_mod, dtype, mod
     check_expect_grad(P, oracle_mod, n, gates, pb, mats, codes, coeffs, dtype, mode, lie=True, init=init)
 
 
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 def test_fsim_brickwork_2d_tfim(P, oracle_mod, mode):
     """Reduced-size instance of the n=32 fSim / 2D TFIM workload: 4x4 lattice, depth 8."""
     c = W.cfg5(rows=4, cols=4, depth=8)
     check_expect_grad(P, oracle_mod, 16, c["gates"], c["params"][None, :], None, c["codes"], c["coeffs"], "c64", mode)
 
 
-@pytest.mark.parametrize("mode", ["tiled", "plain"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
 def test_haar_brickwork_lie_gradients(P, oracle_mod, mode):
     """Haar brick-wall circuits with random 2-local H (the uneven-batch generator, small n)."""
     c = W.cfg4(count=3, n_lo=11, n_hi=14, d_lo=2, d_hi=6, seed=44)
