@@ -286,9 +286,10 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
 // (re, im, re, im) of one block index at two columns, so
 //   O_re += A(lambda) B(psi),  O_im += A(lambda) B'(psi),
 // B' = psi with re and im exchanged across the two 16-lane halves and the
-// new re negated.  Per tile the 8 outputs per lane go to float32 LDS sums;
-// every FLUSH_TILES tiles those are added into this workgroup's float64
-// partials in global memory (no atomics: the slice is the workgroup's own).
+// new re negated.  Each wave's 512 sums go to a staging area; after the
+// block's barrier every thread adds two of the 512 entries over the waves
+// into its registers (no atomics), and every FLUSH_TILES tiles into this
+// workgroup's float64 partials in global memory (its own slice).
 // ---------------------------------------------------------------------------
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int FLUSH_TILES = 16;
@@ -303,14 +304,43 @@ __device__ __forceinline__ float swap16(float v, bool odd_row) {
     return odd_row ? __uint_as_float(r[0]) : -__uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ void flush_osum(float* osum, int nblk, gptr<double> dst, int wgs, bool first) {
-    // dst: this workgroup's slice of block 0; block k at + k * wgs * OSTRIDE
-    for (int i = threadIdx.x; i < nblk * OSTRIDE; i += blockDim.x) {
-        const int k = i / OSTRIDE, e = i - k * OSTRIDE;
-        gptr<double> d = dst + size_t(k) * wgs * OSTRIDE + e;
-        const double v = double(osum[i]);
-        *d = first ? v : *d + v;
-        osum[i] = 0.f;
+// staging index e = r * 128 + part * 64 + lane of MFMA output register r
+// (O[a = 4 (lane / 16) + r][b = lane % 16], part 0 = re) -> O entry
+__device__ __forceinline__ int stage_to_o(int e) {
+    const int r = e >> 7, part = (e >> 6) & 1, ln = e & 63;
+    return ((4 * (ln >> 4) + r) * 16 + (ln & 15)) * 2 + part;
+}
+
+// add the staged sums of the waves into the thread's two entries of block slot kb
+__device__ __forceinline__ void stage_reduce(const float* stage, int nwv, int kb, float (&acc)[FUSED_MAX_BLOCKS][2]) {
+    float v0 = 0.f, v1 = 0.f;
+    for (int w = 0; w < nwv; ++w) {
+        v0 += stage[w * OSTRIDE + threadIdx.x];
+        v1 += stage[w * OSTRIDE + threadIdx.x + 256];
+    }
+    // every slot takes an add (zero for the others): a uniform runtime slot
+    // must not become an indexed register access
+#pragma unroll
+    for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) {
+        const bool hit = k == kb;
+        acc[k][0] += hit ? v0 : 0.f;
+        acc[k][1] += hit ? v1 : 0.f;
+    }
+}
+
+__device__ __forceinline__ void flush_acc(float (&acc)[FUSED_MAX_BLOCKS][2], int nblk, gptr<double> dst, int wgs,
+                                          bool first) {
+    // dst: this workgroup's slice of the pass's first block; block k at + k * wgs * OSTRIDE
+#pragma unroll
+    for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) {
+        if (k >= nblk) break;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            gptr<double> d = dst + size_t(k) * wgs * OSTRIDE + stage_to_o(int(threadIdx.x) + 256 * i);
+            const double v = double(acc[k][i]);
+            *d = first ? v : *d + v;
+            acc[k][i] = 0.f;
+        }
     }
 }
 
@@ -318,7 +348,7 @@ template <int IT>
 __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, const Job single) {
     __shared__ float2 lps[1 << FMAX_M];
     __shared__ float2 llm[1 << FMAX_M];
-    __shared__ float osum[FUSED_MAX_BLOCKS * OSTRIDE];
+    __shared__ float stage[(FTHREADS / 64) * OSTRIDE];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     cptr<FPass> P = as_const(J.frpasses) + (J.n_passes - 1 - jl.step);
@@ -340,13 +370,15 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
     const int blk0 = phases[f_end - 1].block;
     gptr<double> odst = as_global(J.opart) + ((size_t(b) * J.n_blocks + blk0) * wgs + wg) * OSTRIDE;
 
-    for (int i = t; i < nblk * OSTRIDE; i += blockDim.x) osum[i] = 0.f;
+    float acc[FUSED_MAX_BLOCKS][2];
+#pragma unroll
+    for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) acc[k][0] = acc[k][1] = 0.f;
 
     const int n_c = lane & 31;
     const bool odd_row = (lane & 16) != 0;
-    const int g4 = lane >> 4, bcol = lane & 15;
     float* fp = reinterpret_cast<float*>(lps);
     float* fl = reinterpret_cast<float*>(llm);
+    float* my_stage = stage + wave * OSTRIDE + lane;
     const int part = n_c >> 4;
     float2* const bufs[2] = {lps, llm};
     const gptr<cx<float>> sts[2] = {psi, lam};
@@ -360,6 +392,8 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
         __syncthreads();
         for (int f = f_begin; f < f_end; ++f) {
             cptr<FPhase> F = phases + f;
+            // the previous block's staged outer products (after its closing barrier)
+            if (f > f_begin) stage_reduce(stage, K.nwv, phases[f - 1].block - blk0, acc);
             float xp[CT_MAX][16], xl[CT_MAX][16], w[16];
             FView v[CT_MAX];
             if (active) {
@@ -412,29 +446,23 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
                     // one column tile at a time (register pressure)
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                // O[a = 4 (l / 16) + r][b = l % 16]
-                float* ob = osum + (F->block - blk0) * OSTRIDE;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int e = ((4 * g4 + r) * 16 + bcol) * 2;
-                    atomicAdd(ob + e, ore[r] + ore1[r]);
-                    atomicAdd(ob + e + 1, oim[r] + oim1[r]);
+                    my_stage[r * 128] = ore[r] + ore1[r];
+                    my_stage[r * 128 + 64] = oim[r] + oim1[r];
                 }
             }
             __syncthreads();
         }
+        stage_reduce(stage, K.nwv, phases[f_end - 1].block - blk0, acc);
         if (active) ftile_store<IT, 2>(bufs, sts, base, io);
         if (++pending == FLUSH_TILES) {
-            __syncthreads();
-            flush_osum(osum, nblk, odst, wgs, first);
+            flush_acc(acc, nblk, odst, wgs, first);
             first = false;
             pending = 0;
         }
     }
-    if (pending || first) {
-        __syncthreads();
-        flush_osum(osum, nblk, odst, wgs, first);
-    }
+    if (pending || first) flush_acc(acc, nblk, odst, wgs, first);
 }
 
 // ---------------------------------------------------------------------------
