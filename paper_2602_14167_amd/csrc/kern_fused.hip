@@ -530,29 +530,35 @@ __global__ void __launch_bounds__(256)
 k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
              int64_t pstride, const cx<float>* __restrict__ cm, float* __restrict__ out, int want_rev) {
     __shared__ c64d M[256];
+    __shared__ c64d U[16];
     const int f = blockIdx.x;
     const int64_t b = blockIdx.y;
     const int t = threadIdx.x, a = t >> 4, c = t & 15;
     const FPhase F = phases[f];
     const float* prm = params ? params + b * pstride : nullptr;
     M[t] = {a == c ? 1.0 : 0.0, 0.0};
-    __syncthreads();
     for (int o = F.op_begin; o < F.op_end; ++o) {
         const Op op = ops[o];
-        c64d u[16];
-        const int dim = gate_u64(op, prm, cm, u);
+        if (t == 0) {   // gate matrix into LDS (indexed by the threads below)
+            c64d u[16];
+            gate_u64(op, prm, cm, u);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) U[i] = u[i];
+        }
+        __syncthreads();
+        const int dim = kind_arity(op.kind) == 2 ? 4 : 2;
         const int al = gidx(op, a, dim);
         c64d acc = {0.0, 0.0};
         for (int be = 0; be < dim; ++be) {
             const c64d x = M[gset(op, a, dim, be) * 16 + c];
-            const c64d p = cmul(u[al * dim + be], x);
+            const c64d p = cmul(U[al * dim + be], x);
             acc.re += p.re;
             acc.im += p.im;
         }
         __syncthreads();
         M[t] = acc;
-        __syncthreads();
     }
+    __syncthreads();
     // real embedding entry (i, k), i, k < 32
     auto emb = [&](int i, int k) -> float {
         const c64d z = M[(i & 15) * 16 + (k & 15)];
@@ -583,128 +589,151 @@ __global__ void k_fused_osum(const double* __restrict__ opart, int64_t rows, int
 
 // ---------------------------------------------------------------------------
 // gate gradients of a block from its outer product (float64 16 x 16 algebra);
-// writes slot values slots[b][slot] (the gradient slots of the tiled plan)
+// writes slot values slots[b][slot] (the gradient slots of the tiled plan).
+// One wave per (block, member); lane t holds X entries e = t + 64 i.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
+// gate matrix into LDS (lane 0 forms it; rows = output)
+__device__ __forceinline__ int load_gate(const Op& op, const float* prm, const cx<float>* cm, c64d* U) {
+    int dim = kind_arity(op.kind) == 2 ? 4 : 2;
+    if (threadIdx.x == 0) {
+        c64d u[16];
+        gate_u64(op, prm, cm, u);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) U[i] = u[i];
+    }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    return dim;
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
              int64_t pstride, const cx<float>* __restrict__ cm, const double* __restrict__ osum, int total_slots,
              double* __restrict__ slots) {
     __shared__ c64d X[256];
-    __shared__ double red[4];
+    __shared__ c64d U[16];
     const int f = blockIdx.x;
     const int64_t b = blockIdx.y;
-    const int t = threadIdx.x, a = t >> 4, c = t & 15;
+    const int t = threadIdx.x;
     const FPhase F = phases[f];
     if (F.op_end == F.op_begin) return;
     const float* prm = params ? params + b * pstride : nullptr;
     const double* O = osum + (size_t(b) * n_blocks + F.block) * OSTRIDE;
     double* sl = slots + size_t(b) * total_slots;
-    c64d u[16];
+    c64d x[4];
     // X_1 = G_1 O
     {
         const Op op = ops[F.op_begin];
-        const int dim = gate_u64(op, prm, cm, u);
-        const int al = gidx(op, a, dim);
-        c64d acc = {0.0, 0.0};
-        for (int be = 0; be < dim; ++be) {
-            const int r = gset(op, a, dim, be);
-            const c64d p = cmul(u[al * dim + be], c64d{O[(r * 16 + c) * 2], O[(r * 16 + c) * 2 + 1]});
-            acc.re += p.re;
-            acc.im += p.im;
+        const int dim = load_gate(op, prm, cm, U);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = t + 64 * i, a = e >> 4, c = e & 15;
+            const int al = gidx(op, a, dim);
+            c64d acc = {0.0, 0.0};
+            for (int be = 0; be < dim; ++be) {
+                const int r = gset(op, a, dim, be);
+                const c64d p = cmul(U[al * dim + be], c64d{O[(r * 16 + c) * 2], O[(r * 16 + c) * 2 + 1]});
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            x[i] = acc;
         }
-        X[t] = acc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) X[t + 64 * i] = x[i];
         __syncthreads();
     }
     for (int o = F.op_begin; o < F.op_end; ++o) {
         const Op op = ops[o];
-        const int dim = gate_u64(op, prm, cm, u);
-        // U2 cotangent: partial trace of X over the block's other bits
+        const int dim = kind_arity(op.kind) == 2 ? 4 : 2;   // U holds this gate (loaded before)
+        // U2 cotangent: partial trace of X over the block's other two bits
         if (op.kind == K_U2 && op.slot >= 0) {
-            // thread (a, c): contributes X[a][c] to entry (gidx a, gidx c) when the other bits agree
-            const int mask = (1 << op.r0) | (1 << op.r1);
-            const bool diag = (a & ~mask) == (c & ~mask);
-            const int e = gidx(op, a, 4) * 4 + gidx(op, c, 4);
-            for (int ee = 0; ee < 16; ++ee) {
-                const double vr = (diag && e == ee) ? X[t].re : 0.0;
-                const double vi = (diag && e == ee) ? X[t].im : 0.0;
-                const double sr = block_sum256(vr, red);
-                const double si = block_sum256(vi, red);
-                if (t == 0) {
-                    sl[op.slot + 2 * ee] = sr;
-                    sl[op.slot + 2 * ee + 1] = si;
+            if (t < 16) {
+                const int al = t >> 2, be = t & 3;
+                double sr = 0.0, si = 0.0;
+                for (int rest = 0; rest < 16; ++rest) {
+                    if (rest & ((1 << op.r0) | (1 << op.r1))) continue;
+                    const c64d v = X[gset(op, rest, 4, al) * 16 + gset(op, rest, 4, be)];
+                    sr += v.re;
+                    si += v.im;
                 }
+                sl[op.slot + 2 * t] = sr;
+                sl[op.slot + 2 * t + 1] = si;
             }
         }
         // Y = X G^dagger
-        const int cl = gidx(op, c, dim);
-        c64d y = {0.0, 0.0};
-        for (int de = 0; de < dim; ++de) {
-            const c64d x = X[a * 16 + gset(op, c, dim, de)];
-            const c64d g = u[cl * dim + de];   // (G^dagger)[d][c] = conj(G[c][d])
-            y.re += x.re * g.re + x.im * g.im;
-            y.im += x.im * g.re - x.re * g.im;
+        c64d y[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = t + 64 * i, a = e >> 4, c = e & 15;
+            const int cl = gidx(op, c, dim);
+            c64d acc = {0.0, 0.0};
+            for (int de = 0; de < dim; ++de) {
+                const c64d xv = X[a * 16 + gset(op, c, dim, de)];
+                const c64d g = U[cl * dim + de];   // (G^dagger)[d][c] = conj(G[c][d])
+                acc.re += xv.re * g.re + xv.im * g.im;
+                acc.im += xv.im * g.re - xv.re * g.im;
+            }
+            y[i] = acc;
         }
         __syncthreads();
-        X[t] = y;
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) X[t + 64 * i] = y[i];
         // angle derivatives: 2 Im sum_ab Gen_ab conj(Y_ab)
         if (op.slot >= 0 && op.kind != K_U2) {
-            const int al = gidx(op, a, dim), clc = gidx(op, c, dim);
-            const int mask = dim == 2 ? (1 << op.r0) : ((1 << op.r0) | (1 << op.r1));
-            const bool same_rest = (a & ~mask) == (c & ~mask);
             double g0 = 0.0, g1 = 0.0;
-            if (same_rest) {
-                // conj(Y) = (y.re, -y.im); Gen entries per kind (times 2 for the derivative)
-                const double yr = y.re, yi = -y.im;
+            const int mask = dim == 2 ? (1 << op.r0) : ((1 << op.r0) | (1 << op.r1));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = t + 64 * i, a = e >> 4, c = e & 15;
+                if ((a & ~mask) != (c & ~mask)) continue;
+                const int al = gidx(op, a, dim), clc = gidx(op, c, dim);
+                const double yr = y[i].re, yi = -y[i].im;   // conj(Y)
                 switch (op.kind) {
-                    case K_RX:   // X/2: Gen_01 = Gen_10 = 1/2
-                        if (al != clc) g0 = yi;   // 2 Im(0.5 * conj Y) = Im conj Y
+                    case K_RX:   // X/2
+                        if (al != clc) g0 += yi;
                         break;
-                    case K_RY:   // Y/2: Gen_01 = -i/2, Gen_10 = i/2
-                        if (al == 0 && clc == 1) g0 = -yr;   // 2 Im(-i/2 z) = -Re z
-                        if (al == 1 && clc == 0) g0 = yr;
+                    case K_RY:   // Y/2: 2 Im(-i/2 z) = -Re z, 2 Im(i/2 z) = Re z
+                        if (al == 0 && clc == 1) g0 -= yr;
+                        if (al == 1 && clc == 0) g0 += yr;
                         break;
                     case K_RZ:   // Z/2
-                        if (al == clc) g0 = al == 0 ? yi : -yi;
+                        if (al == clc) g0 += al == 0 ? yi : -yi;
                         break;
                     case K_RZZ:  // ZZ/2
-                        if (al == clc) g0 = (al == 0 || al == 3) ? yi : -yi;
+                        if (al == clc) g0 += (al == 0 || al == 3) ? yi : -yi;
                         break;
                     default:     // FSIM: theta (XX+YY)/2 couples 01 and 10 (weight 1); phi |11><11|
-                        if ((al == 1 && clc == 2) || (al == 2 && clc == 1)) g0 = 2.0 * yi;
-                        if (al == 3 && clc == 3) g1 = 2.0 * yi;
+                        if ((al == 1 && clc == 2) || (al == 2 && clc == 1)) g0 += 2.0 * yi;
+                        if (al == 3 && clc == 3) g1 += 2.0 * yi;
                         break;
                 }
             }
-            const double s0 = block_sum256(g0, red);
+            const double s0 = wave_sum(g0);
             if (t == 0) sl[op.slot] = s0;
             if (op.kind == K_FSIM) {
-                const double s1 = block_sum256(g1, red);
+                const double s1 = wave_sum(g1);
                 if (t == 0) sl[op.slot + 1] = s1;
             }
         }
+        __syncthreads();
         // X_{next} = G_next Y
         if (o + 1 < F.op_end) {
             const Op nx = ops[o + 1];
-            const int nd = gate_u64(nx, prm, cm, u);
-            const int al = gidx(nx, a, nd);
-            c64d acc = {0.0, 0.0};
-            for (int be = 0; be < nd; ++be) {
-                const c64d p = cmul(u[al * nd + be], X[gset(nx, a, nd, be) * 16 + c]);
-                acc.re += p.re;
-                acc.im += p.im;
+            const int nd = load_gate(nx, prm, cm, U);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = t + 64 * i, a = e >> 4, c = e & 15;
+                const int al = gidx(nx, a, nd);
+                c64d acc = {0.0, 0.0};
+                for (int be = 0; be < nd; ++be) {
+                    const c64d p = cmul(U[al * nd + be], X[gset(nx, a, nd, be) * 16 + c]);
+                    acc.re += p.re;
+                    acc.im += p.im;
+                }
+                x[i] = acc;
             }
             __syncthreads();
-            X[t] = acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) X[t + 64 * i] = x[i];
             __syncthreads();
         }
     }
@@ -745,7 +774,7 @@ hipError_t launch_fused_grad(const FPhase* phases, const Op* ops, int n_blocks, 
                        osum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fused_grad, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
+    hipLaunchKernelGGL(k_fused_grad, dim3(unsigned(n_blocks), unsigned(batch)), dim3(64), 0, st, phases, ops,
                        n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
                        osum, total_slots, slots);
     return hipGetLastError();
