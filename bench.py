@@ -48,18 +48,23 @@ KIND_NAME = {v: k for k, v in KIND.items()}
 # WRITE_SIZE in separate runs, scaled by what each reads for a 2 GiB device
 # copy: x1.99993 and x1.0), keyed by workload and kernel family, valid only
 # for the kernel sources they were taken with (hash below).
-TILE_SOURCES = ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_tile.hip", "plan.cpp", "plan.h"]
+KERNEL_SOURCES = {
+    "tile": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_tile.hip", "plan.cpp", "plan.h"],
+    "fused": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_fused.hip", "plan.cpp", "plan.h"],
+}
 TRAFFIC = {
     ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "f906f1d349c202dd"),
     ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "f906f1d349c202dd"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.785e9, "33f778e79215f05e"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "33f778e79215f05e"),
 }
 
 
-def tile_source_hash():
+def source_hash(kernel):
     import hashlib
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_2602_14167_amd", "csrc")
-    for f in TILE_SOURCES:
+    for f in KERNEL_SOURCES["fused" if kernel.startswith("fused") else "tile"]:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -68,7 +73,7 @@ def tile_source_hash():
 def measured_traffic(workload_name, kernel):
     """Counter-measured bytes per launch, or None if not taken for these sources."""
     rec = TRAFFIC.get((workload_name, kernel))
-    if rec is None or rec[1] != tile_source_hash():
+    if rec is None or rec[1] != source_hash(kernel):
         return None
     return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
@@ -313,7 +318,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hea28")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--mode", default="tiled", choices=["tiled", "plain", "fused"])
+    ap.add_argument("--mode", default="fused", choices=["tiled", "plain", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick the tiling by timed search first")
@@ -403,6 +408,7 @@ def main():
         flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
         roofline = roofline_entry(dom, flops, algorithmic_bytes(dom, n, s, B, 0), fam_stats[dom]["avg_ms"], "mfma")
         roofline["gate_level_flops_per_launch"] = (rev_flops if dom == "fused_rev" else fwd_flops) / L
+        roofline["traffic"] = measured_traffic(w["name"], dom)
     elif args.mode == "tiled" and "rev_tile" in fam_stats:
         dom = max(("fwd_tile", "rev_tile"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
         L = fam_stats[dom]["launches"] / args.steps
