@@ -234,6 +234,24 @@ tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t 
                               int32_t dtype, int32_t* order, int32_t* pass_of, uint64_t* tile_mask,
                               int32_t* n_passes);
 
+/* Graph capture of one evaluation (the paper's compile-once, run-many):
+ * tcng_graph_create records state init to |basis> (skipped when init_basis
+ * < 0) and tcng_expect_grad with exactly these arguments into a HIP graph;
+ * tcng_graph_launch replays it on `stream`.  Every pointer is captured: to
+ * evaluate new angles, write them into the same `params` buffer (stream-
+ * ordered before the launch) and read energy / grad after it.  The graph
+ * owns no device memory; the caller keeps every buffer alive until
+ * tcng_graph_destroy (which synchronizes the device).  Creation fails while
+ * tcng_profile is recording.  Captures contain kernels only (no memsets or
+ * copies); the uneven-batch call cannot be captured. */
+typedef struct tcng_graph tcng_graph;
+tcng_status tcng_graph_create(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,
+                              const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
+                              double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, int64_t init_basis,
+                              tcng_graph** out);
+tcng_status tcng_graph_launch(tcng_graph* g, void* stream);
+tcng_status tcng_graph_destroy(tcng_graph* g);
+
 /* Host-only inspection of the fused planner (TCNG_MODE_FUSED, complex64).
  * Outputs (host, any may be NULL):
  *   order[n_gates], pass_of[n_gates]  as for tcng_plan_inspect;

@@ -21,7 +21,7 @@ from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_M
                    TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
-           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect"]
+           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
 
@@ -285,6 +285,43 @@ def expect_grad_multi(circs, hams, params_list, dtype=torch.complex64, psis=None
                                        ggp if want_gate_grad else None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream()))
     return energy, grads, (ggs if want_gate_grad else None)
+
+
+class Graph:
+    """A captured value-and-gradient evaluation (tcng_graph_*): state init to
+    |init_basis> (or none if init_basis < 0), forward sweep, H psi and <H>,
+    adjoint sweep, final sums.  `params`, `psi`, `lam`, `energy`, `grad` are
+    device tensors that stay captured: write new angles into `params` and
+    call launch(); the outputs hold the results once the stream reaches them."""
+
+    def __init__(self, circ, params, H, psi, lam, energy, grad, mode="fused", init_basis=0, want_gate_grad=False):
+        self.s = _state(psi, circ.n)
+        self.sl = _state(lam, circ.n)
+        m = _mode(mode)
+        self.ws = _workspace(circ, H, self.s.dtype, self.s.batch, m, psi.device)
+        self.gg = (torch.empty((self.s.batch, circ.n_gates, 15), dtype=torch.float64, device=psi.device)
+                   if want_gate_grad else None)
+        self.keep = (circ, params, H, psi, lam, energy, grad)
+        h = ctypes.c_void_p()
+        check(lib().tcng_graph_create(circ.handle, ctypes.c_void_p(params.data_ptr()) if circ.n_params else None,
+                                      H.handle, ctypes.byref(self.s), ctypes.byref(self.sl),
+                                      ctypes.c_void_p(energy.data_ptr()),
+                                      ctypes.c_void_p(grad.data_ptr()) if circ.n_params else None,
+                                      ctypes.c_void_p(self.gg.data_ptr()) if self.gg is not None else None, m,
+                                      ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), int(init_basis),
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        check(lib().tcng_graph_launch(self.handle, _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib._lib is not None:
+            lib().tcng_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 class TcngEnergy(torch.autograd.Function):

@@ -932,6 +932,71 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     return ok();
 }
 
+// ---------------------------------------------------------------------------
+// graph capture of one value-and-gradient evaluation
+// ---------------------------------------------------------------------------
+struct tcng_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+tcng_status tcng_graph_create(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,
+                              const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
+                              double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, int64_t init_basis,
+                              tcng_graph** out) {
+    if (!out) return fail(TCNG_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (g_prof.on) return fail(TCNG_E_INVALID, "stop profiling before capturing a graph");
+    if (tcng_status e = check_state(psi, "tcng_graph_create(psi)")) return e;
+    if (init_basis >= (int64_t(1) << psi->n_qubits)) return fail(TCNG_E_INVALID, "basis index out of range");
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        return fail(TCNG_E_HIP, "stream capture could not start");
+    }
+    tcng_status e = TCNG_OK;
+    if (init_basis >= 0) e = tcng_state_init(const_cast<tcng_state*>(psi), nullptr, init_basis, st);
+    if (!e) e = tcng_expect_grad(c, params, h, psi, lam, energy, grad, gate_grad, mode, ws, ws_bytes, st);
+    const std::string why = e ? std::string(tcng_last_error()) : std::string();
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    (void)hipStreamDestroy(st);
+    if (e) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(e, why);
+    }
+    if (ec != hipSuccess || !graph) return fail(TCNG_E_HIP, "stream capture failed");
+    auto* g = new (std::nothrow) tcng_graph();
+    if (!g) {
+        (void)hipGraphDestroy(graph);
+        return fail(TCNG_E_ALLOC, "host allocation failed");
+    }
+    g->graph = graph;
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return fail(TCNG_E_HIP, "graph instantiation failed");
+    }
+    *out = g;
+    return ok();
+}
+
+tcng_status tcng_graph_launch(tcng_graph* g, void* stream) {
+    if (!g || !g->exec) return fail(TCNG_E_INVALID, "null graph");
+    HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+tcng_status tcng_graph_destroy(tcng_graph* g) {
+    if (!g) return ok();
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return ok();
+}
+
 tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                                     int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
                                     int32_t* n_blocks, int32_t* bad_layouts) {
