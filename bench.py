@@ -97,6 +97,15 @@ def workload(name):
         return w
     if name == "xxz16_b2048":
         return W.cfg3()
+    if name == "xxz16_per_circuit":
+        w = W.cfg3()
+        w["name"] = "hea_n16_L8_xxz_per_circuit"
+        return w
+    if name == "hea10":
+        w = W.cfg1()
+        w["batch"] = 1
+        w["params"] = w["params"][None, :]
+        return w
     if name == "haar_uneven":
         return W.cfg4()
     if name == "fsim32":
@@ -237,6 +246,58 @@ def run_uneven(args, w, P, torch):
     }
 
 
+def run_per_circuit(args, w, P, torch):
+    """One evaluation per launch sequence (batch 1), the parameter sets of
+    the batched n=16 XXZ workload taken in turn: the per-circuit baseline of
+    the batched launch (complex128 and per-gate kernels by default), eager or
+    as a replayed graph with the angles written into the captured buffer."""
+    n, G = w["n"], len(w["gates"])
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    rdt = torch.float32 if args.dtype == "c64" else torch.float64
+    circ = P.Circuit(n, w["gates"], w["n_params"])
+    H = P.PauliSum(n, w["codes"], w["coeffs"])
+    sets = torch.tensor(np.asarray(w["params"]), dtype=rdt, device="cuda")
+    nsets = min(int(args.sets), sets.shape[0])
+    params = torch.empty((1, w["n_params"]), dtype=rdt, device="cuda")
+    psi = torch.empty((1, 2 ** n), dtype=cdt, device="cuda")
+    lam = torch.empty_like(psi)
+    energy = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((1, w["n_params"]), dtype=torch.float64, device="cuda")
+    graph = P.Graph(circ, params, H, psi, lam, energy, grad, mode=args.mode) if args.graph else None
+    nbytes = ctypes.c_size_t()
+    P.check(P.lib().tcng_workspace_size(circ.handle, H.handle, 0 if args.dtype == "c64" else 1, 1,
+                                        P.MODES[args.mode], ctypes.byref(nbytes)))
+    ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+
+    def one(i):
+        params.copy_(sets[i:i + 1])
+        if graph is not None:
+            graph.launch()
+        else:
+            P.state_init(psi)
+            P.expect_grad(circ, params, H, psi=psi, lam=lam, mode=args.mode, ws=ws)
+
+    for i in range(min(args.warmup, nsets)):
+        one(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for i in range(nsets):
+            one(i)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (args.steps * nsets)
+    if graph is not None:
+        graph.close()
+    return {
+        "metric": "amplitude-updates/s", "value": 3.0 * G * 2 ** n / dt, "unit": "amplitude-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * nsets * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": w["name"], "n_qubits": n, "gates": G, "parameter_sets": nsets, "mode": args.mode,
+                   "graph": bool(args.graph), "parallelism": "single GPU"},
+        "evals_per_s": 1.0 / dt, "us_per_eval": dt * 1e6,
+    }
+
+
 def run_gate_sweep(args, P, torch, n):
     """Per-gate HBM bandwidth of the streaming gate kernels (the unfused path)
     for low and high target qubits: RY (dense real 2x2), RZ (diagonal), CNOT
@@ -323,6 +384,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="pick the tiling by timed search first")
     ap.add_argument("--tiling", default=None, help="m,rb,rb_rev (skips the autotuner)")
+    ap.add_argument("--graph", action="store_true", help="replay a captured graph per evaluation")
+    ap.add_argument("--sets", type=int, default=32, help="parameter sets of the per-circuit workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not built",
@@ -341,6 +404,10 @@ def main():
         return
     if args.workload == "haar_uneven":
         out = run_uneven(args, w, P, torch)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "xxz16_per_circuit":
+        out = run_per_circuit(args, w, P, torch)
         print(json.dumps(out), flush=True)
         return
     n, G, B = w["n"], len(w["gates"]), int(w.get("batch", 1))
@@ -368,14 +435,23 @@ def main():
                                         ctypes.byref(nbytes)))
     ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
 
+    graph = None
+    if args.graph:
+        energy_g = torch.empty(B, dtype=torch.float64, device="cuda")
+        grad_g = torch.empty((B, max(w["n_params"], 1)), dtype=torch.float64, device="cuda")
+        graph = P.Graph(circ, params, H, psi, lam, energy_g, grad_g, mode=args.mode)
+
     def step():
+        if graph is not None:
+            graph.launch()
+            return energy_g, grad_g
         P.state_init(psi)
         return P.expect_grad(circ, params, H, psi=psi, lam=lam, mode=args.mode, ws=ws)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    prof = not args.no_profile
+    prof = not args.no_profile and graph is None   # replays record no per-launch events
     if prof:
         P.check(P.lib().tcng_profile_begin(64 * (G + 64) * (args.steps + 1)))
     torch.cuda.synchronize()
@@ -434,8 +510,10 @@ def main():
         "dtype": "c64 (f32 state, f64 reductions)" if args.dtype == "c64" else "c128",
         "data": "synthetic",
         "config": {"workload": w["name"], "n_qubits": n, "gates": G, "params": w["n_params"], "batch": B,
-                   "pauli_terms": len(w["coeffs"]), "mode": args.mode, "parallelism": "single GPU"},
+                   "pauli_terms": len(w["coeffs"]), "mode": args.mode, "graph": bool(args.graph),
+                   "parallelism": "single GPU"},
         "evals_per_s": B / dt,
+        "us_per_eval": dt / B * 1e6,
         "tiling": list(circ.config(cdt)) if args.mode == "tiled" else None,
         "autotune": tuned,
         "energy0": float(E[0].item()),
