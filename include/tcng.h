@@ -61,7 +61,8 @@ enum { TCNG_C64 = 0, TCNG_C128 = 1 };
  *     the unfused baseline.
  *   TCNG_MODE_FUSED: the tiled passes with every register phase multiplied
  *     out into one 16 x 16 block matrix (float64 product, rounded once to
- *     float32) applied on the matrix cores; the adjoint sweep accumulates each
+ *     float32) applied on the matrix cores (operator fusion, Sec.
+ *     "Foundations Recap", JIT paragraph); the adjoint sweep accumulates each
  *     block's outer product sum(lambda psi^dagger) and derives every gate
  *     derivative from it.  complex64 states with n >= 9 only; otherwise the
  *     call runs as TCNG_MODE_TILED. */
@@ -156,7 +157,9 @@ tcng_status tcng_circuit_configure(tcng_circuit* c, int32_t dtype, int32_t m_max
 tcng_status tcng_circuit_get_config(const tcng_circuit* c, int32_t dtype, int32_t* m_max, int32_t* rb,
                                     int32_t* rb_rev);
 
-/* Autotuner: times tcng_expect_grad (TCNG_MODE_TILED) for every available
+/* Autotuner (the find-then-execute search of contraction strategies, Sec.
+ * "Model Parallelism", applied to tilings): times tcng_expect_grad
+ * (TCNG_MODE_TILED) for every available
  * tiling of c for this dtype and batch, on the given initial states psi
  * (restored afterwards up to rounding) and scratch lam, keeps the fastest
  * (median of `repeats` runs, ties to the earlier candidate) and configures c
@@ -176,21 +179,25 @@ tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const 
 tcng_status tcng_pauli_sum_destroy(tcng_pauli_sum* h);
 
 /* Bytes of workspace needed by tcng_run_circuit / tcng_expect_pauli /
- * tcng_expect_grad for this shape (c or h may be NULL when not used). */
+ * tcng_expect_grad / tcng_graph_create for this shape (c or h may be NULL
+ * when not used); the caller allocates it (device memory). */
 tcng_status tcng_workspace_size(const tcng_circuit* c, const tcng_pauli_sum* h, int32_t dtype, int64_t batch,
                                 int32_t mode, size_t* bytes);
 
-/* Apply the circuit in place to every batch member of s.
+/* Apply the circuit in place to every batch member of s (state evolution by
+ * local contractions, Sec. "Foundations Recap").
  * params: DEVICE [batch][n_params], float32 for TCNG_C64, float64 for TCNG_C128
  * (may be NULL when n_params == 0). */
 tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tcng_state* s, int32_t mode,
                              void* ws, size_t ws_bytes, void* stream);
 
-/* out[b] = Re <psi_b| H |psi_b> accumulated in float64 (DEVICE float64 [batch]). */
+/* out[b] = Re <psi_b| H |psi_b> accumulated in float64 (DEVICE float64 [batch])
+ * (expectation of Pauli strings, Sec. "Foundations Recap"). */
 tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, double* out, int32_t mode, void* ws,
                               size_t ws_bytes, void* stream);
 
-/* Value and adjoint gradient.
+/* Value and adjoint gradient (value_and_grad with reverse-mode AD, Sec.
+ * "Foundations Recap"; the batch is the VMAP axis).
  *   psi   : in  = initial states |psi_0> (batch members);
  *           out = the initial states recomputed by the reverse sweep (equal to
  *                 the input up to rounding);
@@ -208,7 +215,8 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
                              double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, void* stream);
 
 /* Kernel-family timing with HIP events recorded on the launch stream around
- * every launch (instrumentation for benchmarks; off by default).
+ * every launch (benchmark instrumentation, not part of the method; off by
+ * default).
  * tcng_profile_begin allocates up to max_launches event pairs and starts
  * recording; tcng_profile_query synchronises the recorded events and returns
  * the launch count and summed duration (ms) of one family:
@@ -223,7 +231,8 @@ tcng_status tcng_profile_begin(int32_t max_launches);
 tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
 tcng_status tcng_profile_end(void);
 
-/* Host-only inspection of the tiled planner (no device is touched): the
+/* Host-only inspection of the tiled planner (pass scheduling of the gate
+ * contractions of Sec. "Foundations Recap"; no device is touched): the
  * schedule tcng_circuit_create would build for `dtype`.  Outputs (host):
  *   order[n_gates]      gate indices in execution order of the forward sweep;
  *   pass_of[n_gates]    pass in which gate order[i] runs;
@@ -234,7 +243,8 @@ tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t 
                               int32_t dtype, int32_t* order, int32_t* pass_of, uint64_t* tile_mask,
                               int32_t* n_passes);
 
-/* Graph capture of one evaluation (the paper's compile-once, run-many):
+/* Graph capture of one evaluation: the trace-once, run-many JIT paradigm
+ * (Sec. "Foundations Recap", JIT paragraph) done as a HIP graph:
  * tcng_graph_create records state init to |basis> (skipped when init_basis
  * < 0) and tcng_expect_grad with exactly these arguments into a HIP graph;
  * tcng_graph_launch replays it on `stream`.  Every pointer is captured: to
@@ -252,7 +262,8 @@ tcng_status tcng_graph_create(const tcng_circuit* c, const void* params, const t
 tcng_status tcng_graph_launch(tcng_graph* g, void* stream);
 tcng_status tcng_graph_destroy(tcng_graph* g);
 
-/* Host-only inspection of the fused planner (TCNG_MODE_FUSED, complex64).
+/* Host-only inspection of the fused planner (TCNG_MODE_FUSED, complex64;
+ * gate application as local contraction, Sec. "Foundations Recap").
  * Outputs (host, any may be NULL):
  *   order[n_gates], pass_of[n_gates]  as for tcng_plan_inspect;
  *   block_of[n_gates]                 block (16 x 16 matrix) of gate order[i];
