@@ -98,6 +98,10 @@ k_pauli_tile(const JobList jl, const Job single) {
     gptr<cx<R>> lam = as_global(J.costate ? static_cast<cx<R>*>(J.costate) : nullptr) + (J.costate ? b * J.stride : 0);
     const bool has_lam = J.costate != nullptr;
     double e_acc = 0.0;
+    // element l = it * nt + t: the thread's bits (below m - RB) and the
+    // iteration's bits are disjoint, so the global offset and every Z-parity
+    // split into a per-thread and a uniform part
+    const uint64_t gt = loc2glob(uint32_t(t), lo, m, lq);
 
     for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), tmask, n);
@@ -107,7 +111,7 @@ k_pauli_tile(const JobList jl, const Job single) {
 #pragma unroll
             for (int it = 0; it < NB; ++it) {
                 const uint32_t l = uint32_t(it * nt + t);
-                lds[l] = psi[base + loc2glob(l, lo, m, lq)];
+                lds[l] = psi[base + gt + loc2glob(uint32_t(it * nt), lo, m, lq)];
             }
         }
         __syncthreads();
@@ -119,9 +123,14 @@ k_pauli_tile(const JobList jl, const Job single) {
             cx<R> acc[CH];
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                const uint32_t l = uint32_t((c0 + i) * nt + t);
-                acc[i] = (has_lam && accumulate) ? lam[base + loc2glob(l, lo, m, lq)] : cx<R>{R(0), R(0)};
+                acc[i] = (has_lam && accumulate) ? lam[base + gt + loc2glob(uint32_t((c0 + i) * nt), lo, m, lq)]
+                                                 : cx<R>{R(0), R(0)};
             }
+            // this pass's share of (H psi)_l in float64: sum over groups of
+            // (cre + i cim) psi_{l ^ x}; E takes Re(conj(psi_l) * share) once per element
+            double sr[CH], si[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) { sr[i] = 0.0; si[i] = 0.0; }
             const int g_end = P->group_end;
             for (int g = P->group_begin; g < g_end; ++g) {
                 const PGroup G = groups[g];
@@ -136,11 +145,13 @@ k_pauli_tile(const JobList jl, const Job single) {
                     for (int k = C.term_begin; k < C.term_end; ++k) {
                         const PTerm T = terms[k];
                         const uint32_t zl = uint32_t(T.z_local);
-                        const uint32_t tp = uint32_t(__popcll(base & T.z_out) & 1);   // tile-constant part
+                        // parity of (l ^ x) & z = thread part ^ uniform part
+                        const uint32_t pt = uint32_t(__popc(uint32_t(t) & zl)) & 1u;
+                        const uint32_t ub = uint32_t(__popcll(base & T.z_out) + __popc(uint32_t(G.x_local) & zl));
 #pragma unroll
                         for (int i = 0; i < CH; ++i) {
-                            const uint32_t lp = uint32_t((c0 + i) * nt + t) ^ uint32_t(G.x_local);
-                            odd[i] += int((__popc(lp & zl) + tp) & 1u);
+                            const uint32_t u = (ub + uint32_t(__popc(uint32_t((c0 + i) * nt) & zl))) & 1u;
+                            odd[i] += int(pt ^ u);
                         }
                     }
                     const int nterm = C.term_end - C.term_begin;
@@ -153,22 +164,24 @@ k_pauli_tile(const JobList jl, const Job single) {
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const uint32_t l = uint32_t((c0 + i) * nt + t);
-                    const uint32_t lp = l ^ uint32_t(G.x_local);
-                    const cx<R> pp = lds[lp], own = lds[l];
-                    // contribution = (cre + i cim) * psi_{l^x}
-                    const cx<R> cc = {R(cre[i]), R(cim[i])};
-                    acc[i] = cfma(cc, pp, acc[i]);
-                    // E += Re(conj(psi_l) * contribution), float64
-                    const double rr = fma(double(own.re), double(pp.re), double(own.im) * double(pp.im));
-                    const double ri = fma(double(own.re), double(pp.im), -double(own.im) * double(pp.re));
-                    e_acc += cre[i] * rr - cim[i] * ri;
+                    const uint32_t lp = uint32_t((c0 + i) * nt + t) ^ uint32_t(G.x_local);
+                    const cx<R> pp = lds[lp];
+                    const double pr = double(pp.re), pi = double(pp.im);
+                    sr[i] = fma(cre[i], pr, fma(-cim[i], pi, sr[i]));
+                    si[i] = fma(cre[i], pi, fma(cim[i], pr, si[i]));
                 }
+            }
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const cx<R> own = lds[uint32_t((c0 + i) * nt + t)];
+                e_acc = fma(double(own.re), sr[i], fma(double(own.im), si[i], e_acc));
+                acc[i].re += R(sr[i]);
+                acc[i].im += R(si[i]);
             }
             if (has_lam) {
 #pragma unroll
                 for (int i = 0; i < CH; ++i)
-                    lam[base + loc2glob(uint32_t((c0 + i) * nt + t), lo, m, lq)] = acc[i];
+                    lam[base + gt + loc2glob(uint32_t((c0 + i) * nt), lo, m, lq)] = acc[i];
             }
         }
     }
