@@ -32,8 +32,10 @@ namespace {
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int FTHREADS = 256;            // 4 waves; 32-column tiles dealt round-robin (<= 2 per wave)
-constexpr int CT_MAX = 2;
-constexpr int FMAX_M = 12;               // tile bits of the fused kernels
+constexpr int FMAX_M = 12;               // tile bits of the fused kernels (largest)
+// column tiles per wave for tiles of at most 2^MB amplitudes
+template <int MB>
+constexpr int ct_max() { return MB >= 12 ? 2 : 1; }
 constexpr int OSTRIDE = 512;             // doubles per block outer product (16 x 16 complex)
 
 __device__ __forceinline__ uint64_t loc2glob_f(uint32_t l, int lo, int m, cptr<FPass> P) {
@@ -215,9 +217,11 @@ __device__ __forceinline__ FWork fwork(int m) {
     return k;
 }
 
-template <int IT>
+// MB: largest tile bits of the instantiation (LDS size, column tiles per wave)
+template <int IT, int MB>
 __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const Job single) {
-    __shared__ float2 lds[1 << FMAX_M];
+    constexpr int CT_MAX = ct_max<MB>();
+    __shared__ float2 lds[1 << MB];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     cptr<FPass> P = as_const(J.fpasses) + jl.step;
@@ -281,28 +285,20 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
 //
 // Outer product of a block, O[a][b] = sum_col lambda_in[a] conj(psi_in[b]),
 // straight from the un-apply results (lane l, register q: component l % 32 of
-// column 8 (q / 4) + 4 h + q % 4): as the A / B operands of
-// v_mfma_f32_16x16x4f32 (K index 4 s + l / 16) a register supplies
-// (re, im, re, im) of one block index at two columns, so
-//   O_re += A(lambda) B(psi),  O_im += A(lambda) B'(psi),
-// B' = psi with re and im exchanged across the two 16-lane halves and the
-// new re negated.  Each wave's 512 sums go to a staging area; after the
-// block's barrier every thread adds two of the 512 entries over the waves
-// into its registers (no atomics), and every FLUSH_TILES tiles into this
-// workgroup's float64 partials in global memory (its own slice).
+// column 8 (q / 4) + 4 h + q % 4).  v_permlane16_swap on the registers of a
+// pair (q, q + 1) moves the real parts of the four columns (q, q + 1) x
+// (h = 0, 1) into one register and the imaginary parts into the other, each
+// 16-lane row holding one column; as the A / B operands of
+// v_mfma_f32_16x16x4f32 (K index = lane / 16 = that row)
+//   O_re += Re(lambda) Re(psi) + Im(lambda) Im(psi),
+//   O_im += Im(lambda) Re(psi) - Re(lambda) Im(psi)  (two accumulators).
+// Each wave's 512 sums go to a staging area; after the block's barrier every
+// thread adds two of the 512 entries over the waves into its registers (no
+// atomics), and every FLUSH_TILES tiles into this workgroup's float64
+// partials in global memory (its own slice).
 // ---------------------------------------------------------------------------
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int FLUSH_TILES = 16;
-
-// B' operand for the imaginary part: the value of lane l ^ 16 (the other
-// 16-lane half holds the other component of the same amplitude), negated on
-// even 16-lane rows.  v_permlane16_swap with both operands equal leaves the
-// rows of the other half in its two results.
-__device__ __forceinline__ float swap16(float v, bool odd_row) {
-    const unsigned u = __float_as_uint(v);
-    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    return odd_row ? __uint_as_float(r[0]) : -__uint_as_float(r[1]);
-}
 
 // staging index e = r * 128 + part * 64 + lane of MFMA output register r
 // (O[a = 4 (lane / 16) + r][b = lane % 16], part 0 = re) -> O entry
@@ -330,13 +326,18 @@ __device__ __forceinline__ void stage_reduce(const float* stage, int nwv, int kb
 
 __device__ __forceinline__ void flush_acc(float (&acc)[FUSED_MAX_BLOCKS][2], int nblk, gptr<double> dst, int wgs,
                                           bool first) {
-    // dst: this workgroup's slice of the pass's first block; block k at + k * wgs * OSTRIDE
+    // dst: this workgroup's slice of the pass's first block; block k at + k * wgs * OSTRIDE.
+    // The lane offsets are formed here, at each flush (opaque to loop-invariant
+    // code motion): hoisted out of the tile loop, the 16 addresses would hold
+    // 32 registers for the whole kernel.
+    uint32_t off[2] = {uint32_t(stage_to_o(int(threadIdx.x))), uint32_t(stage_to_o(int(threadIdx.x) + 256))};
+    asm volatile("" : "+v"(off[0]), "+v"(off[1]));
 #pragma unroll
     for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) {
         if (k >= nblk) break;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            gptr<double> d = dst + size_t(k) * wgs * OSTRIDE + stage_to_o(int(threadIdx.x) + 256 * i);
+            gptr<double> d = dst + size_t(k) * wgs * OSTRIDE + off[i];
             const double v = double(acc[k][i]);
             *d = first ? v : *d + v;
             acc[k][i] = 0.f;
@@ -344,10 +345,12 @@ __device__ __forceinline__ void flush_acc(float (&acc)[FUSED_MAX_BLOCKS][2], int
     }
 }
 
-template <int IT>
+// two workgroups per CU (72 KiB of LDS each at MB = 12)
+template <int IT, int MB>
 __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, const Job single) {
-    __shared__ float2 lps[1 << FMAX_M];
-    __shared__ float2 llm[1 << FMAX_M];
+    constexpr int CT_MAX = ct_max<MB>();
+    __shared__ float2 lps[1 << MB];
+    __shared__ float2 llm[1 << MB];
     __shared__ float stage[(FTHREADS / 64) * OSTRIDE];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
@@ -375,7 +378,6 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
     for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) acc[k][0] = acc[k][1] = 0.f;
 
     const int n_c = lane & 31;
-    const bool odd_row = (lane & 16) != 0;
     float* fp = reinterpret_cast<float*>(lps);
     float* fl = reinterpret_cast<float*>(llm);
     float* my_stage = stage + wave * OSTRIDE + lane;
@@ -420,15 +422,6 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
                         ap = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[k][s], w[s], ap, 0, 0, 0);
                         al = __builtin_amdgcn_mfma_f32_32x32x2f32(xl[k][s], w[s], al, 0, 0, 0);
                     }
-                    // two independent accumulator pairs (shorter dependency chains)
-#pragma unroll
-                    for (int q = 0; q < 16; q += 2) {
-                        const float s0 = swap16(ap[q], odd_row), s1 = swap16(ap[q + 1], odd_row);
-                        ore = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q], ap[q], ore, 0, 0, 0);
-                        oim = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q], s0, oim, 0, 0, 0);
-                        ore1 = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q + 1], ap[q + 1], ore1, 0, 0, 0);
-                        oim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(al[q + 1], s1, oim1, 0, 0, 0);
-                    }
                     // write back: float component n_c (re if < 16) of block index n_c % 16
                     const uint32_t jb = (v[k].wrR[0] & (0u - uint32_t(n_c & 1))) ^
                                         (v[k].wrR[1] & (0u - uint32_t((n_c >> 1) & 1))) ^
@@ -443,13 +436,29 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
                         fp[2 * a + part] = ap[q];
                         fl[2 * a + part] = al[q];
                     }
+                    // outer product over the registers of a pair (q, q + 1), after the
+                    // write-back: the row swap leaves the real parts of the pair's four
+                    // columns in one register and the imaginary parts in the other
+#pragma unroll
+                    for (int q = 0; q < 16; q += 2) {
+                        const auto sp = __builtin_amdgcn_permlane16_swap(__float_as_uint(ap[q]), __float_as_uint(ap[q + 1]),
+                                                                         false, false);
+                        const auto sl = __builtin_amdgcn_permlane16_swap(__float_as_uint(al[q]), __float_as_uint(al[q + 1]),
+                                                                         false, false);
+                        const float pre = __uint_as_float(sp[0]), pim = __uint_as_float(sp[1]);
+                        const float lre = __uint_as_float(sl[0]), lim = __uint_as_float(sl[1]);
+                        ore = __builtin_amdgcn_mfma_f32_16x16x4f32(lre, pre, ore, 0, 0, 0);
+                        ore1 = __builtin_amdgcn_mfma_f32_16x16x4f32(lim, pim, ore1, 0, 0, 0);
+                        oim = __builtin_amdgcn_mfma_f32_16x16x4f32(lim, pre, oim, 0, 0, 0);
+                        oim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(lre, pim, oim1, 0, 0, 0);
+                    }
                     // one column tile at a time (register pressure)
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     my_stage[r * 128] = ore[r] + ore1[r];
-                    my_stage[r * 128 + 64] = oim[r] + oim1[r];
+                    my_stage[r * 128 + 64] = oim[r] - oim1[r];
                 }
             }
             __syncthreads();
@@ -753,15 +762,15 @@ hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, 
 // chunks per thread of the tile load: 8 at m = 12 (256 threads), 4 for m = 9..11
 hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
-    if (m == 12) hipLaunchKernelGGL((k_fused_fwd<8>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
-    else hipLaunchKernelGGL((k_fused_fwd<4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    if (m == 12) hipLaunchKernelGGL((k_fused_fwd<8, 12>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    else hipLaunchKernelGGL((k_fused_fwd<4, 11>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
     return hipGetLastError();
 }
 
 hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
-    if (m == 12) hipLaunchKernelGGL((k_fused_rev<8>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
-    else hipLaunchKernelGGL((k_fused_rev<4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    if (m == 12) hipLaunchKernelGGL((k_fused_rev<8, 12>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    else hipLaunchKernelGGL((k_fused_rev<4, 11>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
     return hipGetLastError();
 }
 
