@@ -7,8 +7,15 @@ Recap": gates as local contractions, E = <psi|H|psi> with H a Pauli sum,
 reverse-mode gradient / parameter-shift rule); it shares no code with the HIP
 library.  Pins that tie it to the mathematics live in tests/test_oracle_pins.py.
 
+It also runs monitored Haar brick-wall trajectories (Sec. "Universal Quantum
+Dynamics of Haar-Random MIPT"): unitary steps, random Z measurements drawn
+from passed-in uniforms, Born log-probability of the record.
+
 Parity status: every function here is pinned (closed forms, brute-force
 Kronecker products for n <= 6, exact diagonalisation against the free-fermion
-closed form, parameter shift vs adjoint, finite differences).
+closed form, parameter shift vs adjoint, finite differences; for the
+trajectories, tensor-contraction evolution, dense joint Born probabilities,
+p = 0 / p = 1 closed forms and Born-rule sampling statistics in
+tests/test_oracle_mipt.py).
 """
 from .api import *  # noqa: F401,F403

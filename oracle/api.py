@@ -44,6 +44,7 @@ def lib():
         L.orc_norm2.restype = ctypes.c_double
         L.orc_expect_grad.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P, P, P, P]
         L.orc_param_shift.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P]
+        L.orc_mipt.argtypes = [i32, P, i32, i32, P, i32, P, P, ctypes.c_double, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -163,4 +164,28 @@ def param_shift(n, gates, params, codes, coeffs, mats=None, init=None, want_lie=
 
 
 __all__ = ["build", "lib", "run", "apply_matrix", "gate_matrix", "expect", "apply_hamiltonian", "norm2",
-           "expect_grad", "param_shift"]
+           "expect_grad", "param_shift", "mipt"]
+
+
+def mipt(n, gates, mats, u, p, init=None, force=None):
+    """One monitored brick-wall trajectory (complex128).
+
+    gates: the gates of one time step (all U2); mats [n_steps, n_step_mats, 4, 4];
+    u [n_steps, n] uniforms; force (optional) [n_steps, n] int: -1 free, 0 / 1 forced.
+    Returns dict(state, rec [n_steps, 2] uint32 (mask, outcomes), logp, margin [n_steps, n]).
+    """
+    g = _gates(gates)
+    mats = np.ascontiguousarray(np.asarray(mats, dtype=np.complex128))
+    assert mats.ndim == 4 and mats.shape[2:] == (4, 4)
+    n_steps, n_step_mats = mats.shape[0], mats.shape[1]
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(n_steps, n))
+    f = None if force is None else np.ascontiguousarray(np.asarray(force, dtype=np.int32).reshape(n_steps, n))
+    x = _c128(init)
+    st = np.empty(2 ** n, np.complex128)
+    rec = np.zeros((max(n_steps, 1), 2), np.uint32)
+    logp = np.zeros(1)
+    margin = np.empty((max(n_steps, 1), n))
+    rc = lib().orc_mipt(n, _p(g), g.shape[0], n_steps, _p(mats), n_step_mats, _p(x), _p(uu), float(p), _p(f),
+                        _p(st), _p(rec), _p(logp), _p(margin))
+    assert rc == 0, rc
+    return dict(state=st, rec=rec[:n_steps], logp=float(logp[0]), margin=margin[:n_steps])

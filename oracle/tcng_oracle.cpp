@@ -541,4 +541,70 @@ int orc_param_shift(int n, const int32_t* gates, int G, const double* params, in
     return 0;
 }
 
+// Monitored Haar circuit, one trajectory (Sec. "Universal Quantum Dynamics of
+// Haar-Random MIPT"): every time step applies its two-qubit gates in order,
+// then a layer of single-qubit Z measurements, each qubit measured with
+// probability p.  The measurement is the three-outcome Kraus channel
+// {sqrt(1-p) I, sqrt(p) P0, sqrt(p) P1} picked with one uniform v per
+// (step, qubit), qubits in increasing order:
+//   v < 1 - p                        -> not measured;
+//   v - (1 - p) <  p * P(bit q = 0)  -> outcome 0;  otherwise outcome 1,
+// P taken on the current (already collapsed, normalised) state; the state is
+// projected on the outcome and renormalised, and ln P(outcome) is added to
+// the trajectory's Born log-probability.
+//   gates [G_step]: the step's gates; gate g of step s uses matrix
+//                   mats[s * n_step_mats + g.mat] (complex128 4x4, row-major);
+//   u [n_steps][n]; force (nullable) [n_steps][n]: -1 free, 0 / 1 = take
+//   this outcome (the margin is still reported);
+//   rec [n_steps][2]: measured-qubit mask, outcome bits;
+//   margin (nullable) [n_steps][n]: v - (1 - p) - p P(0) for measured
+//   qubits, NaN otherwise.
+int orc_mipt(int n, const int32_t* gates, int G, int n_steps, const double* mats, int n_step_mats,
+             const double* init, const double* u, double p, const int32_t* force, double* out_state,
+             uint32_t* rec, double* logp, double* margin) {
+    if (n < 1 || n > 30) return 1;
+    auto g = read_gates(gates, G);
+    for (auto& gi : g)
+        if (gi.kind != U2 || gi.mat < 0 || gi.mat >= n_step_mats) return 2;
+    auto m = read_mats(mats, n_steps * n_step_mats);
+    std::vector<cplx> psi = initial_state(n, init);
+    const uint64_t dim = uint64_t(1) << n;
+    double lp = 0.0;
+    for (int s = 0; s < n_steps; ++s) {
+        for (auto& gi : g) {
+            Mat4 U = zero4();
+            const cplx* src = m.data() + (size_t(s) * n_step_mats + gi.mat) * 16;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) U.m[a][b] = src[4 * a + b];
+            apply_gate(n, psi, gi, U);
+        }
+        uint32_t mask = 0, bits = 0;
+        for (int q = 0; q < n; ++q) {
+            const double v = u[size_t(s) * n + q];
+            if (margin) margin[size_t(s) * n + q] = std::nan("");
+            if (v < 1.0 - p) continue;
+            const uint64_t bq = uint64_t(1) << q;
+            auto w0 = [&](uint64_t k) { return cplx((k & bq) ? 0.0 : std::norm(psi[k]), 0.0); };
+            auto w1 = [&](uint64_t k) { return cplx((k & bq) ? std::norm(psi[k]) : 0.0, 0.0); };
+            const double s0 = pairwise_sum(w0, 0, dim).real(), s1 = pairwise_sum(w1, 0, dim).real();
+            const double p0 = s0 / (s0 + s1);
+            const double mg = (v - (1.0 - p)) - p * p0;
+            if (margin) margin[size_t(s) * n + q] = mg;
+            int o = mg < 0.0 ? 0 : 1;
+            if (force && force[size_t(s) * n + q] >= 0) o = force[size_t(s) * n + q];
+            const double keep = o ? s1 : s0;
+            lp += std::log(keep / (s0 + s1));
+            const double sc = 1.0 / std::sqrt(keep);
+            for (uint64_t k = 0; k < dim; ++k) psi[k] = (((k & bq) != 0) == (o != 0)) ? psi[k] * sc : cplx(0.0, 0.0);
+            mask |= uint32_t(1) << q;
+            bits |= uint32_t(o) << q;
+        }
+        rec[2 * s] = mask;
+        rec[2 * s + 1] = bits;
+    }
+    write_state(psi, out_state);
+    *logp = lp;
+    return 0;
+}
+
 }  // extern "C"

@@ -86,6 +86,38 @@ def brickwork_haar(n: int, depth: int, rng: np.random.Generator):
     return as_gate_array(g), mats
 
 
+def haar_u4_many(rng: np.random.Generator, count: int) -> np.ndarray:
+    """`count` Haar 4x4 unitaries with the same draws, in the same order, as
+    `count` calls of haar_u4 (16 real parts then 16 imaginary parts each)."""
+    z = rng.standard_normal((count, 2, 4, 4))
+    z = (z[:, 0] + 1j * z[:, 1]) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r, axis1=1, axis2=2)
+    return q * (d / np.abs(d))[:, None, :]
+
+
+def mipt_step_gates(n: int):
+    """One time step of the monitored brick-wall circuit: two-qubit gates on the
+    even bonds (0,1), (2,3), ..., then on the odd bonds (1,2), (3,4), ...;
+    gate g takes step matrix g."""
+    g = [gate(U2, i, j, mat=k) for k, (i, j) in enumerate(brickwork_bonds(n, 2))]
+    return as_gate_array(g)
+
+
+def mipt_workload(n: int, steps: int, batch: int, p: float, seed: int):
+    """Haar-random monitored trajectories (Sec. "Universal Quantum Dynamics of
+    Haar-Random MIPT"): per trajectory and step, independent Haar gates on the
+    step's bonds, then one uniform per qubit for the measurement layer.
+    Draw order: all gate matrices (trajectory-major, then step, then gate),
+    then the uniforms u[batch][steps][n]."""
+    rng = np.random.default_rng(seed)
+    gates = mipt_step_gates(n)
+    G = gates.shape[0]
+    mats = haar_u4_many(rng, batch * steps * G).reshape(batch, steps, G, 4, 4)
+    u = rng.uniform(0.0, 1.0, size=(batch, steps, n))
+    return dict(n=n, steps=steps, batch=batch, p=float(p), gates=gates, mats=mats, u=u)
+
+
 def brickwork_fsim(n: int, depth: int, rng: np.random.Generator):
     """fSim brick-wall; per gate theta then phi drawn U[0, 2pi) in gate order."""
     bonds = brickwork_bonds(n, depth)
