@@ -225,8 +225,9 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
  *   6 reverse one-qubit   7 reverse two-qubit   8 Pauli X-group
  *   9 final reduction     10 state init
  *   11 fused forward pass  12 fused reverse pass  13 fused block matrices and gradients
+ *   14 trajectory marginal pass  15 trajectory decisions  16 trajectory collapse
  * tcng_profile_end stops recording and frees the events. */
-enum { TCNG_PROF_FAMILIES = 14 };
+enum { TCNG_PROF_FAMILIES = 17 };
 tcng_status tcng_profile_begin(int32_t max_launches);
 tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
 tcng_status tcng_profile_end(void);
@@ -275,6 +276,41 @@ tcng_status tcng_graph_destroy(tcng_graph* g);
 tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                                     int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
                                     int32_t* n_blocks, int32_t* bad_layouts);
+
+/* Monitored Haar brick-wall trajectories (Sec. "Universal Quantum Dynamics of
+ * Haar-Random MIPT": per time step two layers of Haar two-qubit gates on the
+ * even, then the odd bonds, then each qubit measured in Z with probability p;
+ * one trajectory per batch member, complex64).
+ * The measurement layer is the Kraus channel {sqrt(1-p) I, sqrt(p) P0,
+ * sqrt(p) P1} per qubit, qubits in increasing order, selected by one uniform
+ * v per (member, step, qubit):
+ *   v < 1 - p                          not measured;
+ *   v - (1 - p) < p P(bit q = 0 | ...)  outcome 0, otherwise outcome 1,
+ * P conditional on the outcomes taken earlier in the step, computed in
+ * float64; the state is projected and renormalised once per step.
+ *   step     circuit of one time step; every gate U2, gate g taking step
+ *            matrix g.mat (its creation matrices only fix the count n_mats);
+ *            needs the fused path (9 <= n) and n <= 32;
+ *   n_steps  time steps (0: nothing is applied, outputs zeroed);
+ *   mats     device, complex64 [batch][n_steps][n_mats][4][4] row-major, the
+ *            first gate qubit the most significant local index;
+ *   psi      complex64 states, evolved in place (the caller initialises them);
+ *   u        device float64 [batch][n_steps][n] uniforms in [0, 1);
+ *   p        measurement probability in [0, 1];
+ *   rec      device uint32 [batch][n_steps][2]: measured-qubit mask, outcome
+ *            bits (written; may be NULL when n_steps is 0);
+ *   logp     device float64 [batch]: sum of ln P(outcome) over the record
+ *            (the trajectory's Born log-probability; written);
+ *   margin   device float64 [batch][n_steps][n] or NULL: v - (1 - p) - p P0
+ *            for each measured qubit (other entries untouched);
+ *   ws       device workspace of tcng_mipt_workspace_size bytes.
+ * Asynchronous on `stream`; TCNG_E_UNSUPPORTED for complex128, n < 9 or
+ * n > 32, TCNG_E_INVALID for non-U2 step gates, angles, bad p or null
+ * arguments, TCNG_E_WORKSPACE if ws is too small. */
+tcng_status tcng_mipt_workspace_size(const tcng_circuit* step, int32_t n_qubits, int64_t batch, size_t* bytes);
+tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void* mats, tcng_state* psi,
+                          const double* u, double p, uint32_t* rec, double* logp, double* margin, void* ws,
+                          size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

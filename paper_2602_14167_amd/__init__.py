@@ -21,7 +21,7 @@ from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_M
                    TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
-           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph"]
+           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
 
@@ -107,7 +107,7 @@ class Circuit:
                                         m.ctypes.data_as(ctypes.c_void_p) if m.shape[0] else None, m.shape[0],
                                         ctypes.byref(h)))
         self.handle = h
-        self.n, self.n_params, self.n_gates = int(n), int(n_params), g.shape[0]
+        self.n, self.n_params, self.n_gates, self.n_mats = int(n), int(n_params), g.shape[0], m.shape[0]
         self.gates = g
 
     def num_passes(self, dtype=torch.complex64):
@@ -379,3 +379,35 @@ def fused_plan_inspect(n, gates, n_params):
                                         block_of.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass),
                                         ctypes.byref(nblk), ctypes.byref(bad)))
     return order[:G], pass_of[:G], block_of[:G], npass.value, nblk.value, bad.value
+
+
+def mipt_run(step: Circuit, mats: torch.Tensor, psi: torch.Tensor, u: torch.Tensor, p: float, want_margin=False,
+             ws=None):
+    """Monitored Haar brick-wall trajectories, one per batch member, in place on psi.
+
+    step: Circuit of one time step (U2 gates, no angles); mats: complex64
+    [batch][n_steps][step.n_mats][4][4]; psi: complex64 [batch, 2^n] (initial
+    states); u: float64 [batch][n_steps][n] uniforms; p: measurement probability.
+    Returns (rec int32 [batch][n_steps][2] holding the uint32 measured mask and
+    outcome bits, logp float64 [batch], margin float64 [batch][n_steps][n] or None).
+    """
+    s = _state(psi, step.n)
+    batch, n_steps = s.batch, int(u.shape[1]) if u.dim() == 3 else 0
+    if mats.dtype != torch.complex64 or not mats.is_contiguous() or u.dtype != torch.float64 or not u.is_contiguous():
+        raise ValueError("mats must be contiguous complex64, u contiguous float64")
+    if tuple(u.shape) != (batch, n_steps, step.n) or tuple(mats.shape) != (batch, n_steps, step.n_mats, 4, 4):
+        raise ValueError("u must be [batch][n_steps][n] and mats [batch][n_steps][n_mats][4][4]")
+    dev = psi.device
+    rec = torch.empty((batch, n_steps, 2), dtype=torch.int32, device=dev)
+    logp = torch.empty(batch, dtype=torch.float64, device=dev)
+    margin = torch.full((batch, n_steps, step.n), float("nan"), dtype=torch.float64, device=dev) if want_margin else None
+    if ws is None:
+        need = ctypes.c_size_t()
+        check(lib().tcng_mipt_workspace_size(step.handle, step.n, batch, ctypes.byref(need)))
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=dev)
+    check(lib().tcng_mipt_run(step.handle, n_steps, ctypes.c_void_p(mats.data_ptr()), ctypes.byref(s),
+                              ctypes.c_void_p(u.data_ptr()), float(p), ctypes.c_void_p(rec.data_ptr()),
+                              ctypes.c_void_p(logp.data_ptr()),
+                              ctypes.c_void_p(margin.data_ptr()) if margin is not None else None,
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return rec, logp, margin

@@ -49,7 +49,8 @@ constexpr int MAX_QUBITS = 34;
 // optional per-launch timing (events on the launch stream)
 // ---------------------------------------------------------------------------
 enum Family { F_FWD_TILE, F_REV_TILE, F_PAULI_TILE, F_GATE1, F_GATE2, F_GATEK, F_REV1, F_REV2, F_PAULI_GROUP,
-              F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_COUNT };
+              F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_MIPT_MARG, F_MIPT_DECIDE,
+              F_MIPT_COLLAPSE, F_COUNT };
 static_assert(F_COUNT == TCNG_PROF_FAMILIES, "profiler families");
 
 struct Profiler {
@@ -540,7 +541,7 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
 tcng_status run_forward_fused(const tcng_circuit* c, const void* params, const tcng_state* s, const Job& J,
                               bool want_rev, hipStream_t st) {
     const DevFusedPlan& F = c->fused;
-    PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, params, c->n_params, c->cm[0],
+    PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, params, c->n_params, c->cm[0], 0,
                                              s->batch, const_cast<void*>(J.fmats), want_rev, st));
     for (size_t p = 0; p < F.host.passes.size(); ++p) {
         const JobList jl{nullptr, nullptr, 0, int32_t(p)};
@@ -1028,6 +1029,87 @@ tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, in
     if (n_passes) *n_passes = int32_t(P.passes.size());
     if (n_blocks) *n_blocks = P.n_blocks;
     if (bad_layouts) *bad_layouts = check_fused_layouts(P);
+    return ok();
+}
+
+// ---- monitored Haar trajectories
+namespace {
+struct MiptLayout {
+    WsLayout F;                      // the fused forward of one step
+    size_t part_off = 0, keep_off = 0, total = 0;
+    int wgs = 0;
+};
+MiptLayout mipt_layout(const tcng_circuit* c, int n, int64_t batch) {
+    MiptLayout M;
+    M.F = layout(c, nullptr, n, TCNG_C64, batch, TCNG_MODE_FUSED);
+    M.wgs = mipt_wgs(n);
+    M.part_off = align256(M.F.total);
+    M.keep_off = M.part_off + align256(size_t(batch) * M.wgs * 2 * sizeof(double));
+    M.total = M.keep_off + align256(size_t(batch) * sizeof(double));
+    return M;
+}
+tcng_status check_mipt(const tcng_circuit* c, int n) {
+    if (!c) return fail(TCNG_E_INVALID, "null circuit");
+    if (c->n != n) return fail(TCNG_E_INVALID, "circuit and state have different qubit counts");
+    if (n > 32) return fail(TCNG_E_UNSUPPORTED, "monitored trajectories: n must be at most 32");
+    if (!c->fused.valid) return fail(TCNG_E_UNSUPPORTED, "monitored trajectories need the fused path (n >= 9)");
+    if (c->n_params != 0) return fail(TCNG_E_INVALID, "monitored trajectories: the step circuit takes no angles");
+    for (const tcng_gate& g : c->gates)
+        if (g.kind != K_U2) return fail(TCNG_E_INVALID, "monitored trajectories: every step gate must be U2");
+    return TCNG_OK;
+}
+}  // namespace
+
+tcng_status tcng_mipt_workspace_size(const tcng_circuit* step, int32_t n_qubits, int64_t batch, size_t* bytes) {
+    if (!bytes) return fail(TCNG_E_INVALID, "null output");
+    if (tcng_status e = check_mipt(step, n_qubits)) return e;
+    if (batch < 1 || batch > 65535) return fail(TCNG_E_INVALID, "batch must be 1..65535");
+    *bytes = mipt_layout(step, n_qubits, batch).total;
+    return ok();
+}
+
+tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void* mats, tcng_state* psi,
+                          const double* u, double p, uint32_t* rec, double* logp, double* margin, void* ws,
+                          size_t ws_bytes, void* stream) {
+    if (tcng_status e = check_state(psi, "tcng_mipt_run")) return e;
+    if (psi->dtype != TCNG_C64) return fail(TCNG_E_UNSUPPORTED, "monitored trajectories run in complex64");
+    if (tcng_status e = check_mipt(step, psi->n_qubits)) return e;
+    if (n_steps < 0) return fail(TCNG_E_INVALID, "n_steps must be >= 0");
+    if (!(p >= 0.0 && p <= 1.0)) return fail(TCNG_E_INVALID, "p must lie in [0, 1]");
+    if (!logp || (n_steps > 0 && (!rec || !u || (step->n_mats > 0 && !mats))))
+        return fail(TCNG_E_INVALID, "null uniforms, matrices or outputs");
+    const MiptLayout M = mipt_layout(step, psi->n_qubits, psi->batch);
+    if (!ws || ws_bytes < M.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = psi->n_qubits;
+    const int64_t batch = psi->batch;
+    char* w = static_cast<char*>(ws);
+    double* part = reinterpret_cast<double*>(w + M.part_off);
+    double* keep = reinterpret_cast<double*>(w + M.keep_off);
+    PROF_TRY(F_MIPT_DECIDE, launch_zero_u32(rec, size_t(batch) * n_steps * 2, st));
+    PROF_TRY(F_MIPT_DECIDE, launch_zero(logp, size_t(batch), st));
+    Job J = make_job(step, nullptr, psi, nullptr, nullptr, nullptr, nullptr, M.F);
+    J.fmats = w + M.F.fmats_off;
+    const DevFusedPlan& F = step->fused;
+    const int64_t nm = step->n_mats;
+    for (int s = 0; s < n_steps; ++s) {
+        // the step's gates: member b takes matrix g.mat of step s at mats[((b * n_steps + s) * nm + g.mat)]
+        const void* cm = static_cast<const char*>(mats) + size_t(s) * nm * 16 * sizeof(float) * 2;
+        PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, nullptr, 0, cm, n_steps * nm, batch,
+                                                 const_cast<void*>(J.fmats), false, st));
+        for (size_t ps = 0; ps < F.host.passes.size(); ++ps) {
+            const JobList jl{nullptr, nullptr, 0, int32_t(ps)};
+            PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st));
+        }
+        for (int q = 0; q < n; ++q) {
+            PROF_TRY(F_MIPT_MARG, launch_mipt_marg(psi->amps, psi->stride, n, batch, u, n_steps, s, q, p, rec, M.wgs,
+                                                   part, st));
+            PROF_TRY(F_MIPT_DECIDE, launch_mipt_decide(u, n, n_steps, s, q, p, M.wgs, part, rec, keep, logp, margin,
+                                                       batch, st));
+        }
+        PROF_TRY(F_MIPT_COLLAPSE, launch_mipt_collapse(psi->amps, psi->stride, n, batch, n_steps, s, rec, keep, M.wgs,
+                                                       st));
+    }
     return ok();
 }
 

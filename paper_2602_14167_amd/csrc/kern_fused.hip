@@ -537,7 +537,8 @@ __device__ __forceinline__ int gset(const Op& op, int a, int dim, int beta) {
 // one workgroup of 256 threads per (block, member): thread (row a, column c)
 __global__ void __launch_bounds__(256)
 k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
-             int64_t pstride, const cx<float>* __restrict__ cm, float* __restrict__ out, int want_rev) {
+             int64_t pstride, const cx<float>* __restrict__ cm, int64_t cmstride, float* __restrict__ out,
+             int want_rev) {
     __shared__ c64d M[256];
     __shared__ c64d U[16];
     const int f = blockIdx.x;
@@ -545,6 +546,7 @@ k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int 
     const int t = threadIdx.x, a = t >> 4, c = t & 15;
     const FPhase F = phases[f];
     const float* prm = params ? params + b * pstride : nullptr;
+    cm += b * cmstride * 16;   // per-member matrices (cmstride 0: shared)
     M[t] = {a == c ? 1.0 : 0.0, 0.0};
     for (int o = F.op_begin; o < F.op_end; ++o) {
         const Op op = ops[o];
@@ -751,11 +753,12 @@ k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int 
 }  // namespace
 
 hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
-                             const void* cmats, int64_t batch, void* out, bool want_rev, hipStream_t st) {
+                             const void* cmats, int64_t cmstride, int64_t batch, void* out, bool want_rev,
+                             hipStream_t st) {
     if (n_blocks == 0 || batch == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fused_mats, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
                        n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
-                       static_cast<float*>(out), int(want_rev));
+                       cmstride, static_cast<float*>(out), int(want_rev));
     return hipGetLastError();
 }
 

@@ -74,9 +74,11 @@ template <typename R, int RB>
 hipError_t launch_pauli_tile(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 
 // ---- fused passes (complex64, matrix cores)
-// block matrices of every forward phase for every member (float64 products rounded to float32)
+// block matrices of every forward phase for every member (float64 products rounded to float32);
+// member b reads its constant matrices at cmats + b * cmstride (cmstride 0: one shared set)
 hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
-                             const void* cmats, int64_t batch, void* out, bool want_rev, hipStream_t st);
+                             const void* cmats, int64_t cmstride, int64_t batch, void* out, bool want_rev,
+                             hipStream_t st);
 // blocks: tiles * batch (forward), wgs * batch (reverse)
 // m: tile bits of the plan (9..12)
 hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st);
@@ -111,6 +113,19 @@ template <typename R>
 hipError_t launch_pauli_group(const void* state, void* costate, bool accumulate, int64_t stride, int n, int64_t batch,
                               uint64_t x, const PClassFull* classes, int class_begin, int class_end,
                               const PTermFull* terms, int wgs, double* epart, int row, int n_rows, hipStream_t st);
+
+// ---- monitored trajectories (complex64): marginal partials of qubit q on the
+// amplitudes consistent with the step's decided outcomes, the Kraus decision,
+// the per-step collapse.  wgs = mipt_wgs(n) workgroups per member.
+int mipt_wgs(int n);
+hipError_t launch_mipt_marg(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
+                            int q, double p, const uint32_t* rec, int wgs, double* part, hipStream_t st);
+hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, int q, double p, int wgs, const double* part,
+                              uint32_t* rec, double* keep, double* logp, double* margin, int64_t batch,
+                              hipStream_t st);
+hipError_t launch_mipt_collapse(void* psi, int64_t stride, int n, int64_t batch, int n_steps, int s,
+                                const uint32_t* rec, const double* keep, int wgs, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t st);
 
 // ---- misc
 template <typename R>

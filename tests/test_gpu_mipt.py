@@ -1,0 +1,157 @@
+"""Monitored Haar brick-wall trajectories: HIP path (through the C ABI) vs
+the CPU oracle.
+
+The measured sets follow from the uniforms alone and must agree exactly.  An
+outcome is a floating-point decision (uniform against p times a conditional
+probability): the kernels take it in float64 from the complex64 state, the
+oracle in float64 from its complex128 state.  Where the oracle's margin lies
+within AMBIG of the threshold both outcomes are correct; everywhere else the
+outcomes must agree.  The oracle is then run with the GPU's record forced, so
+the two follow the same trajectory, and compared on the decision margins, the
+Born log-probability and the final state (complex64 tolerances below).  The
+oracle receives the complex64-rounded gate matrices, widened exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AMBIG = 1e-4      # oracle margins closer than this to 0 admit either outcome
+MARGIN_TOL = 1e-5  # |margin_gpu - margin_oracle| (probabilities are in [0, 1])
+AMP_TOL = 2e-5     # per amplitude, short trajectories
+NORM_TOL = 1e-4    # ||psi_gpu - psi_oracle||_2, full-size trajectories
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2602_14167_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.lib()
+    return pkg
+
+
+def run_gpu(P, w, p, n_steps=None):
+    n, gates = w["n"], w["gates"]
+    S = w["steps"] if n_steps is None else n_steps
+    G = gates.shape[0]
+    step = P.Circuit(n, gates, 0, mats=np.tile(np.eye(4), (G, 1, 1)))
+    mats = torch.as_tensor(np.ascontiguousarray(w["mats"][:, :S]).astype(np.complex64)).cuda().contiguous()
+    u = torch.as_tensor(np.ascontiguousarray(w["u"][:, :S])).cuda().contiguous()
+    psi = P.new_state(n, batch=w["batch"])
+    print(f"mipt n={n} batch={w['batch']} steps={S} p={p}", flush=True)
+    rec, logp, margin = P.mipt_run(step, mats, psi, u, p, want_margin=True)
+    torch.cuda.synchronize()
+    return dict(state=psi.cpu().numpy(), rec=rec.cpu().numpy().view(np.uint32), logp=logp.cpu().numpy(),
+                margin=margin.cpu().numpy())
+
+
+def oracle_following(oracle_mod, w, b, p, g, n_steps=None):
+    n = w["n"]
+    S = w["steps"] if n_steps is None else n_steps
+    mask, bits = g["rec"][b, :, 0], g["rec"][b, :, 1]
+    force = np.full((S, n), -1, np.int32)
+    for s in range(S):
+        for q in range(n):
+            if (int(mask[s]) >> q) & 1:
+                force[s, q] = (int(bits[s]) >> q) & 1
+    return oracle_mod.mipt(n, w["gates"], W.round_mats(w["mats"][b, :S], "c64"), w["u"][b, :S], p, force=force)
+
+
+def check_member(g, o, w, b, p, n_steps=None, amp_tol=AMP_TOL, norm_tol=None):
+    n = w["n"]
+    S = w["steps"] if n_steps is None else n_steps
+    u = w["u"][b, :S]
+    want_mask = [sum(1 << q for q in range(n) if u[s, q] >= 1 - p) for s in range(S)]
+    assert [int(x) for x in g["rec"][b, :, 0]] == want_mask
+    assert [int(x) for x in o["rec"][:, 0]] == want_mask
+    np.testing.assert_array_equal(g["rec"][b, :, 1], o["rec"][:, 1])   # forced: same record
+    n_meas = 0
+    for s in range(S):
+        for q in range(n):
+            if not (want_mask[s] >> q) & 1:
+                continue
+            n_meas += 1
+            om, gm = o["margin"][s, q], g["margin"][b, s, q]
+            out = (int(g["rec"][b, s, 1]) >> q) & 1
+            if abs(om) > AMBIG:
+                assert out == (0 if om < 0 else 1), (b, s, q, om, gm)
+            assert abs(gm - om) < MARGIN_TOL, (b, s, q, om, gm)
+    assert g["logp"][b] == pytest.approx(o["logp"], abs=1e-5 * max(n_meas, 1) + 1e-9)
+    if norm_tol is None:
+        np.testing.assert_allclose(g["state"][b], o["state"], atol=amp_tol)
+    else:
+        assert np.linalg.norm(g["state"][b] - o["state"]) < norm_tol
+    return n_meas
+
+
+@pytest.mark.parametrize("n", [9, 12, 14])
+@pytest.mark.parametrize("p", [0.2, 0.6])
+def test_mipt_matches_oracle(P, oracle_mod, n, p):
+    w = W.mipt_workload(n, 4, 3, p, seed=300 + n)
+    g = run_gpu(P, w, p)
+    total = 0
+    for b in range(w["batch"]):
+        o = oracle_following(oracle_mod, w, b, p, g)
+        total += check_member(g, o, w, b, p)
+    assert total > 0
+
+
+def test_mipt_without_measurement_is_the_unitary_evolution(P, oracle_mod):
+    n = 10
+    w = W.mipt_workload(n, 5, 2, 0.0, seed=310)
+    g = run_gpu(P, w, 0.0)
+    assert not g["rec"].any() and not g["logp"].any()
+    for b in range(2):
+        o = oracle_mod.mipt(n, w["gates"], W.round_mats(w["mats"][b], "c64"), w["u"][b], 0.0)
+        np.testing.assert_allclose(g["state"][b], o["state"], atol=AMP_TOL)
+
+
+def test_mipt_every_qubit_measured_leaves_basis_states(P, oracle_mod):
+    n = 11
+    w = W.mipt_workload(n, 3, 4, 1.0, seed=311)
+    g = run_gpu(P, w, 1.0)
+    for b in range(4):
+        assert (g["rec"][b, :, 0] == (1 << n) - 1).all()
+        st = g["state"][b]
+        o_last = int(g["rec"][b, -1, 1])
+        nz = np.flatnonzero(st)
+        assert list(nz) == [o_last]
+        assert abs(st[o_last]) == pytest.approx(1.0, abs=1e-6)
+        o = oracle_following(oracle_mod, w, b, 1.0, g)
+        check_member(g, o, w, b, 1.0)
+
+
+def test_mipt_zero_steps_leaves_the_state(P):
+    n = 9
+    w = W.mipt_workload(n, 2, 2, 0.5, seed=312)
+    g = run_gpu(P, w, 0.5, n_steps=0)
+    assert g["rec"].size == 0 and not g["logp"].any()
+    ref = np.zeros(2 ** n, np.complex64)
+    ref[0] = 1
+    for b in range(2):
+        np.testing.assert_array_equal(g["state"][b], ref)
+
+
+def test_mipt_full_size_sampled_members(P, oracle_mod):
+    # the benchmarked launch: n = 20, 40 steps, 1000 trajectories, p = 0.2;
+    # properties for every member, the oracle one by one for two of them
+    n, S, B, p = 20, 40, 1000, 0.2
+    w = W.mipt_workload(n, S, B, p, seed=7)
+    g = run_gpu(P, w, p)
+    norms = np.linalg.norm(g["state"], axis=1)
+    np.testing.assert_allclose(norms, 1.0, atol=1e-4)
+    assert (g["logp"] <= 1e-9).all()
+    want = (w["u"] >= 1 - p).astype(np.uint64) << np.arange(n, dtype=np.uint64)
+    np.testing.assert_array_equal(g["rec"][:, :, 0], want.sum(axis=2).astype(np.uint32))
+    assert not (g["rec"][:, :, 1] & ~g["rec"][:, :, 0]).any()
+    # the last step's measured qubits are definite
+    x = np.arange(2 ** n, dtype=np.uint32)
+    for b in range(0, B, 97):
+        m, o = g["rec"][b, -1, 0], g["rec"][b, -1, 1]
+        assert not np.abs(g["state"][b][(x & m) != o]).any()
+    for b in (0, 613):
+        o = oracle_following(oracle_mod, w, b, p, g)
+        check_member(g, o, w, b, p, norm_tol=NORM_TOL)
