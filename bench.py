@@ -83,7 +83,7 @@ MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
 def workload(name):
     import workloads as W
-    if name.startswith("gates"):
+    if name.startswith("gates") or name == "mipt20":
         return None
     if name == "hea28":
         w = W.cfg2()
@@ -352,6 +352,94 @@ def run_gate_sweep(args, P, torch, n):
     }
 
 
+def run_mipt(args, P, torch):
+    """Monitored Haar brick-wall trajectories (n = 20, 40 steps, 1000
+    trajectories, p = 0.2, complex64): one step = every trajectory from
+    |0...0> through all time steps, the record and Born log-probabilities."""
+    import workloads as W
+    n, S, B, p = 20, 40, 1000, 0.2
+    w = W.mipt_workload(n, S, B, p, seed=7)
+    G = w["gates"].shape[0]
+    step_c = P.Circuit(n, w["gates"], 0, mats=np.tile(np.eye(4), (G, 1, 1)))
+    mats = torch.as_tensor(w["mats"].astype(np.complex64)).cuda().contiguous()
+    u = torch.as_tensor(w["u"]).cuda().contiguous()
+    psi = torch.empty((B, 2 ** n), dtype=torch.complex64, device="cuda")
+    need = ctypes.c_size_t()
+    P.check(P.lib().tcng_mipt_workspace_size(step_c.handle, n, B, ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+    steps = max(1, min(args.steps, 5))
+
+    def one():
+        P.state_init(psi)
+        return P.mipt_run(step_c, mats, psi, u, p, ws=ws)
+
+    for _ in range(min(args.warmup, 1)):
+        one()
+    torch.cuda.synchronize()
+    prof = not args.no_profile
+    if prof:
+        P.check(P.lib().tcng_profile_begin(4000 * (steps + 1)))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rec, logp, _ = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    fam = {}
+    if prof:
+        for i, name in enumerate(FAMILIES):
+            cnt, tot = ctypes.c_int32(), ctypes.c_double()
+            P.check(P.lib().tcng_profile_query(i, ctypes.byref(cnt), ctypes.byref(tot)))
+            if cnt.value:
+                fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
+        P.check(P.lib().tcng_profile_end())
+    # algorithmic HBM bytes per step: fused passes read + write every state;
+    # a marginal reads the state of every member measuring that qubit; a
+    # collapse reads + writes the states of members with a measurement in the step
+    meas = w["u"] >= 1 - p
+    amp = 2 ** n * 8
+    fwd_passes = P.fused_plan_inspect(n, w["gates"], 0)[3]
+    alg = {"fused_fwd": S * fwd_passes * B * 2.0 * amp, "mipt_marg": float(meas.sum()) * amp,
+           "mipt_collapse": float(meas.any(axis=2).sum()) * 2.0 * amp}
+    roofline = None
+    if fam:
+        dom = max((k for k in alg if k in fam), key=lambda k: fam[k]["total_ms"])
+        L = fam[dom]["launches"] / steps
+        t = fam[dom]["avg_ms"] * 1e-3
+        gbs = alg[dom] / L / t / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                    "bytes_per_launch": alg[dom] / L, "avg_launch_ms": round(fam[dom]["avg_ms"], 4),
+                    "algorithmic_bytes_per_step": {k: v for k, v in alg.items()}}
+    out = {
+        "metric": "trajectories/s", "value": B / dt, "unit": "trajectories/s", "n_gpus": 1, "steps": steps,
+        "warmup": min(args.warmup, 1), "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 (f32 state, f64 probabilities)", "data": "synthetic",
+        "config": {"workload": "mipt_haar_n20_d40_b1000_p0.2", "n_qubits": n, "time_steps": S, "trajectories": B,
+                   "p": p, "gates_per_step": G, "parallelism": "single GPU"},
+        "ms_per_trajectory": dt / B * 1e3,
+        "paper_reference": {"ms_per_trajectory": 84.16, "hardware": "NVIDIA H200 (context, not the target)"},
+        "measurements_per_trajectory": float(meas.sum()) / B,
+        "logp_mean": float(logp.mean().item()),
+        "roofline": roofline,
+        "kernels": {k: {"launches_per_step": v["launches"] / steps, "avg_ms": round(v["avg_ms"], 4)}
+                    for k, v in fam.items()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        k, t = 1, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.mipt(n, w["gates"], w["mats"][0, :k], w["u"][0, :k], p)
+            t = time.perf_counter() - t0
+            if t * 2 > 15.0 or k >= S:
+                break
+            k = min(S, max(k + 1, int(k * 15.0 / max(t, 1e-3) * 0.5)))
+        out["cpu_baseline"] = {"value": (k / S) / t, "unit": "trajectories/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {k} of {S} steps of one trajectory at n={n} (complex128, single "
+                                         f"thread), {t:.1f} s, scaled to whole trajectories"}
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle (single-threaded, complex128) on a bounded sample of the
     workload: forward application of the first K gates at full n, K grown
@@ -408,6 +496,10 @@ def main():
         return
     if args.workload == "xxz16_per_circuit":
         out = run_per_circuit(args, w, P, torch)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "mipt20":
+        out = run_mipt(args, P, torch)
         print(json.dumps(out), flush=True)
         return
     n, G, B = w["n"], len(w["gates"]), int(w.get("batch", 1))

@@ -1092,7 +1092,11 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
     J.fmats = w + M.F.fmats_off;
     const DevFusedPlan& F = step->fused;
     const int64_t nm = step->n_mats;
+    J.prec_stride = n_steps * 2;
+    J.pkeep = keep;
     for (int s = 0; s < n_steps; ++s) {
+        // the previous step's collapse, applied by the first forward pass as it loads the tiles
+        J.prec = s > 0 ? rec + size_t(s - 1) * 2 : nullptr;
         // the step's gates: member b takes matrix g.mat of step s at mats[((b * n_steps + s) * nm + g.mat)]
         const void* cm = static_cast<const char*>(mats) + size_t(s) * nm * 16 * sizeof(float) * 2;
         PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, nullptr, 0, cm, n_steps * nm, batch,
@@ -1107,9 +1111,10 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
             PROF_TRY(F_MIPT_DECIDE, launch_mipt_decide(u, n, n_steps, s, q, p, M.wgs, part, rec, keep, logp, margin,
                                                        batch, st));
         }
-        PROF_TRY(F_MIPT_COLLAPSE, launch_mipt_collapse(psi->amps, psi->stride, n, batch, n_steps, s, rec, keep, M.wgs,
-                                                       st));
     }
+    if (n_steps > 0)
+        PROF_TRY(F_MIPT_COLLAPSE, launch_mipt_collapse(psi->amps, psi->stride, n, batch, n_steps, n_steps - 1, rec, keep,
+                                                       M.wgs, st));
     return ok();
 }
 

@@ -137,6 +137,24 @@ __device__ __forceinline__ void ftile_store(float2* const* lds, const gptr<cx<fl
         }
 }
 
+// the same load, each amplitude x first projected: kept (times sc) where
+// (x & md) == bd, zero elsewhere (the collapse of a measurement record)
+template <int IT>
+__device__ __forceinline__ void ftile_load_proj(float2* lds, gptr<cx<float>> st, uint64_t base, const TileIO<IT>& io,
+                                                uint32_t md, uint32_t bd, float sc) {
+    float4 v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) v[it] = *reinterpret_cast<gptr<const float4>>(st + base + io.gt + io.gi[it]);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint32_t x = uint32_t(base + io.gt + io.gi[it]);   // global index of local 2c (bit 0 clear)
+        const float f0 = ((x & md) == bd) ? sc : 0.f, f1 = (((x | 1u) & md) == bd) ? sc : 0.f;
+        const uint32_t a = io.at_ld ^ io.ai_ld[it];
+        lds[a] = make_float2(v[it].x * f0, v[it].y * f0);
+        lds[a ^ io.a1_ld] = make_float2(v[it].z * f1, v[it].w * f1);
+    }
+}
+
 // per-lane view of one phase: addresses of the lane's column (block bits
 // zero) and the uniform images of the block bits and of column bits 0..4
 struct FView {
@@ -240,7 +258,14 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
     const gptr<cx<float>> sts[1] = {psi};
     const TileIO<IT> io = tile_io<IT>(P, t, K.nthr);
 
-    if (active) ftile_load<IT, 1>(bufs, sts, base, io);
+    if (active) {
+        if (J.prec && jl.step == 0 && J.prec[b * J.prec_stride] != 0u) {
+            const uint32_t md = J.prec[b * J.prec_stride], bd = J.prec[b * J.prec_stride + 1];
+            ftile_load_proj<IT>(lds, psi, base, io, md, bd, float(1.0 / sqrt(J.pkeep[b])));
+        } else {
+            ftile_load<IT, 1>(bufs, sts, base, io);
+        }
+    }
     __syncthreads();
     const int f_end = P->phase_end;
     for (int f = P->phase_begin; f < f_end; ++f) {

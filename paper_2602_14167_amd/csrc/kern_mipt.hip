@@ -8,15 +8,17 @@
 // iff v - (1 - p) < p P(bit q = 0 | the step's earlier outcomes).  The
 // projections are not applied one by one: the outcomes decided so far in the
 // step (mask, bits) filter the amplitudes of the next marginal, which gives
-// the conditional probability as a ratio of the two filtered sums; one
-// collapse pass per step then zeroes the inconsistent amplitudes and divides
-// by the square root of the kept mass.
+// the conditional probability as a ratio of the two filtered sums.  The
+// step's collapse (zero the inconsistent amplitudes, divide by the square
+// root of the kept mass) is applied by the next step's first forward pass as
+// it loads its tiles, and after the last step by k_mipt_collapse.
 //
 //   k_mipt_marg     float64 sums of |psi_x|^2 over the consistent x with bit q
 //                   = 0 / = 1, one partial pair per workgroup (HBM-bound read)
 //   k_mipt_decide   one thread per member: fixed-order sum of the partials,
 //                   the Kraus decision, record, kept mass, ln P(outcome)
-//   k_mipt_collapse projection and renormalisation (HBM-bound read + write)
+//   k_mipt_collapse projection and renormalisation after the last step
+//                   (HBM-bound read + write)
 // A member that does not measure q leaves its workgroups at once.
 #include <hip/hip_runtime.h>
 

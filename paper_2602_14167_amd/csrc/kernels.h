@@ -39,10 +39,13 @@ struct Job {
     const FPhase* frphases;
     const void* fmats;        // member b at + b * n_blocks * 2048 floats (forward and reverse operand orders)
     double* opart;            // member b at + b * n_blocks * wgs * 512 (block outer products per workgroup)
+    const uint32_t* prec;     // or null: projection applied as the first fused forward pass loads its tiles,
+    const double* pkeep;      // member b keeps x with (x & prec[b * prec_stride]) == prec[.. + 1], scaled by
+                              // 1 / sqrt(pkeep[b]) (no projection where the mask is 0)
     int64_t stride, batch, tiles;
     int32_t n, n_gates, n_passes, n_ppasses;
     int32_t total_slots, wgs, e_rows, e_wgs;
-    int32_t n_blocks, pad;
+    int32_t n_blocks, prec_stride;
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
