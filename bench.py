@@ -53,10 +53,11 @@ KERNEL_SOURCES = {
     "fused": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_fused.hip", "plan.cpp", "plan.h"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "f906f1d349c202dd"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "f906f1d349c202dd"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.785e9, "33f778e79215f05e"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "33f778e79215f05e"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "773dd391851a0468"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "773dd391851a0468"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.782e9, "c03ef322fe821d69"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "c03ef322fe821d69"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.688e10, "c03ef322fe821d69"),
 }
 
 
@@ -407,7 +408,8 @@ def run_mipt(args, P, torch):
         t = fam[dom]["avg_ms"] * 1e-3
         gbs = alg[dom] / L / t / 1e9
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("mipt_haar_n20_d40_b1000_p0.2", dom), "kernel": dom,
                     "bytes_per_launch": alg[dom] / L, "avg_launch_ms": round(fam[dom]["avg_ms"], 4),
                     "algorithmic_bytes_per_step": {k: v for k, v in alg.items()}}
     out = {

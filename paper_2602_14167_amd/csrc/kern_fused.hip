@@ -435,6 +435,9 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
             }
             __syncthreads();
             if (active) {
+                // issue priority over the co-resident workgroup's memory phase while
+                // this wave feeds the matrix cores
+                __builtin_amdgcn_s_setprio(1);
                 const f16v z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 const f4v z4 = {0.f, 0.f, 0.f, 0.f};
                 f4v ore = z4, oim = z4, ore1 = z4, oim1 = z4;
@@ -485,6 +488,7 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
                     my_stage[r * 128] = ore[r] + ore1[r];
                     my_stage[r * 128 + 64] = oim[r] - oim1[r];
                 }
+                __builtin_amdgcn_s_setprio(0);
             }
             __syncthreads();
         }
