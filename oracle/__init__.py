@@ -7,7 +7,8 @@ Recap": gates as local contractions, E = <psi|H|psi> with H a Pauli sum,
 reverse-mode gradient / parameter-shift rule); it shares no code with the HIP
 library.  Pins that tie it to the mathematics live in tests/test_oracle_pins.py.
 
-It also runs monitored Haar brick-wall trajectories (Sec. "Universal Quantum
+It also builds the sparse (COO) matrix of a Pauli sum (Sec. "Lattice and
+Hamiltonian"), and runs monitored Haar brick-wall trajectories (Sec. "Universal Quantum
 Dynamics of Haar-Random MIPT"): unitary steps, random Z measurements drawn
 from passed-in uniforms, Born log-probability of the record.
 
@@ -16,6 +17,7 @@ Kronecker products for n <= 6, exact diagonalisation against the free-fermion
 closed form, parameter shift vs adjoint, finite differences; for the
 trajectories, tensor-contraction evolution, dense joint Born probabilities,
 p = 0 / p = 1 closed forms and Born-rule sampling statistics in
-tests/test_oracle_mipt.py).
+tests/test_oracle_mipt.py; for the COO entries, dense Kronecker-product
+Hamiltonians, Hermiticity and H psi in tests/test_oracle_coo.py).
 """
 from .api import *  # noqa: F401,F403

@@ -44,6 +44,7 @@ def lib():
         L.orc_norm2.restype = ctypes.c_double
         L.orc_expect_grad.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P, P, P, P]
         L.orc_param_shift.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P]
+        L.orc_pauli_coo.argtypes = [i32, P, P, i32, ctypes.c_int64, ctypes.c_int64, P, P, P, P]
         L.orc_mipt.argtypes = [i32, P, i32, i32, P, i32, P, P, ctypes.c_double, P, P, P, P, P]
         _lib = L
     return _lib
@@ -164,7 +165,7 @@ def param_shift(n, gates, params, codes, coeffs, mats=None, init=None, want_lie=
 
 
 __all__ = ["build", "lib", "run", "apply_matrix", "gate_matrix", "expect", "apply_hamiltonian", "norm2",
-           "expect_grad", "param_shift", "mipt"]
+           "expect_grad", "param_shift", "mipt", "pauli_coo"]
 
 
 def mipt(n, gates, mats, u, p, init=None, force=None):
@@ -189,3 +190,22 @@ def mipt(n, gates, mats, u, p, init=None, force=None):
                         _p(st), _p(rec), _p(logp), _p(margin))
     assert rc == 0, rc
     return dict(state=st, rec=rec[:n_steps], logp=float(logp[0]), margin=margin[:n_steps])
+
+
+def pauli_coo(n, codes, coeffs, row_begin=0, row_count=None):
+    """COO entries of H = sum_k c_k P_k for rows [row_begin, row_begin + row_count):
+    (rows int64, cols int64, vals complex128, n_groups), group-major (X-mask
+    groups in first-appearance order), one entry per (group, row)."""
+    c, w = _ham(codes, coeffs, n)
+    count = 2 ** n - row_begin if row_count is None else int(row_count)
+    # group count first (a single row), then the full range
+    ng = ctypes.c_int()
+    cap = max(c.shape[0], 1) * max(count, 1)
+    rows = np.empty(cap, np.int64)
+    cols = np.empty(cap, np.int64)
+    vals = np.empty(cap, np.complex128)
+    rc = lib().orc_pauli_coo(n, _p(c), _p(w), c.shape[0], int(row_begin), count, _p(rows), _p(cols), _p(vals),
+                             ctypes.byref(ng))
+    assert rc == 0, rc
+    m = ng.value * count
+    return rows[:m], cols[:m], vals[:m], ng.value

@@ -607,4 +607,48 @@ int orc_mipt(int n, const int32_t* gates, int G, int n_steps, const double* mats
     return 0;
 }
 
+// Sparse (COO) matrix of a Pauli sum (Sec. "Lattice and Hamiltonian", the
+// PauliStringSum2COO construction): every term P_k maps a basis state |col>
+// to phase |col xor x_k>, so H[row][col] = sum_k c_k <row|P_k|col> is nonzero
+// only at col = row xor x_k.  Terms are grouped by X-mask, groups in the order
+// their mask first appears in the term list; one entry per (group, row) for
+// rows [row_begin, row_begin + row_count), group-major, the value the sum over
+// the group's terms (taken from the qubit-by-qubit action, in term order; an
+// exact zero is kept).  n_groups receives the group count.
+int orc_pauli_coo(int n, const uint8_t* codes, const double* coeffs, int T, int64_t row_begin, int64_t row_count,
+                  int64_t* rows, int64_t* cols, double* vals, int* n_groups) {
+    auto terms = read_terms(n, codes, coeffs, T);
+    std::vector<uint64_t> xs;
+    std::vector<int> group_of(T);
+    for (int k = 0; k < T; ++k) {
+        uint64_t img;
+        cplx ph;
+        pauli_on_basis(terms[k], 0, img, ph);   // the X-mask is the image of |0>
+        int g = 0;
+        while (g < int(xs.size()) && xs[g] != img) ++g;
+        if (g == int(xs.size())) xs.push_back(img);
+        group_of[k] = g;
+    }
+    *n_groups = int(xs.size());
+    for (int g = 0; g < int(xs.size()); ++g)
+        for (int64_t r = 0; r < row_count; ++r) {
+            const uint64_t row = uint64_t(row_begin + r), col = row ^ xs[g];
+            cplx v = 0.0;
+            for (int k = 0; k < T; ++k) {
+                if (group_of[k] != g) continue;
+                uint64_t img;
+                cplx ph;
+                pauli_on_basis(terms[k], col, img, ph);
+                if (img != row) return 1;
+                v += terms[k].coeff * ph;
+            }
+            const size_t e = size_t(g) * size_t(row_count) + size_t(r);
+            rows[e] = int64_t(row);
+            cols[e] = int64_t(col);
+            vals[2 * e] = v.real();
+            vals[2 * e + 1] = v.imag();
+        }
+    return 0;
+}
+
 }  // extern "C"
