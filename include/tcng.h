@@ -178,8 +178,36 @@ tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const 
                                   tcng_pauli_sum** out);
 tcng_status tcng_pauli_sum_destroy(tcng_pauli_sum* h);
 
+/* Matrix-free Pauli-sum operator (Sec. "Time Evolution": the sparse
+ * matrix-vector product of Krylov and Chebyshev evolution):
+ * out_b = H psi_b for every batch member, and, if energy is not NULL,
+ * energy[b] = Re <psi_b|H|psi_b> accumulated in float64 (DEVICE [batch]).
+ * out must match psi in qubits, dtype, batch and stride and must not alias
+ * it; ws as for tcng_expect_pauli (tcng_workspace_size with c = NULL).
+ * Errors as for tcng_expect_pauli, TCNG_E_INVALID for a mismatched or
+ * aliased output. */
+tcng_status tcng_apply_pauli(const tcng_state* psi, const tcng_pauli_sum* h, const tcng_state* out, double* energy,
+                             int32_t mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Sparse (COO) matrix of the Pauli sum (Sec. "Lattice and Hamiltonian", the
+ * PauliStringSum2COO construction).  A term with X-mask x maps |col> to
+ * |col ^ x>, so H[row][col] is nonzero only at col = row ^ x.  Terms are
+ * grouped by X-mask, groups in the order their mask first appears in the
+ * term list; tcng_pauli_coo_info gives the group count G.
+ * tcng_pauli_coo writes one entry per (group g, row) for the rows
+ * [row_begin, row_begin + row_count), group-major: entry g * row_count + r
+ * holds row = row_begin + r, col = row ^ x_g and the complex128 value
+ * sum over the group's terms (in list order) of c_k <row|P_k|col> (exact
+ * zeros are kept).  rows, cols: DEVICE int64 [G * row_count]; vals: DEVICE
+ * complex128 [G * row_count].  Asynchronous on `stream`.
+ * TCNG_E_INVALID for a row range outside [0, 2^n) or null outputs,
+ * TCNG_E_UNSUPPORTED for n > 62 or more than 65535 groups. */
+tcng_status tcng_pauli_coo_info(const tcng_pauli_sum* h, int32_t* n_groups);
+tcng_status tcng_pauli_coo(const tcng_pauli_sum* h, int64_t row_begin, int64_t row_count, int64_t* rows, int64_t* cols,
+                           void* vals, void* stream);
+
 /* Bytes of workspace needed by tcng_run_circuit / tcng_expect_pauli /
- * tcng_expect_grad / tcng_graph_create for this shape (c or h may be NULL
+ * tcng_apply_pauli / tcng_expect_grad / tcng_graph_create for this shape (c or h may be NULL
  * when not used); the caller allocates it (device memory). */
 tcng_status tcng_workspace_size(const tcng_circuit* c, const tcng_pauli_sum* h, int32_t dtype, int64_t batch,
                                 int32_t mode, size_t* bytes);

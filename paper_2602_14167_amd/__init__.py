@@ -21,7 +21,8 @@ from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_M
                    TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
-           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run"]
+           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
+           "apply_pauli", "pauli_coo"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
 
@@ -208,6 +209,39 @@ def expect_pauli(psi: torch.Tensor, H: PauliSum, mode="tiled", out=None):
     check(lib().tcng_expect_pauli(ctypes.byref(s), H.handle, ctypes.c_void_p(out.data_ptr()), m,
                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out
+
+
+def apply_pauli(psi: torch.Tensor, H: PauliSum, out=None, want_energy=False, mode="tiled"):
+    """Matrix-free H psi for every batch member (a new tensor unless `out` is
+    given); with want_energy also float64 [batch] of Re <psi|H|psi>."""
+    s = _state(psi, H.n)
+    if out is None:
+        out = torch.empty_like(psi)
+    o = _state(out, H.n)
+    m = _mode(mode)
+    ws = _workspace(None, H, s.dtype, s.batch, m, psi.device)
+    e = torch.empty(s.batch, dtype=torch.float64, device=psi.device) if want_energy else None
+    check(lib().tcng_apply_pauli(ctypes.byref(s), H.handle, ctypes.byref(o),
+                                 ctypes.c_void_p(e.data_ptr()) if e is not None else None, m,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return (out, e) if want_energy else out
+
+
+def pauli_coo(H: PauliSum, row_begin=0, row_count=None, device="cuda"):
+    """Sparse (COO) form of H for rows [row_begin, row_begin + row_count):
+    (rows int64, cols int64, vals complex128), group-major (one entry per
+    X-mask group and row)."""
+    g = ctypes.c_int32()
+    check(lib().tcng_pauli_coo_info(H.handle, ctypes.byref(g)))
+    count = (1 << H.n) - row_begin if row_count is None else int(row_count)
+    m = g.value * count
+    rows = torch.empty(m, dtype=torch.int64, device=device)
+    cols = torch.empty(m, dtype=torch.int64, device=device)
+    vals = torch.empty(m, dtype=torch.complex128, device=device)
+    check(lib().tcng_pauli_coo(H.handle, int(row_begin), count, ctypes.c_void_p(rows.data_ptr()) if m else None,
+                               ctypes.c_void_p(cols.data_ptr()) if m else None,
+                               ctypes.c_void_p(vals.data_ptr()) if m else None, _stream()))
+    return rows, cols, vals
 
 
 def expect_grad(circ: Circuit, params, H: PauliSum, psi=None, lam=None, batch=None, dtype=torch.complex64,

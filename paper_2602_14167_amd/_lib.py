@@ -24,7 +24,7 @@ EXPORTS = [
     "tcng_fused_plan_inspect", "tcng_graph_create", "tcng_graph_launch", "tcng_graph_destroy",
     "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end", "tcng_circuit_configure",
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
-    "tcng_mipt_workspace_size", "tcng_mipt_run",
+    "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
 ]
 
 
@@ -85,6 +85,9 @@ def lib():
     L.tcng_graph_destroy.argtypes = [P]
     L.tcng_fused_plan_inspect.argtypes = [i32, P, i32, i32, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+    L.tcng_apply_pauli.argtypes = [PS, P, PS, P, i32, P, sz, P]
+    L.tcng_pauli_coo_info.argtypes = [P, ctypes.POINTER(i32)]
+    L.tcng_pauli_coo.argtypes = [P, i64, i64, P, P, P, P]
     L.tcng_mipt_workspace_size.argtypes = [P, i32, i64, ctypes.POINTER(sz)]
     L.tcng_mipt_run.argtypes = [P, i32, P, PS, P, ctypes.c_double, P, P, P, P, sz, P]
     for name in EXPORTS:

@@ -191,6 +191,12 @@ struct tcng_pauli_sum {
     bool tiled_valid[2] = {false, false};
     PauliPlan tplan[2];
     DevPauliPlan dplan[2];
+    // sparse form: X-mask groups in first-appearance order, their terms in list order
+    int coo_groups = 0;
+    uint64_t* coo_x = nullptr;       // [groups]
+    int32_t* coo_start = nullptr;    // [groups + 1]
+    uint64_t* coo_z = nullptr;       // [terms]
+    double* coo_c = nullptr;         // [terms][2]: c i^(number of Y)
 };
 
 namespace {
@@ -753,6 +759,38 @@ tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const 
         }
         h->terms.push_back(th);
     }
+    {
+        std::vector<uint64_t> gx;
+        std::vector<std::vector<int>> members;
+        for (int t = 0; t < n_terms; ++t) {
+            size_t g = 0;
+            while (g < gx.size() && gx[g] != h->terms[t].x) ++g;
+            if (g == gx.size()) {
+                gx.push_back(h->terms[t].x);
+                members.emplace_back();
+            }
+            members[g].push_back(t);
+        }
+        std::vector<int32_t> start(1, 0);
+        std::vector<uint64_t> z;
+        std::vector<double> cc;
+        static const double re_i[4] = {1.0, 0.0, -1.0, 0.0}, im_i[4] = {0.0, 1.0, 0.0, -1.0};
+        for (auto& mem : members) {
+            for (int t : mem) {
+                const PauliTermHost& th = h->terms[t];
+                z.push_back(th.z);
+                cc.push_back(th.c * re_i[th.ny & 3]);
+                cc.push_back(th.c * im_i[th.ny & 3]);
+            }
+            start.push_back(int32_t(z.size()));
+        }
+        h->coo_groups = int(gx.size());
+        if (gx.empty()) gx.push_back(0);
+        if (z.empty()) { z.push_back(0); cc.push_back(0.0); cc.push_back(0.0); }
+        if (upload(gx, &h->coo_x) != hipSuccess || upload(start, &h->coo_start) != hipSuccess ||
+            upload(z, &h->coo_z) != hipSuccess || upload(cc, &h->coo_c) != hipSuccess)
+            return cleanup(fail(TCNG_E_ALLOC, "device allocation failed"));
+    }
     std::vector<PClassFull> cls;
     std::vector<PTermFull> tf;
     group_pauli_full(h->terms, h->groups_full, cls, tf);
@@ -785,6 +823,10 @@ tcng_status tcng_pauli_sum_destroy(tcng_pauli_sum* h) {
     (void)hipDeviceSynchronize();
     (void)hipFree(h->classes_full);
     (void)hipFree(h->terms_full);
+    (void)hipFree(h->coo_x);
+    (void)hipFree(h->coo_start);
+    (void)hipFree(h->coo_z);
+    (void)hipFree(h->coo_c);
     for (auto& d : h->dplan) {
         (void)hipFree(const_cast<PPass*>(d.passes));
         (void)hipFree(const_cast<PGroup*>(d.groups));
@@ -866,6 +908,57 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
     double* red = reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off);
     PROF_TRY(F_FINISH, launch_finish(nullptr, 0, 1, nullptr, nullptr, 0, epart, L.e_rows, L.e_wgs, s->batch, out, nullptr,
                           nullptr, nullptr, nullptr, nullptr, 0, red, st));
+    return ok();
+}
+
+tcng_status tcng_apply_pauli(const tcng_state* psi, const tcng_pauli_sum* h, const tcng_state* out, double* energy,
+                             int32_t mode, void* ws, size_t ws_bytes, void* stream) {
+    if (tcng_status e = check_state(psi, "tcng_apply_pauli")) return e;
+    if (tcng_status e = check_state(out, "tcng_apply_pauli (output)")) return e;
+    if (!h) return fail(TCNG_E_INVALID, "null Pauli sum");
+    if (h->n != psi->n_qubits) return fail(TCNG_E_INVALID, "Pauli sum and state differ in qubit count");
+    if (out->n_qubits != psi->n_qubits || out->dtype != psi->dtype || out->batch != psi->batch ||
+        out->stride != psi->stride)
+        return fail(TCNG_E_INVALID, "output state must match the input's qubits, dtype, batch and stride");
+    if (out->amps == psi->amps) return fail(TCNG_E_INVALID, "the output must not alias the input state");
+    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
+        return fail(TCNG_E_INVALID, "bad mode");
+    mode = pauli_mode(mode, h, h->n, psi->dtype);
+    const WsLayout L = layout(nullptr, h, psi->n_qubits, psi->dtype, psi->batch, mode);
+    if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
+    const Job J = make_job(nullptr, h, psi, out->amps, nullptr, nullptr, epart, L);
+    tcng_status e = psi->dtype == TCNG_C64 ? run_pauli<float, 5>(h, psi, out->amps, L, epart, mode, J, st)
+                                           : run_pauli<double, 4>(h, psi, out->amps, L, epart, mode, J, st);
+    if (e) return e;
+    if (energy) {
+        double* red = reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off);
+        PROF_TRY(F_FINISH, launch_finish(nullptr, 0, 1, nullptr, nullptr, 0, epart, L.e_rows, L.e_wgs, psi->batch, energy,
+                                         nullptr, nullptr, nullptr, nullptr, nullptr, 0, red, st));
+    }
+    return ok();
+}
+
+tcng_status tcng_pauli_coo_info(const tcng_pauli_sum* h, int32_t* n_groups) {
+    if (!h || !n_groups) return fail(TCNG_E_INVALID, "null Pauli sum or output");
+    *n_groups = h->coo_groups;
+    return ok();
+}
+
+tcng_status tcng_pauli_coo(const tcng_pauli_sum* h, int64_t row_begin, int64_t row_count, int64_t* rows, int64_t* cols,
+                           void* vals, void* stream) {
+    if (!h) return fail(TCNG_E_INVALID, "null Pauli sum");
+    if (h->n > 62) return fail(TCNG_E_UNSUPPORTED, "COO indices need n <= 62");
+    const int64_t dim = int64_t(1) << h->n;
+    if (row_begin < 0 || row_count < 0 || row_begin > dim || row_count > dim - row_begin)
+        return fail(TCNG_E_INVALID, "row range outside [0, 2^n)");
+    if (row_count == 0 || h->coo_groups == 0) return ok();
+    if (h->coo_groups > 65535) return fail(TCNG_E_UNSUPPORTED, "more than 65535 distinct X-masks");
+    if (!rows || !cols || !vals) return fail(TCNG_E_INVALID, "null output arrays");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PROF_TRY(F_PAULI_GROUP, launch_pauli_coo(h->coo_x, h->coo_start, h->coo_z, h->coo_c, h->coo_groups, row_begin,
+                                             row_count, rows, cols, vals, st));
     return ok();
 }
 

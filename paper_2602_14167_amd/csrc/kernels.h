@@ -117,6 +117,12 @@ hipError_t launch_pauli_group(const void* state, void* costate, bool accumulate,
                               uint64_t x, const PClassFull* classes, int class_begin, int class_end,
                               const PTermFull* terms, int wgs, double* epart, int row, int n_rows, hipStream_t st);
 
+// ---- sparse form of a Pauli sum: entry (g, r) = row row_begin + r, col row ^ gx[g],
+// value sum over the group's terms [gstart[g], gstart[g+1]) of tc * (-1)^popcount(col & tz)
+hipError_t launch_pauli_coo(const uint64_t* gx, const int32_t* gstart, const uint64_t* tz, const double* tc, int groups,
+                            int64_t row_begin, int64_t row_count, int64_t* rows, int64_t* cols, void* vals,
+                            hipStream_t st);
+
 // ---- monitored trajectories (complex64): marginal partials of qubit q on the
 // amplitudes consistent with the step's decided outcomes, the Kraus decision,
 // the per-step collapse.  wgs = mipt_wgs(n) workgroups per member.
