@@ -51,13 +51,15 @@ KIND_NAME = {v: k for k, v in KIND.items()}
 KERNEL_SOURCES = {
     "tile": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_tile.hip", "plan.cpp", "plan.h"],
     "fused": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_fused.hip", "plan.cpp", "plan.h"],
+    "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "773dd391851a0468"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "773dd391851a0468"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.782e9, "c03ef322fe821d69"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "c03ef322fe821d69"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.688e10, "c03ef322fe821d69"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "1a01cf308e684ac9"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "1a01cf308e684ac9"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.782e9, "5654b808a9af9ec0"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "5654b808a9af9ec0"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.688e10, "5654b808a9af9ec0"),
+    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "58cb5da6ee9a435c"),
 }
 
 
@@ -65,7 +67,8 @@ def source_hash(kernel):
     import hashlib
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_2602_14167_amd", "csrc")
-    for f in KERNEL_SOURCES["fused" if kernel.startswith("fused") else "tile"]:
+    group = "fused" if kernel.startswith("fused") else ("pauli" if kernel.startswith("pauli") else "tile")
+    for f in KERNEL_SOURCES[group]:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,13 +81,14 @@ def measured_traffic(workload_name, kernel):
         return None
     return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
-            "finish", "init", "fused_fwd", "fused_rev", "fused_grad", "mipt_marg", "mipt_decide", "mipt_collapse"]
+            "finish", "init", "fused_fwd", "fused_rev", "fused_grad", "mipt_marg", "mipt_decide", "mipt_collapse",
+            "pauli_coo"]
 MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
 
 def workload(name):
     import workloads as W
-    if name.startswith("gates") or name == "mipt20":
+    if name.startswith("gates") or name in ("mipt20", "coo22", "coo24"):
         return None
     if name == "hea28":
         w = W.cfg2()
@@ -443,6 +447,81 @@ def run_mipt(args, P, torch):
     return out
 
 
+def run_coo(args, P, torch, n):
+    """Sparse (COO) matrix of the open TFIM (-sum ZZ - sum X) on n qubits in
+    complex128: one step = every entry of the matrix written to HBM."""
+    import workloads as W
+    codes, coeffs = W.tfim_1d(n, 1.0, 1.0)
+    H = P.PauliSum(n, codes, coeffs)
+    g = ctypes.c_int32()
+    P.check(P.lib().tcng_pauli_coo_info(H.handle, ctypes.byref(g)))
+    G, dim = g.value, 1 << n
+    nnz = G * dim
+    rows = torch.empty(nnz, dtype=torch.int64, device="cuda")
+    cols = torch.empty(nnz, dtype=torch.int64, device="cuda")
+    vals = torch.empty(nnz, dtype=torch.complex128, device="cuda")
+    args_c = (H.handle, 0, dim, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(cols.data_ptr()),
+              ctypes.c_void_p(vals.data_ptr()), P._stream())
+
+    def one():
+        P.check(P.lib().tcng_pauli_coo(*args_c))
+
+    for _ in range(max(args.warmup, 1)):
+        one()
+    torch.cuda.synchronize()
+    prof = not args.no_profile
+    if prof:
+        P.check(P.lib().tcng_profile_begin(args.steps + 8))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fam = {}
+    if prof:
+        for i, name in enumerate(FAMILIES):
+            cnt, tot = ctypes.c_int32(), ctypes.c_double()
+            P.check(P.lib().tcng_profile_query(i, ctypes.byref(cnt), ctypes.byref(tot)))
+            if cnt.value:
+                fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
+        P.check(P.lib().tcng_profile_end())
+    nbytes = 32.0 * nnz
+    roofline = None
+    if "pauli_coo" in fam:
+        t = fam["pauli_coo"]["avg_ms"] * 1e-3
+        gbs = nbytes / t / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"tfim_coo_n{n}", "pauli_coo"),
+                    "kernel": "pauli_coo", "bytes_per_launch": nbytes, "avg_launch_ms": round(fam["pauli_coo"]["avg_ms"], 4)}
+    paper_ms = {22: 19.0, 24: 59.0}.get(n)
+    out = {
+        "metric": "coo-entries/s", "value": nnz / dt, "unit": "coo-entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128 values, int64 indices", "data": "synthetic",
+        "config": {"workload": f"tfim_coo_n{n}", "n_qubits": n, "terms": len(coeffs), "groups": G, "entries": nnz,
+                   "parallelism": "single GPU"},
+        "paper_reference": ({"ms_per_build": paper_ms, "hardware": "NVIDIA H200 (context, not the target)"}
+                            if paper_ms else None),
+        "roofline": roofline,
+        "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}
+                    for k, v in fam.items()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cnt, t = 1 << 10, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.pauli_coo(n, codes, coeffs, 0, cnt)
+            t = time.perf_counter() - t0
+            if t * 2 > 15.0 or cnt >= dim:
+                break
+            cnt = min(dim, max(cnt * 2, int(cnt * 15.0 / max(t, 1e-3) * 0.5)))
+        out["cpu_baseline"] = {"value": G * cnt / t, "unit": "coo-entries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"rows [0, {cnt}) of the n={n} TFIM matrix ({G} groups, single thread), "
+                                         f"{t:.1f} s"}
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle (single-threaded, complex128) on a bounded sample of the
     workload: forward application of the first K gates at full n, K grown
@@ -503,6 +582,10 @@ def main():
         return
     if args.workload == "mipt20":
         out = run_mipt(args, P, torch)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload in ("coo22", "coo24"):
+        out = run_coo(args, P, torch, int(args.workload[-2:]))
         print(json.dumps(out), flush=True)
         return
     n, G, B = w["n"], len(w["gates"]), int(w.get("batch", 1))

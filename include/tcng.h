@@ -254,8 +254,9 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
  *   9 final reduction     10 state init
  *   11 fused forward pass  12 fused reverse pass  13 fused block matrices and gradients
  *   14 trajectory marginal pass  15 trajectory decisions  16 trajectory collapse
+ *   17 Pauli-sum COO entries
  * tcng_profile_end stops recording and frees the events. */
-enum { TCNG_PROF_FAMILIES = 17 };
+enum { TCNG_PROF_FAMILIES = 18 };
 tcng_status tcng_profile_begin(int32_t max_launches);
 tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
 tcng_status tcng_profile_end(void);

@@ -50,7 +50,7 @@ constexpr int MAX_QUBITS = 34;
 // ---------------------------------------------------------------------------
 enum Family { F_FWD_TILE, F_REV_TILE, F_PAULI_TILE, F_GATE1, F_GATE2, F_GATEK, F_REV1, F_REV2, F_PAULI_GROUP,
               F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_MIPT_MARG, F_MIPT_DECIDE,
-              F_MIPT_COLLAPSE, F_COUNT };
+              F_MIPT_COLLAPSE, F_PAULI_COO, F_COUNT };
 static_assert(F_COUNT == TCNG_PROF_FAMILIES, "profiler families");
 
 struct Profiler {
@@ -957,7 +957,7 @@ tcng_status tcng_pauli_coo(const tcng_pauli_sum* h, int64_t row_begin, int64_t r
     if (h->coo_groups > 65535) return fail(TCNG_E_UNSUPPORTED, "more than 65535 distinct X-masks");
     if (!rows || !cols || !vals) return fail(TCNG_E_INVALID, "null output arrays");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    PROF_TRY(F_PAULI_GROUP, launch_pauli_coo(h->coo_x, h->coo_start, h->coo_z, h->coo_c, h->coo_groups, row_begin,
+    PROF_TRY(F_PAULI_COO, launch_pauli_coo(h->coo_x, h->coo_start, h->coo_z, h->coo_c, h->coo_groups, row_begin,
                                              row_count, rows, cols, vals, st));
     return ok();
 }
