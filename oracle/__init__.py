@@ -8,7 +8,8 @@ reverse-mode gradient / parameter-shift rule); it shares no code with the HIP
 library.  Pins that tie it to the mathematics live in tests/test_oracle_pins.py.
 
 It also builds the sparse (COO) matrix of a Pauli sum (Sec. "Lattice and
-Hamiltonian"), and runs monitored Haar brick-wall trajectories (Sec. "Universal Quantum
+Hamiltonian"), draws classical-shadow snapshots (Sec. "Efficient ML Pipeline
+via Classical Shadows"), and runs monitored Haar brick-wall trajectories (Sec. "Universal Quantum
 Dynamics of Haar-Random MIPT"): unitary steps, random Z measurements drawn
 from passed-in uniforms, Born log-probability of the record.
 
@@ -18,6 +19,8 @@ closed form, parameter shift vs adjoint, finite differences; for the
 trajectories, tensor-contraction evolution, dense joint Born probabilities,
 p = 0 / p = 1 closed forms and Born-rule sampling statistics in
 tests/test_oracle_mipt.py; for the COO entries, dense Kronecker-product
-Hamiltonians, Hermiticity and H psi in tests/test_oracle_coo.py).
+Hamiltonians, Hermiticity and H psi in tests/test_oracle_coo.py; for the
+shadows, eigenstates, GHZ parities, Born frequencies, the unbiased shadow
+estimator and Kronecker-product rotations in tests/test_oracle_shadow.py).
 """
 from .api import *  # noqa: F401,F403

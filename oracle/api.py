@@ -45,6 +45,7 @@ def lib():
         L.orc_expect_grad.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P, P, P, P]
         L.orc_param_shift.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P]
         L.orc_pauli_coo.argtypes = [i32, P, P, i32, ctypes.c_int64, ctypes.c_int64, P, P, P, P]
+        L.orc_shadow.argtypes = [i32, P, i32, P, P, P, P, P]
         L.orc_mipt.argtypes = [i32, P, i32, i32, P, i32, P, P, ctypes.c_double, P, P, P, P, P]
         _lib = L
     return _lib
@@ -165,7 +166,7 @@ def param_shift(n, gates, params, codes, coeffs, mats=None, init=None, want_lie=
 
 
 __all__ = ["build", "lib", "run", "apply_matrix", "gate_matrix", "expect", "apply_hamiltonian", "norm2",
-           "expect_grad", "param_shift", "mipt", "pauli_coo"]
+           "expect_grad", "param_shift", "mipt", "pauli_coo", "shadow"]
 
 
 def mipt(n, gates, mats, u, p, init=None, force=None):
@@ -209,3 +210,19 @@ def pauli_coo(n, codes, coeffs, row_begin=0, row_count=None):
     assert rc == 0, rc
     m = ng.value * count
     return rows[:m], cols[:m], vals[:m], ng.value
+
+
+def shadow(n, psi, bases, u):
+    """Classical-shadow snapshots of one state: bases uint8 [S, n] (1=X, 2=Y, 3=Z),
+    u [S] uniforms.  Returns (outcomes int64 [S], lo [S], hi [S]) with lo / hi the
+    normalised running probability just before and at the outcome."""
+    x = _c128(psi)
+    b = np.ascontiguousarray(np.asarray(bases, dtype=np.uint8).reshape(-1, n))
+    S = b.shape[0]
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(S))
+    out = np.empty(max(S, 1), np.int64)
+    lo = np.empty(max(S, 1))
+    hi = np.empty(max(S, 1))
+    rc = lib().orc_shadow(n, _p(x), S, _p(b), _p(uu), _p(out), _p(lo), _p(hi))
+    assert rc == 0, rc
+    return out[:S], lo[:S], hi[:S]

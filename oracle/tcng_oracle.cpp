@@ -651,4 +651,49 @@ int orc_pauli_coo(int n, const uint8_t* codes, const double* coeffs, int T, int6
     return 0;
 }
 
+// Classical-shadow snapshots (Sec. "Efficient ML Pipeline via Classical
+// Shadows", shadow_snapshots with measurement only): snapshot s measures
+// every qubit q in the Pauli basis bases[s][q] (1 = X, 2 = Y, 3 = Z): the
+// state is rotated by V_q (X: H; Y: H S^dagger; Z: identity), so that Z
+// outcome 0 is the +1 eigenvector of the chosen Pauli, and one basis state x
+// is drawn from |psi'_x|^2 by the inverse distribution function with the
+// uniform u[s]: the first x whose running sum of probabilities (in increasing
+// x, normalised by the total) exceeds u[s].
+//   out[s]: the outcome x (bit q = outcome of qubit q);
+//   lo / hi (nullable) [s]: the running sums just before and at x.
+int orc_shadow(int n, const double* psi_in, int S, const uint8_t* bases, const double* u, int64_t* out, double* lo,
+               double* hi) {
+    if (n < 1 || n > 30) return 1;
+    const uint64_t dim = uint64_t(1) << n;
+    const double r = 1.0 / std::sqrt(2.0);
+    Mat4 VX = zero4(), VY = zero4();
+    VX.m[0][0] = r; VX.m[0][1] = r; VX.m[1][0] = r; VX.m[1][1] = -r;
+    VY.m[0][0] = r; VY.m[0][1] = cplx(0.0, -r); VY.m[1][0] = r; VY.m[1][1] = cplx(0.0, r);   // H S^dagger
+    const std::vector<cplx> psi0 = initial_state(n, psi_in);
+    for (int s = 0; s < S; ++s) {
+        std::vector<cplx> psi = psi0;
+        for (int q = 0; q < n; ++q) {
+            const uint8_t b = bases[size_t(s) * n + q];
+            if (b < 1 || b > 3) return 2;
+            if (b == 3) continue;
+            int qq[1] = {q};
+            apply_matrix(n, psi, qq, 1, b == 1 ? VX : VY);
+        }
+        auto w = [&](uint64_t k) { return cplx(std::norm(psi[k]), 0.0); };
+        const double total = pairwise_sum(w, 0, dim).real();
+        const double target = u[s] * total;
+        double run = 0.0, prev = 0.0;
+        uint64_t x = dim - 1;
+        for (uint64_t k = 0; k < dim; ++k) {
+            prev = run;
+            run += std::norm(psi[k]);
+            if (run > target) { x = k; break; }
+        }
+        out[s] = int64_t(x);
+        if (lo) lo[s] = prev / total;
+        if (hi) hi[s] = run / total;
+    }
+    return 0;
+}
+
 }  // extern "C"

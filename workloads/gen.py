@@ -118,6 +118,19 @@ def mipt_workload(n: int, steps: int, batch: int, p: float, seed: int):
     return dict(n=n, steps=steps, batch=batch, p=float(p), gates=gates, mats=mats, u=u)
 
 
+def shadow_workload(n: int, snapshots: int, seed: int):
+    """Classical-shadow snapshots of one n-qubit state (Sec. "Efficient ML
+    Pipeline via Classical Shadows"): a seeded random state (standing in for
+    the paper's ground state), Pauli bases drawn uniformly from {1=X, 2=Y, 3=Z}
+    per snapshot and qubit, and one uniform per snapshot for the outcome draw.
+    Draw order: state, bases [snapshots][n], uniforms [snapshots]."""
+    rng = np.random.default_rng(seed)
+    psi = random_state(n, rng)
+    bases = rng.integers(1, 4, size=(snapshots, n)).astype(np.uint8)
+    u = rng.uniform(0.0, 1.0, size=snapshots)
+    return dict(n=n, snapshots=snapshots, psi=psi, bases=bases, u=u)
+
+
 def brickwork_fsim(n: int, depth: int, rng: np.random.Generator):
     """fSim brick-wall; per gate theta then phi drawn U[0, 2pi) in gate order."""
     bonds = brickwork_bonds(n, depth)
