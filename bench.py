@@ -82,7 +82,7 @@ def measured_traffic(workload_name, kernel):
     return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
             "finish", "init", "fused_fwd", "fused_rev", "fused_grad", "mipt_marg", "mipt_decide", "mipt_collapse",
-            "pauli_coo"]
+            "pauli_coo", "shadow_sum", "shadow_pick"]
 MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
 

@@ -254,9 +254,9 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
  *   9 final reduction     10 state init
  *   11 fused forward pass  12 fused reverse pass  13 fused block matrices and gradients
  *   14 trajectory marginal pass  15 trajectory decisions  16 trajectory collapse
- *   17 Pauli-sum COO entries
+ *   17 Pauli-sum COO entries  18 shadow chunk sums  19 shadow rotations and draws
  * tcng_profile_end stops recording and frees the events. */
-enum { TCNG_PROF_FAMILIES = 18 };
+enum { TCNG_PROF_FAMILIES = 20 };
 tcng_status tcng_profile_begin(int32_t max_launches);
 tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
 tcng_status tcng_profile_end(void);
@@ -305,6 +305,30 @@ tcng_status tcng_graph_destroy(tcng_graph* g);
 tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                                     int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
                                     int32_t* n_blocks, int32_t* bad_layouts);
+
+/* Classical-shadow snapshots (Sec. "Efficient ML Pipeline via Classical
+ * Shadows", measurement only): snapshot s measures every qubit q of the state
+ * in the Pauli basis bases[s][q] (1 = X, 2 = Y, 3 = Z): the state is rotated
+ * by V_q (X: H; Y: H S^dagger; Z: identity), so that outcome 0 is the +1
+ * eigenvector of the chosen Pauli, and one basis state x is drawn from
+ * |psi'_x|^2 by the inverse distribution function with the uniform u[s]:
+ * the first x whose running probability (increasing x, float64) exceeds u[s].
+ *   layer     circuit of n one-qubit gates, gate q = U1 on qubit q with matrix
+ *             q (its creation matrices only fix the count); needs n >= 9;
+ *   psi       device complex64 [2^n], the state (not modified);
+ *   work      complex64 state with batch = number of snapshots S, overwritten
+ *             with the rotated copies;
+ *   bases     device uint8 [S][n] (codes other than 1 and 2 act as 3);
+ *   u         device float64 [S] in [0, 1);
+ *   outcomes  device int64 [S]: x, bit q = the outcome of qubit q (written);
+ *   ws        device workspace of tcng_shadow_workspace_size bytes.
+ * Asynchronous on `stream`; TCNG_E_UNSUPPORTED for complex128 or n < 9,
+ * TCNG_E_INVALID for a malformed layer, mismatched state or null arguments,
+ * TCNG_E_WORKSPACE if ws is too small. */
+tcng_status tcng_shadow_workspace_size(const tcng_circuit* layer, int64_t snapshots, size_t* bytes);
+tcng_status tcng_shadow_snapshots(const tcng_circuit* layer, const void* psi, const tcng_state* work,
+                                  const uint8_t* bases, const double* u, int64_t* outcomes, void* ws, size_t ws_bytes,
+                                  void* stream);
 
 /* Monitored Haar brick-wall trajectories (Sec. "Universal Quantum Dynamics of
  * Haar-Random MIPT": per time step two layers of Haar two-qubit gates on the

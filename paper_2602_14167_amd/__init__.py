@@ -17,12 +17,12 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TcngError, TcngGate,  # noqa: F401
-                   TcngState, check, lib)
+from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TCNG_U1_KIND,  # noqa: F401
+                   TcngError, TcngGate, TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
            "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
-           "apply_pauli", "pauli_coo"]
+           "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
 
@@ -445,3 +445,36 @@ def mipt_run(step: Circuit, mats: torch.Tensor, psi: torch.Tensor, u: torch.Tens
                               ctypes.c_void_p(margin.data_ptr()) if margin is not None else None,
                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return rec, logp, margin
+
+
+def shadow_layer(n: int) -> Circuit:
+    """The rotation layer of classical-shadow snapshots: U1 on every qubit q
+    taking per-snapshot matrix q."""
+    g = np.array([[TCNG_U1_KIND, q, -1, -1, -1, q] for q in range(n)], dtype=np.int32)
+    return Circuit(n, g, 0, mats=np.tile(np.eye(4), (n, 1, 1)))
+
+
+def shadow_snapshots(layer: Circuit, psi: torch.Tensor, bases: torch.Tensor, u: torch.Tensor, work=None, ws=None):
+    """Classical-shadow snapshots of one complex64 state psi [2^n]: bases uint8
+    [S][n] (1=X, 2=Y, 3=Z), u float64 [S].  Returns int64 [S] outcomes (bit q =
+    outcome of qubit q); `work` ([S, 2^n] complex64) receives the rotated copies."""
+    n, S = layer.n, int(u.shape[0])
+    if psi.dtype != torch.complex64 or psi.numel() != 2 ** n or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous complex64 vector of 2^n amplitudes")
+    if bases.dtype != torch.uint8 or tuple(bases.shape) != (S, n) or not bases.is_contiguous():
+        raise ValueError("bases must be contiguous uint8 [S][n]")
+    if u.dtype != torch.float64 or not u.is_contiguous():
+        raise ValueError("u must be contiguous float64 [S]")
+    if work is None:
+        work = torch.empty((S, 2 ** n), dtype=torch.complex64, device=psi.device)
+    w = _state(work, n)
+    if ws is None:
+        need = ctypes.c_size_t()
+        check(lib().tcng_shadow_workspace_size(layer.handle, S, ctypes.byref(need)))
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=psi.device)
+    out = torch.empty(S, dtype=torch.int64, device=psi.device)
+    check(lib().tcng_shadow_snapshots(layer.handle, ctypes.c_void_p(psi.data_ptr()), ctypes.byref(w),
+                                      ctypes.c_void_p(bases.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream()))
+    return out

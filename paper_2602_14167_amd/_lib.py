@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtcng.so")
 TCNG_OK, TCNG_E_INVALID, TCNG_E_UNSUPPORTED, TCNG_E_WORKSPACE, TCNG_E_HIP, TCNG_E_ALLOC = range(6)
 TCNG_C64, TCNG_C128 = 0, 1
 TCNG_MODE_TILED, TCNG_MODE_PLAIN, TCNG_MODE_FUSED = 0, 1, 2
+TCNG_U1_KIND = 12   # constant one-qubit gate (top-left 2 x 2 block of its matrix)
 
 # every function include/tcng.h declares
 EXPORTS = [
@@ -25,6 +26,7 @@ EXPORTS = [
     "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end", "tcng_circuit_configure",
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
+    "tcng_shadow_workspace_size", "tcng_shadow_snapshots",
 ]
 
 
@@ -88,6 +90,8 @@ def lib():
     L.tcng_apply_pauli.argtypes = [PS, P, PS, P, i32, P, sz, P]
     L.tcng_pauli_coo_info.argtypes = [P, ctypes.POINTER(i32)]
     L.tcng_pauli_coo.argtypes = [P, i64, i64, P, P, P, P]
+    L.tcng_shadow_workspace_size.argtypes = [P, i64, ctypes.POINTER(sz)]
+    L.tcng_shadow_snapshots.argtypes = [P, P, PS, P, P, P, P, sz, P]
     L.tcng_mipt_workspace_size.argtypes = [P, i32, i64, ctypes.POINTER(sz)]
     L.tcng_mipt_run.argtypes = [P, i32, P, PS, P, ctypes.c_double, P, P, P, P, sz, P]
     for name in EXPORTS:

@@ -50,7 +50,7 @@ constexpr int MAX_QUBITS = 34;
 // ---------------------------------------------------------------------------
 enum Family { F_FWD_TILE, F_REV_TILE, F_PAULI_TILE, F_GATE1, F_GATE2, F_GATEK, F_REV1, F_REV2, F_PAULI_GROUP,
               F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_MIPT_MARG, F_MIPT_DECIDE,
-              F_MIPT_COLLAPSE, F_PAULI_COO, F_COUNT };
+              F_MIPT_COLLAPSE, F_PAULI_COO, F_SHADOW_SUM, F_SHADOW_PICK, F_COUNT };
 static_assert(F_COUNT == TCNG_PROF_FAMILIES, "profiler families");
 
 struct Profiler {
@@ -1122,6 +1122,74 @@ tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, in
     if (n_passes) *n_passes = int32_t(P.passes.size());
     if (n_blocks) *n_blocks = P.n_blocks;
     if (bad_layouts) *bad_layouts = check_fused_layouts(P);
+    return ok();
+}
+
+// ---- classical-shadow snapshots
+namespace {
+struct ShadowLayout {
+    WsLayout F;
+    size_t mats_off = 0, part_off = 0, total = 0;
+};
+ShadowLayout shadow_layout(const tcng_circuit* c, int n, int64_t S) {
+    ShadowLayout M;
+    M.F = layout(c, nullptr, n, TCNG_C64, S, TCNG_MODE_FUSED);
+    M.mats_off = align256(M.F.total);
+    M.part_off = M.mats_off + align256(size_t(S) * n * 16 * 2 * sizeof(float));
+    M.total = M.part_off + align256(size_t(S) * shadow_chunks(n) * sizeof(double));
+    return M;
+}
+tcng_status check_shadow_layer(const tcng_circuit* c) {
+    if (!c) return fail(TCNG_E_INVALID, "null layer circuit");
+    if (!c->fused.valid) return fail(TCNG_E_UNSUPPORTED, "shadow snapshots need the fused path (n >= 9)");
+    if (c->n_params != 0 || int(c->gates.size()) != c->n)
+        return fail(TCNG_E_INVALID, "the layer must hold n one-qubit gates and no angles");
+    for (int q = 0; q < c->n; ++q) {
+        const tcng_gate& g = c->gates[q];
+        if (g.kind != K_U1 || g.q0 != q || g.mat != q)
+            return fail(TCNG_E_INVALID, "layer gate q must be U1 on qubit q with matrix q");
+    }
+    return TCNG_OK;
+}
+}  // namespace
+
+tcng_status tcng_shadow_workspace_size(const tcng_circuit* layer, int64_t snapshots, size_t* bytes) {
+    if (!bytes) return fail(TCNG_E_INVALID, "null output");
+    if (tcng_status e = check_shadow_layer(layer)) return e;
+    if (snapshots < 1 || snapshots > 65535) return fail(TCNG_E_INVALID, "snapshots must be 1..65535");
+    *bytes = shadow_layout(layer, layer->n, snapshots).total;
+    return ok();
+}
+
+tcng_status tcng_shadow_snapshots(const tcng_circuit* layer, const void* psi, const tcng_state* work,
+                                  const uint8_t* bases, const double* u, int64_t* outcomes, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    if (tcng_status e = check_state(work, "tcng_shadow_snapshots")) return e;
+    if (work->dtype != TCNG_C64) return fail(TCNG_E_UNSUPPORTED, "shadow snapshots run in complex64");
+    if (tcng_status e = check_shadow_layer(layer)) return e;
+    if (layer->n != work->n_qubits) return fail(TCNG_E_INVALID, "layer and work state differ in qubit count");
+    if (!psi || !bases || !u || !outcomes) return fail(TCNG_E_INVALID, "null state, bases, uniforms or outcomes");
+    const int n = work->n_qubits;
+    const int64_t S = work->batch;
+    const ShadowLayout M = shadow_layout(layer, n, S);
+    if (!ws || ws_bytes < M.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    void* mats = w + M.mats_off;
+    double* part = reinterpret_cast<double*>(w + M.part_off);
+    PROF_TRY(F_INIT, launch_init<float>(work->amps, work->stride, n, S, psi, 0, st));
+    PROF_TRY(F_SHADOW_PICK, launch_shadow_mats(bases, n, S, mats, st));
+    Job J = make_job(layer, nullptr, work, nullptr, nullptr, nullptr, nullptr, M.F);
+    J.fmats = w + M.F.fmats_off;
+    const DevFusedPlan& F = layer->fused;
+    PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, nullptr, 0, mats, n, S,
+                                             const_cast<void*>(J.fmats), false, st));
+    for (size_t ps = 0; ps < F.host.passes.size(); ++ps) {
+        const JobList jl{nullptr, nullptr, 0, int32_t(ps)};
+        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st));
+    }
+    PROF_TRY(F_SHADOW_SUM, launch_shadow_chunks(work->amps, work->stride, n, S, part, st));
+    PROF_TRY(F_SHADOW_PICK, launch_shadow_pick(work->amps, work->stride, n, S, part, u, outcomes, st));
     return ok();
 }
 

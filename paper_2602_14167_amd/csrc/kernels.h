@@ -123,6 +123,14 @@ hipError_t launch_pauli_coo(const uint64_t* gx, const int32_t* gstart, const uin
                             int64_t row_begin, int64_t row_count, int64_t* rows, int64_t* cols, void* vals,
                             hipStream_t st);
 
+// ---- classical-shadow snapshots: per-snapshot rotation tables [S][n][16] (complex64),
+// chunk sums [S][shadow_chunks(n)], inverse-distribution draw per snapshot
+int shadow_chunks(int n);
+hipError_t launch_shadow_mats(const uint8_t* bases, int n, int64_t S, void* mats, hipStream_t st);
+hipError_t launch_shadow_chunks(const void* psi, int64_t stride, int n, int64_t S, double* part, hipStream_t st);
+hipError_t launch_shadow_pick(const void* psi, int64_t stride, int n, int64_t S, const double* part, const double* u,
+                              int64_t* out, hipStream_t st);
+
 // ---- monitored trajectories (complex64): marginal partials of qubit q on the
 // amplitudes consistent with the step's decided outcomes, the Kraus decision,
 // the per-step collapse.  wgs = mipt_wgs(n) workgroups per member.
