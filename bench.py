@@ -88,7 +88,7 @@ MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
 def workload(name):
     import workloads as W
-    if name.startswith("gates") or name in ("mipt20", "coo22", "coo24"):
+    if name.startswith("gates") or name in ("mipt20", "coo22", "coo24", "shadow20"):
         return None
     if name == "hea28":
         w = W.cfg2()
@@ -522,6 +522,80 @@ def run_coo(args, P, torch, n):
     return out
 
 
+def run_shadow(args, P, torch):
+    """Classical-shadow snapshots (n = 20, 256 snapshots, complex64): one step
+    = copy, rotate and sample every snapshot of one state."""
+    import workloads as W
+    n, S = 20, 256
+    w = W.shadow_workload(n, S, seed=20)
+    layer = P.shadow_layer(n)
+    psi = torch.as_tensor(np.asarray(w["psi"], np.complex64)).cuda()
+    bases = torch.as_tensor(w["bases"]).cuda()
+    u = torch.as_tensor(w["u"]).cuda()
+    work = torch.empty((S, 2 ** n), dtype=torch.complex64, device="cuda")
+    need = ctypes.c_size_t()
+    P.check(P.lib().tcng_shadow_workspace_size(layer.handle, S, ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+
+    def one():
+        return P.shadow_snapshots(layer, psi, bases, u, work=work, ws=ws)
+
+    for _ in range(max(args.warmup, 1)):
+        one()
+    torch.cuda.synchronize()
+    prof = not args.no_profile
+    if prof:
+        P.check(P.lib().tcng_profile_begin(16 * (args.steps + 1)))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fam = {}
+    if prof:
+        for i, name in enumerate(FAMILIES):
+            cnt, tot = ctypes.c_int32(), ctypes.c_double()
+            P.check(P.lib().tcng_profile_query(i, ctypes.byref(cnt), ctypes.byref(tot)))
+            if cnt.value:
+                fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
+        P.check(P.lib().tcng_profile_end())
+    amp = 2 ** n * 8 * S
+    passes = P.fused_plan_inspect(n, layer.gates, 0)[3]
+    alg = {"fused_fwd": 2.0 * amp, "init": float(amp), "shadow_sum": float(amp)}   # per launch
+    roofline = None
+    if fam:
+        dom = max((k for k in alg if k in fam), key=lambda k: fam[k]["total_ms"])
+        t = fam[dom]["avg_ms"] * 1e-3
+        gbs = alg[dom] / t / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                    "bytes_per_launch": alg[dom], "avg_launch_ms": round(fam[dom]["avg_ms"], 4)}
+    res = {
+        "metric": "snapshots/s", "value": S / dt, "unit": "snapshots/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 (f32 state, f64 probabilities)", "data": "synthetic",
+        "config": {"workload": "shadow_n20_s256", "n_qubits": n, "snapshots": S, "rotation_passes": passes,
+                   "parallelism": "single GPU"},
+        "paper_reference": {"ms_per_256_snapshots": 290.0, "hardware": "NVIDIA RTX 5090 (context, not the target)"},
+        "roofline": roofline,
+        "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}
+                    for k, v in fam.items()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        k, t = 1, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.shadow(n, w["psi"], w["bases"][:k], w["u"][:k])
+            t = time.perf_counter() - t0
+            if t * 2 > 15.0 or k >= S:
+                break
+            k = min(S, max(k + 1, int(k * 15.0 / max(t, 1e-3) * 0.5)))
+        res["cpu_baseline"] = {"value": k / t, "unit": "snapshots/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} of {S} snapshots at n={n} (complex128, single thread), {t:.1f} s"}
+    return res
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle (single-threaded, complex128) on a bounded sample of the
     workload: forward application of the first K gates at full n, K grown
@@ -582,6 +656,10 @@ def main():
         return
     if args.workload == "mipt20":
         out = run_mipt(args, P, torch)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "shadow20":
+        out = run_shadow(args, P, torch)
         print(json.dumps(out), flush=True)
         return
     if args.workload in ("coo22", "coo24"):
