@@ -9,7 +9,9 @@ library.  Pins that tie it to the mathematics live in tests/test_oracle_pins.py.
 
 It also builds the sparse (COO) matrix of a Pauli sum (Sec. "Lattice and
 Hamiltonian"), draws classical-shadow snapshots (Sec. "Efficient ML Pipeline
-via Classical Shadows"), and runs monitored Haar brick-wall trajectories (Sec. "Universal Quantum
+via Classical Shadows"), takes the loss and gradient of the SU(4) QML circuit
+(Sec. "End-to-End Pure QML for Computer Vision"), and runs monitored Haar
+brick-wall trajectories (Sec. "Universal Quantum
 Dynamics of Haar-Random MIPT"): unitary steps, random Z measurements drawn
 from passed-in uniforms, Born log-probability of the record.
 
@@ -21,6 +23,8 @@ p = 0 / p = 1 closed forms and Born-rule sampling statistics in
 tests/test_oracle_mipt.py; for the COO entries, dense Kronecker-product
 Hamiltonians, Hermiticity and H psi in tests/test_oracle_coo.py; for the
 shadows, eigenstates, GHZ parities, Born frequencies, the unbiased shadow
-estimator and Kronecker-product rotations in tests/test_oracle_shadow.py).
+estimator and Kronecker-product rotations in tests/test_oracle_shadow.py; for
+the QML step, scipy's matrix exponential, finite differences and the
+identity-gate closed form in tests/test_oracle_qml.py).
 """
 from .api import *  # noqa: F401,F403

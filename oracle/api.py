@@ -46,6 +46,8 @@ def lib():
         L.orc_param_shift.argtypes = [i32, P, i32, P, i32, P, i32, P, P, i32, P, P, P]
         L.orc_pauli_coo.argtypes = [i32, P, P, i32, ctypes.c_int64, ctypes.c_int64, P, P, P, P]
         L.orc_shadow.argtypes = [i32, P, i32, P, P, P, P, P]
+        L.orc_su4.argtypes = [P, P, P]
+        L.orc_qml.argtypes = [i32, P, i32, P, P, i32, P, i32, i32, P, P, P]
         L.orc_mipt.argtypes = [i32, P, i32, i32, P, i32, P, P, ctypes.c_double, P, P, P, P, P]
         _lib = L
     return _lib
@@ -166,7 +168,7 @@ def param_shift(n, gates, params, codes, coeffs, mats=None, init=None, want_lie=
 
 
 __all__ = ["build", "lib", "run", "apply_matrix", "gate_matrix", "expect", "apply_hamiltonian", "norm2",
-           "expect_grad", "param_shift", "mipt", "pauli_coo", "shadow"]
+           "expect_grad", "param_shift", "mipt", "pauli_coo", "shadow", "su4", "qml"]
 
 
 def mipt(n, gates, mats, u, p, init=None, force=None):
@@ -226,3 +228,32 @@ def shadow(n, psi, bases, u):
     rc = lib().orc_shadow(n, _p(x), S, _p(b), _p(uu), _p(out), _p(lo), _p(hi))
     assert rc == 0, rc
     return out[:S], lo[:S], hi[:S]
+
+
+def su4(theta):
+    """SU(4) gate exp(-i sum_k theta_k P_k / 2) and its 15 derivatives: (U [4, 4], dU [15, 4, 4])."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(15))
+    U = np.empty((4, 4), np.complex128)
+    dU = np.empty((15, 4, 4), np.complex128)
+    lib().orc_su4(_p(th), _p(U), _p(dU))
+    return U, dU
+
+
+def qml(n, gates, theta, inputs, labels, k, C, want_probs=False):
+    """Softmax cross-entropy loss per sample and the batch-mean gradient
+    d(mean L)/dtheta [G, 15] of the SU(4) QML circuit."""
+    g = _gates(gates)
+    G = g.shape[0]
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(G, 15))
+    x = np.ascontiguousarray(np.asarray(inputs, dtype=np.complex128).reshape(-1, 2 ** n))
+    B = x.shape[0]
+    y = np.ascontiguousarray(np.asarray(labels, dtype=np.int32).reshape(B))
+    loss = np.empty(B)
+    grad = np.empty((G, 15))
+    probs = np.empty((B, 2 ** k)) if want_probs else None
+    rc = lib().orc_qml(n, _p(g), G, _p(th), _p(x), B, _p(y), int(k), int(C), _p(loss), _p(grad), _p(probs))
+    assert rc == 0, rc
+    out = dict(loss=loss, grad=grad)
+    if want_probs:
+        out["probs"] = probs
+    return out

@@ -351,6 +351,70 @@ double energy_with_param(int n, const std::vector<Gate>& gates, std::vector<doub
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// SU(4) gate of the QML ansatz (Sec. "End-to-End Pure QML for Computer
+// Vision", the su4 gate): U(theta) = exp(X), X = -i sum_k theta_k P_k / 2,
+// P_k = sigma_a (x) sigma_b, k = 4a + b - 1 (sigma_a on the gate's first
+// qubit).  The exponential is its Taylor series after scaling X by 2^-s
+// (||X|| <= 1/2), then s squarings; the derivative in direction
+// E_j = -i P_j / 2 follows the differentiated recurrence
+// D_m = (D_{m-1} X + T_{m-1} E) / m beside T_m = T_{m-1} X / m, and the
+// product rule through the squarings.
+// ---------------------------------------------------------------------------
+struct SU4 { Mat4 U; Mat4 dU[15]; };
+
+Mat4 madd(const Mat4& a, const Mat4& b) {
+    Mat4 c;
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) c.m[i][j] = a.m[i][j] + b.m[i][j];
+    return c;
+}
+Mat4 mscale(const Mat4& a, cplx f) {
+    Mat4 c;
+    for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) c.m[i][j] = a.m[i][j] * f;
+    return c;
+}
+
+SU4 su4_gate(const double* th) {
+    Mat4 X = zero4();
+    Mat4 E[15];
+    for (int k = 0; k < 15; ++k) {
+        const int a = (k + 1) >> 2, b = (k + 1) & 3;
+        E[k] = mscale(pauli2(a, b), cplx(0.0, -0.5));
+        X = madd(X, mscale(E[k], th[k]));
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < 4; ++j) r += std::abs(X.m[i][j]);
+        nrm = std::max(nrm, r);
+    }
+    int sq = 0;
+    while (nrm > 0.5) { nrm *= 0.5; ++sq; }
+    const double f = std::ldexp(1.0, -sq);
+    X = mscale(X, f);
+    for (auto& e : E) e = mscale(e, f);
+    Mat4 I = zero4();
+    for (int i = 0; i < 4; ++i) I.m[i][i] = 1.0;
+    SU4 r;
+    Mat4 T = I;
+    r.U = I;
+    Mat4 D[15];
+    for (int k = 0; k < 15; ++k) { D[k] = zero4(); r.dU[k] = zero4(); }
+    for (int m = 1; m <= 24; ++m) {
+        for (int k = 0; k < 15; ++k) {
+            D[k] = mscale(madd(matmul(D[k], X, 4), matmul(T, E[k], 4)), 1.0 / m);
+            r.dU[k] = madd(r.dU[k], D[k]);
+        }
+        T = mscale(matmul(T, X, 4), 1.0 / m);
+        r.U = madd(r.U, T);
+    }
+    for (int t = 0; t < sq; ++t) {
+        for (int k = 0; k < 15; ++k) r.dU[k] = madd(matmul(r.U, r.dU[k], 4), matmul(r.dU[k], r.U, 4));
+        r.U = matmul(r.U, r.U, 4);
+    }
+    return r;
+}
+
 extern "C" {
 
 int orc_version() { return 1; }
@@ -692,6 +756,78 @@ int orc_shadow(int n, const double* psi_in, int S, const uint8_t* bases, const d
         out[s] = int64_t(x);
         if (lo) lo[s] = prev / total;
         if (hi) hi[s] = run / total;
+    }
+    return 0;
+}
+
+// U(theta) and dU/dtheta_j (row-major complex 4 x 4, dU [15][4][4]) of the SU(4) gate
+int orc_su4(const double* theta, double* U, double* dU) {
+    const SU4 g = su4_gate(theta);
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            U[2 * (4 * a + b)] = g.U.m[a][b].real();
+            U[2 * (4 * a + b) + 1] = g.U.m[a][b].imag();
+            for (int k = 0; k < 15; ++k) {
+                dU[2 * (16 * k + 4 * a + b)] = g.dU[k].m[a][b].real();
+                dU[2 * (16 * k + 4 * a + b) + 1] = g.dU[k].m[a][b].imag();
+            }
+        }
+    return 0;
+}
+
+// QML training step (Sec. "End-to-End Pure QML for Computer Vision"): every
+// sample starts from its amplitude-encoded input (given normalised), the
+// gates (all two-qubit, gate g = SU(4) with theta[g][15]) act in order, the
+// readout probabilities are p_o = sum of |psi_x|^2 over the x whose top k
+// index bits equal o (the paper's first k qubits, its qubit 0 being the most
+// significant), the first C of them are the logits, and the loss is the
+// softmax cross entropy with the label: L_b = logsumexp(p_0..p_{C-1}) - p_{y_b}.
+// grad = d(mean_b L_b)/dtheta by the adjoint recursion: lambda = sum_o
+// dL/dp_o Pi_o psi at the end, then per gate (last to first)
+// dL/dtheta_j += 2 Re <lambda_g| dU_g/dtheta_j |psi_{g-1}>.
+int orc_qml(int n, const int32_t* gates, int G, const double* theta, const double* inputs, int B,
+            const int32_t* labels, int k, int C, double* loss, double* grad, double* probs) {
+    if (k < 1 || k > n || C < 1 || C > (1 << k)) return 1;
+    auto g = read_gates(gates, G);
+    for (auto& gi : g)
+        if (arity(gi.kind) != 2) return 2;
+    std::vector<SU4> su(G);
+    for (int i = 0; i < G; ++i) su[i] = su4_gate(theta + 15 * size_t(i));
+    const uint64_t dim = uint64_t(1) << n;
+    const int K = 1 << k;
+    for (int i = 0; i < 15 * G; ++i) grad[i] = 0.0;
+    for (int b = 0; b < B; ++b) {
+        std::vector<cplx> psi = initial_state(n, inputs + 2 * dim * size_t(b));
+        for (int i = 0; i < G; ++i) apply_gate(n, psi, g[i], su[i].U);
+        std::vector<double> p(K, 0.0);
+        for (int o = 0; o < K; ++o) {
+            auto w = [&](uint64_t r) { return cplx(std::norm(psi[(uint64_t(o) << (n - k)) | r]), 0.0); };
+            p[o] = pairwise_sum(w, 0, dim >> k).real();
+        }
+        if (probs) for (int o = 0; o < K; ++o) probs[size_t(b) * K + o] = p[o];
+        double mx = p[0];
+        for (int o = 1; o < C; ++o) mx = std::max(mx, p[o]);
+        double se = 0.0;
+        for (int o = 0; o < C; ++o) se += std::exp(p[o] - mx);
+        const int y = labels[b];
+        if (y < 0 || y >= C) return 3;
+        loss[b] = mx + std::log(se) - p[y];
+        // dL/dp_o of the batch mean
+        std::vector<double> dp(K, 0.0);
+        for (int o = 0; o < C; ++o) dp[o] = (std::exp(p[o] - mx) / se - (o == y ? 1.0 : 0.0)) / B;
+        std::vector<cplx> lam(dim);
+        for (uint64_t x = 0; x < dim; ++x) lam[x] = dp[x >> (n - k)] * psi[x];
+        for (int i = G - 1; i >= 0; --i) {
+            std::vector<cplx> prev = psi;
+            apply_gate(n, prev, g[i], dagger(su[i].U));
+            for (int j = 0; j < 15; ++j) {
+                std::vector<cplx> t = prev;
+                apply_gate(n, t, g[i], su[i].dU[j]);
+                grad[15 * i + j] += 2.0 * inner(lam, t).real();
+            }
+            apply_gate(n, lam, g[i], dagger(su[i].U));
+            psi.swap(prev);
+        }
     }
     return 0;
 }

@@ -131,6 +131,42 @@ def shadow_workload(n: int, snapshots: int, seed: int):
     return dict(n=n, snapshots=snapshots, psi=psi, bases=bases, u=u)
 
 
+def qml_gates(n: int, layers: int):
+    """SU(4) brick-wall QML ansatz (Sec. "End-to-End Pure QML for Computer
+    Vision"): per layer one gate on each even bond (0,1), (2,3), ..., then on
+    each odd bond (1,2), (3,4), ...; gate g has its own 15 angles theta[g]."""
+    g = []
+    for _ in range(layers):
+        for i in list(range(0, n - 1, 2)) + list(range(1, n - 1, 2)):
+            g.append(gate(U2, i, i + 1, mat=len(g)))
+    return as_gate_array(g)
+
+
+QML_TASKS = {   # qubits, layers, samples, batch, input features, readout qubits, classes
+    "mnist": (10, 40, 60000, 15000, 784, 4, 10),
+    "cifar100": (12, 30, 50000, 5000, 3072, 7, 100),
+}
+
+
+def qml_workload(task: str, seed: int, batch=None, layers=None):
+    """Synthetic stand-in for the paper's MNIST / CIFAR-100 QML runs (the
+    datasets are not used): angles theta[G][15] ~ U[0, 2 pi), then per sample
+    `features` values ~ U[0, 1) zero-padded to 2^n and normalised (amplitude
+    encoding), then labels ~ U{0..C-1}; in that order."""
+    n, L, samples, B, feat, k, C = QML_TASKS[task]
+    B = B if batch is None else batch
+    L = L if layers is None else layers
+    rng = np.random.default_rng(seed)
+    gates = qml_gates(n, L)
+    theta = rng.uniform(0.0, PI2, size=(gates.shape[0], 15))
+    x = np.zeros((B, 2 ** n))
+    x[:, :feat] = rng.uniform(0.0, 1.0, size=(B, feat))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    labels = rng.integers(0, C, size=B).astype(np.int32)
+    return dict(task=task, n=n, layers=L, samples=samples, batch=B, k=k, C=C, gates=gates, theta=theta,
+                inputs=x, labels=labels)
+
+
 def brickwork_fsim(n: int, depth: int, rng: np.random.Generator):
     """fSim brick-wall; per gate theta then phi drawn U[0, 2pi) in gate order."""
     bonds = brickwork_bonds(n, depth)
