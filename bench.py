@@ -82,13 +82,13 @@ def measured_traffic(workload_name, kernel):
     return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
             "finish", "init", "fused_fwd", "fused_rev", "fused_grad", "mipt_marg", "mipt_decide", "mipt_collapse",
-            "pauli_coo", "shadow_sum", "shadow_pick"]
+            "pauli_coo", "shadow_sum", "shadow_pick", "qml"]
 MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
 
 def workload(name):
     import workloads as W
-    if name.startswith("gates") or name in ("mipt20", "coo22", "coo24", "shadow20"):
+    if name.startswith("gates") or name in ("mipt20", "coo22", "coo24", "shadow20", "qml_mnist", "qml_cifar100"):
         return None
     if name == "hea28":
         w = W.cfg2()
@@ -596,6 +596,92 @@ def run_shadow(args, P, torch):
     return res
 
 
+def run_qml(args, P, torch, task):
+    """SU(4) brick-wall QML training (MNIST: n = 10, 40 layers, batch 15000;
+    CIFAR-100: n = 12, 30 layers, batch 5000; synthetic amplitude-encoded
+    inputs): one step = loss and gradient of one batch plus a plain gradient
+    step on the angles; an epoch is samples / batch steps."""
+    import workloads as W
+    w = W.qml_workload(task, seed=1)
+    n, B, k, C, samples = w["n"], w["batch"], w["k"], w["C"], w["samples"]
+    G = w["gates"].shape[0]
+    circ = P.Circuit(n, w["gates"], 0, np.tile(np.eye(4, dtype=np.complex128), (G, 1, 1)))
+    theta = torch.as_tensor(w["theta"]).cuda()
+    x = torch.as_tensor(np.asarray(w["inputs"], np.complex64)).cuda()
+    y = torch.as_tensor(w["labels"]).cuda()
+    psi, lam = torch.empty_like(x), torch.empty_like(x)
+    need = ctypes.c_size_t()
+    P.check(P.lib().tcng_qml_workspace_size(circ.handle, B, ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+    lr = 1e-3
+
+    def one():
+        loss, grad = P.qml_step(circ, theta, x, y, k, C, psi=psi, lam=lam, ws=ws)
+        theta.add_(grad, alpha=-lr)
+        return loss
+
+    for _ in range(max(args.warmup, 1)):
+        one()
+    torch.cuda.synchronize()
+    prof = not args.no_profile
+    if prof:
+        P.check(P.lib().tcng_profile_begin(512 * (args.steps + 1)))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    fam = {}
+    if prof:
+        for i, name in enumerate(FAMILIES):
+            cnt, tot = ctypes.c_int32(), ctypes.c_double()
+            P.check(P.lib().tcng_profile_query(i, ctypes.byref(cnt), ctypes.byref(tot)))
+            if cnt.value:
+                fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
+        P.check(P.lib().tcng_profile_end())
+    _, _, _, passes, nblk, _ = P.fused_plan_inspect(n, w["gates"], 0)
+    roofline = None
+    if "fused_rev" in fam:
+        # matrix-core work of the block formulation: 8 * 16 flops per amplitude and block,
+        # three products per block in reverse (psi, lambda, outer product)
+        blk_flops = 8.0 * 16 * (2 ** n) * B * nblk
+        dom = max(("fused_fwd", "fused_rev"), key=lambda f: fam.get(f, {"total_ms": 0})["total_ms"])
+        L = fam[dom]["launches"] / args.steps
+        flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
+        roofline = roofline_entry(dom, flops, algorithmic_bytes(dom, n, 8, B, 0), fam[dom]["avg_ms"], "mfma")
+    epoch_steps = samples / B
+    paper = {"mnist": 1.88, "cifar100": 4.60}[task]
+    res = {
+        "metric": "QML training samples/s", "value": B / dt, "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": max(args.warmup, 1), "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (f32 state and MFMA, f64 gates and reductions)",
+        "data": "synthetic (uniform features, amplitude-encoded; random labels)",
+        "config": {"workload": f"qml_{task}_n{n}_l{w['layers']}_b{B}", "n_qubits": n, "layers": w["layers"],
+                   "gates": G, "params": 15 * G, "batch": B, "readout_qubits": k, "classes": C,
+                   "epoch_samples": samples, "fused_passes": passes, "fused_blocks": nblk,
+                   "update": "theta -= 1e-3 grad (one torch axpy over the angles)", "parallelism": "single GPU"},
+        "epoch_s": dt * epoch_steps,
+        "paper_reference": {"epoch_s": paper, "hardware": "NVIDIA RTX 5090 (context, not the target)"},
+        "roofline": roofline,
+        "kernels": {f: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}
+                    for f, v in fam.items()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        m, t = 1, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.qml(n, w["gates"], w["theta"], w["inputs"][:m], w["labels"][:m], k, C)
+            t = time.perf_counter() - t0
+            if t * 2 > 15.0 or m >= B:
+                break
+            m = min(B, max(m + 1, int(m * 15.0 / max(t, 1e-3) * 0.5)))
+        res["cpu_baseline"] = {"value": m / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                               "sample": f"loss and gradient of {m} of {B} samples (complex128, single thread), "
+                                         f"{t:.1f} s"}
+    return res
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle (single-threaded, complex128) on a bounded sample of the
     workload: forward application of the first K gates at full n, K grown
@@ -660,6 +746,10 @@ def main():
         return
     if args.workload == "shadow20":
         out = run_shadow(args, P, torch)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload in ("qml_mnist", "qml_cifar100"):
+        out = run_qml(args, P, torch, args.workload[4:])
         print(json.dumps(out), flush=True)
         return
     if args.workload in ("coo22", "coo24"):

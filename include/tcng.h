@@ -255,8 +255,9 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
  *   11 fused forward pass  12 fused reverse pass  13 fused block matrices and gradients
  *   14 trajectory marginal pass  15 trajectory decisions  16 trajectory collapse
  *   17 Pauli-sum COO entries  18 shadow chunk sums  19 shadow rotations and draws
+ *   20 QML gate matrices, readout and angle gradients
  * tcng_profile_end stops recording and frees the events. */
-enum { TCNG_PROF_FAMILIES = 20 };
+enum { TCNG_PROF_FAMILIES = 21 };
 tcng_status tcng_profile_begin(int32_t max_launches);
 tcng_status tcng_profile_query(int32_t family, int32_t* launches, double* total_ms);
 tcng_status tcng_profile_end(void);
@@ -305,6 +306,33 @@ tcng_status tcng_graph_destroy(tcng_graph* g);
 tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                                     int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
                                     int32_t* n_blocks, int32_t* bad_layouts);
+
+/* SU(4) brick-wall QML training step (Sec. "End-to-End Pure QML for Computer
+ * Vision"): every sample starts from its amplitude-encoded input, the gates of
+ * c act in order, gate g being the SU(4) gate U(theta[g.mat]) =
+ * exp(-i sum_k theta_k P_k / 2), P_k = sigma_a (x) sigma_b, k = 4a + b - 1,
+ * sigma_a on the gate's first qubit; the readout p_o sums |psi_x|^2 over the
+ * x whose top k index bits equal o (the paper's first k qubits, its qubit 0
+ * being the most significant); the first n_classes of them are the logits of
+ * a softmax cross entropy with the sample's label.
+ *   c        n_params = 0, every gate U2 with its own matrix index (the
+ *            creation matrices only fix the count M = n_mats); n >= 9;
+ *   theta    device float64 [M][15];
+ *   inputs   complex64 states (normalised amplitude encodings), not modified;
+ *   psi, lam complex64 work states of the same shape (overwritten);
+ *   labels   device int32 [batch] in [0, n_classes) (a label outside gives a
+ *            NaN loss and no gradient contribution);
+ *   k        readout qubits, 1..min(8, n); n_classes in 1..2^k;
+ *   loss     device float64 [batch]: per-sample cross entropy (written);
+ *   grad     device float64 [M][15]: d(mean loss)/dtheta (written);
+ *   ws       device workspace of tcng_qml_workspace_size bytes.
+ * Asynchronous on `stream`; TCNG_E_UNSUPPORTED for complex128 or n < 9,
+ * TCNG_E_INVALID for a malformed circuit, mismatched states, bad k or classes
+ * or null arguments, TCNG_E_WORKSPACE if ws is too small. */
+tcng_status tcng_qml_workspace_size(const tcng_circuit* c, int64_t batch, size_t* bytes);
+tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng_state* inputs, const tcng_state* psi,
+                          const tcng_state* lam, const int32_t* labels, int32_t k, int32_t n_classes, double* loss,
+                          double* grad, void* ws, size_t ws_bytes, void* stream);
 
 /* Classical-shadow snapshots (Sec. "Efficient ML Pipeline via Classical
  * Shadows", measurement only): snapshot s measures every qubit q of the state

@@ -22,7 +22,7 @@ from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_M
 
 __all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
            "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
-           "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots"]
+           "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots", "qml_step"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
 
@@ -478,3 +478,30 @@ def shadow_snapshots(layer: Circuit, psi: torch.Tensor, bases: torch.Tensor, u: 
                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                       _stream()))
     return out
+
+
+def qml_step(circ: Circuit, theta: torch.Tensor, inputs: torch.Tensor, labels: torch.Tensor, k: int, n_classes: int,
+             psi=None, lam=None, ws=None):
+    """One SU(4) QML training evaluation: per-sample softmax cross entropy
+    (float64 [batch]) and d(mean loss)/dtheta (float64 [n_mats, 15]).
+    theta float64 [n_mats, 15]; inputs complex64 [batch, 2^n]; labels int32 [batch]."""
+    n, B = circ.n, int(inputs.shape[0])
+    if theta.dtype != torch.float64 or tuple(theta.shape) != (circ.n_mats, 15) or not theta.is_contiguous():
+        raise ValueError("theta must be contiguous float64 [n_mats, 15]")
+    if labels.dtype != torch.int32 or labels.numel() != B or not labels.is_contiguous():
+        raise ValueError("labels must be contiguous int32 [batch]")
+    x = _state(inputs, n)
+    psi = torch.empty_like(inputs) if psi is None else psi
+    lam = torch.empty_like(inputs) if lam is None else lam
+    p, l = _state(psi, n), _state(lam, n)
+    if ws is None:
+        need = ctypes.c_size_t()
+        check(lib().tcng_qml_workspace_size(circ.handle, B, ctypes.byref(need)))
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=inputs.device)
+    loss = torch.empty(B, dtype=torch.float64, device=inputs.device)
+    grad = torch.empty((circ.n_mats, 15), dtype=torch.float64, device=inputs.device)
+    check(lib().tcng_qml_step(circ.handle, ctypes.c_void_p(theta.data_ptr()), ctypes.byref(x), ctypes.byref(p),
+                              ctypes.byref(l), ctypes.c_void_p(labels.data_ptr()), int(k), int(n_classes),
+                              ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return loss, grad

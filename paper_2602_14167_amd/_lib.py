@@ -26,7 +26,7 @@ EXPORTS = [
     "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end", "tcng_circuit_configure",
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
-    "tcng_shadow_workspace_size", "tcng_shadow_snapshots",
+    "tcng_shadow_workspace_size", "tcng_shadow_snapshots", "tcng_qml_workspace_size", "tcng_qml_step",
 ]
 
 
@@ -90,6 +90,8 @@ def lib():
     L.tcng_apply_pauli.argtypes = [PS, P, PS, P, i32, P, sz, P]
     L.tcng_pauli_coo_info.argtypes = [P, ctypes.POINTER(i32)]
     L.tcng_pauli_coo.argtypes = [P, i64, i64, P, P, P, P]
+    L.tcng_qml_workspace_size.argtypes = [P, i64, ctypes.POINTER(sz)]
+    L.tcng_qml_step.argtypes = [P, P, PS, PS, PS, P, i32, i32, P, P, P, sz, P]
     L.tcng_shadow_workspace_size.argtypes = [P, i64, ctypes.POINTER(sz)]
     L.tcng_shadow_snapshots.argtypes = [P, P, PS, P, P, P, P, sz, P]
     L.tcng_mipt_workspace_size.argtypes = [P, i32, i64, ctypes.POINTER(sz)]

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtcng.so")
 SOURCES = ["api.cpp", "plan.cpp", "kern_plain.hip", "kern_tile.hip", "kern_pauli.hip", "kern_fused.hip",
-           "kern_mipt.hip", "kern_shadow.hip"]
+           "kern_mipt.hip", "kern_shadow.hip", "kern_qml.hip"]
 ARCH = os.environ.get("TCNG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

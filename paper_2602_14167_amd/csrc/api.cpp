@@ -50,7 +50,7 @@ constexpr int MAX_QUBITS = 34;
 // ---------------------------------------------------------------------------
 enum Family { F_FWD_TILE, F_REV_TILE, F_PAULI_TILE, F_GATE1, F_GATE2, F_GATEK, F_REV1, F_REV2, F_PAULI_GROUP,
               F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_MIPT_MARG, F_MIPT_DECIDE,
-              F_MIPT_COLLAPSE, F_PAULI_COO, F_SHADOW_SUM, F_SHADOW_PICK, F_COUNT };
+              F_MIPT_COLLAPSE, F_PAULI_COO, F_SHADOW_SUM, F_SHADOW_PICK, F_QML, F_COUNT };
 static_assert(F_COUNT == TCNG_PROF_FAMILIES, "profiler families");
 
 struct Profiler {
@@ -1122,6 +1122,105 @@ tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, in
     if (n_passes) *n_passes = int32_t(P.passes.size());
     if (n_blocks) *n_blocks = P.n_blocks;
     if (bad_layouts) *bad_layouts = check_fused_layouts(P);
+    return ok();
+}
+
+// ---- SU(4) QML training step
+namespace {
+constexpr int QML_WGS = 512;   // reverse workgroups over (member, tile) pairs: two per CU
+struct QmlLayout {
+    WsLayout F;   // job fields of the fused plan (one set of block matrices)
+    int wgs = 0;
+    size_t fmats_off = 0, opart_off = 0, osum_off = 0, slots_off = 0, utab_off = 0, dutab_off = 0, total = 0;
+};
+QmlLayout qml_layout(const tcng_circuit* c, int n, int64_t batch) {
+    QmlLayout M;
+    M.F = layout(c, nullptr, n, TCNG_C64, 1, TCNG_MODE_FUSED);
+    const FusedPlan& P = c->fused.host;
+    const int64_t items = (int64_t(1) << (n - P.m)) * batch;
+    M.wgs = int(std::min<int64_t>(QML_WGS, items));
+    const size_t nb = size_t(std::max(P.n_blocks, 1));
+    M.fmats_off = 0;
+    M.opart_off = align256(nb * 2048 * sizeof(float));
+    M.osum_off = M.opart_off + align256(nb * size_t(M.wgs) * 512 * sizeof(double));
+    M.slots_off = M.osum_off + align256(nb * 512 * sizeof(double));
+    M.utab_off = M.slots_off + align256(size_t(std::max(P.total_slots, 1)) * sizeof(double));
+    M.dutab_off = M.utab_off + align256(size_t(std::max(c->n_mats, 1)) * 16 * 2 * sizeof(float));
+    M.total = M.dutab_off + align256(size_t(std::max(c->n_mats, 1)) * 15 * 32 * sizeof(double));
+    return M;
+}
+tcng_status check_qml(const tcng_circuit* c, int n) {
+    if (!c) return fail(TCNG_E_INVALID, "null circuit");
+    if (c->n != n) return fail(TCNG_E_INVALID, "circuit and states differ in qubit count");
+    if (!c->fused.valid) return fail(TCNG_E_UNSUPPORTED, "the QML step needs the fused path (n >= 9)");
+    if (c->n_params != 0) return fail(TCNG_E_INVALID, "the QML circuit takes its angles per matrix, not as params");
+    std::vector<char> seen(size_t(std::max(c->n_mats, 1)), 0);
+    for (const tcng_gate& g : c->gates) {
+        if (g.kind != K_U2) return fail(TCNG_E_INVALID, "every QML gate must be U2 (an SU(4) gate)");
+        if (seen[g.mat]) return fail(TCNG_E_INVALID, "every QML gate needs its own matrix index");
+        seen[g.mat] = 1;
+    }
+    if (int64_t(c->gates.size()) != c->n_mats) return fail(TCNG_E_INVALID, "every QML matrix index needs its gate");
+    return TCNG_OK;
+}
+}  // namespace
+
+tcng_status tcng_qml_workspace_size(const tcng_circuit* c, int64_t batch, size_t* bytes) {
+    if (!bytes) return fail(TCNG_E_INVALID, "null output");
+    if (!c) return fail(TCNG_E_INVALID, "null circuit");
+    if (tcng_status e = check_qml(c, c->n)) return e;
+    if (batch < 1 || batch > 65535) return fail(TCNG_E_INVALID, "batch must be 1..65535");
+    *bytes = qml_layout(c, c->n, batch).total;
+    return ok();
+}
+
+tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng_state* inputs, const tcng_state* psi,
+                          const tcng_state* lam, const int32_t* labels, int32_t k, int32_t n_classes, double* loss,
+                          double* grad, void* ws, size_t ws_bytes, void* stream) {
+    if (tcng_status e = check_state(inputs, "tcng_qml_step (inputs)")) return e;
+    if (tcng_status e = check_state(psi, "tcng_qml_step (psi)")) return e;
+    if (tcng_status e = check_state(lam, "tcng_qml_step (lambda)")) return e;
+    if (psi->dtype != TCNG_C64) return fail(TCNG_E_UNSUPPORTED, "the QML step runs in complex64");
+    const int n = psi->n_qubits;
+    const int64_t B = psi->batch;
+    for (const tcng_state* x : {inputs, lam})
+        if (x->n_qubits != n || x->dtype != psi->dtype || x->batch != B || x->stride != psi->stride)
+            return fail(TCNG_E_INVALID, "inputs, psi and lambda must match in qubits, dtype, batch and stride");
+    if (tcng_status e = check_qml(c, n)) return e;
+    if (k < 1 || k > 8 || k > n) return fail(TCNG_E_INVALID, "readout qubits k must lie in 1..min(8, n)");
+    if (n_classes < 1 || n_classes > (1 << k)) return fail(TCNG_E_INVALID, "classes must lie in 1..2^k");
+    if (!theta || !labels || !loss || !grad) return fail(TCNG_E_INVALID, "null angles, labels or outputs");
+    const QmlLayout M = qml_layout(c, n, B);
+    if (!ws || ws_bytes < M.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    void* utab = w + M.utab_off;
+    double* dutab = reinterpret_cast<double*>(w + M.dutab_off);
+    const DevFusedPlan& F = c->fused;
+    PROF_TRY(F_QML, launch_su4(theta, c->n_mats, utab, dutab, st));
+    HIP_TRY(hipMemcpy2DAsync(psi->amps, size_t(psi->stride) * 8, inputs->amps, size_t(inputs->stride) * 8,
+                             (size_t(1) << n) * 8, size_t(B), hipMemcpyDeviceToDevice, st));
+    Job J = make_job(c, nullptr, psi, lam->amps, nullptr, nullptr, nullptr, M.F);
+    J.shared = 1;
+    J.fmats = w + M.fmats_off;
+    J.opart = reinterpret_cast<double*>(w + M.opart_off);
+    J.wgs = M.wgs;
+    PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, nullptr, 0, utab, 0, 1,
+                                             const_cast<void*>(J.fmats), true, st));
+    for (size_t ps = 0; ps < F.host.passes.size(); ++ps) {
+        const JobList jl{nullptr, nullptr, 0, int32_t(ps)};
+        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st));
+    }
+    PROF_TRY(F_QML, launch_qml_seed(psi->amps, lam->amps, psi->stride, n, B, k, n_classes, labels, loss, st));
+    for (size_t ps = 0; ps < F.host.passes.size(); ++ps) {
+        const JobList jl{nullptr, nullptr, 0, int32_t(ps)};
+        PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, J, F.host.m, J.wgs, st));
+    }
+    double* osum = reinterpret_cast<double*>(w + M.osum_off);
+    double* slots = reinterpret_cast<double*>(w + M.slots_off);
+    PROF_TRY(F_FUSED_GRAD, launch_fused_grad(F.phases, F.ops, F.host.n_blocks, nullptr, 0, utab, 1, J.opart, J.wgs, osum,
+                                             F.host.total_slots, slots, st));
+    PROF_TRY(F_QML, launch_qml_grad(slots, F.slots.gate_slot, c->gate_mat, dutab, int(c->gates.size()), grad, st));
     return ok();
 }
 

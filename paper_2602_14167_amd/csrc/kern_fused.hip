@@ -251,7 +251,8 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
     const int64_t b = local / J.tiles;
     const uint64_t tile = uint64_t(local - b * J.tiles);
     gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
-    gptr<const float> mats = as_global(static_cast<const float*>(J.fmats)) + size_t(b) * J.n_blocks * 2048;
+    gptr<const float> mats =
+        as_global(static_cast<const float*>(J.fmats)) + size_t(J.shared ? 0 : b) * J.n_blocks * 2048;
     cptr<FPhase> phases = as_const(J.fphases);
     const uint64_t base = tile_base_f(tile, P->tile_mask, J.n);
     float2* const bufs[1] = {lds};
@@ -386,7 +387,9 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
     const int wave = uniform(t >> 6), lane = t & 63, h = lane >> 5;
     const bool active = wave < K.nwv;
     const int wgs = J.wgs;
-    const int64_t b = local / wgs;
+    // shared block matrices: the workgroups loop over (member, tile) pairs and sum
+    // the outer products of all members into member 0's partials
+    const int64_t b = J.shared ? 0 : local / wgs;
     const int wg = int(local - b * wgs);
     gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
     gptr<cx<float>> lam = as_global(static_cast<cx<float>*>(J.costate)) + b * J.stride;
@@ -412,8 +415,11 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
     const TileIO<IT> io = tile_io<IT>(P, t, K.nthr);
     int pending = 0;
     bool first = true;
-    for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
-        const uint64_t base = tile_base_f(uint64_t(tile), P->tile_mask, J.n);
+    const int64_t items = J.shared ? J.tiles * J.batch : J.tiles;
+    for (int64_t item = wg; item < items; item += wgs) {
+        const int64_t mb = J.shared ? item / J.tiles : 0;
+        const uint64_t base =
+            tile_base_f(uint64_t(item - mb * J.tiles), P->tile_mask, J.n) + uint64_t(mb) * uint64_t(J.stride);
         __syncthreads();
         if (active) ftile_load<IT, 2>(bufs, sts, base, io);
         __syncthreads();

@@ -46,6 +46,8 @@ struct Job {
     int32_t n, n_gates, n_passes, n_ppasses;
     int32_t total_slots, wgs, e_rows, e_wgs;
     int32_t n_blocks, prec_stride;
+    int32_t shared, pad2;     // shared: one set of block matrices for every member (fmats and the outer-product
+                              // partials of member 0); the reverse grid is `wgs` workgroups over (member, tile)
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
@@ -116,6 +118,15 @@ template <typename R>
 hipError_t launch_pauli_group(const void* state, void* costate, bool accumulate, int64_t stride, int n, int64_t batch,
                               uint64_t x, const PClassFull* classes, int class_begin, int class_end,
                               const PTermFull* terms, int wgs, double* epart, int row, int n_rows, hipStream_t st);
+
+// ---- SU(4) QML step: gate matrices U = exp(-i sum theta_k P_k / 2) (complex64 table [M][16]) and
+// dU/dtheta_j (float64 complex [M][15][16]); readout, softmax cross entropy and the adjoint seed
+// lambda = diag(dL/dp) psi per member; dL/dtheta from the batch-summed gate cotangents
+hipError_t launch_su4(const double* theta, int M, void* utab, double* dutab, hipStream_t st);
+hipError_t launch_qml_seed(const void* psi, void* lam, int64_t stride, int n, int64_t batch, int k, int C,
+                           const int32_t* labels, double* loss, hipStream_t st);
+hipError_t launch_qml_grad(const double* slots, const int32_t* gate_slot, const int32_t* gate_mat, const double* dutab,
+                           int n_gates, double* grad, hipStream_t st);
 
 // ---- sparse form of a Pauli sum: entry (g, r) = row row_begin + r, col row ^ gx[g],
 // value sum over the group's terms [gstart[g], gstart[g+1]) of tc * (-1)^popcount(col & tz)

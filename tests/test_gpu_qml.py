@@ -1,0 +1,124 @@
+"""SU(4) QML training step: HIP path (through the C ABI) vs the CPU oracle.
+
+The kernels form each gate in float64 and round it to complex64, evolve
+complex64 states on the matrix cores, and reduce probabilities, losses and
+gradients in float64; the oracle works in complex128 throughout.  A gate
+rounded to float32 moves a state by about 1e-7 per gate, so after G gates
+the probabilities carry about G * 1e-7 relative error (G <= 400 here): the
+per-sample losses must agree to LOSS_TOL absolute, the batch-mean gradient to
+GRAD_TOL * (1 + max |g|) per component.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+LOSS_TOL = 1e-4
+GRAD_TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2602_14167_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.lib()
+    return pkg
+
+
+def circuit(P, n, gates):
+    return P.Circuit(n, gates, 0, np.tile(np.eye(4, dtype=np.complex128), (len(gates), 1, 1)))
+
+
+def run_gpu(P, w, idx=None):
+    n = w["n"]
+    x, y = w["inputs"], w["labels"]
+    if idx is not None:
+        x, y = x[idx], y[idx]
+    print(f"qml {w['task']} n={n} layers={w['layers']} batch={len(y)}", flush=True)
+    c = circuit(P, n, w["gates"])
+    xs = torch.as_tensor(np.asarray(x, np.complex64)).cuda()
+    loss, grad = P.qml_step(c, torch.as_tensor(w["theta"]).cuda(), xs, torch.as_tensor(y).cuda(), w["k"], w["C"])
+    torch.cuda.synchronize()
+    return loss.cpu().numpy(), grad.cpu().numpy(), np.asarray(x, np.complex64).astype(np.complex128)
+
+
+def check_oracle(oracle_mod, w, loss, grad, seen, y):
+    ref = oracle_mod.qml(w["n"], w["gates"], w["theta"], seen, y, w["k"], w["C"])
+    np.testing.assert_allclose(loss, ref["loss"], atol=LOSS_TOL)
+    np.testing.assert_allclose(grad, ref["grad"], atol=GRAD_TOL * (1 + np.abs(ref["grad"]).max()))
+    assert np.abs(ref["grad"]).max() > 1e-3   # the comparison is not between two near-zero arrays
+
+
+@pytest.mark.parametrize("task,n,layers,batch", [
+    ("mnist", 9, 3, 5),        # fused tile of 9 bits, one tile per sample
+    ("mnist", 10, 6, 24),      # the MNIST register
+    ("cifar100", 12, 4, 12),   # the CIFAR-100 register, 7 readout qubits, 100 classes
+    ("mnist", 10, 2, 700),     # more (sample, tile) items than reverse workgroups
+    ("cifar100", 14, 2, 150),  # several tiles per sample
+])
+def test_qml_matches_oracle(P, oracle_mod, task, n, layers, batch):
+    w = W.qml_workload(task, seed=300 + n + layers, batch=batch, layers=layers)
+    if n != w["n"]:
+        w = dict(w, n=n, gates=W.qml_gates(n, layers))
+        r = np.random.default_rng(400 + n)
+        w["theta"] = r.uniform(0, 2 * np.pi, size=(w["gates"].shape[0], 15))
+        x = np.zeros((batch, 2 ** n))
+        feat = min(2 ** n, W.QML_TASKS[task][4])
+        x[:, :feat] = r.uniform(size=(batch, feat))
+        w["inputs"] = x / np.linalg.norm(x, axis=1, keepdims=True)
+    loss, grad, seen = run_gpu(P, w)
+    check_oracle(oracle_mod, w, loss, grad, seen, w["labels"])
+
+
+def test_qml_bad_label_gives_nan_and_no_gradient(P, oracle_mod):
+    w = W.qml_workload("mnist", seed=310, batch=6, layers=3)
+    good = np.arange(6) != 2
+    w["labels"] = w["labels"].copy()
+    w["labels"][2] = 10   # outside the 10 classes
+    loss, grad, seen = run_gpu(P, w)
+    assert np.isnan(loss[2]) and np.isfinite(loss[good]).all()
+    ref = oracle_mod.qml(w["n"], w["gates"], w["theta"], seen[good], w["labels"][good], w["k"], w["C"])
+    np.testing.assert_allclose(loss[good], ref["loss"], atol=LOSS_TOL)
+    # the bad sample contributes nothing; the mean is still over all six
+    np.testing.assert_allclose(grad, ref["grad"] * 5 / 6, atol=GRAD_TOL * (1 + np.abs(ref["grad"]).max()))
+
+
+def test_qml_rejects_bad_arguments(P):
+    w = W.qml_workload("mnist", seed=311, batch=2, layers=1)
+    c = circuit(P, w["n"], w["gates"])
+    x = torch.as_tensor(np.asarray(w["inputs"], np.complex64)).cuda()
+    th = torch.as_tensor(w["theta"]).cuda()
+    y = torch.as_tensor(w["labels"]).cuda()
+    with pytest.raises(P.TcngError):
+        P.qml_step(c, th, x, y, 0, 1)        # no readout qubit
+    with pytest.raises(P.TcngError):
+        P.qml_step(c, th, x, y, 4, 17)       # more classes than 2^k
+    shared = np.asarray(w["gates"]).copy()
+    shared[1, 5] = 0                         # two gates on one matrix
+    with pytest.raises(P.TcngError):
+        P.qml_step(P.Circuit(w["n"], shared, 0, np.tile(np.eye(4), (len(shared), 1, 1))), th, x, y, 4, 10)
+
+
+@pytest.mark.parametrize("task", ["mnist", "cifar100"])
+def test_qml_full_size(P, oracle_mod, task):
+    # the benchmarked launch: the paper's register, depth and batch
+    w = W.qml_workload(task, seed=1)
+    loss, grad, _ = run_gpu(P, w)
+    B = w["batch"]
+    assert np.isfinite(loss).all() and np.isfinite(grad).all()
+    # sampled per-sample losses and a sub-batch gradient at full depth against the oracle
+    idx = np.random.default_rng(320).choice(B, size=12, replace=False)
+    seen = np.asarray(w["inputs"][idx], np.complex64).astype(np.complex128)
+    ref = oracle_mod.qml(w["n"], w["gates"], w["theta"], seen, w["labels"][idx], w["k"], w["C"])
+    np.testing.assert_allclose(loss[idx], ref["loss"], atol=LOSS_TOL)
+    lsub, gsub, _ = run_gpu(P, w, idx)
+    np.testing.assert_allclose(lsub, ref["loss"], atol=LOSS_TOL)
+    np.testing.assert_allclose(gsub, ref["grad"], atol=GRAD_TOL * (1 + np.abs(ref["grad"]).max()))
+    # the batch-mean gradient is the size-weighted mean of the two halves' gradients
+    h = B // 2
+    _, g1, _ = run_gpu(P, w, np.arange(h))
+    _, g2, _ = run_gpu(P, w, np.arange(h, B))
+    np.testing.assert_allclose(grad, (h * g1 + (B - h) * g2) / B, atol=1e-9 + 1e-6 * np.abs(grad).max())
