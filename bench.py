@@ -639,7 +639,9 @@ def run_qml(args, P, torch, task):
             if cnt.value:
                 fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
         P.check(P.lib().tcng_profile_end())
-    _, _, _, passes, nblk, _ = P.fused_plan_inspect(n, w["gates"], 0)
+    # below 12 qubits, 2^(12 - n) samples share a 12-bit tile when the batch divides evenly
+    wide = n < 12 and B % (1 << (12 - n)) == 0
+    _, _, _, passes, nblk, _ = P.fused_plan_inspect(12 if wide else n, w["gates"], 0)
     roofline = None
     if "fused_rev" in fam:
         # matrix-core work of the block formulation: 8 * 16 flops per amplitude and block,
@@ -659,6 +661,7 @@ def run_qml(args, P, torch, task):
         "config": {"workload": f"qml_{task}_n{n}_l{w['layers']}_b{B}", "n_qubits": n, "layers": w["layers"],
                    "gates": G, "params": 15 * G, "batch": B, "readout_qubits": k, "classes": C,
                    "epoch_samples": samples, "fused_passes": passes, "fused_blocks": nblk,
+                   "samples_per_tile": (1 << (12 - n)) if wide else 1,
                    "update": "theta -= 1e-3 grad (one torch axpy over the angles)", "parallelism": "single GPU"},
         "epoch_s": dt * epoch_steps,
         "paper_reference": {"epoch_s": paper, "hardware": "NVIDIA RTX 5090 (context, not the target)"},

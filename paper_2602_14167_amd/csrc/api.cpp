@@ -178,6 +178,9 @@ struct tcng_circuit {
     SlotTables plain;
     DevCircuitPlan tiled[2];
     DevFusedPlan fused;              // complex64 matrix-core plan
+    // n < FUSED_M: the same gates planned on FUSED_M qubits, so that 2^(FUSED_M - n)
+    // contiguous batch members fill one tile (the extra index bits select the member)
+    DevFusedPlan fused_wide;
 };
 
 struct tcng_pauli_sum {
@@ -235,9 +238,9 @@ tcng_status make_plan(tcng_circuit* c, int dt, const TileConfig& cfg) {
     return TCNG_OK;
 }
 
-tcng_status make_fused(tcng_circuit* c) {
+tcng_status make_fused(tcng_circuit* c, int nq, DevFusedPlan& out) {
     DevFusedPlan P;
-    std::string why = plan_fused(c->n, c->gates, c->n_params, FUSED_M, FUSED_LO, P.host);
+    std::string why = plan_fused(nq, c->gates, c->n_params, FUSED_M, FUSED_LO, P.host);
     if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "fused planner: " + why);
     if (upload(P.host.passes, &P.passes) != hipSuccess || upload(P.host.phases, &P.phases) != hipSuccess ||
         upload(P.host.rpasses, &P.rpasses) != hipSuccess || upload(P.host.rphases, &P.rphases) != hipSuccess ||
@@ -251,8 +254,8 @@ tcng_status make_fused(tcng_circuit* c) {
         return e;
     }
     P.valid = true;
-    free_fused(c->fused);
-    c->fused = P;
+    free_fused(out);
+    out = P;
     return TCNG_OK;
 }
 
@@ -704,8 +707,11 @@ tcng_status tcng_circuit_create(int32_t n_qubits, const tcng_gate* gates, int32_
         if (!tiled_ok(n_qubits, dt)) continue;
         if (tcng_status e = make_plan(c, dt, tile_config(dt))) return cleanup(e);
     }
-    if (fused_ok(n_qubits, TCNG_C64))
-        if (tcng_status e = make_fused(c)) return cleanup(e);
+    if (fused_ok(n_qubits, TCNG_C64)) {
+        if (tcng_status e = make_fused(c, n_qubits, c->fused)) return cleanup(e);
+        if (n_qubits < FUSED_M)
+            if (tcng_status e = make_fused(c, FUSED_M, c->fused_wide)) return cleanup(e);
+    }
     *out = c;
     return ok();
 }
@@ -724,6 +730,7 @@ tcng_status tcng_circuit_destroy(tcng_circuit* c) {
     (void)hipFree(c->plain.gate_slot);
     for (auto& P : c->tiled) free_plan(P);
     free_fused(c->fused);
+    free_fused(c->fused_wide);
     delete c;
     return ok();
 }
@@ -1128,16 +1135,28 @@ tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, in
 // ---- SU(4) QML training step
 namespace {
 constexpr int QML_WGS = 512;   // reverse workgroups over (member, tile) pairs: two per CU
+// the plan a step runs on: below FUSED_M qubits, 2^(FUSED_M - n) contiguous members
+// share one tile of the wide plan whenever the batch divides evenly
+struct QmlView {
+    const DevFusedPlan* F;
+    int n;                     // index bits of a plan member
+    int64_t batch, stride;     // plan members and their spacing (amplitudes)
+};
+QmlView qml_view(const tcng_circuit* c, int64_t batch, int64_t stride) {
+    if (c->fused_wide.valid && stride == (int64_t(1) << c->n)) {
+        const int64_t g = int64_t(1) << (FUSED_M - c->n);
+        if (batch % g == 0) return {&c->fused_wide, FUSED_M, batch / g, int64_t(1) << FUSED_M};
+    }
+    return {&c->fused, c->n, batch, stride};
+}
 struct QmlLayout {
-    WsLayout F;   // job fields of the fused plan (one set of block matrices)
     int wgs = 0;
     size_t fmats_off = 0, opart_off = 0, osum_off = 0, slots_off = 0, utab_off = 0, dutab_off = 0, total = 0;
 };
-QmlLayout qml_layout(const tcng_circuit* c, int n, int64_t batch) {
+QmlLayout qml_layout(const tcng_circuit* c, const QmlView& V) {
     QmlLayout M;
-    M.F = layout(c, nullptr, n, TCNG_C64, 1, TCNG_MODE_FUSED);
-    const FusedPlan& P = c->fused.host;
-    const int64_t items = (int64_t(1) << (n - P.m)) * batch;
+    const FusedPlan& P = V.F->host;
+    const int64_t items = (int64_t(1) << (V.n - P.m)) * V.batch;
     M.wgs = int(std::min<int64_t>(QML_WGS, items));
     const size_t nb = size_t(std::max(P.n_blocks, 1));
     M.fmats_off = 0;
@@ -1170,7 +1189,10 @@ tcng_status tcng_qml_workspace_size(const tcng_circuit* c, int64_t batch, size_t
     if (!c) return fail(TCNG_E_INVALID, "null circuit");
     if (tcng_status e = check_qml(c, c->n)) return e;
     if (batch < 1 || batch > 65535) return fail(TCNG_E_INVALID, "batch must be 1..65535");
-    *bytes = qml_layout(c, c->n, batch).total;
+    // enough for either plan (the step picks one by the states' spacing)
+    const QmlLayout a = qml_layout(c, qml_view(c, batch, int64_t(1) << c->n));
+    const QmlLayout b = qml_layout(c, QmlView{&c->fused, c->n, batch, int64_t(1) << c->n});
+    *bytes = std::max(a.total, b.total);
     return ok();
 }
 
@@ -1187,20 +1209,36 @@ tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng
         if (x->n_qubits != n || x->dtype != psi->dtype || x->batch != B || x->stride != psi->stride)
             return fail(TCNG_E_INVALID, "inputs, psi and lambda must match in qubits, dtype, batch and stride");
     if (tcng_status e = check_qml(c, n)) return e;
+    if (B > 65535) return fail(TCNG_E_INVALID, "batch must be 1..65535");
     if (k < 1 || k > 8 || k > n) return fail(TCNG_E_INVALID, "readout qubits k must lie in 1..min(8, n)");
     if (n_classes < 1 || n_classes > (1 << k)) return fail(TCNG_E_INVALID, "classes must lie in 1..2^k");
     if (!theta || !labels || !loss || !grad) return fail(TCNG_E_INVALID, "null angles, labels or outputs");
-    const QmlLayout M = qml_layout(c, n, B);
+    const QmlView V = qml_view(c, B, psi->stride);
+    const QmlLayout M = qml_layout(c, V);
     if (!ws || ws_bytes < M.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
     void* utab = w + M.utab_off;
     double* dutab = reinterpret_cast<double*>(w + M.dutab_off);
-    const DevFusedPlan& F = c->fused;
+    const DevFusedPlan& F = *V.F;
     PROF_TRY(F_QML, launch_su4(theta, c->n_mats, utab, dutab, st));
     HIP_TRY(hipMemcpy2DAsync(psi->amps, size_t(psi->stride) * 8, inputs->amps, size_t(inputs->stride) * 8,
                              (size_t(1) << n) * 8, size_t(B), hipMemcpyDeviceToDevice, st));
-    Job J = make_job(c, nullptr, psi, lam->amps, nullptr, nullptr, nullptr, M.F);
+    Job J{};
+    J.fpasses = F.passes;
+    J.fphases = F.phases;
+    J.frpasses = F.rpasses;
+    J.frphases = F.rphases;
+    J.n_passes = int32_t(F.host.passes.size());
+    J.n_blocks = F.host.n_blocks;
+    J.n_gates = int32_t(c->gates.size());
+    J.total_slots = F.host.total_slots;
+    J.tiles = int64_t(1) << (V.n - F.host.m);
+    J.state = psi->amps;
+    J.costate = lam->amps;
+    J.stride = V.stride;
+    J.batch = V.batch;
+    J.n = V.n;
     J.shared = 1;
     J.fmats = w + M.fmats_off;
     J.opart = reinterpret_cast<double*>(w + M.opart_off);

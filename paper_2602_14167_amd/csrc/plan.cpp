@@ -304,6 +304,11 @@ int column_bit(int m, uint32_t rmask, int c) {
 
 }  // namespace
 
+// The fused reverse keeps one outer product per block and forms every gradient
+// slot after the sweep, so a fused pass has no per-pass slot limit (the tiled
+// passes reduce their slots inside the pass and keep RED_SLOTS).
+constexpr int FUSED_SLOT_BUDGET = 1 << 30;
+
 std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params, int m_max, int lo_cfg,
                        FusedPlan& out) {
     out = FusedPlan();
@@ -341,13 +346,13 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
         }
         int best = -1, best_count = -1;
         for (size_t c = 0; c < cands.size(); ++c) {
-            int cnt = schedule_into_tile(gates, rem, cands[c], RED_SLOTS, nullptr);
+            int cnt = schedule_into_tile(gates, rem, cands[c], FUSED_SLOT_BUDGET, nullptr);
             if (cnt > best_count) { best_count = cnt; best = int(c); }
         }
         if (best_count <= 0) return "planner made no progress";
         const uint64_t T = cands[best];
         std::vector<char> taken(rem.size(), 0);
-        schedule_into_tile(gates, rem, T, RED_SLOTS, &taken);
+        schedule_into_tile(gates, rem, T, FUSED_SLOT_BUDGET, &taken);
         std::vector<int> sel, rest;
         for (size_t i = 0; i < rem.size(); ++i) (taken[i] ? sel : rest).push_back(rem[i]);
         rem.swap(rest);

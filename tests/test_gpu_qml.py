@@ -52,11 +52,17 @@ def check_oracle(oracle_mod, w, loss, grad, seen, y):
     assert np.abs(ref["grad"]).max() > 1e-3   # the comparison is not between two near-zero arrays
 
 
+# Below 12 qubits a batch divisible by 2^(12 - n) runs 2^(12 - n) samples per
+# 12-bit tile (the "wide" plan); other batches run one sample per tile.
 @pytest.mark.parametrize("task,n,layers,batch", [
-    ("mnist", 9, 3, 5),        # fused tile of 9 bits, one tile per sample
-    ("mnist", 10, 6, 24),      # the MNIST register
+    ("mnist", 9, 3, 5),        # one 9-bit tile per sample
+    ("mnist", 9, 3, 16),       # eight samples per tile
+    ("mnist", 10, 6, 24),      # the MNIST register, four samples per tile
+    ("mnist", 10, 3, 26),      # the MNIST register, one sample per tile
+    ("mnist", 11, 4, 6),       # two samples per tile
     ("cifar100", 12, 4, 12),   # the CIFAR-100 register, 7 readout qubits, 100 classes
-    ("mnist", 10, 2, 700),     # more (sample, tile) items than reverse workgroups
+    ("mnist", 10, 2, 2400),    # more (sample group, tile) items than reverse workgroups
+    ("mnist", 10, 2, 702),     # the same with one sample per tile
     ("cifar100", 14, 2, 150),  # several tiles per sample
 ])
 def test_qml_matches_oracle(P, oracle_mod, task, n, layers, batch):
@@ -71,6 +77,23 @@ def test_qml_matches_oracle(P, oracle_mod, task, n, layers, batch):
         w["inputs"] = x / np.linalg.norm(x, axis=1, keepdims=True)
     loss, grad, seen = run_gpu(P, w)
     check_oracle(oracle_mod, w, loss, grad, seen, w["labels"])
+
+
+def test_qml_padded_rows(P, oracle_mod):
+    # states spaced wider than 2^n (one sample per tile): same results as the oracle
+    w = W.qml_workload("mnist", seed=312, batch=8, layers=3)
+    n, B, pad = w["n"], 8, 64
+    c = circuit(P, n, w["gates"])
+    bufs = [torch.zeros((B, 2 ** n + pad), dtype=torch.complex64, device="cuda") for _ in range(3)]
+    x, psi, lam = (b[:, :2 ** n] for b in bufs)
+    x.copy_(torch.as_tensor(np.asarray(w["inputs"], np.complex64)))
+    print("qml padded rows", flush=True)
+    loss, grad = P.qml_step(c, torch.as_tensor(w["theta"]).cuda(), x, torch.as_tensor(w["labels"]).cuda(), w["k"],
+                            w["C"], psi=psi, lam=lam)
+    torch.cuda.synchronize()
+    seen = np.asarray(w["inputs"], np.complex64).astype(np.complex128)
+    check_oracle(oracle_mod, w, loss.cpu().numpy(), grad.cpu().numpy(), seen, w["labels"])
+    assert not bufs[1][:, 2 ** n:].any() and not bufs[2][:, 2 ** n:].any()   # padding untouched
 
 
 def test_qml_bad_label_gives_nan_and_no_gradient(P, oracle_mod):
