@@ -54,12 +54,16 @@ KERNEL_SOURCES = {
     "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "1a01cf308e684ac9"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "1a01cf308e684ac9"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.782e9, "5654b808a9af9ec0"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "5654b808a9af9ec0"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.688e10, "5654b808a9af9ec0"),
-    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "58cb5da6ee9a435c"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.609e9, "2c1f803b5510b0b9"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "2c1f803b5510b0b9"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.783e9, "2021689077f9072f"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "2021689077f9072f"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e10, "2021689077f9072f"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e8, "2021689077f9072f"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.466e8, "2021689077f9072f"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.745e8, "2021689077f9072f"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.285e8, "2021689077f9072f"),
+    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "a763560a3571bc15"),
 }
 
 
@@ -651,6 +655,7 @@ def run_qml(args, P, torch, task):
         L = fam[dom]["launches"] / args.steps
         flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
         roofline = roofline_entry(dom, flops, algorithmic_bytes(dom, n, 8, B, 0), fam[dom]["avg_ms"], "mfma")
+        roofline["traffic"] = measured_traffic(f"qml_{task}_n{n}_l{w['layers']}_b{B}", dom)
     epoch_steps = samples / B
     paper = {"mnist": 1.88, "cifar100": 4.60}[task]
     res = {
