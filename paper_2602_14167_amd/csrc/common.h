@@ -131,6 +131,10 @@ struct FPhase {
     int32_t wr[MAX_TILE_BITS];     // layout this phase writes
     int32_t block;                 // index of the block (matrix table, outer-product sums)
     int32_t pad;
+    // the layouts resolved at the bits the kernels need (no dependent lookups
+    // on the device): images of column bit k (0 where C[k] < 0) and of block bit t
+    int32_t rdc[9], wrc[9];
+    int32_t rdr[FUSED_K], wrr[FUSED_K];
 };
 
 struct FPass {

@@ -168,9 +168,7 @@ __device__ __forceinline__ FView fview(cptr<FPhase> F, int ct, int lane) {
     uint32_t rl = 0, wl = 0, rw = 0, ww = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int cb = F->C[k];
-        if (cb < 0) continue;
-        const uint32_t ir = uint32_t(F->rd[cb]), iw = uint32_t(F->wr[cb]);
+        const uint32_t ir = uint32_t(F->rdc[k]), iw = uint32_t(F->wrc[k]);   // 0 beyond the tile
         if (k < 5) {
             v.wrC[k] = iw;
             const uint32_t msk = 0u - ((uint32_t(lane) >> k) & 1u);
@@ -186,8 +184,8 @@ __device__ __forceinline__ FView fview(cptr<FPhase> F, int ct, int lane) {
     v.wr_tile = ww;
 #pragma unroll
     for (int t = 0; t < FUSED_K; ++t) {
-        v.rdR[t] = uint32_t(F->rd[F->R[t]]);
-        v.wrR[t] = uint32_t(F->wr[F->R[t]]);
+        v.rdR[t] = uint32_t(F->rdr[t]);
+        v.wrR[t] = uint32_t(F->wrr[t]);
     }
     return v;
 }

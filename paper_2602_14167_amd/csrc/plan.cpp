@@ -480,6 +480,19 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
         out.rpasses.push_back(Q);
     }
 
+    // ---- layouts resolved at the column and block bits of every phase
+    for (std::vector<FPhase>* v : {&out.phases, &out.rphases})
+        for (FPhase& F : *v) {
+            for (int k = 0; k < 9; ++k) {
+                F.rdc[k] = F.C[k] >= 0 ? F.rd[F.C[k]] : 0;
+                F.wrc[k] = F.C[k] >= 0 ? F.wr[F.C[k]] : 0;
+            }
+            for (int t = 0; t < FUSED_K; ++t) {
+                F.rdr[t] = F.rd[F.R[t]];
+                F.wrr[t] = F.wr[F.R[t]];
+            }
+        }
+
     // ---- gradient assembly tables
     std::vector<std::vector<int32_t>> per_param(std::max(n_params, 0));
     for (const FPass& P : out.passes)
