@@ -265,14 +265,17 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
             ftile_load<IT, 1>(bufs, sts, base, io);
         }
     }
-    __syncthreads();
     const int f_end = P->phase_end;
+    // block matrices one phase ahead: the next phase's loads are in flight
+    // while this phase's matrix products run
+    float wn[16];
+    if (active) read_mat(mats + size_t(phases[P->phase_begin].block) * 2048, lane, wn);
+    __syncthreads();
     for (int f = P->phase_begin; f < f_end; ++f) {
         cptr<FPhase> F = phases + f;
         float x[CT_MAX][16], w[16];
         FView v[CT_MAX];
         if (active) {
-            read_mat(mats + size_t(F->block) * 2048, lane, w);
 #pragma unroll
             for (int k = 0; k < CT_MAX; ++k) {
                 if (k >= K.ctw) break;
@@ -282,6 +285,9 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
         }
         __syncthreads();   // the phase writes another layout: all reads first
         if (active) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) w[i] = wn[i];
+            if (f + 1 < f_end) read_mat(mats + size_t(phases[f + 1].block) * 2048, lane, wn);
 #pragma unroll
             for (int k = 0; k < CT_MAX; ++k) {
                 if (k >= K.ctw) break;
