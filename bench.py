@@ -54,16 +54,16 @@ KERNEL_SOURCES = {
     "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.609e9, "2c1f803b5510b0b9"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "2c1f803b5510b0b9"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.783e9, "2021689077f9072f"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "2021689077f9072f"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e10, "2021689077f9072f"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e8, "2021689077f9072f"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.466e8, "2021689077f9072f"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.745e8, "2021689077f9072f"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.285e8, "2021689077f9072f"),
-    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "a763560a3571bc15"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.609e9, "1121847db9fa6803"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "1121847db9fa6803"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.787e9, "c000545b73abe2a3"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "c000545b73abe2a3"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e10, "c000545b73abe2a3"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e8, "c000545b73abe2a3"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e8, "c000545b73abe2a3"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.747e8, "c000545b73abe2a3"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e8, "c000545b73abe2a3"),
+    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "c50197d815b2a69a"),
 }
 
 
