@@ -80,6 +80,12 @@ struct ProfScope {
 TileConfig tile_config(int dtype) {
     return dtype == TCNG_C64 ? TileConfig{13, 5, 4, 4} : TileConfig{12, 4, 4, 3};
 }
+// Pauli passes: 12-bit tiles for both precisions (32 KiB of LDS in complex64,
+// so five workgroups share a CU), 16 amplitudes per thread
+TileConfig pauli_config(int dtype) {
+    return dtype == TCNG_C64 ? TileConfig{12, 4, 4, 4} : TileConfig{12, 4, 4, 3};
+}
+constexpr int PAULI_RB = 4;
 // the tiled kernels need at least one full wave per tile
 bool tiled_ok(int n, int dtype) {
     const TileConfig c = tile_config(dtype);
@@ -807,7 +813,7 @@ tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const 
         return cleanup(fail(TCNG_E_ALLOC, "device allocation failed"));
     for (int dt = 0; dt < 2; ++dt) {
         if (!tiled_ok(n_qubits, dt)) continue;
-        std::string why = plan_pauli(n_qubits, h->terms, tile_config(dt), h->tplan[dt]);
+        std::string why = plan_pauli(n_qubits, h->terms, pauli_config(dt), h->tplan[dt]);
         if (!why.empty()) continue;   // the plain path still serves this Hamiltonian
         PauliPlan& P = h->tplan[dt];
         PPass* pp = nullptr; PGroup* pg = nullptr; PClass* pc = nullptr; PTerm* pt = nullptr;
@@ -909,8 +915,8 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
     hipStream_t st = static_cast<hipStream_t>(stream);
     double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
     const Job J = make_job(nullptr, h, s, nullptr, nullptr, nullptr, epart, L);
-    tcng_status e = s->dtype == TCNG_C64 ? run_pauli<float, 5>(h, s, nullptr, L, epart, mode, J, st)
-                                         : run_pauli<double, 4>(h, s, nullptr, L, epart, mode, J, st);
+    tcng_status e = s->dtype == TCNG_C64 ? run_pauli<float, PAULI_RB>(h, s, nullptr, L, epart, mode, J, st)
+                                         : run_pauli<double, PAULI_RB>(h, s, nullptr, L, epart, mode, J, st);
     if (e) return e;
     double* red = reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off);
     PROF_TRY(F_FINISH, launch_finish(nullptr, 0, 1, nullptr, nullptr, 0, epart, L.e_rows, L.e_wgs, s->batch, out, nullptr,
@@ -936,8 +942,8 @@ tcng_status tcng_apply_pauli(const tcng_state* psi, const tcng_pauli_sum* h, con
     hipStream_t st = static_cast<hipStream_t>(stream);
     double* epart = reinterpret_cast<double*>(static_cast<char*>(ws) + L.epart_off);
     const Job J = make_job(nullptr, h, psi, out->amps, nullptr, nullptr, epart, L);
-    tcng_status e = psi->dtype == TCNG_C64 ? run_pauli<float, 5>(h, psi, out->amps, L, epart, mode, J, st)
-                                           : run_pauli<double, 4>(h, psi, out->amps, L, epart, mode, J, st);
+    tcng_status e = psi->dtype == TCNG_C64 ? run_pauli<float, PAULI_RB>(h, psi, out->amps, L, epart, mode, J, st)
+                                           : run_pauli<double, PAULI_RB>(h, psi, out->amps, L, epart, mode, J, st);
     if (e) return e;
     if (energy) {
         double* red = reinterpret_cast<double*>(static_cast<char*>(ws) + L.red_off);
@@ -1000,7 +1006,7 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
         J.fmats = w + L.fmats_off;
         J.opart = reinterpret_cast<double*>(w + L.opart_off);
         tcng_status e = run_forward_fused(c, params, psi, J, true, st);
-        if (!e) e = run_pauli<float, 5>(h, psi, lam->amps, L, epart, pmode, J, st);
+        if (!e) e = run_pauli<float, PAULI_RB>(h, psi, lam->amps, L, epart, pmode, J, st);
         if (!e) e = run_reverse_fused(c, params, psi, L, part, reinterpret_cast<double*>(w + L.osum_off), J, st);
         if (e) return e;
         const SlotTables& S = c->fused.slots;
@@ -1017,12 +1023,12 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     if (dt == TCNG_C64) {
         e = ctiled ? build_ops<float>(c, params, psi->batch, dt, opm, st) : TCNG_OK;
         if (!e) e = run_forward<float, 5>(c, params, psi, mode, J, st);
-        if (!e) e = run_pauli<float, 5>(h, psi, lam->amps, L, epart, pmode, J, st);
+        if (!e) e = run_pauli<float, PAULI_RB>(h, psi, lam->amps, L, epart, pmode, J, st);
         if (!e) e = run_reverse<float, 5>(c, params, psi, lam->amps, L, part, mode, J, st);
     } else {
         e = ctiled ? build_ops<double>(c, params, psi->batch, dt, opm, st) : TCNG_OK;
         if (!e) e = run_forward<double, 4>(c, params, psi, mode, J, st);
-        if (!e) e = run_pauli<double, 4>(h, psi, lam->amps, L, epart, pmode, J, st);
+        if (!e) e = run_pauli<double, PAULI_RB>(h, psi, lam->amps, L, epart, pmode, J, st);
         if (!e) e = run_reverse<double, 4>(c, params, psi, lam->amps, L, part, mode, J, st);
     }
     if (e) return e;
@@ -1497,7 +1503,7 @@ MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum*
     return L;
 }
 
-template <typename R, int RB, int RBR, int RBP = (sizeof(R) == 4 ? 5 : 4)>
+template <typename R, int RB, int RBR, int RBP = PAULI_RB>
 tcng_status run_multi(const std::vector<Job>& jobs, const tcng_circuit* const* circs,
                       const tcng_pauli_sum* const* hams, int count, int dt, const MultiLayout& L, char* ws,
                       hipStream_t st) {

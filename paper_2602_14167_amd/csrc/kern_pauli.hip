@@ -22,7 +22,7 @@ constexpr int NTHREADS = 256;
 
 template <typename R>
 struct PTile {
-    static constexpr int ELEMS = (sizeof(R) == 4) ? (1 << 13) : (1 << 12);
+    static constexpr int ELEMS = 1 << 12;   // 12-bit tiles: 32 KiB (complex64) or 64 KiB (complex128)
 };
 
 __device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const int* lq) {
@@ -118,7 +118,7 @@ k_pauli_tile(const JobList jl, const Job single) {
         if (!active) continue;
         // elements l = it*nt + t, CH at a time; the term loop is outside the
         // element loop so every scalar load of a term serves CH elements
-        constexpr int CH = (NB < 8) ? NB : 8;
+        constexpr int CH = (NB < 4) ? NB : 4;
         for (int c0 = 0; c0 < NB; c0 += CH) {
             cx<R> acc[CH];
 #pragma unroll
@@ -248,7 +248,7 @@ hipError_t launch_pauli_group(const void* state, void* costate, bool accumulate,
     return hipGetLastError();
 }
 
-template hipError_t launch_pauli_tile<float, 5>(const JobList&, const Job&, int64_t, int, hipStream_t);
+template hipError_t launch_pauli_tile<float, 4>(const JobList&, const Job&, int64_t, int, hipStream_t);
 template hipError_t launch_pauli_tile<double, 4>(const JobList&, const Job&, int64_t, int, hipStream_t);
 template hipError_t launch_pauli_group<float>(const void*, void*, bool, int64_t, int, int64_t, uint64_t,
                                               const PClassFull*, int, int, const PTermFull*, int, double*, int, int,
