@@ -318,17 +318,21 @@ tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, in
  *   c        n_params = 0, every gate U2 with its own matrix index (the
  *            creation matrices only fix the count M = n_mats); n >= 9;
  *   theta    device float64 [M][15];
- *   inputs   complex64 states (normalised amplitude encodings), not modified;
- *   psi, lam complex64 work states of the same shape (overwritten);
+ *   inputs   complex64 states (normalised amplitude encodings), not modified
+ *            unless psi is the same memory (then evolved in place);
+ *   psi, lam complex64 work states of the same shape (overwritten); lam must
+ *            not share memory with psi or the inputs;
  *   labels   device int32 [batch] in [0, n_classes) (a label outside gives a
  *            NaN loss and no gradient contribution);
  *   k        readout qubits, 1..min(8, n); n_classes in 1..2^k;
  *   loss     device float64 [batch]: per-sample cross entropy (written);
  *   grad     device float64 [M][15]: d(mean loss)/dtheta (written);
  *   ws       device workspace of tcng_qml_workspace_size bytes.
+ * An angle that is infinite or NaN gives NaN losses and gradients.
  * Asynchronous on `stream`; TCNG_E_UNSUPPORTED for complex128 or n < 9,
- * TCNG_E_INVALID for a malformed circuit, mismatched states, bad k or classes
- * or null arguments, TCNG_E_WORKSPACE if ws is too small. */
+ * TCNG_E_INVALID for a malformed circuit, mismatched or aliased states, bad k
+ * or classes, batch above 65535 or null arguments, TCNG_E_WORKSPACE if ws is
+ * too small. */
 tcng_status tcng_qml_workspace_size(const tcng_circuit* c, int64_t batch, size_t* bytes);
 tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng_state* inputs, const tcng_state* psi,
                           const tcng_state* lam, const int32_t* labels, int32_t k, int32_t n_classes, double* loss,

@@ -1219,6 +1219,8 @@ tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng
     if (k < 1 || k > 8 || k > n) return fail(TCNG_E_INVALID, "readout qubits k must lie in 1..min(8, n)");
     if (n_classes < 1 || n_classes > (1 << k)) return fail(TCNG_E_INVALID, "classes must lie in 1..2^k");
     if (!theta || !labels || !loss || !grad) return fail(TCNG_E_INVALID, "null angles, labels or outputs");
+    if (lam->amps == psi->amps || lam->amps == inputs->amps)
+        return fail(TCNG_E_INVALID, "lambda must not share memory with psi or the inputs");
     const QmlView V = qml_view(c, B, psi->stride);
     const QmlLayout M = qml_layout(c, V);
     if (!ws || ws_bytes < M.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total));
@@ -1228,8 +1230,9 @@ tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng
     double* dutab = reinterpret_cast<double*>(w + M.dutab_off);
     const DevFusedPlan& F = *V.F;
     PROF_TRY(F_QML, launch_su4(theta, c->n_mats, utab, dutab, st));
-    HIP_TRY(hipMemcpy2DAsync(psi->amps, size_t(psi->stride) * 8, inputs->amps, size_t(inputs->stride) * 8,
-                             (size_t(1) << n) * 8, size_t(B), hipMemcpyDeviceToDevice, st));
+    if (inputs->amps != psi->amps)   // psi may be the inputs themselves (evolved in place)
+        HIP_TRY(hipMemcpy2DAsync(psi->amps, size_t(psi->stride) * 8, inputs->amps, size_t(inputs->stride) * 8,
+                                 (size_t(1) << n) * 8, size_t(B), hipMemcpyDeviceToDevice, st));
     Job J{};
     J.fpasses = F.passes;
     J.fphases = F.phases;

@@ -40,7 +40,8 @@ __device__ cd pauli2_entry(int a, int b, int r, int c) {
     return cmul(sig(a, r >> 1, c >> 1), sig(b, r & 1, c & 1));
 }
 
-constexpr int TAYLOR = 20;   // terms after scaling to ||X||_inf <= 1/2
+constexpr int TAYLOR = 20;          // terms after scaling to ||X||_inf <= 1/2
+constexpr int MAX_SQUARINGS = 64;   // |theta| up to about 2^63
 
 __global__ void __launch_bounds__(256) k_su4(const double* __restrict__ theta, float2* __restrict__ utab,
                                             double* __restrict__ dutab) {
@@ -73,8 +74,9 @@ __global__ void __launch_bounds__(256) k_su4(const double* __restrict__ theta, f
             for (int k = 0; k < 4; ++k) rs += sqrt(X[4 * i + k].re * X[4 * i + k].re + X[4 * i + k].im * X[4 * i + k].im);
             nrm = rs > nrm ? rs : nrm;
         }
+        // bounded: an infinite or NaN angle gives a NaN gate, never an endless loop
         int s = 0;
-        while (nrm > 0.5) {
+        while (nrm > 0.5 && s < MAX_SQUARINGS) {
             nrm *= 0.5;
             ++s;
         }

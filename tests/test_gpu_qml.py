@@ -109,6 +109,39 @@ def test_qml_bad_label_gives_nan_and_no_gradient(P, oracle_mod):
     np.testing.assert_allclose(grad, ref["grad"] * 5 / 6, atol=GRAD_TOL * (1 + np.abs(ref["grad"]).max()))
 
 
+def test_qml_in_place_and_aliases(P):
+    # psi may be the inputs themselves (evolved in place); lambda may share memory with neither
+    w = W.qml_workload("mnist", seed=313, batch=8, layers=2)
+    c = circuit(P, w["n"], w["gates"])
+    th = torch.as_tensor(w["theta"]).cuda()
+    y = torch.as_tensor(w["labels"]).cuda()
+    x = torch.as_tensor(np.asarray(w["inputs"], np.complex64)).cuda()
+    print("qml in place", flush=True)
+    loss0, grad0 = P.qml_step(c, th, x, y, w["k"], w["C"])
+    x2 = x.clone()
+    loss1, grad1 = P.qml_step(c, th, x2, y, w["k"], w["C"], psi=x2)
+    torch.cuda.synchronize()
+    assert torch.equal(loss0, loss1) and torch.equal(grad0, grad1)
+    with pytest.raises(P.TcngError):
+        P.qml_step(c, th, x, y, w["k"], w["C"], lam=x)
+    psi = torch.empty_like(x)
+    with pytest.raises(P.TcngError):
+        P.qml_step(c, th, x, y, w["k"], w["C"], psi=psi, lam=psi)
+
+
+def test_qml_non_finite_angle_gives_nan(P):
+    # an infinite angle: the gate's scaling loop is bounded, the results are NaN
+    w = W.qml_workload("mnist", seed=314, batch=4, layers=1)
+    c = circuit(P, w["n"], w["gates"])
+    th = w["theta"].copy()
+    th[3, 7] = np.inf
+    x = torch.as_tensor(np.asarray(w["inputs"], np.complex64)).cuda()
+    print("qml infinite angle", flush=True)
+    loss, grad = P.qml_step(c, torch.as_tensor(th).cuda(), x, torch.as_tensor(w["labels"]).cuda(), w["k"], w["C"])
+    torch.cuda.synchronize()
+    assert torch.isnan(loss).all() and torch.isnan(grad).any()
+
+
 def test_qml_rejects_bad_arguments(P):
     w = W.qml_workload("mnist", seed=311, batch=2, layers=1)
     c = circuit(P, w["n"], w["gates"])
