@@ -236,18 +236,27 @@ def run_uneven(args, w, P, torch):
         P.check(P.lib().tcng_profile_end())
     G = sum(len(c["gates"]) for c in cs)
     amp = sum(3.0 * len(c["gates"]) * 2 ** c["n"] for c in cs)
-    # algorithmic bytes and flops of the reverse sweep (dominant) over one step
-    rev_bytes = sum(c2.num_passes() * 4 * 8 * 2 ** c["n"] for c, c2 in zip(cs, circs))
-    rev_flops = sum(sweep_flops(c["gates"], c["n"], 1, with_u2_grad=True)[1] for c in cs)
+    fused = all(c["n"] >= 12 for c in cs)   # complex64 batches of n >= 12 run on the matrix-core passes
     roofline = None
-    if "rev_tile" in fam:
+    if fused and "fused_rev" in fam:
+        # reverse sweep (dominant): psi and lambda read and written per pass; 3 block products per amplitude
+        plans = [P.fused_plan_inspect(c["n"], c["gates"], 0) for c in cs]
+        rev_bytes = sum(pl[3] * 4 * 8 * 2 ** c["n"] for c, pl in zip(cs, plans))
+        rev_flops = sum(3 * 8.0 * 16 * 2 ** c["n"] * pl[4] for c, pl in zip(cs, plans))
+        L = fam["fused_rev"]["launches"] / args.steps
+        roofline = roofline_entry("fused_rev", rev_flops / L, rev_bytes / L, fam["fused_rev"]["avg_ms"], "mfma")
+    elif "rev_tile" in fam:
+        # algorithmic bytes and flops of the reverse sweep (dominant) over one step
+        rev_bytes = sum(c2.num_passes() * 4 * 8 * 2 ** c["n"] for c, c2 in zip(cs, circs))
+        rev_flops = sum(sweep_flops(c["gates"], c["n"], 1, with_u2_grad=True)[1] for c in cs)
         L = fam["rev_tile"]["launches"] / args.steps
         roofline = roofline_entry("rev_tile", rev_flops / L, rev_bytes / L, fam["rev_tile"]["avg_ms"])
     return {
         "metric": "amplitude-updates/s", "value": amp / dt, "unit": "amplitude-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "c64 (f32 state, f64 reductions)", "data": "synthetic",
-        "config": {"workload": w["name"], "circuits": count, "gates": G, "mode": "tiled, uneven batch",
+        "config": {"workload": w["name"], "circuits": count, "gates": G,
+                   "mode": ("fused" if fused else "tiled") + ", uneven batch",
                    "parallelism": "single GPU"},
         "evals_per_s": count / dt, "roofline": roofline,
         "kernels": {k: {"launches_per_step": v["launches"] / args.steps, "avg_ms": round(v["avg_ms"], 4)}

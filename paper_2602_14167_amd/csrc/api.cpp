@@ -1434,9 +1434,24 @@ namespace {
 
 constexpr int MULTI_WGS = 16;   // workgroups per circuit in the reverse and Pauli sweeps
 
+// complex64 batches whose every circuit has a fused plan on FUSED_M-bit tiles
+// (n >= FUSED_M) run on the matrix-core passes; the others on the tiled passes
+bool multi_fused(const tcng_circuit* const* circs, int32_t count, int32_t dtype) {
+    if (dtype != TCNG_C64) return false;
+    for (int i = 0; i < count; ++i)
+        if (!circs[i]->fused.valid || circs[i]->fused.host.m != FUSED_M) return false;
+    return true;
+}
+
 struct MultiLayout {
+    bool fused = false;
     // per circuit offsets (bytes) into the workspace and row offsets
     std::vector<size_t> opm_off;
+    // fused: block matrices, outer-product partials and sums, gradient slots; reverse workgroups
+    std::vector<size_t> fmats_off, opart_off, osum_off, fslot_off;
+    std::vector<int> fwgs;
+    size_t fjobs_off = 0;   // FusedCircJob [count]
+    int max_blocks = 0;
     std::vector<int64_t> slot_row, erow_row;
     size_t part_off = 0, epart_off = 0, ssum_off = 0, esum_off = 0;
     size_t jobs_off[3] = {0, 0, 0}, prefix_off[3] = {0, 0, 0};
@@ -1479,6 +1494,30 @@ MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum*
         L.slot_rows += std::max(circs[i]->tiled[dtype].host.total_slots, 1);
         L.erow_row[i] = L.e_rows;
         L.e_rows += std::max<int64_t>(int64_t(hams[i]->tplan[dtype].passes.size()), 1);
+    }
+    L.fused = multi_fused(circs, count, dtype);
+    if (L.fused) {
+        L.fmats_off.resize(count);
+        L.opart_off.resize(count);
+        L.osum_off.resize(count);
+        L.fslot_off.resize(count);
+        L.fwgs.resize(count);
+        for (int i = 0; i < count; ++i) {
+            const FusedPlan& F = circs[i]->fused.host;
+            const size_t nb = size_t(std::max(F.n_blocks, 1));
+            L.fwgs[i] = int(std::min<int64_t>(int64_t(1) << (circs[i]->n - F.m), MULTI_WGS));
+            L.fmats_off[i] = off;
+            off = align256(off + nb * 2048 * sizeof(float));
+            L.opart_off[i] = off;
+            off = align256(off + nb * size_t(L.fwgs[i]) * 512 * sizeof(double));
+            L.osum_off[i] = off;
+            off = align256(off + nb * 512 * sizeof(double));
+            L.fslot_off[i] = off;
+            off = align256(off + size_t(std::max(F.total_slots, 1)) * sizeof(double));
+            L.max_blocks = std::max(L.max_blocks, F.n_blocks);
+        }
+        L.fjobs_off = off;
+        off = align256(off + size_t(count) * sizeof(FusedCircJob));
     }
     L.part_off = off;
     off = align256(off + size_t(L.slot_rows) * MULTI_WGS * sizeof(double));
@@ -1568,6 +1607,61 @@ tcng_status run_multi(const std::vector<Job>& jobs, const tcng_circuit* const* c
     return TCNG_OK;
 }
 
+// fused sweeps of an uneven batch: the k-th forward / reverse pass of every
+// circuit that has one in one launch (circuits ordered by pass count), the
+// Pauli passes as in the tiled sweeps
+tcng_status run_multi_fused(const std::vector<Job>& jobs, const tcng_pauli_sum* const* hams, int count, int dt,
+                            const MultiLayout& L, char* ws, hipStream_t st) {
+    std::vector<int> ord_c(count), ord_p(count);
+    for (int i = 0; i < count; ++i) ord_c[i] = ord_p[i] = i;
+    std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) { return jobs[x].n_passes > jobs[y].n_passes; });
+    std::stable_sort(ord_p.begin(), ord_p.end(), [&](int x, int y) { return jobs[x].n_ppasses > jobs[y].n_ppasses; });
+    const int* orders[3] = {ord_c.data(), ord_p.data(), ord_c.data()};
+    int pauli_nt = 64, max_steps[3] = {0, 0, 0};
+    std::vector<int64_t> prefix_host[3];
+    for (int k = 0; k < 3; ++k) {
+        std::vector<Job> sorted(count);
+        prefix_host[k].assign(count + 1, 0);
+        for (int i = 0; i < count; ++i) {
+            const Job& J = jobs[orders[k][i]];
+            sorted[i] = J;
+            const int64_t per = (k == 0) ? J.tiles : (k == 1 ? J.e_wgs : J.wgs);
+            prefix_host[k][i + 1] = prefix_host[k][i] + per * J.batch;
+            if (k == 1 && !hams[orders[k][i]]->tplan[dt].passes.empty())
+                pauli_nt = std::max(pauli_nt, 1 << (hams[orders[k][i]]->tplan[dt].passes[0].m - PAULI_RB));
+            max_steps[k] = std::max(max_steps[k], k == 1 ? J.n_ppasses : J.n_passes);
+        }
+        HIP_TRY(hipMemcpyAsync(ws + L.jobs_off[k], sorted.data(), sizeof(Job) * count, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(ws + L.prefix_off[k], prefix_host[k].data(), sizeof(int64_t) * (count + 1),
+                               hipMemcpyHostToDevice, st));
+    }
+    auto active = [&](int sweep, int k) {
+        int c = 0;
+        for (int i = 0; i < count; ++i) {
+            const Job& J = jobs[orders[sweep][i]];
+            if ((sweep == 1 ? J.n_ppasses : J.n_passes) > k) ++c;
+        }
+        return c;
+    };
+    auto list = [&](int sweep, int k) {
+        return JobList{reinterpret_cast<const Job*>(ws + L.jobs_off[sweep]),
+                       reinterpret_cast<const int64_t*>(ws + L.prefix_off[sweep]), active(sweep, k), k};
+    };
+    for (int k = 0; k < max_steps[0]; ++k) {
+        const JobList jl = list(0, k);
+        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, jobs[0], FUSED_M, prefix_host[0][jl.njobs], st));
+    }
+    for (int k = 0; k < max_steps[1]; ++k) {
+        const JobList jl = list(1, k);
+        PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<float, PAULI_RB>(jl, jobs[0], prefix_host[1][jl.njobs], pauli_nt, st)));
+    }
+    for (int k = 0; k < max_steps[2]; ++k) {
+        const JobList jl = list(2, k);
+        PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, jobs[0], FUSED_M, prefix_host[2][jl.njobs], st));
+    }
+    return TCNG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1612,18 +1706,23 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
         const tcng_circuit* c = circs[i];
         const tcng_pauli_sum* h = hams[i];
         WsLayout Li;
-        Li.total_slots = std::max(c->tiled[dt].host.total_slots, 1);
-        Li.rev_wgs = MULTI_WGS;
+        Li.fused = L.fused;
+        Li.total_slots = std::max(L.fused ? c->fused.host.total_slots : c->tiled[dt].host.total_slots, 1);
+        Li.rev_wgs = L.fused ? L.fwgs[i] : MULTI_WGS;
         Li.e_rows = std::max<int>(int(h->tplan[dt].passes.size()), 1);
         Li.e_wgs = MULTI_WGS;
         jobs[i] = make_job(c, h, &psi[i], lam[i].amps, w + L.opm_off[i], part + L.slot_row[i] * MULTI_WGS,
                            epart + L.erow_row[i] * MULTI_WGS, Li);
+        if (L.fused) {
+            jobs[i].fmats = w + L.fmats_off[i];
+            jobs[i].opart = reinterpret_cast<double*>(w + L.opart_off[i]);
+        }
         builds[i] = BuildJob{c->tiled[dt].ops, params ? params[i] : nullptr, c->cm[dt], w + L.opm_off[i],
                              int32_t(c->gates.size()), 0};
         bprefix[i + 1] = bprefix[i] + int64_t(c->gates.size());
-        const SlotTables& S = c->tiled[dt].slots;
+        const SlotTables& S = L.fused ? c->fused.slots : c->tiled[dt].slots;
         FinishJob F{};
-        F.slots = ssum + L.slot_row[i];
+        F.slots = L.fused ? reinterpret_cast<double*>(w + L.fslot_off[i]) : ssum + L.slot_row[i];
         F.erow = esum + L.erow_row[i];
         F.slot_ptr = S.ptr;
         F.slot_idx = S.idx;
@@ -1647,6 +1746,35 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
                            st));
     // every Pauli pass writes its rows; circuits with fewer passes leave rows unwritten: clear
     HIP_TRY(launch_zero(epart, size_t(L.e_rows) * MULTI_WGS, st));
+    if (L.fused) {
+        std::vector<FusedCircJob> fj(count);
+        for (int i = 0; i < count; ++i) {
+            const DevFusedPlan& F = circs[i]->fused;
+            FusedCircJob& J = fj[i];
+            J.phases = F.phases;
+            J.ops = F.ops;
+            J.params = (params && circs[i]->n_params) ? static_cast<const float*>(params[i]) : nullptr;
+            J.cm = static_cast<const cx<float>*>(circs[i]->cm[0]);
+            J.fmats = reinterpret_cast<float*>(w + L.fmats_off[i]);
+            J.opart = reinterpret_cast<const double*>(w + L.opart_off[i]);
+            J.osum = reinterpret_cast<double*>(w + L.osum_off[i]);
+            J.slots = reinterpret_cast<double*>(w + L.fslot_off[i]);
+            J.n_blocks = F.host.n_blocks;
+            J.wgs = L.fwgs[i];
+            J.total_slots = F.host.total_slots;
+            J.pstride = circs[i]->n_params;
+        }
+        const FusedCircJob* djobs = reinterpret_cast<const FusedCircJob*>(w + L.fjobs_off);
+        HIP_TRY(hipMemcpyAsync(w + L.fjobs_off, fj.data(), sizeof(FusedCircJob) * count, hipMemcpyHostToDevice, st));
+        PROF_TRY(F_FUSED_GRAD, launch_fused_multi_mats(djobs, count, L.max_blocks, st));
+        if (tcng_status e = run_multi_fused(jobs, hams, count, dt, L, w, st)) return e;
+        PROF_TRY(F_FUSED_GRAD, launch_fused_multi_grad(djobs, count, L.max_blocks, st));
+        PROF_TRY(F_FINISH, launch_finish_multi(part, 0, MULTI_WGS, epart, L.e_rows, MULTI_WGS, ssum, esum,
+                                               reinterpret_cast<const FinishJob*>(w + L.fin_off),
+                                               reinterpret_cast<const int64_t*>(w + L.fin_prefix_off), count,
+                                               fprefix[count], st));
+        return ok();
+    }
     HIP_TRY(launch_zero(part, size_t(L.slot_rows) * MULTI_WGS, st));
     const TileConfig& cfg = circs[0]->tiled[dt].host.cfg;
     tcng_status e = TCNG_OK;

@@ -573,15 +573,13 @@ __device__ __forceinline__ int gset(const Op& op, int a, int dim, int beta) {
     return (a & ~((1 << op.r0) | (1 << op.r1))) | ((beta >> 1) << op.r0) | ((beta & 1) << op.r1);
 }
 
-// one workgroup of 256 threads per (block, member): thread (row a, column c)
-__global__ void __launch_bounds__(256)
-k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
-             int64_t pstride, const cx<float>* __restrict__ cm, int64_t cmstride, float* __restrict__ out,
-             int want_rev) {
+// one workgroup of 256 threads per (block f, member b): thread (row a, column c)
+__device__ __forceinline__ void fused_mats_body(const FPhase* __restrict__ phases, const Op* __restrict__ ops,
+                                                int n_blocks, const float* __restrict__ params, int64_t pstride,
+                                                const cx<float>* __restrict__ cm, int64_t cmstride,
+                                                float* __restrict__ out, int want_rev, int f, int64_t b) {
     __shared__ c64d M[256];
     __shared__ c64d U[16];
-    const int f = blockIdx.x;
-    const int64_t b = blockIdx.y;
     const int t = threadIdx.x, a = t >> 4, c = t & 15;
     const FPhase F = phases[f];
     const float* prm = params ? params + b * pstride : nullptr;
@@ -624,17 +622,45 @@ k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int 
     }
 }
 
+__global__ void __launch_bounds__(256)
+k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
+             int64_t pstride, const cx<float>* __restrict__ cm, int64_t cmstride, float* __restrict__ out,
+             int want_rev) {
+    fused_mats_body(phases, ops, n_blocks, params, pstride, cm, cmstride, out, want_rev, int(blockIdx.x),
+                    int64_t(blockIdx.y));
+}
+
+// uneven batch: circuit blockIdx.y, its block blockIdx.x (grid x: the most blocks of any circuit)
+__global__ void __launch_bounds__(256) k_fused_mats_multi(const FusedCircJob* __restrict__ jobs) {
+    const FusedCircJob J = jobs[blockIdx.y];
+    if (int(blockIdx.x) >= J.n_blocks) return;   // the whole workgroup leaves together
+    fused_mats_body(J.phases, J.ops, J.n_blocks, J.params, J.pstride, J.cm, 0, J.fmats, 1, int(blockIdx.x), 0);
+}
+
 // ---------------------------------------------------------------------------
 // outer products: fixed-order sum over workgroups
 // ---------------------------------------------------------------------------
-__global__ void k_fused_osum(const double* __restrict__ opart, int64_t rows, int wgs, double* __restrict__ osum) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= rows * OSTRIDE) return;
+__device__ __forceinline__ void fused_osum_one(const double* __restrict__ opart, int wgs, double* __restrict__ osum,
+                                               int64_t i) {
     const int64_t r = i / OSTRIDE, e = i - r * OSTRIDE;
     const double* p = opart + size_t(r) * wgs * OSTRIDE + e;
     double s = 0.0;
     for (int w = 0; w < wgs; ++w) s += p[size_t(w) * OSTRIDE];
     osum[i] = s;
+}
+
+__global__ void k_fused_osum(const double* __restrict__ opart, int64_t rows, int wgs, double* __restrict__ osum) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows * OSTRIDE) return;
+    fused_osum_one(opart, wgs, osum, i);
+}
+
+// uneven batch: circuit blockIdx.y, entries of its n_blocks outer products
+__global__ void k_fused_osum_multi(const FusedCircJob* __restrict__ jobs) {
+    const FusedCircJob J = jobs[blockIdx.y];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(J.n_blocks) * OSTRIDE) return;
+    fused_osum_one(J.opart, J.wgs, J.osum, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,14 +681,12 @@ __device__ __forceinline__ int load_gate(const Op& op, const float* prm, const c
     return dim;
 }
 
-__global__ void __launch_bounds__(64)
-k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
-             int64_t pstride, const cx<float>* __restrict__ cm, const double* __restrict__ osum, int total_slots,
-             double* __restrict__ slots) {
+__device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phases, const Op* __restrict__ ops,
+                                                int n_blocks, const float* __restrict__ params, int64_t pstride,
+                                                const cx<float>* __restrict__ cm, const double* __restrict__ osum,
+                                                int total_slots, double* __restrict__ slots, int f, int64_t b) {
     __shared__ c64d X[256];
     __shared__ c64d U[16];
-    const int f = blockIdx.x;
-    const int64_t b = blockIdx.y;
     const int t = threadIdx.x;
     const FPhase F = phases[f];
     if (F.op_end == F.op_begin) return;
@@ -789,6 +813,22 @@ k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int 
     }
 }
 
+
+__global__ void __launch_bounds__(64)
+k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
+             int64_t pstride, const cx<float>* __restrict__ cm, const double* __restrict__ osum, int total_slots,
+             double* __restrict__ slots) {
+    fused_grad_body(phases, ops, n_blocks, params, pstride, cm, osum, total_slots, slots, int(blockIdx.x),
+                    int64_t(blockIdx.y));
+}
+
+// uneven batch: circuit blockIdx.y, its phase blockIdx.x
+__global__ void __launch_bounds__(64) k_fused_grad_multi(const FusedCircJob* __restrict__ jobs) {
+    const FusedCircJob J = jobs[blockIdx.y];
+    if (int(blockIdx.x) >= J.n_blocks || J.total_slots <= 0) return;
+    fused_grad_body(J.phases, J.ops, J.n_blocks, J.params, J.pstride, J.cm, J.osum, J.total_slots, J.slots,
+                    int(blockIdx.x), 0);
+}
 }  // namespace
 
 hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
@@ -813,6 +853,22 @@ hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t
     if (blocks <= 0) return hipSuccess;
     if (m == 12) hipLaunchKernelGGL((k_fused_rev<8, 12>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
     else hipLaunchKernelGGL((k_fused_rev<4, 11>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_multi_mats(const FusedCircJob* jobs, int count, int max_blocks, hipStream_t st) {
+    if (count == 0 || max_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fused_mats_multi, dim3(unsigned(max_blocks), unsigned(count)), dim3(256), 0, st, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_multi_grad(const FusedCircJob* jobs, int count, int max_blocks, hipStream_t st) {
+    if (count == 0 || max_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fused_osum_multi, dim3(unsigned((int64_t(max_blocks) * OSTRIDE + 255) / 256), unsigned(count)),
+                       dim3(256), 0, st, jobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fused_grad_multi, dim3(unsigned(max_blocks), unsigned(count)), dim3(64), 0, st, jobs);
     return hipGetLastError();
 }
 

@@ -90,6 +90,24 @@ hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t
 hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st);
 // outer products summed over workgroups (osum: batch * n_blocks * 512), then the
 // gate gradient slots slots[b][slot] (total_slots per member)
+// one circuit of an uneven batch on the fused passes (batch 1): its plan, angles, constant
+// matrices and workspace regions
+struct FusedCircJob {
+    const FPhase* phases;
+    const Op* ops;
+    const float* params;      // or null
+    const cx<float>* cm;
+    float* fmats;             // n_blocks * 2048
+    const double* opart;      // n_blocks * wgs * 512
+    double* osum;             // n_blocks * 512
+    double* slots;            // total_slots
+    int32_t n_blocks, wgs, total_slots, pad;
+    int64_t pstride;
+};
+// block matrices of every circuit in one launch (grid: max_blocks x count)
+hipError_t launch_fused_multi_mats(const FusedCircJob* jobs, int count, int max_blocks, hipStream_t st);
+// outer-product sums and gradient slots of every circuit in two launches
+hipError_t launch_fused_multi_grad(const FusedCircJob* jobs, int count, int max_blocks, hipStream_t st);
 hipError_t launch_fused_grad(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
                              const void* cmats, int64_t batch, const double* opart, int wgs, double* osum,
                              int total_slots, double* slots, hipStream_t st);

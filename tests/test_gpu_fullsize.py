@@ -153,3 +153,34 @@ def test_fsim32_shift_rule_and_finite_differences(P, mode):
         assert abs(fd - g[k_th]) <= 1e-4 * S
     del psi, lam
     torch.cuda.empty_cache()
+
+
+def test_uneven_full_size_sampled(P, oracle_mod):
+    # the benchmarked uneven launch: 1024 Haar brick-walls, n in 12..22, depth 2..16 (matrix-core passes)
+    import torch
+    w = W.cfg4()
+    cs = [P.Circuit(c["n"], c["gates"], 0, W.round_mats(c["mats"], "c64")) for c in w["circuits"]]
+    hs = [P.PauliSum(c["n"], c["codes"], c["coeffs"]) for c in w["circuits"]]
+    print("uneven full size", flush=True)
+    E, _, ggs = P.expect_grad_multi(cs, hs, [None] * len(cs), dtype=torch.complex64, want_gate_grad=True)
+    torch.cuda.synchronize()
+    E = E.cpu().numpy()
+    assert np.isfinite(E).all()
+    # the smallest circuits against the oracle, one by one
+    small = sorted(range(len(cs)), key=lambda i: (w["circuits"][i]["n"], w["circuits"][i]["depth"]))[:4]
+    for i in small:
+        c = w["circuits"][i]
+        ref = oracle_mod.expect_grad(c["n"], c["gates"], None, c["codes"], c["coeffs"], W.round_mats(c["mats"], "c64"),
+                                     want_lie=True)
+        S = np.abs(c["coeffs"]).sum()
+        assert abs(E[i] - ref["E"]) <= 1e-5 * S, i
+        assert np.max(np.abs(ggs[i].cpu().numpy() - ref["lie"])) <= 1e-4 * S, i
+    # the largest ones against the single-circuit fused path (same kernels, one circuit per launch)
+    big = sorted(range(len(cs)), key=lambda i: (-w["circuits"][i]["n"], -w["circuits"][i]["depth"]))[:2]
+    for i in big:
+        c = w["circuits"][i]
+        e1, _, gg1 = P.expect_grad(cs[i], None, hs[i], want_gate_grad=True, mode="fused")
+        torch.cuda.synchronize()
+        S = np.abs(c["coeffs"]).sum()
+        assert abs(E[i] - float(e1[0])) <= 1e-6 * S, i
+        np.testing.assert_allclose(ggs[i].cpu().numpy(), gg1[0].cpu().numpy(), atol=1e-6 * S)

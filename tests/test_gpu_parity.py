@@ -321,13 +321,16 @@ def test_autotune_picks_an_available_tiling_and_keeps_results(P, oracle_mod, tmp
     assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= 1e-4 * S
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_uneven_batch_matches_oracle(P, oracle_mod, dtype):
+# complex64 batches whose circuits all have n >= 12 run on the matrix-core
+# passes; a batch with an 11-qubit circuit (or complex128) on the tiled passes
+@pytest.mark.parametrize("dtype,n_lo", [("c64", 11), ("c64", 12), ("c128", 11)])
+def test_uneven_batch_matches_oracle(P, oracle_mod, dtype, n_lo):
     """Different circuits (qubit counts, depths, Hamiltonians; Haar brick-walls
     and parameterised ansatzes) in one uneven-batch evaluation."""
+    print(f"uneven batch {dtype} n_lo={n_lo}", flush=True)
     r = np.random.default_rng(90)
     cs, hs, ps, refs = [], [], [], []
-    c4 = W.cfg4(count=5, n_lo=11, n_hi=15, d_lo=2, d_hi=9, seed=91)
+    c4 = W.cfg4(count=5, n_lo=n_lo, n_hi=15, d_lo=2, d_hi=9, seed=91)
     for cc in c4["circuits"]:
         cs.append(P.Circuit(cc["n"], cc["gates"], 0, W.round_mats(cc["mats"], dtype)))
         hs.append(P.PauliSum(cc["n"], cc["codes"], cc["coeffs"]))
