@@ -1432,7 +1432,9 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int MULTI_WGS = 16;   // workgroups per circuit in the reverse and Pauli sweeps
+constexpr int MULTI_WGS = 16;    // workgroups per circuit in the tiled reverse sweep
+constexpr int MULTI_EWGS = 64;   // workgroups per circuit (at most) in the Pauli sweep
+constexpr int MULTI_FWGS = 64;   // workgroups per circuit (at most) in the fused reverse sweep
 
 // complex64 batches whose every circuit has a fused plan on FUSED_M-bit tiles
 // (n >= FUSED_M) run on the matrix-core passes; the others on the tiled passes
@@ -1505,7 +1507,7 @@ MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum*
         for (int i = 0; i < count; ++i) {
             const FusedPlan& F = circs[i]->fused.host;
             const size_t nb = size_t(std::max(F.n_blocks, 1));
-            L.fwgs[i] = int(std::min<int64_t>(int64_t(1) << (circs[i]->n - F.m), MULTI_WGS));
+            L.fwgs[i] = int(std::min<int64_t>(int64_t(1) << (circs[i]->n - F.m), MULTI_FWGS));
             L.fmats_off[i] = off;
             off = align256(off + nb * 2048 * sizeof(float));
             L.opart_off[i] = off;
@@ -1522,7 +1524,7 @@ MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum*
     L.part_off = off;
     off = align256(off + size_t(L.slot_rows) * MULTI_WGS * sizeof(double));
     L.epart_off = off;
-    off = align256(off + size_t(L.e_rows) * MULTI_WGS * sizeof(double));
+    off = align256(off + size_t(L.e_rows) * MULTI_EWGS * sizeof(double));
     L.ssum_off = off;
     off = align256(off + size_t(L.slot_rows) * sizeof(double));
     L.esum_off = off;
@@ -1710,9 +1712,9 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
         Li.total_slots = std::max(L.fused ? c->fused.host.total_slots : c->tiled[dt].host.total_slots, 1);
         Li.rev_wgs = L.fused ? L.fwgs[i] : MULTI_WGS;
         Li.e_rows = std::max<int>(int(h->tplan[dt].passes.size()), 1);
-        Li.e_wgs = MULTI_WGS;
+        Li.e_wgs = MULTI_EWGS;
         jobs[i] = make_job(c, h, &psi[i], lam[i].amps, w + L.opm_off[i], part + L.slot_row[i] * MULTI_WGS,
-                           epart + L.erow_row[i] * MULTI_WGS, Li);
+                           epart + L.erow_row[i] * MULTI_EWGS, Li);
         if (L.fused) {
             jobs[i].fmats = w + L.fmats_off[i];
             jobs[i].opart = reinterpret_cast<double*>(w + L.opart_off[i]);
@@ -1745,7 +1747,7 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
     HIP_TRY(hipMemcpyAsync(w + L.fin_prefix_off, fprefix.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
                            st));
     // every Pauli pass writes its rows; circuits with fewer passes leave rows unwritten: clear
-    HIP_TRY(launch_zero(epart, size_t(L.e_rows) * MULTI_WGS, st));
+    HIP_TRY(launch_zero(epart, size_t(L.e_rows) * MULTI_EWGS, st));
     if (L.fused) {
         std::vector<FusedCircJob> fj(count);
         for (int i = 0; i < count; ++i) {
@@ -1769,7 +1771,7 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
         PROF_TRY(F_FUSED_GRAD, launch_fused_multi_mats(djobs, count, L.max_blocks, st));
         if (tcng_status e = run_multi_fused(jobs, hams, count, dt, L, w, st)) return e;
         PROF_TRY(F_FUSED_GRAD, launch_fused_multi_grad(djobs, count, L.max_blocks, st));
-        PROF_TRY(F_FINISH, launch_finish_multi(part, 0, MULTI_WGS, epart, L.e_rows, MULTI_WGS, ssum, esum,
+        PROF_TRY(F_FINISH, launch_finish_multi(part, 0, MULTI_WGS, epart, L.e_rows, MULTI_EWGS, ssum, esum,
                                                reinterpret_cast<const FinishJob*>(w + L.fin_off),
                                                reinterpret_cast<const int64_t*>(w + L.fin_prefix_off), count,
                                                fprefix[count], st));
@@ -1796,7 +1798,7 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
         else e = run_multi<double, 3, 4>(jobs, circs, hams, count, dt, L, w, st);
     }
     if (e) return e;
-    PROF_TRY(F_FINISH, launch_finish_multi(part, L.slot_rows, MULTI_WGS, epart, L.e_rows, MULTI_WGS, ssum, esum,
+    PROF_TRY(F_FINISH, launch_finish_multi(part, L.slot_rows, MULTI_WGS, epart, L.e_rows, MULTI_EWGS, ssum, esum,
                                            reinterpret_cast<const FinishJob*>(w + L.fin_off),
                                            reinterpret_cast<const int64_t*>(w + L.fin_prefix_off), count,
                                            fprefix[count], st));
