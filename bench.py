@@ -236,7 +236,7 @@ def run_uneven(args, w, P, torch):
         P.check(P.lib().tcng_profile_end())
     G = sum(len(c["gates"]) for c in cs)
     amp = sum(3.0 * len(c["gates"]) * 2 ** c["n"] for c in cs)
-    fused = all(c["n"] >= 12 for c in cs)   # complex64 batches of n >= 12 run on the matrix-core passes
+    fused = True   # complex64 batches run on the matrix-core passes
     roofline = None
     if fused and "fused_rev" in fam:
         # reverse sweep (dominant): psi and lambda read and written per pass; 3 block products per amplitude

@@ -131,8 +131,8 @@ tcng_status tcng_circuit_num_passes(const tcng_circuit* c, int32_t dtype, int32_
  * number of circuits.  Every circuit must have the tiled path for the dtype
  * (n >= 11 for complex64, >= 10 for complex128) with the same register block
  * sizes, and its Pauli sum a tiled plan; else TCNG_E_UNSUPPORTED.  A complex64
- * batch whose circuits all have n >= 12 runs on the matrix-core (fused)
- * passes, any other on the tiled passes.
+ * batch runs on the matrix-core (fused) passes, a complex128 batch on the
+ * tiled passes.
  *   circs, hams : host arrays [count] of handles
  *   params      : host array [count] of DEVICE pointers to the angles (NULL when
  *                 the circuit has none), float32 / float64 as the dtype

@@ -1436,12 +1436,12 @@ constexpr int MULTI_WGS = 16;    // workgroups per circuit in the tiled reverse 
 constexpr int MULTI_EWGS = 64;   // workgroups per circuit (at most) in the Pauli sweep
 constexpr int MULTI_FWGS = 64;   // workgroups per circuit (at most) in the fused reverse sweep
 
-// complex64 batches whose every circuit has a fused plan on FUSED_M-bit tiles
-// (n >= FUSED_M) run on the matrix-core passes; the others on the tiled passes
+// complex64 batches whose every circuit has a fused plan run on the matrix-core
+// passes; the others (complex128) on the tiled passes
 bool multi_fused(const tcng_circuit* const* circs, int32_t count, int32_t dtype) {
     if (dtype != TCNG_C64) return false;
     for (int i = 0; i < count; ++i)
-        if (!circs[i]->fused.valid || circs[i]->fused.host.m != FUSED_M) return false;
+        if (!circs[i]->fused.valid) return false;
     return true;
 }
 
@@ -1533,7 +1533,7 @@ MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum*
         L.jobs_off[k] = off;
         off = align256(off + size_t(count) * sizeof(Job));
         L.prefix_off[k] = off;
-        off = align256(off + size_t(count + 1) * sizeof(int64_t));
+        off = align256(off + size_t(count + 2) * sizeof(int64_t));   // fused: one prefix per tile-size group
     }
     L.build_off = off;
     off = align256(off + size_t(count) * sizeof(BuildJob));
@@ -1610,57 +1610,76 @@ tcng_status run_multi(const std::vector<Job>& jobs, const tcng_circuit* const* c
 }
 
 // fused sweeps of an uneven batch: the k-th forward / reverse pass of every
-// circuit that has one in one launch (circuits ordered by pass count), the
-// Pauli passes as in the tiled sweeps
+// circuit that has one in one launch per tile-size group (12-bit tiles, and
+// the smaller ones of circuits below 12 qubits), circuits ordered by pass
+// count inside a group; the Pauli passes as in the tiled sweeps
 tcng_status run_multi_fused(const std::vector<Job>& jobs, const tcng_pauli_sum* const* hams, int count, int dt,
                             const MultiLayout& L, char* ws, hipStream_t st) {
+    auto group = [&](int i) { return jobs[i].n < FUSED_M ? 1 : 0; };
     std::vector<int> ord_c(count), ord_p(count);
     for (int i = 0; i < count; ++i) ord_c[i] = ord_p[i] = i;
-    std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) { return jobs[x].n_passes > jobs[y].n_passes; });
+    std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) {
+        return group(x) != group(y) ? group(x) < group(y) : jobs[x].n_passes > jobs[y].n_passes;
+    });
     std::stable_sort(ord_p.begin(), ord_p.end(), [&](int x, int y) { return jobs[x].n_ppasses > jobs[y].n_ppasses; });
+    int g0 = 0;   // jobs of group 0 (12-bit tiles) come first
+    while (g0 < count && group(ord_c[g0]) == 0) ++g0;
     const int* orders[3] = {ord_c.data(), ord_p.data(), ord_c.data()};
     int pauli_nt = 64, max_steps[3] = {0, 0, 0};
+    // prefix entries: group 0 at [0, g0], group 1 at [g0 + 1, count + 1] (each from 0); the Pauli sweep at [0, count]
     std::vector<int64_t> prefix_host[3];
     for (int k = 0; k < 3; ++k) {
         std::vector<Job> sorted(count);
-        prefix_host[k].assign(count + 1, 0);
+        prefix_host[k].assign(count + 2, 0);
         for (int i = 0; i < count; ++i) {
             const Job& J = jobs[orders[k][i]];
             sorted[i] = J;
             const int64_t per = (k == 0) ? J.tiles : (k == 1 ? J.e_wgs : J.wgs);
-            prefix_host[k][i + 1] = prefix_host[k][i] + per * J.batch;
+            const int at = (k != 1 && i >= g0) ? i + 1 : i;   // group 1 entries one further on
+            prefix_host[k][at + 1] = prefix_host[k][at] + per * J.batch;
             if (k == 1 && !hams[orders[k][i]]->tplan[dt].passes.empty())
                 pauli_nt = std::max(pauli_nt, 1 << (hams[orders[k][i]]->tplan[dt].passes[0].m - PAULI_RB));
             max_steps[k] = std::max(max_steps[k], k == 1 ? J.n_ppasses : J.n_passes);
         }
+        if (k != 1 && g0 < count) prefix_host[k][g0 + 1] = 0;   // group 1 starts its own count
         HIP_TRY(hipMemcpyAsync(ws + L.jobs_off[k], sorted.data(), sizeof(Job) * count, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(ws + L.prefix_off[k], prefix_host[k].data(), sizeof(int64_t) * (count + 1),
+        HIP_TRY(hipMemcpyAsync(ws + L.prefix_off[k], prefix_host[k].data(), sizeof(int64_t) * (count + 2),
                                hipMemcpyHostToDevice, st));
     }
-    auto active = [&](int sweep, int k) {
+    // jobs of sorted positions [lo, hi) taking part in step k (a prefix of the range)
+    auto active = [&](int sweep, int k, int lo, int hi) {
         int c = 0;
-        for (int i = 0; i < count; ++i) {
+        for (int i = lo; i < hi; ++i) {
             const Job& J = jobs[orders[sweep][i]];
             if ((sweep == 1 ? J.n_ppasses : J.n_passes) > k) ++c;
         }
         return c;
     };
-    auto list = [&](int sweep, int k) {
-        return JobList{reinterpret_cast<const Job*>(ws + L.jobs_off[sweep]),
-                       reinterpret_cast<const int64_t*>(ws + L.prefix_off[sweep]), active(sweep, k), k};
+    // sweeps 0 and 2: one launch per group with active jobs
+    auto launch_group = [&](int sweep, int k, int grp) -> tcng_status {
+        const int lo = grp == 0 ? 0 : g0, hi = grp == 0 ? g0 : count;
+        const int na = active(sweep, k, lo, hi);
+        if (na == 0) return TCNG_OK;
+        const int poff = grp == 0 ? 0 : g0 + 1;
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[sweep]) + lo,
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[sweep]) + poff, na, k};
+        const int64_t blocks = prefix_host[sweep][poff + na];
+        const int m = grp == 0 ? FUSED_M : FUSED_M - 1;   // selects the kernel's tile-size instantiation
+        if (sweep == 0) PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, jobs[0], m, blocks, st));
+        else PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, jobs[0], m, blocks, st));
+        return TCNG_OK;
     };
-    for (int k = 0; k < max_steps[0]; ++k) {
-        const JobList jl = list(0, k);
-        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, jobs[0], FUSED_M, prefix_host[0][jl.njobs], st));
-    }
+    for (int k = 0; k < max_steps[0]; ++k)
+        for (int grp = 0; grp < 2; ++grp)
+            if (tcng_status e = launch_group(0, k, grp)) return e;
     for (int k = 0; k < max_steps[1]; ++k) {
-        const JobList jl = list(1, k);
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[1]),
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[1]), active(1, k, 0, count), k};
         PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<float, PAULI_RB>(jl, jobs[0], prefix_host[1][jl.njobs], pauli_nt, st)));
     }
-    for (int k = 0; k < max_steps[2]; ++k) {
-        const JobList jl = list(2, k);
-        PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, jobs[0], FUSED_M, prefix_host[2][jl.njobs], st));
-    }
+    for (int k = 0; k < max_steps[2]; ++k)
+        for (int grp = 0; grp < 2; ++grp)
+            if (tcng_status e = launch_group(2, k, grp)) return e;
     return TCNG_OK;
 }
 

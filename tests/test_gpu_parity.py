@@ -321,8 +321,8 @@ def test_autotune_picks_an_available_tiling_and_keeps_results(P, oracle_mod, tmp
     assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= 1e-4 * S
 
 
-# complex64 batches whose circuits all have n >= 12 run on the matrix-core
-# passes; a batch with an 11-qubit circuit (or complex128) on the tiled passes
+# complex64 batches run on the matrix-core passes (one launch per tile size:
+# 12-bit tiles, and 11-bit ones for 11-qubit circuits), complex128 on the tiled passes
 @pytest.mark.parametrize("dtype,n_lo", [("c64", 11), ("c64", 12), ("c128", 11)])
 def test_uneven_batch_matches_oracle(P, oracle_mod, dtype, n_lo):
     """Different circuits (qubit counts, depths, Hamiltonians; Haar brick-walls
@@ -331,6 +331,8 @@ def test_uneven_batch_matches_oracle(P, oracle_mod, dtype, n_lo):
     r = np.random.default_rng(90)
     cs, hs, ps, refs = [], [], [], []
     c4 = W.cfg4(count=5, n_lo=n_lo, n_hi=15, d_lo=2, d_hi=9, seed=91)
+    # two more at the smallest size (at 11 qubits: the group of smaller tiles)
+    c4["circuits"] += W.cfg4(count=2, n_lo=n_lo, n_hi=n_lo, d_lo=2, d_hi=6, seed=92)["circuits"]
     for cc in c4["circuits"]:
         cs.append(P.Circuit(cc["n"], cc["gates"], 0, W.round_mats(cc["mats"], dtype)))
         hs.append(P.PauliSum(cc["n"], cc["codes"], cc["coeffs"]))
