@@ -54,16 +54,17 @@ KERNEL_SOURCES = {
     "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.609e9, "1121847db9fa6803"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "1121847db9fa6803"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.787e9, "c000545b73abe2a3"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "c000545b73abe2a3"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e10, "c000545b73abe2a3"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e8, "c000545b73abe2a3"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e8, "c000545b73abe2a3"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.747e8, "c000545b73abe2a3"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e8, "c000545b73abe2a3"),
-    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "c50197d815b2a69a"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "ebfafdb8d2bb02e3"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "ebfafdb8d2bb02e3"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.788e9, "74da8a840397ebfa"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "74da8a840397ebfa"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e10, "74da8a840397ebfa"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e8, "74da8a840397ebfa"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e8, "74da8a840397ebfa"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.745e8, "74da8a840397ebfa"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e8, "74da8a840397ebfa"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e10, "74da8a840397ebfa"),
+    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "2b3d60a0078ff391"),
 }
 
 
@@ -245,6 +246,7 @@ def run_uneven(args, w, P, torch):
         rev_flops = sum(3 * 8.0 * 16 * 2 ** c["n"] * pl[4] for c, pl in zip(cs, plans))
         L = fam["fused_rev"]["launches"] / args.steps
         roofline = roofline_entry("fused_rev", rev_flops / L, rev_bytes / L, fam["fused_rev"]["avg_ms"], "mfma")
+        roofline["traffic"] = measured_traffic(w["name"], "fused_rev")
     elif "rev_tile" in fam:
         # algorithmic bytes and flops of the reverse sweep (dominant) over one step
         rev_bytes = sum(c2.num_passes() * 4 * 8 * 2 ** c["n"] for c, c2 in zip(cs, circs))
