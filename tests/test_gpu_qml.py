@@ -79,6 +79,28 @@ def test_qml_matches_oracle(P, oracle_mod, task, n, layers, batch):
     check_oracle(oracle_mod, w, loss, grad, seen, w["labels"])
 
 
+@pytest.mark.parametrize("n,k,C,batch", [
+    (9, 8, 256, 4),   # the widest readout: 256 bins of two amplitudes each
+    (10, 1, 1, 3),    # one class: the loss and its gradient vanish
+    (10, 2, 3, 1),    # a single sample
+])
+def test_qml_readout_edge_cases(P, oracle_mod, n, k, C, batch):
+    r = np.random.default_rng(500 + n + k)
+    gates = W.qml_gates(n, 2)
+    w = dict(task="edge", n=n, layers=2, k=k, C=C, gates=gates,
+             theta=r.uniform(0, 2 * np.pi, size=(gates.shape[0], 15)),
+             labels=r.integers(0, C, size=batch).astype(np.int32))
+    x = r.uniform(size=(batch, 2 ** n))
+    w["inputs"] = x / np.linalg.norm(x, axis=1, keepdims=True)
+    loss, grad, seen = run_gpu(P, w)
+    ref = oracle_mod.qml(n, gates, w["theta"], seen, w["labels"], k, C)
+    # 18 gates: about 2e-6 relative error in the probabilities, so tighter bounds than above
+    np.testing.assert_allclose(loss, ref["loss"], atol=1e-5)
+    np.testing.assert_allclose(grad, ref["grad"], atol=1e-5 * (1 + np.abs(ref["grad"]).max()))
+    if C == 1:
+        assert np.all(loss == 0.0) and np.all(grad == 0.0)
+
+
 def test_qml_padded_rows(P, oracle_mod):
     # states spaced wider than 2^n (one sample per tile): same results as the oracle
     w = W.qml_workload("mnist", seed=312, batch=8, layers=3)
