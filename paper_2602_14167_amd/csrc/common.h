@@ -158,6 +158,7 @@ struct PTerm {
 struct PClass {
     int32_t term_begin, term_end;
     double cre, cim;     // common coefficient c * i^{#Y}
+    int32_t zfree, pad;  // every term without Z/Y bits: each contributes +1, no parities to count
 };
 struct PGroup {
     int32_t x_local;     // X/Y bits (all inside the tile), local positions

@@ -139,6 +139,15 @@ k_pauli_tile(const JobList jl, const Job single) {
                 for (int i = 0; i < CH; ++i) { cre[i] = 0.0; cim[i] = 0.0; }
                 for (int c = G.class_begin; c < G.class_end; ++c) {
                     const PClass C = classes[c];
+                    if (C.zfree) {   // uniform: every term adds +1 (no parities)
+                        const double sgn = double(C.term_end - C.term_begin);
+#pragma unroll
+                        for (int i = 0; i < CH; ++i) {
+                            cre[i] = fma(C.cre, sgn, cre[i]);
+                            cim[i] = fma(C.cim, sgn, cim[i]);
+                        }
+                        continue;
+                    }
                     int odd[CH];
 #pragma unroll
                     for (int i = 0; i < CH; ++i) odd[i] = 0;

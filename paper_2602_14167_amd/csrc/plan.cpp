@@ -646,10 +646,12 @@ std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const Til
                 pc.cre = cls.first.first;
                 pc.cim = cls.first.second;
                 pc.term_begin = int(out.terms.size());
+                pc.zfree = 1;
                 for (int t : cls.second) {
                     PTerm pt{};
                     pt.z_local = to_local(terms[t].z);
                     pt.z_out = terms[t].z & ~T;
+                    if (terms[t].z) pc.zfree = 0;
                     out.terms.push_back(pt);
                 }
                 pc.term_end = int(out.terms.size());
