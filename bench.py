@@ -54,17 +54,17 @@ KERNEL_SOURCES = {
     "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.608e9, "ebfafdb8d2bb02e3"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e9, "ebfafdb8d2bb02e3"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.788e9, "74da8a840397ebfa"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e9, "74da8a840397ebfa"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e10, "74da8a840397ebfa"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e8, "74da8a840397ebfa"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e8, "74da8a840397ebfa"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.745e8, "74da8a840397ebfa"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e8, "74da8a840397ebfa"),
-    ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e10, "74da8a840397ebfa"),
-    ("tfim_coo_n24", "pauli_coo"): (1.342e10, "2b3d60a0078ff391"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.608e+09, "47b4bc7bb3640677"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e+09, "47b4bc7bb3640677"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.787e+09, "2e22e61a8a622ab6"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e+09, "2e22e61a8a622ab6"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e+10, "2e22e61a8a622ab6"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e+08, "2e22e61a8a622ab6"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e+08, "2e22e61a8a622ab6"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.746e+08, "2e22e61a8a622ab6"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e+08, "2e22e61a8a622ab6"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e+10, "2e22e61a8a622ab6"),
+    ("tfim_coo_n24", "pauli_coo"): (1.342e+10, "66558959c5dc4da0"),
 }
 
 
