@@ -1230,10 +1230,13 @@ tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng
     double* dutab = reinterpret_cast<double*>(w + M.dutab_off);
     const DevFusedPlan& F = *V.F;
     PROF_TRY(F_QML, launch_su4(theta, c->n_mats, utab, dutab, st));
-    if (inputs->amps != psi->amps)   // psi may be the inputs themselves (evolved in place)
+    // the first forward pass loads the inputs (psi may be the inputs themselves, evolved in place)
+    if (F.host.passes.empty() && inputs->amps != psi->amps)
         HIP_TRY(hipMemcpy2DAsync(psi->amps, size_t(psi->stride) * 8, inputs->amps, size_t(inputs->stride) * 8,
                                  (size_t(1) << n) * 8, size_t(B), hipMemcpyDeviceToDevice, st));
     Job J{};
+    J.src = inputs->amps;
+    J.src_stride = V.stride;   // inputs and psi are spaced alike
     J.fpasses = F.passes;
     J.fphases = F.phases;
     J.frpasses = F.rpasses;
@@ -1323,11 +1326,14 @@ tcng_status tcng_shadow_snapshots(const tcng_circuit* layer, const void* psi, co
     char* w = static_cast<char*>(ws);
     void* mats = w + M.mats_off;
     double* part = reinterpret_cast<double*>(w + M.part_off);
-    PROF_TRY(F_INIT, launch_init<float>(work->amps, work->stride, n, S, psi, 0, st));
+    const DevFusedPlan& F = layer->fused;
+    // the first rotation pass reads the one input state for every snapshot (no copies)
+    if (F.host.passes.empty()) PROF_TRY(F_INIT, launch_init<float>(work->amps, work->stride, n, S, psi, 0, st));
     PROF_TRY(F_SHADOW_PICK, launch_shadow_mats(bases, n, S, mats, st));
     Job J = make_job(layer, nullptr, work, nullptr, nullptr, nullptr, nullptr, M.F);
     J.fmats = w + M.F.fmats_off;
-    const DevFusedPlan& F = layer->fused;
+    J.src = psi;
+    J.src_stride = 0;
     PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, nullptr, 0, mats, n, S,
                                              const_cast<void*>(J.fmats), false, st));
     for (size_t ps = 0; ps < F.host.passes.size(); ++ps) {

@@ -255,14 +255,18 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
     const uint64_t base = tile_base_f(tile, P->tile_mask, J.n);
     float2* const bufs[1] = {lds};
     const gptr<cx<float>> sts[1] = {psi};
+    // the first pass may load from another state (the tiles are stored into psi)
+    const gptr<cx<float>> lsrc[1] = {(J.src && jl.step == 0)
+                                         ? as_global(static_cast<cx<float>*>(const_cast<void*>(J.src))) + b * J.src_stride
+                                         : psi};
     const TileIO<IT> io = tile_io<IT>(P, t, K.nthr);
 
     if (active) {
         if (J.prec && jl.step == 0 && J.prec[b * J.prec_stride] != 0u) {
             const uint32_t md = J.prec[b * J.prec_stride], bd = J.prec[b * J.prec_stride + 1];
-            ftile_load_proj<IT>(lds, psi, base, io, md, bd, float(1.0 / sqrt(J.pkeep[b])));
+            ftile_load_proj<IT>(lds, lsrc[0], base, io, md, bd, float(1.0 / sqrt(J.pkeep[b])));
         } else {
-            ftile_load<IT, 1>(bufs, sts, base, io);
+            ftile_load<IT, 1>(bufs, lsrc, base, io);
         }
     }
     const int f_end = P->phase_end;

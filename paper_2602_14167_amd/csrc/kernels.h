@@ -48,6 +48,8 @@ struct Job {
     int32_t n_blocks, prec_stride;
     int32_t shared, pad2;     // shared: one set of block matrices for every member (fmats and the outer-product
                               // partials of member 0); the reverse grid is `wgs` workgroups over (member, tile)
+    const void* src;          // or null: the first fused forward pass loads member b's tiles from
+    int64_t src_stride;       // src + b * src_stride (0: one state for every member) instead of its own state
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
