@@ -54,17 +54,17 @@ KERNEL_SOURCES = {
     "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.608e+09, "47b4bc7bb3640677"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e+09, "47b4bc7bb3640677"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.787e+09, "2e22e61a8a622ab6"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e+09, "2e22e61a8a622ab6"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e+10, "2e22e61a8a622ab6"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e+08, "2e22e61a8a622ab6"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e+08, "2e22e61a8a622ab6"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.746e+08, "2e22e61a8a622ab6"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e+08, "2e22e61a8a622ab6"),
-    ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e+10, "2e22e61a8a622ab6"),
-    ("tfim_coo_n24", "pauli_coo"): (1.342e+10, "66558959c5dc4da0"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.608e+09, "3562a1ea2ffdc471"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e+09, "3562a1ea2ffdc471"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.787e+09, "1d30ca8be5b147dc"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e+09, "1d30ca8be5b147dc"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e+10, "1d30ca8be5b147dc"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e+08, "1d30ca8be5b147dc"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e+08, "1d30ca8be5b147dc"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.745e+08, "1d30ca8be5b147dc"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e+08, "1d30ca8be5b147dc"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e+10, "1d30ca8be5b147dc"),
+    ("tfim_coo_n24", "pauli_coo"): (1.342e+10, "a892d74871e9a4e5"),
 }
 
 
@@ -576,7 +576,9 @@ def run_shadow(args, P, torch):
         P.check(P.lib().tcng_profile_end())
     amp = 2 ** n * 8 * S
     passes = P.fused_plan_inspect(n, layer.gates, 0)[3]
-    alg = {"fused_fwd": 2.0 * amp, "init": float(amp), "shadow_sum": float(amp)}   # per launch
+    # per launch: every pass writes the S rotated states; the first reads the one input state,
+    # the later ones the S states
+    alg = {"fused_fwd": (amp * (2 * passes - 1) + 2 ** n * 8) / passes, "shadow_sum": float(amp)}
     roofline = None
     if fam:
         dom = max((k for k in alg if k in fam), key=lambda k: fam[k]["total_ms"])
