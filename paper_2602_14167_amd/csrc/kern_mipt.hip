@@ -50,14 +50,18 @@ __global__ void __launch_bounds__(MTHREADS) k_mipt_marg(const float4* __restrict
     const uint32_t bq = 1u << q;
     double s0 = 0.0, s1 = 0.0;
     for (uint64_t i = threadIdx.x; i < per4; i += MTHREADS) {
-        const float4 a = src[i];
         const uint32_t x = uint32_t(2 * (c0 + i));   // n <= 32: the low word holds every qubit
+        const bool k0 = (x & md) == bd, k1 = ((x | 1u) & md) == bd;
+        // amplitudes ruled out by the step's earlier outcomes are not read: after j outcomes
+        // on qubits above the lowest few, whole lines of the state are skipped (2^-j of it read)
+        if (!k0 && !k1) continue;
+        const float4 a = src[i];
         const float w0 = a.x * a.x + a.y * a.y, w1 = a.z * a.z + a.w * a.w;
-        if ((x & md) == bd) {
+        if (k0) {
             if (x & bq) s1 += double(w0);
             else s0 += double(w0);
         }
-        if (((x | 1u) & md) == bd) {
+        if (k1) {
             if ((x | 1u) & bq) s1 += double(w1);
             else s0 += double(w1);
         }
