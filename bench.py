@@ -413,13 +413,15 @@ def run_mipt(args, P, torch):
                 fam[name] = dict(launches=cnt.value, total_ms=tot.value, avg_ms=tot.value / cnt.value)
         P.check(P.lib().tcng_profile_end())
     # algorithmic HBM bytes per step: fused passes read + write every state (the
-    # first pass of a time step also applies the previous step's collapse); a
-    # marginal reads the state of every member measuring that qubit; the final
-    # collapse reads + writes the states of members measuring in the last step
+    # first pass of a time step also applies the previous step's collapse); the
+    # final collapse reads + writes the states of members measuring in the last step
     meas = w["u"] >= 1 - p
     amp = 2 ** n * 8
     fwd_passes = P.fused_plan_inspect(n, w["gates"], 0)[3]
-    alg = {"fused_fwd": S * fwd_passes * B * 2.0 * amp, "mipt_marg": float(meas.sum()) * amp,
+    # a marginal reads the amplitudes consistent with the step's earlier outcomes: 2^-j of the
+    # state for the j-th measured qubit of a step (j from 0)
+    earlier = np.cumsum(meas, axis=2) - meas
+    alg = {"fused_fwd": S * fwd_passes * B * 2.0 * amp, "mipt_marg": float((meas * 0.5 ** earlier).sum()) * amp,
            "mipt_collapse": float(meas[:, -1, :].any(axis=1).sum()) * 2.0 * amp}
     roofline = None
     if fam:
