@@ -158,8 +158,8 @@ def sweep_flops(gates, n, batch, with_u2_grad=False):
 
 def roofline_entry(kernel, flops_per_launch, bytes_per_launch, avg_ms, compute="alu"):
     """Roofline of one kernel family from its average launch: compute-bound
-    (vector ALU, or matrix cores for the fused passes) when its arithmetic
-    intensity exceeds the ridge point, HBM-bound otherwise."""
+    (vector ALU) when its arithmetic intensity exceeds the ridge point,
+    HBM-bound otherwise."""
     t = avg_ms * 1e-3
     ai = flops_per_launch / bytes_per_launch
     peak = MFMA_F32_PEAK_TFLOPS if compute == "mfma" else ALU_PEAK_TFLOPS
@@ -174,6 +174,34 @@ def roofline_entry(kernel, flops_per_launch, bytes_per_launch, avg_ms, compute="
            "avg_launch_ms": round(avg_ms, 4), "intensity_flop_per_byte": round(ai, 2),
            "ridge_flop_per_byte": round(ridge, 2), "other_roof": other}
     return out
+
+
+def fused_roofline(kernel, gate_flops, bytes_per_launch, block_flops, avg_ms):
+    """Roofline of a matrix-core pass against the method's own work.  The
+    gate-by-gate flops of the gates the pass applies (sweep_flops) over its
+    algorithmic bytes give the arithmetic intensity; the roof is
+    min(matrix-core peak, intensity x HBM peak), so a pass below the ridge is
+    HBM-bound and `frac` is its algorithmic bytes per second over 8 TB/s.  The
+    dense 16 x 16 block products do more flops than the gates need; their
+    rate against the matrix-core peak is reported beside as `mfma_util`."""
+    t = avg_ms * 1e-3
+    ai = gate_flops / bytes_per_launch
+    ridge = MFMA_F32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    gbs = bytes_per_launch / t / 1e9
+    tfl = gate_flops / t / 1e12
+    if ai < ridge:
+        main = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        main = {"bound": "mfma", "achieved": round(tfl, 2), "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / MFMA_F32_PEAK_TFLOPS, 4)}
+    return {**main, "traffic": None, "kernel": kernel, "gate_level_flops_per_launch": gate_flops,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_ms, 4),
+            "intensity_flop_per_byte": round(ai, 2), "ridge_flop_per_byte": round(ridge, 2),
+            "roof": round(min(MFMA_F32_PEAK_TFLOPS, ai * HBM_PEAK_GBS / 1e3), 2), "roof_unit": "TFLOP/s",
+            "achieved_gate_TFLOP_s": round(tfl, 2),
+            "block_flops_per_launch": block_flops,
+            "mfma_util": round(block_flops / t / 1e12 / MFMA_F32_PEAK_TFLOPS, 4)}
 
 
 def copy_ceiling(torch, nbytes):
@@ -243,9 +271,11 @@ def run_uneven(args, w, P, torch):
         # reverse sweep (dominant): psi and lambda read and written per pass; 3 block products per amplitude
         plans = [P.fused_plan_inspect(c["n"], c["gates"], 0) for c in cs]
         rev_bytes = sum(pl[3] * 4 * 8 * 2 ** c["n"] for c, pl in zip(cs, plans))
-        rev_flops = sum(3 * 8.0 * 16 * 2 ** c["n"] * pl[4] for c, pl in zip(cs, plans))
+        blk_flops = sum(3 * 8.0 * 16 * 2 ** c["n"] * pl[4] for c, pl in zip(cs, plans))
+        gate_flops = sum(sweep_flops(c["gates"], c["n"], 1, with_u2_grad=True)[1] for c in cs)
         L = fam["fused_rev"]["launches"] / args.steps
-        roofline = roofline_entry("fused_rev", rev_flops / L, rev_bytes / L, fam["fused_rev"]["avg_ms"], "mfma")
+        roofline = fused_roofline("fused_rev", gate_flops / L, rev_bytes / L, blk_flops / L,
+                                  fam["fused_rev"]["avg_ms"])
         roofline["traffic"] = measured_traffic(w["name"], "fused_rev")
     elif "rev_tile" in fam:
         # algorithmic bytes and flops of the reverse sweep (dominant) over one step
@@ -321,10 +351,13 @@ def run_per_circuit(args, w, P, torch):
 def run_gate_sweep(args, P, torch, n):
     """Per-gate HBM bandwidth of the streaming gate kernels (the unfused path)
     for low and high target qubits: RY (dense real 2x2), RZ (diagonal), CNOT
-    (q, q+1) and a Haar 4x4 on (q, q') with q' low or high; complex64."""
+    (q, q+1) and a Haar 4x4 on (q, q') with q' low or high; complex64 or
+    complex128 (--dtype).  Bytes per launch: the state read and written once."""
     import workloads as W
     rng = np.random.default_rng(7)
-    psi = torch.empty((1, 2 ** n), dtype=torch.complex64, device="cuda")
+    c64 = args.dtype == "c64"
+    s = 8 if c64 else 16
+    psi = torch.empty((1, 2 ** n), dtype=torch.complex64 if c64 else torch.complex128, device="cuda")
     P.state_init(psi)
     cases = []
     targets = [0, 1, 2, 3, 4, 6, 8, 12, 16, 20, 24, n - 2]
@@ -335,7 +368,7 @@ def run_gate_sweep(args, P, torch, n):
         mats = W.haar_u4(rng)[None]
         cases.append(("U2low", [W.gate(W.U2, max(q, 1), 0, mat=0)], mats))
         cases.append(("U2high", [W.gate(W.U2, q, n - 1 if q != n - 1 else n - 2, mat=0)], mats))
-    theta = torch.tensor([[0.37]], dtype=torch.float32, device="cuda")
+    theta = torch.tensor([[0.37]], dtype=torch.float32 if c64 else torch.float64, device="cuda")
     res = []
     for name, g, mats in cases:
         circ = P.Circuit(n, g, 1 if name in ("RY", "RZ") else 0, mats)
@@ -353,21 +386,22 @@ def run_gate_sweep(args, P, torch, n):
         P.check(P.lib().tcng_profile_query(fam, ctypes.byref(cnt), ctypes.byref(tot)))
         P.check(P.lib().tcng_profile_end())
         ms = tot.value / max(cnt.value, 1)
-        gbs = 2 * 8 * 2 ** n / (ms * 1e-3) / 1e9
+        gbs = 2 * s * 2 ** n / (ms * 1e-3) / 1e9
         res.append({"gate": name, "q": [int(g[0][1])] + ([int(g[0][2])] if g[0][2] >= 0 else []),
                     "ms": round(ms, 4), "GB_s": round(gbs, 1)})
     gb = sorted(r["GB_s"] for r in res)
     med = gb[len(gb) // 2]
-    ms_med = 2 * 8 * 2 ** n / (med * 1e9) * 1e3
+    ms_med = 2 * s * 2 ** n / (med * 1e9) * 1e3
     return {
         "metric": "amplitude-updates/s", "value": 2 ** n / (ms_med * 1e-3), "unit": "amplitude-updates/s",
         "n_gpus": 1, "steps": 10, "warmup": 2, "ms_per_step": ms_med, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
-        "config": {"workload": f"single_gate_sweep_n{n}", "n_qubits": n, "cases": len(res),
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"single_gate_sweep_n{n}_{args.dtype}", "n_qubits": n, "cases": len(res),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": med, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(med / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "gate1/gate2 (median case)",
-                     "min_GB_s": gb[0], "max_GB_s": gb[-1]},
+                     "min_GB_s": gb[0], "max_GB_s": gb[-1],
+                     "cases_at_or_above_70pct": sum(1 for v in gb if v >= 0.7 * HBM_PEAK_GBS)},
         "gate_sweep": res,
     }
 
@@ -458,7 +492,7 @@ def run_mipt(args, P, torch):
             if t * 2 > 15.0 or k >= S:
                 break
             k = min(S, max(k + 1, int(k * 15.0 / max(t, 1e-3) * 0.5)))
-        out["cpu_baseline"] = {"value": (k / S) / t, "unit": "trajectories/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": (k / S) / t, "unit": "trajectories/s", "cores": 1, "kind": "oracle", **host_info(),
                                "sample": f"first {k} of {S} steps of one trajectory at n={n} (complex128, single "
                                          f"thread), {t:.1f} s, scaled to whole trajectories"}
     return out
@@ -533,7 +567,7 @@ def run_coo(args, P, torch, n):
             if t * 2 > 15.0 or cnt >= dim:
                 break
             cnt = min(dim, max(cnt * 2, int(cnt * 15.0 / max(t, 1e-3) * 0.5)))
-        out["cpu_baseline"] = {"value": G * cnt / t, "unit": "coo-entries/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": G * cnt / t, "unit": "coo-entries/s", "cores": 1, "kind": "oracle", **host_info(),
                                "sample": f"rows [0, {cnt}) of the n={n} TFIM matrix ({G} groups, single thread), "
                                          f"{t:.1f} s"}
     return out
@@ -610,7 +644,7 @@ def run_shadow(args, P, torch):
             if t * 2 > 15.0 or k >= S:
                 break
             k = min(S, max(k + 1, int(k * 15.0 / max(t, 1e-3) * 0.5)))
-        res["cpu_baseline"] = {"value": k / t, "unit": "snapshots/s", "cores": 1, "kind": "oracle",
+        res["cpu_baseline"] = {"value": k / t, "unit": "snapshots/s", "cores": 1, "kind": "oracle", **host_info(),
                                "sample": f"{k} of {S} snapshots at n={n} (complex128, single thread), {t:.1f} s"}
     return res
 
@@ -669,7 +703,9 @@ def run_qml(args, P, torch, task):
         dom = max(("fused_fwd", "fused_rev"), key=lambda f: fam.get(f, {"total_ms": 0})["total_ms"])
         L = fam[dom]["launches"] / args.steps
         flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
-        roofline = roofline_entry(dom, flops, algorithmic_bytes(dom, n, 8, B, 0), fam[dom]["avg_ms"], "mfma")
+        fwd_g, rev_g = sweep_flops(w["gates"], n, B, with_u2_grad=True)
+        roofline = fused_roofline(dom, (rev_g if dom == "fused_rev" else fwd_g) / L,
+                                  algorithmic_bytes(dom, n, 8, B, 0), flops, fam[dom]["avg_ms"])
         roofline["traffic"] = measured_traffic(f"qml_{task}_n{n}_l{w['layers']}_b{B}", dom)
     epoch_steps = samples / B
     paper = {"mnist": 1.88, "cifar100": 4.60}[task]
@@ -699,30 +735,94 @@ def run_qml(args, P, torch, task):
             if t * 2 > 15.0 or m >= B:
                 break
             m = min(B, max(m + 1, int(m * 15.0 / max(t, 1e-3) * 0.5)))
-        res["cpu_baseline"] = {"value": m / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
+        res["cpu_baseline"] = {"value": m / t, "unit": "samples/s", "cores": 1, "kind": "oracle", **host_info(),
                                "sample": f"loss and gradient of {m} of {B} samples (complex128, single thread), "
                                          f"{t:.1f} s"}
     return res
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The oracle (single-threaded, complex128) on a bounded sample of the
-    workload: forward application of the first K gates at full n, K grown
-    until about `budget_s` of CPU time."""
+def host_info():
+    """CPU model and core counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"host_cpu": model, "host_cores": os.cpu_count(), "host_cores_usable": usable}
+
+
+def _oracle_eval(w, budget_s, max_evals=1000):
+    """Oracle value and gradient of the batch members of w in turn (whole
+    circuit, full H) until `budget_s` is spent; (evals, seconds)."""
     import oracle
-    n = w["n"]
-    params = w["params"][0] if w["params"].ndim == 2 else w["params"]
-    k, t = 1, 0.0
-    while True:
+    prm = np.asarray(w["params"])
+    prm = prm.reshape(-1, prm.shape[-1]) if prm.size else np.zeros((1, 0))
+    done, t = 0, 0.0
+    while done < max_evals and (done == 0 or t < budget_s):
         t0 = time.perf_counter()
-        oracle.run(n, w["gates"][:k], params, w.get("mats"))
-        t = time.perf_counter() - t0
-        if t * 2 > budget_s or k >= len(w["gates"]):
-            break
-        k = min(len(w["gates"]), max(k + 1, int(k * budget_s / max(t, 1e-3) * 0.5)))
-    rate = k * (2 ** n) / t
-    return {"value": rate, "unit": "amplitude-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"forward sweep of the first {k} gates at n={n} (complex128, single thread), {t:.1f} s"}
+        oracle.expect_grad(w["n"], w["gates"], prm[done % prm.shape[0]], w["codes"], w["coeffs"], w.get("mats"))
+        t += time.perf_counter() - t0
+        done += 1
+    return done, t
+
+
+def cpu_baseline(w, name, budget_s=15.0):
+    """The oracle (single-threaded, complex128) on a bounded sample of the
+    workload.  Primary figure: whole value-and-gradient evaluations (forward
+    sweep, H psi and <H>, adjoint sweep) counted like the GPU's
+    3 * G * 2^n amplitude-updates.  When one evaluation at the workload's own
+    size would exceed the budget (the 28- and 32-qubit workloads), the same
+    generator runs at the largest smaller size whose evaluation fits, found
+    from a timed 14-qubit evaluation; beside it, the forward sweep of the
+    first K gates at the workload's own n."""
+    import oracle
+    import workloads as W
+    n, G = w["n"], len(w["gates"])
+    out = {"unit": "amplitude-updates/s", "cores": 1, "kind": "oracle", **host_info()}
+    ew = w
+    if n >= 24:
+        def small(k):
+            v = W.cfg2(n=k) if name.startswith("hea") else W.cfg5(rows=4, cols=k // 4)
+            v["params"] = np.asarray(v["params"])[None, :]
+            return v
+        sizes = list(range(14, 23)) if name.startswith("hea") else [16, 20]
+        _, t0 = _oracle_eval(small(sizes[0]), 0.0, 1)
+        g0 = len(small(sizes[0])["gates"])
+        pick = sizes[0]
+        for k in sizes:
+            gk = len(small(k)["gates"])
+            if t0 * 2 ** (k - sizes[0]) * gk / g0 <= budget_s:
+                pick = k
+        ew = small(pick)
+    done, t = _oracle_eval(ew, min(budget_s, 2.0) if ew is w else 0.0)
+    ne, Ge = ew["n"], len(ew["gates"])
+    out["value"] = 3.0 * Ge * 2 ** ne * done / t
+    out["evals_per_s"] = done / t
+    out["sample"] = (f"{done} whole value-and-gradient evaluation(s) of "
+                     f"{'the workload' if ew is w else 'the same generator'} at n={ne} ({Ge} gates, "
+                     f"{len(ew['coeffs'])} terms; complex128, single thread), {t:.1f} s, each counted as "
+                     f"3*G*2^n amplitude-updates")
+    if ew is not w:
+        params = w["params"][0] if np.asarray(w["params"]).ndim == 2 else w["params"]
+        kf, tf = 1, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.run(n, w["gates"][:kf], params, w.get("mats"))
+            tf = time.perf_counter() - t0
+            if tf * 2 > budget_s or kf >= G:
+                break
+            kf = min(G, max(kf + 1, int(kf * budget_s / max(tf, 1e-3) * 0.5)))
+        out["forward_at_n"] = {"value": kf * (2 ** n) / tf, "unit": "amplitude-updates/s",
+                               "sample": f"forward sweep of the first {kf} gates at n={n}, {tf:.1f} s"}
+    return out
 
 
 def main():
@@ -851,8 +951,8 @@ def main():
         dom = max(("fused_fwd", "fused_rev"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
         L = fam_stats[dom]["launches"] / args.steps
         flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
-        roofline = roofline_entry(dom, flops, algorithmic_bytes(dom, n, s, B, 0), fam_stats[dom]["avg_ms"], "mfma")
-        roofline["gate_level_flops_per_launch"] = (rev_flops if dom == "fused_rev" else fwd_flops) / L
+        roofline = fused_roofline(dom, (rev_flops if dom == "fused_rev" else fwd_flops) / L,
+                                  algorithmic_bytes(dom, n, s, B, 0), flops, fam_stats[dom]["avg_ms"])
         roofline["traffic"] = measured_traffic(w["name"], dom)
     elif args.mode == "tiled" and "rev_tile" in fam_stats:
         dom = max(("fwd_tile", "rev_tile"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
@@ -892,7 +992,7 @@ def main():
                     for k, v in fam_stats.items()},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, args.workload)
     print(json.dumps(out), flush=True)
 
 

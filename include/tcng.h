@@ -112,10 +112,22 @@ tcng_status tcng_state_init(const tcng_state* s, const void* amps_in, int64_t ba
 tcng_status tcng_apply_gate(const tcng_state* s, const int32_t* qubits, int32_t k, const void* unitary,
                             void* stream);
 
-/* Build a circuit handle on the current device.  gates: host [n_gates];
- * const_mats: host complex128 [n_mats][4][4] interleaved (NULL if n_mats = 0).
+/* Build a circuit handle on the current device: the gate list of a
+ * parameterised circuit, each gate added by kind with its qubits and angle
+ * indices (the paper's Circuit(n) followed by c.rx(i, theta=...),
+ * c.cnot(i, j), ..., Sec. "Foundations Recap").  The handle is immutable and
+ * owns its host plans and their small device tables (uploaded here; the only
+ * device allocation of the library besides tcng_pauli_sum_create).
+ *   n_qubits    1 .. 34;
+ *   gates       host [n_gates] (read before return), in application order;
+ *   n_params    length of every parameter vector the circuit is evaluated with;
+ *               each p0/p1 is -1 or in [0, n_params);
+ *   const_mats  host complex128 [n_mats][4][4] interleaved (NULL if n_mats = 0);
+ *               U1 uses the top-left 2x2 of its matrix, U2 the whole 4x4;
+ *   out         receives the handle (release with tcng_circuit_destroy).
  * Errors: TCNG_E_INVALID for out-of-range / duplicate qubits, bad kinds,
- * parameter or matrix indices out of range. */
+ * parameter or matrix indices out of range, null pointers; TCNG_E_ALLOC if
+ * host or device memory runs out. */
 tcng_status tcng_circuit_create(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                                 const double* const_mats, int32_t n_mats, tcng_circuit** out);
 /* Waits for the device (enqueued work may still read the tables), then frees. */
@@ -349,7 +361,8 @@ tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng
  * the first x whose running probability (increasing x, float64) exceeds u[s].
  *   layer     circuit of n one-qubit gates, gate q = U1 on qubit q with matrix
  *             q (its creation matrices only fix the count); needs n >= 9;
- *   psi       device complex64 [2^n], the state (not modified);
+ *   psi       device complex64 [2^n], the state (not modified); it must not
+ *             overlap the memory of `work` (TCNG_E_INVALID);
  *   work      complex64 state with batch = number of snapshots S, overwritten
  *             with the rotated copies;
  *   bases     device uint8 [S][n] (codes other than 1 and 2 act as 3);
@@ -357,8 +370,8 @@ tcng_status tcng_qml_step(const tcng_circuit* c, const double* theta, const tcng
  *   outcomes  device int64 [S]: x, bit q = the outcome of qubit q (written);
  *   ws        device workspace of tcng_shadow_workspace_size bytes.
  * Asynchronous on `stream`; TCNG_E_UNSUPPORTED for complex128 or n < 9,
- * TCNG_E_INVALID for a malformed layer, mismatched state or null arguments,
- * TCNG_E_WORKSPACE if ws is too small. */
+ * TCNG_E_INVALID for a malformed layer, mismatched state, psi overlapping
+ * work or null arguments, TCNG_E_WORKSPACE if ws is too small. */
 tcng_status tcng_shadow_workspace_size(const tcng_circuit* layer, int64_t snapshots, size_t* bytes);
 tcng_status tcng_shadow_snapshots(const tcng_circuit* layer, const void* psi, const tcng_state* work,
                                   const uint8_t* bases, const double* u, int64_t* outcomes, void* ws, size_t ws_bytes,

@@ -1320,6 +1320,14 @@ tcng_status tcng_shadow_snapshots(const tcng_circuit* layer, const void* psi, co
     if (!psi || !bases || !u || !outcomes) return fail(TCNG_E_INVALID, "null state, bases, uniforms or outcomes");
     const int n = work->n_qubits;
     const int64_t S = work->batch;
+    {
+        // every snapshot's first rotation pass reads psi while others already write work
+        const char* lo = static_cast<const char*>(work->amps);
+        const char* hi = lo + (size_t(S - 1) * size_t(work->stride) + (size_t(1) << n)) * 8;
+        const char* a = static_cast<const char*>(psi);
+        if (a + (size_t(1) << n) * 8 > lo && a < hi)
+            return fail(TCNG_E_INVALID, "psi must not overlap the work states");
+    }
     const ShadowLayout M = shadow_layout(layer, n, S);
     if (!ws || ws_bytes < M.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(M.total));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1418,6 +1426,10 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
             const JobList jl{nullptr, nullptr, 0, int32_t(ps)};
             PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st));
         }
+        // a step without gates has no forward pass to fold the previous collapse into
+        if (F.host.passes.empty() && s > 0)
+            PROF_TRY(F_MIPT_COLLAPSE, launch_mipt_collapse(psi->amps, psi->stride, n, batch, n_steps, s - 1, rec, keep,
+                                                           M.wgs, st));
         for (int q = 0; q < n; ++q) {
             PROF_TRY(F_MIPT_MARG, launch_mipt_marg(psi->amps, psi->stride, n, batch, u, n_steps, s, q, p, rec, M.wgs,
                                                    part, st));

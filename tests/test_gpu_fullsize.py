@@ -9,7 +9,8 @@ benchmark times (tiled and fused passes, complex64).
 * the n=28 HEA workload in complex64 against the same run in complex128
   (self-consistency of the two precisions, not oracle parity), norm, and the
   reverse sweep's recomputed initial state;
-* the n=32 fSim / 2D TFIM workload: phi-derivatives against the exact
+* the n=32 fSim / 2D TFIM workload (a Hadamard layer, then the fSim brick
+  wall): phi-derivatives against the exact
   two-term shift rule, theta-derivatives against a fourth-order central
   difference, computed with GPU forward evaluations.
 """
@@ -73,6 +74,24 @@ def test_ghz_and_single_rotation_n30(P):
     idx = torch.randint(1, 2 ** n - 1, (4096,), device="cuda")
     assert torch.max(torch.abs(psi[0, idx])).item() == 0.0
     assert abs(torch.sum(torch.abs(psi) ** 2).item() - 1) < 1e-5
+    # GHZ closed forms of full-weight strings: <X...X> = 1, <Y0 Y1 X...X> = -1 (pins the Y phase),
+    # <Z0 Z_{n-1}> = 1; a full-weight X-mask spans more qubits than a tile, so every mode takes
+    # the per-group Pauli kernels here
+    codes = np.full((3, n), 1, np.uint8)
+    codes[1, :2] = 2
+    codes[2, :] = 0
+    codes[2, [0, n - 1]] = 3
+    for mode in ("plain", "tiled", "fused"):
+        for row, want in ((0, 1.0), (1, -1.0), (2, 1.0)):
+            Hs = P.PauliSum(n, codes[row:row + 1], [1.0])
+            assert abs(P.expect_pauli(psi, Hs, mode=mode).item() - want) < 1e-5, (mode, row)
+    ghz = P.Circuit(n, g, 0)
+    Hg = P.PauliSum(n, codes, [1.0, 0.5, 0.25])
+    for mode in ("tiled", "fused"):
+        E, _ = P.expect_grad(ghz, None, Hg, mode=mode)
+        assert abs(E.item() - 0.75) < 1e-5 * 1.75, mode
+    del ghz, Hg
+    torch.cuda.empty_cache()
     # RY(theta) on qubit 29 of |0..0> on the per-gate path (high target qubit)
     P.state_init(psi)
     th = 1.234
@@ -135,7 +154,9 @@ def test_fsim32_shift_rule_and_finite_differences(P, mode):
 
     assert abs(energy(p) - E) <= 1e-5 * S
     rng = np.random.default_rng(7)
-    for gi in rng.choice(len(c["gates"]), size=2, replace=False):
+    fsim = np.flatnonzero(np.asarray(c["gates"])[:, 0] == W.FSIM)
+    assert np.max(np.abs(g)) > 1e-3 * S      # not a vanishing gradient
+    for gi in rng.choice(fsim, size=2, replace=False):
         k_phi = int(c["gates"][gi][4])
         pp, pm = p.copy(), p.copy()
         pp[k_phi] += np.pi / 2

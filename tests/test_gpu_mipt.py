@@ -155,3 +155,43 @@ def test_mipt_full_size_sampled_members(P, oracle_mod):
     for b in (0, 613):
         o = oracle_following(oracle_mod, w, b, p, g)
         check_member(g, o, w, b, p, norm_tol=NORM_TOL)
+
+
+def test_mipt_measurement_only_step(P, oracle_mod):
+    # a step circuit without gates: every step is the measurement layer alone, so each
+    # step's collapse has no forward pass to be folded into and runs on its own; the
+    # trajectories start from a random state so that the outcomes are not forced
+    n, S, B, p = 10, 4, 3, 0.5
+    rng = np.random.default_rng(313)
+    gates = np.zeros((0, 6), np.int32)
+    step = P.Circuit(n, gates, 0, mats=np.zeros((0, 4, 4)))
+    u = rng.random((B, S, n))
+    init = W.random_state(n, rng).astype(np.complex64)
+    psi = torch.as_tensor(np.tile(init, (B, 1))).cuda().contiguous()
+    mats = torch.zeros((B, S, 0, 4, 4), dtype=torch.complex64, device="cuda")
+    print(f"mipt measurement-only n={n} batch={B} steps={S} p={p}", flush=True)
+    rec, logp, margin = P.mipt_run(step, mats, psi, torch.as_tensor(u).cuda().contiguous(), p, want_margin=True)
+    torch.cuda.synchronize()
+    g = dict(state=psi.cpu().numpy(), rec=rec.cpu().numpy().view(np.uint32), logp=logp.cpu().numpy(),
+             margin=margin.cpu().numpy())
+    w = dict(n=n, gates=gates, mats=np.zeros((B, S, 0, 4, 4)), u=u, steps=S)
+    total = 0
+    for b in range(B):
+        mask, bits = g["rec"][b, :, 0], g["rec"][b, :, 1]
+        force = np.full((S, n), -1, np.int32)
+        for s in range(S):
+            for q in range(n):
+                if (int(mask[s]) >> q) & 1:
+                    force[s, q] = (int(bits[s]) >> q) & 1
+        o = oracle_mod.mipt(n, gates, np.zeros((S, 0, 4, 4)), u[b], p, init=init.astype(np.complex128), force=force)
+        total += check_member(g, o, w, b, p)
+        # with no gates, a qubit measured in an earlier step keeps its outcome
+        seen = {}
+        for s in range(S):
+            for q in range(n):
+                if (int(mask[s]) >> q) & 1:
+                    out = (int(bits[s]) >> q) & 1
+                    if q in seen:
+                        assert out == seen[q]
+                    seen[q] = out
+    assert total > 0

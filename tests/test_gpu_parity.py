@@ -242,6 +242,28 @@ def test_haar_brickwork_lie_gradients(P, oracle_mod, mode):
                           cc["coeffs"], "c64", mode, lie=True)
 
 
+@pytest.mark.parametrize("dtype,mode", [("c64", "fused"), ("c64", "tiled"), ("c128", "tiled")])
+@pytest.mark.parametrize("n", [16, 20])
+def test_full_weight_pauli_terms_match_oracle(P, oracle_mod, n, dtype, mode):
+    """Terms whose X-mask spans more qubits than a tile (X on every qubit,
+    Y0 Y1 X...X, and random weight-n X/Y strings): the Pauli sum has no tiled
+    plan, so the circuit passes run with the per-group Pauli kernels."""
+    if n == 20 and dtype == "c128":
+        pytest.skip("covered at n = 16")
+    c = W.cfg2(n=n, layers=2)
+    r = np.random.default_rng(600 + n)
+    codes = [c["codes"]]
+    full = np.ones((2, n), np.uint8)
+    full[1, :2] = 2
+    codes.append(full)
+    codes.append(r.integers(1, 3, size=(3, n)).astype(np.uint8))
+    codes = np.concatenate(codes)
+    coeffs = np.concatenate([c["coeffs"], r.standard_normal(codes.shape[0] - len(c["coeffs"]))])
+    print(f"full-weight Pauli n={n} {dtype} {mode}", flush=True)
+    E, g = check_expect_grad(P, oracle_mod, n, c["gates"], c["params"][None, :], None, codes, coeffs, dtype, mode)
+    assert np.max(np.abs(g)) > 1e-3
+
+
 def test_autograd_function(P, oracle_mod):
     c = W.cfg2(n=12, layers=2)
     circ = P.Circuit(12, c["gates"], c["n_params"])
@@ -252,6 +274,63 @@ def test_autograd_function(P, oracle_mod):
     ref = oracle_mod.expect_grad(12, c["gates"], c["params"], c["codes"], c["coeffs"])
     assert abs(E.item() - ref["E"]) < 1e-12 * 20
     np.testing.assert_allclose(theta.grad.cpu().numpy(), 2.0 * ref["grad"], atol=1e-11)
+
+
+@pytest.mark.parametrize("mode", ["tiled", "plain"])
+def test_autograd_gradcheck_and_shift_rule_c128(P, mode):
+    """TcngEnergy against torch.autograd.gradcheck (central differences of its
+    own forward) and against the exact two-term parameter-shift rule, both
+    evaluated with GPU forward runs, complex128."""
+    c = W.cfg2(n=11, layers=2)
+    circ = P.Circuit(11, c["gates"], c["n_params"])
+    H = P.PauliSum(11, c["codes"], c["coeffs"])
+    S = np.abs(c["coeffs"]).sum()
+    theta = torch.tensor(c["params"], dtype=torch.float64, device="cuda", requires_grad=True)
+    f = lambda t: P.TcngEnergy.apply(t, circ, H, torch.complex128, mode)   # noqa: E731
+    assert torch.autograd.gradcheck(f, (theta,), eps=1e-6, atol=1e-7, rtol=1e-5)
+    E = f(theta)
+    E.backward()
+    g = theta.grad.cpu().numpy()
+    Pn = c["n_params"]
+    shifted = np.repeat(c["params"][None, :], 2 * Pn, axis=0)
+    shifted[np.arange(Pn), np.arange(Pn)] += np.pi / 2
+    shifted[Pn + np.arange(Pn), np.arange(Pn)] -= np.pi / 2
+    Es = f(torch.tensor(shifted, dtype=torch.float64, device="cuda")).detach().cpu().numpy()
+    shift = 0.5 * (Es[:Pn] - Es[Pn:])
+    assert np.max(np.abs(shift - g)) <= 1e-12 * S
+    assert np.max(np.abs(g)) > 1e-2
+
+
+@pytest.mark.parametrize("mode", ["tiled", "fused"])
+def test_autograd_shift_rule_and_differences_c64(P, mode):
+    """TcngEnergy in complex64 (float32 angles): its gradient against the
+    two-term shift rule and a fourth-order central difference (h = 0.05),
+    from batched GPU forward runs of the same op."""
+    c = W.cfg2(n=12, layers=2)
+    circ = P.Circuit(12, c["gates"], c["n_params"])
+    H = P.PauliSum(12, c["codes"], c["coeffs"])
+    S = np.abs(c["coeffs"]).sum()
+    p32 = W.round_params(c["params"], "c64")
+    theta = torch.tensor(p32, dtype=torch.float32, device="cuda", requires_grad=True)
+    f = lambda t: P.TcngEnergy.apply(t, circ, H, torch.complex64, mode)   # noqa: E731
+    E = f(theta)
+    E.backward()
+    g = theta.grad.double().cpu().numpy()
+    Pn = c["n_params"]
+    rows = []
+    for d in (np.pi / 2, -np.pi / 2, 0.1, 0.05, -0.05, -0.1):
+        x = np.repeat(p32[None, :], Pn, axis=0)
+        x[np.arange(Pn), np.arange(Pn)] += d
+        rows.append(x)
+    Es = f(torch.tensor(np.concatenate(rows), dtype=torch.float32, device="cuda")).detach().double().cpu().numpy()
+    Es = Es.reshape(6, Pn)
+    shift = 0.5 * (Es[0] - Es[1])
+    fd = (-Es[2] + 8 * Es[3] - 8 * Es[4] + Es[5]) / (12 * 0.05)
+    assert np.max(np.abs(shift - g)) <= 1e-4 * S
+    # the difference quotient divides float32 rounding of E (~1e-7 S) by h, and its
+    # truncation error is h^4 |d^5E| / 30 <= 2e-7 S
+    assert np.max(np.abs(fd - g)) <= 1e-4 * S
+    assert np.max(np.abs(g)) > 1e-2
 
 
 def test_results_are_deterministic(P):

@@ -384,11 +384,16 @@ def cfg4(count=1024, n_lo=12, n_hi=22, d_lo=2, d_hi=16, seed=4):
 
 
 def cfg5(rows=4, cols=8, depth=20, seed=5):
-    """n = rows*cols fSim brick-wall (depth 20 -> 310 gates at n=32, 620
-    angles), 2D open TFIM -sum ZZ - 3.04 sum X on the rows x cols lattice."""
+    """n = rows*cols: a Hadamard on every qubit, then the fSim brick-wall
+    (depth 20 -> 310 fSim gates at n=32, 620 angles), 2D open TFIM
+    -sum ZZ - 3.04 sum X on the rows x cols lattice.  The Hadamard layer is
+    part of the reading of this workload: an fSim gate keeps |00> as it is and
+    only mixes |01> with |10>, so the brick wall alone would leave |0...0>
+    unchanged (E = -sum ZZ for every angle, a zero gradient)."""
     rng = np.random.default_rng(seed)
     n = rows * cols
     gates, params = brickwork_fsim(n, depth, rng)
+    gates = np.concatenate([as_gate_array([gate(H, q) for q in range(n)]), gates])
     codes, coeffs = tfim_2d(rows, cols, -1.0, -3.04)
     return dict(name=f"fsim_brickwork_n{n}_d{depth}_tfim2d", dtype="c64", n=n, gates=gates,
                 n_params=len(params), params=params, mats=np.zeros((0, 4, 4), np.complex128),
