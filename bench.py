@@ -52,6 +52,7 @@ KERNEL_SOURCES = {
     "tile": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_tile.hip", "plan.cpp", "plan.h"],
     "fused": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_fused.hip", "plan.cpp", "plan.h"],
     "pauli": ["common.h", "devutil.h", "kernels.h", "kern_pauli.hip"],
+    "plain": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_plain.hip"],
 }
 TRAFFIC = {
     ("hea_n28_L12_tfim", "rev_tile"): (8.608e+09, "3562a1ea2ffdc471"),
@@ -65,6 +66,7 @@ TRAFFIC = {
     ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e+08, "1d30ca8be5b147dc"),
     ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e+10, "1d30ca8be5b147dc"),
     ("tfim_coo_n24", "pauli_coo"): (1.342e+10, "a892d74871e9a4e5"),
+    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7187e+10, "860d66c76ac604b3"),
 }
 
 
@@ -72,7 +74,8 @@ def source_hash(kernel):
     import hashlib
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_2602_14167_amd", "csrc")
-    group = "fused" if kernel.startswith("fused") else ("pauli" if kernel.startswith("pauli") else "tile")
+    group = ("fused" if kernel.startswith("fused") else "pauli" if kernel.startswith("pauli")
+             else "plain" if kernel.startswith("plain") else "tile")
     for f in KERNEL_SOURCES[group]:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
@@ -357,6 +360,9 @@ def run_gate_sweep(args, P, torch, n):
     rng = np.random.default_rng(7)
     c64 = args.dtype == "c64"
     s = 8 if c64 else 16
+    # a device copy of the state's size first: the HBM reference of the sweep
+    # (and the counter calibration of its profiles)
+    copy = copy_ceiling(torch, (2 ** n) * s)
     psi = torch.empty((1, 2 ** n), dtype=torch.complex64 if c64 else torch.complex128, device="cuda")
     P.state_init(psi)
     cases = []
@@ -399,9 +405,12 @@ def run_gate_sweep(args, P, torch, n):
         "config": {"workload": f"single_gate_sweep_n{n}_{args.dtype}", "n_qubits": n, "cases": len(res),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": med, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(med / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "gate1/gate2 (median case)",
-                     "min_GB_s": gb[0], "max_GB_s": gb[-1],
+                     "frac": round(med / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"single_gate_sweep_n{n}_{args.dtype}", "plain_gate"),
+                     "kernel": "gate1/gate2 (median case)", "bytes_per_launch": 2 * s * 2 ** n,
+                     "min_GB_s": gb[0], "max_GB_s": gb[-1], "cases": len(gb),
                      "cases_at_or_above_70pct": sum(1 for v in gb if v >= 0.7 * HBM_PEAK_GBS)},
+        "copy_ceiling": copy,
         "gate_sweep": res,
     }
 

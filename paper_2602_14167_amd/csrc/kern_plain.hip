@@ -505,6 +505,178 @@ __global__ void k_finish_multi(const FinishJob* __restrict__ jobs, const int64_t
     finish_one(jobs[lo], i - prefix[lo]);
 }
 
+// ---------------------------------------------------------------------------
+// chunked one- and two-qubit gates (the state has at least CHUNK_BITS qubits).
+// A workgroup owns a chunk of 2^c amplitudes: those whose index bits outside
+// a set T of c qubits are fixed, T = the gate's qubits and the lowest other
+// qubits.  The chunk moves as 16-byte vectors, thread t taking vectors
+// k * 256 + t (k = 0..7), so a wave's 64 vectors are 1 KiB of consecutive
+// amplitudes and every access is a full, contiguous wave access; chunks of
+// 32 KiB give the grid 2^(n - c) small workgroups, which keep more of HBM
+// busy than a persistent grid of large ones.  A gate whose qubits avoid the
+// wave's lane bits pairs amplitudes inside a thread's registers (the host
+// gives those qubits the local bits of the vector or of k); otherwise the
+// chunk goes through LDS once (the low-target case).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct ChunkCfg {
+    static constexpr int A = sizeof(R) == 4 ? 2 : 1;          // amplitudes per 16-byte vector
+    static constexpr int C = sizeof(R) == 4 ? 12 : 11;        // chunk bits (32 KiB)
+    static constexpr int VPT = (1 << C) / A / NTHREADS;       // vectors per thread (8)
+    static constexpr int RA = VPT * A;                        // register amplitudes per thread
+    static constexpr int TB = sizeof(R) == 4 ? 1 : 0;         // first local bit of the thread index
+    static constexpr int KB = TB + 8;                         // first local bit of k
+};
+
+struct ChunkMap {
+    uint64_t tmask;      // the qubits of T
+    int32_t lq[12];      // local bit -> qubit
+    int32_t g0, g1;      // local bits of the gate's qubits (q0 = matrix MSB; g1 = -1: one qubit)
+};
+
+template <typename R>
+__device__ __forceinline__ uint64_t chunk_base(uint64_t chunk, uint64_t tmask, int n) {
+    uint64_t base = 0;
+    int k = 0;
+    for (int q = 0; q < n; ++q) {
+        if ((tmask >> q) & 1) continue;
+        base |= ((chunk >> k) & 1) << q;
+        ++k;
+    }
+    return base;
+}
+
+// global offset of local index l (disjoint bits: OR of the bits' qubits)
+template <typename R>
+__device__ __forceinline__ uint64_t chunk_off(uint32_t l, const ChunkMap& m) {
+    uint64_t g = 0;
+#pragma unroll
+    for (int i = 0; i < ChunkCfg<R>::C; ++i) g |= uint64_t((l >> i) & 1) << m.lq[i];
+    return g;
+}
+
+template <typename R>
+__device__ __forceinline__ void vload(const cx<R>* p, cx<R>* o);
+template <>
+__device__ __forceinline__ void vload<float>(const cx<float>* p, cx<float>* o) { ld2(p, o[0], o[1]); }
+template <>
+__device__ __forceinline__ void vload<double>(const cx<double>* p, cx<double>* o) { o[0] = ld1(p); }
+template <typename R>
+__device__ __forceinline__ void vstore(cx<R>* p, const cx<R>* o);
+template <>
+__device__ __forceinline__ void vstore<float>(cx<float>* p, const cx<float>* o) { st2(p, o[0], o[1]); }
+template <>
+__device__ __forceinline__ void vstore<double>(cx<double>* p, const cx<double>* o) { st1(p, o[0]); }
+
+// register pairing: the gate's qubits sit at register-index bits P0 (matrix
+// MSB) and P1 (-1: one qubit) of the thread's RA amplitudes (register index =
+// k * A + vector element)
+template <typename R, int P0, int P1>
+__global__ void __launch_bounds__(NTHREADS)
+k_gate_chunk_reg(cx<R>* __restrict__ state, int64_t stride, int n, ChunkMap map, int kind, int p0, int p1, int mat,
+                 const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm,
+                 const cx<R>* __restrict__ umat, int inv) {
+    using CF = ChunkCfg<R>;
+    const int64_t b = blockIdx.y;
+    cx<R>* psi = state + b * stride;
+    const R* prm = params ? params + b * pstride : nullptr;
+    const uint64_t base = chunk_base<R>(blockIdx.x, map.tmask, n);
+    const uint64_t lane_off = chunk_off<R>(uint32_t(threadIdx.x) << CF::TB, map);
+    cx<R> a[CF::RA];
+#pragma unroll
+    for (int k = 0; k < CF::VPT; ++k)
+        vload<R>(psi + base + lane_off + chunk_off<R>(uint32_t(k) << CF::KB, map), a + k * CF::A);
+    if constexpr (P1 < 0) {
+        cx<R> u[4];
+        gate_mat1<R>(kind, prm, p0, cm, mat, umat, inv != 0, u);
+#pragma unroll
+        for (int i = 0; i < CF::RA; ++i)
+            if (!((i >> P0) & 1)) mv2(u, a[i], a[i | (1 << P0)]);
+    } else {
+        cx<R> u[16];
+        gate_mat2<R>(kind, prm, p0, p1, cm, mat, umat, inv != 0, u);
+        constexpr int M0 = 1 << P0, M1 = 1 << P1;
+#pragma unroll
+        for (int i = 0; i < CF::RA; ++i) {
+            if ((i & M0) || (i & M1)) continue;
+            cx<R> x[4] = {a[i], a[i | M1], a[i | M0], a[i | M0 | M1]};
+            mv4(u, x);
+            a[i] = x[0];
+            a[i | M1] = x[1];
+            a[i | M0] = x[2];
+            a[i | M0 | M1] = x[3];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CF::VPT; ++k)
+        vstore<R>(psi + base + lane_off + chunk_off<R>(uint32_t(k) << CF::KB, map), a + k * CF::A);
+}
+
+// LDS pairing (a gate qubit among the lane bits): the chunk is staged in LDS
+// at its local index; each thread applies the gate to pairs / quads
+// j * 256 + t of the local index space, then the chunk is stored back
+template <typename R, int NQ>
+__global__ void __launch_bounds__(NTHREADS)
+k_gate_chunk_lds(cx<R>* __restrict__ state, int64_t stride, int n, ChunkMap map, int kind, int p0, int p1, int mat,
+                 const R* __restrict__ params, int64_t pstride, const cx<R>* __restrict__ cm,
+                 const cx<R>* __restrict__ umat, int inv) {
+    using CF = ChunkCfg<R>;
+    __shared__ cx<R> lds[1 << CF::C];
+    const int64_t b = blockIdx.y;
+    cx<R>* psi = state + b * stride;
+    const R* prm = params ? params + b * pstride : nullptr;
+    const uint64_t base = chunk_base<R>(blockIdx.x, map.tmask, n);
+    const uint32_t t = threadIdx.x;
+    const uint64_t lane_off = chunk_off<R>(t << CF::TB, map);
+    {
+        cx<R> a[CF::RA];
+#pragma unroll
+        for (int k = 0; k < CF::VPT; ++k)
+            vload<R>(psi + base + lane_off + chunk_off<R>(uint32_t(k) << CF::KB, map), a + k * CF::A);
+#pragma unroll
+        for (int k = 0; k < CF::VPT; ++k)
+#pragma unroll
+            for (int e = 0; e < CF::A; ++e) lds[((uint32_t(k) << 8 | t) << CF::TB) | uint32_t(e)] = a[k * CF::A + e];
+    }
+    __syncthreads();
+    const int lo = NQ == 2 ? min(map.g0, map.g1) : map.g0, hi = NQ == 2 ? max(map.g0, map.g1) : map.g0;
+    const uint32_t m0 = 1u << map.g0, m1 = NQ == 2 ? (1u << map.g1) : 0u;
+    if constexpr (NQ == 1) {
+        cx<R> u[4];
+        gate_mat1<R>(kind, prm, p0, cm, mat, umat, inv != 0, u);
+#pragma unroll
+        for (int j = 0; j < (1 << CF::C) / 2 / NTHREADS; ++j) {
+            const uint32_t i = uint32_t(insert0(uint64_t(j) * NTHREADS + t, lo));
+            cx<R> x0 = lds[i], x1 = lds[i | m0];
+            mv2(u, x0, x1);
+            lds[i] = x0;
+            lds[i | m0] = x1;
+        }
+    } else {
+        cx<R> u[16];
+        gate_mat2<R>(kind, prm, p0, p1, cm, mat, umat, inv != 0, u);
+#pragma unroll
+        for (int j = 0; j < (1 << CF::C) / 4 / NTHREADS; ++j) {
+            const uint32_t i = uint32_t(insert0(insert0(uint64_t(j) * NTHREADS + t, lo), hi));
+            cx<R> x[4] = {lds[i], lds[i | m1], lds[i | m0], lds[i | m0 | m1]};
+            mv4(u, x);
+            lds[i] = x[0];
+            lds[i | m1] = x[1];
+            lds[i | m0] = x[2];
+            lds[i | m0 | m1] = x[3];
+        }
+    }
+    __syncthreads();
+    cx<R> a[CF::RA];
+#pragma unroll
+    for (int k = 0; k < CF::VPT; ++k)
+#pragma unroll
+        for (int e = 0; e < CF::A; ++e) a[k * CF::A + e] = lds[((uint32_t(k) << 8 | t) << CF::TB) | uint32_t(e)];
+#pragma unroll
+    for (int k = 0; k < CF::VPT; ++k)
+        vstore<R>(psi + base + lane_off + chunk_off<R>(uint32_t(k) << CF::KB, map), a + k * CF::A);
+}
+
 }  // namespace
 
 template <typename R>
@@ -525,6 +697,115 @@ static unsigned stream_grid(uint64_t units, int64_t batch) {
     return unsigned(std::max<uint64_t>(blocks, 1));
 }
 
+// chunk map and kernel of a one- or two-qubit gate (see k_gate_chunk_reg / _lds)
+template <typename R>
+static hipError_t launch_gate_chunk(void* state, int64_t stride, int n, int64_t batch, const int* qs, int nq, int kind,
+                                    int p0, int p1, int mat, const void* params, int64_t pstride, const void* cmats,
+                                    const void* umat, bool inv, hipStream_t st) {
+    using CF = ChunkCfg<R>;
+    constexpr int LANE_LO = CF::TB, LANE_HI = CF::TB + 5;   // local (= global) bits of a wave's lanes
+    bool is_gate[64] = {};
+    for (int i = 0; i < nq; ++i) is_gate[qs[i]] = true;
+    bool reg = true;
+    for (int i = 0; i < nq; ++i)
+        if (qs[i] >= LANE_LO && qs[i] <= LANE_HI) reg = false;
+    ChunkMap m{};
+    int nl = 0;
+    auto push = [&](int q) { m.lq[nl++] = q; };
+    int next = 0;   // next non-gate qubit candidate
+    auto next_other = [&]() {
+        while (is_gate[next]) ++next;
+        return next++;
+    };
+    // the k bits not taken by the gate: qubits from c up (a chunk is then 8 runs
+    // of 4 KiB spaced 32 KiB apart, the neighbouring chunks filling the gaps,
+    // which HBM serves faster than contiguous 32 KiB chunks), then the rest
+    int kfill[64], nk = 0;
+    for (int q = CF::C; q < n; ++q) kfill[nk++] = q;
+    for (int q = 0; q < CF::C && q < n; ++q) kfill[nk++] = q;
+    int kf = 0;
+    bool used[64] = {};
+    auto next_k = [&]() {
+        while (is_gate[kfill[kf]] || used[kfill[kf]]) ++kf;
+        return kfill[kf++];
+    };
+    int pos[2] = {-1, -1};
+    if (reg) {
+        if (CF::TB == 1) {   // complex64: local bit 0 is the vector element, always qubit 0
+            if (is_gate[0]) {
+                for (int i = 0; i < nq; ++i)
+                    if (qs[i] == 0) pos[i] = 0;
+                push(0);
+            } else {
+                push(next_other());
+            }
+        }
+        while (nl < CF::KB) push(next_other());
+        for (int i = 0; i < nl; ++i) used[m.lq[i]] = true;
+        for (int i = 0; i < nq; ++i)
+            if (pos[i] < 0) {
+                pos[i] = nl;
+                push(qs[i]);
+            }
+        while (nl < CF::C) push(next_k());
+    } else {
+        // T = the qubits below the k bits (4 KiB runs), the gate's qubits, the
+        // k-bit fill; in increasing order (the lanes keep the lowest qubits)
+        bool in_t[64] = {};
+        int cnt = 0;
+        for (int q = 0; q < CF::KB; ++q) in_t[q] = true, ++cnt;
+        for (int i = 0; i < nq; ++i)
+            if (!in_t[qs[i]]) in_t[qs[i]] = true, ++cnt;
+        for (int q = 0; q < n; ++q) used[q] = in_t[q];
+        while (cnt < CF::C) in_t[next_k()] = true, ++cnt;
+        for (int q = 0; q < n; ++q)
+            if (in_t[q]) {
+                for (int i = 0; i < nq; ++i)
+                    if (qs[i] == q) pos[i] = nl;
+                push(q);
+            }
+    }
+    if (nl != CF::C) return hipErrorInvalidValue;
+    for (int i = 0; i < nl; ++i) {
+        if (m.lq[i] < 0 || m.lq[i] >= n) return hipErrorInvalidValue;
+        m.tmask |= uint64_t(1) << m.lq[i];
+    }
+    m.g0 = pos[0];
+    m.g1 = nq == 2 ? pos[1] : -1;
+    const dim3 grid(unsigned(uint64_t(1) << (n - CF::C)), unsigned(batch));
+    cx<R>* sp = static_cast<cx<R>*>(state);
+    const R* pp = static_cast<const R*>(params);
+    const cx<R>* cp = static_cast<const cx<R>*>(cmats);
+    const cx<R>* up = static_cast<const cx<R>*>(umat);
+    const int iv = int(inv);
+    if (!reg) {
+        if (nq == 1)
+            hipLaunchKernelGGL((k_gate_chunk_lds<R, 1>), grid, dim3(NTHREADS), 0, st, sp, stride, n, m, kind, p0, p1,
+                               mat, pp, pstride, cp, up, iv);
+        else
+            hipLaunchKernelGGL((k_gate_chunk_lds<R, 2>), grid, dim3(NTHREADS), 0, st, sp, stride, n, m, kind, p0, p1,
+                               mat, pp, pstride, cp, up, iv);
+        return hipGetLastError();
+    }
+    // register-index bits of the gate's local bits: the vector element (complex64 qubit 0), then k
+    constexpr int KSHIFT = CF::TB;   // log2(amplitudes per vector)
+    auto rbit = [&](int g) { return g < CF::KB ? g : g - CF::KB + KSHIFT; };
+    const int r0 = rbit(m.g0), r1 = nq == 2 ? rbit(m.g1) : -1;
+#define TCNG_CHUNK_REG(P0, P1)                                                                                     \
+    if (r0 == P0 && r1 == P1) {                                                                                    \
+        hipLaunchKernelGGL((k_gate_chunk_reg<R, P0, P1>), grid, dim3(NTHREADS), 0, st, sp, stride, n, m, kind, p0,  \
+                           p1, mat, pp, pstride, cp, up, iv);                                                      \
+        return hipGetLastError();                                                                                  \
+    }
+    TCNG_CHUNK_REG(0, -1)
+    TCNG_CHUNK_REG(1, -1)
+    TCNG_CHUNK_REG(0, 1)
+    TCNG_CHUNK_REG(1, 0)
+    TCNG_CHUNK_REG(1, 2)
+#undef TCNG_CHUNK_REG
+    return hipErrorInvalidValue;
+}
+
 template <typename R>
 hipError_t launch_gate1(void* state, int64_t stride, int n, int64_t batch, int q, int kind, int p0, int mat,
                         const void* params, int64_t pstride, const void* cmats, const void* umat, bool inv,
@@ -534,6 +815,11 @@ hipError_t launch_gate1(void* state, int64_t stride, int n, int64_t batch, int q
                            stride, q, kind, p0, mat, static_cast<const R*>(params), pstride,
                            static_cast<const cx<R>*>(cmats), static_cast<const cx<R>*>(umat), int(inv));
         return hipGetLastError();
+    }
+    if (n >= ChunkCfg<R>::C && batch <= 65535) {
+        const int qs[1] = {q};
+        return launch_gate_chunk<R>(state, stride, n, batch, qs, 1, kind, p0, -1, mat, params, pstride, cmats, umat,
+                                    inv, st);
     }
     const uint64_t units = (sizeof(R) == 4) ? (uint64_t(1) << (n - 2)) : (uint64_t(1) << (n - 1));
     hipLaunchKernelGGL((k_gate1<R>), dim3(stream_grid(units, batch), unsigned(batch)), dim3(NTHREADS), 0, st,
@@ -546,6 +832,11 @@ template <typename R>
 hipError_t launch_gate2(void* state, int64_t stride, int n, int64_t batch, int q0, int q1, int kind, int p0, int p1,
                         int mat, const void* params, int64_t pstride, const void* cmats, const void* umat, bool inv,
                         hipStream_t st) {
+    if (n >= ChunkCfg<R>::C && batch <= 65535) {
+        const int qs[2] = {q0, q1};
+        return launch_gate_chunk<R>(state, stride, n, batch, qs, 2, kind, p0, p1, mat, params, pstride, cmats, umat,
+                                    inv, st);
+    }
     hipLaunchKernelGGL((k_gate2<R>), dim3(stream_grid(uint64_t(1) << (n - 2), batch), unsigned(batch)), dim3(NTHREADS), 0,
                        st, static_cast<cx<R>*>(state), stride, n, q0, q1, kind, p0, p1, mat,
                        static_cast<const R*>(params), pstride, static_cast<const cx<R>*>(cmats),

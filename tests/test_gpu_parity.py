@@ -7,14 +7,16 @@ all relative to S = sum_k |c_k|, the a-priori bound on |<H>| and on each
 gradient component of a generator with norm <= 1 (a relative error of a value
 that concentrates near 0 is undefined).  For complex64 the oracle receives the
 float32-rounded angles and complex64-rounded matrices widened exactly, so the
-comparison measures the kernels, not input rounding.  Amplitudes: absolute
-1e-12 (c128) / 2e-5 (c64).
+comparison measures the kernels, not input rounding.  Amplitudes: the
+largest error over the state's largest amplitude, at most 8 * (gate
+applications) * (unit roundoff), see tests/bars.py.
 """
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
+from tests.bars import assert_amps
 
 pytestmark = pytest.mark.gpu
 
@@ -65,8 +67,10 @@ def test_state_init(P, dtype):
     ref[:, 37] = 1
     np.testing.assert_array_equal(psi.cpu().numpy(), ref)
     amps = W.random_state(n, np.random.default_rng(1))
-    P.state_init(psi, amps=dev(amps, TDT[dtype]))
-    np.testing.assert_allclose(psi.cpu().numpy(), np.tile(amps, (3, 1)), atol=TOL[dtype]["amp"])
+    src = dev(amps, TDT[dtype])
+    P.state_init(psi, amps=src)
+    # a copy: bit-exact
+    np.testing.assert_array_equal(psi.cpu().numpy(), np.tile(src.cpu().numpy(), (3, 1)))
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
@@ -83,7 +87,31 @@ def test_apply_gate_matches_oracle(P, oracle_mod, dtype, k):
         A = W.round_mats(A, dtype)
         P.apply_gate(psi, qs, dev(A, TDT[dtype]))
         init = oracle_mod.apply_matrix(n, init, qs, A)
-    np.testing.assert_allclose(psi.cpu().numpy()[0], init, atol=TOL[dtype]["amp"])
+    assert_amps(psi.cpu().numpy()[0], init, dtype, 3 * 2 ** k, f"apply_gate k={k}")
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 12), ("c64", 13), ("c128", 11), ("c128", 13)])
+def test_chunked_gates_every_target(P, oracle_mod, dtype, n):
+    """Streaming gate kernels on states of at least one chunk: every target of
+    a one-qubit matrix, and two-qubit matrices on pairs of low (lane-bit),
+    high and vector-element qubits in both orders, applied in turn."""
+    r = np.random.default_rng(20 + n)
+    ref = W.random_state(n, r)
+    psi = dev(ref, TDT[dtype]).reshape(1, -1).contiguous()
+    ref = psi.cpu().numpy()[0].astype(np.complex128)
+    ops = 0
+    targets = [[q] for q in range(n)]
+    pairs = [(0, 1), (1, 0), (0, n - 1), (n - 1, 0), (1, 2), (3, 1), (2, 9), (9, 2), (7, 8), (n - 1, n - 2), (5, 6),
+             (6, 7), (0, 7), (10, 4)]
+    for qs in targets + [list(p) for p in pairs]:
+        k = len(qs)
+        A = r.standard_normal((2 ** k, 2 ** k)) + 1j * r.standard_normal((2 ** k, 2 ** k))
+        A = np.linalg.qr(A)[0]
+        A = W.round_mats(A, dtype)
+        P.apply_gate(psi, qs, dev(A, TDT[dtype]))
+        ref = oracle_mod.apply_matrix(n, ref, qs, A)
+        ops += 2 ** k
+    assert_amps(psi.cpu().numpy()[0], ref, dtype, ops, f"chunked gates n={n}")
 
 
 # ---------------------------------------------------------------------------
@@ -102,7 +130,7 @@ def test_run_circuit_random_all_kinds(P, oracle_mod, dtype, mode, n):
     got = run_gpu(P, n, gates, params, mats, dtype, mode, batch_params=bp, init=np.tile(init, (B, 1)))
     for b in range(B):
         ref = oracle_mod.run(n, gates, W.round_params(bp[b], dtype), W.round_mats(mats, dtype), init=init if dtype == "c128" else init.astype(np.complex64))
-        np.testing.assert_allclose(got[b], ref, atol=TOL[dtype]["amp"] * (5 if dtype == "c64" else 1))
+        assert_amps(got[b], ref, dtype, 4 * len(gates), f"random circuit n={n} {mode}")
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
@@ -110,7 +138,7 @@ def test_tiled_and_plain_agree_on_hea(P, dtype):
     c = W.cfg2(n=15, layers=4)
     a = run_gpu(P, 15, c["gates"], c["params"], None, dtype, "tiled")
     b = run_gpu(P, 15, c["gates"], c["params"], None, dtype, "plain")
-    np.testing.assert_allclose(a, b, atol=TOL[dtype]["amp"])
+    assert_amps(a, b, dtype, 2 * len(c["gates"]), "hea15 tiled vs plain")
 
 
 # ---------------------------------------------------------------------------
@@ -180,7 +208,7 @@ def check_expect_grad(P, oracle_mod, n, gates, params_b, mats, codes, coeffs, dt
             assert err <= tol["g"] * S, (b, err)
             assert np.all(gl[~u2] == 0.0)
     # the reverse sweep recomputes the initial states
-    np.testing.assert_allclose(psi.cpu().numpy(), psi0.cpu().numpy(), atol=(1e-11 if dtype == "c128" else 1e-4))
+    assert_amps(psi.cpu().numpy(), psi0.cpu().numpy(), dtype, 8 * len(gates), f"recomputed psi0 n={n} {mode}")
     return E, g
 
 
@@ -190,7 +218,7 @@ def test_cfg1_state_energy_gradient_c128(P, oracle_mod, mode):
     c = W.cfg1()
     st = run_gpu(P, 10, c["gates"], c["params"], None, "c128", mode)[0]
     ref = oracle_mod.expect_grad(10, c["gates"], c["params"], c["codes"], c["coeffs"], want_state=True)
-    np.testing.assert_allclose(st, ref["state"], atol=1e-13)
+    assert_amps(st, ref["state"], "c128", len(c["gates"]), f"cfg1 final state {mode}")
     check_expect_grad(P, oracle_mod, 10, c["gates"], c["params"][None, :], None, c["codes"], c["coeffs"], "c128", mode)
 
 
