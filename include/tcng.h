@@ -256,6 +256,23 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
                              const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
                              double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, void* stream);
 
+/* tcng_expect_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  The workspace is a fixed device array inside the
+ * library of tcng_noalloc_scratch_bytes() bytes (64 MiB), one copy per GPU,
+ * held until the process ends; its device address is resolved once per device
+ * on the first call there.  Arguments, outputs and modes are those of
+ * tcng_expect_grad; the call allocates nothing (no hipMalloc, no library
+ * allocation) and leaves the array holding the evaluation's partial sums.
+ * Errors: those of tcng_expect_grad, and TCNG_E_WORKSPACE when the shape needs
+ * more workspace than the array holds (tcng_workspace_size tells).
+ * Every call on one GPU shares its array: calls that overlap on one GPU (two
+ * streams, two threads) race and must be ordered by the caller. */
+tcng_status tcng_expect_grad_noalloc(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,
+                                     const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
+                                     double* gate_grad, int32_t mode, void* stream);
+size_t tcng_noalloc_scratch_bytes(void);
+
 /* Kernel-family timing with HIP events recorded on the launch stream around
  * every launch (benchmark instrumentation, not part of the method; off by
  * default).

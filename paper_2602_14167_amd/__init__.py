@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TCNG_U1_KIND,  # noqa: F401
                    TcngError, TcngGate, TcngState, check, lib)
 
-__all__ = ["expect_grad_multi", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
+__all__ = ["expect_grad_multi", "expect_grad_noalloc", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
            "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
            "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots", "qml_step"]
 
@@ -271,6 +271,33 @@ def expect_grad(circ: Circuit, params, H: PauliSum, psi=None, lam=None, batch=No
                                  ctypes.c_void_p(grad.data_ptr()) if circ.n_params else None,
                                  ctypes.c_void_p(gg.data_ptr()) if gg is not None else None, m,
                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    if want_gate_grad:
+        return energy, grad, gg
+    return energy, grad
+
+
+def expect_grad_noalloc(circ: Circuit, params, H: PauliSum, psi=None, lam=None, batch=None, dtype=torch.complex64,
+                        want_gate_grad=False, mode="tiled"):
+    """expect_grad through the allocation-free entry point: the library's
+    fixed per-GPU scratch array replaces the workspace (shapes whose workspace
+    exceeds it raise).  Calls that overlap on one GPU race on that array."""
+    if psi is None:
+        if batch is None:
+            batch = 1 if params is None or circ.n_params == 0 else params.numel() // circ.n_params
+        psi = new_state(circ.n, batch, dtype)
+    s = _state(psi, circ.n)
+    if lam is None:
+        lam = torch.empty_like(psi)
+    sl = _state(lam, circ.n)
+    m = _mode(mode)
+    p, pp = _params(circ, params, psi, s.batch)
+    energy = torch.empty(s.batch, dtype=torch.float64, device=psi.device)
+    grad = torch.empty((s.batch, max(circ.n_params, 0)), dtype=torch.float64, device=psi.device)
+    gg = torch.empty((s.batch, circ.n_gates, 15), dtype=torch.float64, device=psi.device) if want_gate_grad else None
+    check(lib().tcng_expect_grad_noalloc(circ.handle, pp, H.handle, ctypes.byref(s), ctypes.byref(sl),
+                                         ctypes.c_void_p(energy.data_ptr()),
+                                         ctypes.c_void_p(grad.data_ptr()) if circ.n_params else None,
+                                         ctypes.c_void_p(gg.data_ptr()) if gg is not None else None, m, _stream()))
     if want_gate_grad:
         return energy, grad, gg
     return energy, grad

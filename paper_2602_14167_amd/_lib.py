@@ -27,6 +27,7 @@ EXPORTS = [
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
     "tcng_shadow_workspace_size", "tcng_shadow_snapshots", "tcng_qml_workspace_size", "tcng_qml_step",
+    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes",
 ]
 
 
@@ -73,6 +74,8 @@ def lib():
     L.tcng_run_circuit.argtypes = [P, P, PS, i32, P, sz, P]
     L.tcng_expect_pauli.argtypes = [PS, P, P, i32, P, sz, P]
     L.tcng_expect_grad.argtypes = [P, P, P, PS, PS, P, P, P, i32, P, sz, P]
+    L.tcng_expect_grad_noalloc.argtypes = [P, P, P, PS, PS, P, P, P, i32, P]
+    L.tcng_noalloc_scratch_bytes.argtypes = []
     L.tcng_workspace_size_multi.argtypes = [P, P, i32, i32, ctypes.POINTER(sz)]
     L.tcng_expect_grad_multi.argtypes = [P, P, i32, P, PS, PS, P, P, P, P, sz, P]
     L.tcng_circuit_configure.argtypes = [P, i32, i32, i32, i32]
@@ -97,8 +100,9 @@ def lib():
     L.tcng_mipt_workspace_size.argtypes = [P, i32, i64, ctypes.POINTER(sz)]
     L.tcng_mipt_run.argtypes = [P, i32, P, PS, P, ctypes.c_double, P, P, P, P, sz, P]
     for name in EXPORTS:
-        if name != "tcng_last_error" and name != "tcng_version":
+        if name not in ("tcng_last_error", "tcng_version", "tcng_noalloc_scratch_bytes"):
             getattr(L, name).restype = i32
+    L.tcng_noalloc_scratch_bytes.restype = sz
     _lib = L
     return L
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <cstring>
 #include <string>
@@ -2057,6 +2058,63 @@ tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t 
     }
     if (n_passes) *n_passes = int32_t(P.passes.size());
     return ok();
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free value and gradient: the evaluation's workspace is a fixed
+// device array of the library (one copy per GPU, held until the process
+// ends) instead of caller memory
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// host code never uses this name as an address (it is a host-side stand-in):
+// the device address comes from hipGetSymbolAddress, once per device
+__device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// the current device's copy of `scratch` (resolved on its first use there)
+tcng_status scratch_address(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(TCNG_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(TCNG_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TCNG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tcng_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+tcng_status tcng_expect_grad_noalloc(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,
+                                     const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
+                                     double* gate_grad, int32_t mode, void* stream) {
+    if (!c || !h) return fail(TCNG_E_INVALID, "null circuit or Pauli sum");
+    if (tcng_status e = check_state(psi, "tcng_expect_grad_noalloc(psi)")) return e;
+    size_t need = 0;
+    if (tcng_status e = tcng_workspace_size(c, h, psi->dtype, psi->batch, mode, &need)) return e;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(TCNG_E_WORKSPACE, "the evaluation needs " + std::to_string(need) +
+                                          " bytes of workspace; the allocation-free entry point holds " +
+                                          std::to_string(NOALLOC_SCRATCH_BYTES) + " (use tcng_expect_grad)");
+    void* ws = nullptr;
+    if (tcng_status e = scratch_address(&ws)) return e;
+    return tcng_expect_grad(c, params, h, psi, lam, energy, grad, gate_grad, mode, ws, NOALLOC_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"
