@@ -316,10 +316,11 @@ def run_per_circuit(args, w, P, torch):
     lam = torch.empty_like(psi)
     energy = torch.empty(1, dtype=torch.float64, device="cuda")
     grad = torch.empty((1, w["n_params"]), dtype=torch.float64, device="cuda")
-    graph = P.Graph(circ, params, H, psi, lam, energy, grad, mode=args.mode) if args.graph else None
+    run_mode = circ.mode(cdt) if args.mode == "auto" else args.mode
+    graph = P.Graph(circ, params, H, psi, lam, energy, grad, mode=run_mode) if args.graph else None
     nbytes = ctypes.c_size_t()
     P.check(P.lib().tcng_workspace_size(circ.handle, H.handle, 0 if args.dtype == "c64" else 1, 1,
-                                        P.MODES[args.mode], ctypes.byref(nbytes)))
+                                        P.MODES[run_mode], ctypes.byref(nbytes)))
     ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
 
     def one(i):
@@ -328,7 +329,7 @@ def run_per_circuit(args, w, P, torch):
             graph.launch()
         else:
             P.state_init(psi)
-            P.expect_grad(circ, params, H, psi=psi, lam=lam, mode=args.mode, ws=ws)
+            P.expect_grad(circ, params, H, psi=psi, lam=lam, mode=run_mode, ws=ws)
 
     for i in range(min(args.warmup, nsets)):
         one(i)
@@ -345,7 +346,7 @@ def run_per_circuit(args, w, P, torch):
         "metric": "amplitude-updates/s", "value": 3.0 * G * 2 ** n / dt, "unit": "amplitude-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * nsets * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": w["name"], "n_qubits": n, "gates": G, "parameter_sets": nsets, "mode": args.mode,
+        "config": {"workload": w["name"], "n_qubits": n, "gates": G, "parameter_sets": nsets, "mode": run_mode,
                    "graph": bool(args.graph), "parallelism": "single GPU"},
         "evals_per_s": 1.0 / dt, "us_per_eval": dt * 1e6,
     }
@@ -841,10 +842,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="hea28")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--mode", default="fused", choices=["tiled", "plain", "fused"])
+    ap.add_argument("--mode", default="auto", choices=["tiled", "plain", "fused", "fused5", "auto"],
+                    help="auto: the autotuner's choice among the tiled tilings and the 4- / 5-qubit matrix-core plans")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="pick the tiling by timed search first")
+    ap.add_argument("--autotune", action="store_true", help="tiled mode: pick the tiling by timed search first")
     ap.add_argument("--tiling", default=None, help="m,rb,rb_rev (skips the autotuner)")
     ap.add_argument("--graph", action="store_true", help="replay a captured graph per evaluation")
     ap.add_argument("--sets", type=int, default=32, help="parameter sets of the per-circuit workload")
@@ -898,15 +900,22 @@ def main():
     params = torch.tensor(np.asarray(w["params"]).reshape(B, -1), dtype=rdt, device="cuda")
     psi = torch.empty((B, 2 ** n), dtype=cdt, device="cuda")
     lam = torch.empty_like(psi)
-    mode = P.MODES[args.mode]
     tuned = None
     if args.mode == "tiled" and args.tiling:
         circ.configure(cdt, *[int(v) for v in args.tiling.split(",")])
-    elif args.mode == "tiled" and args.autotune:
+    elif args.mode == "auto" or (args.mode == "tiled" and args.autotune):
+        # timed search (untimed here): tilings of the tiled passes and, in
+        # complex64, the 4- and 5-qubit matrix-core plans; cached per shape
+        t0 = time.perf_counter()
         P.state_init(psi)
         cfg, tms = P.autotune(circ, params, H, psi, lam, repeats=3,
                               cache_path=os.path.join(os.environ.get("TMPDIR", "/tmp"), "tcng_autotune.txt"))
-        tuned = {"tiling": list(cfg), "median_ms": round(tms, 3)}
+        tuned = {"mode": circ.mode(cdt), "tiling": list(cfg), "median_ms": round(tms, 3),
+                 "search_s": round(time.perf_counter() - t0, 1)}
+    run_mode = circ.mode(cdt) if args.mode == "auto" else args.mode
+    if args.mode == "tiled" and args.autotune:
+        run_mode = "tiled"
+    mode = P.MODES[run_mode]
     # workspace for the chosen tiling
     nbytes = ctypes.c_size_t()
     P.check(P.lib().tcng_workspace_size(circ.handle, H.handle, 0 if args.dtype == "c64" else 1, B, mode,
@@ -917,14 +926,14 @@ def main():
     if args.graph:
         energy_g = torch.empty(B, dtype=torch.float64, device="cuda")
         grad_g = torch.empty((B, max(w["n_params"], 1)), dtype=torch.float64, device="cuda")
-        graph = P.Graph(circ, params, H, psi, lam, energy_g, grad_g, mode=args.mode)
+        graph = P.Graph(circ, params, H, psi, lam, energy_g, grad_g, mode=run_mode)
 
     def step():
         if graph is not None:
             graph.launch()
             return energy_g, grad_g
         P.state_init(psi)
-        return P.expect_grad(circ, params, H, psi=psi, lam=lam, mode=args.mode, ws=ws)
+        return P.expect_grad(circ, params, H, psi=psi, lam=lam, mode=run_mode, ws=ws)
 
     for _ in range(args.warmup):
         step()
@@ -952,18 +961,19 @@ def main():
     value = amp_updates / dt
     fwd_flops, rev_flops = sweep_flops(w["gates"], n, B)
     roofline = None
-    if args.mode == "fused" and "fused_rev" in fam_stats:
-        # matrix-core work of the block formulation: 8 * 16 flops per amplitude
-        # and block (16 x 16 complex product), three products per block in reverse
-        nblk = P.fused_plan_inspect(n, w["gates"], w["n_params"])[4]
-        blk_flops = 8.0 * 16 * (2 ** n) * B * nblk
+    if run_mode in ("fused", "fused5") and "fused_rev" in fam_stats:
+        # matrix-core work of the block formulation: 8 * 2^k flops per amplitude
+        # and block (2^k x 2^k complex product), three products per block in reverse
+        kb = 5 if run_mode == "fused5" else 4
+        nblk = P.fused_plan_inspect(n, w["gates"], w["n_params"], kb)[4]
+        blk_flops = 8.0 * 2 ** kb * (2 ** n) * B * nblk
         dom = max(("fused_fwd", "fused_rev"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
         L = fam_stats[dom]["launches"] / args.steps
         flops = (3 * blk_flops if dom == "fused_rev" else blk_flops) / L
         roofline = fused_roofline(dom, (rev_flops if dom == "fused_rev" else fwd_flops) / L,
                                   algorithmic_bytes(dom, n, s, B, 0), flops, fam_stats[dom]["avg_ms"])
-        roofline["traffic"] = measured_traffic(w["name"], dom)
-    elif args.mode == "tiled" and "rev_tile" in fam_stats:
+        roofline["traffic"] = measured_traffic(w["name"], dom) if run_mode == "fused" else None
+    elif run_mode == "tiled" and "rev_tile" in fam_stats:
         dom = max(("fwd_tile", "rev_tile"), key=lambda k: fam_stats.get(k, {"total_ms": 0})["total_ms"])
         L = fam_stats[dom]["launches"] / args.steps
         flops = (rev_flops if dom == "rev_tile" else fwd_flops) / L
@@ -988,11 +998,11 @@ def main():
         "dtype": "c64 (f32 state, f64 reductions)" if args.dtype == "c64" else "c128",
         "data": "synthetic",
         "config": {"workload": w["name"], "n_qubits": n, "gates": G, "params": w["n_params"], "batch": B,
-                   "pauli_terms": len(w["coeffs"]), "mode": args.mode, "graph": bool(args.graph),
+                   "pauli_terms": len(w["coeffs"]), "mode": run_mode, "graph": bool(args.graph),
                    "parallelism": "single GPU"},
         "evals_per_s": B / dt,
         "us_per_eval": dt / B * 1e6,
-        "tiling": list(circ.config(cdt)) if args.mode == "tiled" else None,
+        "tiling": list(circ.config(cdt)) if run_mode == "tiled" else None,
         "autotune": tuned,
         "energy0": float(E[0].item()),
         "roofline": roofline,

@@ -65,8 +65,16 @@ enum { TCNG_C64 = 0, TCNG_C128 = 1 };
  *     "Foundations Recap", JIT paragraph); the adjoint sweep accumulates each
  *     block's outer product sum(lambda psi^dagger) and derives every gate
  *     derivative from it.  complex64 states with n >= 9 only; otherwise the
- *     call runs as TCNG_MODE_TILED. */
-enum { TCNG_MODE_TILED = 0, TCNG_MODE_PLAIN = 1, TCNG_MODE_FUSED = 2 };
+ *     call runs as TCNG_MODE_TILED.
+ *   TCNG_MODE_FUSED5: the same with 5-qubit blocks, 32 x 32 block matrices
+ *     (applied as four 16 x 16 sub-block products; one block holds more gates
+ *     and costs twice the matrix-core work per amplitude).  complex64 states
+ *     with n >= 12 only; otherwise the call runs as TCNG_MODE_FUSED.
+ *     tcng_autotune picks among the modes per circuit. */
+enum { TCNG_MODE_TILED = 0, TCNG_MODE_PLAIN = 1, TCNG_MODE_FUSED = 2, TCNG_MODE_FUSED5 = 3, TCNG_MODE_AUTO = 4 };
+/* TCNG_MODE_AUTO: the mode tcng_autotune chose for the circuit and dtype;
+ * before any tuning, TCNG_MODE_FUSED for complex64 and TCNG_MODE_TILED for
+ * complex128. */
 
 /* gate kinds of tcng_gate.kind */
 enum {
@@ -170,18 +178,24 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
 tcng_status tcng_circuit_configure(tcng_circuit* c, int32_t dtype, int32_t m_max, int32_t rb, int32_t rb_rev);
 tcng_status tcng_circuit_get_config(const tcng_circuit* c, int32_t dtype, int32_t* m_max, int32_t* rb,
                                     int32_t* rb_rev);
+/* The mode TCNG_MODE_AUTO runs for this circuit and dtype (after tuning, or
+ * the default), resolved to the plan that exists (never TCNG_MODE_AUTO). */
+tcng_status tcng_circuit_get_mode(const tcng_circuit* c, int32_t dtype, int32_t* mode);
 
 /* Autotuner (the find-then-execute search of contraction strategies, Sec.
- * "Model Parallelism", applied to tilings): times tcng_expect_grad
- * (TCNG_MODE_TILED) for every available
- * tiling of c for this dtype and batch, on the given initial states psi
- * (restored afterwards up to rounding) and scratch lam, keeps the fastest
- * (median of `repeats` runs, ties to the earlier candidate) and configures c
- * with it.  Allocates and frees its own workspace and synchronises; not for
- * the hot path.  params as for tcng_expect_grad.  best_ms (nullable) receives
- * the winner's median time.  If cache_path is not NULL, the choice is looked
- * up in / appended to that text file, keyed by the circuit's structure, dtype,
- * batch and device architecture; a cached choice is applied without timing. */
+ * "Model Parallelism", applied to execution strategies): times
+ * tcng_expect_grad for every available tiling of the tiled passes
+ * (TCNG_MODE_TILED) and, for complex64, the matrix-core passes with 4- and
+ * 5-qubit blocks (TCNG_MODE_FUSED, TCNG_MODE_FUSED5), for this dtype and
+ * batch, on the given initial states psi (restored afterwards up to rounding)
+ * and scratch lam.  The fastest (median of `repeats` runs, ties to the earlier
+ * candidate) becomes the circuit's TCNG_MODE_AUTO for the dtype; the tiled
+ * passes keep their fastest tiling.  Allocates and frees its own workspace and
+ * synchronises; not for the hot path.  params as for tcng_expect_grad.
+ * best_ms (nullable) receives the winner's median time.  If cache_path is not
+ * NULL, the choice is looked up in / appended to that text file, keyed by the
+ * circuit's structure, dtype, batch and device architecture; a cached choice
+ * is applied without timing. */
 tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* params, const tcng_state* psi,
                           const tcng_state* lam, int32_t repeats, const char* cache_path, double* best_ms,
                           void* stream);
@@ -324,19 +338,21 @@ tcng_status tcng_graph_create(const tcng_circuit* c, const void* params, const t
 tcng_status tcng_graph_launch(tcng_graph* g, void* stream);
 tcng_status tcng_graph_destroy(tcng_graph* g);
 
-/* Host-only inspection of the fused planner (TCNG_MODE_FUSED, complex64;
- * gate application as local contraction, Sec. "Foundations Recap").
+/* Host-only inspection of the fused planner (TCNG_MODE_FUSED with
+ * block_bits = 4, TCNG_MODE_FUSED5 with 5; complex64; gate application as
+ * local contraction, Sec. "Foundations Recap").
  * Outputs (host, any may be NULL):
  *   order[n_gates], pass_of[n_gates]  as for tcng_plan_inspect;
- *   block_of[n_gates]                 block (16 x 16 matrix) of gate order[i];
+ *   block_of[n_gates]                 block (2^k x 2^k matrix) of gate order[i];
  *   n_passes, n_blocks;
  *   bad_layouts  number of LDS layouts of the plan that are not bijections of
  *                the tile or that put two lanes of a 32-lane access of the
  *                phases that write or read them on one bank (0 expected).
- * Returns TCNG_E_UNSUPPORTED when the fused path does not apply (n < 9). */
+ * Returns TCNG_E_UNSUPPORTED when the fused path does not apply (n < 9, or
+ * n < 12 for 5-qubit blocks); TCNG_E_INVALID for block_bits other than 4, 5. */
 tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
-                                    int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
-                                    int32_t* n_blocks, int32_t* bad_layouts);
+                                    int32_t block_bits, int32_t* order, int32_t* pass_of, int32_t* block_of,
+                                    int32_t* n_passes, int32_t* n_blocks, int32_t* bad_layouts);
 
 /* SU(4) brick-wall QML training step (Sec. "End-to-End Pure QML for Computer
  * Vision"): every sample starts from its amplitude-encoded input, the gates of

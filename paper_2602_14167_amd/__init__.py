@@ -17,14 +17,17 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_FUSED, TCNG_MODE_PLAIN, TCNG_MODE_TILED, TCNG_U1_KIND,  # noqa: F401
+from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_AUTO, TCNG_MODE_FUSED, TCNG_MODE_FUSED5,  # noqa: F401
+                   TCNG_MODE_PLAIN, TCNG_MODE_TILED, TCNG_U1_KIND,
                    TcngError, TcngGate, TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "expect_grad_noalloc", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
            "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
            "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots", "qml_step"]
 
-MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED}
+MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED, "fused5": TCNG_MODE_FUSED5,
+         "auto": TCNG_MODE_AUTO}
+MODE_NAMES = {v: k for k, v in MODES.items()}
 
 
 def _mode(mode):
@@ -125,6 +128,12 @@ class Circuit:
         check(lib().tcng_circuit_get_config(self.handle, _dt(dtype), *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
+    def mode(self, dtype=torch.complex64):
+        """Name of the mode "auto" runs for this dtype (the autotuner's choice, or the default)."""
+        v = ctypes.c_int32()
+        check(lib().tcng_circuit_get_mode(self.handle, _dt(dtype), ctypes.byref(v)))
+        return MODE_NAMES[v.value]
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib._lib is not None:
@@ -137,7 +146,10 @@ def _dt(dtype):
 
 
 def autotune(circ, params, H, psi, lam=None, repeats=3, cache_path=None):
-    """Pick the fastest tiling for this circuit, dtype and batch (see tcng_autotune)."""
+    """Pick the fastest execution mode (tilings of the tiled passes, matrix-core
+    passes with 4- or 5-qubit blocks) for this circuit, dtype and batch (see
+    tcng_autotune); circ.mode(dtype) names the choice, which mode="auto" runs.
+    Returns (tiling of the tiled passes, the winner's median ms)."""
     s = _state(psi, circ.n)
     if lam is None:
         lam = torch.empty_like(psi)
@@ -426,16 +438,16 @@ def plan_inspect(n, gates, n_params, dtype=torch.complex64):
     return order[:G] if k else None, pass_of[:G] if k else None, masks[:k]
 
 
-def fused_plan_inspect(n, gates, n_params):
-    """Host-only view of the fused schedule (complex64 matrix-core blocks):
-    (order, pass_of, block_of, n_passes, n_blocks, bad_layouts)."""
+def fused_plan_inspect(n, gates, n_params, block_bits=4):
+    """Host-only view of the fused schedule (complex64 matrix-core blocks of
+    block_bits = 4 or 5 qubits): (order, pass_of, block_of, n_passes, n_blocks, bad_layouts)."""
     g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 6))
     G = g.shape[0]
     order = np.zeros(max(G, 1), np.int32)
     pass_of = np.zeros(max(G, 1), np.int32)
     block_of = np.zeros(max(G, 1), np.int32)
     npass, nblk, bad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    check(lib().tcng_fused_plan_inspect(int(n), g.ctypes.data_as(ctypes.c_void_p), G, int(n_params),
+    check(lib().tcng_fused_plan_inspect(int(n), g.ctypes.data_as(ctypes.c_void_p), G, int(n_params), int(block_bits),
                                         order.ctypes.data_as(ctypes.c_void_p), pass_of.ctypes.data_as(ctypes.c_void_p),
                                         block_of.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass),
                                         ctypes.byref(nblk), ctypes.byref(bad)))

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libtcng.so")
 
 TCNG_OK, TCNG_E_INVALID, TCNG_E_UNSUPPORTED, TCNG_E_WORKSPACE, TCNG_E_HIP, TCNG_E_ALLOC = range(6)
 TCNG_C64, TCNG_C128 = 0, 1
-TCNG_MODE_TILED, TCNG_MODE_PLAIN, TCNG_MODE_FUSED = 0, 1, 2
+TCNG_MODE_TILED, TCNG_MODE_PLAIN, TCNG_MODE_FUSED, TCNG_MODE_FUSED5, TCNG_MODE_AUTO = 0, 1, 2, 3, 4
 TCNG_U1_KIND = 12   # constant one-qubit gate (top-left 2 x 2 block of its matrix)
 
 # every function include/tcng.h declares
@@ -27,7 +27,7 @@ EXPORTS = [
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
     "tcng_shadow_workspace_size", "tcng_shadow_snapshots", "tcng_qml_workspace_size", "tcng_qml_step",
-    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes",
+    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes", "tcng_circuit_get_mode",
 ]
 
 
@@ -80,6 +80,7 @@ def lib():
     L.tcng_expect_grad_multi.argtypes = [P, P, i32, P, PS, PS, P, P, P, P, sz, P]
     L.tcng_circuit_configure.argtypes = [P, i32, i32, i32, i32]
     L.tcng_circuit_get_config.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.tcng_circuit_get_mode.argtypes = [P, i32, ctypes.POINTER(i32)]
     L.tcng_autotune.argtypes = [P, P, P, PS, PS, i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), P]
     L.tcng_profile_begin.argtypes = [i32]
     L.tcng_profile_query.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -88,7 +89,7 @@ def lib():
     L.tcng_graph_create.argtypes = [P, P, P, PS, PS, P, P, P, i32, P, sz, i64, ctypes.POINTER(P)]
     L.tcng_graph_launch.argtypes = [P, P]
     L.tcng_graph_destroy.argtypes = [P]
-    L.tcng_fused_plan_inspect.argtypes = [i32, P, i32, i32, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+    L.tcng_fused_plan_inspect.argtypes = [i32, P, i32, i32, i32, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
     L.tcng_apply_pauli.argtypes = [PS, P, PS, P, i32, P, sz, P]
     L.tcng_pauli_coo_info.argtypes = [P, ctypes.POINTER(i32)]

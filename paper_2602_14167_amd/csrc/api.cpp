@@ -157,6 +157,13 @@ void free_fused(DevFusedPlan& P) {
 // fused passes: tile bits and low qubits (complex64 only)
 constexpr int FUSED_M = 12, FUSED_LO = 4;
 bool fused_ok(int n, int dtype) { return dtype == TCNG_C64 && n >= FUSED_K + 5; }
+// 32 x 32 blocks: full 12-bit tiles only
+bool fused5_ok(int n, int dtype) { return dtype == TCNG_C64 && n >= FUSED_M; }
+bool valid_mode(int mode) {
+    return mode == TCNG_MODE_TILED || mode == TCNG_MODE_PLAIN || mode == TCNG_MODE_FUSED || mode == TCNG_MODE_FUSED5 ||
+           mode == TCNG_MODE_AUTO;
+}
+bool is_fused_mode(int mode) { return mode == TCNG_MODE_FUSED || mode == TCNG_MODE_FUSED5; }
 
 void free_plan(DevCircuitPlan& P) {
     (void)hipFree(P.passes);
@@ -184,7 +191,9 @@ struct tcng_circuit {
     std::vector<int> plain_slot;               // first slot per gate (plain path), -1 none
     SlotTables plain;
     DevCircuitPlan tiled[2];
-    DevFusedPlan fused;              // complex64 matrix-core plan
+    DevFusedPlan fused;              // complex64 matrix-core plan (16 x 16 blocks)
+    DevFusedPlan fused5;             // the same with 32 x 32 blocks (n >= 12)
+    int tuned_mode[2] = {-1, -1};    // per dtype: the mode tcng_autotune chose (-1: not tuned)
     // n < FUSED_M: the same gates planned on FUSED_M qubits, so that 2^(FUSED_M - n)
     // contiguous batch members fill one tile (the extra index bits select the member)
     DevFusedPlan fused_wide;
@@ -245,9 +254,9 @@ tcng_status make_plan(tcng_circuit* c, int dt, const TileConfig& cfg) {
     return TCNG_OK;
 }
 
-tcng_status make_fused(tcng_circuit* c, int nq, DevFusedPlan& out) {
+tcng_status make_fused(tcng_circuit* c, int nq, DevFusedPlan& out, int kb = FUSED_K) {
     DevFusedPlan P;
-    std::string why = plan_fused(nq, c->gates, c->n_params, FUSED_M, FUSED_LO, P.host);
+    std::string why = plan_fused(nq, c->gates, c->n_params, FUSED_M, FUSED_LO, P.host, kb);
     if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "fused planner: " + why);
     if (upload(P.host.passes, &P.passes) != hipSuccess || upload(P.host.phases, &P.phases) != hipSuccess ||
         upload(P.host.rpasses, &P.rpasses) != hipSuccess || upload(P.host.rphases, &P.rphases) != hipSuccess ||
@@ -303,6 +312,7 @@ int pauli_wgs_plain(int n, int64_t batch) {
 
 struct WsLayout {
     bool fused = false;
+    int fk = FUSED_K;                        // fused: block bits of the plan
     size_t fmats_off = 0, fmats_bytes = 0;   // fused: block matrices
     size_t opart_off = 0, opart_bytes = 0;   // fused: outer products per workgroup
     size_t osum_off = 0, osum_bytes = 0;     // fused: outer products summed
@@ -330,30 +340,42 @@ void finish_layout(WsLayout& L, int64_t batch) {
 
 bool use_tiled(int mode, int n, int dtype) { return mode == TCNG_MODE_TILED && tiled_ok(n, dtype); }
 
-// the mode a call runs in: FUSED needs a complex64 circuit with a fused plan
+// the mode a call runs in: FUSED needs a complex64 circuit with a fused plan;
+// FUSED5 one with a 32 x 32-block plan, else it runs as FUSED
 int run_mode(int mode, const tcng_circuit* c, int dtype) {
+    if (mode == TCNG_MODE_AUTO)
+        mode = (c && c->tuned_mode[dtype] >= 0) ? c->tuned_mode[dtype]
+                                                  : (dtype == TCNG_C64 ? TCNG_MODE_FUSED : TCNG_MODE_TILED);
+    if (mode == TCNG_MODE_FUSED5) {
+        if (c && dtype == TCNG_C64 && c->fused5.valid) return TCNG_MODE_FUSED5;
+        mode = TCNG_MODE_FUSED;
+    }
     if (mode != TCNG_MODE_FUSED) return mode;
     return (c && dtype == TCNG_C64 && c->fused.valid) ? TCNG_MODE_FUSED : TCNG_MODE_TILED;
 }
 
-// fused reverse: one 512-thread workgroup per CU, looping over tiles
-int fused_wgs(int n, int m, int64_t batch) {
+const DevFusedPlan& fused_plan(const tcng_circuit* c, int kb) { return kb == 5 ? c->fused5 : c->fused; }
+
+// fused reverse: two workgroups per CU (one with 32 x 32 blocks), looping over tiles
+int fused_wgs(int n, int m, int64_t batch, int kb = FUSED_K) {
     const int64_t tiles = int64_t(1) << (n - m);
-    const int64_t cap = std::max<int64_t>(1, ceil_div(512, batch));
+    const int64_t cap = std::max<int64_t>(1, ceil_div(kb == 5 ? 256 : 512, batch));
     return int(std::min(tiles, cap));
 }
 
 WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype, int64_t batch, int mode) {
     WsLayout L;
     const bool tiled = use_tiled(mode, n, dtype);
-    if (c && mode == TCNG_MODE_FUSED) {
-        const FusedPlan& F = c->fused.host;
+    if (c && is_fused_mode(mode)) {
+        const FusedPlan& F = fused_plan(c, mode == TCNG_MODE_FUSED5 ? 5 : FUSED_K).host;
+        const size_t sub = F.k == 5 ? 4 : 1;   // 16 x 16 sub-blocks per block
         L.fused = true;
+        L.fk = F.k;
         L.total_slots = F.total_slots;
-        L.rev_wgs = fused_wgs(n, F.m, batch);
-        L.fmats_bytes = size_t(batch) * F.n_blocks * 2048 * sizeof(float);
-        L.opart_bytes = size_t(batch) * F.n_blocks * size_t(L.rev_wgs) * 512 * sizeof(double);
-        L.osum_bytes = size_t(batch) * F.n_blocks * 512 * sizeof(double);
+        L.rev_wgs = fused_wgs(n, F.m, batch, F.k);
+        L.fmats_bytes = size_t(batch) * F.n_blocks * 2048 * sub * sizeof(float);
+        L.opart_bytes = size_t(batch) * F.n_blocks * size_t(L.rev_wgs) * 512 * sub * sizeof(double);
+        L.osum_bytes = size_t(batch) * F.n_blocks * 512 * sub * sizeof(double);
         L.part_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1)) * sizeof(double);
     } else if (c) {
         if (tiled)
@@ -379,7 +401,7 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
 
 // the Pauli passes run tiled unless the mode is plain or the tiled Pauli plan is impossible
 int pauli_mode(int mode, const tcng_pauli_sum* h, int n, int dt) {
-    const int m = mode == TCNG_MODE_FUSED ? TCNG_MODE_TILED : mode;
+    const int m = is_fused_mode(mode) ? TCNG_MODE_TILED : mode;
     return (use_tiled(m, n, dt) && !h->tiled_valid[dt]) ? TCNG_MODE_PLAIN : m;
 }
 
@@ -423,7 +445,7 @@ Job make_job(const tcng_circuit* c, const tcng_pauli_sum* h, const tcng_state* s
         J.tiles = int64_t(1) << (s->n_qubits - std::min(s->n_qubits, P.host.cfg.m_max));
     }
     if (c && L.fused) {
-        const DevFusedPlan& F = c->fused;
+        const DevFusedPlan& F = fused_plan(c, L.fk);
         J.fpasses = F.passes;
         J.fphases = F.phases;
         J.frpasses = F.rpasses;
@@ -555,13 +577,13 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
 // fused: block matrices (forward operand order, and the reverse one when
 // gradients follow), then the forward passes
 tcng_status run_forward_fused(const tcng_circuit* c, const void* params, const tcng_state* s, const Job& J,
-                              bool want_rev, hipStream_t st) {
-    const DevFusedPlan& F = c->fused;
+                              bool want_rev, hipStream_t st, int kb) {
+    const DevFusedPlan& F = fused_plan(c, kb);
     PROF_TRY(F_FUSED_GRAD, launch_fused_mats(F.phases, F.ops, F.host.n_blocks, params, c->n_params, c->cm[0], 0,
-                                             s->batch, const_cast<void*>(J.fmats), want_rev, st));
+                                             s->batch, const_cast<void*>(J.fmats), want_rev, st, kb));
     for (size_t p = 0; p < F.host.passes.size(); ++p) {
         const JobList jl{nullptr, nullptr, 0, int32_t(p)};
-        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st));
+        PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, J, F.host.m, J.tiles * J.batch, st, kb));
     }
     return TCNG_OK;
 }
@@ -569,15 +591,15 @@ tcng_status run_forward_fused(const tcng_circuit* c, const void* params, const t
 // fused adjoint sweep: passes in reverse, then gradient slots from the block outer products
 tcng_status run_reverse_fused(const tcng_circuit* c, const void* params, const tcng_state* psi, const WsLayout& L,
                               double* part, double* osum, const Job& J, hipStream_t st) {
-    const DevFusedPlan& F = c->fused;
+    const DevFusedPlan& F = fused_plan(c, L.fk);
     const int np = int(F.host.passes.size());
     for (int k = 0; k < np; ++k) {
         const JobList jl{nullptr, nullptr, 0, int32_t(k)};
-        PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, J, F.host.m, int64_t(J.wgs) * J.batch, st));
+        PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, J, F.host.m, int64_t(J.wgs) * J.batch, st, L.fk));
     }
     if (L.total_slots > 0)
         PROF_TRY(F_FUSED_GRAD, launch_fused_grad(F.phases, F.ops, F.host.n_blocks, params, c->n_params, c->cm[0],
-                                                 psi->batch, J.opart, J.wgs, osum, L.total_slots, part, st));
+                                                 psi->batch, J.opart, J.wgs, osum, L.total_slots, part, st, L.fk));
     return TCNG_OK;
 }
 
@@ -719,6 +741,8 @@ tcng_status tcng_circuit_create(int32_t n_qubits, const tcng_gate* gates, int32_
         if (n_qubits < FUSED_M)
             if (tcng_status e = make_fused(c, FUSED_M, c->fused_wide)) return cleanup(e);
     }
+    if (fused5_ok(n_qubits, TCNG_C64))
+        if (tcng_status e = make_fused(c, n_qubits, c->fused5, 5)) return cleanup(e);
     *out = c;
     return ok();
 }
@@ -737,6 +761,7 @@ tcng_status tcng_circuit_destroy(tcng_circuit* c) {
     (void)hipFree(c->plain.gate_slot);
     for (auto& P : c->tiled) free_plan(P);
     free_fused(c->fused);
+    free_fused(c->fused5);
     free_fused(c->fused_wide);
     delete c;
     return ok();
@@ -856,16 +881,15 @@ tcng_status tcng_workspace_size(const tcng_circuit* c, const tcng_pauli_sum* h, 
     if (!bytes) return fail(TCNG_E_INVALID, "null output");
     if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
     if (batch < 1) return fail(TCNG_E_INVALID, "batch < 1");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
-        return fail(TCNG_E_INVALID, "bad mode");
+    if (!valid_mode(mode)) return fail(TCNG_E_INVALID, "bad mode");
     const int n = c ? c->n : (h ? h->n : 0);
     if (!n) return fail(TCNG_E_INVALID, "need a circuit or a Pauli sum");
     if (c && h && c->n != h->n) return fail(TCNG_E_INVALID, "circuit and Pauli sum differ in qubit count");
     mode = run_mode(mode, c, dtype);
     if (!c || !h) {
-        if (h && use_tiled(mode == TCNG_MODE_FUSED ? TCNG_MODE_TILED : mode, n, dtype) && !h->tiled_valid[dtype])
+        if (h && use_tiled(is_fused_mode(mode) ? TCNG_MODE_TILED : mode, n, dtype) && !h->tiled_valid[dtype])
             mode = TCNG_MODE_PLAIN;
-        *bytes = layout(c, h, n, dtype, batch, (!c && mode == TCNG_MODE_FUSED) ? TCNG_MODE_TILED : mode).total;
+        *bytes = layout(c, h, n, dtype, batch, (!c && is_fused_mode(mode)) ? TCNG_MODE_TILED : mode).total;
         return ok();
     }
     *bytes = grad_layout(c, h, n, dtype, batch, mode).total;
@@ -876,8 +900,7 @@ tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tc
                              size_t ws_bytes, void* stream) {
     if (tcng_status e = check_state(s, "tcng_run_circuit")) return e;
     if (tcng_status e = check_circuit_state(c, s, params)) return e;
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
-        return fail(TCNG_E_INVALID, "bad mode");
+    if (!valid_mode(mode)) return fail(TCNG_E_INVALID, "bad mode");
     mode = run_mode(mode, c, s->dtype);
     const WsLayout L = layout(c, nullptr, s->n_qubits, s->dtype, s->batch, mode);
     const bool tiled = use_tiled(mode, s->n_qubits, s->dtype);
@@ -887,7 +910,7 @@ tcng_status tcng_run_circuit(const tcng_circuit* c, const void* params, const tc
     if (L.fused) {
         Job J = make_job(c, nullptr, s, nullptr, nullptr, nullptr, nullptr, L);
         J.fmats = static_cast<char*>(ws) + L.fmats_off;
-        const tcng_status e = run_forward_fused(c, params, s, J, false, st);
+        const tcng_status e = run_forward_fused(c, params, s, J, false, st, L.fk);
         return e ? e : ok();
     }
     void* opm = tiled ? static_cast<char*>(ws) + L.opm_off : nullptr;
@@ -908,8 +931,7 @@ tcng_status tcng_expect_pauli(const tcng_state* s, const tcng_pauli_sum* h, doub
     if (tcng_status e = check_state(s, "tcng_expect_pauli")) return e;
     if (!h || !out) return fail(TCNG_E_INVALID, "null Pauli sum or output");
     if (h->n != s->n_qubits) return fail(TCNG_E_INVALID, "Pauli sum and state differ in qubit count");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
-        return fail(TCNG_E_INVALID, "bad mode");
+    if (!valid_mode(mode)) return fail(TCNG_E_INVALID, "bad mode");
     mode = pauli_mode(mode, h, h->n, s->dtype);
     const WsLayout L = layout(nullptr, h, s->n_qubits, s->dtype, s->batch, mode);
     if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
@@ -935,8 +957,7 @@ tcng_status tcng_apply_pauli(const tcng_state* psi, const tcng_pauli_sum* h, con
         out->stride != psi->stride)
         return fail(TCNG_E_INVALID, "output state must match the input's qubits, dtype, batch and stride");
     if (out->amps == psi->amps) return fail(TCNG_E_INVALID, "the output must not alias the input state");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
-        return fail(TCNG_E_INVALID, "bad mode");
+    if (!valid_mode(mode)) return fail(TCNG_E_INVALID, "bad mode");
     mode = pauli_mode(mode, h, h->n, psi->dtype);
     const WsLayout L = layout(nullptr, h, psi->n_qubits, psi->dtype, psi->batch, mode);
     if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
@@ -990,8 +1011,7 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
     if (lam->amps == psi->amps) return fail(TCNG_E_INVALID, "psi and lam must not alias");
     if (!energy) return fail(TCNG_E_INVALID, "null energy output");
     if (c->n_params > 0 && !grad) return fail(TCNG_E_INVALID, "null gradient output");
-    if (mode != TCNG_MODE_TILED && mode != TCNG_MODE_PLAIN && mode != TCNG_MODE_FUSED)
-        return fail(TCNG_E_INVALID, "bad mode");
+    if (!valid_mode(mode)) return fail(TCNG_E_INVALID, "bad mode");
     const int dt = psi->dtype;
     mode = run_mode(mode, c, dt);
     const int pmode = pauli_mode(mode, h, h->n, dt);
@@ -1006,11 +1026,11 @@ tcng_status tcng_expect_grad(const tcng_circuit* c, const void* params, const tc
         Job J = make_job(c, h, psi, lam->amps, nullptr, part, epart, L);
         J.fmats = w + L.fmats_off;
         J.opart = reinterpret_cast<double*>(w + L.opart_off);
-        tcng_status e = run_forward_fused(c, params, psi, J, true, st);
+        tcng_status e = run_forward_fused(c, params, psi, J, true, st, L.fk);
         if (!e) e = run_pauli<float, PAULI_RB>(h, psi, lam->amps, L, epart, pmode, J, st);
         if (!e) e = run_reverse_fused(c, params, psi, L, part, reinterpret_cast<double*>(w + L.osum_off), J, st);
         if (e) return e;
-        const SlotTables& S = c->fused.slots;
+        const SlotTables& S = fused_plan(c, L.fk).slots;
         PROF_TRY(F_FINISH, launch_finish(L.total_slots > 0 ? part : nullptr, std::max(L.total_slots, 1), 1, S.ptr,
                                          S.idx, c->n_params, epart, L.e_rows, L.e_wgs, psi->batch, energy, grad,
                                          gate_grad, S.gate_slot, c->u2m[dt], c->gate_mat, int(c->gates.size()), red,
@@ -1106,8 +1126,9 @@ tcng_status tcng_graph_destroy(tcng_graph* g) {
 }
 
 tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
-                                    int32_t* order, int32_t* pass_of, int32_t* block_of, int32_t* n_passes,
-                                    int32_t* n_blocks, int32_t* bad_layouts) {
+                                    int32_t block_bits, int32_t* order, int32_t* pass_of, int32_t* block_of,
+                                    int32_t* n_passes, int32_t* n_blocks, int32_t* bad_layouts) {
+    if (block_bits != 4 && block_bits != 5) return fail(TCNG_E_INVALID, "block bits must be 4 or 5");
     if (n_qubits < 1 || n_qubits > MAX_QUBITS) return fail(TCNG_E_UNSUPPORTED, "n_qubits out of range");
     if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(TCNG_E_INVALID, "bad gate list");
     for (int i = 0; i < n_gates; ++i) {
@@ -1120,9 +1141,11 @@ tcng_status tcng_fused_plan_inspect(int32_t n_qubits, const tcng_gate* gates, in
             return fail(TCNG_E_INVALID, "gate " + std::to_string(i) + ": parameter index out of range");
     }
     if (!fused_ok(n_qubits, TCNG_C64)) return fail(TCNG_E_UNSUPPORTED, "fused path needs n >= 9");
+    if (block_bits == 5 && !fused5_ok(n_qubits, TCNG_C64))
+        return fail(TCNG_E_UNSUPPORTED, "5-qubit blocks need n >= 12");
     FusedPlan P;
     std::vector<tcng_gate> g(gates, gates + n_gates);
-    std::string why = plan_fused(n_qubits, g, n_params, FUSED_M, FUSED_LO, P);
+    std::string why = plan_fused(n_qubits, g, n_params, FUSED_M, FUSED_LO, P, block_bits);
     if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "fused planner: " + why);
     int k = 0;
     for (size_t p = 0; p < P.passes.size(); ++p)
@@ -1895,14 +1918,46 @@ std::string circuit_key(const tcng_circuit* c, int dtype, int64_t batch) {
 
 }  // namespace
 
+tcng_status tcng_circuit_get_mode(const tcng_circuit* c, int32_t dtype, int32_t* mode) {
+    if (!c || !mode) return fail(TCNG_E_INVALID, "null argument");
+    if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
+    *mode = run_mode(TCNG_MODE_AUTO, c, dtype);
+    return ok();
+}
+
 tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* params, const tcng_state* psi,
                           const tcng_state* lam, int32_t repeats, const char* cache_path, double* best_ms,
                           void* stream) {
     if (!c || !h || !psi || !lam) return fail(TCNG_E_INVALID, "null argument");
     if (tcng_status e = check_state(psi, "tcng_autotune(psi)")) return e;
     const int dt = psi->dtype;
-    if (!c->tiled[dt].valid) return ok();   // plain path only: nothing to tune
     if (repeats < 1) repeats = 1;
+    // candidates: every tiling of the tiled passes, then the matrix-core plans
+    // with 4- and 5-qubit blocks (complex64)
+    struct Cand {
+        int mode;
+        TileConfig t;
+    };
+    std::vector<Cand> cands;
+    const TileConfig cur = c->tiled[dt].host.cfg;
+    if (c->tiled[dt].valid) {
+        const TileConfig def = tile_config(dt);
+        const int rbs64[2] = {5, 4}, rbs128[2] = {4, 3};
+        const int* rbs = dt == TCNG_C64 ? rbs64 : rbs128;
+        for (int dm = 0; dm <= 1; ++dm)
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    TileConfig t = def;
+                    t.m_max = def.m_max - dm;
+                    t.rb = rbs[i];
+                    t.rb_rev = rbs[j];
+                    if (config_ok(t, dt) && std::min(c->n, t.m_max) >= std::max(t.rb, t.rb_rev) + 6)
+                        cands.push_back({TCNG_MODE_TILED, t});
+                }
+    }
+    if (dt == TCNG_C64 && c->fused.valid) cands.push_back({TCNG_MODE_FUSED, cur});
+    if (dt == TCNG_C64 && c->fused5.valid) cands.push_back({TCNG_MODE_FUSED5, cur});
+    if (cands.empty()) return ok();   // plain path only: nothing to tune
     const std::string key = circuit_key(c, dt, psi->batch);
     if (cache_path) {
         std::ifstream in(cache_path);
@@ -1910,28 +1965,19 @@ tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* 
         while (std::getline(in, line)) {
             const size_t bar = line.find(" | ");
             if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-            int m = 0, rb = 0, rr = 0;
+            int m = 0, rb = 0, rr = 0, md = TCNG_MODE_TILED;
             double ms = 0;
-            if (std::sscanf(line.c_str() + bar + 3, "%d %d %d %lf", &m, &rb, &rr, &ms) == 4) {
+            const int got = std::sscanf(line.c_str() + bar + 3, "%d %d %d %lf %d", &m, &rb, &rr, &ms, &md);
+            if (got >= 4) {
                 if (best_ms) *best_ms = ms;
-                return tcng_circuit_configure(c, dt, m, rb, rr);
+                if (c->tiled[dt].valid)
+                    if (tcng_status e = tcng_circuit_configure(c, dt, m, rb, rr)) return e;
+                c->tuned_mode[dt] = (got == 5 && valid_mode(md) && md != TCNG_MODE_AUTO) ? md : TCNG_MODE_TILED;
+                return ok();
             }
         }
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const TileConfig def = tile_config(dt);
-    std::vector<TileConfig> cands;
-    const int rbs64[2] = {5, 4}, rbs128[2] = {4, 3};
-    const int* rbs = dt == TCNG_C64 ? rbs64 : rbs128;
-    for (int dm = 0; dm <= 1; ++dm)
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
-                TileConfig t = def;
-                t.m_max = def.m_max - dm;
-                t.rb = rbs[i];
-                t.rb_rev = rbs[j];
-                if (config_ok(t, dt) && std::min(c->n, t.m_max) >= std::max(t.rb, t.rb_rev) + 6) cands.push_back(t);
-            }
     // the initial states are overwritten by each run's reverse sweep: keep a copy
     const size_t state_bytes = size_t(psi->batch) * psi->stride * (dt == TCNG_C64 ? 8 : 16);
     void* save = nullptr;
@@ -1944,20 +1990,22 @@ tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* 
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    double best = 1e300;
-    TileConfig best_cfg = c->tiled[dt].host.cfg;
+    double best = 1e300, best_tiled = 1e300;
+    Cand best_c = cands[0];
+    TileConfig best_t = cur;
     tcng_status err = TCNG_OK;
-    for (const TileConfig& t : cands) {
-        if ((err = tcng_circuit_configure(c, dt, t.m_max, t.rb, t.rb_rev))) break;
+    for (const Cand& cd : cands) {
+        if (cd.mode == TCNG_MODE_TILED && (err = tcng_circuit_configure(c, dt, cd.t.m_max, cd.t.rb, cd.t.rb_rev)))
+            break;
         size_t wsb = 0;
-        if ((err = tcng_workspace_size(c, h, dt, psi->batch, TCNG_MODE_TILED, &wsb))) break;
+        if ((err = tcng_workspace_size(c, h, dt, psi->batch, cd.mode, &wsb))) break;
         void* ws = nullptr;
         if (hipMalloc(&ws, wsb) != hipSuccess) { err = fail(TCNG_E_ALLOC, "autotune workspace"); break; }
         std::vector<double> times;
         for (int r = 0; r <= repeats && !err; ++r) {   // run 0 is a warm-up
             (void)hipMemcpyAsync(psi->amps, save, state_bytes, hipMemcpyDeviceToDevice, st);
             (void)hipEventRecord(e0, st);
-            err = tcng_expect_grad(c, params, h, psi, lam, energy, grad, nullptr, TCNG_MODE_TILED, ws, wsb, stream);
+            err = tcng_expect_grad(c, params, h, psi, lam, energy, grad, nullptr, cd.mode, ws, wsb, stream);
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1968,7 +2016,8 @@ tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* 
         if (err) break;
         std::sort(times.begin(), times.end());
         const double med = times[times.size() / 2];
-        if (med < best) { best = med; best_cfg = t; }
+        if (med < best) { best = med; best_c = cd; }
+        if (cd.mode == TCNG_MODE_TILED && med < best_tiled) { best_tiled = med; best_t = cd.t; }
     }
     (void)hipMemcpyAsync(psi->amps, save, state_bytes, hipMemcpyDeviceToDevice, st);
     (void)hipStreamSynchronize(st);
@@ -1978,11 +2027,16 @@ tcng_status tcng_autotune(tcng_circuit* c, const tcng_pauli_sum* h, const void* 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err) return err;
-    if (tcng_status e = tcng_circuit_configure(c, dt, best_cfg.m_max, best_cfg.rb, best_cfg.rb_rev)) return e;
+    // the tiled passes keep their fastest tiling also when another mode wins
+    const TileConfig keep = best_t;
+    if (c->tiled[dt].valid)
+        if (tcng_status e = tcng_circuit_configure(c, dt, keep.m_max, keep.rb, keep.rb_rev)) return e;
+    c->tuned_mode[dt] = best_c.mode;
     if (best_ms) *best_ms = best;
     if (cache_path) {
         std::ofstream out(cache_path, std::ios::app);
-        out << key << " | " << best_cfg.m_max << " " << best_cfg.rb << " " << best_cfg.rb_rev << " " << best << "\n";
+        out << key << " | " << keep.m_max << " " << keep.rb << " " << keep.rb_rev << " " << best << " " << best_c.mode
+            << "\n";
     }
     return ok();
 }

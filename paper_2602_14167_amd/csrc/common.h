@@ -120,21 +120,26 @@ struct Pass {
 // chosen by the planner so that the 32-lane accesses of both the phase that
 // writes a layout and the phase that reads it hit distinct banks).
 // ---------------------------------------------------------------------------
+// A plan uses one block width for all its phases: FUSED_K = 4 (16 x 16 blocks,
+// the default), or 5 (32 x 32 blocks, each applied as its four 16 x 16
+// sub-blocks: the top block bit selects the half of a column).
 constexpr int FUSED_K = 4;
+constexpr int FUSED_KMAX = 5;
 constexpr int FUSED_MAX_BLOCKS = 8;    // blocks per fused pass (outer-product accumulators in LDS)
+constexpr int FUSED5_MAX_BLOCKS = 4;   // the same for 32 x 32 blocks (8 accumulated entries per thread and block)
 
 struct FPhase {
     int32_t op_begin, op_end;      // gates of the block, circuit order (Op.r0/r1 = bit of j)
-    int32_t R[FUSED_K];
+    int32_t R[FUSED_KMAX];         // local bit of block bit t (t < k)
     int32_t C[9];                  // local bit of column bit k (-1 beyond the tile)
     int32_t rd[MAX_TILE_BITS];     // layout this phase reads
     int32_t wr[MAX_TILE_BITS];     // layout this phase writes
     int32_t block;                 // index of the block (matrix table, outer-product sums)
-    int32_t pad;
+    int32_t k;                     // block bits (4 or 5)
     // the layouts resolved at the bits the kernels need (no dependent lookups
     // on the device): images of column bit k (0 where C[k] < 0) and of block bit t
     int32_t rdc[9], wrc[9];
-    int32_t rdr[FUSED_K], wrr[FUSED_K];
+    int32_t rdr[FUSED_KMAX], wrr[FUSED_KMAX];
 };
 
 struct FPass {

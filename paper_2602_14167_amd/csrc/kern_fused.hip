@@ -160,7 +160,7 @@ __device__ __forceinline__ void ftile_load_proj(float2* lds, gptr<cx<float>> st,
 struct FView {
     uint32_t rd_col, wr_col;   // column ct * 32 + lane % 32
     uint32_t wr_tile;          // column ct * 32 (write layout)
-    uint32_t rdR[FUSED_K], wrR[FUSED_K], wrC[5];
+    uint32_t rdR[FUSED_KMAX], wrR[FUSED_KMAX], wrC[5];   // block bit 4: 32 x 32 blocks only
 };
 
 __device__ __forceinline__ FView fview(cptr<FPhase> F, int ct, int lane) {
@@ -183,7 +183,7 @@ __device__ __forceinline__ FView fview(cptr<FPhase> F, int ct, int lane) {
     v.wr_col = wl ^ ww;
     v.wr_tile = ww;
 #pragma unroll
-    for (int t = 0; t < FUSED_K; ++t) {
+    for (int t = 0; t < FUSED_KMAX; ++t) {
         v.rdR[t] = uint32_t(F->rdr[t]);
         v.wrR[t] = uint32_t(F->wrr[t]);
     }
@@ -191,9 +191,10 @@ __device__ __forceinline__ FView fview(cptr<FPhase> F, int ct, int lane) {
 }
 
 // the lane's MFMA input: components 2 s + h (s = 0..15) of its column,
-// i.e. the 8 amplitudes with block index j = 2 s' + h (re for s < 8, im after)
-__device__ __forceinline__ void read_cols(const float2* lds, const FView& v, int h, float* x) {
-    const uint32_t base = v.rd_col ^ (v.rdR[0] & (0u - uint32_t(h)));
+// i.e. the 8 amplitudes with block index j = 2 s' + h (re for s < 8, im after);
+// `half` is the image of the top block bit of a 32 x 32 block's half (0 otherwise)
+__device__ __forceinline__ void read_cols(const float2* lds, const FView& v, int h, float* x, uint32_t half = 0u) {
+    const uint32_t base = v.rd_col ^ (v.rdR[0] & (0u - uint32_t(h))) ^ half;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const uint32_t a = base ^ ((s & 1) ? v.rdR[1] : 0u) ^ ((s & 2) ? v.rdR[2] : 0u) ^ ((s & 4) ? v.rdR[3] : 0u);
@@ -224,25 +225,31 @@ __device__ __forceinline__ void read_mat(gptr<const float> tbl, int lane, float*
 struct FWork {
     int nwv, ctw, nthr;
 };
-__device__ __forceinline__ FWork fwork(int m) {
+__device__ __forceinline__ FWork fwork(int m, int kb = FUSED_K) {
     FWork k;
-    const int ct = 1 << (m - 9);
+    const int ct = 1 << (m - kb - 5);
     k.nwv = ct < 4 ? ct : 4;
     k.ctw = ct / k.nwv;
     k.nthr = 64 * k.nwv;
     return k;
 }
 
-// MB: largest tile bits of the instantiation (LDS size, column tiles per wave)
-template <int IT, int MB>
+// floats of one block's operand tables: the forward order, then the reverse
+// one (four sub-blocks each for 32 x 32 blocks)
+template <int KB>
+constexpr int mats_stride() { return KB == 5 ? 8192 : 2048; }
+
+// MB: largest tile bits of the instantiation (LDS size, column tiles per wave);
+// KB: block bits of the plan
+template <int IT, int MB, int KB>
 __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const Job single) {
-    constexpr int CT_MAX = ct_max<MB>();
+    constexpr int CT_MAX = KB == 5 ? 1 : ct_max<MB>();
     __shared__ float2 lds[1 << MB];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     cptr<FPass> P = as_const(J.fpasses) + jl.step;
     const int m = P->m;
-    const FWork K = fwork(m);
+    const FWork K = fwork(m, KB);
     const int t = threadIdx.x;
     const int wave = uniform(t >> 6), lane = t & 63, h = lane >> 5;
     const bool active = wave < K.nwv;
@@ -250,7 +257,7 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
     const uint64_t tile = uint64_t(local - b * J.tiles);
     gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
     gptr<const float> mats =
-        as_global(static_cast<const float*>(J.fmats)) + size_t(J.shared ? 0 : b) * J.n_blocks * 2048;
+        as_global(static_cast<const float*>(J.fmats)) + size_t(J.shared ? 0 : b) * J.n_blocks * mats_stride<KB>();
     cptr<FPhase> phases = as_const(J.fphases);
     const uint64_t base = tile_base_f(tile, P->tile_mask, J.n);
     float2* const bufs[1] = {lds};
@@ -270,6 +277,52 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
         }
     }
     const int f_end = P->phase_end;
+    if constexpr (KB == 5) {
+        // 32 x 32 blocks: y_i = M_i0 x_0 + M_i1 x_1 over the halves of a column
+        // (top block bit 0 / 1), four 16 x 16 sub-block products, one column
+        // tile per wave
+        __syncthreads();
+        for (int f = P->phase_begin; f < f_end; ++f) {
+            cptr<FPhase> F = phases + f;
+            float x0[16], x1[16], w[4][16];
+            FView v;
+            if (active) {
+                v = fview(F, wave, lane);
+                read_cols(lds, v, h, x0);
+                read_cols(lds, v, h, x1, v.rdR[4]);
+#pragma unroll
+                for (int sb = 0; sb < 4; ++sb) read_mat(mats + size_t(F->block) * 8192 + sb * 1024, lane, w[sb]);
+            }
+            __syncthreads();   // the phase writes another layout: all reads first
+            if (active) {
+                const f16v z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                f16v acc[2] = {z, z};
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[0][s], x0[s], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[2][s], x0[s], acc[1], 0, 0, 0);
+                }
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[1][s], x1[s], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[3][s], x1[s], acc[1], 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const uint32_t wb = v.wr_col ^ (v.wrR[2] & (0u - uint32_t(h))) ^ (i ? v.wrR[4] : 0u);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const uint32_t a = wb ^ ((q & 1) ? v.wrR[0] : 0u) ^ ((q & 2) ? v.wrR[1] : 0u) ^
+                                           ((q & 4) ? v.wrR[3] : 0u);
+                        lds[a] = make_float2(acc[i][q], acc[i][q + 8]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (active) ftile_store<IT, 1>(bufs, sts, base, io);
+        return;
+    }
     // block matrices one phase ahead: the next phase's loads are in flight
     // while this phase's matrix products run
     float wn[16];
@@ -334,44 +387,67 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
 typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int FLUSH_TILES = 16;
 
-// staging index e = r * 128 + part * 64 + lane of MFMA output register r
-// (O[a = 4 (lane / 16) + r][b = lane % 16], part 0 = re) -> O entry
+// per block width: doubles of one outer product (16 x 16 or 32 x 32 complex),
+// entries a thread accumulates, blocks a pass holds
+template <int KB>
+struct ORev {
+    static constexpr int OS = KB == 5 ? 4 * OSTRIDE : OSTRIDE;
+    static constexpr int NE = OS / FTHREADS;
+    static constexpr int MAXB = KB == 5 ? FUSED5_MAX_BLOCKS : FUSED_MAX_BLOCKS;
+};
+
+// staging index e = sb * 512 + r * 128 + part * 64 + lane of MFMA output
+// register r of sub-block sb = 2 i + j (O[a = 16 i + 4 (lane / 16) + r]
+// [b = 16 j + lane % 16], part 0 = re; sb = 0 for 16 x 16 blocks) -> O entry
+template <int KB>
 __device__ __forceinline__ int stage_to_o(int e) {
-    const int r = e >> 7, part = (e >> 6) & 1, ln = e & 63;
-    return ((4 * (ln >> 4) + r) * 16 + (ln & 15)) * 2 + part;
+    constexpr int D = 1 << KB;
+    const int sb = e >> 9, r = (e >> 7) & 3, part = (e >> 6) & 1, ln = e & 63;
+    const int a = 16 * (sb >> 1) + 4 * (ln >> 4) + r, bb = 16 * (sb & 1) + (ln & 15);
+    return (a * D + bb) * 2 + part;
 }
 
-// add the staged sums of the waves into the thread's two entries of block slot kb
-__device__ __forceinline__ void stage_reduce(const float* stage, int nwv, int kb, float (&acc)[FUSED_MAX_BLOCKS][2]) {
-    float v0 = 0.f, v1 = 0.f;
-    for (int w = 0; w < nwv; ++w) {
-        v0 += stage[w * OSTRIDE + threadIdx.x];
-        v1 += stage[w * OSTRIDE + threadIdx.x + 256];
-    }
+// add the staged sums of the waves into the thread's entries of block slot kb
+template <int KB>
+__device__ __forceinline__ void stage_reduce(const float* stage, int nwv, int kb,
+                                             float (&acc)[ORev<KB>::MAXB][ORev<KB>::NE]) {
+    constexpr int OS = ORev<KB>::OS, NE = ORev<KB>::NE;
+    float v[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) v[u] = 0.f;
+    for (int w = 0; w < nwv; ++w)
+#pragma unroll
+        for (int u = 0; u < NE; ++u) v[u] += stage[w * OS + threadIdx.x + FTHREADS * u];
     // every slot takes an add (zero for the others): a uniform runtime slot
     // must not become an indexed register access
 #pragma unroll
-    for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) {
+    for (int k = 0; k < ORev<KB>::MAXB; ++k) {
         const bool hit = k == kb;
-        acc[k][0] += hit ? v0 : 0.f;
-        acc[k][1] += hit ? v1 : 0.f;
+#pragma unroll
+        for (int u = 0; u < NE; ++u) acc[k][u] += hit ? v[u] : 0.f;
     }
 }
 
-__device__ __forceinline__ void flush_acc(float (&acc)[FUSED_MAX_BLOCKS][2], int nblk, gptr<double> dst, int wgs,
-                                          bool first) {
-    // dst: this workgroup's slice of the pass's first block; block k at + k * wgs * OSTRIDE.
+template <int KB>
+__device__ __forceinline__ void flush_acc(float (&acc)[ORev<KB>::MAXB][ORev<KB>::NE], int nblk, gptr<double> dst,
+                                          int wgs, bool first) {
+    constexpr int OS = ORev<KB>::OS, NE = ORev<KB>::NE;
+    // dst: this workgroup's slice of the pass's first block; block k at + k * wgs * OS.
     // The lane offsets are formed here, at each flush (opaque to loop-invariant
-    // code motion): hoisted out of the tile loop, the 16 addresses would hold
-    // 32 registers for the whole kernel.
-    uint32_t off[2] = {uint32_t(stage_to_o(int(threadIdx.x))), uint32_t(stage_to_o(int(threadIdx.x) + 256))};
-    asm volatile("" : "+v"(off[0]), "+v"(off[1]));
+    // code motion): hoisted out of the tile loop, the addresses would hold
+    // registers for the whole kernel.
+    uint32_t off[NE];
 #pragma unroll
-    for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) {
+    for (int u = 0; u < NE; ++u) {
+        off[u] = uint32_t(stage_to_o<KB>(int(threadIdx.x) + FTHREADS * u));
+        asm volatile("" : "+v"(off[u]));
+    }
+#pragma unroll
+    for (int k = 0; k < ORev<KB>::MAXB; ++k) {
         if (k >= nblk) break;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            gptr<double> d = dst + size_t(k) * wgs * OSTRIDE + off[i];
+        for (int i = 0; i < NE; ++i) {
+            gptr<double> d = dst + size_t(k) * wgs * OS + off[i];
             const double v = double(acc[k][i]);
             *d = first ? v : *d + v;
             acc[k][i] = 0.f;
@@ -379,18 +455,59 @@ __device__ __forceinline__ void flush_acc(float (&acc)[FUSED_MAX_BLOCKS][2], int
     }
 }
 
-// two workgroups per CU (72 KiB of LDS each at MB = 12)
-template <int IT, int MB>
-__global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, const Job single) {
-    constexpr int CT_MAX = ct_max<MB>();
+// outer-product contribution of one 16-row half pair: al = the un-applied
+// lambda half (rows a), ap = the psi half (rows b), both in the output
+// layout of the un-apply (after their write-back); v_permlane16_swap on a
+// register pair (q, q + 1) leaves the real parts of the pair's four columns
+// in one register and the imaginary parts in the other, one column per
+// 16-lane row: the K layout of v_mfma_f32_16x16x4f32
+__device__ __forceinline__ void outer_half(const f16v& ap, const f16v& al, f4v& ore, f4v& ore1, f4v& oim, f4v& oim1) {
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+        const auto sp = __builtin_amdgcn_permlane16_swap(__float_as_uint(ap[q]), __float_as_uint(ap[q + 1]), false,
+                                                         false);
+        const auto sl = __builtin_amdgcn_permlane16_swap(__float_as_uint(al[q]), __float_as_uint(al[q + 1]), false,
+                                                         false);
+        const float pre = __uint_as_float(sp[0]), pim = __uint_as_float(sp[1]);
+        const float lre = __uint_as_float(sl[0]), lim = __uint_as_float(sl[1]);
+        ore = __builtin_amdgcn_mfma_f32_16x16x4f32(lre, pre, ore, 0, 0, 0);
+        ore1 = __builtin_amdgcn_mfma_f32_16x16x4f32(lim, pim, ore1, 0, 0, 0);
+        oim = __builtin_amdgcn_mfma_f32_16x16x4f32(lim, pre, oim, 0, 0, 0);
+        oim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(lre, pim, oim1, 0, 0, 0);
+    }
+}
+
+// write-back of an un-apply result: float component n_c (re if < 16) of block
+// index n_c % 16 of the half selected by `half` (the image of block bit 4)
+__device__ __forceinline__ void rev_writeback(float* fdst, const FView& v, int n_c, int h, int part, uint32_t half,
+                                              const f16v& r) {
+    const uint32_t jb = (v.wrR[0] & (0u - uint32_t(n_c & 1))) ^ (v.wrR[1] & (0u - uint32_t((n_c >> 1) & 1))) ^
+                        (v.wrR[2] & (0u - uint32_t((n_c >> 2) & 1))) ^ (v.wrR[3] & (0u - uint32_t((n_c >> 3) & 1)));
+    const uint32_t wb = v.wr_tile ^ jb ^ (v.wrC[2] & (0u - uint32_t(h))) ^ half;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        // column ct * 32 + 8 (q / 4) + 4 h + q % 4: bits 0, 1 <- q, bit 2 <- h, bits 3, 4 <- q / 4
+        const uint32_t a = wb ^ ((q & 1) ? v.wrC[0] : 0u) ^ ((q & 2) ? v.wrC[1] : 0u) ^ ((q & 4) ? v.wrC[3] : 0u) ^
+                           ((q & 8) ? v.wrC[4] : 0u);
+        fdst[2 * a + part] = r[q];
+    }
+}
+
+// 16 x 16 blocks: two workgroups per CU (72 KiB of LDS each at MB = 12);
+// 32 x 32 blocks: one (96 KiB: both tiles and four staged sub-block products
+// per wave)
+template <int IT, int MB, int KB>
+__global__ void __launch_bounds__(FTHREADS, KB == 5 ? 1 : 2) k_fused_rev(const JobList jl, const Job single) {
+    constexpr int CT_MAX = KB == 5 ? 1 : ct_max<MB>();
+    constexpr int OS = ORev<KB>::OS, NE = ORev<KB>::NE, MAXB = ORev<KB>::MAXB;
     __shared__ float2 lps[1 << MB];
     __shared__ float2 llm[1 << MB];
-    __shared__ float stage[(FTHREADS / 64) * OSTRIDE];
+    __shared__ float stage[(FTHREADS / 64) * OS];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     cptr<FPass> P = as_const(J.frpasses) + (J.n_passes - 1 - jl.step);
     const int m = P->m;
-    const FWork K = fwork(m);
+    const FWork K = fwork(m, KB);
     const int t = threadIdx.x;
     const int wave = uniform(t >> 6), lane = t & 63, h = lane >> 5;
     const bool active = wave < K.nwv;
@@ -401,22 +518,25 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
     const int wg = int(local - b * wgs);
     gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
     gptr<cx<float>> lam = as_global(static_cast<cx<float>*>(J.costate)) + b * J.stride;
-    gptr<const float> mats = as_global(static_cast<const float*>(J.fmats)) + size_t(b) * J.n_blocks * 2048 + 1024;
+    gptr<const float> mats = as_global(static_cast<const float*>(J.fmats)) + size_t(b) * J.n_blocks * mats_stride<KB>() +
+                             mats_stride<KB>() / 2;
     cptr<FPhase> phases = as_const(J.frphases);
     const int f_begin = P->phase_begin, f_end = P->phase_end;
     const int nblk = f_end - f_begin;
     // blocks of a pass are numbered consecutively (visited in reverse)
     const int blk0 = phases[f_end - 1].block;
-    gptr<double> odst = as_global(J.opart) + ((size_t(b) * J.n_blocks + blk0) * wgs + wg) * OSTRIDE;
+    gptr<double> odst = as_global(J.opart) + ((size_t(b) * J.n_blocks + blk0) * wgs + wg) * OS;
 
-    float acc[FUSED_MAX_BLOCKS][2];
+    float acc[MAXB][NE];
 #pragma unroll
-    for (int k = 0; k < FUSED_MAX_BLOCKS; ++k) acc[k][0] = acc[k][1] = 0.f;
+    for (int k = 0; k < MAXB; ++k)
+#pragma unroll
+        for (int u = 0; u < NE; ++u) acc[k][u] = 0.f;
 
     const int n_c = lane & 31;
     float* fp = reinterpret_cast<float*>(lps);
     float* fl = reinterpret_cast<float*>(llm);
-    float* my_stage = stage + wave * OSTRIDE + lane;
+    float* my_stage = stage + wave * OS + lane;
     const int part = n_c >> 4;
     float2* const bufs[2] = {lps, llm};
     const gptr<cx<float>> sts[2] = {psi, lam};
@@ -434,7 +554,58 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
         for (int f = f_begin; f < f_end; ++f) {
             cptr<FPhase> F = phases + f;
             // the previous block's staged outer products (after its closing barrier)
-            if (f > f_begin) stage_reduce(stage, K.nwv, phases[f - 1].block - blk0, acc);
+            if (f > f_begin) stage_reduce<KB>(stage, K.nwv, phases[f - 1].block - blk0, acc);
+            if constexpr (KB == 5) {
+                // 32 x 32 blocks: each output half i of psi_in = M^dagger psi_out is
+                // sum_j (M_ji)^dagger psi_out_j (sub-block operand 2 i + j); the outer
+                // product's four sub-blocks O_ij = sum lambda_in_i psi_in_j^dagger
+                float xp[2][16], xl[2][16], w[4][16];
+                FView v;
+                if (active) {
+#pragma unroll
+                    for (int sb = 0; sb < 4; ++sb) read_mat(mats + size_t(F->block) * 8192 + sb * 1024, lane, w[sb]);
+                    v = fview(F, wave, lane);
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        read_cols(lps, v, h, xp[j], j ? v.rdR[4] : 0u);
+                        read_cols(llm, v, h, xl[j], j ? v.rdR[4] : 0u);
+                    }
+                }
+                __syncthreads();
+                if (active) {
+                    __builtin_amdgcn_s_setprio(1);
+                    const f16v z = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    f16v ap[2] = {z, z}, al[2] = {z, z};
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+#pragma unroll
+                            for (int s = 0; s < 16; ++s) {
+                                ap[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[j][s], w[2 * i + j][s], ap[i], 0, 0, 0);
+                                al[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(xl[j][s], w[2 * i + j][s], al[i], 0, 0, 0);
+                            }
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) {
+                        rev_writeback(fp, v, n_c, h, part, i ? v.wrR[4] : 0u, ap[i]);
+                        rev_writeback(fl, v, n_c, h, part, i ? v.wrR[4] : 0u, al[i]);
+                    }
+                    const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int sb = 0; sb < 4; ++sb) {
+                        f4v ore = z4, oim = z4, ore1 = z4, oim1 = z4;
+                        outer_half(ap[sb & 1], al[sb >> 1], ore, ore1, oim, oim1);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            my_stage[sb * 512 + r * 128] = ore[r] + ore1[r];
+                            my_stage[sb * 512 + r * 128 + 64] = oim[r] - oim1[r];
+                        }
+                    }
+                    __builtin_amdgcn_s_setprio(0);
+                }
+                __syncthreads();
+                continue;
+            }
             float xp[CT_MAX][16], xl[CT_MAX][16], w[16];
             FView v[CT_MAX];
             if (active) {
@@ -464,36 +635,9 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
                         ap = __builtin_amdgcn_mfma_f32_32x32x2f32(xp[k][s], w[s], ap, 0, 0, 0);
                         al = __builtin_amdgcn_mfma_f32_32x32x2f32(xl[k][s], w[s], al, 0, 0, 0);
                     }
-                    // write back: float component n_c (re if < 16) of block index n_c % 16
-                    const uint32_t jb = (v[k].wrR[0] & (0u - uint32_t(n_c & 1))) ^
-                                        (v[k].wrR[1] & (0u - uint32_t((n_c >> 1) & 1))) ^
-                                        (v[k].wrR[2] & (0u - uint32_t((n_c >> 2) & 1))) ^
-                                        (v[k].wrR[3] & (0u - uint32_t((n_c >> 3) & 1)));
-                    const uint32_t wb = v[k].wr_tile ^ jb ^ (v[k].wrC[2] & (0u - uint32_t(h)));
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        // column ct * 32 + 8 (q / 4) + 4 h + q % 4: bits 0, 1 <- q, bit 2 <- h, bits 3, 4 <- q / 4
-                        const uint32_t a = wb ^ ((q & 1) ? v[k].wrC[0] : 0u) ^ ((q & 2) ? v[k].wrC[1] : 0u) ^
-                                           ((q & 4) ? v[k].wrC[3] : 0u) ^ ((q & 8) ? v[k].wrC[4] : 0u);
-                        fp[2 * a + part] = ap[q];
-                        fl[2 * a + part] = al[q];
-                    }
-                    // outer product over the registers of a pair (q, q + 1), after the
-                    // write-back: the row swap leaves the real parts of the pair's four
-                    // columns in one register and the imaginary parts in the other
-#pragma unroll
-                    for (int q = 0; q < 16; q += 2) {
-                        const auto sp = __builtin_amdgcn_permlane16_swap(__float_as_uint(ap[q]), __float_as_uint(ap[q + 1]),
-                                                                         false, false);
-                        const auto sl = __builtin_amdgcn_permlane16_swap(__float_as_uint(al[q]), __float_as_uint(al[q + 1]),
-                                                                         false, false);
-                        const float pre = __uint_as_float(sp[0]), pim = __uint_as_float(sp[1]);
-                        const float lre = __uint_as_float(sl[0]), lim = __uint_as_float(sl[1]);
-                        ore = __builtin_amdgcn_mfma_f32_16x16x4f32(lre, pre, ore, 0, 0, 0);
-                        ore1 = __builtin_amdgcn_mfma_f32_16x16x4f32(lim, pim, ore1, 0, 0, 0);
-                        oim = __builtin_amdgcn_mfma_f32_16x16x4f32(lim, pre, oim, 0, 0, 0);
-                        oim1 = __builtin_amdgcn_mfma_f32_16x16x4f32(lre, pim, oim1, 0, 0, 0);
-                    }
+                    rev_writeback(fp, v[k], n_c, h, part, 0u, ap);
+                    rev_writeback(fl, v[k], n_c, h, part, 0u, al);
+                    outer_half(ap, al, ore, ore1, oim, oim1);
                     // one column tile at a time (register pressure)
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -506,15 +650,15 @@ __global__ void __launch_bounds__(FTHREADS, 2) k_fused_rev(const JobList jl, con
             }
             __syncthreads();
         }
-        stage_reduce(stage, K.nwv, phases[f_end - 1].block - blk0, acc);
+        stage_reduce<KB>(stage, K.nwv, phases[f_end - 1].block - blk0, acc);
         if (active) ftile_store<IT, 2>(bufs, sts, base, io);
         if (++pending == FLUSH_TILES) {
-            flush_acc(acc, nblk, odst, wgs, first);
+            flush_acc<KB>(acc, nblk, odst, wgs, first);
             first = false;
             pending = 0;
         }
     }
-    if (pending || first) flush_acc(acc, nblk, odst, wgs, first);
+    if (pending || first) flush_acc<KB>(acc, nblk, odst, wgs, first);
 }
 
 // ---------------------------------------------------------------------------
@@ -577,18 +721,25 @@ __device__ __forceinline__ int gset(const Op& op, int a, int dim, int beta) {
     return (a & ~((1 << op.r0) | (1 << op.r1))) | ((beta >> 1) << op.r0) | ((beta & 1) << op.r1);
 }
 
-// one workgroup of 256 threads per (block f, member b): thread (row a, column c)
+// one workgroup of 256 threads per (block f, member b): thread entries
+// e = t + 256 i of the 2^KB x 2^KB product (row a = e >> KB, column c)
+template <int KB>
 __device__ __forceinline__ void fused_mats_body(const FPhase* __restrict__ phases, const Op* __restrict__ ops,
                                                 int n_blocks, const float* __restrict__ params, int64_t pstride,
                                                 const cx<float>* __restrict__ cm, int64_t cmstride,
                                                 float* __restrict__ out, int want_rev, int f, int64_t b) {
-    __shared__ c64d M[256];
+    constexpr int D = 1 << KB, EPT = D * D / 256, NSB = KB == 5 ? 4 : 1;
+    __shared__ c64d M[D * D];
     __shared__ c64d U[16];
-    const int t = threadIdx.x, a = t >> 4, c = t & 15;
+    const int t = threadIdx.x;
     const FPhase F = phases[f];
     const float* prm = params ? params + b * pstride : nullptr;
     cm += b * cmstride * 16;   // per-member matrices (cmstride 0: shared)
-    M[t] = {a == c ? 1.0 : 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = t + 256 * i;
+        M[e] = {(e >> KB) == (e & (D - 1)) ? 1.0 : 0.0, 0.0};
+    }
     for (int o = F.op_begin; o < F.op_end; ++o) {
         const Op op = ops[o];
         if (t == 0) {   // gate matrix into LDS (indexed by the threads below)
@@ -599,64 +750,77 @@ __device__ __forceinline__ void fused_mats_body(const FPhase* __restrict__ phase
         }
         __syncthreads();
         const int dim = kind_arity(op.kind) == 2 ? 4 : 2;
-        const int al = gidx(op, a, dim);
-        c64d acc = {0.0, 0.0};
-        for (int be = 0; be < dim; ++be) {
-            const c64d x = M[gset(op, a, dim, be) * 16 + c];
-            const c64d p = cmul(U[al * dim + be], x);
-            acc.re += p.re;
-            acc.im += p.im;
+        c64d nv[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = t + 256 * i, a = e >> KB, c = e & (D - 1);
+            const int al = gidx(op, a, dim);
+            c64d acc = {0.0, 0.0};
+            for (int be = 0; be < dim; ++be) {
+                const c64d x = M[gset(op, a, dim, be) * D + c];
+                const c64d p = cmul(U[al * dim + be], x);
+                acc.re += p.re;
+                acc.im += p.im;
+            }
+            nv[i] = acc;
         }
         __syncthreads();
-        M[t] = acc;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) M[t + 256 * i] = nv[i];
     }
     __syncthreads();
-    // real embedding entry (i, k), i, k < 32
-    auto emb = [&](int i, int k) -> float {
-        const c64d z = M[(i & 15) * 16 + (k & 15)];
+    // real embedding entry (i, k), i, k < 32, of the 16 x 16 sub-block (bi, bj)
+    auto emb = [&](int bi, int bj, int i, int k) -> float {
+        const c64d z = M[(16 * bi + (i & 15)) * D + 16 * bj + (k & 15)];
         if ((i < 16) == (k < 16)) return float(z.re);
         return (i < 16) ? float(-z.im) : float(z.im);
     };
-    float* dst = out + (size_t(b) * n_blocks + F.block) * 2048;
-    for (int e = t; e < 1024; e += 256) {
-        const int l = e >> 4, s = e & 15;
-        const int kk = 2 * s + (l >> 5), ll = l & 31;
-        dst[e] = emb(ll, kk);                     // forward: A[l % 32][2 s + h]
-        if (want_rev) dst[1024 + e] = emb(kk, ll);   // reverse: B[2 s + h][l % 32]
+    float* dst = out + (size_t(b) * n_blocks + F.block) * (2048 * NSB);
+    for (int sb = 0; sb < NSB; ++sb) {
+        const int bi = sb >> 1, bj = sb & 1;
+        for (int e = t; e < 1024; e += 256) {
+            const int l = e >> 4, s = e & 15;
+            const int kk = 2 * s + (l >> 5), ll = l & 31;
+            dst[sb * 1024 + e] = emb(bi, bj, ll, kk);                            // forward: A[l % 32][2 s + h] of M_ij
+            if (want_rev) dst[NSB * 1024 + sb * 1024 + e] = emb(bj, bi, kk, ll);   // reverse: B[2 s + h][l % 32] of M_ji
+        }
     }
 }
 
+template <int KB>
 __global__ void __launch_bounds__(256)
 k_fused_mats(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
              int64_t pstride, const cx<float>* __restrict__ cm, int64_t cmstride, float* __restrict__ out,
              int want_rev) {
-    fused_mats_body(phases, ops, n_blocks, params, pstride, cm, cmstride, out, want_rev, int(blockIdx.x),
-                    int64_t(blockIdx.y));
+    fused_mats_body<KB>(phases, ops, n_blocks, params, pstride, cm, cmstride, out, want_rev, int(blockIdx.x),
+                        int64_t(blockIdx.y));
 }
 
 // uneven batch: circuit blockIdx.y, its block blockIdx.x (grid x: the most blocks of any circuit)
 __global__ void __launch_bounds__(256) k_fused_mats_multi(const FusedCircJob* __restrict__ jobs) {
     const FusedCircJob J = jobs[blockIdx.y];
     if (int(blockIdx.x) >= J.n_blocks) return;   // the whole workgroup leaves together
-    fused_mats_body(J.phases, J.ops, J.n_blocks, J.params, J.pstride, J.cm, 0, J.fmats, 1, int(blockIdx.x), 0);
+    fused_mats_body<FUSED_K>(J.phases, J.ops, J.n_blocks, J.params, J.pstride, J.cm, 0, J.fmats, 1, int(blockIdx.x), 0);
 }
 
 // ---------------------------------------------------------------------------
 // outer products: fixed-order sum over workgroups
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void fused_osum_one(const double* __restrict__ opart, int wgs, double* __restrict__ osum,
-                                               int64_t i) {
-    const int64_t r = i / OSTRIDE, e = i - r * OSTRIDE;
-    const double* p = opart + size_t(r) * wgs * OSTRIDE + e;
+                                               int64_t i, int os = OSTRIDE) {
+    const int64_t r = i / os, e = i - r * os;
+    const double* p = opart + size_t(r) * wgs * os + e;
     double s = 0.0;
-    for (int w = 0; w < wgs; ++w) s += p[size_t(w) * OSTRIDE];
+    for (int w = 0; w < wgs; ++w) s += p[size_t(w) * os];
     osum[i] = s;
 }
 
-__global__ void k_fused_osum(const double* __restrict__ opart, int64_t rows, int wgs, double* __restrict__ osum) {
+// os: doubles of one outer product (512 for 16 x 16 blocks, 2048 for 32 x 32)
+__global__ void k_fused_osum(const double* __restrict__ opart, int64_t rows, int wgs, double* __restrict__ osum,
+                             int os) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= rows * OSTRIDE) return;
-    fused_osum_one(opart, wgs, osum, i);
+    if (i >= rows * os) return;
+    fused_osum_one(opart, wgs, osum, i, os);
 }
 
 // uneven batch: circuit blockIdx.y, entries of its n_blocks outer products
@@ -685,38 +849,40 @@ __device__ __forceinline__ int load_gate(const Op& op, const float* prm, const c
     return dim;
 }
 
+template <int KB>
 __device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phases, const Op* __restrict__ ops,
                                                 int n_blocks, const float* __restrict__ params, int64_t pstride,
                                                 const cx<float>* __restrict__ cm, const double* __restrict__ osum,
                                                 int total_slots, double* __restrict__ slots, int f, int64_t b) {
-    __shared__ c64d X[256];
+    constexpr int D = 1 << KB, EPT = D * D / 64, OS = KB == 5 ? 4 * OSTRIDE : OSTRIDE;
+    __shared__ c64d X[D * D];
     __shared__ c64d U[16];
     const int t = threadIdx.x;
     const FPhase F = phases[f];
     if (F.op_end == F.op_begin) return;
     const float* prm = params ? params + b * pstride : nullptr;
-    const double* O = osum + (size_t(b) * n_blocks + F.block) * OSTRIDE;
+    const double* O = osum + (size_t(b) * n_blocks + F.block) * OS;
     double* sl = slots + size_t(b) * total_slots;
-    c64d x[4];
+    c64d x[EPT];
     // X_1 = G_1 O
     {
         const Op op = ops[F.op_begin];
         const int dim = load_gate(op, prm, cm, U);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = t + 64 * i, a = e >> 4, c = e & 15;
+        for (int i = 0; i < EPT; ++i) {
+            const int e = t + 64 * i, a = e >> KB, c = e & (D - 1);
             const int al = gidx(op, a, dim);
             c64d acc = {0.0, 0.0};
             for (int be = 0; be < dim; ++be) {
                 const int r = gset(op, a, dim, be);
-                const c64d p = cmul(U[al * dim + be], c64d{O[(r * 16 + c) * 2], O[(r * 16 + c) * 2 + 1]});
+                const c64d p = cmul(U[al * dim + be], c64d{O[(r * D + c) * 2], O[(r * D + c) * 2 + 1]});
                 acc.re += p.re;
                 acc.im += p.im;
             }
             x[i] = acc;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) X[t + 64 * i] = x[i];
+        for (int i = 0; i < EPT; ++i) X[t + 64 * i] = x[i];
         __syncthreads();
     }
     for (int o = F.op_begin; o < F.op_end; ++o) {
@@ -727,9 +893,9 @@ __device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phase
             if (t < 16) {
                 const int al = t >> 2, be = t & 3;
                 double sr = 0.0, si = 0.0;
-                for (int rest = 0; rest < 16; ++rest) {
+                for (int rest = 0; rest < D; ++rest) {
                     if (rest & ((1 << op.r0) | (1 << op.r1))) continue;
-                    const c64d v = X[gset(op, rest, 4, al) * 16 + gset(op, rest, 4, be)];
+                    const c64d v = X[gset(op, rest, 4, al) * D + gset(op, rest, 4, be)];
                     sr += v.re;
                     si += v.im;
                 }
@@ -738,14 +904,14 @@ __device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phase
             }
         }
         // Y = X G^dagger
-        c64d y[4];
+        c64d y[EPT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = t + 64 * i, a = e >> 4, c = e & 15;
+        for (int i = 0; i < EPT; ++i) {
+            const int e = t + 64 * i, a = e >> KB, c = e & (D - 1);
             const int cl = gidx(op, c, dim);
             c64d acc = {0.0, 0.0};
             for (int de = 0; de < dim; ++de) {
-                const c64d xv = X[a * 16 + gset(op, c, dim, de)];
+                const c64d xv = X[a * D + gset(op, c, dim, de)];
                 const c64d g = U[cl * dim + de];   // (G^dagger)[d][c] = conj(G[c][d])
                 acc.re += xv.re * g.re + xv.im * g.im;
                 acc.im += xv.im * g.re - xv.re * g.im;
@@ -754,14 +920,14 @@ __device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phase
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) X[t + 64 * i] = y[i];
+        for (int i = 0; i < EPT; ++i) X[t + 64 * i] = y[i];
         // angle derivatives: 2 Im sum_ab Gen_ab conj(Y_ab)
         if (op.slot >= 0 && op.kind != K_U2) {
             double g0 = 0.0, g1 = 0.0;
             const int mask = dim == 2 ? (1 << op.r0) : ((1 << op.r0) | (1 << op.r1));
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = t + 64 * i, a = e >> 4, c = e & 15;
+            for (int i = 0; i < EPT; ++i) {
+                const int e = t + 64 * i, a = e >> KB, c = e & (D - 1);
                 if ((a & ~mask) != (c & ~mask)) continue;
                 const int al = gidx(op, a, dim), clc = gidx(op, c, dim);
                 const double yr = y[i].re, yi = -y[i].im;   // conj(Y)
@@ -798,12 +964,12 @@ __device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phase
             const Op nx = ops[o + 1];
             const int nd = load_gate(nx, prm, cm, U);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = t + 64 * i, a = e >> 4, c = e & 15;
+            for (int i = 0; i < EPT; ++i) {
+                const int e = t + 64 * i, a = e >> KB, c = e & (D - 1);
                 const int al = gidx(nx, a, nd);
                 c64d acc = {0.0, 0.0};
                 for (int be = 0; be < nd; ++be) {
-                    const c64d p = cmul(U[al * nd + be], X[gset(nx, a, nd, be) * 16 + c]);
+                    const c64d p = cmul(U[al * nd + be], X[gset(nx, a, nd, be) * D + c]);
                     acc.re += p.re;
                     acc.im += p.im;
                 }
@@ -811,18 +977,19 @@ __device__ __forceinline__ void fused_grad_body(const FPhase* __restrict__ phase
             }
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 4; ++i) X[t + 64 * i] = x[i];
+            for (int i = 0; i < EPT; ++i) X[t + 64 * i] = x[i];
             __syncthreads();
         }
     }
 }
 
 
+template <int KB>
 __global__ void __launch_bounds__(64)
 k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int n_blocks, const float* __restrict__ params,
              int64_t pstride, const cx<float>* __restrict__ cm, const double* __restrict__ osum, int total_slots,
              double* __restrict__ slots) {
-    fused_grad_body(phases, ops, n_blocks, params, pstride, cm, osum, total_slots, slots, int(blockIdx.x),
+    fused_grad_body<KB>(phases, ops, n_blocks, params, pstride, cm, osum, total_slots, slots, int(blockIdx.x),
                     int64_t(blockIdx.y));
 }
 
@@ -830,33 +997,51 @@ k_fused_grad(const FPhase* __restrict__ phases, const Op* __restrict__ ops, int 
 __global__ void __launch_bounds__(64) k_fused_grad_multi(const FusedCircJob* __restrict__ jobs) {
     const FusedCircJob J = jobs[blockIdx.y];
     if (int(blockIdx.x) >= J.n_blocks || J.total_slots <= 0) return;
-    fused_grad_body(J.phases, J.ops, J.n_blocks, J.params, J.pstride, J.cm, J.osum, J.total_slots, J.slots,
+    fused_grad_body<FUSED_K>(J.phases, J.ops, J.n_blocks, J.params, J.pstride, J.cm, J.osum, J.total_slots, J.slots,
                     int(blockIdx.x), 0);
 }
 }  // namespace
 
 hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
                              const void* cmats, int64_t cmstride, int64_t batch, void* out, bool want_rev,
-                             hipStream_t st) {
+                             hipStream_t st, int kb) {
     if (n_blocks == 0 || batch == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fused_mats, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
-                       n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
-                       cmstride, static_cast<float*>(out), int(want_rev));
+    if (kb == 5)
+        hipLaunchKernelGGL(k_fused_mats<5>, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
+                           n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
+                           cmstride, static_cast<float*>(out), int(want_rev));
+    else
+        hipLaunchKernelGGL(k_fused_mats<4>, dim3(unsigned(n_blocks), unsigned(batch)), dim3(256), 0, st, phases, ops,
+                           n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
+                           cmstride, static_cast<float*>(out), int(want_rev));
     return hipGetLastError();
 }
 
-// chunks per thread of the tile load: 8 at m = 12 (256 threads), 4 for m = 9..11
-hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st) {
+// chunks per thread of the tile load: 8 at m = 12 (256 threads), 4 for m = 9..11;
+// 32 x 32 blocks only at m = 12
+hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st, int kb) {
     if (blocks <= 0) return hipSuccess;
-    if (m == 12) hipLaunchKernelGGL((k_fused_fwd<8, 12>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
-    else hipLaunchKernelGGL((k_fused_fwd<4, 11>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    if (kb == 5) {
+        if (m != 12) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_fused_fwd<8, 12, 5>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    } else if (m == 12) {
+        hipLaunchKernelGGL((k_fused_fwd<8, 12, 4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    } else {
+        hipLaunchKernelGGL((k_fused_fwd<4, 11, 4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st) {
+hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st, int kb) {
     if (blocks <= 0) return hipSuccess;
-    if (m == 12) hipLaunchKernelGGL((k_fused_rev<8, 12>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
-    else hipLaunchKernelGGL((k_fused_rev<4, 11>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    if (kb == 5) {
+        if (m != 12) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_fused_rev<8, 12, 5>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    } else if (m == 12) {
+        hipLaunchKernelGGL((k_fused_rev<8, 12, 4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    } else {
+        hipLaunchKernelGGL((k_fused_rev<4, 11, 4>), dim3(unsigned(blocks)), dim3(FTHREADS), 0, st, jl, single);
+    }
     return hipGetLastError();
 }
 
@@ -878,16 +1063,22 @@ hipError_t launch_fused_multi_grad(const FusedCircJob* jobs, int count, int max_
 
 hipError_t launch_fused_grad(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
                              const void* cmats, int64_t batch, const double* opart, int wgs, double* osum,
-                             int total_slots, double* slots, hipStream_t st) {
+                             int total_slots, double* slots, hipStream_t st, int kb) {
     if (n_blocks == 0 || batch == 0) return hipSuccess;
     const int64_t rows = batch * int64_t(n_blocks);
-    hipLaunchKernelGGL(k_fused_osum, dim3(unsigned((rows * OSTRIDE + 255) / 256)), dim3(256), 0, st, opart, rows, wgs,
-                       osum);
+    const int os = kb == 5 ? 4 * OSTRIDE : OSTRIDE;
+    hipLaunchKernelGGL(k_fused_osum, dim3(unsigned((rows * os + 255) / 256)), dim3(256), 0, st, opart, rows, wgs,
+                       osum, os);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fused_grad, dim3(unsigned(n_blocks), unsigned(batch)), dim3(64), 0, st, phases, ops,
-                       n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
-                       osum, total_slots, slots);
+    if (kb == 5)
+        hipLaunchKernelGGL(k_fused_grad<5>, dim3(unsigned(n_blocks), unsigned(batch)), dim3(64), 0, st, phases, ops,
+                           n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
+                           osum, total_slots, slots);
+    else
+        hipLaunchKernelGGL(k_fused_grad<4>, dim3(unsigned(n_blocks), unsigned(batch)), dim3(64), 0, st, phases, ops,
+                           n_blocks, static_cast<const float*>(params), pstride, static_cast<const cx<float>*>(cmats),
+                           osum, total_slots, slots);
     return hipGetLastError();
 }
 

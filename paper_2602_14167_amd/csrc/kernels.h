@@ -85,11 +85,14 @@ hipError_t launch_pauli_tile(const JobList& jl, const Job& single, int64_t block
 // member b reads its constant matrices at cmats + b * cmstride (cmstride 0: one shared set)
 hipError_t launch_fused_mats(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
                              const void* cmats, int64_t cmstride, int64_t batch, void* out, bool want_rev,
-                             hipStream_t st);
+                             hipStream_t st, int kb = FUSED_K);
 // blocks: tiles * batch (forward), wgs * batch (reverse)
 // m: tile bits of the plan (9..12)
-hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st);
-hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st);
+// kb: block bits of the plan (4, or 5 at m = 12)
+hipError_t launch_fused_fwd(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st,
+                            int kb = FUSED_K);
+hipError_t launch_fused_rev(const JobList& jl, const Job& single, int m, int64_t blocks, hipStream_t st,
+                            int kb = FUSED_K);
 // outer products summed over workgroups (osum: batch * n_blocks * 512), then the
 // gate gradient slots slots[b][slot] (total_slots per member)
 // one circuit of an uneven batch on the fused passes (batch 1): its plan, angles, constant
@@ -112,7 +115,7 @@ hipError_t launch_fused_multi_mats(const FusedCircJob* jobs, int count, int max_
 hipError_t launch_fused_multi_grad(const FusedCircJob* jobs, int count, int max_blocks, hipStream_t st);
 hipError_t launch_fused_grad(const FPhase* phases, const Op* ops, int n_blocks, const void* params, int64_t pstride,
                              const void* cmats, int64_t batch, const double* opart, int wgs, double* osum,
-                             int total_slots, double* slots, hipStream_t st);
+                             int total_slots, double* slots, hipStream_t st, int kb = FUSED_K);
 
 // ---- plain (one kernel per gate / per Pauli X-group)
 template <typename R>

@@ -310,12 +310,14 @@ int column_bit(int m, uint32_t rmask, int c) {
 constexpr int FUSED_SLOT_BUDGET = 1 << 30;
 
 std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params, int m_max, int lo_cfg,
-                       FusedPlan& out) {
+                       FusedPlan& out, int kb) {
     out = FusedPlan();
+    if (kb != 4 && kb != 5) return "fused blocks have 4 or 5 qubits";
     const int m = std::min(n, m_max);
     const int lo = std::min(lo_cfg, m);
-    if (m < FUSED_K + 5) return "tile too small for fused blocks (needs 2^(K+5) amplitudes)";
+    if (m < kb + 5) return "tile too small for fused blocks (needs 2^(K+5) amplitudes)";
     out.m = m;
+    out.k = kb;
     const uint64_t lo_mask = (lo >= 64) ? ~uint64_t(0) : ((uint64_t(1) << lo) - 1);
     const uint64_t all_mask = (n >= 64) ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
     const uint32_t ldst = 0x3Eu;   // tile load / store: 32 lanes vary local bits 1..5
@@ -369,13 +371,13 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
             if ((T >> q) & 1) { qubit_to_local[q] = li; P.local_qubit[li] = q; ++li; }
         if (li != m) return "internal: tile size mismatch";
 
-        // ---- blocks: a gate joins while its qubits fit in FUSED_K local bits
+        // ---- blocks: a gate joins while its qubits fit in kb local bits
         // and no earlier gate of the pass left out shares a qubit with it
         std::vector<uint32_t> rmasks;
         const int first = int(out.phases.size());
         std::vector<int> prem = sel;
         while (!prem.empty()) {
-            if (int(out.phases.size()) - first == FUSED_MAX_BLOCKS) {
+            if (int(out.phases.size()) - first == (kb == 5 ? FUSED5_MAX_BLOCKS : FUSED_MAX_BLOCKS)) {
                 // the rest of the pass goes back to the queue (disjoint from
                 // everything it overtakes, so order is preserved)
                 std::vector<int> back = prem;
@@ -392,7 +394,7 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
                 const uint64_t qm = gate_qmask(g);
                 uint32_t need = 1u << qubit_to_local[g.q0];
                 if (kind_arity(g.kind) == 2) need |= 1u << qubit_to_local[g.q1];
-                if (!(qm & blocked) && popc(R | need) <= FUSED_K) {
+                if (!(qm & blocked) && popc(R | need) <= kb) {
                     R |= need;
                     ph.push_back(gi);
                 } else {
@@ -401,8 +403,10 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
                 }
             }
             prem.swap(rest2);
-            for (int b = m - 1; b >= 0 && popc(R) < FUSED_K; --b) R |= 1u << b;
+            for (int b = m - 1; b >= 0 && popc(R) < kb; --b) R |= 1u << b;
             FPhase F{};
+            F.k = kb;
+            for (int t = 0; t < FUSED_KMAX; ++t) F.R[t] = -1;
             int reg_of_local[MAX_TILE_BITS];
             for (int b = 0; b < MAX_TILE_BITS; ++b) reg_of_local[b] = -1;
             int t = 0, kc = 0;
@@ -449,7 +453,8 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
         // writes its 5 lowest column bits, the store reads bits 1..5.
         // Reverse (phases visited last to first): phase f writes its block
         // bits plus column bit 2 (one float per lane, 32 components of two
-        // columns per 64 lanes).
+        // columns per 64 lanes); with 5 block bits, one half at a time (the top
+        // block bit is fixed in a write).
         const int F = last - first;
         auto lowc = [&](int i) { return low_columns(m, rmasks[i]); };
         lds_layout(m, lowc(0), ldst, P.ld);
@@ -465,7 +470,10 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
 
         FPass Q = P;
         Q.phase_begin = int(out.rphases.size());
-        auto rev_w = [&](int i) { return rmasks[i] | (1u << column_bit(m, rmasks[i], 2)); };
+        auto rev_w = [&](int i) {
+            const uint32_t half = kb == 5 ? (1u << out.phases[first + i].R[4]) : 0u;
+            return (rmasks[i] & ~half) | (1u << column_bit(m, rmasks[i], 2));
+        };
         lds_layout(m, lowc(F - 1), ldst, Q.ld);
         for (int i = F - 1; i >= 0; --i) {
             FPhase Ph = out.phases[first + i];
@@ -487,9 +495,9 @@ std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params,
                 F.rdc[k] = F.C[k] >= 0 ? F.rd[F.C[k]] : 0;
                 F.wrc[k] = F.C[k] >= 0 ? F.wr[F.C[k]] : 0;
             }
-            for (int t = 0; t < FUSED_K; ++t) {
-                F.rdr[t] = F.rd[F.R[t]];
-                F.wrr[t] = F.wr[F.R[t]];
+            for (int t = 0; t < FUSED_KMAX; ++t) {
+                F.rdr[t] = t < F.k ? F.rd[F.R[t]] : 0;
+                F.wrr[t] = t < F.k ? F.wr[F.R[t]] : 0;
             }
         }
 
@@ -556,7 +564,7 @@ bool layout_ok(const int32_t* img, int m, std::initializer_list<uint32_t> pats) 
 
 uint32_t phase_rmask(const FPhase& F) {
     uint32_t r = 0;
-    for (int t = 0; t < FUSED_K; ++t) r |= 1u << F.R[t];
+    for (int t = 0; t < F.k; ++t) r |= 1u << F.R[t];
     return r;
 }
 
@@ -582,7 +590,8 @@ int check_fused_layouts(const FusedPlan& P) {
         auto low = [&](int i) { return low_columns(m, phase_rmask(P.rphases[Q.phase_begin + i])); };
         auto wpat = [&](int i) {
             const FPhase& Ph = P.rphases[Q.phase_begin + i];
-            return phase_rmask(Ph) | (1u << Ph.C[2]);
+            const uint32_t half = Ph.k == 5 ? (1u << Ph.R[4]) : 0u;
+            return (phase_rmask(Ph) & ~half) | (1u << Ph.C[2]);
         };
         bad += !layout_ok(Q.ld, m, {ldst, low(0)});
         for (int i = 0; i < F; ++i) {

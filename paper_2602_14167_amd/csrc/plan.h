@@ -34,6 +34,7 @@ struct CircuitPlan {
 // hold every qubit of their gates, one block matrix per phase.
 struct FusedPlan {
     int m = 0;
+    int k = FUSED_K;                        // block bits of every phase (4 or 5)
     std::vector<FPass> passes, rpasses;     // reverse: phases listed in the order the reverse sweep visits them
     std::vector<FPhase> phases, rphases;
     std::vector<Op> ops;                    // gates of the forward phases (r0/r1 = bit of the block index)
@@ -59,7 +60,7 @@ struct PauliTermHost {
 std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_params, const TileConfig& cfg,
                          CircuitPlan& out);
 std::string plan_fused(int n, const std::vector<tcng_gate>& gates, int n_params, int m_max, int lo,
-                       FusedPlan& out);
+                       FusedPlan& out, int k = FUSED_K);
 // LDS layout of a tile of 2^m amplitudes: img[b] = address of local bit b
 // alone; 32-lane accesses varying the local bits of v_read (5 bits), or of
 // v_write, map to 32 distinct 8-byte bank pairs.

@@ -127,8 +127,8 @@ def test_planner_workloads(P, oracle_mod):
         _check_schedule(P, oracle_mod, cc["n"], cc["gates"], 0, None, cc["mats"], torch.complex64)
 
 
-def _check_fused_schedule(P, oracle_mod, n, gates, n_params, params, mats):
-    order, pass_of, block_of, npass, nblk, bad = P.fused_plan_inspect(n, gates, n_params)
+def _check_fused_schedule(P, oracle_mod, n, gates, n_params, params, mats, k=4):
+    order, pass_of, block_of, npass, nblk, bad = P.fused_plan_inspect(n, gates, n_params, k)
     G = len(gates)
     assert bad == 0                                   # every LDS layout a bank-conflict-free bijection
     assert sorted(order.tolist()) == list(range(G))
@@ -142,10 +142,12 @@ def _check_fused_schedule(P, oracle_mod, n, gates, n_params, params, mats):
                 assert pos[last[q]] < pos[i]
             last[q] = i
     assert np.all(np.diff(pass_of) >= 0) and np.all(np.diff(block_of) >= 0)
-    # a block touches at most 4 qubits
+    # a block touches at most k qubits; a pass holds at most 8 (k = 4) or 4 (k = 5) blocks
     for b in range(nblk):
         qs = set().union(*[qsets[gi] for gi in order[block_of == b]])
-        assert 1 <= len(qs) <= 4
+        assert 1 <= len(qs) <= k
+    for p in range(npass):
+        assert len(set(block_of[pass_of == p].tolist())) <= (8 if k == 4 else 4)
     if n <= 14:
         a = oracle_mod.run(n, gates, params, mats)
         b = oracle_mod.run(n, gates[order], params, mats)
@@ -153,11 +155,11 @@ def _check_fused_schedule(P, oracle_mod, n, gates, n_params, params, mats):
     return npass, nblk
 
 
-@pytest.mark.parametrize("n", [9, 12, 14])
-def test_fused_planner_random_circuits(P, oracle_mod, n):
+@pytest.mark.parametrize("n,k", [(9, 4), (12, 4), (14, 4), (12, 5), (14, 5)])
+def test_fused_planner_random_circuits(P, oracle_mod, n, k):
     r = np.random.default_rng(60 + n)
     gates, params, mats = W.random_circuit(n, 200, r)
-    _check_fused_schedule(P, oracle_mod, n, gates, len(params), params, mats)
+    _check_fused_schedule(P, oracle_mod, n, gates, len(params), params, mats, k)
 
 
 def test_fused_planner_workloads(P, oracle_mod):
@@ -172,7 +174,21 @@ def test_fused_planner_workloads(P, oracle_mod):
         _check_fused_schedule(P, oracle_mod, cc["n"], cc["gates"], 0, None, cc["mats"])
 
 
+def test_fused5_planner_workloads(P, oracle_mod):
+    # 5-qubit blocks hold more gates than 4-qubit ones
+    for w, n in ((W.cfg2(), 28), (W.cfg5(), 32)):
+        _, nb4 = _check_fused_schedule(P, oracle_mod, n, w["gates"], w["n_params"], w["params"], None, 4)
+        _, nb5 = _check_fused_schedule(P, oracle_mod, n, w["gates"], w["n_params"], w["params"], None, 5)
+        assert nb5 < nb4
+    for cc in W.cfg4(count=4, n_lo=12)["circuits"]:
+        _check_fused_schedule(P, oracle_mod, cc["n"], cc["gates"], 0, None, cc["mats"], 5)
+
+
 def test_fused_planner_rejects_small_tiles(P):
     gates = np.array([W.gate(W.RY, 0, p0=0)], np.int32)
     with pytest.raises(P.TcngError):
         P.fused_plan_inspect(8, gates, 1)
+    with pytest.raises(P.TcngError):
+        P.fused_plan_inspect(11, gates, 1, 5)     # 5-qubit blocks need full 12-bit tiles
+    with pytest.raises(P.TcngError):
+        P.fused_plan_inspect(12, gates, 1, 6)

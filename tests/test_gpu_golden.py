@@ -35,7 +35,7 @@ GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 TOL = {"c64": (1e-5, 1e-4), "c128": (1e-12, 1e-12)}
 TDT = {"c64": torch.complex64, "c128": torch.complex128}
 RDT = {"c64": torch.float32, "c128": torch.float64}
-MODES = [("c64", "fused"), ("c64", "tiled"), ("c128", "tiled")]
+MODES = [("c64", "fused"), ("c64", "fused5"), ("c64", "tiled"), ("c128", "tiled")]
 
 
 @pytest.fixture(scope="module")

@@ -21,6 +21,10 @@ from tests.bars import assert_amps
 pytestmark = pytest.mark.gpu
 
 TOL = {"c64": dict(E=1e-5, g=1e-4, amp=2e-5), "c128": dict(E=1e-12, g=1e-12, amp=1e-12)}
+# (precision, mode) pairs: complex128 has no matrix-core plan (its "fused" runs the tiled passes);
+# "fused5" is the 5-qubit-block plan (complex64, n >= 12; smaller states run the 4-qubit plan)
+DM = [("c64", "tiled"), ("c64", "plain"), ("c64", "fused"), ("c64", "fused5"), ("c128", "tiled"), ("c128", "plain"),
+      ("c128", "fused")]
 TDT = {"c64": torch.complex64, "c128": torch.complex128}
 
 
@@ -118,8 +122,7 @@ def test_chunked_gates_every_target(P, oracle_mod, dtype, n):
 # circuits
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("dtype,mode", DM)
 @pytest.mark.parametrize("n", [1, 2, 5, 9, 10, 11, 12, 13, 14, 16])
 def test_run_circuit_random_all_kinds(P, oracle_mod, dtype, mode, n):
     r = np.random.default_rng(100 + n)
@@ -145,8 +148,7 @@ def test_tiled_and_plain_agree_on_hea(P, dtype):
 # Pauli expectations
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("dtype,mode", DM)
 @pytest.mark.parametrize("n,kind", [(3, "random"), (11, "random"), (12, "tfim"), (15, "xxz"), (16, "2local"),
                                     (16, "random")])
 def test_expect_pauli_matches_oracle(P, oracle_mod, dtype, mode, n, kind):
@@ -222,8 +224,7 @@ def test_cfg1_state_energy_gradient_c128(P, oracle_mod, mode):
     check_expect_grad(P, oracle_mod, 10, c["gates"], c["params"][None, :], None, c["codes"], c["coeffs"], "c128", mode)
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("dtype,mode", DM)
 def test_hea_tfim_batched(P, oracle_mod, dtype, mode):
     """Reduced-size instance of the n=28 HEA/TFIM workload (same generator), batch 3."""
     c = W.cfg2(n=16, layers=3)
@@ -232,16 +233,14 @@ def test_hea_tfim_batched(P, oracle_mod, dtype, mode):
     check_expect_grad(P, oracle_mod, 16, c["gates"], pb, None, c["codes"], c["coeffs"], dtype, mode)
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("dtype,mode", DM)
 def test_xxz_batched(P, oracle_mod, dtype, mode):
     """Batched XXZ workload (n=16, L=8) on a subset of parameter sets."""
     c = W.cfg3(batch=4)
     check_expect_grad(P, oracle_mod, 16, c["gates"], c["params"], None, c["codes"], c["coeffs"], dtype, mode)
 
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("dtype,mode", DM)
 @pytest.mark.parametrize("n", [5, 11, 12, 14])
 def test_random_circuits_all_kinds_with_gate_gradients(P, oracle_mod, dtype, mode, n):
     r = np.random.default_rng(500 + n)
@@ -254,14 +253,14 @@ def test_random_circuits_all_kinds_with_gate_gradients(P, oracle_mod, dtype, mod
     check_expect_grad(P, oracle_mod, n, gates, pb, mats, codes, coeffs, dtype, mode, lie=True, init=init)
 
 
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused", "fused5"])
 def test_fsim_brickwork_2d_tfim(P, oracle_mod, mode):
     """Reduced-size instance of the n=32 fSim / 2D TFIM workload: 4x4 lattice, depth 8."""
     c = W.cfg5(rows=4, cols=4, depth=8)
     check_expect_grad(P, oracle_mod, 16, c["gates"], c["params"][None, :], None, c["codes"], c["coeffs"], "c64", mode)
 
 
-@pytest.mark.parametrize("mode", ["tiled", "plain", "fused"])
+@pytest.mark.parametrize("mode", ["tiled", "plain", "fused", "fused5"])
 def test_haar_brickwork_lie_gradients(P, oracle_mod, mode):
     """Haar brick-wall circuits with random 2-local H (the uneven-batch generator, small n)."""
     c = W.cfg4(count=3, n_lo=11, n_hi=14, d_lo=2, d_hi=6, seed=44)
@@ -270,7 +269,29 @@ def test_haar_brickwork_lie_gradients(P, oracle_mod, mode):
                           cc["coeffs"], "c64", mode, lie=True)
 
 
-@pytest.mark.parametrize("dtype,mode", [("c64", "fused"), ("c64", "tiled"), ("c128", "tiled")])
+def test_fused5_plan_is_used(P, oracle_mod):
+    """The 5-qubit-block plan exists from 12 qubits on and its run differs in
+    rounding from the 4-qubit plan's, both within the bar of the oracle."""
+    n = 14
+    r = np.random.default_rng(700)
+    gates, params, mats = W.random_circuit(n, 120, r)
+    codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=3)
+    assert P.fused_plan_inspect(n, gates, len(params), 5)[4] < P.fused_plan_inspect(n, gates, len(params), 4)[4]
+    circ = P.Circuit(n, gates, len(params), W.round_mats(mats, "c64"))
+    H = P.PauliSum(n, codes, coeffs)
+    p = dev(params[None], torch.float32)
+    E4, g4 = P.expect_grad(circ, p, H, mode="fused")
+    E5, g5 = P.expect_grad(circ, p, H, mode="fused5")
+    torch.cuda.synchronize()
+    assert not torch.equal(g4, g5)
+    ref = oracle_mod.expect_grad(n, gates, W.round_params(params, "c64"), codes, coeffs, W.round_mats(mats, "c64"))
+    S = np.abs(coeffs).sum()
+    for E, g in ((E4, g4), (E5, g5)):
+        assert abs(float(E[0]) - ref["E"]) <= 1e-5 * S
+        assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= 1e-4 * S
+
+
+@pytest.mark.parametrize("dtype,mode", [("c64", "fused"), ("c64", "fused5"), ("c64", "tiled"), ("c128", "tiled")])
 @pytest.mark.parametrize("n", [16, 20])
 def test_full_weight_pauli_terms_match_oracle(P, oracle_mod, n, dtype, mode):
     """Terms whose X-mask spans more qubits than a tile (X on every qubit,
@@ -329,7 +350,7 @@ def test_autograd_gradcheck_and_shift_rule_c128(P, mode):
     assert np.max(np.abs(g)) > 1e-2
 
 
-@pytest.mark.parametrize("mode", ["tiled", "fused"])
+@pytest.mark.parametrize("mode", ["tiled", "fused", "fused5"])
 def test_autograd_shift_rule_and_differences_c64(P, mode):
     """TcngEnergy in complex64 (float32 angles): its gradient against the
     two-term shift rule and a fourth-order central difference (h = 0.05),
@@ -421,11 +442,20 @@ def test_autotune_picks_an_available_tiling_and_keeps_results(P, oracle_mod, tmp
     circ2 = P.Circuit(15, c["gates"], c["n_params"])
     cfg2, ms2 = P.autotune(circ2, p, H, psi, repeats=2, cache_path=cache)
     assert cfg2 == cfg and ms2 == pytest.approx(ms)
+    # the choice among tiled, fused and fused5 is the circuit's "auto" mode
+    assert circ.mode() in ("tiled", "fused", "fused5") and circ2.mode() == circ.mode()
+    print(f"autotune n=15: mode {circ.mode()}, tiling {cfg}, {ms:.3f} ms", flush=True)
     ref = oracle_mod.expect_grad(15, c["gates"], W.round_params(c["params"], "c64"), c["codes"], c["coeffs"])
-    E, g = P.expect_grad(circ, p, H)
     S = np.abs(c["coeffs"]).sum()
-    assert abs(E.item() - ref["E"]) <= 1e-5 * S
-    assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= 1e-4 * S
+    for mode in ("tiled", "auto"):
+        E, g = P.expect_grad(circ, p, H, mode=mode)
+        assert abs(E.item() - ref["E"]) <= 1e-5 * S
+        assert np.max(np.abs(g.cpu().numpy()[0] - ref["grad"])) <= 1e-4 * S
+    # complex128: the tiled tilings only
+    circ3 = P.Circuit(15, c["gates"], c["n_params"])
+    assert circ3.mode(torch.complex128) == "tiled" and circ3.mode() == "fused"   # defaults before tuning
+    P.autotune(circ3, dev(c["params"][None, :], torch.float64), H, P.new_state(15, 1, torch.complex128), repeats=1)
+    assert circ3.mode(torch.complex128) == "tiled"
 
 
 # complex64 batches run on the matrix-core passes (one launch per tile size:
@@ -468,7 +498,8 @@ def test_uneven_batch_matches_oracle(P, oracle_mod, dtype, n_lo):
 # graph capture: replays with new angles written into the captured buffer
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dtype,mode", [("c64", "fused"), ("c64", "tiled"), ("c64", "plain"), ("c128", "tiled")])
+@pytest.mark.parametrize("dtype,mode", [("c64", "fused"), ("c64", "fused5"), ("c64", "tiled"), ("c64", "plain"),
+                                        ("c128", "tiled")])
 def test_graph_replays_match_eager_and_oracle(P, oracle_mod, dtype, mode):
     n = 12
     c = W.cfg2(n=n, layers=3)
