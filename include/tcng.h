@@ -206,6 +206,25 @@ tcng_status tcng_pauli_sum_create(int32_t n_qubits, const uint8_t* codes, const 
                                   tcng_pauli_sum** out);
 tcng_status tcng_pauli_sum_destroy(tcng_pauli_sum* h);
 
+/* An uneven batch bound once to its circuits, Pauli sums, angle buffers,
+ * states, outputs and workspace (arguments as for tcng_expect_grad_multi):
+ * the launch tables are built on the host and copied into the workspace here
+ * (after the device is idle; synchronises), so tcng_multi_launch enqueues
+ * kernels only and can be captured in a graph (tcng_graph_create_multi) and
+ * replayed; new angles are written into the same buffers between launches.
+ * init_basis >= 0: every launch starts each circuit from |init_basis> (the
+ * matrix-core first pass forms its tiles without reading the state; the tiled
+ * path sets the states first); -1: from the states' contents, as
+ * tcng_expect_grad_multi.  The handle, the workspace and every bound buffer
+ * must outlive the launches; handles own no device memory. */
+typedef struct tcng_multi tcng_multi;
+tcng_status tcng_multi_create(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                              const void* const* params, const tcng_state* psi, const tcng_state* lam, double* energy,
+                              double* const* grad, double* const* gate_grad, int64_t init_basis, void* ws,
+                              size_t ws_bytes, tcng_multi** out);
+tcng_status tcng_multi_launch(const tcng_multi* m, void* stream);
+tcng_status tcng_multi_destroy(tcng_multi* m);
+
 /* Matrix-free Pauli-sum operator (Sec. "Time Evolution": the sparse
  * matrix-vector product of Krylov and Chebyshev evolution):
  * out_b = H psi_b for every batch member, and, if energy is not NULL,
@@ -336,6 +355,8 @@ tcng_status tcng_graph_create(const tcng_circuit* c, const void* params, const t
                               double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, int64_t init_basis,
                               tcng_graph** out);
 tcng_status tcng_graph_launch(tcng_graph* g, void* stream);
+/* One launch of a bound uneven batch (tcng_multi_launch) recorded as a graph. */
+tcng_status tcng_graph_create_multi(const tcng_multi* m, tcng_graph** out);
 tcng_status tcng_graph_destroy(tcng_graph* g);
 
 /* Host-only inspection of the fused planner (TCNG_MODE_FUSED with

@@ -21,7 +21,7 @@ from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_AUTO, TCNG_MODE_FUSED, TCNG_MO
                    TCNG_MODE_PLAIN, TCNG_MODE_TILED, TCNG_U1_KIND,
                    TcngError, TcngGate, TcngState, check, lib)
 
-__all__ = ["expect_grad_multi", "expect_grad_noalloc", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
+__all__ = ["expect_grad_multi", "Multi", "expect_grad_noalloc", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
            "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
            "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots", "qml_step"]
 
@@ -358,6 +358,85 @@ def expect_grad_multi(circs, hams, params_list, dtype=torch.complex64, psis=None
                                        ggp if want_gate_grad else None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream()))
     return energy, grads, (ggs if want_gate_grad else None)
+
+
+class Multi:
+    """An uneven batch bound once (tcng_multi_*): circuits, Pauli sums, angle
+    tensors (written in place between launches), states, outputs and
+    workspace.  launch() enqueues one evaluation (kernels only); graph()
+    records one as a replayable graph.  init_basis >= 0 starts every circuit
+    from that basis state at each launch; -1 from the states' contents."""
+
+    def __init__(self, circs, hams, params_list, dtype=torch.complex64, psis=None, want_gate_grad=False,
+                 init_basis=0, ws=None):
+        count = len(circs)
+        dev = torch.device("cuda")
+        rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+        self.psis = psis if psis is not None else [new_state(c.n, 1, dtype) for c in circs]
+        self.lams = [torch.empty_like(p) for p in self.psis]
+        st_psi = (TcngState * count)(*[_state(p, c.n) for p, c in zip(self.psis, circs)])
+        st_lam = (TcngState * count)(*[_state(l, c.n) for l, c in zip(self.lams, circs)])
+        ch = (ctypes.c_void_p * count)(*[c.handle.value for c in circs])
+        hh = (ctypes.c_void_p * count)(*[h.handle.value for h in hams])
+        pp = (ctypes.c_void_p * count)()
+        gp = (ctypes.c_void_p * count)()
+        ggp = (ctypes.c_void_p * count)()
+        self.params, self.grads, self.gate_grads = [], [], []
+        for i, c in enumerate(circs):
+            if c.n_params:
+                t = params_list[i]
+                if t.dtype != rdt or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError("angle tensors must be contiguous device tensors of the run's real type")
+                self.params.append(t)
+                pp[i] = t.data_ptr()
+            g = torch.empty(max(c.n_params, 1), dtype=torch.float64, device=dev)
+            self.grads.append(g[: c.n_params])
+            gp[i] = g.data_ptr()
+            if want_gate_grad:
+                gg = torch.empty((c.n_gates, 15), dtype=torch.float64, device=dev)
+                self.gate_grads.append(gg)
+                ggp[i] = gg.data_ptr()
+        if ws is None:
+            nbytes = ctypes.c_size_t()
+            check(lib().tcng_workspace_size_multi(ch, hh, count, _dt(dtype), ctypes.byref(nbytes)))
+            ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        self.ws = ws
+        self.energy = torch.empty(count, dtype=torch.float64, device=dev)
+        self.keep = (circs, hams)
+        h = ctypes.c_void_p()
+        check(lib().tcng_multi_create(ch, hh, count, pp, st_psi, st_lam, ctypes.c_void_p(self.energy.data_ptr()), gp,
+                                      ggp if want_gate_grad else None, int(init_basis),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(h)))
+        self.handle = h
+        self.graph_handle = None
+
+    def launch(self):
+        check(lib().tcng_multi_launch(self.handle, _stream()))
+        return self.energy, self.grads, (self.gate_grads or None)
+
+    def graph(self):
+        """Capture one launch; returns a callable that replays it."""
+        g = ctypes.c_void_p()
+        check(lib().tcng_graph_create_multi(self.handle, ctypes.byref(g)))
+        self.graph_handle = g
+
+        def replay():
+            check(lib().tcng_graph_launch(g, _stream()))
+            return self.energy, self.grads, (self.gate_grads or None)
+        return replay
+
+    def close(self):
+        if _lib._lib is None:
+            return
+        if getattr(self, "graph_handle", None) is not None:
+            lib().tcng_graph_destroy(self.graph_handle)
+            self.graph_handle = None
+        if getattr(self, "handle", None) is not None:
+            lib().tcng_multi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 class Graph:

@@ -27,7 +27,8 @@ EXPORTS = [
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
     "tcng_shadow_workspace_size", "tcng_shadow_snapshots", "tcng_qml_workspace_size", "tcng_qml_step",
-    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes", "tcng_circuit_get_mode",
+    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes", "tcng_circuit_get_mode", "tcng_multi_create",
+    "tcng_multi_launch", "tcng_multi_destroy", "tcng_graph_create_multi",
 ]
 
 
@@ -78,6 +79,10 @@ def lib():
     L.tcng_noalloc_scratch_bytes.argtypes = []
     L.tcng_workspace_size_multi.argtypes = [P, P, i32, i32, ctypes.POINTER(sz)]
     L.tcng_expect_grad_multi.argtypes = [P, P, i32, P, PS, PS, P, P, P, P, sz, P]
+    L.tcng_multi_create.argtypes = [P, P, i32, P, PS, PS, P, P, P, i64, P, sz, ctypes.POINTER(P)]
+    L.tcng_multi_launch.argtypes = [P, P]
+    L.tcng_multi_destroy.argtypes = [P]
+    L.tcng_graph_create_multi.argtypes = [P, ctypes.POINTER(P)]
     L.tcng_circuit_configure.argtypes = [P, i32, i32, i32, i32]
     L.tcng_circuit_get_config.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.tcng_circuit_get_mode.argtypes = [P, i32, ctypes.POINTER(i32)]

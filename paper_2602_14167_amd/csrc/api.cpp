@@ -1068,6 +1068,49 @@ struct tcng_graph {
     hipGraphExec_t exec = nullptr;
 };
 
+}  // extern "C"
+
+namespace {
+// records `body` (stream-ordered launches only) on a private stream as a graph
+template <typename F>
+tcng_status capture_graph(F body, tcng_graph** out) {
+    if (!out) return fail(TCNG_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (g_prof.on) return fail(TCNG_E_INVALID, "stop profiling before capturing a graph");
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        return fail(TCNG_E_HIP, "stream capture could not start");
+    }
+    const tcng_status e = body(st);
+    const std::string why = e ? std::string(tcng_last_error()) : std::string();
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    (void)hipStreamDestroy(st);
+    if (e) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(e, why);
+    }
+    if (ec != hipSuccess || !graph) return fail(TCNG_E_HIP, "stream capture failed");
+    auto* g = new (std::nothrow) tcng_graph();
+    if (!g) {
+        (void)hipGraphDestroy(graph);
+        return fail(TCNG_E_ALLOC, "host allocation failed");
+    }
+    g->graph = graph;
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return fail(TCNG_E_HIP, "graph instantiation failed");
+    }
+    *out = g;
+    return ok();
+}
+}  // namespace
+
+extern "C" {
+
 tcng_status tcng_graph_create(const tcng_circuit* c, const void* params, const tcng_pauli_sum* h,
                               const tcng_state* psi, const tcng_state* lam, double* energy, double* grad,
                               double* gate_grad, int32_t mode, void* ws, size_t ws_bytes, int64_t init_basis,
@@ -1589,106 +1632,64 @@ MultiLayout multi_layout(const tcng_circuit* const* circs, const tcng_pauli_sum*
     return L;
 }
 
-template <typename R, int RB, int RBR, int RBP = PAULI_RB>
-tcng_status run_multi(const std::vector<Job>& jobs, const tcng_circuit* const* circs,
-                      const tcng_pauli_sum* const* hams, int count, int dt, const MultiLayout& L, char* ws,
-                      hipStream_t st) {
-    // order per sweep: circuits with more passes first, so launch k covers a prefix of the order
-    std::vector<int> ord_c(count), ord_p(count);
-    for (int i = 0; i < count; ++i) ord_c[i] = ord_p[i] = i;
-    std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) { return jobs[x].n_passes > jobs[y].n_passes; });
-    std::stable_sort(ord_p.begin(), ord_p.end(), [&](int x, int y) { return jobs[x].n_ppasses > jobs[y].n_ppasses; });
-    const int* orders[3] = {ord_c.data(), ord_p.data(), ord_c.data()};
-    int nt_max[3] = {64, 64, 64};
-    int max_steps[3] = {0, 0, 0};
-    std::vector<int64_t> prefix_host[3];
-    for (int k = 0; k < 3; ++k) {
-        std::vector<Job> sorted(count);
-        prefix_host[k].assign(count + 1, 0);
-        for (int i = 0; i < count; ++i) {
-            const Job& J = jobs[orders[k][i]];
-            sorted[i] = J;
-            const int64_t per = (k == 0) ? J.tiles : (k == 1 ? J.e_wgs : J.wgs);
-            prefix_host[k][i + 1] = prefix_host[k][i] + per * J.batch;
-            const int m = (k == 1) ? hams[orders[k][i]]->tplan[dt].passes[0].m
-                                   : circs[orders[k][i]]->tiled[dt].host.passes[0].m;
-            const int rbk = (k == 2) ? RBR : (k == 1 ? RBP : RB);
-            nt_max[k] = std::max(nt_max[k], 1 << (m - rbk));
-            max_steps[k] = std::max(max_steps[k], k == 1 ? J.n_ppasses : J.n_passes);
-        }
-        HIP_TRY(hipMemcpyAsync(ws + L.jobs_off[k], sorted.data(), sizeof(Job) * count, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(ws + L.prefix_off[k], prefix_host[k].data(), sizeof(int64_t) * (count + 1),
-                               hipMemcpyHostToDevice, st));
-    }
-    // number of jobs of each sweep taking part in step k
-    auto active = [&](int sweep, int k) {
-        int c = 0;
-        for (int i = 0; i < count; ++i) {
-            const Job& J = jobs[orders[sweep][i]];
-            if ((sweep == 1 ? J.n_ppasses : J.n_passes) > k) ++c;
-        }
-        return c;
-    };
-    for (int k = 0; k < max_steps[0]; ++k) {
-        const int na = active(0, k);
-        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[0]),
-                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[0]), na, k};
-        PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, jobs[0], prefix_host[0][na], nt_max[0], st)));
-    }
-    for (int k = 0; k < max_steps[1]; ++k) {
-        const int na = active(1, k);
-        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[1]),
-                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[1]), na, k};
-        PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<R, RBP>(jl, jobs[0], prefix_host[1][na], nt_max[1], st)));
-    }
-    for (int k = 0; k < max_steps[2]; ++k) {
-        const int na = active(2, k);
-        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[2]),
-                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[2]), na, k};
-        PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RBR>(jl, jobs[0], prefix_host[2][na], nt_max[2], st)));
-    }
-    (void)circs;
-    return TCNG_OK;
-}
+// One launch of an uneven batch: step `step` of a sweep (0 forward, 1 Pauli,
+// 2 reverse) over the first `njobs` jobs of the sorted job list at `job_off`
+// (prefix sums at `prefix_off`); `m` selects the fused kernels' tile-size
+// instantiation.
+struct MultiLaunch {
+    int sweep, step, njobs, m;
+    int job_off, prefix_off;
+    int64_t blocks;
+};
 
-// fused sweeps of an uneven batch: the k-th forward / reverse pass of every
-// circuit that has one in one launch per tile-size group (12-bit tiles, and
-// the smaller ones of circuits below 12 qubits), circuits ordered by pass
-// count inside a group; the Pauli passes as in the tiled sweeps
-tcng_status run_multi_fused(const std::vector<Job>& jobs, const tcng_pauli_sum* const* hams, int count, int dt,
-                            const MultiLayout& L, char* ws, hipStream_t st) {
-    auto group = [&](int i) { return jobs[i].n < FUSED_M ? 1 : 0; };
+// Sorted job lists and the launches of every sweep.  Circuits with more
+// passes come first in each list, so the jobs of step k are a prefix.
+// Fused (complex64): the forward and reverse lists hold the circuits of
+// 12-bit tiles first, then those of smaller tiles, each group with its own
+// prefix sums and launches.
+struct MultiPlan {
+    std::vector<Job> sorted[3];
+    std::vector<int64_t> prefix[3];
+    std::vector<MultiLaunch> launches;
+    int nt_max[3] = {64, 64, 64};
+};
+
+MultiPlan multi_plan(const std::vector<Job>& jobs, const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams,
+                     int count, int dt, bool fused, int rb, int rbr) {
+    MultiPlan M;
+    auto group = [&](int i) { return (fused && jobs[i].n < FUSED_M) ? 1 : 0; };
     std::vector<int> ord_c(count), ord_p(count);
     for (int i = 0; i < count; ++i) ord_c[i] = ord_p[i] = i;
     std::stable_sort(ord_c.begin(), ord_c.end(), [&](int x, int y) {
         return group(x) != group(y) ? group(x) < group(y) : jobs[x].n_passes > jobs[y].n_passes;
     });
     std::stable_sort(ord_p.begin(), ord_p.end(), [&](int x, int y) { return jobs[x].n_ppasses > jobs[y].n_ppasses; });
-    int g0 = 0;   // jobs of group 0 (12-bit tiles) come first
+    int g0 = 0;   // jobs of group 0 come first
     while (g0 < count && group(ord_c[g0]) == 0) ++g0;
     const int* orders[3] = {ord_c.data(), ord_p.data(), ord_c.data()};
-    int pauli_nt = 64, max_steps[3] = {0, 0, 0};
+    int max_steps[3] = {0, 0, 0};
     // prefix entries: group 0 at [0, g0], group 1 at [g0 + 1, count + 1] (each from 0); the Pauli sweep at [0, count]
-    std::vector<int64_t> prefix_host[3];
     for (int k = 0; k < 3; ++k) {
-        std::vector<Job> sorted(count);
-        prefix_host[k].assign(count + 2, 0);
+        M.sorted[k].resize(count);
+        M.prefix[k].assign(count + 2, 0);
         for (int i = 0; i < count; ++i) {
-            const Job& J = jobs[orders[k][i]];
-            sorted[i] = J;
+            const int ci = orders[k][i];
+            const Job& J = jobs[ci];
+            M.sorted[k][i] = J;
             const int64_t per = (k == 0) ? J.tiles : (k == 1 ? J.e_wgs : J.wgs);
             const int at = (k != 1 && i >= g0) ? i + 1 : i;   // group 1 entries one further on
-            prefix_host[k][at + 1] = prefix_host[k][at] + per * J.batch;
-            if (k == 1 && !hams[orders[k][i]]->tplan[dt].passes.empty())
-                pauli_nt = std::max(pauli_nt, 1 << (hams[orders[k][i]]->tplan[dt].passes[0].m - PAULI_RB));
+            M.prefix[k][at + 1] = M.prefix[k][at] + per * J.batch;
+            if (k == 1) {
+                if (!hams[ci]->tplan[dt].passes.empty())
+                    M.nt_max[1] = std::max(M.nt_max[1], 1 << (hams[ci]->tplan[dt].passes[0].m - PAULI_RB));
+            } else if (!fused) {
+                const int rbk = k == 2 ? rbr : rb;
+                M.nt_max[k] = std::max(M.nt_max[k], 1 << (circs[ci]->tiled[dt].host.passes[0].m - rbk));
+            }
             max_steps[k] = std::max(max_steps[k], k == 1 ? J.n_ppasses : J.n_passes);
         }
-        if (k != 1 && g0 < count) prefix_host[k][g0 + 1] = 0;   // group 1 starts its own count
-        HIP_TRY(hipMemcpyAsync(ws + L.jobs_off[k], sorted.data(), sizeof(Job) * count, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(ws + L.prefix_off[k], prefix_host[k].data(), sizeof(int64_t) * (count + 2),
-                               hipMemcpyHostToDevice, st));
+        if (k != 1 && g0 < count) M.prefix[k][g0 + 1] = 0;   // group 1 starts its own count
     }
-    // jobs of sorted positions [lo, hi) taking part in step k (a prefix of the range)
     auto active = [&](int sweep, int k, int lo, int hi) {
         int c = 0;
         for (int i = lo; i < hi; ++i) {
@@ -1697,31 +1698,253 @@ tcng_status run_multi_fused(const std::vector<Job>& jobs, const tcng_pauli_sum* 
         }
         return c;
     };
-    // sweeps 0 and 2: one launch per group with active jobs
-    auto launch_group = [&](int sweep, int k, int grp) -> tcng_status {
-        const int lo = grp == 0 ? 0 : g0, hi = grp == 0 ? g0 : count;
-        const int na = active(sweep, k, lo, hi);
-        if (na == 0) return TCNG_OK;
-        const int poff = grp == 0 ? 0 : g0 + 1;
-        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[sweep]) + lo,
-                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[sweep]) + poff, na, k};
-        const int64_t blocks = prefix_host[sweep][poff + na];
-        const int m = grp == 0 ? FUSED_M : FUSED_M - 1;   // selects the kernel's tile-size instantiation
-        if (sweep == 0) PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, jobs[0], m, blocks, st));
-        else PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, jobs[0], m, blocks, st));
-        return TCNG_OK;
+    auto add_circuit_steps = [&](int sweep) {
+        for (int k = 0; k < max_steps[sweep]; ++k)
+            for (int grp = 0; grp < 2; ++grp) {
+                const int lo = grp == 0 ? 0 : g0, hi = grp == 0 ? g0 : count;
+                const int na = active(sweep, k, lo, hi);
+                if (na == 0) continue;
+                const int poff = grp == 0 ? 0 : g0 + 1;
+                M.launches.push_back({sweep, k, na, grp == 0 ? FUSED_M : FUSED_M - 1, lo, poff, M.prefix[sweep][poff + na]});
+            }
     };
-    for (int k = 0; k < max_steps[0]; ++k)
-        for (int grp = 0; grp < 2; ++grp)
-            if (tcng_status e = launch_group(0, k, grp)) return e;
+    add_circuit_steps(0);
     for (int k = 0; k < max_steps[1]; ++k) {
-        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[1]),
-                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[1]), active(1, k, 0, count), k};
-        PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<float, PAULI_RB>(jl, jobs[0], prefix_host[1][jl.njobs], pauli_nt, st)));
+        const int na = active(1, k, 0, count);
+        M.launches.push_back({1, k, na, 0, 0, 0, M.prefix[1][na]});
     }
-    for (int k = 0; k < max_steps[2]; ++k)
-        for (int grp = 0; grp < 2; ++grp)
-            if (tcng_status e = launch_group(2, k, grp)) return e;
+    add_circuit_steps(2);
+    return M;
+}
+
+template <typename R, int RB, int RBR>
+tcng_status launch_multi_tiled(const MultiPlan& M, const Job& job0, char* ws, const MultiLayout& L, hipStream_t st) {
+    for (const MultiLaunch& X : M.launches) {
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[X.sweep]) + X.job_off,
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[X.sweep]) + X.prefix_off, X.njobs,
+                         X.step};
+        if (X.sweep == 0) PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, job0, X.blocks, M.nt_max[0], st)));
+        else if (X.sweep == 1) PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<R, PAULI_RB>(jl, job0, X.blocks, M.nt_max[1], st)));
+        else PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RBR>(jl, job0, X.blocks, M.nt_max[2], st)));
+    }
+    return TCNG_OK;
+}
+
+tcng_status launch_multi_fused(const MultiPlan& M, const Job& job0, char* ws, const MultiLayout& L, hipStream_t st) {
+    for (const MultiLaunch& X : M.launches) {
+        const JobList jl{reinterpret_cast<const Job*>(ws + L.jobs_off[X.sweep]) + X.job_off,
+                         reinterpret_cast<const int64_t*>(ws + L.prefix_off[X.sweep]) + X.prefix_off, X.njobs,
+                         X.step};
+        if (X.sweep == 0) PROF_TRY(F_FUSED_FWD, launch_fused_fwd(jl, job0, X.m, X.blocks, st));
+        else if (X.sweep == 1) PROF_TRY(F_PAULI_TILE, (launch_pauli_tile<float, PAULI_RB>(jl, job0, X.blocks, M.nt_max[1], st)));
+        else PROF_TRY(F_FUSED_REV, launch_fused_rev(jl, job0, X.m, X.blocks, st));
+    }
+    return TCNG_OK;
+}
+
+}  // namespace
+
+// An uneven batch bound to its states, outputs and workspace: the host tables
+// (sorted job lists, prefix sums, matrix-build, block and finish jobs) and the
+// launch list, built once; the tables live in the workspace.
+struct tcng_multi {
+    int count = 0, dt = 0, rb = 0, rbr = 0;
+    MultiLayout L;
+    char* ws = nullptr;
+    MultiPlan plan;
+    Job job0{};
+    std::vector<BuildJob> builds;
+    std::vector<FinishJob> fins;
+    std::vector<FusedCircJob> fjobs;
+    std::vector<int64_t> bprefix, fprefix;
+    int64_t init_basis = -1;               // tiled path: states set to |basis> at launch (fused: in the first pass)
+    std::vector<tcng_state> psi;
+    bool uploaded = false;
+};
+
+namespace {
+
+tcng_status multi_build(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                        const void* const* params, const tcng_state* psi, const tcng_state* lam, double* energy,
+                        double* const* grad, double* const* gate_grad, int64_t init_basis, void* ws, size_t ws_bytes,
+                        tcng_multi& M) {
+    if (!psi || !lam || !energy) return fail(TCNG_E_INVALID, "null argument");
+    const int dt = psi[0].dtype;
+    if (tcng_status e = multi_check(circs, hams, count, dt)) return e;
+    for (int i = 0; i < count; ++i) {
+        if (tcng_status e = check_state(&psi[i], "tcng_expect_grad_multi(psi)")) return e;
+        if (tcng_status e = check_state(&lam[i], "tcng_expect_grad_multi(lam)")) return e;
+        if (psi[i].dtype != dt || lam[i].dtype != dt || psi[i].batch != 1 || lam[i].batch != 1 ||
+            psi[i].n_qubits != circs[i]->n || lam[i].n_qubits != circs[i]->n || psi[i].amps == lam[i].amps)
+            return fail(TCNG_E_INVALID, "uneven batch: states must be single, distinct and match their circuits");
+        if (circs[i]->n_params > 0 && (!params || !params[i] || !grad || !grad[i]))
+            return fail(TCNG_E_INVALID, "uneven batch: missing angles or gradient output");
+        if (init_basis >= (int64_t(1) << circs[i]->n))
+            return fail(TCNG_E_INVALID, "uneven batch: basis index out of range");
+    }
+    M.L = multi_layout(circs, hams, count, dt);
+    const MultiLayout& L = M.L;
+    if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
+    char* w = static_cast<char*>(ws);
+    M.ws = w;
+    M.count = count;
+    M.dt = dt;
+    M.init_basis = init_basis;
+    M.psi.assign(psi, psi + count);
+    M.rb = circs[0]->tiled[dt].host.cfg.rb;
+    M.rbr = circs[0]->tiled[dt].host.cfg.rb_rev;
+    std::vector<Job> jobs(count);
+    M.builds.resize(count);
+    M.fins.resize(count);
+    M.bprefix.assign(count + 1, 0);
+    M.fprefix.assign(count + 1, 0);
+    double* part = reinterpret_cast<double*>(w + L.part_off);
+    double* epart = reinterpret_cast<double*>(w + L.epart_off);
+    double* ssum = reinterpret_cast<double*>(w + L.ssum_off);
+    double* esum = reinterpret_cast<double*>(w + L.esum_off);
+    for (int i = 0; i < count; ++i) {
+        const tcng_circuit* c = circs[i];
+        const tcng_pauli_sum* h = hams[i];
+        WsLayout Li;
+        Li.fused = L.fused;
+        Li.total_slots = std::max(L.fused ? c->fused.host.total_slots : c->tiled[dt].host.total_slots, 1);
+        Li.rev_wgs = L.fused ? L.fwgs[i] : MULTI_WGS;
+        Li.e_rows = std::max<int>(int(h->tplan[dt].passes.size()), 1);
+        Li.e_wgs = MULTI_EWGS;
+        jobs[i] = make_job(c, h, &psi[i], lam[i].amps, w + L.opm_off[i], part + L.slot_row[i] * MULTI_WGS,
+                           epart + L.erow_row[i] * MULTI_EWGS, Li);
+        if (L.fused) {
+            jobs[i].fmats = w + L.fmats_off[i];
+            jobs[i].opart = reinterpret_cast<double*>(w + L.opart_off[i]);
+            if (init_basis >= 0) jobs[i].init_basis1 = init_basis + 1;
+        }
+        M.builds[i] = BuildJob{c->tiled[dt].ops, params ? params[i] : nullptr, c->cm[dt], w + L.opm_off[i],
+                               int32_t(c->gates.size()), 0};
+        M.bprefix[i + 1] = M.bprefix[i] + int64_t(c->gates.size());
+        const SlotTables& S = L.fused ? c->fused.slots : c->tiled[dt].slots;
+        FinishJob F{};
+        F.slots = L.fused ? reinterpret_cast<double*>(w + L.fslot_off[i]) : ssum + L.slot_row[i];
+        F.erow = esum + L.erow_row[i];
+        F.slot_ptr = S.ptr;
+        F.slot_idx = S.idx;
+        F.gate_slot = S.gate_slot;
+        F.u2m = c->u2m[dt];
+        F.gate_mat = c->gate_mat;
+        F.energy = energy + i;
+        F.grad = (grad && c->n_params) ? grad[i] : nullptr;
+        F.gate_grad = gate_grad ? gate_grad[i] : nullptr;
+        F.n_params = c->n_params;
+        F.n_gates = int32_t(c->gates.size());
+        F.erows = Li.e_rows;
+        M.fins[i] = F;
+        M.fprefix[i + 1] = M.fprefix[i] + 1 + c->n_params + (F.gate_grad ? int64_t(c->gates.size()) : 0);
+    }
+    if (L.fused) {
+        M.fjobs.resize(count);
+        for (int i = 0; i < count; ++i) {
+            const DevFusedPlan& F = circs[i]->fused;
+            FusedCircJob& J = M.fjobs[i];
+            J.phases = F.phases;
+            J.ops = F.ops;
+            J.params = (params && circs[i]->n_params) ? static_cast<const float*>(params[i]) : nullptr;
+            J.cm = static_cast<const cx<float>*>(circs[i]->cm[0]);
+            J.fmats = reinterpret_cast<float*>(w + L.fmats_off[i]);
+            J.opart = reinterpret_cast<const double*>(w + L.opart_off[i]);
+            J.osum = reinterpret_cast<double*>(w + L.osum_off[i]);
+            J.slots = reinterpret_cast<double*>(w + L.fslot_off[i]);
+            J.n_blocks = F.host.n_blocks;
+            J.wgs = L.fwgs[i];
+            J.total_slots = F.host.total_slots;
+            J.pstride = circs[i]->n_params;
+        }
+    }
+    M.plan = multi_plan(jobs, circs, hams, count, dt, L.fused, M.rb, M.rbr);
+    M.job0 = jobs[0];
+    return TCNG_OK;
+}
+
+// the host tables into the workspace: stream-ordered copies (sync == false),
+// or synchronous ones after the device is idle (a bound batch, whose launches
+// then enqueue kernels only)
+tcng_status multi_upload(tcng_multi& M, hipStream_t st, bool sync) {
+    const MultiLayout& L = M.L;
+    char* w = M.ws;
+    const int count = M.count;
+    struct Part {
+        size_t off;
+        const void* src;
+        size_t bytes;
+    };
+    std::vector<Part> parts;
+    for (int k = 0; k < 3; ++k) {
+        parts.push_back({L.jobs_off[k], M.plan.sorted[k].data(), sizeof(Job) * count});
+        parts.push_back({L.prefix_off[k], M.plan.prefix[k].data(), sizeof(int64_t) * (count + 2)});
+    }
+    parts.push_back({L.build_off, M.builds.data(), sizeof(BuildJob) * count});
+    parts.push_back({L.build_prefix_off, M.bprefix.data(), sizeof(int64_t) * (count + 1)});
+    parts.push_back({L.fin_off, M.fins.data(), sizeof(FinishJob) * count});
+    parts.push_back({L.fin_prefix_off, M.fprefix.data(), sizeof(int64_t) * (count + 1)});
+    if (L.fused) parts.push_back({L.fjobs_off, M.fjobs.data(), sizeof(FusedCircJob) * count});
+    if (sync) HIP_TRY(hipDeviceSynchronize());
+    for (const Part& p : parts) {
+        if (sync) HIP_TRY(hipMemcpy(w + p.off, p.src, p.bytes, hipMemcpyHostToDevice));
+        else HIP_TRY(hipMemcpyAsync(w + p.off, p.src, p.bytes, hipMemcpyHostToDevice, st));
+    }
+    M.uploaded = true;
+    return TCNG_OK;
+}
+
+// every kernel of one evaluation (no copies)
+tcng_status multi_launch(const tcng_multi& M, hipStream_t st) {
+    const MultiLayout& L = M.L;
+    char* w = M.ws;
+    const int count = M.count, dt = M.dt;
+    double* part = reinterpret_cast<double*>(w + L.part_off);
+    double* epart = reinterpret_cast<double*>(w + L.epart_off);
+    double* ssum = reinterpret_cast<double*>(w + L.ssum_off);
+    double* esum = reinterpret_cast<double*>(w + L.esum_off);
+    const FinishJob* fins = reinterpret_cast<const FinishJob*>(w + L.fin_off);
+    const int64_t* fpre = reinterpret_cast<const int64_t*>(w + L.fin_prefix_off);
+    // every Pauli pass writes its rows; circuits with fewer passes leave rows unwritten: clear
+    HIP_TRY(launch_zero(epart, size_t(L.e_rows) * MULTI_EWGS, st));
+    if (L.fused) {
+        const FusedCircJob* djobs = reinterpret_cast<const FusedCircJob*>(w + L.fjobs_off);
+        PROF_TRY(F_FUSED_GRAD, launch_fused_multi_mats(djobs, count, L.max_blocks, st));
+        if (tcng_status e = launch_multi_fused(M.plan, M.job0, w, L, st)) return e;
+        PROF_TRY(F_FUSED_GRAD, launch_fused_multi_grad(djobs, count, L.max_blocks, st));
+        PROF_TRY(F_FINISH, launch_finish_multi(part, 0, MULTI_WGS, epart, L.e_rows, MULTI_EWGS, ssum, esum, fins, fpre,
+                                               count, M.fprefix[count], st));
+        return TCNG_OK;
+    }
+    if (M.init_basis >= 0)
+        for (int i = 0; i < count; ++i) {
+            const tcng_state& s = M.psi[i];
+            if (dt == TCNG_C64)
+                PROF_TRY(F_INIT, launch_init<float>(s.amps, s.stride, s.n_qubits, 1, nullptr, M.init_basis, st));
+            else
+                PROF_TRY(F_INIT, launch_init<double>(s.amps, s.stride, s.n_qubits, 1, nullptr, M.init_basis, st));
+        }
+    HIP_TRY(launch_zero(part, size_t(L.slot_rows) * MULTI_WGS, st));
+    const BuildJob* bj = reinterpret_cast<const BuildJob*>(w + L.build_off);
+    const int64_t* bpre = reinterpret_cast<const int64_t*>(w + L.build_prefix_off);
+    const int rb = M.rb, rr = M.rbr;
+    tcng_status e = TCNG_OK;
+    if (dt == TCNG_C64) {
+        HIP_TRY(launch_build_ops_multi<float>(bj, bpre, count, M.bprefix[count], st));
+        if (rb == 5 && rr == 4) e = launch_multi_tiled<float, 5, 4>(M.plan, M.job0, w, L, st);
+        else if (rb == 5 && rr == 5) e = launch_multi_tiled<float, 5, 5>(M.plan, M.job0, w, L, st);
+        else if (rb == 4 && rr == 4) e = launch_multi_tiled<float, 4, 4>(M.plan, M.job0, w, L, st);
+        else e = launch_multi_tiled<float, 4, 5>(M.plan, M.job0, w, L, st);
+    } else {
+        HIP_TRY(launch_build_ops_multi<double>(bj, bpre, count, M.bprefix[count], st));
+        if (rb == 4 && rr == 3) e = launch_multi_tiled<double, 4, 3>(M.plan, M.job0, w, L, st);
+        else if (rb == 4 && rr == 4) e = launch_multi_tiled<double, 4, 4>(M.plan, M.job0, w, L, st);
+        else if (rb == 3 && rr == 3) e = launch_multi_tiled<double, 3, 3>(M.plan, M.job0, w, L, st);
+        else e = launch_multi_tiled<double, 3, 4>(M.plan, M.job0, w, L, st);
+    }
+    if (e) return e;
+    PROF_TRY(F_FINISH, launch_finish_multi(part, L.slot_rows, MULTI_WGS, epart, L.e_rows, MULTI_EWGS, ssum, esum, fins,
+                                           fpre, count, M.fprefix[count], st));
     return TCNG_OK;
 }
 
@@ -1741,129 +1964,48 @@ tcng_status tcng_expect_grad_multi(const tcng_circuit* const* circs, const tcng_
                                    const void* const* params, const tcng_state* psi, const tcng_state* lam,
                                    double* energy, double* const* grad, double* const* gate_grad, void* ws,
                                    size_t ws_bytes, void* stream) {
-    if (!psi || !lam || !energy) return fail(TCNG_E_INVALID, "null argument");
-    const int dt = psi[0].dtype;
-    if (tcng_status e = multi_check(circs, hams, count, dt)) return e;
-    for (int i = 0; i < count; ++i) {
-        if (tcng_status e = check_state(&psi[i], "tcng_expect_grad_multi(psi)")) return e;
-        if (tcng_status e = check_state(&lam[i], "tcng_expect_grad_multi(lam)")) return e;
-        if (psi[i].dtype != dt || lam[i].dtype != dt || psi[i].batch != 1 || lam[i].batch != 1 ||
-            psi[i].n_qubits != circs[i]->n || lam[i].n_qubits != circs[i]->n || psi[i].amps == lam[i].amps)
-            return fail(TCNG_E_INVALID, "uneven batch: states must be single, distinct and match their circuits");
-        if (circs[i]->n_params > 0 && (!params || !params[i] || !grad || !grad[i]))
-            return fail(TCNG_E_INVALID, "uneven batch: missing angles or gradient output");
-    }
-    const MultiLayout L = multi_layout(circs, hams, count, dt);
-    if (!ws || ws_bytes < L.total) return fail(TCNG_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total));
-    char* w = static_cast<char*>(ws);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    std::vector<Job> jobs(count);
-    std::vector<BuildJob> builds(count);
-    std::vector<FinishJob> fins(count);
-    std::vector<int64_t> bprefix(count + 1, 0), fprefix(count + 1, 0);
-    double* part = reinterpret_cast<double*>(w + L.part_off);
-    double* epart = reinterpret_cast<double*>(w + L.epart_off);
-    double* ssum = reinterpret_cast<double*>(w + L.ssum_off);
-    double* esum = reinterpret_cast<double*>(w + L.esum_off);
-    for (int i = 0; i < count; ++i) {
-        const tcng_circuit* c = circs[i];
-        const tcng_pauli_sum* h = hams[i];
-        WsLayout Li;
-        Li.fused = L.fused;
-        Li.total_slots = std::max(L.fused ? c->fused.host.total_slots : c->tiled[dt].host.total_slots, 1);
-        Li.rev_wgs = L.fused ? L.fwgs[i] : MULTI_WGS;
-        Li.e_rows = std::max<int>(int(h->tplan[dt].passes.size()), 1);
-        Li.e_wgs = MULTI_EWGS;
-        jobs[i] = make_job(c, h, &psi[i], lam[i].amps, w + L.opm_off[i], part + L.slot_row[i] * MULTI_WGS,
-                           epart + L.erow_row[i] * MULTI_EWGS, Li);
-        if (L.fused) {
-            jobs[i].fmats = w + L.fmats_off[i];
-            jobs[i].opart = reinterpret_cast<double*>(w + L.opart_off[i]);
-        }
-        builds[i] = BuildJob{c->tiled[dt].ops, params ? params[i] : nullptr, c->cm[dt], w + L.opm_off[i],
-                             int32_t(c->gates.size()), 0};
-        bprefix[i + 1] = bprefix[i] + int64_t(c->gates.size());
-        const SlotTables& S = L.fused ? c->fused.slots : c->tiled[dt].slots;
-        FinishJob F{};
-        F.slots = L.fused ? reinterpret_cast<double*>(w + L.fslot_off[i]) : ssum + L.slot_row[i];
-        F.erow = esum + L.erow_row[i];
-        F.slot_ptr = S.ptr;
-        F.slot_idx = S.idx;
-        F.gate_slot = S.gate_slot;
-        F.u2m = c->u2m[dt];
-        F.gate_mat = c->gate_mat;
-        F.energy = energy + i;
-        F.grad = (grad && c->n_params) ? grad[i] : nullptr;
-        F.gate_grad = gate_grad ? gate_grad[i] : nullptr;
-        F.n_params = c->n_params;
-        F.n_gates = int32_t(c->gates.size());
-        F.erows = Li.e_rows;
-        fins[i] = F;
-        fprefix[i + 1] = fprefix[i] + 1 + c->n_params + (F.gate_grad ? int64_t(c->gates.size()) : 0);
-    }
-    HIP_TRY(hipMemcpyAsync(w + L.build_off, builds.data(), sizeof(BuildJob) * count, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(w + L.build_prefix_off, bprefix.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
-                           st));
-    HIP_TRY(hipMemcpyAsync(w + L.fin_off, fins.data(), sizeof(FinishJob) * count, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(w + L.fin_prefix_off, fprefix.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice,
-                           st));
-    // every Pauli pass writes its rows; circuits with fewer passes leave rows unwritten: clear
-    HIP_TRY(launch_zero(epart, size_t(L.e_rows) * MULTI_EWGS, st));
-    if (L.fused) {
-        std::vector<FusedCircJob> fj(count);
-        for (int i = 0; i < count; ++i) {
-            const DevFusedPlan& F = circs[i]->fused;
-            FusedCircJob& J = fj[i];
-            J.phases = F.phases;
-            J.ops = F.ops;
-            J.params = (params && circs[i]->n_params) ? static_cast<const float*>(params[i]) : nullptr;
-            J.cm = static_cast<const cx<float>*>(circs[i]->cm[0]);
-            J.fmats = reinterpret_cast<float*>(w + L.fmats_off[i]);
-            J.opart = reinterpret_cast<const double*>(w + L.opart_off[i]);
-            J.osum = reinterpret_cast<double*>(w + L.osum_off[i]);
-            J.slots = reinterpret_cast<double*>(w + L.fslot_off[i]);
-            J.n_blocks = F.host.n_blocks;
-            J.wgs = L.fwgs[i];
-            J.total_slots = F.host.total_slots;
-            J.pstride = circs[i]->n_params;
-        }
-        const FusedCircJob* djobs = reinterpret_cast<const FusedCircJob*>(w + L.fjobs_off);
-        HIP_TRY(hipMemcpyAsync(w + L.fjobs_off, fj.data(), sizeof(FusedCircJob) * count, hipMemcpyHostToDevice, st));
-        PROF_TRY(F_FUSED_GRAD, launch_fused_multi_mats(djobs, count, L.max_blocks, st));
-        if (tcng_status e = run_multi_fused(jobs, hams, count, dt, L, w, st)) return e;
-        PROF_TRY(F_FUSED_GRAD, launch_fused_multi_grad(djobs, count, L.max_blocks, st));
-        PROF_TRY(F_FINISH, launch_finish_multi(part, 0, MULTI_WGS, epart, L.e_rows, MULTI_EWGS, ssum, esum,
-                                               reinterpret_cast<const FinishJob*>(w + L.fin_off),
-                                               reinterpret_cast<const int64_t*>(w + L.fin_prefix_off), count,
-                                               fprefix[count], st));
-        return ok();
-    }
-    HIP_TRY(launch_zero(part, size_t(L.slot_rows) * MULTI_WGS, st));
-    const TileConfig& cfg = circs[0]->tiled[dt].host.cfg;
-    tcng_status e = TCNG_OK;
-    if (dt == TCNG_C64) {
-        HIP_TRY(launch_build_ops_multi<float>(reinterpret_cast<const BuildJob*>(w + L.build_off),
-                                              reinterpret_cast<const int64_t*>(w + L.build_prefix_off), count,
-                                              bprefix[count], st));
-        if (cfg.rb == 5 && cfg.rb_rev == 4) e = run_multi<float, 5, 4>(jobs, circs, hams, count, dt, L, w, st);
-        else if (cfg.rb == 5 && cfg.rb_rev == 5) e = run_multi<float, 5, 5>(jobs, circs, hams, count, dt, L, w, st);
-        else if (cfg.rb == 4 && cfg.rb_rev == 4) e = run_multi<float, 4, 4>(jobs, circs, hams, count, dt, L, w, st);
-        else e = run_multi<float, 4, 5>(jobs, circs, hams, count, dt, L, w, st);
-    } else {
-        HIP_TRY(launch_build_ops_multi<double>(reinterpret_cast<const BuildJob*>(w + L.build_off),
-                                               reinterpret_cast<const int64_t*>(w + L.build_prefix_off), count,
-                                               bprefix[count], st));
-        if (cfg.rb == 4 && cfg.rb_rev == 3) e = run_multi<double, 4, 3>(jobs, circs, hams, count, dt, L, w, st);
-        else if (cfg.rb == 4 && cfg.rb_rev == 4) e = run_multi<double, 4, 4>(jobs, circs, hams, count, dt, L, w, st);
-        else if (cfg.rb == 3 && cfg.rb_rev == 3) e = run_multi<double, 3, 3>(jobs, circs, hams, count, dt, L, w, st);
-        else e = run_multi<double, 3, 4>(jobs, circs, hams, count, dt, L, w, st);
-    }
-    if (e) return e;
-    PROF_TRY(F_FINISH, launch_finish_multi(part, L.slot_rows, MULTI_WGS, epart, L.e_rows, MULTI_EWGS, ssum, esum,
-                                           reinterpret_cast<const FinishJob*>(w + L.fin_off),
-                                           reinterpret_cast<const int64_t*>(w + L.fin_prefix_off), count,
-                                           fprefix[count], st));
+    tcng_multi M;
+    if (tcng_status e = multi_build(circs, hams, count, params, psi, lam, energy, grad, gate_grad, -1, ws, ws_bytes, M))
+        return e;
+    if (tcng_status e = multi_upload(M, st, false)) return e;
+    if (tcng_status e = multi_launch(M, st)) return e;
     return ok();
+}
+
+tcng_status tcng_multi_create(const tcng_circuit* const* circs, const tcng_pauli_sum* const* hams, int32_t count,
+                              const void* const* params, const tcng_state* psi, const tcng_state* lam, double* energy,
+                              double* const* grad, double* const* gate_grad, int64_t init_basis, void* ws,
+                              size_t ws_bytes, tcng_multi** out) {
+    if (!out) return fail(TCNG_E_INVALID, "null output handle");
+    *out = nullptr;
+    auto* M = new (std::nothrow) tcng_multi();
+    if (!M) return fail(TCNG_E_ALLOC, "host allocation failed");
+    tcng_status e = multi_build(circs, hams, count, params, psi, lam, energy, grad, gate_grad, init_basis, ws,
+                                ws_bytes, *M);
+    if (!e) e = multi_upload(*M, nullptr, true);
+    if (e) {
+        delete M;
+        return e;
+    }
+    *out = M;
+    return ok();
+}
+
+tcng_status tcng_multi_launch(const tcng_multi* m, void* stream) {
+    if (!m || !m->uploaded) return fail(TCNG_E_INVALID, "null uneven batch");
+    if (tcng_status e = multi_launch(*m, static_cast<hipStream_t>(stream))) return e;
+    return ok();
+}
+
+tcng_status tcng_multi_destroy(tcng_multi* m) {
+    delete m;
+    return ok();
+}
+
+tcng_status tcng_graph_create_multi(const tcng_multi* m, tcng_graph** out) {
+    if (!m || !m->uploaded) return fail(TCNG_E_INVALID, "null uneven batch");
+    return capture_graph([&](hipStream_t st) { return multi_launch(*m, st); }, out);
 }
 
 tcng_status tcng_circuit_configure(tcng_circuit* c, int32_t dtype, int32_t m_max, int32_t rb, int32_t rb_rev) {

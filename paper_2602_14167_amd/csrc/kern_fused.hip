@@ -155,6 +155,19 @@ __device__ __forceinline__ void ftile_load_proj(float2* lds, gptr<cx<float>> st,
     }
 }
 
+// the tile of a basis state |basis> written to LDS under the load layout
+// (every chunk zero but the one amplitude equal to 1); nothing is read
+template <int IT>
+__device__ __forceinline__ void ftile_basis(float2* lds, uint64_t base, const TileIO<IT>& io, uint64_t basis) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint64_t x = base + io.gt + io.gi[it];   // global index of local 2c (bit 0 clear)
+        const uint32_t a = io.at_ld ^ io.ai_ld[it];
+        lds[a] = make_float2(x == basis ? 1.f : 0.f, 0.f);
+        lds[a ^ io.a1_ld] = make_float2((x | 1u) == basis ? 1.f : 0.f, 0.f);
+    }
+}
+
 // per-lane view of one phase: addresses of the lane's column (block bits
 // zero) and the uniform images of the block bits and of column bits 0..4
 struct FView {
@@ -269,7 +282,9 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
     const TileIO<IT> io = tile_io<IT>(P, t, K.nthr);
 
     if (active) {
-        if (J.prec && jl.step == 0 && J.prec[b * J.prec_stride] != 0u) {
+        if (J.init_basis1 && jl.step == 0) {
+            ftile_basis<IT>(lds, base, io, uint64_t(J.init_basis1 - 1));
+        } else if (J.prec && jl.step == 0 && J.prec[b * J.prec_stride] != 0u) {
             const uint32_t md = J.prec[b * J.prec_stride], bd = J.prec[b * J.prec_stride + 1];
             ftile_load_proj<IT>(lds, lsrc[0], base, io, md, bd, float(1.0 / sqrt(J.pkeep[b])));
         } else {

@@ -50,6 +50,8 @@ struct Job {
                               // partials of member 0); the reverse grid is `wgs` workgroups over (member, tile)
     const void* src;          // or null: the first fused forward pass loads member b's tiles from
     int64_t src_stride;       // src + b * src_stride (0: one state for every member) instead of its own state
+    int64_t init_basis1;      // 0, or 1 + a basis index: the first fused forward pass starts every member
+                              // from that basis state (formed in LDS; the state is not read)
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
