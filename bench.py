@@ -89,7 +89,7 @@ def measured_traffic(workload_name, kernel):
         return None
     return rec[0]
 FAMILIES = ["fwd_tile", "rev_tile", "pauli_tile", "gate1", "gate2", "gatek", "rev1", "rev2", "pauli_group",
-            "finish", "init", "fused_fwd", "fused_rev", "fused_grad", "mipt_marg", "mipt_decide", "mipt_collapse",
+            "finish", "init", "fused_fwd", "fused_rev", "fused_grad", "mipt_hist", "mipt_decide", "mipt_collapse",
             "pauli_coo", "shadow_sum", "shadow_pick", "qml"]
 MFMA_F32_PEAK_TFLOPS = 157.3   # dense float32 matrix-core peak
 
@@ -455,10 +455,11 @@ def run_mipt(args, P, torch):
     meas = w["u"] >= 1 - p
     amp = 2 ** n * 8
     fwd_passes = P.fused_plan_inspect(n, w["gates"], 0)[3]
-    # a marginal reads the amplitudes consistent with the step's earlier outcomes: 2^-j of the
-    # state for the j-th measured qubit of a step (j from 0)
-    earlier = np.cumsum(meas, axis=2) - meas
-    alg = {"fused_fwd": S * fwd_passes * B * 2.0 * amp, "mipt_marg": float((meas * 0.5 ** earlier).sum()) * amp,
+    # the histogram of round r (the step's measured qubits of rank 8r .. 8r + 7) reads, for a
+    # member with a qubit in that round, the amplitudes consistent with the 8r earlier outcomes
+    cnt = meas.sum(axis=2)
+    hist_states = sum(float(((cnt > 8 * r)) .sum()) * 0.5 ** (8 * r) for r in range((n + 7) // 8))
+    alg = {"fused_fwd": S * fwd_passes * B * 2.0 * amp, "mipt_hist": hist_states * amp,
            "mipt_collapse": float(meas[:, -1, :].any(axis=1).sum()) * 2.0 * amp}
     roofline = None
     if fam:

@@ -317,7 +317,7 @@ size_t tcng_noalloc_scratch_bytes(void);
  *   6 reverse one-qubit   7 reverse two-qubit   8 Pauli X-group
  *   9 final reduction     10 state init
  *   11 fused forward pass  12 fused reverse pass  13 fused block matrices and gradients
- *   14 trajectory marginal pass  15 trajectory decisions  16 trajectory collapse
+ *   14 trajectory histogram pass  15 trajectory decisions  16 trajectory collapse
  *   17 Pauli-sum COO entries  18 shadow chunk sums  19 shadow rotations and draws
  *   20 QML gate matrices, readout and angle gradients
  * tcng_profile_end stops recording and frees the events. */

@@ -50,7 +50,7 @@ constexpr int MAX_QUBITS = 34;
 // optional per-launch timing (events on the launch stream)
 // ---------------------------------------------------------------------------
 enum Family { F_FWD_TILE, F_REV_TILE, F_PAULI_TILE, F_GATE1, F_GATE2, F_GATEK, F_REV1, F_REV2, F_PAULI_GROUP,
-              F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_MIPT_MARG, F_MIPT_DECIDE,
+              F_FINISH, F_INIT, F_FUSED_FWD, F_FUSED_REV, F_FUSED_GRAD, F_MIPT_HIST, F_MIPT_DECIDE,
               F_MIPT_COLLAPSE, F_PAULI_COO, F_SHADOW_SUM, F_SHADOW_PICK, F_QML, F_COUNT };
 static_assert(F_COUNT == TCNG_PROF_FAMILIES, "profiler families");
 
@@ -1432,7 +1432,7 @@ MiptLayout mipt_layout(const tcng_circuit* c, int n, int64_t batch) {
     M.F = layout(c, nullptr, n, TCNG_C64, batch, TCNG_MODE_FUSED);
     M.wgs = mipt_wgs(n);
     M.part_off = align256(M.F.total);
-    M.keep_off = M.part_off + align256(size_t(batch) * M.wgs * 2 * sizeof(double));
+    M.keep_off = M.part_off + align256(mipt_hist_doubles(n, batch) * sizeof(double));
     M.total = M.keep_off + align256(size_t(batch) * sizeof(double));
     return M;
 }
@@ -1497,11 +1497,10 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
         if (F.host.passes.empty() && s > 0)
             PROF_TRY(F_MIPT_COLLAPSE, launch_mipt_collapse(psi->amps, psi->stride, n, batch, n_steps, s - 1, rec, keep,
                                                            M.wgs, st));
-        for (int q = 0; q < n; ++q) {
-            PROF_TRY(F_MIPT_MARG, launch_mipt_marg(psi->amps, psi->stride, n, batch, u, n_steps, s, q, p, rec, M.wgs,
-                                                   part, st));
-            PROF_TRY(F_MIPT_DECIDE, launch_mipt_decide(u, n, n_steps, s, q, p, M.wgs, part, rec, keep, logp, margin,
-                                                       batch, st));
+        // the measured qubits in rounds of up to 8: one histogram read and the decisions each
+        for (int r = 0; r < mipt_rounds(n); ++r) {
+            PROF_TRY(F_MIPT_HIST, launch_mipt_hist(psi->amps, psi->stride, n, batch, u, n_steps, s, p, r, rec, part, st));
+            PROF_TRY(F_MIPT_DECIDE, launch_mipt_decide(u, n, n_steps, s, p, r, part, rec, keep, logp, margin, batch, st));
         }
     }
     if (n_steps > 0)

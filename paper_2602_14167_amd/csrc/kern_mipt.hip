@@ -5,21 +5,27 @@
 // A step's measurements are taken qubit by qubit, in increasing order, as the
 // three-outcome Kraus channel {sqrt(1-p) I, sqrt(p) P0, sqrt(p) P1} selected by
 // one uniform v per (member, step, qubit): measured iff v >= 1 - p, outcome 0
-// iff v - (1 - p) < p P(bit q = 0 | the step's earlier outcomes).  The
-// projections are not applied one by one: the outcomes decided so far in the
-// step (mask, bits) filter the amplitudes of the next marginal, which gives
-// the conditional probability as a ratio of the two filtered sums.  The
-// step's collapse (zero the inconsistent amplitudes, divide by the square
-// root of the kept mass) is applied by the next step's first forward pass as
-// it loads its tiles, and after the last step by k_mipt_collapse.
+// iff v - (1 - p) < p P(bit q = 0 | the step's earlier outcomes).  Which
+// qubits a member measures follows from its uniforms alone, so one read of
+// the state gives the joint distribution of up to HK of them (a histogram of
+// |psi_x|^2 over their bit patterns), and every conditional probability of
+// their sequential decisions is a ratio of sums of its bins.  A member
+// measuring more than HK qubits takes them in rounds of HK, each round's read
+// filtered by the outcomes of the rounds before (only consistent amplitudes
+// are loaded).  The step's collapse (zero the inconsistent amplitudes, divide
+// by the square root of the kept mass) is applied by the next step's first
+// forward pass as it loads its tiles, and after the last step by
+// k_mipt_collapse.
 //
-//   k_mipt_marg     float64 sums of |psi_x|^2 over the consistent x with bit q
-//                   = 0 / = 1, one partial pair per workgroup (HBM-bound read)
-//   k_mipt_decide   one thread per member: fixed-order sum of the partials,
-//                   the Kraus decision, record, kept mass, ln P(outcome)
+//   k_mipt_hist     per workgroup (2^13 consecutive amplitudes): float64 sums
+//                   of the consistent |psi_x|^2 per pattern of the round's
+//                   qubits inside the chunk, in a fixed order (HBM-bound read)
+//   k_mipt_decide   one wave per member: fixed-order sums of the partials into
+//                   the joint histogram, the round's decisions in increasing
+//                   qubit order, record, kept mass, ln P(outcome)
 //   k_mipt_collapse projection and renormalisation after the last step
 //                   (HBM-bound read + write)
-// A member that does not measure q leaves its workgroups at once.
+// A member with no qubit in a round leaves its workgroups at once.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -30,83 +36,151 @@ namespace tcng {
 namespace {
 
 constexpr int MTHREADS = 256;
+constexpr int HK = 8;                 // measured qubits per histogram round
+constexpr int HBINS = 1 << HK;
+constexpr int HCHUNK = 13;            // amplitudes per histogram workgroup: at most 2^13
 
 __device__ __forceinline__ bool measures(const double* u, int64_t b, int n_steps, int s, int n, int q, double p) {
     return u[(b * n_steps + s) * n + q] >= 1.0 - p;
 }
 
-__global__ void __launch_bounds__(MTHREADS) k_mipt_marg(const float4* __restrict__ psi, int64_t stride4, int n,
-                                                        const double* __restrict__ u, int n_steps, int s, int q,
-                                                        double p, const uint32_t* __restrict__ rec, int wgs,
+// the qubits member b measures in step s with rank [r HK, (r + 1) HK) among them
+__device__ __forceinline__ uint32_t round_mask(const double* u, int64_t b, int n_steps, int s, int n, double p, int r) {
+    uint32_t m = 0;
+    int c = 0;
+    for (int q = 0; q < n; ++q)
+        if (u[(b * n_steps + s) * n + q] >= 1.0 - p) {
+            if (c >= r * HK && c < (r + 1) * HK) m |= 1u << q;
+            ++c;
+        }
+    return m;
+}
+
+// the low bits of v deposited at the set bits of mask (lowest first)
+__device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
+    uint32_t out = 0;
+    for (uint32_t mk = mask; mk; mk &= mk - 1) {
+        if (v & 1u) out |= mk & (0u - mk);
+        v >>= 1;
+    }
+    return out;
+}
+
+__global__ void __launch_bounds__(MTHREADS) k_mipt_hist(const float4* __restrict__ psi, int64_t stride4, int n,
+                                                        const double* __restrict__ u, int n_steps, int s, double p,
+                                                        int r, const uint32_t* __restrict__ rec, int wgs,
                                                         double* __restrict__ part) {
-    __shared__ double red[2][MTHREADS / 64];
+    __shared__ float w2[1 << HCHUNK];
+    __shared__ double red[MTHREADS];
     const int64_t b = blockIdx.y;
     const int wg = blockIdx.x;
-    if (!measures(u, b, n_steps, s, n, q, p)) return;   // the whole workgroup leaves together
+    const uint32_t M = round_mask(u, b, n_steps, s, n, p, r);
+    if (!M) return;   // the whole workgroup leaves together
     const uint32_t md = rec[(b * n_steps + s) * 2], bd = rec[(b * n_steps + s) * 2 + 1];
-    const uint64_t per4 = (uint64_t(1) << n) / 2 / uint64_t(wgs);   // 16-byte chunks (amplitude pairs) per workgroup
-    const uint64_t c0 = uint64_t(wg) * per4;
-    const float4* src = psi + b * stride4 + c0;
-    const uint32_t bq = 1u << q;
-    double s0 = 0.0, s1 = 0.0;
-    for (uint64_t i = threadIdx.x; i < per4; i += MTHREADS) {
-        const uint32_t x = uint32_t(2 * (c0 + i));   // n <= 32: the low word holds every qubit
+    const uint32_t A = (1u << n) / uint32_t(wgs);   // amplitudes of the chunk (<= 2^HCHUNK)
+    const uint32_t c0 = uint32_t(wg) * A;
+    const float4* src = psi + b * stride4 + c0 / 2;
+    // |psi_x|^2 of the chunk into LDS, zero where x contradicts the round's earlier
+    // outcomes; every load of the thread in flight before the first use
+    constexpr int LMAX = (1 << HCHUNK) / 2 / MTHREADS;   // 16-byte chunks per thread (at most)
+    float4 a[LMAX];
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+        const uint32_t i = threadIdx.x + uint32_t(k) * MTHREADS;
+        const uint32_t x = c0 + 2 * i;
         const bool k0 = (x & md) == bd, k1 = ((x | 1u) & md) == bd;
-        // amplitudes ruled out by the step's earlier outcomes are not read: after j outcomes
-        // on qubits above the lowest few, whole lines of the state are skipped (2^-j of it read)
-        if (!k0 && !k1) continue;
-        const float4 a = src[i];
-        const float w0 = a.x * a.x + a.y * a.y, w1 = a.z * a.z + a.w * a.w;
-        if (k0) {
-            if (x & bq) s1 += double(w0);
-            else s0 += double(w0);
-        }
-        if (k1) {
-            if ((x | 1u) & bq) s1 += double(w1);
-            else s0 += double(w1);
-        }
+        a[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < A / 2 && (k0 || k1)) a[k] = src[i];   // whole lines of amplitudes ruled out are not read
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][wave] = s0;
-        red[1][wave] = s1;
+#pragma unroll
+    for (int k = 0; k < LMAX; ++k) {
+        const uint32_t i = threadIdx.x + uint32_t(k) * MTHREADS;
+        if (i >= A / 2) break;
+        const uint32_t x = c0 + 2 * i;
+        const bool k0 = (x & md) == bd, k1 = ((x | 1u) & md) == bd;
+        w2[2 * i] = k0 ? a[k].x * a[k].x + a[k].y * a[k].y : 0.f;
+        w2[2 * i + 1] = k1 ? a[k].z * a[k].z + a[k].w * a[k].w : 0.f;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t0 = 0.0, t1 = 0.0;
-        for (int w = 0; w < MTHREADS / 64; ++w) {
-            t0 += red[0][w];
-            t1 += red[1][w];
-        }
-        part[(b * wgs + wg) * 2] = t0;
-        part[(b * wgs + wg) * 2 + 1] = t1;
+    // bins of the round's qubits inside the chunk: thread t sums its share of bin t / T
+    // (T threads per bin) over the chunk's indices of that bin, in increasing order
+    const uint32_t mloc = M & (A - 1), free = (A - 1) & ~mloc;
+    const int kloc = __popc(mloc);
+    const int T = MTHREADS >> kloc;            // threads per bin (kloc <= HK = 8)
+    const uint32_t j = threadIdx.x / T, part_i = threadIdx.x % T;
+    const uint32_t per = (A >> kloc) / uint32_t(T);   // indices per thread (>= 1 at A >= 2^HK)
+    const uint32_t fixed = deposit(j, mloc);
+    uint32_t v = deposit(part_i * per, free);
+    double sum = 0.0;
+    for (uint32_t k = 0; k < per; ++k) {
+        sum += double(w2[v | fixed]);
+        v = ((v | ~free) + 1u) & free;   // next index of the free bits, increasing
+    }
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x < (1u << kloc)) {
+        double t = 0.0;
+        for (int k = 0; k < T; ++k) t += red[threadIdx.x * T + k];
+        part[(size_t(b) * wgs + wg) * HBINS + threadIdx.x] = t;
     }
 }
 
-__global__ void k_mipt_decide(const double* __restrict__ u, int n, int n_steps, int s, int q, double p, int wgs,
-                              const double* __restrict__ part, uint32_t* __restrict__ rec, double* __restrict__ keep,
-                              double* __restrict__ logp, double* __restrict__ margin, int64_t batch) {
-    const int64_t b = int64_t(blockIdx.x) * 64 + threadIdx.x;
-    if (b >= batch) return;
-    const double v = u[(b * n_steps + s) * n + q];
-    if (v < 1.0 - p) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int w = 0; w < wgs; ++w) {
-        s0 += part[(b * wgs + w) * 2];
-        s1 += part[(b * wgs + w) * 2 + 1];
+// one wave per member: joint histogram of the round's qubits (bins: their bits
+// in increasing qubit order), then the decisions
+__global__ void __launch_bounds__(64) k_mipt_decide(const double* __restrict__ u, int n, int n_steps, int s, double p,
+                                                    int r, int wgs, const double* __restrict__ part,
+                                                    uint32_t* __restrict__ rec, double* __restrict__ keep,
+                                                    double* __restrict__ logp, double* __restrict__ margin) {
+    __shared__ double H[HBINS];
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t M = round_mask(u, b, n_steps, s, n, p, r);
+    if (!M) return;
+    const int K = __popc(M);
+    const uint32_t A = (1u << n) / uint32_t(wgs);
+    const uint32_t mloc = M & (A - 1), mhigh = M & ~(A - 1);
+    const int kloc = __popc(mloc);
+    // bin g: low kloc bits from inside a chunk, the rest from the chunk's base
+    for (int g = lane; g < (1 << K); g += 64) {
+        const uint32_t lo = uint32_t(g) & ((1u << kloc) - 1), hi = deposit(uint32_t(g) >> kloc, mhigh);
+        double t = 0.0;
+        for (int w = 0; w < wgs; ++w)
+            if (((uint32_t(w) * A) & mhigh) == hi) t += part[(size_t(b) * wgs + w) * HBINS + lo];
+        H[g] = t;
     }
-    const double tot = s0 + s1;
-    const double mg = (v - (1.0 - p)) - p * (s0 / tot);
-    const int o = mg < 0.0 ? 0 : 1;
-    const double kp = o ? s1 : s0;
-    logp[b] += log(kp / tot);
-    keep[b] = kp;
-    uint32_t* r = rec + (b * n_steps + s) * 2;
-    r[0] |= 1u << q;
-    r[1] |= uint32_t(o) << q;
-    if (margin) margin[(b * n_steps + s) * n + q] = mg;
+    __syncthreads();
+    uint32_t* rc = rec + (b * n_steps + s) * 2;
+    uint32_t dm = 0, db = 0;   // decided bits (bin positions) and their values
+    double lp = 0.0, kp = 0.0;
+    int i = 0;
+    for (uint32_t mk = M; mk; mk &= mk - 1, ++i) {
+        const int q = __ffs(mk) - 1;
+        double s0 = 0.0, s1 = 0.0;
+        for (int g = lane; g < (1 << K); g += 64) {
+            if ((uint32_t(g) & dm) != db) continue;
+            if ((g >> i) & 1) s1 += H[g];
+            else s0 += H[g];
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        const double v = u[(b * n_steps + s) * n + q];
+        const double tot = s0 + s1;
+        const double mg = (v - (1.0 - p)) - p * (s0 / tot);
+        const int o = mg < 0.0 ? 0 : 1;
+        kp = o ? s1 : s0;
+        lp += log(kp / tot);
+        dm |= 1u << i;
+        db |= uint32_t(o) << i;
+        if (lane == 0) {
+            rc[0] |= 1u << q;
+            rc[1] |= uint32_t(o) << q;
+            if (margin) margin[(b * n_steps + s) * n + q] = mg;
+        }
+    }
+    if (lane == 0) {
+        logp[b] += lp;
+        keep[b] = kp;
+    }
 }
 
 __global__ void __launch_bounds__(MTHREADS) k_mipt_collapse(float4* __restrict__ psi, int64_t stride4, int n,
@@ -142,20 +216,26 @@ int mipt_wgs(int n) {
     return int(std::max<uint64_t>(1, std::min<uint64_t>(256, dim >> 13)));
 }
 
-hipError_t launch_mipt_marg(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
-                            int q, double p, const uint32_t* rec, int wgs, double* part, hipStream_t st) {
+int mipt_hist_wgs(int n) { return n > HCHUNK ? 1 << (n - HCHUNK) : 1; }
+int mipt_rounds(int n) { return (n + HK - 1) / HK; }
+size_t mipt_hist_doubles(int n, int64_t batch) { return size_t(batch) * mipt_hist_wgs(n) * HBINS; }
+
+hipError_t launch_mipt_hist(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
+                            double p, int r, const uint32_t* rec, double* part, hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mipt_marg, dim3(unsigned(wgs), unsigned(batch)), dim3(MTHREADS), 0, st,
-                       static_cast<const float4*>(psi), stride / 2, n, u, n_steps, s, q, p, rec, wgs, part);
+    if (n < HK) return hipErrorInvalidValue;   // a chunk holds at least one index per thread and bin
+    const int wgs = mipt_hist_wgs(n);
+    hipLaunchKernelGGL(k_mipt_hist, dim3(unsigned(wgs), unsigned(batch)), dim3(MTHREADS), 0, st,
+                       static_cast<const float4*>(psi), stride / 2, n, u, n_steps, s, p, r, rec, wgs, part);
     return hipGetLastError();
 }
 
-hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, int q, double p, int wgs, const double* part,
+hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, double p, int r, const double* part,
                               uint32_t* rec, double* keep, double* logp, double* margin, int64_t batch,
                               hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mipt_decide, dim3(unsigned((batch + 63) / 64)), dim3(64), 0, st, u, n, n_steps, s, q, p, wgs,
-                       part, rec, keep, logp, margin, batch);
+    hipLaunchKernelGGL(k_mipt_decide, dim3(unsigned(batch)), dim3(64), 0, st, u, n, n_steps, s, p, r,
+                       mipt_hist_wgs(n), part, rec, keep, logp, margin);
     return hipGetLastError();
 }
 

@@ -167,13 +167,18 @@ hipError_t launch_shadow_chunks(const void* psi, int64_t stride, int n, int64_t 
 hipError_t launch_shadow_pick(const void* psi, int64_t stride, int n, int64_t S, const double* part, const double* u,
                               int64_t* out, hipStream_t st);
 
-// ---- monitored trajectories (complex64): marginal partials of qubit q on the
-// amplitudes consistent with the step's decided outcomes, the Kraus decision,
-// the per-step collapse.  wgs = mipt_wgs(n) workgroups per member.
+// ---- monitored trajectories (complex64): joint histograms of the measured
+// qubits (rounds of up to 8 in increasing order, each read filtered by the
+// step's earlier outcomes), the Kraus decisions, the per-step collapse.
+// Collapse: wgs = mipt_wgs(n) workgroups per member; histograms:
+// mipt_hist_wgs(n) per member, mipt_hist_doubles(n, batch) partials.
 int mipt_wgs(int n);
-hipError_t launch_mipt_marg(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
-                            int q, double p, const uint32_t* rec, int wgs, double* part, hipStream_t st);
-hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, int q, double p, int wgs, const double* part,
+int mipt_hist_wgs(int n);
+int mipt_rounds(int n);
+size_t mipt_hist_doubles(int n, int64_t batch);
+hipError_t launch_mipt_hist(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
+                            double p, int r, const uint32_t* rec, double* part, hipStream_t st);
+hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, double p, int r, const double* part,
                               uint32_t* rec, double* keep, double* logp, double* margin, int64_t batch,
                               hipStream_t st);
 hipError_t launch_mipt_collapse(void* psi, int64_t stride, int n, int64_t batch, int n_steps, int s,
