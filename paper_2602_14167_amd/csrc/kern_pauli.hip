@@ -103,8 +103,16 @@ k_pauli_tile(const JobList jl, const Job single) {
     // split into a per-thread and a uniform part
     const uint64_t gt = loc2glob(uint32_t(t), lo, m, lq);
 
+    const bool read_lam = has_lam && accumulate;
+    constexpr int CH = (NB < 4) ? NB : 4;
     for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), tmask, n);
+        // lambda elements of the first chunk (later passes accumulate into
+        // them), in flight together with the psi tile; each chunk loads the next one's
+        cx<R> lamn[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            lamn[i] = (read_lam && active) ? lam[base + gt + loc2glob(uint32_t(i * nt), lo, m, lq)] : cx<R>{R(0), R(0)};
         __syncthreads();
         // psi tile -> LDS; element l = it*nt + t (lane-consecutive, coalesced)
         if (active) {
@@ -118,13 +126,13 @@ k_pauli_tile(const JobList jl, const Job single) {
         if (!active) continue;
         // elements l = it*nt + t, CH at a time; the term loop is outside the
         // element loop so every scalar load of a term serves CH elements
-        constexpr int CH = (NB < 4) ? NB : 4;
         for (int c0 = 0; c0 < NB; c0 += CH) {
             cx<R> acc[CH];
 #pragma unroll
-            for (int i = 0; i < CH; ++i) {
-                acc[i] = (has_lam && accumulate) ? lam[base + gt + loc2glob(uint32_t((c0 + i) * nt), lo, m, lq)]
-                                                 : cx<R>{R(0), R(0)};
+            for (int i = 0; i < CH; ++i) acc[i] = lamn[i];
+            if (read_lam && c0 + CH < NB) {
+#pragma unroll
+                for (int i = 0; i < CH; ++i) lamn[i] = lam[base + gt + loc2glob(uint32_t((c0 + CH + i) * nt), lo, m, lq)];
             }
             // this pass's share of (H psi)_l in float64: sum over groups of
             // (cre + i cim) psi_{l ^ x}; E takes Re(conj(psi_l) * share) once per element
