@@ -176,6 +176,117 @@ __device__ __forceinline__ Regs<R, NB> app_rx(Regs<R, NB> a, R c, R s) {
     return a;
 }
 
+// ---------------------------------------------------------------------------
+// Rotations by three shears.  A plane rotation
+//   R(a) = [[cos a, -sin a], [sin a, cos a]]
+// equals the product of shears [[1, -t], [0, 1]] [[1, 0], [s, 1]] [[1, -t], [0, 1]]
+// with t = tan(a/2) = sin a / (1 + cos a) and s = sin a (the three-shear
+// factorisation of a rotation, also known as lifting).  Applied to a pair of
+// reals it is three in-place FMAs and needs no temporary; a direct 2x2 product
+// needs four multiplies plus a copy of one operand.  For cos a < 0 the rotation
+// is applied as -R(a - pi), keeping |t| <= 1 (every shear is then as well
+// conditioned as the direct product); the factor -1 multiplies every amplitude
+// of the state alike, so it is carried as one sign per state and applied when
+// the state is stored.
+//
+// RY(t) rotates (re x0, re x1) and (im x0, im x1) by a = t/2.  RX(t) rotates
+// (re x0, im x1) by -a and (im x0, re x1) by a.  A phase c + i sigma s rotates
+// (re, im) of an amplitude by sigma a: RZ is sigma = -1 on |0>, +1 on |1>.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Lift {
+    R t, s;
+};
+
+// shear coefficients of the rotation with cosine c and sine s; toggles `flip`
+// when the rotation is taken as -R(a - pi)
+template <typename R>
+__device__ __forceinline__ Lift<R> lift_of(R c, R s, bool& flip) {
+    if (c < R(0)) {
+        c = -c;
+        s = -s;
+        flip = !flip;
+    }
+    return {s / (R(1) + c), s};
+}
+
+template <typename R>
+__device__ __forceinline__ void lift(R& x0, R& x1, R t, R s) {
+    x0 = fmaR(-t, x1, x0);
+    x1 = fmaR(s, x0, x1);
+    x0 = fmaR(-t, x1, x0);
+}
+
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_ry_lift(Regs<R, NB> a, Lift<R> L) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        lift(a.v[j].re, a.v[j | (1 << B)].re, L.t, L.s);
+        lift(a.v[j].im, a.v[j | (1 << B)].im, L.t, L.s);
+    }
+    return a;
+}
+
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_rx_lift(Regs<R, NB> a, Lift<R> L) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) continue;
+        lift(a.v[j].re, a.v[j | (1 << B)].im, -L.t, -L.s);
+        lift(a.v[j].im, a.v[j | (1 << B)].re, L.t, L.s);
+    }
+    return a;
+}
+
+// RZ on register bit B: phase c - i s on bit 0, c + i s on bit 1
+template <typename R, int NB, int B>
+__device__ __forceinline__ Regs<R, NB> app_rz_lift(Regs<R, NB> a, Lift<R> L) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) lift(a.v[j].re, a.v[j].im, L.t, L.s);
+        else lift(a.v[j].re, a.v[j].im, -L.t, -L.s);
+    }
+    return a;
+}
+
+// the same phase c + i sigma s on every amplitude (RZ on a thread bit)
+template <typename R, int NB>
+__device__ __forceinline__ Regs<R, NB> app_phase_lift(Regs<R, NB> a, Lift<R> L) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) lift(a.v[j].re, a.v[j].im, L.t, L.s);
+    return a;
+}
+
+// RZ gradient on register bit B: sum_j (-1)^{j_B} Im(conj(l_j) p_j)
+template <typename R, int NB, int B>
+__device__ __forceinline__ R grad_rz(Regs<R, NB> l, Regs<R, NB> p) {
+    R g = R(0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j & (1 << B)) {
+            g = fmaR(-l.v[j].re, p.v[j].im, g);
+            g = fmaR(l.v[j].im, p.v[j].re, g);
+        } else {
+            g = fmaR(l.v[j].re, p.v[j].im, g);
+            g = fmaR(-l.v[j].im, p.v[j].re, g);
+        }
+    }
+    return g;
+}
+
+// sum_j Im(conj(l_j) p_j) (RZ on a thread bit, before its sign)
+template <typename R, int NB>
+__device__ __forceinline__ R sum_im_conj(Regs<R, NB> l, Regs<R, NB> p) {
+    R g = R(0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        g = fmaR(l.v[j].re, p.v[j].im, g);
+        g = fmaR(-l.v[j].im, p.v[j].re, g);
+    }
+    return g;
+}
+
 // diagonal (d0, d1) on register bit B (compile-time selection)
 template <typename R, int NB, int B>
 __device__ __forceinline__ Regs<R, NB> app_diag1r(Regs<R, NB> a, cx<R> d0, cx<R> d1) {

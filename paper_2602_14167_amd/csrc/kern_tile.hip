@@ -128,18 +128,23 @@ __device__ __forceinline__ void tile_load(cx<R>* lds, gptr<const cx<R>> psi, uin
     }
 }
 
+// flip: the tile holds -psi (shear rotations taken as -R(a - pi)); stored negated
 template <typename R, int RB>
 __device__ __forceinline__ void tile_store(const cx<R>* lds, gptr<cx<R>> psi, uint64_t base, const PassInfo& pi, int t,
-                                           int nt) {
+                                           int nt, bool flip) {
     constexpr int VN = V16<R>::N;
     const int iters = (1 << RB) / VN;
     const uint64_t off_t = loc2glob(uint32_t(t * VN), pi.lo, pi.m, pi.lq);
+    const R sg = flip ? R(-1) : R(1);
 #pragma unroll
     for (int it = 0; it < iters; ++it) {
         const uint32_t e = uint32_t((it * nt + t) * VN);
         cx<R> v[VN];
 #pragma unroll
-        for (int k = 0; k < VN; ++k) v[k] = lds[swz(e + k)];
+        for (int k = 0; k < VN; ++k) {
+            v[k] = lds[swz(e + k)];
+            if (flip) v[k] = {sg * v[k].re, sg * v[k].im};
+        }
         const uint64_t g = base + loc2glob(uint32_t(it * nt * VN), pi.lo, pi.m, pi.lq) + off_t;
         V16<R>::store(psi + g, v);
     }
@@ -267,6 +272,47 @@ __device__ __forceinline__ Regs<R, (1 << RB)> diag1r_at(Regs<R, (1 << RB)> a, in
     return a;
 }
 template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> ry_lift_at(Regs<R, (1 << RB)> a, int r, Lift<R> L) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_ry_lift<R, (1 << RB), B>(a, L); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> rx_lift_at(Regs<R, (1 << RB)> a, int r, Lift<R> L) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_rx_lift<R, (1 << RB), B>(a, L); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ Regs<R, (1 << RB)> rz_lift_at(Regs<R, (1 << RB)> a, int r, Lift<R> L) {
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) a = app_rz_lift<R, (1 << RB), B>(a, L); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return a;
+}
+template <typename R, int RB>
+__device__ __forceinline__ R grad_rz_at(int r, Regs<R, (1 << RB)> l, Regs<R, (1 << RB)> p) {
+    R g = R(0);
+    switch (r) {
+#define C1(B) case B: if constexpr (B < RB) g = grad_rz<R, (1 << RB), B>(l, p); break;
+        TCNG_SINGLES(C1)
+#undef C1
+        default: break;
+    }
+    return g;
+}
+template <typename R, int RB>
 __device__ __forceinline__ Regs<R, (1 << RB)> cxr_at(Regs<R, (1 << RB)> a, int rt, int rc) {
     switch (rt * 8 + rc) {
 #define C2(B0, B1) case B0 * 8 + B1: if constexpr (B0 < RB && B1 < RB) a = app_cxr<R, (1 << RB), B0, B1>(a); break;
@@ -324,11 +370,29 @@ __device__ __forceinline__ void cot_u2_at(int r0, int r1, Regs<R, (1 << RB)> l, 
 
 // apply one op (forward, or its inverse when INV) to the register block;
 // om: the op's matrix entries for this batch member (k_build_ops)
+// RY, RX and RZ go through shear rotations and toggle `flip` (one sign per
+// state, see lift_of).
 template <typename R, int RB, bool INV>
 __device__ __forceinline__ Regs<R, (1 << RB)> apply_op(Regs<R, (1 << RB)> a, const Op& op, uint32_t tpart,
-                                                      cptr<cx<R>> om) {
+                                                      cptr<cx<R>> om, bool& flip) {
     const int tb0 = op.lb0 >= 0 ? int((tpart >> op.lb0) & 1) : 0;
     const int tb1 = op.lb1 >= 0 ? int((tpart >> op.lb1) & 1) : 0;
+    if (op.kind == K_RY) {
+        const R c = om[0].re, s = om[2].re;
+        return ry_lift_at<R, RB>(a, op.r0, lift_of<R>(c, INV ? -s : s, flip));
+    }
+    if (op.kind == K_RX) {
+        const R c = om[0].re, s = -om[1].im;
+        return rx_lift_at<R, RB>(a, op.r0, lift_of<R>(c, INV ? -s : s, flip));
+    }
+    if (op.kind == K_RZ) {
+        // om[1] = c + i s: the phase of |1>
+        const R c = om[1].re, s = om[1].im;
+        const Lift<R> L = lift_of<R>(c, INV ? -s : s, flip);
+        if (op.r0 >= 0) return rz_lift_at<R, RB>(a, op.r0, L);
+        const R sg = tb0 ? R(1) : R(-1);
+        return app_phase_lift<R, (1 << RB)>(a, Lift<R>{sg * L.t, sg * L.s});
+    }
     switch (op.type) {
         case OP_DENSE1: {
             M2<R> u;
@@ -474,6 +538,7 @@ k_tile_fwd(const JobList jl, const Job single) {
 
     if (active) tile_load<R, RB>(lds, psi, base, pi, t, nt);
     __syncthreads();
+    bool flip = false;
     for (int f = P->phase_begin; f < f_end; ++f) {
         if (active) {
             const PhaseMap pm = phase_map<RB>(phases + f, t, pi.m);
@@ -481,13 +546,13 @@ k_tile_fwd(const JobList jl, const Job single) {
             const int o_end = phases[f].op_end;
             for (int o = phases[f].op_begin; o < o_end; ++o) {
                 const Op op = ops[o];
-                a = apply_op<R, RB, false>(a, op, pm.tpart, om + 16 * op.gate);
+                a = apply_op<R, RB, false>(a, op, pm.tpart, om + 16 * op.gate, flip);
             }
             regs_to_lds<R, RB>(a, lds, pm);
         }
         __syncthreads();
     }
-    if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt);
+    if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt, flip);
 }
 
 // accumulate a thread's gradient partial into the wave's slot (float64)
@@ -538,6 +603,7 @@ k_tile_rev(const JobList jl, const Job single) {
         int f = f_last;
         PhaseMap pm = phase_map<RB>(rphases + f, t, pi.m);
         Blk ps, la;
+        bool flip = false, flip_l = false;   // equal: psi and lambda see the same ops
         __syncthreads();
         if (active) tile_load<R, RB>(lds, psi, base, pi, t, nt);
         __syncthreads();
@@ -561,7 +627,16 @@ k_tile_rev(const JobList jl, const Job single) {
                             grad_fsim_at<R, RB>(op.r0, op.r1, la, ps, gt, gp);
                             red_add(red, slot, gt, lane);
                             red_add(red, slot + nwaves, gp, lane);
-                        } else {                            // RZ, RZZ
+                        } else if (op.kind == K_RZ) {
+                            R g;
+                            if (op.r0 >= 0) {
+                                g = grad_rz_at<R, RB>(op.r0, la, ps);
+                            } else {
+                                const R v = sum_im_conj<R, (1 << RB)>(la, ps);
+                                g = ((pm.tpart >> op.lb0) & 1) ? -v : v;
+                            }
+                            red_add(red, slot, g, lane);
+                        } else {                            // RZZ
                             const int tb0 = op.lb0 >= 0 ? int((pm.tpart >> op.lb0) & 1) : 0;
                             const int tb1 = op.lb1 >= 0 ? int((pm.tpart >> op.lb1) & 1) : 0;
                             red_add(red, slot,
@@ -570,7 +645,7 @@ k_tile_rev(const JobList jl, const Job single) {
                                     lane);
                         }
                     }
-                    ps = apply_op<R, RB, true>(ps, op, pm.tpart, m16);
+                    ps = apply_op<R, RB, true>(ps, op, pm.tpart, m16, flip);
                     if (op.kind == K_U2 && op.slot >= 0) {
 #pragma unroll
                         for (int e = 0; e < 16; ++e) {
@@ -580,7 +655,7 @@ k_tile_rev(const JobList jl, const Job single) {
                             red_add(red, slot + (2 * e + 1) * nwaves, gi, lane);
                         }
                     }
-                    la = apply_op<R, RB, true>(la, op, pm.tpart, m16);
+                    la = apply_op<R, RB, true>(la, op, pm.tpart, m16, flip_l);
                 }
             }
             if (f == f_begin) break;
@@ -600,11 +675,11 @@ k_tile_rev(const JobList jl, const Job single) {
         __syncthreads();
         if (active) regs_to_lds<R, RB>(ps, lds, pm);
         __syncthreads();
-        if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt);
+        if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt, flip);
         __syncthreads();
         if (active) regs_to_lds<R, RB>(la, lds, pm);
         __syncthreads();
-        if (active) tile_store<R, RB>(lds, lam, base, pi, t, nt);
+        if (active) tile_store<R, RB>(lds, lam, base, pi, t, nt, flip_l);
     }
     __syncthreads();
     double* part = J.part + size_t(b) * J.total_slots * wgs;
