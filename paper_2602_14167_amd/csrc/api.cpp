@@ -1424,7 +1424,7 @@ tcng_status tcng_shadow_snapshots(const tcng_circuit* layer, const void* psi, co
 namespace {
 struct MiptLayout {
     WsLayout F;                      // the fused forward of one step
-    size_t part_off = 0, keep_off = 0, total = 0;
+    size_t part_off = 0, keep_off = 0, list_off = 0, total = 0;
     int wgs = 0;
 };
 MiptLayout mipt_layout(const tcng_circuit* c, int n, int64_t batch) {
@@ -1433,7 +1433,8 @@ MiptLayout mipt_layout(const tcng_circuit* c, int n, int64_t batch) {
     M.wgs = mipt_wgs(n);
     M.part_off = align256(M.F.total);
     M.keep_off = M.part_off + align256(mipt_hist_doubles(n, batch) * sizeof(double));
-    M.total = M.keep_off + align256(size_t(batch) * sizeof(double));
+    M.list_off = M.keep_off + align256(size_t(batch) * sizeof(double));
+    M.total = M.list_off + align256(mipt_list_words(n, batch) * sizeof(uint32_t));
     return M;
 }
 tcng_status check_mipt(const tcng_circuit* c, int n) {
@@ -1474,6 +1475,7 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
     char* w = static_cast<char*>(ws);
     double* part = reinterpret_cast<double*>(w + M.part_off);
     double* keep = reinterpret_cast<double*>(w + M.keep_off);
+    uint32_t* lists = reinterpret_cast<uint32_t*>(w + M.list_off);
     PROF_TRY(F_MIPT_DECIDE, launch_zero_u32(rec, size_t(batch) * n_steps * 2, st));
     PROF_TRY(F_MIPT_DECIDE, launch_zero(logp, size_t(batch), st));
     Job J = make_job(step, nullptr, psi, nullptr, nullptr, nullptr, nullptr, M.F);
@@ -1497,10 +1499,14 @@ tcng_status tcng_mipt_run(const tcng_circuit* step, int32_t n_steps, const void*
         if (F.host.passes.empty() && s > 0)
             PROF_TRY(F_MIPT_COLLAPSE, launch_mipt_collapse(psi->amps, psi->stride, n, batch, n_steps, s - 1, rec, keep,
                                                            M.wgs, st));
-        // the measured qubits in rounds of up to 8: one histogram read and the decisions each
+        // the measured qubits in rounds of up to 8: one histogram read and the decisions
+        // each; rounds after the first visit only the members their predecessor listed
+        PROF_TRY(F_MIPT_DECIDE, launch_mipt_lists_reset(lists, n, batch, st));
         for (int r = 0; r < mipt_rounds(n); ++r) {
-            PROF_TRY(F_MIPT_HIST, launch_mipt_hist(psi->amps, psi->stride, n, batch, u, n_steps, s, p, r, rec, part, st));
-            PROF_TRY(F_MIPT_DECIDE, launch_mipt_decide(u, n, n_steps, s, p, r, part, rec, keep, logp, margin, batch, st));
+            PROF_TRY(F_MIPT_HIST,
+                     launch_mipt_hist(psi->amps, psi->stride, n, batch, u, n_steps, s, p, r, rec, part, lists, st));
+            PROF_TRY(F_MIPT_DECIDE,
+                     launch_mipt_decide(u, n, n_steps, s, p, r, part, rec, keep, logp, margin, lists, batch, st));
         }
     }
     if (n_steps > 0)

@@ -66,16 +66,14 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
     return out;
 }
 
-__global__ void __launch_bounds__(MTHREADS) k_mipt_hist(const float4* __restrict__ psi, int64_t stride4, int n,
-                                                        const double* __restrict__ u, int n_steps, int s, double p,
-                                                        int r, const uint32_t* __restrict__ rec, int wgs,
-                                                        double* __restrict__ part) {
-    __shared__ float w2[1 << HCHUNK];
-    __shared__ double red[MTHREADS];
-    const int64_t b = blockIdx.y;
-    const int wg = blockIdx.x;
+// one member's histogram partial of chunk wg (the whole workgroup returns
+// together when the member measures nothing in this round)
+__device__ __forceinline__ void hist_member(const float4* __restrict__ psi, int64_t stride4, int n,
+                                            const double* __restrict__ u, int n_steps, int s, double p, int r,
+                                            const uint32_t* __restrict__ rec, int wgs, double* __restrict__ part,
+                                            int64_t b, int wg, float* w2, double* red) {
     const uint32_t M = round_mask(u, b, n_steps, s, n, p, r);
-    if (!M) return;   // the whole workgroup leaves together
+    if (!M) return;
     const uint32_t md = rec[(b * n_steps + s) * 2], bd = rec[(b * n_steps + s) * 2 + 1];
     const uint32_t A = (1u << n) / uint32_t(wgs);   // amplitudes of the chunk (<= 2^HCHUNK)
     const uint32_t c0 = uint32_t(wg) * A;
@@ -102,37 +100,78 @@ __global__ void __launch_bounds__(MTHREADS) k_mipt_hist(const float4* __restrict
         w2[2 * i + 1] = k1 ? a[k].z * a[k].z + a[k].w * a[k].w : 0.f;
     }
     __syncthreads();
-    // bins of the round's qubits inside the chunk: thread t sums its share of bin t / T
-    // (T threads per bin) over the chunk's indices of that bin, in increasing order
+    // bins of the round's qubits inside the chunk: the T threads of bin t / T (kloc <=
+    // HK = 8) take the bin's indices f = part_i + k T (f numbers the chunk's free bits),
+    // so lanes read neighbouring LDS words; each thread sums its share in increasing k
     const uint32_t mloc = M & (A - 1), free = (A - 1) & ~mloc;
     const int kloc = __popc(mloc);
-    const int T = MTHREADS >> kloc;            // threads per bin (kloc <= HK = 8)
+    const int T = MTHREADS >> kloc;            // threads per bin
     const uint32_t j = threadIdx.x / T, part_i = threadIdx.x % T;
     const uint32_t per = (A >> kloc) / uint32_t(T);   // indices per thread (>= 1 at A >= 2^HK)
-    const uint32_t fixed = deposit(j, mloc);
-    uint32_t v = deposit(part_i * per, free);
-    double sum = 0.0;
-    for (uint32_t k = 0; k < per; ++k) {
-        sum += double(w2[v | fixed]);
-        v = ((v | ~free) + 1u) & free;   // next index of the free bits, increasing
+    // free_lo: the lowest log2(T) free bits (chosen by part_i), free_hi: the rest (by k)
+    uint32_t free_lo = 0, rest = free;
+    for (int i = 1; i < T; i <<= 1) {
+        free_lo |= rest & (0u - rest);
+        rest &= rest - 1u;
     }
-    red[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x < (1u << kloc)) {
-        double t = 0.0;
-        for (int k = 0; k < T; ++k) t += red[threadIdx.x * T + k];
-        part[(size_t(b) * wgs + wg) * HBINS + threadIdx.x] = t;
+    const uint32_t free_hi = free & ~free_lo;
+    const uint32_t base = deposit(j, mloc) | deposit(part_i, free_lo);
+    uint32_t v = 0;
+    double sum = 0.0;
+#pragma unroll 4
+    for (uint32_t k = 0; k < per; ++k) {
+        sum += double(w2[v | base]);
+        v = ((v | ~free_hi) + 1u) & free_hi;   // next index of the high free bits, increasing
+    }
+    // the T shares of a bin: a butterfly over min(T, 64) lanes (every lane adds the
+    // same two operands at each level, so all of them hold the same sum), then the
+    // bin's waves in increasing order
+    const int L = T < 64 ? T : 64;
+    for (int off = 1; off < L; off <<= 1) sum += __shfl_xor(sum, off, 64);
+    double* out = part + (size_t(b) * wgs + wg) * HBINS;
+    if (T <= 64) {
+        if (part_i == 0) out[j] = sum;
+    } else {
+        const int wave = threadIdx.x >> 6, per_bin = T >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = sum;
+        __syncthreads();
+        if (threadIdx.x < (1u << kloc)) {
+            double t = 0.0;
+            for (int k = 0; k < per_bin; ++k) t += red[threadIdx.x * per_bin + k];
+            out[threadIdx.x] = t;
+        }
+    }
+}
+
+// round 0: one member per grid row.  Later rounds: the members listed by the
+// previous round's decisions (those with a qubit in this round), looped over by
+// the grid rows.
+__global__ void __launch_bounds__(MTHREADS) k_mipt_hist(const float4* __restrict__ psi, int64_t stride4, int n,
+                                                        const double* __restrict__ u, int n_steps, int s, double p,
+                                                        int r, const uint32_t* __restrict__ rec, int wgs,
+                                                        double* __restrict__ part, const uint32_t* __restrict__ list,
+                                                        const uint32_t* __restrict__ cnt) {
+    __shared__ float w2[1 << HCHUNK];
+    __shared__ double red[MTHREADS / 64];
+    if (!list) {
+        hist_member(psi, stride4, n, u, n_steps, s, p, r, rec, wgs, part, blockIdx.y, blockIdx.x, w2, red);
+        return;
+    }
+    const uint32_t C = *cnt;
+    for (uint32_t i = blockIdx.y; i < C; i += gridDim.y) {
+        __syncthreads();   // LDS of the previous member
+        hist_member(psi, stride4, n, u, n_steps, s, p, r, rec, wgs, part, list[i], blockIdx.x, w2, red);
     }
 }
 
 // one wave per member: joint histogram of the round's qubits (bins: their bits
 // in increasing qubit order), then the decisions
-__global__ void __launch_bounds__(64) k_mipt_decide(const double* __restrict__ u, int n, int n_steps, int s, double p,
-                                                    int r, int wgs, const double* __restrict__ part,
-                                                    uint32_t* __restrict__ rec, double* __restrict__ keep,
-                                                    double* __restrict__ logp, double* __restrict__ margin) {
-    __shared__ double H[HBINS];
-    const int64_t b = blockIdx.x;
+__device__ __forceinline__ void decide_member(const double* __restrict__ u, int n, int n_steps, int s, double p,
+                                              int r, int wgs, const double* __restrict__ part,
+                                              uint32_t* __restrict__ rec, double* __restrict__ keep,
+                                              double* __restrict__ logp, double* __restrict__ margin,
+                                              uint32_t* __restrict__ list_next, uint32_t* __restrict__ cnt_next,
+                                              int64_t b, double* H) {
     const int lane = threadIdx.x;
     const uint32_t M = round_mask(u, b, n_steps, s, n, p, r);
     if (!M) return;
@@ -181,6 +220,30 @@ __global__ void __launch_bounds__(64) k_mipt_decide(const double* __restrict__ u
         logp[b] += lp;
         keep[b] = kp;
     }
+    // members with a qubit in the next round go on its list
+    if (list_next && lane == 0 && round_mask(u, b, n_steps, s, n, p, r + 1) != 0u)
+        list_next[atomicAdd(cnt_next, 1u)] = uint32_t(b);
+}
+
+// round 0: one member per workgroup; later rounds: the listed members.  The
+// order of a list depends on scheduling, its content and every member's
+// results do not.
+__global__ void __launch_bounds__(64) k_mipt_decide(const double* __restrict__ u, int n, int n_steps, int s, double p,
+                                                    int r, int wgs, const double* __restrict__ part,
+                                                    uint32_t* __restrict__ rec, double* __restrict__ keep,
+                                                    double* __restrict__ logp, double* __restrict__ margin,
+                                                    const uint32_t* __restrict__ list, const uint32_t* __restrict__ cnt,
+                                                    uint32_t* __restrict__ list_next, uint32_t* __restrict__ cnt_next) {
+    __shared__ double H[HBINS];
+    if (!list) {
+        decide_member(u, n, n_steps, s, p, r, wgs, part, rec, keep, logp, margin, list_next, cnt_next, blockIdx.x, H);
+        return;
+    }
+    const uint32_t C = *cnt;
+    for (uint32_t i = blockIdx.x; i < C; i += gridDim.x) {
+        __syncthreads();
+        decide_member(u, n, n_steps, s, p, r, wgs, part, rec, keep, logp, margin, list_next, cnt_next, list[i], H);
+    }
 }
 
 __global__ void __launch_bounds__(MTHREADS) k_mipt_collapse(float4* __restrict__ psi, int64_t stride4, int n,
@@ -205,6 +268,10 @@ __global__ void __launch_bounds__(MTHREADS) k_mipt_collapse(float4* __restrict__
     }
 }
 
+__global__ void k_reset_counts(uint32_t* lists, int rounds, size_t stride) {
+    if (int(threadIdx.x) < rounds) lists[size_t(threadIdx.x) * stride] = 0u;
+}
+
 __global__ void k_zero_u32(uint32_t* p, size_t count) {
     for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += size_t(gridDim.x) * 256) p[i] = 0u;
 }
@@ -220,22 +287,45 @@ int mipt_hist_wgs(int n) { return n > HCHUNK ? 1 << (n - HCHUNK) : 1; }
 int mipt_rounds(int n) { return (n + HK - 1) / HK; }
 size_t mipt_hist_doubles(int n, int64_t batch) { return size_t(batch) * mipt_hist_wgs(n) * HBINS; }
 
+size_t mipt_list_words(int n, int64_t batch) { return size_t(mipt_rounds(n)) * (size_t(batch) + 1); }
+
+// rows of the grid that loop over a later round's member list
+static unsigned list_rows(int64_t batch, unsigned cap) { return unsigned(std::min<int64_t>(batch, cap)); }
+
 hipError_t launch_mipt_hist(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
-                            double p, int r, const uint32_t* rec, double* part, hipStream_t st) {
+                            double p, int r, const uint32_t* rec, double* part, const uint32_t* lists,
+                            hipStream_t st) {
     if (batch == 0) return hipSuccess;
     if (n < HK) return hipErrorInvalidValue;   // a chunk holds at least one index per thread and bin
     const int wgs = mipt_hist_wgs(n);
-    hipLaunchKernelGGL(k_mipt_hist, dim3(unsigned(wgs), unsigned(batch)), dim3(MTHREADS), 0, st,
-                       static_cast<const float4*>(psi), stride / 2, n, u, n_steps, s, p, r, rec, wgs, part);
+    const uint32_t* list = r > 0 ? lists + size_t(r) * (batch + 1) + 1 : nullptr;
+    const uint32_t* cnt = r > 0 ? lists + size_t(r) * (batch + 1) : nullptr;
+    const unsigned rows = r > 0 ? list_rows(batch, 64) : unsigned(batch);
+    hipLaunchKernelGGL(k_mipt_hist, dim3(unsigned(wgs), rows), dim3(MTHREADS), 0, st, static_cast<const float4*>(psi),
+                       stride / 2, n, u, n_steps, s, p, r, rec, wgs, part, list, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, double p, int r, const double* part,
-                              uint32_t* rec, double* keep, double* logp, double* margin, int64_t batch,
-                              hipStream_t st) {
+                              uint32_t* rec, double* keep, double* logp, double* margin, uint32_t* lists,
+                              int64_t batch, hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mipt_decide, dim3(unsigned(batch)), dim3(64), 0, st, u, n, n_steps, s, p, r,
-                       mipt_hist_wgs(n), part, rec, keep, logp, margin);
+    const size_t L = size_t(batch) + 1;
+    const uint32_t* list = r > 0 ? lists + size_t(r) * L + 1 : nullptr;
+    const uint32_t* cnt = r > 0 ? lists + size_t(r) * L : nullptr;
+    const bool next = r + 1 < mipt_rounds(n);
+    uint32_t* list_next = next ? lists + size_t(r + 1) * L + 1 : nullptr;
+    uint32_t* cnt_next = next ? lists + size_t(r + 1) * L : nullptr;
+    const unsigned rows = r > 0 ? list_rows(batch, 1024) : unsigned(batch);
+    hipLaunchKernelGGL(k_mipt_decide, dim3(rows), dim3(64), 0, st, u, n, n_steps, s, p, r, mipt_hist_wgs(n), part,
+                       rec, keep, logp, margin, list, cnt, list_next, cnt_next);
+    return hipGetLastError();
+}
+
+// the list counters of rounds 1.. (before a step's round 0)
+hipError_t launch_mipt_lists_reset(uint32_t* lists, int n, int64_t batch, hipStream_t st) {
+    if (batch == 0 || mipt_rounds(n) < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_counts, dim3(1), dim3(64), 0, st, lists, mipt_rounds(n), size_t(batch) + 1);
     return hipGetLastError();
 }
 

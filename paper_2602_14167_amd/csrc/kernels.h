@@ -176,11 +176,16 @@ int mipt_wgs(int n);
 int mipt_hist_wgs(int n);
 int mipt_rounds(int n);
 size_t mipt_hist_doubles(int n, int64_t batch);
+// member lists of the rounds after the first: per round a counter and batch
+// entries (round r's decisions list the members with a qubit in round r + 1)
+size_t mipt_list_words(int n, int64_t batch);
+hipError_t launch_mipt_lists_reset(uint32_t* lists, int n, int64_t batch, hipStream_t st);
 hipError_t launch_mipt_hist(const void* psi, int64_t stride, int n, int64_t batch, const double* u, int n_steps, int s,
-                            double p, int r, const uint32_t* rec, double* part, hipStream_t st);
+                            double p, int r, const uint32_t* rec, double* part, const uint32_t* lists,
+                            hipStream_t st);
 hipError_t launch_mipt_decide(const double* u, int n, int n_steps, int s, double p, int r, const double* part,
-                              uint32_t* rec, double* keep, double* logp, double* margin, int64_t batch,
-                              hipStream_t st);
+                              uint32_t* rec, double* keep, double* logp, double* margin, uint32_t* lists,
+                              int64_t batch, hipStream_t st);
 hipError_t launch_mipt_collapse(void* psi, int64_t stride, int n, int64_t batch, int n_steps, int s,
                                 const uint32_t* rec, const double* keep, int wgs, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t st);
