@@ -55,18 +55,18 @@ KERNEL_SOURCES = {
     "plain": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_plain.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.608e+09, "3562a1ea2ffdc471"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.298e+09, "3562a1ea2ffdc471"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.787e+09, "1d30ca8be5b147dc"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.296e+09, "1d30ca8be5b147dc"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.686e+10, "1d30ca8be5b147dc"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.098e+08, "1d30ca8be5b147dc"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.465e+08, "1d30ca8be5b147dc"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.745e+08, "1d30ca8be5b147dc"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.284e+08, "1d30ca8be5b147dc"),
-    ("haar_brickwork_uneven_1024", "fused_rev"): (1.515e+10, "1d30ca8be5b147dc"),
-    ("tfim_coo_n24", "pauli_coo"): (1.342e+10, "a892d74871e9a4e5"),
-    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7187e+10, "860d66c76ac604b3"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.6076e+09, "d7072ed679cc66aa"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.2981e+09, "d7072ed679cc66aa"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.7866e+09, "66d1390ee27fbd6c"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.2964e+09, "66d1390ee27fbd6c"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6865e+10, "66d1390ee27fbd6c"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0970e+08, "66d1390ee27fbd6c"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4651e+08, "66d1390ee27fbd6c"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7451e+08, "66d1390ee27fbd6c"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2843e+08, "66d1390ee27fbd6c"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5149e+10, "66d1390ee27fbd6c"),
+    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "68bfec6c64405833"),
+    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7187e+10, "d029f66455d0abfb"),
 }
 
 
