@@ -134,6 +134,12 @@ class Circuit:
         check(lib().tcng_circuit_get_mode(self.handle, _dt(dtype), ctypes.byref(v)))
         return MODE_NAMES[v.value]
 
+    def rounds(self, dtype=torch.complex64):
+        """Number of rotation-round phases of the tiled plan (0: not on that path)."""
+        v = ctypes.c_int32()
+        check(lib().tcng_circuit_rounds(self.handle, _dt(dtype), ctypes.byref(v)))
+        return v.value
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib._lib is not None:

@@ -27,7 +27,8 @@ EXPORTS = [
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
     "tcng_shadow_workspace_size", "tcng_shadow_snapshots", "tcng_qml_workspace_size", "tcng_qml_step",
-    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes", "tcng_circuit_get_mode", "tcng_multi_create",
+    "tcng_expect_grad_noalloc", "tcng_noalloc_scratch_bytes", "tcng_circuit_get_mode", "tcng_circuit_rounds",
+    "tcng_multi_create",
     "tcng_multi_launch", "tcng_multi_destroy", "tcng_graph_create_multi",
 ]
 
@@ -86,6 +87,7 @@ def lib():
     L.tcng_circuit_configure.argtypes = [P, i32, i32, i32, i32]
     L.tcng_circuit_get_config.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.tcng_circuit_get_mode.argtypes = [P, i32, ctypes.POINTER(i32)]
+    L.tcng_circuit_rounds.argtypes = [P, i32, ctypes.POINTER(i32)]
     L.tcng_autotune.argtypes = [P, P, P, PS, PS, i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), P]
     L.tcng_profile_begin.argtypes = [i32]
     L.tcng_profile_query.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]

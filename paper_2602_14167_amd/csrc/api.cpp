@@ -128,6 +128,9 @@ struct DevCircuitPlan {
     Pass* rpasses = nullptr;
     Phase* rphases = nullptr;
     Op* rops = nullptr;
+    QPass* qpasses = nullptr;     // rotation rounds (host.rounds)
+    QPhase* qphases = nullptr;
+    QStep* qsteps = nullptr;
     SlotTables slots;
 };
 
@@ -172,6 +175,9 @@ void free_plan(DevCircuitPlan& P) {
     (void)hipFree(P.rpasses);
     (void)hipFree(P.rphases);
     (void)hipFree(P.rops);
+    (void)hipFree(P.qpasses);
+    (void)hipFree(P.qphases);
+    (void)hipFree(P.qsteps);
     (void)hipFree(P.slots.ptr);
     (void)hipFree(P.slots.idx);
     (void)hipFree(P.slots.gate_slot);
@@ -239,7 +245,10 @@ tcng_status make_plan(tcng_circuit* c, int dt, const TileConfig& cfg) {
     if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "planner: " + why);
     if (upload(P.host.passes, &P.passes) != hipSuccess || upload(P.host.phases, &P.phases) != hipSuccess ||
         upload(P.host.ops, &P.ops) != hipSuccess || upload(P.host.rpasses, &P.rpasses) != hipSuccess ||
-        upload(P.host.rphases, &P.rphases) != hipSuccess || upload(P.host.rops, &P.rops) != hipSuccess) {
+        upload(P.host.rphases, &P.rphases) != hipSuccess || upload(P.host.rops, &P.rops) != hipSuccess ||
+        (P.host.rounds && (upload(P.host.qpasses, &P.qpasses) != hipSuccess ||
+                           upload(P.host.qphases, &P.qphases) != hipSuccess ||
+                           upload(P.host.qsteps, &P.qsteps) != hipSuccess))) {
         free_plan(P);
         return fail(TCNG_E_ALLOC, "device allocation failed");
     }
@@ -440,6 +449,11 @@ Job make_job(const tcng_circuit* c, const tcng_pauli_sum* h, const tcng_state* s
         J.rpasses = P.rpasses;
         J.rphases = P.rphases;
         J.rops = P.rops;
+        if (dt == TCNG_C64 && P.host.rounds) {
+            J.qpasses = P.qpasses;
+            J.qphases = P.qphases;
+            J.qsteps = P.qsteps;
+        }
         J.n_passes = int32_t(P.host.passes.size());
         J.n_gates = int32_t(c->gates.size());
         J.tiles = int64_t(1) << (s->n_qubits - std::min(s->n_qubits, P.host.cfg.m_max));
@@ -490,7 +504,9 @@ tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_st
             const int m = P.host.passes[p].m;
             const JobList jl{nullptr, nullptr, 0, int32_t(p)};
             const int64_t blocks = J.tiles * J.batch;
-            if (rb == RB)
+            if (J.qpasses)
+                PROF_TRY(F_FWD_TILE, launch_rounds_fwd(jl, J, blocks, 1 << (m - QREG), st));
+            else if (rb == RB)
                 PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
             else
                 PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB - 1>(jl, J, blocks, 1 << (m - RB + 1), st)));
@@ -553,7 +569,9 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
             const int m = P.host.rpasses[np - 1 - k].m;
             const JobList jl{nullptr, nullptr, 0, int32_t(k)};
             const int64_t blocks = int64_t(J.wgs) * J.batch;
-            if (rb == RB)
+            if (J.qpasses)
+                PROF_TRY(F_REV_TILE, launch_rounds_rev(jl, J, blocks, 1 << (m - QREG), st));
+            else if (rb == RB)
                 PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
             else
                 PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB - 1>(jl, J, blocks, 1 << (m - RB + 1), st)));
@@ -2064,6 +2082,14 @@ std::string circuit_key(const tcng_circuit* c, int dtype, int64_t batch) {
 }
 
 }  // namespace
+
+tcng_status tcng_circuit_rounds(const tcng_circuit* c, int32_t dtype, int32_t* phases) {
+    if (!c || !phases) return fail(TCNG_E_INVALID, "null argument");
+    if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
+    const DevCircuitPlan& P = c->tiled[dtype];
+    *phases = (dtype == TCNG_C64 && P.valid && P.host.rounds) ? int32_t(P.host.qphases.size()) : 0;
+    return ok();
+}
 
 tcng_status tcng_circuit_get_mode(const tcng_circuit* c, int32_t dtype, int32_t* mode) {
     if (!c || !mode) return fail(TCNG_E_INVALID, "null argument");

@@ -112,6 +112,35 @@ struct Pass {
 };
 
 // ---------------------------------------------------------------------------
+// Rotation rounds: the tiled passes of a circuit made of RY, RZ and CNOT only
+// (complex64, 5 register bits).  The register position of every rotation is
+// a compile-time constant of the kernel: a phase holds up to 5 qubits in
+// registers and runs rounds (RY on register bits 0..4, then RZ on 0..4; an
+// absent gate is the identity rotation).  The phase's CNOTs, all taken after
+// its rounds, form a GF(2)-linear permutation of the tile's local index:
+// amplitude y of the phase moves to C(y), which the phase applies by writing
+// register j at LDS position C(y) (the reverse sweep reads it from there).
+// C is given by cimg[b] = C(e_b), the image of local bit b.
+// ---------------------------------------------------------------------------
+constexpr int QREG = 5;
+
+struct QStep {
+    int32_t ry[QREG], rz[QREG];   // gate index of the RY / RZ on register bit i, -1: identity
+    int32_t sy[QREG], sz[QREG];   // its gradient slot inside the pass, -1 none
+};
+
+struct QPhase {
+    int32_t step_begin, step_end;
+    int32_t R[QREG];              // local bit of register bit i
+    int32_t has_map;              // 0: C is the identity
+    int32_t cimg[16];             // C(e_b) for local bits b < m
+};
+
+struct QPass {
+    int32_t phase_begin, phase_end;
+};
+
+// ---------------------------------------------------------------------------
 // fused passes: each phase applies one 2^FUSED_K x 2^FUSED_K block matrix on
 // matrix cores.  A tile's local index splits, per phase, into the block index
 // j (local bits R[0..3], R[t] = bit t of j) and the column index (the other

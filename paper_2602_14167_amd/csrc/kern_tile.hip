@@ -473,7 +473,19 @@ __device__ __forceinline__ void build_op(const Op& op, const R* prm, const cx<R>
         case OP_DENSE2: case OP_FSIM: mat2<R>(op.kind, prm, op.p0, op.p1, cm, op.mat, u); break;
         default: break;
     }
-    const int cnt = (op.type == OP_DENSE2 || op.type == OP_FSIM) ? 16 : (op.type == OP_CX ? 0 : 4);
+    int cnt = (op.type == OP_DENSE2 || op.type == OP_FSIM) ? 16 : (op.type == OP_CX ? 0 : 4);
+    if (op.kind == K_RY || op.kind == K_RZ) {
+        // shear coefficients for the rotation rounds: entry 4 = (t, s), entry 5 = (-1 if the
+        // rotation is taken as -R(a - pi), else 1; 0).  RY: cos, sin of a = theta / 2 in
+        // u[0], u[2]; RZ: the phase of |1> is u[1] = cos + i sin.
+        const R c = op.kind == K_RY ? u[0].re : u[1].re;
+        const R sn = op.kind == K_RY ? u[2].re : u[1].im;
+        bool flip = false;
+        const Lift<R> L = lift_of<R>(c, sn, flip);
+        u[4] = {L.t, L.s};
+        u[5] = {flip ? R(-1) : R(1), R(0)};
+        cnt = 6;
+    }
 #pragma unroll
     for (int k = 0; k < 16; ++k)
         if (k < cnt) dst[k] = u[k];
@@ -690,6 +702,294 @@ k_tile_rev(const JobList jl, const Job single) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// rotation rounds (complex64, 5 register bits; see QPhase)
+// ---------------------------------------------------------------------------
+// A zero the compiler cannot see through.  XORed into an address it stops the
+// address arithmetic of one use from being shared with (or hoisted to) another:
+// shared, the 32 element addresses of a tile (64-bit global, or LDS) stay live
+// from the load to the store and the reverse sweep needs 370 registers.
+__device__ __forceinline__ uint32_t opaque_zero() {
+    uint32_t z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
+using QBlk = Regs<float, (1 << QREG)>;
+
+// a phase's register map: the thread's part of the local index, and the LDS
+// positions of its registers with and without the phase's permutation C
+struct QMap {
+    uint32_t tsw, ctsw;          // swz(tpart), swz(C(tpart))
+    uint32_t rsw[QREG], crsw[QREG];   // swz(e_R[i]), swz(C(e_R[i])) (uniform)
+};
+
+__device__ __forceinline__ QMap qmap(cptr<QPhase> F, int t, int m) {
+    QMap q;
+    uint32_t rmask = 0;
+#pragma unroll
+    for (int i = 0; i < QREG; ++i) {
+        const int l = F->R[i];
+        rmask |= 1u << l;
+        q.rsw[i] = swz(1u << l);
+        q.crsw[i] = swz(uint32_t(F->cimg[l]));
+    }
+    uint32_t tp = 0, ct = 0;
+    int k = 0;
+    for (int b = 0; b < m; ++b) {
+        if ((rmask >> b) & 1) continue;
+        if ((t >> k) & 1) {
+            tp |= 1u << b;
+            ct ^= uint32_t(F->cimg[b]);
+        }
+        ++k;
+    }
+    q.tsw = swz(tp);
+    q.ctsw = swz(ct);
+    return q;
+}
+
+// LDS position of register j: through C (mapped) or not
+template <bool MAPPED>
+__device__ __forceinline__ uint32_t qaddr(const QMap& q, int j) {
+    uint32_t a = MAPPED ? q.ctsw : q.tsw;
+#pragma unroll
+    for (int i = 0; i < QREG; ++i)
+        if ((j >> i) & 1) a ^= MAPPED ? q.crsw[i] : q.rsw[i];
+    return a;
+}
+
+// (each call forms its addresses anew: shared between calls, the compiler
+// keeps them all live in registers across the sweep)
+template <bool MAPPED>
+__device__ __forceinline__ QBlk q_read(const cx<float>* lds, const QMap& q) {
+    const uint32_t z = opaque_zero();
+    QBlk a;
+#pragma unroll
+    for (int j = 0; j < (1 << QREG); ++j) a.v[j] = lds[qaddr<MAPPED>(q, j) ^ z];
+    return a;
+}
+template <bool MAPPED>
+__device__ __forceinline__ void q_write(cx<float>* lds, const QBlk& a, const QMap& q) {
+    const uint32_t z = opaque_zero();
+#pragma unroll
+    for (int j = 0; j < (1 << QREG); ++j) lds[qaddr<MAPPED>(q, j) ^ z] = a.v[j];
+}
+
+// shear coefficients of gate g (identity for g < 0); INV: the inverse rotation
+template <bool INV>
+__device__ __forceinline__ Lift<float> q_lift(cptr<cx<float>> om, int g, bool& flip) {
+    if (g < 0) return {0.f, 0.f};
+    const cx<float> e = om[size_t(g) * 16 + 4];
+    if (om[size_t(g) * 16 + 5].re < 0.f) flip = !flip;
+    return INV ? Lift<float>{-e.re, -e.im} : Lift<float>{e.re, e.im};
+}
+
+// RY on register bits 0..4, then (separately) RZ on 0..4, with the register
+// positions unrolled: no run-time register index, so no copies of the block
+template <bool INV>
+__device__ __forceinline__ QBlk q_ry_round(QBlk a, const int32_t* g, cptr<cx<float>> om, bool& flip) {
+    a = app_ry_lift<float, 32, 0>(a, q_lift<INV>(om, g[0], flip));
+    a = app_ry_lift<float, 32, 1>(a, q_lift<INV>(om, g[1], flip));
+    a = app_ry_lift<float, 32, 2>(a, q_lift<INV>(om, g[2], flip));
+    a = app_ry_lift<float, 32, 3>(a, q_lift<INV>(om, g[3], flip));
+    a = app_ry_lift<float, 32, 4>(a, q_lift<INV>(om, g[4], flip));
+    return a;
+}
+template <bool INV>
+__device__ __forceinline__ QBlk q_rz_round(QBlk a, const int32_t* g, cptr<cx<float>> om, bool& flip) {
+    a = app_rz_lift<float, 32, 0>(a, q_lift<INV>(om, g[0], flip));
+    a = app_rz_lift<float, 32, 1>(a, q_lift<INV>(om, g[1], flip));
+    a = app_rz_lift<float, 32, 2>(a, q_lift<INV>(om, g[2], flip));
+    a = app_rz_lift<float, 32, 3>(a, q_lift<INV>(om, g[3], flip));
+    a = app_rz_lift<float, 32, 4>(a, q_lift<INV>(om, g[4], flip));
+    return a;
+}
+
+// tile_load / tile_store of the rotation rounds (complex64, 32 amplitudes per
+// thread): element it of thread t is local index (it * nt + t) * 2 (+1)
+__device__ __forceinline__ void q_tile_load(cx<float>* lds, gptr<const cx<float>> psi, uint64_t base,
+                                            const PassInfo& pi, int t, int nt) {
+    const uint32_t zo = opaque_zero();
+    const uint64_t off_t = loc2glob(uint32_t(t * 2) ^ zo, pi.lo, pi.m, pi.lq);
+    cx<float> v[32];
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const uint64_t g = base + loc2glob(uint32_t(it * nt * 2) ^ zo, pi.lo, pi.m, pi.lq) + off_t;
+        V16<float>::load(psi + g, &v[it * 2]);
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const uint32_t e = uint32_t((it * nt + t) * 2) ^ zo;
+        lds[swz(e)] = v[it * 2];
+        lds[swz(e + 1)] = v[it * 2 + 1];
+    }
+}
+
+__device__ __forceinline__ void q_tile_store(const cx<float>* lds, gptr<cx<float>> psi, uint64_t base,
+                                             const PassInfo& pi, int t, int nt, bool flip) {
+    const uint32_t zo = opaque_zero();
+    const uint64_t off_t = loc2glob(uint32_t(t * 2) ^ zo, pi.lo, pi.m, pi.lq);
+    const float sg = flip ? -1.f : 1.f;
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const uint32_t e = uint32_t((it * nt + t) * 2) ^ zo;
+        cx<float> v[2] = {lds[swz(e)], lds[swz(e + 1)]};
+        if (flip) {
+            v[0] = {sg * v[0].re, sg * v[0].im};
+            v[1] = {sg * v[1].re, sg * v[1].im};
+        }
+        const uint64_t g = base + loc2glob(uint32_t(it * nt * 2) ^ zo, pi.lo, pi.m, pi.lq) + off_t;
+        V16<float>::store(psi + g, v);
+    }
+}
+
+// a round's five derivative partials into their slots (absent gates have none)
+__device__ __forceinline__ void q_red5(double* red, const int32_t* slot, int nwaves, int wave, int lane, float g0,
+                                       float g1, float g2, float g3, float g4) {
+    if (slot[0] >= 0) red_add(red, slot[0] * nwaves + wave, g0, lane);
+    if (slot[1] >= 0) red_add(red, slot[1] * nwaves + wave, g1, lane);
+    if (slot[2] >= 0) red_add(red, slot[2] * nwaves + wave, g2, lane);
+    if (slot[3] >= 0) red_add(red, slot[3] * nwaves + wave, g3, lane);
+    if (slot[4] >= 0) red_add(red, slot[4] * nwaves + wave, g4, lane);
+}
+
+__global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_fwd(const JobList jl, const Job single) {
+    __shared__ cx<float> lds[Tile<float>::ELEMS];
+    int64_t local;
+    const Job J = load_job(jl, single, blockIdx.x, local);
+    cptr<Pass> P = as_const(J.passes) + jl.step;
+    const PassInfo pi = read_pass(P);
+    const QPass Q = as_const(J.qpasses)[jl.step];
+    // the launch has exactly 2^(m - QREG) threads: every wave is active
+    const int nt = 1 << (pi.m - QREG);
+    const int t = threadIdx.x;
+    const int64_t b = local / J.tiles;
+    const uint64_t tile = uint64_t(local - b * J.tiles);
+    gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
+    cptr<cx<float>> om = as_const(static_cast<const cx<float>*>(J.opm)) + size_t(b) * J.n_gates * 16;
+    cptr<QPhase> phases = as_const(J.qphases);
+    cptr<QStep> steps = as_const(J.qsteps);
+    const uint64_t base = tile_base(tile, pi.tmask, J.n);
+
+    q_tile_load(lds, psi, base, pi, t, nt);
+    __syncthreads();
+    bool flip = false;
+    for (int f = Q.phase_begin; f < Q.phase_end; ++f) {
+        cptr<QPhase> F = phases + f;
+        const QMap q = qmap(F, t, pi.m);
+        QBlk a = q_read<false>(lds, q);
+        const int s_end = F->step_end;
+        for (int s = F->step_begin; s < s_end; ++s) {
+            const QStep S = steps[s];
+            a = q_ry_round<false>(a, S.ry, om, flip);
+            a = q_rz_round<false>(a, S.rz, om, flip);
+        }
+        __syncthreads();   // the write permutes positions: every read first
+        q_write<true>(lds, a, q);
+        __syncthreads();
+    }
+    q_tile_store(lds, psi, base, pi, t, nt, flip);
+}
+
+// reverse: phases and steps backwards; each phase reads through C, un-applies
+// its rounds (derivatives first: every rotation of a round at the round's
+// end point, where all of them commute) and writes without C
+__global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_rev(const JobList jl, const Job single) {
+    __shared__ cx<float> lds[Tile<float>::ELEMS];
+    __shared__ double red[RED_SLOTS * ((1 << (13 - QREG)) / 64)];
+    int64_t local;
+    const Job J = load_job(jl, single, blockIdx.x, local);
+    const int pidx = J.n_passes - 1 - jl.step;
+    cptr<Pass> P = as_const(J.passes) + pidx;
+    const PassInfo pi = read_pass(P);
+    const QPass Q = as_const(J.qpasses)[pidx];
+    const int nt = 1 << (pi.m - QREG);   // the launch's thread count: every wave is active
+    const int nwaves = nt >> 6;
+    const int t = threadIdx.x;
+    const int wave = uniform(t >> 6), lane = t & 63;
+    const int wgs = J.wgs;
+    const int64_t b = local / wgs;
+    const int wg = int(local - b * wgs);
+    gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
+    gptr<cx<float>> lam = as_global(static_cast<cx<float>*>(J.costate)) + b * J.stride;
+    cptr<cx<float>> om = as_const(static_cast<const cx<float>*>(J.opm)) + size_t(b) * J.n_gates * 16;
+    cptr<QPhase> phases = as_const(J.qphases);
+    cptr<QStep> steps = as_const(J.qsteps);
+    const int nslots = P->n_slots;
+
+    for (int i = t; i < nslots * nwaves; i += blockDim.x) red[i] = 0.0;
+    // (the first __syncthreads below orders these writes before any accumulation)
+
+    for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
+        const uint64_t base = tile_base(uint64_t(tile), pi.tmask, J.n);
+        int f = Q.phase_end - 1;
+        QMap q = qmap(phases + f, t, pi.m);
+        QBlk ps, la;
+        bool flip = false, flip_l = false;   // equal: psi and lambda see the same rotations
+        __syncthreads();
+        q_tile_load(lds, psi, base, pi, t, nt);
+        __syncthreads();
+        ps = q_read<true>(lds, q);
+        __syncthreads();
+        q_tile_load(lds, lam, base, pi, t, nt);
+        __syncthreads();
+        la = q_read<true>(lds, q);
+        for (;;) {
+            {
+                cptr<QPhase> F = phases + f;
+                const int s_begin = F->step_begin;
+                for (int s = F->step_end - 1; s >= s_begin; --s) {
+                    const QStep S = steps[s];
+                    // the round's derivatives first (five sums), then the un-apply,
+                    // then their reductions (which leave the blocks alone)
+                    const float gz0 = grad_rz<float, 32, 0>(la, ps), gz1 = grad_rz<float, 32, 1>(la, ps),
+                                gz2 = grad_rz<float, 32, 2>(la, ps), gz3 = grad_rz<float, 32, 3>(la, ps),
+                                gz4 = grad_rz<float, 32, 4>(la, ps);
+                    ps = q_rz_round<true>(ps, S.rz, om, flip);
+                    la = q_rz_round<true>(la, S.rz, om, flip_l);
+                    q_red5(red, S.sz, nwaves, wave, lane, gz0, gz1, gz2, gz3, gz4);
+                    const float gy0 = grad_rot1<float, 32, 0>(K_RY, la, ps), gy1 = grad_rot1<float, 32, 1>(K_RY, la, ps),
+                                gy2 = grad_rot1<float, 32, 2>(K_RY, la, ps), gy3 = grad_rot1<float, 32, 3>(K_RY, la, ps),
+                                gy4 = grad_rot1<float, 32, 4>(K_RY, la, ps);
+                    ps = q_ry_round<true>(ps, S.ry, om, flip);
+                    la = q_ry_round<true>(la, S.ry, om, flip_l);
+                    q_red5(red, S.sy, nwaves, wave, lane, gy0, gy1, gy2, gy3, gy4);
+                }
+            }
+            if (f == Q.phase_begin) break;
+            // hand both blocks to the previous phase: written in plain order,
+            // read back through that phase's permutation
+            const QMap qn = qmap(phases + (f - 1), t, pi.m);
+            __syncthreads();
+            q_write<false>(lds, ps, q);
+            __syncthreads();
+            ps = q_read<true>(lds, qn);
+            __syncthreads();
+            q_write<false>(lds, la, q);
+            __syncthreads();
+            la = q_read<true>(lds, qn);
+            q = qn;
+            --f;
+        }
+        __syncthreads();
+        q_write<false>(lds, ps, q);
+        __syncthreads();
+        q_tile_store(lds, psi, base, pi, t, nt, flip);
+        __syncthreads();
+        q_write<false>(lds, la, q);
+        __syncthreads();
+        q_tile_store(lds, lam, base, pi, t, nt, flip_l);
+    }
+    __syncthreads();
+    double* part = J.part + size_t(b) * J.total_slots * wgs;
+    for (int s = t; s < nslots; s += blockDim.x) {
+        double v = 0.0;
+        for (int w = 0; w < nwaves; ++w) v += red[s * nwaves + w];
+        part[size_t(P->slot_base + s) * wgs + wg] = v;
+    }
+}
+
 }  // namespace
 
 template <typename R>
@@ -714,6 +1014,21 @@ template <typename R, int RB>
 hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_tile_rev<R, RB>), dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
+    return hipGetLastError();
+}
+
+// nthreads must be 2^(m - QREG) for the launched pass's m (single jobs only)
+hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (jl.jobs || nthreads > (1 << (13 - QREG)) || nthreads < 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rounds_fwd, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
+    return hipGetLastError();
+}
+
+hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (jl.jobs || nthreads > (1 << (13 - QREG)) || nthreads < 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rounds_rev, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
     return hipGetLastError();
 }
 

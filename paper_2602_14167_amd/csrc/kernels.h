@@ -52,6 +52,9 @@ struct Job {
     int64_t src_stride;       // src + b * src_stride (0: one state for every member) instead of its own state
     int64_t init_basis1;      // 0, or 1 + a basis index: the first fused forward pass starts every member
                               // from that basis state (formed in LDS; the state is not read)
+    const QPass* qpasses;     // rotation rounds of the tiled passes (complex64), or null
+    const QPhase* qphases;
+    const QStep* qsteps;
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
@@ -77,6 +80,9 @@ hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, in
 // nthreads: workgroup size (2^(m - RB) of the largest tile among the jobs)
 template <typename R, int RB>
 hipError_t launch_tile_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
+// rotation rounds (complex64, 5 register bits; the job's qpasses are set)
+hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
+hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 template <typename R, int RB>

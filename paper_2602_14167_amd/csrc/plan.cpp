@@ -149,6 +149,105 @@ std::string plan_phases(const std::vector<tcng_gate>& gates, const std::vector<i
     return "";
 }
 
+// Rotation rounds of one pass (see QPhase).  A phase takes up to QREG qubits
+// whose first remaining gate is a rotation, then steps: each step applies, per
+// register qubit, its first remaining gate if that is an RY, then its next if
+// that is an RZ.  Then every CNOT whose qubits no earlier remaining gate
+// touches joins the phase's permutation, in circuit order.
+std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<int>& sel, const int* qubit_to_local,
+                        int m, const std::vector<int32_t>& gate_slot_first, std::vector<QPhase>& phases,
+                        std::vector<QStep>& steps, QPass& qp) {
+    qp.phase_begin = int(phases.size());
+    const size_t first_step = steps.size();
+    size_t cnots = 0;
+    std::vector<int> rem = sel;
+    auto first_gate = [&](int q) -> int {   // position in rem of the first remaining gate on q
+        for (size_t i = 0; i < rem.size(); ++i)
+            if ((gate_qmask(gates[rem[i]]) >> q) & 1) return int(i);
+        return -1;
+    };
+    auto drop = [&](std::vector<char>& mark) {
+        std::vector<int> keep;
+        for (size_t i = 0; i < rem.size(); ++i)
+            if (!mark[i]) keep.push_back(rem[i]);
+        rem.swap(keep);
+    };
+    while (!rem.empty()) {
+        // register qubits: the first QREG whose first remaining gate is a rotation
+        std::vector<int> R;
+        for (size_t i = 0; i < rem.size() && int(R.size()) < QREG; ++i) {
+            const tcng_gate& g = gates[rem[i]];
+            if (g.kind == K_CNOT) continue;
+            if (std::find(R.begin(), R.end(), g.q0) != R.end()) continue;
+            if (first_gate(g.q0) == int(i)) R.push_back(g.q0);
+        }
+        QPhase F{};
+        F.step_begin = int(steps.size());
+        for (;;) {
+            QStep S;
+            for (int b = 0; b < QREG; ++b) S.ry[b] = S.rz[b] = S.sy[b] = S.sz[b] = -1;
+            bool took = false;
+            for (int round = 0; round < 2; ++round) {
+                const int kind = round == 0 ? K_RY : K_RZ;
+                std::vector<char> mark(rem.size(), 0);
+                for (size_t b = 0; b < R.size(); ++b) {
+                    const int i = first_gate(R[b]);
+                    if (i < 0 || gates[rem[i]].kind != kind) continue;
+                    const int gi = rem[i];
+                    (round == 0 ? S.ry : S.rz)[b] = gi;
+                    (round == 0 ? S.sy : S.sz)[b] = gate_slot_first[gi];
+                    mark[i] = 1;
+                    took = true;
+                }
+                drop(mark);
+            }
+            if (!took) break;
+            steps.push_back(S);
+        }
+        F.step_end = int(steps.size());
+        // the phase's CNOTs: images of the local basis bits under their product
+        for (int b = 0; b < 16; ++b) F.cimg[b] = b < m ? (1 << b) : 0;
+        {
+            std::vector<char> mark(rem.size(), 0);
+            uint64_t blocked = 0;
+            for (size_t i = 0; i < rem.size(); ++i) {
+                const tcng_gate& g = gates[rem[i]];
+                const uint64_t qm = gate_qmask(g);
+                if (g.kind == K_CNOT && !(qm & blocked)) {
+                    const int lc = qubit_to_local[g.q0], lt = qubit_to_local[g.q1];
+                    for (int b = 0; b < m; ++b)
+                        if ((F.cimg[b] >> lc) & 1) F.cimg[b] ^= 1 << lt;
+                    F.has_map = 1;
+                    mark[i] = 1;
+                    ++cnots;
+                } else {
+                    blocked |= qm;
+                }
+            }
+            drop(mark);
+        }
+        if (F.step_end == F.step_begin && !F.has_map) return "internal: rotation rounds made no progress";
+        // register bits: the phase's qubits, then the highest unused local bits
+        uint32_t used = 0;
+        for (size_t b = 0; b < R.size(); ++b) {
+            F.R[b] = qubit_to_local[R[b]];
+            used |= 1u << F.R[b];
+        }
+        for (int b = int(R.size()), l = m - 1; b < QREG; ++b) {
+            while ((used >> l) & 1) --l;
+            F.R[b] = l;
+            used |= 1u << l;
+        }
+        phases.push_back(F);
+    }
+    qp.phase_end = int(phases.size());
+    size_t rots = 0;
+    for (size_t k = first_step; k < steps.size(); ++k)
+        for (int b = 0; b < QREG; ++b) rots += (steps[k].ry[b] >= 0) + (steps[k].rz[b] >= 0);
+    if (rots + cnots != sel.size()) return "internal: rotation rounds lost a gate";
+    return "";
+}
+
 }  // namespace
 
 std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_params, const TileConfig& cfg,
@@ -164,6 +263,9 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
 
     std::vector<int> rem(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
+    out.rounds = m >= QREG + 6;   // a wave's 64 lanes hold thread bits
+    for (const tcng_gate& g : gates)
+        if (g.kind != K_RY && g.kind != K_RZ && g.kind != K_CNOT) out.rounds = false;
 
     // per-gate slot assignment (global, in reverse-sweep order is not needed:
     // slots are contiguous per pass, assigned as passes are formed)
@@ -235,6 +337,12 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
         if (!why.empty()) return why;
         why = plan_phases(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, R, out.rphases, out.rops);
         if (!why.empty()) return why;
+        if (out.rounds) {
+            QPass Q{};
+            why = plan_rounds(gates, sel, qubit_to_local, m, gate_slot_first, out.qphases, out.qsteps, Q);
+            if (!why.empty()) return why;
+            out.qpasses.push_back(Q);
+        }
         out.passes.push_back(P);
         out.rpasses.push_back(R);
     }

@@ -28,6 +28,12 @@ struct CircuitPlan {
     std::vector<int32_t> slot_ptr, slot_idx;
     // U2 gates: gate index -> first of its 32 cotangent slots (-1 otherwise)
     std::vector<int32_t> gate_slot;
+    // rotation rounds of the same passes (empty unless every gate is RY, RZ or
+    // CNOT and the tile holds at least the register bits)
+    bool rounds = false;
+    std::vector<QPass> qpasses;
+    std::vector<QPhase> qphases;
+    std::vector<QStep> qsteps;
 };
 
 // Fused passes: the same tiles as the tiled plan, phases of FUSED_K bits that

@@ -1,0 +1,108 @@
+"""Rotation rounds: the complex64 tiled passes of circuits made of RY, RZ and
+CNOT (fixed rounds of rotations on 5 register bits, each phase's CNOTs a
+permutation of the tile's local index), through the C ABI, against the CPU
+oracle.
+
+Bars as in test_gpu_parity: |dE| <= 1e-5 S and |d grad|_inf <= 1e-4 S with
+S = sum |c_k|; amplitudes within 8 * (gate applications) * 2^-24 of the
+state's largest amplitude (tests/bars.py).  Angles are uniform on [0, 2 pi),
+so about half of the rotations have cos(theta / 2) < 0 and take the negated
+form (-R(a - pi)).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.bars import assert_amps
+
+pytestmark = pytest.mark.gpu
+
+TOL_E, TOL_G = 1e-5, 1e-4
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2602_14167_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.lib()
+    return pkg
+
+
+def ry_rz_cnot_circuit(n, n_gates, rng, low_bias=False):
+    """Random RY / RZ / CNOT circuit: each gate's kind and qubits drawn at random
+    (CNOT control and target distinct, in either order)."""
+    g, npar = [], 0
+    for _ in range(n_gates):
+        k = rng.integers(3)
+        hi = 4 if (low_bias and rng.random() < 0.4) else n
+        if k == 2:
+            a, b = rng.choice(n if hi == n else max(hi, 2), size=2, replace=False)
+            g.append(W.gate(W.CNOT, int(a), int(b)))
+        else:
+            q = int(rng.integers(hi))
+            g.append(W.gate(W.RY if k == 0 else W.RZ, q, p0=npar))
+            npar += 1
+    return W.as_gate_array(g), npar
+
+
+def check(P, oracle_mod, n, gates, n_params, codes, coeffs, pb, init, tiling=None, label=""):
+    circ = P.Circuit(n, gates, n_params)
+    if tiling:
+        circ.configure(torch.complex64, *tiling)
+    assert circ.rounds() > 0, "the circuit should run as rotation rounds"
+    H = P.PauliSum(n, codes, coeffs)
+    B = pb.shape[0]
+    psi = torch.as_tensor(np.tile(init, (B, 1))).to(device="cuda", dtype=torch.complex64)
+    psi0 = psi.clone()
+    p = torch.as_tensor(pb).to(device="cuda", dtype=torch.float32)
+    E, g = P.expect_grad(circ, p, H, psi=psi, mode="tiled")[:2]
+    E, g = E.cpu().numpy(), g.cpu().numpy()
+    S = float(np.abs(coeffs).sum())
+    worst_e = worst_g = 0.0
+    for b in range(B):
+        ref = oracle_mod.expect_grad(n, gates, W.round_params(pb[b], "c64"), codes, coeffs, None, init=init)
+        worst_e = max(worst_e, abs(E[b] - ref["E"]) / S)
+        worst_g = max(worst_g, float(np.max(np.abs(g[b] - ref["grad"]))) / S)
+    print(f"rounds {label} n={n} gates={len(gates)} phases={circ.rounds()}: |dE|/S={worst_e:.2e} |dg|/S={worst_g:.2e}",
+          flush=True)
+    assert worst_e <= TOL_E and worst_g <= TOL_G, (worst_e, worst_g)
+    # the reverse sweep un-computes the states back to the input
+    assert_amps(psi.cpu().numpy(), psi0.cpu().numpy(), "c64", 8 * len(gates), f"rounds recomputed psi0 {label}")
+    # forward only: the final state
+    st = torch.empty((1, 2 ** n), dtype=torch.complex64, device="cuda")
+    st.copy_(torch.as_tensor(np.ascontiguousarray(init[None, :])))
+    P.run_circuit(circ, p[:1].contiguous(), st, mode="tiled")
+    ref = oracle_mod.expect_grad(n, gates, W.round_params(pb[0], "c64"), codes, coeffs, None, init=init,
+                                 want_state=True)
+    assert_amps(st.cpu().numpy()[0], ref["state"], "c64", len(gates), f"rounds final state {label}")
+
+
+def test_rounds_taken_only_where_they_apply(P):
+    w = W.cfg2(n=16, layers=3)
+    c = P.Circuit(16, w["gates"], w["n_params"])
+    assert c.rounds() > 0 and c.rounds(torch.complex128) == 0
+    r = np.random.default_rng(1)
+    gates, params, mats = W.random_circuit(14, 40, r)   # every kind: not rotation rounds
+    assert P.Circuit(14, gates, len(params), mats).rounds() == 0
+    assert P.Circuit(10, w["gates"][:0], 0).rounds() == 0   # below 11 qubits: no 64-lane thread part
+
+
+@pytest.mark.parametrize("n,layers,tiling", [(11, 2, None), (13, 4, None), (16, 3, None), (16, 3, (12, 5, 5)),
+                                             (18, 4, (13, 5, 4)), (20, 2, None)])
+def test_rounds_hea(P, oracle_mod, n, layers, tiling):
+    w = W.cfg2(n=n, layers=layers)
+    r = np.random.default_rng(100 + n)
+    pb = np.stack([w["params"], r.uniform(0, 2 * np.pi, w["n_params"])])
+    init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
+    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, tiling, f"hea L={layers}")
+
+
+@pytest.mark.parametrize("n,n_gates,seed", [(11, 60, 1), (12, 120, 2), (13, 150, 3), (14, 150, 4), (16, 200, 5)])
+def test_rounds_random_ry_rz_cnot(P, oracle_mod, n, n_gates, seed):
+    r = np.random.default_rng(seed)
+    gates, npar = ry_rz_cnot_circuit(n, n_gates, r, low_bias=(seed % 2 == 0))
+    codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=4)
+    pb = r.uniform(0, 2 * np.pi, (2, npar))
+    init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
+    check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, None, f"random seed={seed}")
