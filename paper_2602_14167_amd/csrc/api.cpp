@@ -128,9 +128,12 @@ struct DevCircuitPlan {
     Pass* rpasses = nullptr;
     Phase* rphases = nullptr;
     Op* rops = nullptr;
-    QPass* qpasses = nullptr;     // rotation rounds (host.rounds)
+    QPass* qpasses = nullptr;     // rotation rounds (host.rounds), forward and reverse
     QPhase* qphases = nullptr;
     QStep* qsteps = nullptr;
+    QPass* qrpasses = nullptr;
+    QPhase* qrphases = nullptr;
+    QStep* qrsteps = nullptr;
     SlotTables slots;
 };
 
@@ -178,6 +181,9 @@ void free_plan(DevCircuitPlan& P) {
     (void)hipFree(P.qpasses);
     (void)hipFree(P.qphases);
     (void)hipFree(P.qsteps);
+    (void)hipFree(P.qrpasses);
+    (void)hipFree(P.qrphases);
+    (void)hipFree(P.qrsteps);
     (void)hipFree(P.slots.ptr);
     (void)hipFree(P.slots.idx);
     (void)hipFree(P.slots.gate_slot);
@@ -248,7 +254,10 @@ tcng_status make_plan(tcng_circuit* c, int dt, const TileConfig& cfg) {
         upload(P.host.rphases, &P.rphases) != hipSuccess || upload(P.host.rops, &P.rops) != hipSuccess ||
         (P.host.rounds && (upload(P.host.qpasses, &P.qpasses) != hipSuccess ||
                            upload(P.host.qphases, &P.qphases) != hipSuccess ||
-                           upload(P.host.qsteps, &P.qsteps) != hipSuccess))) {
+                           upload(P.host.qsteps, &P.qsteps) != hipSuccess ||
+                           upload(P.host.qrpasses, &P.qrpasses) != hipSuccess ||
+                           upload(P.host.qrphases, &P.qrphases) != hipSuccess ||
+                           upload(P.host.qrsteps, &P.qrsteps) != hipSuccess))) {
         free_plan(P);
         return fail(TCNG_E_ALLOC, "device allocation failed");
     }
@@ -387,8 +396,13 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
         L.osum_bytes = size_t(batch) * F.n_blocks * 512 * sub * sizeof(double);
         L.part_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1)) * sizeof(double);
     } else if (c) {
-        if (tiled)
+        if (tiled) {
             L.opm_bytes = size_t(batch) * c->gates.size() * 16 * (dtype == TCNG_C64 ? 8 : 16);
+            // rotation rounds: their coefficient blocks follow the members' matrix tables
+            const CircuitPlan& H = c->tiled[dtype].host;
+            if (dtype == TCNG_C64 && H.rounds)
+                L.opm_bytes += size_t(batch) * rounds_coef_bytes(int(H.qsteps.size() + H.qrsteps.size()));
+        }
         L.total_slots = tiled ? c->tiled[dtype].host.total_slots : c->plain.total;
         L.rev_wgs = tiled ? rev_wgs_tiled(n, c->tiled[dtype].host.cfg.m_max, batch) : rev_wgs_plain(n, batch);
         L.part_bytes = size_t(batch) * size_t(std::max(L.total_slots, 1)) * size_t(L.rev_wgs) * sizeof(double);
@@ -426,6 +440,11 @@ WsLayout grad_layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int 
     return L;
 }
 
+// byte offset of the rotation rounds' coefficient blocks inside the op table
+size_t rounds_coef_offset(const tcng_circuit* c, int64_t batch) {
+    return size_t(batch) * c->gates.size() * 16 * sizeof(cx<float>);
+}
+
 // op matrix entries for the tiled passes (once per evaluation)
 template <typename R>
 tcng_status build_ops(const tcng_circuit* c, const void* params, int64_t batch, int dt, void* opm, hipStream_t st) {
@@ -433,6 +452,10 @@ tcng_status build_ops(const tcng_circuit* c, const void* params, int64_t batch, 
     DevPlan dp{P.passes, P.phases, P.ops};
     PROF_TRY(F_FINISH, launch_build_ops<R>(dp, int(P.host.ops.size()), params, c->n_params, c->cm[dt], batch, opm, st));
     // (the forward plan lists every gate exactly once: the table is indexed by gate)
+    if (dt == TCNG_C64 && P.host.rounds)
+        PROF_TRY(F_FINISH, launch_rounds_coef(P.qsteps, int(P.host.qsteps.size()), P.qrsteps,
+                                              int(P.host.qrsteps.size()), opm, int(c->gates.size()), batch,
+                                              static_cast<char*>(opm) + rounds_coef_offset(c, batch), st));
     return TCNG_OK;
 }
 
@@ -453,6 +476,12 @@ Job make_job(const tcng_circuit* c, const tcng_pauli_sum* h, const tcng_state* s
             J.qpasses = P.qpasses;
             J.qphases = P.qphases;
             J.qsteps = P.qsteps;
+            J.qrpasses = P.qrpasses;
+            J.qrphases = P.qrphases;
+            J.qrsteps = P.qrsteps;
+            J.qcoef = opm ? static_cast<const char*>(opm) + rounds_coef_offset(c, s->batch) : nullptr;
+            J.qsteps_fwd = int32_t(P.host.qsteps.size());
+            J.qsteps_all = int32_t(P.host.qsteps.size() + P.host.qrsteps.size());
         }
         J.n_passes = int32_t(P.host.passes.size());
         J.n_gates = int32_t(c->gates.size());
@@ -504,8 +533,11 @@ tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_st
             const int m = P.host.passes[p].m;
             const JobList jl{nullptr, nullptr, 0, int32_t(p)};
             const int64_t blocks = J.tiles * J.batch;
-            if (J.qpasses)
-                PROF_TRY(F_FWD_TILE, launch_rounds_fwd(jl, J, blocks, 1 << (m - QREG), st));
+            if (J.qpasses && J.qcoef) {
+                // a few tiles per workgroup, so each fetch overlaps a tile's phases
+                const int wgs = int(std::min<int64_t>(J.tiles, std::max<int64_t>(1, 2048 / J.batch)));
+                PROF_TRY(F_FWD_TILE, launch_rounds_fwd(jl, J, rb, wgs, int64_t(wgs) * J.batch, 1 << (m - rb), st));
+            }
             else if (rb == RB)
                 PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
             else
@@ -569,8 +601,8 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
             const int m = P.host.rpasses[np - 1 - k].m;
             const JobList jl{nullptr, nullptr, 0, int32_t(k)};
             const int64_t blocks = int64_t(J.wgs) * J.batch;
-            if (J.qpasses)
-                PROF_TRY(F_REV_TILE, launch_rounds_rev(jl, J, blocks, 1 << (m - QREG), st));
+            if (J.qrpasses && J.qcoef)
+                PROF_TRY(F_REV_TILE, launch_rounds_rev(jl, J, rb, blocks, 1 << (m - rb), st));
             else if (rb == RB)
                 PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
             else

@@ -567,11 +567,14 @@ k_tile_fwd(const JobList jl, const Job single) {
     if (active) tile_store<R, RB>(lds, psi, base, pi, t, nt, flip);
 }
 
-// accumulate a thread's gradient partial into the wave's slot (float64)
+// accumulate a thread's gradient partial into the wave's slot (float64).  The
+// slot is the wave's own, so the add is an LDS atomic without return: the wave
+// does not wait for a read of the slot, and the adds of one wave still land in
+// program order (the sum's order does not depend on scheduling).
 template <typename R>
 __device__ __forceinline__ void red_add(double* red, int idx, R v, int lane) {
     const double s = wave_sum(double(v));
-    if (lane == 0) red[idx] += s;
+    if (lane == 0) (void)__hip_atomic_fetch_add(red + idx, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,32 +706,40 @@ k_tile_rev(const JobList jl, const Job single) {
 }
 
 // ---------------------------------------------------------------------------
-// rotation rounds (complex64, 5 register bits; see QPhase)
+// rotation rounds (complex64, QR = 4 or 5 register bits; see QPhase)
 // ---------------------------------------------------------------------------
-// A zero the compiler cannot see through.  XORed into an address it stops the
-// address arithmetic of one use from being shared with (or hoisted to) another:
-// shared, the 32 element addresses of a tile (64-bit global, or LDS) stay live
-// from the load to the store and the reverse sweep needs 370 registers.
-__device__ __forceinline__ uint32_t opaque_zero() {
-    uint32_t z;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-    return z;
+// `pin` passes a value through an empty asm statement: the compiler cannot
+// hoist what is computed from it out of the loop it sits in, nor share it
+// between two uses (shared or hoisted, the LDS and global addresses of a
+// tile's elements stay live across the whole sweep, and the reverse sweep
+// needs 370 registers); it costs no instruction.
+__device__ __forceinline__ uint64_t pin(uint64_t v) {
+    uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    return (uint64_t(hi) << 32) | lo;
+}
+__device__ __forceinline__ uint32_t pin(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
-using QBlk = Regs<float, (1 << QREG)>;
+template <int QR>
+using QBlk = Regs<float, (1 << QR)>;
 
 // a phase's register map: the thread's part of the local index, and the LDS
 // positions of its registers with and without the phase's permutation C
+template <int QR>
 struct QMap {
-    uint32_t tsw, ctsw;          // swz(tpart), swz(C(tpart))
-    uint32_t rsw[QREG], crsw[QREG];   // swz(e_R[i]), swz(C(e_R[i])) (uniform)
+    uint32_t tsw, ctsw;              // swz(tpart), swz(C(tpart))
+    uint32_t rsw[QR], crsw[QR];      // swz(e_R[i]), swz(C(e_R[i])) (uniform)
 };
 
-__device__ __forceinline__ QMap qmap(cptr<QPhase> F, int t, int m) {
-    QMap q;
+template <int QR>
+__device__ __forceinline__ QMap<QR> qmap(cptr<QPhase> F, int t, int m) {
+    QMap<QR> q;
     uint32_t rmask = 0;
 #pragma unroll
-    for (int i = 0; i < QREG; ++i) {
+    for (int i = 0; i < QR; ++i) {
         const int l = F->R[i];
         rmask |= 1u << l;
         q.rsw[i] = swz(1u << l);
@@ -750,161 +761,239 @@ __device__ __forceinline__ QMap qmap(cptr<QPhase> F, int t, int m) {
 }
 
 // LDS position of register j: through C (mapped) or not
-template <bool MAPPED>
-__device__ __forceinline__ uint32_t qaddr(const QMap& q, int j) {
+template <bool MAPPED, int QR>
+__device__ __forceinline__ uint32_t qaddr(const QMap<QR>& q, int j) {
     uint32_t a = MAPPED ? q.ctsw : q.tsw;
 #pragma unroll
-    for (int i = 0; i < QREG; ++i)
+    for (int i = 0; i < QR; ++i)
         if ((j >> i) & 1) a ^= MAPPED ? q.crsw[i] : q.rsw[i];
     return a;
 }
 
 // (each call forms its addresses anew: shared between calls, the compiler
 // keeps them all live in registers across the sweep)
-template <bool MAPPED>
-__device__ __forceinline__ QBlk q_read(const cx<float>* lds, const QMap& q) {
-    const uint32_t z = opaque_zero();
-    QBlk a;
+template <bool MAPPED, int QR>
+__device__ __forceinline__ QBlk<QR> q_read(const cx<float>* lds, QMap<QR> q) {
+    q.tsw = pin(q.tsw);
+    q.ctsw = pin(q.ctsw);
+    QBlk<QR> a;
 #pragma unroll
-    for (int j = 0; j < (1 << QREG); ++j) a.v[j] = lds[qaddr<MAPPED>(q, j) ^ z];
+    for (int j = 0; j < (1 << QR); ++j) a.v[j] = lds[qaddr<MAPPED>(q, j)];
     return a;
 }
-template <bool MAPPED>
-__device__ __forceinline__ void q_write(cx<float>* lds, const QBlk& a, const QMap& q) {
-    const uint32_t z = opaque_zero();
+template <bool MAPPED, int QR>
+__device__ __forceinline__ void q_write(cx<float>* lds, const QBlk<QR>& a, QMap<QR> q) {
+    q.tsw = pin(q.tsw);
+    q.ctsw = pin(q.ctsw);
 #pragma unroll
-    for (int j = 0; j < (1 << QREG); ++j) lds[qaddr<MAPPED>(q, j) ^ z] = a.v[j];
+    for (int j = 0; j < (1 << QR); ++j) lds[qaddr<MAPPED>(q, j)] = a.v[j];
 }
 
-// shear coefficients of gate g (identity for g < 0); INV: the inverse rotation
-template <bool INV>
-__device__ __forceinline__ Lift<float> q_lift(cptr<cx<float>> om, int g, bool& flip) {
-    if (g < 0) return {0.f, 0.f};
-    const cx<float> e = om[size_t(g) * 16 + 4];
-    if (om[size_t(g) * 16 + 5].re < 0.f) flip = !flip;
-    return INV ? Lift<float>{-e.re, -e.im} : Lift<float>{e.re, e.im};
-}
+// Shear coefficients of a step, one block per (member, step) written once per
+// evaluation by k_rounds_coef: [RY t x5, RY s x5, RZ t x5, RZ s x5, sign, 0, 0, 0]
+// (an absent gate: t = s = 0; sign = -1 if an odd number of the step's
+// rotations are taken as -R(a - pi)).  A step reads its block with two scalar
+// loads instead of one round trip per gate.
+constexpr int QCOEF = 24;
 
-// RY on register bits 0..4, then (separately) RZ on 0..4, with the register
-// positions unrolled: no run-time register index, so no copies of the block
-template <bool INV>
-__device__ __forceinline__ QBlk q_ry_round(QBlk a, const int32_t* g, cptr<cx<float>> om, bool& flip) {
-    a = app_ry_lift<float, 32, 0>(a, q_lift<INV>(om, g[0], flip));
-    a = app_ry_lift<float, 32, 1>(a, q_lift<INV>(om, g[1], flip));
-    a = app_ry_lift<float, 32, 2>(a, q_lift<INV>(om, g[2], flip));
-    a = app_ry_lift<float, 32, 3>(a, q_lift<INV>(om, g[3], flip));
-    a = app_ry_lift<float, 32, 4>(a, q_lift<INV>(om, g[4], flip));
+template <bool INV, int QR>
+__device__ __forceinline__ QBlk<QR> q_ry_round(QBlk<QR> a, const float* c) {
+    constexpr int NB = 1 << QR;
+    const float sg = INV ? -1.f : 1.f;
+    a = app_ry_lift<float, NB, 0>(a, Lift<float>{sg * c[0], sg * c[5]});
+    a = app_ry_lift<float, NB, 1>(a, Lift<float>{sg * c[1], sg * c[6]});
+    a = app_ry_lift<float, NB, 2>(a, Lift<float>{sg * c[2], sg * c[7]});
+    a = app_ry_lift<float, NB, 3>(a, Lift<float>{sg * c[3], sg * c[8]});
+    if constexpr (QR > 4) a = app_ry_lift<float, NB, 4>(a, Lift<float>{sg * c[4], sg * c[9]});
     return a;
 }
-template <bool INV>
-__device__ __forceinline__ QBlk q_rz_round(QBlk a, const int32_t* g, cptr<cx<float>> om, bool& flip) {
-    a = app_rz_lift<float, 32, 0>(a, q_lift<INV>(om, g[0], flip));
-    a = app_rz_lift<float, 32, 1>(a, q_lift<INV>(om, g[1], flip));
-    a = app_rz_lift<float, 32, 2>(a, q_lift<INV>(om, g[2], flip));
-    a = app_rz_lift<float, 32, 3>(a, q_lift<INV>(om, g[3], flip));
-    a = app_rz_lift<float, 32, 4>(a, q_lift<INV>(om, g[4], flip));
+template <bool INV, int QR>
+__device__ __forceinline__ QBlk<QR> q_rz_round(QBlk<QR> a, const float* c) {
+    constexpr int NB = 1 << QR;
+    const float sg = INV ? -1.f : 1.f;
+    a = app_rz_lift<float, NB, 0>(a, Lift<float>{sg * c[10], sg * c[15]});
+    a = app_rz_lift<float, NB, 1>(a, Lift<float>{sg * c[11], sg * c[16]});
+    a = app_rz_lift<float, NB, 2>(a, Lift<float>{sg * c[12], sg * c[17]});
+    a = app_rz_lift<float, NB, 3>(a, Lift<float>{sg * c[13], sg * c[18]});
+    if constexpr (QR > 4) a = app_rz_lift<float, NB, 4>(a, Lift<float>{sg * c[14], sg * c[19]});
     return a;
 }
 
-// tile_load / tile_store of the rotation rounds (complex64, 32 amplitudes per
+struct QCoef {
+    float c[QCOEF];
+};
+
+// tile_load / tile_store of the rotation rounds (complex64, 2^QR amplitudes per
 // thread): element it of thread t is local index (it * nt + t) * 2 (+1)
-__device__ __forceinline__ void q_tile_load(cx<float>* lds, gptr<const cx<float>> psi, uint64_t base,
-                                            const PassInfo& pi, int t, int nt) {
-    const uint32_t zo = opaque_zero();
-    const uint64_t off_t = loc2glob(uint32_t(t * 2) ^ zo, pi.lo, pi.m, pi.lq);
-    cx<float> v[32];
+// Tile addressing of the rotation rounds.  Element it of thread t is local
+// index it * 2 nt + 2 t (+1): the bits of it are the top QR - 1 local bits, so
+// its global offset is a compile-time sum of their images hb[k] (per pass,
+// uniform), and the thread's part off_t is computed once (and pinned per use).
+
+template <int QR>
+struct QTileAddr {
+    uint64_t hb[QR - 1];   // global offsets of the element-index bits (uniform)
+    uint64_t off_t;        // the thread's part
+    uint32_t lsw_t;        // swz(2 t)
+    uint32_t lhb[QR - 1];  // swz of the element-index bits (uniform)
+};
+
+template <int QR>
+__device__ __forceinline__ QTileAddr<QR> q_tile_addr(const PassInfo& pi, int t, int nt) {
+    QTileAddr<QR> A;
+    const int b0 = pi.m - (QR - 1);   // first local bit of the element index (2 nt = 2^b0)
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const uint64_t g = base + loc2glob(uint32_t(it * nt * 2) ^ zo, pi.lo, pi.m, pi.lq) + off_t;
-        V16<float>::load(psi + g, &v[it * 2]);
+    for (int k = 0; k < QR - 1; ++k) {
+        int q = b0 + k;
+#pragma unroll
+        for (int i = 0; i < MAX_TILE_BITS; ++i)
+            if (i == b0 + k) q = pi.lq[i];
+        A.hb[k] = uint64_t(1) << q;
+        A.lhb[k] = swz(1u << (b0 + k));
     }
+    A.off_t = loc2glob(uint32_t(t * 2), pi.lo, pi.m, pi.lq);
+    A.lsw_t = swz(uint32_t(t * 2));
+    (void)nt;
+    return A;
+}
+
+// (it is a constant once the loops over elements are unrolled: the selects fold)
+template <int QR>
+__device__ __forceinline__ uint64_t q_goff(const QTileAddr<QR>& A, int it) {
+    uint64_t g = 0;
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const uint32_t e = uint32_t((it * nt + t) * 2) ^ zo;
-        lds[swz(e)] = v[it * 2];
-        lds[swz(e + 1)] = v[it * 2 + 1];
+    for (int k = 0; k < QR - 1; ++k)
+        if ((it >> k) & 1) g += A.hb[k];
+    return g;
+}
+template <int QR>
+__device__ __forceinline__ uint32_t q_loff(const QTileAddr<QR>& A, int it) {
+    uint32_t a = 0;
+#pragma unroll
+    for (int k = 0; k < QR - 1; ++k)
+        if ((it >> k) & 1) a ^= A.lhb[k];
+    return a;
+}
+
+// HBM -> registers (the loads stay in flight until the registers are used)
+// and registers -> LDS, separately, so that a tile can be fetched while
+// another one is processed
+template <int QR>
+struct QTileRegs {
+    cx<float> v[1 << QR];
+};
+
+template <int QR>
+__device__ __forceinline__ QTileRegs<QR> q_tile_fetch(gptr<const cx<float>> psi, uint64_t base,
+                                                      const QTileAddr<QR>& A) {
+    const gptr<const cx<float>> p = psi + pin(A.off_t);
+    QTileRegs<QR> r;
+#pragma unroll
+    for (int it = 0; it < (1 << QR) / 2; ++it) V16<float>::load(p + (base + q_goff<QR>(A, it)), &r.v[it * 2]);
+    return r;
+}
+
+template <int QR>
+__device__ __forceinline__ void q_tile_put(cx<float>* lds, const QTileRegs<QR>& r, const QTileAddr<QR>& A) {
+    const uint32_t lt = pin(A.lsw_t);
+#pragma unroll
+    for (int it = 0; it < (1 << QR) / 2; ++it) {
+        const uint32_t e = lt ^ q_loff<QR>(A, it);
+        lds[e] = r.v[it * 2];
+        lds[e ^ swz(1u)] = r.v[it * 2 + 1];
     }
 }
 
+template <int QR>
 __device__ __forceinline__ void q_tile_store(const cx<float>* lds, gptr<cx<float>> psi, uint64_t base,
-                                             const PassInfo& pi, int t, int nt, bool flip) {
-    const uint32_t zo = opaque_zero();
-    const uint64_t off_t = loc2glob(uint32_t(t * 2) ^ zo, pi.lo, pi.m, pi.lq);
+                                             const QTileAddr<QR>& A, bool flip) {
+    const gptr<cx<float>> p = psi + pin(A.off_t);
+    const uint32_t lt = pin(A.lsw_t);
     const float sg = flip ? -1.f : 1.f;
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-        const uint32_t e = uint32_t((it * nt + t) * 2) ^ zo;
-        cx<float> v[2] = {lds[swz(e)], lds[swz(e + 1)]};
+    for (int it = 0; it < (1 << QR) / 2; ++it) {
+        const uint32_t e = lt ^ q_loff<QR>(A, it);
+        cx<float> v[2] = {lds[e], lds[e ^ swz(1u)]};
         if (flip) {
             v[0] = {sg * v[0].re, sg * v[0].im};
             v[1] = {sg * v[1].re, sg * v[1].im};
         }
-        const uint64_t g = base + loc2glob(uint32_t(it * nt * 2) ^ zo, pi.lo, pi.m, pi.lq) + off_t;
-        V16<float>::store(psi + g, v);
+        V16<float>::store(p + (base + q_goff<QR>(A, it)), v);
     }
 }
 
-// a round's five derivative partials into their slots (absent gates have none)
-__device__ __forceinline__ void q_red5(double* red, const int32_t* slot, int nwaves, int wave, int lane, float g0,
-                                       float g1, float g2, float g3, float g4) {
-    if (slot[0] >= 0) red_add(red, slot[0] * nwaves + wave, g0, lane);
-    if (slot[1] >= 0) red_add(red, slot[1] * nwaves + wave, g1, lane);
-    if (slot[2] >= 0) red_add(red, slot[2] * nwaves + wave, g2, lane);
-    if (slot[3] >= 0) red_add(red, slot[3] * nwaves + wave, g3, lane);
-    if (slot[4] >= 0) red_add(red, slot[4] * nwaves + wave, g4, lane);
+// a round's derivative partials into their slots (absent gates have none)
+template <int QR>
+__device__ __forceinline__ void q_red(double* red, const int32_t* slot, int nwaves, int wave, int lane,
+                                      const float* g) {
+#pragma unroll
+    for (int i = 0; i < QR; ++i)
+        if (slot[i] >= 0) red_add(red, slot[i] * nwaves + wave, g[i], lane);
 }
 
-__global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_fwd(const JobList jl, const Job single) {
+// forward: `wgs` workgroups per member loop over the tiles; the next tile's
+// loads are in flight while the current tile's phases run
+template <int QR>
+__global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl, const Job single, int wgs) {
     __shared__ cx<float> lds[Tile<float>::ELEMS];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     cptr<Pass> P = as_const(J.passes) + jl.step;
     const PassInfo pi = read_pass(P);
     const QPass Q = as_const(J.qpasses)[jl.step];
-    // the launch has exactly 2^(m - QREG) threads: every wave is active
-    const int nt = 1 << (pi.m - QREG);
+    // the launch has exactly 2^(m - QR) threads: every wave is active
+    const int nt = 1 << (pi.m - QR);
     const int t = threadIdx.x;
-    const int64_t b = local / J.tiles;
-    const uint64_t tile = uint64_t(local - b * J.tiles);
+    const int64_t b = local / wgs;
+    const int wg = int(local - b * wgs);
     gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
-    cptr<cx<float>> om = as_const(static_cast<const cx<float>*>(J.opm)) + size_t(b) * J.n_gates * 16;
     cptr<QPhase> phases = as_const(J.qphases);
-    cptr<QStep> steps = as_const(J.qsteps);
-    const uint64_t base = tile_base(tile, pi.tmask, J.n);
+    cptr<QCoef> coef = as_const(reinterpret_cast<const QCoef*>(J.qcoef)) + size_t(b) * J.qsteps_all;
 
-    q_tile_load(lds, psi, base, pi, t, nt);
-    __syncthreads();
-    bool flip = false;
-    for (int f = Q.phase_begin; f < Q.phase_end; ++f) {
-        cptr<QPhase> F = phases + f;
-        const QMap q = qmap(F, t, pi.m);
-        QBlk a = q_read<false>(lds, q);
-        const int s_end = F->step_end;
-        for (int s = F->step_begin; s < s_end; ++s) {
-            const QStep S = steps[s];
-            a = q_ry_round<false>(a, S.ry, om, flip);
-            a = q_rz_round<false>(a, S.rz, om, flip);
-        }
-        __syncthreads();   // the write permutes positions: every read first
-        q_write<true>(lds, a, q);
+    const QTileAddr<QR> A = q_tile_addr<QR>(pi, t, nt);
+    QTileRegs<QR> nx;
+    if (wg < J.tiles) nx = q_tile_fetch<QR>(psi, tile_base(uint64_t(wg), pi.tmask, J.n), A);
+    for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
+        const uint64_t base = tile_base(uint64_t(tile), pi.tmask, J.n);
+        __syncthreads();   // the previous tile's stores have read the LDS
+        q_tile_put<QR>(lds, nx, A);
+        if (tile + wgs < J.tiles) nx = q_tile_fetch<QR>(psi, tile_base(uint64_t(tile + wgs), pi.tmask, J.n), A);
         __syncthreads();
+        bool flip = false;
+        for (int f = Q.phase_begin; f < Q.phase_end; ++f) {
+            cptr<QPhase> F = phases + f;
+            const QMap<QR> q = qmap<QR>(F, t, pi.m);
+            QBlk<QR> a = q_read<false>(lds, q);
+            const int s_end = F->step_end;
+            for (int s = F->step_begin; s < s_end; ++s) {
+                const QCoef C = coef[s];
+                a = q_ry_round<false, QR>(a, C.c);
+                a = q_rz_round<false, QR>(a, C.c);
+                flip = flip != (C.c[20] < 0.f);
+            }
+            __syncthreads();   // the write permutes positions: every read first
+            q_write<true>(lds, a, q);
+            __syncthreads();
+        }
+        q_tile_store<QR>(lds, psi, base, A, flip);
     }
-    q_tile_store(lds, psi, base, pi, t, nt, flip);
 }
 
 // reverse: phases and steps backwards; each phase reads through C, un-applies
 // its rounds (derivatives first: every rotation of a round at the round's
 // end point, where all of them commute) and writes without C
-__global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_rev(const JobList jl, const Job single) {
+template <int QR>
+__global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl, const Job single) {
+    constexpr int NB = 1 << QR;
     __shared__ cx<float> lds[Tile<float>::ELEMS];
-    __shared__ double red[RED_SLOTS * ((1 << (13 - QREG)) / 64)];
+    __shared__ double red[RED_SLOTS * ((1 << (13 - QR)) / 64)];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     const int pidx = J.n_passes - 1 - jl.step;
     cptr<Pass> P = as_const(J.passes) + pidx;
     const PassInfo pi = read_pass(P);
-    const QPass Q = as_const(J.qpasses)[pidx];
-    const int nt = 1 << (pi.m - QREG);   // the launch's thread count: every wave is active
+    const QPass Q = as_const(J.qrpasses)[pidx];
+    const int nt = 1 << (pi.m - QR);   // the launch's thread count: every wave is active
     const int nwaves = nt >> 6;
     const int t = threadIdx.x;
     const int wave = uniform(t >> 6), lane = t & 63;
@@ -913,54 +1002,65 @@ __global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_rev(const JobList j
     const int wg = int(local - b * wgs);
     gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
     gptr<cx<float>> lam = as_global(static_cast<cx<float>*>(J.costate)) + b * J.stride;
-    cptr<cx<float>> om = as_const(static_cast<const cx<float>*>(J.opm)) + size_t(b) * J.n_gates * 16;
-    cptr<QPhase> phases = as_const(J.qphases);
-    cptr<QStep> steps = as_const(J.qsteps);
+    cptr<QPhase> phases = as_const(J.qrphases);
+    cptr<QStep> steps = as_const(J.qrsteps);
+    cptr<QCoef> coef = as_const(reinterpret_cast<const QCoef*>(J.qcoef)) + size_t(b) * J.qsteps_all + J.qsteps_fwd;
     const int nslots = P->n_slots;
 
     for (int i = t; i < nslots * nwaves; i += blockDim.x) red[i] = 0.0;
     // (the first __syncthreads below orders these writes before any accumulation)
+    const QTileAddr<QR> A = q_tile_addr<QR>(pi, t, nt);
 
     for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), pi.tmask, J.n);
         int f = Q.phase_end - 1;
-        QMap q = qmap(phases + f, t, pi.m);
-        QBlk ps, la;
-        bool flip = false, flip_l = false;   // equal: psi and lambda see the same rotations
-        __syncthreads();
-        q_tile_load(lds, psi, base, pi, t, nt);
-        __syncthreads();
-        ps = q_read<true>(lds, q);
-        __syncthreads();
-        q_tile_load(lds, lam, base, pi, t, nt);
-        __syncthreads();
-        la = q_read<true>(lds, q);
+        QMap<QR> q = qmap<QR>(phases + f, t, pi.m);
+        QBlk<QR> ps, la;
+        bool flip = false;   // psi and lambda see the same rotations: one sign for both
+        {
+            // both states' loads in flight together
+            const QTileRegs<QR> vp = q_tile_fetch<QR>(psi, base, A);
+            const QTileRegs<QR> vl = q_tile_fetch<QR>(lam, base, A);
+            __syncthreads();
+            q_tile_put<QR>(lds, vp, A);
+            __syncthreads();
+            ps = q_read<true>(lds, q);
+            __syncthreads();
+            q_tile_put<QR>(lds, vl, A);
+            __syncthreads();
+            la = q_read<true>(lds, q);
+        }
         for (;;) {
-            {
-                cptr<QPhase> F = phases + f;
-                const int s_begin = F->step_begin;
-                for (int s = F->step_end - 1; s >= s_begin; --s) {
-                    const QStep S = steps[s];
-                    // the round's derivatives first (five sums), then the un-apply,
-                    // then their reductions (which leave the blocks alone)
-                    const float gz0 = grad_rz<float, 32, 0>(la, ps), gz1 = grad_rz<float, 32, 1>(la, ps),
-                                gz2 = grad_rz<float, 32, 2>(la, ps), gz3 = grad_rz<float, 32, 3>(la, ps),
-                                gz4 = grad_rz<float, 32, 4>(la, ps);
-                    ps = q_rz_round<true>(ps, S.rz, om, flip);
-                    la = q_rz_round<true>(la, S.rz, om, flip_l);
-                    q_red5(red, S.sz, nwaves, wave, lane, gz0, gz1, gz2, gz3, gz4);
-                    const float gy0 = grad_rot1<float, 32, 0>(K_RY, la, ps), gy1 = grad_rot1<float, 32, 1>(K_RY, la, ps),
-                                gy2 = grad_rot1<float, 32, 2>(K_RY, la, ps), gy3 = grad_rot1<float, 32, 3>(K_RY, la, ps),
-                                gy4 = grad_rot1<float, 32, 4>(K_RY, la, ps);
-                    ps = q_ry_round<true>(ps, S.ry, om, flip);
-                    la = q_ry_round<true>(la, S.ry, om, flip_l);
-                    q_red5(red, S.sy, nwaves, wave, lane, gy0, gy1, gy2, gy3, gy4);
-                }
+            cptr<QPhase> F = phases + f;
+            const int s_begin = F->step_begin;
+            for (int s = F->step_end - 1; s >= s_begin; --s) {
+                const QStep S = steps[s];
+                const QCoef C = coef[s];
+                // the round's derivatives first, then the un-apply, then their
+                // reductions (which leave the blocks alone)
+                float gz[QR], gy[QR];
+                gz[0] = grad_rz<float, NB, 0>(la, ps);
+                gz[1] = grad_rz<float, NB, 1>(la, ps);
+                gz[2] = grad_rz<float, NB, 2>(la, ps);
+                gz[3] = grad_rz<float, NB, 3>(la, ps);
+                if constexpr (QR > 4) gz[QR - 1] = grad_rz<float, NB, (QR > 4 ? 4 : 0)>(la, ps);
+                ps = q_rz_round<true, QR>(ps, C.c);
+                la = q_rz_round<true, QR>(la, C.c);
+                q_red<QR>(red, S.sz, nwaves, wave, lane, gz);
+                gy[0] = grad_rot1<float, NB, 0>(K_RY, la, ps);
+                gy[1] = grad_rot1<float, NB, 1>(K_RY, la, ps);
+                gy[2] = grad_rot1<float, NB, 2>(K_RY, la, ps);
+                gy[3] = grad_rot1<float, NB, 3>(K_RY, la, ps);
+                if constexpr (QR > 4) gy[QR - 1] = grad_rot1<float, NB, (QR > 4 ? 4 : 0)>(K_RY, la, ps);
+                ps = q_ry_round<true, QR>(ps, C.c);
+                la = q_ry_round<true, QR>(la, C.c);
+                flip = flip != (C.c[20] < 0.f);
+                q_red<QR>(red, S.sy, nwaves, wave, lane, gy);
             }
             if (f == Q.phase_begin) break;
             // hand both blocks to the previous phase: written in plain order,
             // read back through that phase's permutation
-            const QMap qn = qmap(phases + (f - 1), t, pi.m);
+            const QMap<QR> qn = qmap<QR>(phases + (f - 1), t, pi.m);
             __syncthreads();
             q_write<false>(lds, ps, q);
             __syncthreads();
@@ -975,11 +1075,11 @@ __global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_rev(const JobList j
         __syncthreads();
         q_write<false>(lds, ps, q);
         __syncthreads();
-        q_tile_store(lds, psi, base, pi, t, nt, flip);
+        q_tile_store<QR>(lds, psi, base, A, flip);
         __syncthreads();
         q_write<false>(lds, la, q);
         __syncthreads();
-        q_tile_store(lds, lam, base, pi, t, nt, flip_l);
+        q_tile_store<QR>(lds, lam, base, A, flip);
     }
     __syncthreads();
     double* part = J.part + size_t(b) * J.total_slots * wgs;
@@ -988,6 +1088,33 @@ __global__ void __launch_bounds__(1 << (13 - QREG)) k_rounds_rev(const JobList j
         for (int w = 0; w < nwaves; ++w) v += red[s * nwaves + w];
         part[size_t(P->slot_base + s) * wgs + wg] = v;
     }
+}
+
+// the shear-coefficient blocks of every (member, step): forward steps, then
+// reverse steps, from the ops' matrix tables (entries 4 and 5 of RY / RZ)
+__global__ void k_rounds_coef(const QStep* __restrict__ fsteps, int nf, const QStep* __restrict__ rsteps, int nr,
+                              const cx<float>* __restrict__ opm, int n_gates, int64_t batch, QCoef* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int per = nf + nr;
+    if (i >= int64_t(per) * batch) return;
+    const int64_t b = i / per;
+    const int s = int(i - b * per);
+    const QStep S = s < nf ? fsteps[s] : rsteps[s - nf];
+    const cx<float>* om = opm + size_t(b) * n_gates * 16;
+    QCoef C;
+    bool odd = false;
+    for (int k = 0; k < QREG; ++k) {
+        const int gy = S.ry[k], gz = S.rz[k];
+        C.c[k] = gy >= 0 ? om[size_t(gy) * 16 + 4].re : 0.f;
+        C.c[5 + k] = gy >= 0 ? om[size_t(gy) * 16 + 4].im : 0.f;
+        C.c[10 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].re : 0.f;
+        C.c[15 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].im : 0.f;
+        if (gy >= 0 && om[size_t(gy) * 16 + 5].re < 0.f) odd = !odd;
+        if (gz >= 0 && om[size_t(gz) * 16 + 5].re < 0.f) odd = !odd;
+    }
+    C.c[20] = odd ? -1.f : 1.f;
+    C.c[21] = C.c[22] = C.c[23] = 0.f;
+    out[i] = C;
 }
 
 }  // namespace
@@ -1017,18 +1144,35 @@ hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks,
     return hipGetLastError();
 }
 
-// nthreads must be 2^(m - QREG) for the launched pass's m (single jobs only)
-hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
-    if (blocks <= 0) return hipSuccess;
-    if (jl.jobs || nthreads > (1 << (13 - QREG)) || nthreads < 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rounds_fwd, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
+// nthreads must be 2^(m - qr) for the launched pass's m (single jobs only)
+hipError_t launch_rounds_coef(const QStep* fsteps, int nf, const QStep* rsteps, int nr, const void* opm, int n_gates,
+                              int64_t batch, void* out, hipStream_t st) {
+    const int64_t work = int64_t(nf + nr) * batch;
+    if (work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rounds_coef, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, fsteps, nf, rsteps, nr,
+                       static_cast<const cx<float>*>(opm), n_gates, batch, static_cast<QCoef*>(out));
     return hipGetLastError();
 }
 
-hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st) {
+size_t rounds_coef_bytes(int steps) { return size_t(steps) * sizeof(QCoef); }
+
+// forward: wgs workgroups per member (each loops over tiles), blocks = wgs * batch
+hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, int wgs, int64_t blocks, int nthreads,
+                             hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
-    if (jl.jobs || nthreads > (1 << (13 - QREG)) || nthreads < 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rounds_rev, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
+    if (jl.jobs || (qr != 4 && qr != 5) || nthreads > (1 << (13 - qr)) || nthreads < 64 || wgs < 1)
+        return hipErrorInvalidValue;
+    if (qr == 5) hipLaunchKernelGGL(k_rounds_fwd<5>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single, wgs);
+    else hipLaunchKernelGGL(k_rounds_fwd<4>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single, wgs);
+    return hipGetLastError();
+}
+
+hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, int64_t blocks, int nthreads,
+                             hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (jl.jobs || (qr != 4 && qr != 5) || nthreads > (1 << (13 - qr)) || nthreads < 64) return hipErrorInvalidValue;
+    if (qr == 5) hipLaunchKernelGGL(k_rounds_rev<5>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
+    else hipLaunchKernelGGL(k_rounds_rev<4>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
     return hipGetLastError();
 }
 

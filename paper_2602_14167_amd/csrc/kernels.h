@@ -52,9 +52,14 @@ struct Job {
     int64_t src_stride;       // src + b * src_stride (0: one state for every member) instead of its own state
     int64_t init_basis1;      // 0, or 1 + a basis index: the first fused forward pass starts every member
                               // from that basis state (formed in LDS; the state is not read)
-    const QPass* qpasses;     // rotation rounds of the tiled passes (complex64), or null
-    const QPhase* qphases;
+    const QPass* qpasses;     // rotation rounds of the tiled passes (complex64), or null:
+    const QPhase* qphases;    // the forward sweep (rb register bits) ...
     const QStep* qsteps;
+    const QPass* qrpasses;    // ... and the reverse sweep (rb_rev register bits)
+    const QPhase* qrphases;
+    const QStep* qrsteps;
+    const void* qcoef;        // shear coefficients per (member, step): member b at + b * qsteps_all blocks,
+    int32_t qsteps_all, qsteps_fwd;   // forward steps first
 };
 
 // job list of a launch; a single job may be passed by value (jobs == nullptr)
@@ -80,9 +85,16 @@ hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, in
 // nthreads: workgroup size (2^(m - RB) of the largest tile among the jobs)
 template <typename R, int RB>
 hipError_t launch_tile_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
-// rotation rounds (complex64, 5 register bits; the job's qpasses are set)
-hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
-hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
+// rotation rounds (complex64, qr = 4 or 5 register bits; the job's qpasses /
+// qrpasses are set).  launch_rounds_coef fills the coefficient blocks (after
+// launch_build_ops); rounds_coef_bytes: bytes per member for `steps` steps.
+hipError_t launch_rounds_coef(const QStep* fsteps, int nf, const QStep* rsteps, int nr, const void* opm, int n_gates,
+                              int64_t batch, void* out, hipStream_t st);
+size_t rounds_coef_bytes(int steps);
+hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, int wgs, int64_t blocks, int nthreads,
+                             hipStream_t st);
+hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, int64_t blocks, int nthreads,
+                             hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
 template <typename R, int RB>

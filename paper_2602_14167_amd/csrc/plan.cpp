@@ -149,13 +149,13 @@ std::string plan_phases(const std::vector<tcng_gate>& gates, const std::vector<i
     return "";
 }
 
-// Rotation rounds of one pass (see QPhase).  A phase takes up to QREG qubits
+// Rotation rounds of one pass (see QPhase).  A phase takes up to qreg qubits
 // whose first remaining gate is a rotation, then steps: each step applies, per
 // register qubit, its first remaining gate if that is an RY, then its next if
 // that is an RZ.  Then every CNOT whose qubits no earlier remaining gate
 // touches joins the phase's permutation, in circuit order.
 std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<int>& sel, const int* qubit_to_local,
-                        int m, const std::vector<int32_t>& gate_slot_first, std::vector<QPhase>& phases,
+                        int m, int qreg, const std::vector<int32_t>& gate_slot_first, std::vector<QPhase>& phases,
                         std::vector<QStep>& steps, QPass& qp) {
     qp.phase_begin = int(phases.size());
     const size_t first_step = steps.size();
@@ -173,9 +173,9 @@ std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<i
         rem.swap(keep);
     };
     while (!rem.empty()) {
-        // register qubits: the first QREG whose first remaining gate is a rotation
+        // register qubits: the first qreg whose first remaining gate is a rotation
         std::vector<int> R;
-        for (size_t i = 0; i < rem.size() && int(R.size()) < QREG; ++i) {
+        for (size_t i = 0; i < rem.size() && int(R.size()) < qreg; ++i) {
             const tcng_gate& g = gates[rem[i]];
             if (g.kind == K_CNOT) continue;
             if (std::find(R.begin(), R.end(), g.q0) != R.end()) continue;
@@ -233,11 +233,12 @@ std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<i
             F.R[b] = qubit_to_local[R[b]];
             used |= 1u << F.R[b];
         }
-        for (int b = int(R.size()), l = m - 1; b < QREG; ++b) {
+        for (int b = int(R.size()), l = m - 1; b < qreg; ++b) {
             while ((used >> l) & 1) --l;
             F.R[b] = l;
             used |= 1u << l;
         }
+        for (int b = qreg; b < QREG; ++b) F.R[b] = -1;
         phases.push_back(F);
     }
     qp.phase_end = int(phases.size());
@@ -263,7 +264,8 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
 
     std::vector<int> rem(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
-    out.rounds = m >= QREG + 6;   // a wave's 64 lanes hold thread bits
+    // a wave's 64 lanes hold thread bits in both sweeps
+    out.rounds = m >= std::max(cfg.rb, cfg.rb_rev) + 6 && cfg.rb >= 4 && cfg.rb_rev >= 4;
     for (const tcng_gate& g : gates)
         if (g.kind != K_RY && g.kind != K_RZ && g.kind != K_CNOT) out.rounds = false;
 
@@ -338,10 +340,14 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
         why = plan_phases(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, R, out.rphases, out.rops);
         if (!why.empty()) return why;
         if (out.rounds) {
-            QPass Q{};
-            why = plan_rounds(gates, sel, qubit_to_local, m, gate_slot_first, out.qphases, out.qsteps, Q);
+            QPass Q{}, QR{};
+            why = plan_rounds(gates, sel, qubit_to_local, m, cfg.rb, gate_slot_first, out.qphases, out.qsteps, Q);
+            if (!why.empty()) return why;
+            why = plan_rounds(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, out.qrphases, out.qrsteps,
+                              QR);
             if (!why.empty()) return why;
             out.qpasses.push_back(Q);
+            out.qrpasses.push_back(QR);
         }
         out.passes.push_back(P);
         out.rpasses.push_back(R);

@@ -29,11 +29,12 @@ struct CircuitPlan {
     // U2 gates: gate index -> first of its 32 cotangent slots (-1 otherwise)
     std::vector<int32_t> gate_slot;
     // rotation rounds of the same passes (empty unless every gate is RY, RZ or
-    // CNOT and the tile holds at least the register bits)
+    // CNOT and a wave's 64 lanes fit the thread bits): the forward sweep with
+    // cfg.rb register bits, the reverse sweep with cfg.rb_rev
     bool rounds = false;
-    std::vector<QPass> qpasses;
-    std::vector<QPhase> qphases;
-    std::vector<QStep> qsteps;
+    std::vector<QPass> qpasses, qrpasses;
+    std::vector<QPhase> qphases, qrphases;
+    std::vector<QStep> qsteps, qrsteps;
 };
 
 // Fused passes: the same tiles as the tiled plan, phases of FUSED_K bits that

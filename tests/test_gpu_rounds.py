@@ -89,7 +89,8 @@ def test_rounds_taken_only_where_they_apply(P):
 
 
 @pytest.mark.parametrize("n,layers,tiling", [(11, 2, None), (13, 4, None), (16, 3, None), (16, 3, (12, 5, 5)),
-                                             (18, 4, (13, 5, 4)), (20, 2, None)])
+                                             (18, 4, (13, 5, 4)), (18, 3, (13, 4, 4)), (16, 3, (13, 4, 5)),
+                                             (12, 3, (12, 4, 4)), (20, 2, None)])
 def test_rounds_hea(P, oracle_mod, n, layers, tiling):
     w = W.cfg2(n=n, layers=layers)
     r = np.random.default_rng(100 + n)
@@ -98,11 +99,13 @@ def test_rounds_hea(P, oracle_mod, n, layers, tiling):
     check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, tiling, f"hea L={layers}")
 
 
+@pytest.mark.parametrize("tiling", [None, (13, 4, 4)])
 @pytest.mark.parametrize("n,n_gates,seed", [(11, 60, 1), (12, 120, 2), (13, 150, 3), (14, 150, 4), (16, 200, 5)])
-def test_rounds_random_ry_rz_cnot(P, oracle_mod, n, n_gates, seed):
+def test_rounds_random_ry_rz_cnot(P, oracle_mod, n, n_gates, seed, tiling):
+    """Register blocks of 5 (the default tiling) and of 4 bits per thread."""
     r = np.random.default_rng(seed)
     gates, npar = ry_rz_cnot_circuit(n, n_gates, r, low_bias=(seed % 2 == 0))
     codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=4)
     pb = r.uniform(0, 2 * np.pi, (2, npar))
     init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
-    check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, None, f"random seed={seed}")
+    check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, tiling, f"random seed={seed} tiling={tiling}")
