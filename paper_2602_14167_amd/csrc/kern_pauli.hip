@@ -33,6 +33,26 @@ __device__ __forceinline__ uint64_t loc2glob(uint32_t l, int lo, int m, const in
     return g;
 }
 
+// the thread's offset passed through an empty asm statement at each use:
+// otherwise the compiler keeps every element's 64-bit address live across the
+// tile loop (166 registers instead of about 60)
+__device__ __forceinline__ uint64_t pinned(uint64_t v) {
+    uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// global offset of element it's local index bits it * nt (the top RB local
+// bits), from their images: a few selects instead of a loop over every local bit
+template <int RB>
+__device__ __forceinline__ uint64_t elem_off(const uint64_t* hb, int it) {
+    uint64_t g = 0;
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+        if ((it >> k) & 1) g += hb[k];
+    return g;
+}
+
 __device__ __forceinline__ uint64_t tile_base(uint64_t tile, uint64_t tmask, int n) {
     uint64_t base = 0;
     int k = 0;
@@ -102,6 +122,10 @@ k_pauli_tile(const JobList jl, const Job single) {
     // iteration's bits are disjoint, so the global offset and every Z-parity
     // split into a per-thread and a uniform part
     const uint64_t gt = loc2glob(uint32_t(t), lo, m, lq);
+    // images of the element-index bits (local bits m - RB .. m - 1)
+    uint64_t hb[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) hb[k] = loc2glob(1u << (m - RB + k), lo, m, lq);
 
     const bool read_lam = has_lam && accumulate;
     constexpr int CH = (NB < 4) ? NB : 4;
@@ -112,27 +136,28 @@ k_pauli_tile(const JobList jl, const Job single) {
         cx<R> lamn[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i)
-            lamn[i] = (read_lam && active) ? lam[base + gt + loc2glob(uint32_t(i * nt), lo, m, lq)] : cx<R>{R(0), R(0)};
+            lamn[i] = (read_lam && active) ? lam[(base + elem_off<RB>(hb, i)) + pinned(gt)] : cx<R>{R(0), R(0)};
         __syncthreads();
         // psi tile -> LDS; element l = it*nt + t (lane-consecutive, coalesced)
         if (active) {
 #pragma unroll
             for (int it = 0; it < NB; ++it) {
                 const uint32_t l = uint32_t(it * nt + t);
-                lds[l] = psi[base + gt + loc2glob(uint32_t(it * nt), lo, m, lq)];
+                lds[l] = psi[(base + elem_off<RB>(hb, it)) + pinned(gt)];
             }
         }
         __syncthreads();
         if (!active) continue;
         // elements l = it*nt + t, CH at a time; the term loop is outside the
         // element loop so every scalar load of a term serves CH elements
+#pragma unroll 1   // (unrolled, the chunks' double accumulators double the registers)
         for (int c0 = 0; c0 < NB; c0 += CH) {
             cx<R> acc[CH];
 #pragma unroll
             for (int i = 0; i < CH; ++i) acc[i] = lamn[i];
             if (read_lam && c0 + CH < NB) {
 #pragma unroll
-                for (int i = 0; i < CH; ++i) lamn[i] = lam[base + gt + loc2glob(uint32_t((c0 + CH + i) * nt), lo, m, lq)];
+                for (int i = 0; i < CH; ++i) lamn[i] = lam[(base + elem_off<RB>(hb, c0 + CH + i)) + pinned(gt)];
             }
             // this pass's share of (H psi)_l in float64: sum over groups of
             // (cre + i cim) psi_{l ^ x}; E takes Re(conj(psi_l) * share) once per element
@@ -198,7 +223,7 @@ k_pauli_tile(const JobList jl, const Job single) {
             if (has_lam) {
 #pragma unroll
                 for (int i = 0; i < CH; ++i)
-                    lam[base + gt + loc2glob(uint32_t((c0 + i) * nt), lo, m, lq)] = acc[i];
+                    lam[(base + elem_off<RB>(hb, c0 + i)) + pinned(gt)] = acc[i];
             }
         }
     }
