@@ -86,7 +86,6 @@ TileConfig tile_config(int dtype) {
 TileConfig pauli_config(int dtype) {
     return dtype == TCNG_C64 ? TileConfig{12, 4, 4, 4} : TileConfig{12, 4, 4, 3};
 }
-constexpr int PAULI_RB = 4;
 // the tiled kernels need at least one full wave per tile
 bool tiled_ok(int n, int dtype) {
     const TileConfig c = tile_config(dtype);

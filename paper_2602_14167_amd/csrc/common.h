@@ -183,21 +183,35 @@ struct FPass {
 
 // Pauli sum, grouped by X-mask, for the tiled H|psi> / <H> passes.  Inside a
 // group the terms are split into classes of equal coefficient c_k i^{#Y_k},
-// so the kernels count sign parities with integer adds per class.
+// so the kernels count sign parities with integer adds per class: four
+// elements' counts packed as bytes in one 32-bit word, so a class holds at most
+// PCLASS_MAX terms.
+constexpr int PAULI_RB = 4;          // element-index bits per thread in the Pauli passes (16 elements)
+constexpr int PCLASS_MAX = 255;
 struct PTerm {
     int32_t z_local;     // Z/Y bits inside the tile, as local bit positions
     int32_t pad;
     uint64_t z_out;      // Z/Y qubits outside the tile
+    // element-index part of the sign parity: byte i of word w is
+    // parity(((e << (m - PAULI_RB)) ^ x_local) & z_local) for element index e = 4 w + i
+    uint32_t epar[4];
 };
+// A group's coefficient of psi_{l ^ x} is sum over classes of
+// c * (n_terms - 2 * #odd parities): the element-independent part
+// sum c * n_terms is stored with the group, and terms without Z/Y bits
+// (parities all even) are not listed; a group lists at least one class (one
+// without terms when none of its terms has Z/Y bits).
 struct PClass {
     int32_t term_begin, term_end;
     double cre, cim;     // common coefficient c * i^{#Y}
-    int32_t zfree, pad;  // every term without Z/Y bits: each contributes +1, no parities to count
+    float fre, fim;      // the same, rounded to float32 (the complex64 passes)
 };
 struct PGroup {
     int32_t x_local;     // X/Y bits (all inside the tile), local positions
     int32_t class_begin, class_end;
     int32_t pad;
+    double cbr, cbi;     // sum over all its classes of c * n_terms
+    float fbr, fbi;      // the same, rounded to float32
 };
 struct PPass {
     int32_t group_begin, group_end;

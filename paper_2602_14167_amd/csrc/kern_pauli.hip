@@ -6,10 +6,13 @@
 // read the same partner amplitude psi_{j^x}, so H is applied group by group:
 //   (H psi)_j = psi_{j^x} * sum_{k in group} c_k i^{#Y_k} (-1)^{popcount((j^x) & z_k)}.
 // Inside a group, terms of equal coefficient form a class whose signed sum is
-// c * (n_terms - 2 * #odd parities): integer counting, no float adds per term.
-// E is accumulated in float64 (exact products of the float32 amplitudes),
-// reduced per wave by butterfly shuffles and per workgroup in a fixed order
-// (deterministic); the partial sums go to `epart` for a final fixed-order sum.
+// c * (n_terms - 2 * #odd parities): integer counting (four elements' counts
+// as bytes of one word), no float adds per term.  The tiled pass forms each
+// element's share of (H psi)_l in the state's precision (float32 for
+// complex64: lambda is stored in it); E accumulates Re(conj(psi_l) * share)
+// in float64, reduced per wave by butterfly shuffles and per workgroup in a
+// fixed order (deterministic); the partial sums go to `epart` for a final
+// fixed-order sum.
 // Measurement parallelism over terms (Sec. "Data Parallelism") is realised on
 // one GPU as parallelism over amplitudes with all terms of a group fused.
 #include "devutil.h"
@@ -42,6 +45,15 @@ __device__ __forceinline__ uint64_t pinned(uint64_t v) {
     return (uint64_t(hi) << 32) | lo;
 }
 
+// v ^ u for a per-lane v and a uniform u, as one instruction the compiler
+// cannot hoist out of a loop (hoisted, every element's xor would hold a
+// register across the group loop)
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, uint32_t u) {
+    uint32_t r;
+    asm volatile("v_xor_b32 %0, %1, %2" : "=v"(r) : "s"(u), "v"(v));
+    return r;
+}
+
 // global offset of element it's local index bits it * nt (the top RB local
 // bits), from their images: a few selects instead of a loop over every local bit
 template <int RB>
@@ -52,6 +64,26 @@ __device__ __forceinline__ uint64_t elem_off(const uint64_t* hb, int it) {
         if ((it >> k) & 1) g += hb[k];
     return g;
 }
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// a class's coefficient in the state's precision
+template <typename R> __device__ __forceinline__ R coef_re(const PClass& C);
+template <typename R> __device__ __forceinline__ R coef_im(const PClass& C);
+template <> __device__ __forceinline__ float coef_re<float>(const PClass& C) { return C.fre; }
+template <> __device__ __forceinline__ float coef_im<float>(const PClass& C) { return C.fim; }
+template <> __device__ __forceinline__ double coef_re<double>(const PClass& C) { return C.cre; }
+template <> __device__ __forceinline__ double coef_im<double>(const PClass& C) { return C.cim; }
+template <typename R> __device__ __forceinline__ R grp_re(const PGroup& G);
+template <typename R> __device__ __forceinline__ R grp_im(const PGroup& G);
+template <> __device__ __forceinline__ float grp_re<float>(const PGroup& G) { return G.fbr; }
+template <> __device__ __forceinline__ float grp_im<float>(const PGroup& G) { return G.fbi; }
+template <> __device__ __forceinline__ double grp_re<double>(const PGroup& G) { return G.cbr; }
+template <> __device__ __forceinline__ double grp_im<double>(const PGroup& G) { return G.cbi; }
 
 __device__ __forceinline__ uint64_t tile_base(uint64_t tile, uint64_t tmask, int n) {
     uint64_t base = 0;
@@ -83,6 +115,33 @@ __device__ double block_sum(double v, double* sh, int nthreads) {
     return s;
 }
 
+// the tile's element l ^ x for the thread's element l = e + t (e: the element
+// index's bits, uniform): the thread's bits and e's are disjoint, so the byte
+// offset is the thread's xor a uniform part
+template <typename R>
+__device__ __forceinline__ cx<R> partner(const cx<R>* lds, uint32_t tb8, uint32_t e, uint32_t x) {
+    const uint32_t off = lane_xor(tb8, (e ^ x) * uint32_t(sizeof(cx<R>)));
+    return *reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(lds) + off);
+}
+
+// odd-parity counts of a class's terms for the elements c0 .. c0 + 4 CW - 1 of
+// the thread, a byte per element: parity((l ^ x) & z) splits into the
+// thread's part, the tile's part and the element index's part (the planner's epar)
+template <int CW>
+__device__ __forceinline__ void odd_counts(cptr<PTerm> terms, int k0, int k1, uint64_t base, uint32_t t, int c0,
+                                           uint32_t (&odd)[CW]) {
+#pragma unroll
+    for (int w = 0; w < CW; ++w) odd[w] = 0;
+    for (int k = k0; k < k1; ++k) {
+        const uint32_t zl = uint32_t(terms[k].z_local);
+        const uint32_t tb = (__popcll(base & terms[k].z_out) & 1) ? 0x01010101u : 0u;
+        const uint32_t pt = (uint32_t(__popc(t & zl)) & 1u) * 0x01010101u;   // per lane
+        cptr<uint32_t> ep = terms[k].epar + (c0 >> 2);
+#pragma unroll
+        for (int w = 0; w < CW; ++w) odd[w] += pt ^ (ep[w] ^ tb);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // tiled: one pass handles every X-group whose mask lies inside its tile
 // ---------------------------------------------------------------------------
@@ -101,8 +160,10 @@ k_pauli_tile(const JobList jl, const Job single) {
     const int accumulate = pass_idx > 0;
     const int wgs = J.e_wgs;
     const int n = J.n;
-    const int64_t b = local / wgs;
-    const int wg = int(local - b * wgs);
+    // (the 64-bit division runs on the vector unit: its results are moved back
+    // to scalar registers, so the tile's base offset and its parities stay scalar)
+    const int64_t b = uniform64(local / wgs);
+    const int wg = uniform(int(local - b * wgs));
     cptr<PPass> P = as_const(J.ppasses) + pass_idx;
     const int m = P->m, lo = P->lo;
     const uint64_t tmask = P->tile_mask;
@@ -127,16 +188,14 @@ k_pauli_tile(const JobList jl, const Job single) {
 #pragma unroll
     for (int k = 0; k < RB; ++k) hb[k] = loc2glob(1u << (m - RB + k), lo, m, lq);
 
+    const uint32_t tb8 = uint32_t(t) * uint32_t(sizeof(cx<R>));   // the thread's byte offset in the LDS tile
     const bool read_lam = has_lam && accumulate;
-    constexpr int CH = (NB < 4) ? NB : 4;
+    // elements per chunk: CH lambda values in flight and CH accumulators
+    constexpr int CH = (sizeof(R) == 4) ? 8 : 4;
+    constexpr int CW = CH / 4;   // packed parity-count words (a byte per element)
+    static_assert(NB % CH == 0 && CH % 4 == 0, "chunks of whole count words");
     for (int64_t tile = wg; tile < tiles_per_state; tile += wgs) {
-        const uint64_t base = tile_base(uint64_t(tile), tmask, n);
-        // lambda elements of the first chunk (later passes accumulate into
-        // them), in flight together with the psi tile; each chunk loads the next one's
-        cx<R> lamn[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i)
-            lamn[i] = (read_lam && active) ? lam[(base + elem_off<RB>(hb, i)) + pinned(gt)] : cx<R>{R(0), R(0)};
+        const uint64_t base = uniform64(int64_t(tile_base(uint64_t(tile), tmask, n)));
         __syncthreads();
         // psi tile -> LDS; element l = it*nt + t (lane-consecutive, coalesced)
         if (active) {
@@ -150,75 +209,62 @@ k_pauli_tile(const JobList jl, const Job single) {
         if (!active) continue;
         // elements l = it*nt + t, CH at a time; the term loop is outside the
         // element loop so every scalar load of a term serves CH elements
-#pragma unroll 1   // (unrolled, the chunks' double accumulators double the registers)
+#pragma unroll 1   // (unrolled, the chunks' accumulators double the registers)
         for (int c0 = 0; c0 < NB; c0 += CH) {
+            // the chunk's lambda elements (later passes accumulate into them):
+            // in flight while the groups are summed
             cx<R> acc[CH];
 #pragma unroll
-            for (int i = 0; i < CH; ++i) acc[i] = lamn[i];
-            if (read_lam && c0 + CH < NB) {
+            for (int i = 0; i < CH; ++i)
+                acc[i] = read_lam ? lam[(base + elem_off<RB>(hb, c0 + i)) + pinned(gt)] : cx<R>{R(0), R(0)};
+            // this pass's share of (H psi)_l: sum over groups of
+            // (cre + i cim) psi_{l ^ x}, in the state's precision; E takes
+            // Re(conj(psi_l) * share) in float64 once per element
+            R sr[CH], si[CH];
 #pragma unroll
-                for (int i = 0; i < CH; ++i) lamn[i] = lam[(base + elem_off<RB>(hb, c0 + CH + i)) + pinned(gt)];
-            }
-            // this pass's share of (H psi)_l in float64: sum over groups of
-            // (cre + i cim) psi_{l ^ x}; E takes Re(conj(psi_l) * share) once per element
-            double sr[CH], si[CH];
-#pragma unroll
-            for (int i = 0; i < CH; ++i) { sr[i] = 0.0; si[i] = 0.0; }
+            for (int i = 0; i < CH; ++i) { sr[i] = R(0); si[i] = R(0); }
             const int g_end = P->group_end;
             for (int g = P->group_begin; g < g_end; ++g) {
                 const PGroup G = groups[g];
-                double cre[CH], cim[CH];
+                // the group's coefficient of psi_{l ^ x}: the element-independent
+                // sum c * n_terms, then -2 c * #odd parities per class
+                const R gbr = grp_re<R>(G), gbi = grp_im<R>(G);
+                // (every group lists at least one class, possibly without terms)
+                int c = G.class_begin;
+                const int c_end = G.class_end;
+                R cre[CH], cim[CH];
+                uint32_t odd[CW];
+                odd_counts<CW>(terms, classes[c].term_begin, classes[c].term_end, base, uint32_t(t), c0, odd);
+                const R m2r = R(-2) * coef_re<R>(classes[c]), m2i = R(-2) * coef_im<R>(classes[c]);
 #pragma unroll
-                for (int i = 0; i < CH; ++i) { cre[i] = 0.0; cim[i] = 0.0; }
-                for (int c = G.class_begin; c < G.class_end; ++c) {
-                    const PClass C = classes[c];
-                    if (C.zfree) {   // uniform: every term adds +1 (no parities)
-                        const double sgn = double(C.term_end - C.term_begin);
-#pragma unroll
-                        for (int i = 0; i < CH; ++i) {
-                            cre[i] = fma(C.cre, sgn, cre[i]);
-                            cim[i] = fma(C.cim, sgn, cim[i]);
-                        }
-                        continue;
-                    }
-                    int odd[CH];
-#pragma unroll
-                    for (int i = 0; i < CH; ++i) odd[i] = 0;
-                    for (int k = C.term_begin; k < C.term_end; ++k) {
-                        const PTerm T = terms[k];
-                        const uint32_t zl = uint32_t(T.z_local);
-                        // parity of (l ^ x) & z = thread part ^ uniform part
-                        const uint32_t pt = uint32_t(__popc(uint32_t(t) & zl)) & 1u;
-                        const uint32_t ub = uint32_t(__popcll(base & T.z_out) + __popc(uint32_t(G.x_local) & zl));
-#pragma unroll
-                        for (int i = 0; i < CH; ++i) {
-                            const uint32_t u = (ub + uint32_t(__popc(uint32_t((c0 + i) * nt) & zl))) & 1u;
-                            odd[i] += int(pt ^ u);
-                        }
-                    }
-                    const int nterm = C.term_end - C.term_begin;
+                for (int i = 0; i < CH; ++i) {
+                    const R cnt = R((odd[i >> 2] >> (8 * (i & 3))) & 0xFFu);   // (a byte-to-float convert)
+                    cre[i] = fma(m2r, cnt, gbr);
+                    cim[i] = fma(m2i, cnt, gbi);
+                }
+                for (++c; c < c_end; ++c) {
+                    odd_counts<CW>(terms, classes[c].term_begin, classes[c].term_end, base, uint32_t(t), c0, odd);
+                    const R n2r = R(-2) * coef_re<R>(classes[c]), n2i = R(-2) * coef_im<R>(classes[c]);
 #pragma unroll
                     for (int i = 0; i < CH; ++i) {
-                        const double sgn = double(nterm - 2 * odd[i]);
-                        cre[i] = fma(C.cre, sgn, cre[i]);
-                        cim[i] = fma(C.cim, sgn, cim[i]);
+                        const R cnt = R((odd[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+                        cre[i] = fma(n2r, cnt, cre[i]);
+                        cim[i] = fma(n2i, cnt, cim[i]);
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < CH; ++i) {
-                    const uint32_t lp = uint32_t((c0 + i) * nt + t) ^ uint32_t(G.x_local);
-                    const cx<R> pp = lds[lp];
-                    const double pr = double(pp.re), pi = double(pp.im);
-                    sr[i] = fma(cre[i], pr, fma(-cim[i], pi, sr[i]));
-                    si[i] = fma(cre[i], pi, fma(cim[i], pr, si[i]));
+                    const cx<R> pp = partner<R>(lds, tb8, uint32_t((c0 + i) * nt), uint32_t(G.x_local));
+                    sr[i] = fma(cre[i], pp.re, fma(-cim[i], pp.im, sr[i]));
+                    si[i] = fma(cre[i], pp.im, fma(cim[i], pp.re, si[i]));
                 }
             }
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const cx<R> own = lds[uint32_t((c0 + i) * nt + t)];
-                e_acc = fma(double(own.re), sr[i], fma(double(own.im), si[i], e_acc));
-                acc[i].re += R(sr[i]);
-                acc[i].im += R(si[i]);
+                e_acc = fma(double(own.re), double(sr[i]), fma(double(own.im), double(si[i]), e_acc));
+                acc[i].re += sr[i];
+                acc[i].im += si[i];
             }
             if (has_lam) {
 #pragma unroll

@@ -765,22 +765,42 @@ std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const Til
             G.x_local = to_local(xs[i]);
             G.class_begin = int(out.classes.size());
             for (auto& cls : coefficient_classes(terms, by_x[xs[i]])) {
-                PClass pc{};
-                pc.cre = cls.first.first;
-                pc.cim = cls.first.second;
-                pc.term_begin = int(out.terms.size());
-                pc.zfree = 1;
-                for (int t : cls.second) {
-                    PTerm pt{};
-                    pt.z_local = to_local(terms[t].z);
-                    pt.z_out = terms[t].z & ~T;
-                    if (terms[t].z) pc.zfree = 0;
-                    out.terms.push_back(pt);
+                G.cbr += cls.first.first * double(cls.second.size());
+                G.cbi += cls.first.second * double(cls.second.size());
+                std::vector<int> zt;   // the terms with Z/Y bits: the others' parities are all even
+                for (int t : cls.second)
+                    if (terms[t].z) zt.push_back(t);
+                for (size_t c0 = 0; c0 < zt.size(); c0 += PCLASS_MAX) {
+                    PClass pc{};
+                    pc.cre = cls.first.first;
+                    pc.cim = cls.first.second;
+                    pc.fre = float(pc.cre);
+                    pc.fim = float(pc.cim);
+                    pc.term_begin = int(out.terms.size());
+                    const size_t c1 = std::min(zt.size(), c0 + PCLASS_MAX);
+                    for (size_t j = c0; j < c1; ++j) {
+                        const int t = zt[j];
+                        PTerm pt{};
+                        pt.z_local = to_local(terms[t].z);
+                        pt.z_out = terms[t].z & ~T;
+                        for (int e = 0; m >= PAULI_RB && e < (1 << PAULI_RB); ++e) {   // (below, no tiled pass runs)
+                            const uint32_t l = (uint32_t(e) << (m - PAULI_RB)) ^ uint32_t(G.x_local);
+                            pt.epar[e >> 2] |= uint32_t(popc(uint64_t(l & uint32_t(pt.z_local))) & 1) << (8 * (e & 3));
+                        }
+                        out.terms.push_back(pt);
+                    }
+                    pc.term_end = int(out.terms.size());
+                    out.classes.push_back(pc);
                 }
-                pc.term_end = int(out.terms.size());
+            }
+            if (int(out.classes.size()) == G.class_begin) {   // no Z/Y bits at all: one class without terms
+                PClass pc{};
+                pc.term_begin = pc.term_end = int(out.terms.size());
                 out.classes.push_back(pc);
             }
             G.class_end = int(out.classes.size());
+            G.fbr = float(G.cbr);
+            G.fbi = float(G.cbi);
             out.groups.push_back(G);
         }
         P.group_end = int(out.groups.size());
