@@ -532,10 +532,12 @@ tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_st
             const int m = P.host.passes[p].m;
             const JobList jl{nullptr, nullptr, 0, int32_t(p)};
             const int64_t blocks = J.tiles * J.batch;
-            if (J.qpasses && J.qcoef) {
+            const int qk = (J.qpasses && J.qcoef) ? P.host.qpasses[p].kind : QK_GENERIC;
+            if (qk != QK_GENERIC) {
                 // a few tiles per workgroup, so each fetch overlaps a tile's phases
                 const int wgs = int(std::min<int64_t>(J.tiles, std::max<int64_t>(1, 2048 / J.batch)));
-                PROF_TRY(F_FWD_TILE, launch_rounds_fwd(jl, J, rb, wgs, int64_t(wgs) * J.batch, 1 << (m - rb), st));
+                PROF_TRY(F_FWD_TILE, launch_rounds_fwd(jl, J, rb, qk == QK_FSIM, wgs, int64_t(wgs) * J.batch,
+                                                       1 << (m - rb), st));
             }
             else if (rb == RB)
                 PROF_TRY(F_FWD_TILE, (launch_tile_fwd<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
@@ -600,8 +602,9 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
             const int m = P.host.rpasses[np - 1 - k].m;
             const JobList jl{nullptr, nullptr, 0, int32_t(k)};
             const int64_t blocks = int64_t(J.wgs) * J.batch;
-            if (J.qrpasses && J.qcoef)
-                PROF_TRY(F_REV_TILE, launch_rounds_rev(jl, J, rb, blocks, 1 << (m - rb), st));
+            const int qk = (J.qrpasses && J.qcoef) ? P.host.qrpasses[np - 1 - k].kind : QK_GENERIC;
+            if (qk != QK_GENERIC)
+                PROF_TRY(F_REV_TILE, launch_rounds_rev(jl, J, rb, qk == QK_FSIM, blocks, 1 << (m - rb), st));
             else if (rb == RB)
                 PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
             else

@@ -121,12 +121,25 @@ struct Pass {
 // amplitude y of the phase moves to C(y), which the phase applies by writing
 // register j at LDS position C(y) (the reverse sweep reads it from there).
 // C is given by cimg[b] = C(e_b), the image of local bit b.
+//
+// fSim rounds: the passes made of fSim gates and Hadamards only.  A phase holds a chain of
+// up to 5 qubits in register bits 0..4 and runs steps of two rounds on fixed
+// register pairs: (0,1) and (2,3), then (1,2) and (3,4) (an absent gate is
+// the identity; fSim is symmetric in its two qubits).  Each step lists the
+// gate of pair slot k (k = 0..3 in that order) in ry[k] and its first
+// gradient slot (theta; phi is the next) in sy[k].  Hadamards that precede
+// every other gate of their qubit in the pass are applied at the start of the
+// phase holding the qubit (hmask: register bits).
+//
+// A pass whose gates are neither kind runs on the generic tiled kernels.
 // ---------------------------------------------------------------------------
 constexpr int QREG = 5;
+constexpr int QK_GENERIC = 0, QK_ROT = 1, QK_FSIM = 2;   // QPass::kind
 
 struct QStep {
     int32_t ry[QREG], rz[QREG];   // gate index of the RY / RZ on register bit i, -1: identity
     int32_t sy[QREG], sz[QREG];   // its gradient slot inside the pass, -1 none
+    int32_t kind, pad;            // QK_ROT or QK_FSIM
 };
 
 struct QPhase {
@@ -134,10 +147,12 @@ struct QPhase {
     int32_t R[QREG];              // local bit of register bit i
     int32_t has_map;              // 0: C is the identity
     int32_t cimg[16];             // C(e_b) for local bits b < m
+    int32_t hmask, pad;           // fSim rounds: register bits taking a Hadamard before the steps
 };
 
 struct QPass {
     int32_t phase_begin, phase_end;
+    int32_t kind, pad;            // QK_*: the pass's kernel
 };
 
 // ---------------------------------------------------------------------------

@@ -819,6 +819,48 @@ __device__ __forceinline__ QBlk<QR> q_rz_round(QBlk<QR> a, const float* c) {
     return a;
 }
 
+// fSim rounds: pair slot k of a step has [cos t, sin t, Re e^{-ip}, Im e^{-ip}]
+// in c[4k .. 4k + 3] (an absent gate: 1, 0, 1, 0, the identity); the inverse
+// negates sin t and Im e^{-ip}.  Round A: slots 0, 1 on register bits (0,1),
+// (2,3); round B: slots 2, 3 on (1,2), (3,4).
+template <bool INV, int QR>
+__device__ __forceinline__ QBlk<QR> q_fs_round_a(QBlk<QR> a, const float* c) {
+    constexpr int NB = 1 << QR;
+    const float sg = INV ? -1.f : 1.f;
+    a = app_fsim<float, NB, 0, 1>(a, c[0], sg * c[1], cx<float>{c[2], sg * c[3]});
+    a = app_fsim<float, NB, 2, 3>(a, c[4], sg * c[5], cx<float>{c[6], sg * c[7]});
+    return a;
+}
+template <bool INV, int QR>
+__device__ __forceinline__ QBlk<QR> q_fs_round_b(QBlk<QR> a, const float* c) {
+    constexpr int NB = 1 << QR;
+    const float sg = INV ? -1.f : 1.f;
+    a = app_fsim<float, NB, 1, 2>(a, c[8], sg * c[9], cx<float>{c[10], sg * c[11]});
+    if constexpr (QR > 4) a = app_fsim<float, NB, 3, 4>(a, c[12], sg * c[13], cx<float>{c[14], sg * c[15]});
+    return a;
+}
+
+// Hadamard on the register bits set in mask (uniform), the others unchanged
+template <int QR>
+__device__ __forceinline__ QBlk<QR> q_h_round(QBlk<QR> a, uint32_t mask) {
+    constexpr int NB = 1 << QR;
+    const float r = 0.70710678118654752f;
+#pragma unroll
+    for (int b = 0; b < QR; ++b) {
+        const bool on = (mask >> b) & 1;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (j & (1 << b)) continue;
+            const cx<float> x0 = a.v[j], x1 = a.v[j | (1 << b)];
+            const cx<float> y0 = {r * (x0.re + x1.re), r * (x0.im + x1.im)};
+            const cx<float> y1 = {r * (x0.re - x1.re), r * (x0.im - x1.im)};
+            a.v[j] = on ? y0 : x0;
+            a.v[j | (1 << b)] = on ? y1 : x1;
+        }
+    }
+    return a;
+}
+
 struct QCoef {
     float c[QCOEF];
 };
@@ -931,9 +973,21 @@ __device__ __forceinline__ void q_red(double* red, const int32_t* slot, int nwav
         if (slot[i] >= 0) red_add(red, slot[i] * nwaves + wave, g[i], lane);
 }
 
+// an fSim round's (theta, phi) partials into their slots (slot, slot + 1)
+template <int NS>
+__device__ __forceinline__ void q_red_fs(double* red, const int32_t* slot, int nwaves, int wave, int lane,
+                                         const float* gt, const float* gp) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+        if (slot[i] >= 0) {
+            red_add(red, slot[i] * nwaves + wave, gt[i], lane);
+            red_add(red, (slot[i] + 1) * nwaves + wave, gp[i], lane);
+        }
+}
+
 // forward: `wgs` workgroups per member loop over the tiles; the next tile's
 // loads are in flight while the current tile's phases run
-template <int QR>
+template <int QR, bool FS>
 __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl, const Job single, int wgs) {
     __shared__ cx<float> lds[Tile<float>::ELEMS];
     int64_t local;
@@ -964,15 +1018,24 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl,
             cptr<QPhase> F = phases + f;
             const QMap<QR> q = qmap<QR>(F, t, pi.m);
             QBlk<QR> a = q_read<false>(lds, q);
+            if constexpr (FS) {
+                const uint32_t hm = uint32_t(F->hmask);
+                if (hm) a = q_h_round<QR>(a, hm);
+            }
             const int s_end = F->step_end;
             for (int s = F->step_begin; s < s_end; ++s) {
                 const QCoef C = coef[s];
-                a = q_ry_round<false, QR>(a, C.c);
-                a = q_rz_round<false, QR>(a, C.c);
-                flip = flip != (C.c[20] < 0.f);
+                if constexpr (FS) {
+                    a = q_fs_round_a<false, QR>(a, C.c);
+                    a = q_fs_round_b<false, QR>(a, C.c);
+                } else {
+                    a = q_ry_round<false, QR>(a, C.c);
+                    a = q_rz_round<false, QR>(a, C.c);
+                    flip = flip != (C.c[20] < 0.f);
+                }
             }
             __syncthreads();   // the write permutes positions: every read first
-            q_write<true>(lds, a, q);
+            q_write<!FS>(lds, a, q);
             __syncthreads();
         }
         q_tile_store<QR>(lds, psi, base, A, flip);
@@ -982,7 +1045,7 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl,
 // reverse: phases and steps backwards; each phase reads through C, un-applies
 // its rounds (derivatives first: every rotation of a round at the round's
 // end point, where all of them commute) and writes without C
-template <int QR>
+template <int QR, bool FS>
 __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl, const Job single) {
     constexpr int NB = 1 << QR;
     __shared__ cx<float> lds[Tile<float>::ELEMS];
@@ -1024,11 +1087,11 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
             __syncthreads();
             q_tile_put<QR>(lds, vp, A);
             __syncthreads();
-            ps = q_read<true>(lds, q);
+            ps = q_read<!FS>(lds, q);
             __syncthreads();
             q_tile_put<QR>(lds, vl, A);
             __syncthreads();
-            la = q_read<true>(lds, q);
+            la = q_read<!FS>(lds, q);
         }
         for (;;) {
             cptr<QPhase> F = phases + f;
@@ -1036,6 +1099,23 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
             for (int s = F->step_end - 1; s >= s_begin; --s) {
                 const QStep S = steps[s];
                 const QCoef C = coef[s];
+                if constexpr (FS) {
+                    // round B, then round A: each round's derivatives at its end
+                    // point (its gates act on disjoint pairs and commute), then
+                    // the un-apply, then the reductions
+                    float gt[2], gp[2];
+                    grad_fsim<float, NB, 1, 2>(la, ps, gt[0], gp[0]);
+                    if constexpr (QR > 4) grad_fsim<float, NB, (QR > 4 ? 3 : 0), (QR > 4 ? 4 : 1)>(la, ps, gt[1], gp[1]);
+                    ps = q_fs_round_b<true, QR>(ps, C.c);
+                    la = q_fs_round_b<true, QR>(la, C.c);
+                    q_red_fs<(QR > 4 ? 2 : 1)>(red, S.sy + 2, nwaves, wave, lane, gt, gp);
+                    grad_fsim<float, NB, 0, 1>(la, ps, gt[0], gp[0]);
+                    grad_fsim<float, NB, 2, 3>(la, ps, gt[1], gp[1]);
+                    ps = q_fs_round_a<true, QR>(ps, C.c);
+                    la = q_fs_round_a<true, QR>(la, C.c);
+                    q_red_fs<2>(red, S.sy, nwaves, wave, lane, gt, gp);
+                    continue;
+                }
                 // the round's derivatives first, then the un-apply, then their
                 // reductions (which leave the blocks alone)
                 float gz[QR], gy[QR];
@@ -1057,6 +1137,13 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
                 flip = flip != (C.c[20] < 0.f);
                 q_red<QR>(red, S.sy, nwaves, wave, lane, gy);
             }
+            if constexpr (FS) {   // the phase's Hadamards (their own inverses) last
+                const uint32_t hm = uint32_t(F->hmask);
+                if (hm) {
+                    ps = q_h_round<QR>(ps, hm);
+                    la = q_h_round<QR>(la, hm);
+                }
+            }
             if (f == Q.phase_begin) break;
             // hand both blocks to the previous phase: written in plain order,
             // read back through that phase's permutation
@@ -1064,11 +1151,11 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
             __syncthreads();
             q_write<false>(lds, ps, q);
             __syncthreads();
-            ps = q_read<true>(lds, qn);
+            ps = q_read<!FS>(lds, qn);
             __syncthreads();
             q_write<false>(lds, la, q);
             __syncthreads();
-            la = q_read<true>(lds, qn);
+            la = q_read<!FS>(lds, qn);
             q = qn;
             --f;
         }
@@ -1102,6 +1189,18 @@ __global__ void k_rounds_coef(const QStep* __restrict__ fsteps, int nf, const QS
     const QStep S = s < nf ? fsteps[s] : rsteps[s - nf];
     const cx<float>* om = opm + size_t(b) * n_gates * 16;
     QCoef C;
+    if (S.kind == QK_FSIM) {   // the fSim matrix: entry 5 = cos t, entry 6 = -i sin t, entry 15 = e^{-ip}
+        for (int k = 0; k < 4; ++k) {
+            const int g = S.ry[k];
+            C.c[4 * k] = g >= 0 ? om[size_t(g) * 16 + 5].re : 1.f;
+            C.c[4 * k + 1] = g >= 0 ? -om[size_t(g) * 16 + 6].im : 0.f;
+            C.c[4 * k + 2] = g >= 0 ? om[size_t(g) * 16 + 15].re : 1.f;
+            C.c[4 * k + 3] = g >= 0 ? om[size_t(g) * 16 + 15].im : 0.f;
+        }
+        for (int k = 16; k < QCOEF; ++k) C.c[k] = 0.f;
+        out[i] = C;
+        return;
+    }
     bool odd = false;
     for (int k = 0; k < QREG; ++k) {
         const int gy = S.ry[k], gz = S.rz[k];
@@ -1157,22 +1256,28 @@ hipError_t launch_rounds_coef(const QStep* fsteps, int nf, const QStep* rsteps, 
 size_t rounds_coef_bytes(int steps) { return size_t(steps) * sizeof(QCoef); }
 
 // forward: wgs workgroups per member (each loops over tiles), blocks = wgs * batch
-hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, int wgs, int64_t blocks, int nthreads,
-                             hipStream_t st) {
+hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, bool fsim, int wgs, int64_t blocks,
+                             int nthreads, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     if (jl.jobs || (qr != 4 && qr != 5) || nthreads > (1 << (13 - qr)) || nthreads < 64 || wgs < 1)
         return hipErrorInvalidValue;
-    if (qr == 5) hipLaunchKernelGGL(k_rounds_fwd<5>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single, wgs);
-    else hipLaunchKernelGGL(k_rounds_fwd<4>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single, wgs);
+    const dim3 g = dim3(unsigned(blocks)), b = dim3(unsigned(nthreads));
+    if (qr == 5 && fsim) hipLaunchKernelGGL((k_rounds_fwd<5, true>), g, b, 0, st, jl, single, wgs);
+    else if (qr == 5) hipLaunchKernelGGL((k_rounds_fwd<5, false>), g, b, 0, st, jl, single, wgs);
+    else if (fsim) hipLaunchKernelGGL((k_rounds_fwd<4, true>), g, b, 0, st, jl, single, wgs);
+    else hipLaunchKernelGGL((k_rounds_fwd<4, false>), g, b, 0, st, jl, single, wgs);
     return hipGetLastError();
 }
 
-hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, int64_t blocks, int nthreads,
+hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, bool fsim, int64_t blocks, int nthreads,
                              hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     if (jl.jobs || (qr != 4 && qr != 5) || nthreads > (1 << (13 - qr)) || nthreads < 64) return hipErrorInvalidValue;
-    if (qr == 5) hipLaunchKernelGGL(k_rounds_rev<5>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
-    else hipLaunchKernelGGL(k_rounds_rev<4>, dim3(unsigned(blocks)), dim3(nthreads), 0, st, jl, single);
+    const dim3 g = dim3(unsigned(blocks)), b = dim3(unsigned(nthreads));
+    if (qr == 5 && fsim) hipLaunchKernelGGL((k_rounds_rev<5, true>), g, b, 0, st, jl, single);
+    else if (qr == 5) hipLaunchKernelGGL((k_rounds_rev<5, false>), g, b, 0, st, jl, single);
+    else if (fsim) hipLaunchKernelGGL((k_rounds_rev<4, true>), g, b, 0, st, jl, single);
+    else hipLaunchKernelGGL((k_rounds_rev<4, false>), g, b, 0, st, jl, single);
     return hipGetLastError();
 }
 

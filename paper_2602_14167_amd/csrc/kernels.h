@@ -91,9 +91,10 @@ hipError_t launch_tile_fwd(const JobList& jl, const Job& single, int64_t blocks,
 hipError_t launch_rounds_coef(const QStep* fsteps, int nf, const QStep* rsteps, int nr, const void* opm, int n_gates,
                               int64_t batch, void* out, hipStream_t st);
 size_t rounds_coef_bytes(int steps);
-hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, int wgs, int64_t blocks, int nthreads,
-                             hipStream_t st);
-hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, int64_t blocks, int nthreads,
+// fsim: the pass's rounds are fSim rounds (QK_FSIM), else rotation rounds
+hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, bool fsim, int wgs, int64_t blocks,
+                             int nthreads, hipStream_t st);
+hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, bool fsim, int64_t blocks, int nthreads,
                              hipStream_t st);
 template <typename R, int RB>
 hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);

@@ -184,8 +184,9 @@ std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<i
         QPhase F{};
         F.step_begin = int(steps.size());
         for (;;) {
-            QStep S;
+            QStep S{};
             for (int b = 0; b < QREG; ++b) S.ry[b] = S.rz[b] = S.sy[b] = S.sz[b] = -1;
+            S.kind = QK_ROT;
             bool took = false;
             for (int round = 0; round < 2; ++round) {
                 const int kind = round == 0 ? K_RY : K_RZ;
@@ -242,10 +243,95 @@ std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<i
         phases.push_back(F);
     }
     qp.phase_end = int(phases.size());
+    qp.kind = QK_ROT;
     size_t rots = 0;
     for (size_t k = first_step; k < steps.size(); ++k)
         for (int b = 0; b < QREG; ++b) rots += (steps[k].ry[b] >= 0) + (steps[k].rz[b] >= 0);
     if (rots + cnots != sel.size()) return "internal: rotation rounds lost a gate";
+    return "";
+}
+
+// fSim rounds of one pass (see QPhase).  A phase's register qubits form a
+// chain grown from the first remaining gate: later fSim gates (in circuit order)
+// that join one end of the chain with a new qubit extend it, up to qreg
+// qubits, so that chain neighbours sit on adjacent register bits.  Steps then
+// take, per pair slot, the gate that is the first remaining gate of both of
+// the pair's qubits: pairs (0,1), (2,3), then (1,2), (3,4).
+std::string plan_rounds_fsim(const std::vector<tcng_gate>& gates, const std::vector<int>& sel,
+                             const int* qubit_to_local, int m, int qreg, const std::vector<int32_t>& gate_slot_first,
+                             std::vector<QPhase>& phases, std::vector<QStep>& steps, QPass& qp) {
+    static const int pair_lo[4] = {0, 2, 1, 3};   // pair slot k: register bits (pair_lo[k], pair_lo[k] + 1)
+    qp.phase_begin = int(phases.size());
+    qp.kind = QK_FSIM;
+    size_t taken_total = 0;
+    std::vector<int> rem = sel;
+    auto first_gate = [&](int q) -> int {
+        for (size_t i = 0; i < rem.size(); ++i)
+            if ((gate_qmask(gates[rem[i]]) >> q) & 1) return int(i);
+        return -1;
+    };
+    while (!rem.empty()) {
+        std::vector<int> chain = {gates[rem[0]].q0};
+        if (gates[rem[0]].kind == K_FSIM) chain.push_back(gates[rem[0]].q1);
+        for (size_t i = 1; i < rem.size() && int(chain.size()) < qreg; ++i) {
+            const tcng_gate& g = gates[rem[i]];
+            if (g.kind != K_FSIM) continue;
+            const bool in0 = std::find(chain.begin(), chain.end(), g.q0) != chain.end();
+            const bool in1 = std::find(chain.begin(), chain.end(), g.q1) != chain.end();
+            if (in0 == in1) continue;
+            const int inner = in0 ? g.q0 : g.q1, outer = in0 ? g.q1 : g.q0;
+            if (inner == chain.back()) chain.push_back(outer);
+            else if (inner == chain.front()) chain.insert(chain.begin(), outer);
+        }
+        const int len = int(chain.size());
+        QPhase F{};
+        for (int b = 0; b < len; ++b) {   // Hadamards first
+            const int i = first_gate(chain[b]);
+            if (i >= 0 && gates[rem[i]].kind == K_H) {
+                F.hmask |= 1 << b;
+                rem.erase(rem.begin() + i);
+                ++taken_total;
+            }
+        }
+        F.step_begin = int(steps.size());
+        for (;;) {
+            QStep S{};
+            for (int b = 0; b < QREG; ++b) S.ry[b] = S.rz[b] = S.sy[b] = S.sz[b] = -1;
+            S.kind = QK_FSIM;
+            bool took = false;
+            for (int k = 0; k < 4; ++k) {
+                const int p = pair_lo[k];
+                if (p + 1 >= len || p + 1 >= qreg) continue;
+                const int a = first_gate(chain[p]), b = first_gate(chain[p + 1]);
+                if (a < 0 || a != b || gates[rem[a]].kind != K_FSIM) continue;
+                const int gi = rem[a];
+                S.ry[k] = gi;
+                S.sy[k] = gate_slot_first[gi];
+                rem.erase(rem.begin() + a);
+                took = true;
+                ++taken_total;
+            }
+            if (!took) break;
+            steps.push_back(S);
+        }
+        F.step_end = int(steps.size());
+        if (F.step_end == F.step_begin && !F.hmask) return "internal: fSim rounds made no progress";
+        for (int b = 0; b < 16; ++b) F.cimg[b] = b < m ? (1 << b) : 0;
+        uint32_t used = 0;
+        for (int b = 0; b < len; ++b) {
+            F.R[b] = qubit_to_local[chain[b]];
+            used |= 1u << F.R[b];
+        }
+        for (int b = len, l = m - 1; b < qreg; ++b) {
+            while ((used >> l) & 1) --l;
+            F.R[b] = l;
+            used |= 1u << l;
+        }
+        for (int b = qreg; b < QREG; ++b) F.R[b] = -1;
+        phases.push_back(F);
+    }
+    qp.phase_end = int(phases.size());
+    if (taken_total != sel.size()) return "internal: fSim rounds lost a gate";
     return "";
 }
 
@@ -264,10 +350,9 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
 
     std::vector<int> rem(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
-    // a wave's 64 lanes hold thread bits in both sweeps
-    out.rounds = m >= std::max(cfg.rb, cfg.rb_rev) + 6 && cfg.rb >= 4 && cfg.rb_rev >= 4;
-    for (const tcng_gate& g : gates)
-        if (g.kind != K_RY && g.kind != K_RZ && g.kind != K_CNOT) out.rounds = false;
+    // rounds: a wave's 64 lanes hold thread bits in both sweeps
+    const bool rounds_ok = m >= std::max(cfg.rb, cfg.rb_rev) + 6 && cfg.rb >= 4 && cfg.rb_rev >= 4;
+    out.rounds = false;
 
     // per-gate slot assignment (global, in reverse-sweep order is not needed:
     // slots are contiguous per pass, assigned as passes are formed)
@@ -339,16 +424,34 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
         if (!why.empty()) return why;
         why = plan_phases(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, R, out.rphases, out.rops);
         if (!why.empty()) return why;
-        if (out.rounds) {
-            QPass Q{}, QR{};
-            why = plan_rounds(gates, sel, qubit_to_local, m, cfg.rb, gate_slot_first, out.qphases, out.qsteps, Q);
-            if (!why.empty()) return why;
-            why = plan_rounds(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, out.qrphases, out.qrsteps,
-                              QR);
-            if (!why.empty()) return why;
-            out.qpasses.push_back(Q);
-            out.qrpasses.push_back(QR);
+        // ---- rounds, when every gate of the pass is of one rounds kind
+        int kind = rounds_ok ? QK_ROT : QK_GENERIC;
+        for (int gi : sel)
+            if (gates[gi].kind != K_RY && gates[gi].kind != K_RZ && gates[gi].kind != K_CNOT) kind = QK_GENERIC;
+        if (rounds_ok && kind == QK_GENERIC) {
+            kind = QK_FSIM;
+            for (int gi : sel)
+                if (gates[gi].kind != K_FSIM && gates[gi].kind != K_H) kind = QK_GENERIC;
         }
+        QPass Q{}, QR{};
+        Q.phase_begin = Q.phase_end = int(out.qphases.size());
+        QR.phase_begin = QR.phase_end = int(out.qrphases.size());
+        if (kind == QK_ROT) {
+            why = plan_rounds(gates, sel, qubit_to_local, m, cfg.rb, gate_slot_first, out.qphases, out.qsteps, Q);
+            if (why.empty())
+                why = plan_rounds(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, out.qrphases,
+                                  out.qrsteps, QR);
+        } else if (kind == QK_FSIM) {
+            why = plan_rounds_fsim(gates, sel, qubit_to_local, m, cfg.rb, gate_slot_first, out.qphases, out.qsteps,
+                                   Q);
+            if (why.empty())
+                why = plan_rounds_fsim(gates, sel, qubit_to_local, m, cfg.rb_rev, gate_slot_first, out.qrphases,
+                                       out.qrsteps, QR);
+        }
+        if (!why.empty()) return why;
+        out.qpasses.push_back(Q);
+        out.qrpasses.push_back(QR);
+        if (kind != QK_GENERIC) out.rounds = true;
         out.passes.push_back(P);
         out.rpasses.push_back(R);
     }

@@ -28,9 +28,10 @@ struct CircuitPlan {
     std::vector<int32_t> slot_ptr, slot_idx;
     // U2 gates: gate index -> first of its 32 cotangent slots (-1 otherwise)
     std::vector<int32_t> gate_slot;
-    // rotation rounds of the same passes (empty unless every gate is RY, RZ or
-    // CNOT and a wave's 64 lanes fit the thread bits): the forward sweep with
-    // cfg.rb register bits, the reverse sweep with cfg.rb_rev
+    // rounds of the same passes, one QPass per pass (kind QK_GENERIC where the
+    // pass's gates are not all RY / RZ / CNOT, or all fSim, or a wave's 64
+    // lanes do not fit the thread bits): the forward sweep with cfg.rb register
+    // bits, the reverse sweep with cfg.rb_rev; `rounds`: some pass has them
     bool rounds = false;
     std::vector<QPass> qpasses, qrpasses;
     std::vector<QPhase> qphases, qrphases;

@@ -1,7 +1,8 @@
-"""Rotation rounds: the complex64 tiled passes of circuits made of RY, RZ and
-CNOT (fixed rounds of rotations on 5 register bits, each phase's CNOTs a
-permutation of the tile's local index), through the C ABI, against the CPU
-oracle.
+"""Rounds: the complex64 tiled passes of circuits made of RY, RZ and CNOT
+(fixed rounds of rotations on 5 register bits, each phase's CNOTs a
+permutation of the tile's local index) or of fSim gates and Hadamards (fixed
+rounds on register pairs), and circuits mixing them with passes of other
+gates (the generic tiled kernels), through the C ABI, against the CPU oracle.
 
 Bars as in test_gpu_parity: |dE| <= 1e-5 S and |d grad|_inf <= 1e-4 S with
 S = sum |c_k|; amplitudes within 8 * (gate applications) * 2^-24 of the
@@ -86,6 +87,8 @@ def test_rounds_taken_only_where_they_apply(P):
     gates, params, mats = W.random_circuit(14, 40, r)   # every kind: not rotation rounds
     assert P.Circuit(14, gates, len(params), mats).rounds() == 0
     assert P.Circuit(10, w["gates"][:0], 0).rounds() == 0   # below 11 qubits: no 64-lane thread part
+    f = W.cfg5(rows=4, cols=4, depth=8)
+    assert P.Circuit(16, f["gates"], f["n_params"]).rounds() > 0
 
 
 @pytest.mark.parametrize("n,layers,tiling", [(11, 2, None), (13, 4, None), (16, 3, None), (16, 3, (12, 5, 5)),
@@ -109,3 +112,81 @@ def test_rounds_random_ry_rz_cnot(P, oracle_mod, n, n_gates, seed, tiling):
     pb = r.uniform(0, 2 * np.pi, (2, npar))
     init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
     check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, tiling, f"random seed={seed} tiling={tiling}")
+
+
+# ---------------------------------------------------------------------------
+# fSim rounds: passes of fSim gates and Hadamards (pair slots (0,1), (2,3),
+# then (1,2), (3,4) of a chain of register qubits)
+# ---------------------------------------------------------------------------
+def fsim_h_circuit(n, n_gates, rng, nearest=False):
+    """Random fSim / Hadamard circuit: about a fifth Hadamards; fSim pairs
+    random (or nearest neighbours), in either order, angles uniform."""
+    g, npar = [], 0
+    for _ in range(n_gates):
+        if rng.random() < 0.2:
+            g.append(W.gate(W.H, int(rng.integers(n))))
+            continue
+        if nearest:
+            a = int(rng.integers(n - 1))
+            q0, q1 = (a, a + 1) if rng.random() < 0.5 else (a + 1, a)
+        else:
+            q0, q1 = (int(v) for v in rng.choice(n, size=2, replace=False))
+        g.append(W.gate(W.FSIM, q0, q1, p0=npar, p1=npar + 1))
+        npar += 2
+    return W.as_gate_array(g), npar
+
+
+@pytest.mark.parametrize("rows,cols,depth,tiling", [(3, 4, 8, None), (2, 7, 10, None), (4, 4, 12, None),
+                                                    (4, 4, 12, (13, 4, 4)), (3, 6, 10, (13, 5, 4)),
+                                                    (3, 6, 10, (12, 5, 5)), (4, 5, 6, (12, 4, 4))])
+def test_fsim_rounds_brickwork(P, oracle_mod, rows, cols, depth, tiling):
+    """The fSim brick-wall workload (Hadamard layer, depth-d fSim brick wall,
+    2D TFIM) on small lattices."""
+    w = W.cfg5(rows=rows, cols=cols, depth=depth)
+    n = w["n"]
+    r = np.random.default_rng(200 + n + depth)
+    pb = np.stack([w["params"], r.uniform(0, 2 * np.pi, w["n_params"])])
+    init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
+    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, tiling,
+          f"fsim {rows}x{cols} d={depth}")
+
+
+@pytest.mark.parametrize("tiling", [None, (13, 4, 4)])
+@pytest.mark.parametrize("n,n_gates,seed,nearest", [(11, 60, 1, True), (12, 90, 2, False), (13, 120, 3, True),
+                                                    (14, 120, 4, False), (16, 160, 5, True)])
+def test_fsim_rounds_random(P, oracle_mod, n, n_gates, seed, nearest, tiling):
+    r = np.random.default_rng(300 + seed)
+    gates, npar = fsim_h_circuit(n, n_gates, r, nearest)
+    codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=4)
+    pb = r.uniform(0, 2 * np.pi, (2, npar))
+    init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
+    check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, tiling, f"fsim random seed={seed}")
+
+
+@pytest.mark.parametrize("n", [15, 16])
+def test_rounds_mixed_with_generic_passes(P, oracle_mod, n):
+    """fSim-round, rotation-round and generic passes in one circuit (11-bit
+    tiles: the planner's passes of these sizes take all three kinds): a
+    12-layer fSim brick wall, 8 HEA layers (RY, RZ on every qubit, a CNOT
+    chain), then RX on every qubit (no rounds kind)."""
+    r = np.random.default_rng(400 + n)
+    g, npar = [], 0
+    for L in range(12):
+        for i in range(L % 2, n - 1, 2):
+            g.append(W.gate(W.FSIM, i, i + 1, p0=npar, p1=npar + 1))
+            npar += 2
+    for L in range(8):
+        for q in range(n):
+            g.append(W.gate(W.RY, q, p0=npar))
+            g.append(W.gate(W.RZ, q, p0=npar + 1))
+            npar += 2
+        for q in range(n - 1):
+            g.append(W.gate(W.CNOT, q, q + 1))
+    for q in range(n):
+        g.append(W.gate(W.RX, q, p0=npar))
+        npar += 1
+    gates = W.as_gate_array(g)
+    codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=4)
+    pb = r.uniform(0, 2 * np.pi, (2, npar))
+    init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
+    check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, (11, 5, 4), "mixed")
