@@ -573,7 +573,9 @@ k_tile_fwd(const JobList jl, const Job single) {
 // program order (the sum's order does not depend on scheduling).
 template <typename R>
 __device__ __forceinline__ void red_add(double* red, int idx, R v, int lane) {
-    const double s = wave_sum(double(v));
+    // (complex64: the wave's 64 lanes summed in float, each lane holding a
+    // float sum of its own amplitudes' products already; waves and tiles in float64)
+    const double s = double(wave_sum(v));
     if (lane == 0) (void)__hip_atomic_fetch_add(red + idx, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -840,6 +842,16 @@ __device__ __forceinline__ QBlk<QR> q_fs_round_b(QBlk<QR> a, const float* c) {
     return a;
 }
 
+// reverse sweep, one fSim gate on register bits (B0, B1): its (theta, phi)
+// derivative partials at the current point, then the inverse on psi and lambda
+template <int QR, int B0, int B1>
+__device__ __forceinline__ void fs_unapply(QBlk<QR>& ps, QBlk<QR>& la, const float* c, float& gt, float& gp) {
+    constexpr int NB = 1 << QR;
+    grad_fsim<float, NB, B0, B1>(la, ps, gt, gp);
+    ps = app_fsim<float, NB, B0, B1>(ps, c[0], -c[1], cx<float>{c[2], -c[3]});
+    la = app_fsim<float, NB, B0, B1>(la, c[0], -c[1], cx<float>{c[2], -c[3]});
+}
+
 // Hadamard on the register bits set in mask (uniform), the others unchanged
 template <int QR>
 __device__ __forceinline__ QBlk<QR> q_h_round(QBlk<QR> a, uint32_t mask) {
@@ -1100,19 +1112,16 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
                 const QStep S = steps[s];
                 const QCoef C = coef[s];
                 if constexpr (FS) {
-                    // round B, then round A: each round's derivatives at its end
-                    // point (its gates act on disjoint pairs and commute), then
-                    // the un-apply, then the reductions
-                    float gt[2], gp[2];
-                    grad_fsim<float, NB, 1, 2>(la, ps, gt[0], gp[0]);
-                    if constexpr (QR > 4) grad_fsim<float, NB, (QR > 4 ? 3 : 0), (QR > 4 ? 4 : 1)>(la, ps, gt[1], gp[1]);
-                    ps = q_fs_round_b<true, QR>(ps, C.c);
-                    la = q_fs_round_b<true, QR>(la, C.c);
-                    q_red_fs<(QR > 4 ? 2 : 1)>(red, S.sy + 2, nwaves, wave, lane, gt, gp);
-                    grad_fsim<float, NB, 0, 1>(la, ps, gt[0], gp[0]);
-                    grad_fsim<float, NB, 2, 3>(la, ps, gt[1], gp[1]);
-                    ps = q_fs_round_a<true, QR>(ps, C.c);
-                    la = q_fs_round_a<true, QR>(la, C.c);
+                    // round B, then round A, gate by gate (the gates of a round
+                    // act on disjoint pairs and commute, so each one's derivative
+                    // is taken just before it is un-applied); absent gates skipped
+                    float gt[4], gp[4];
+                    if (S.ry[2] >= 0) fs_unapply<QR, 1, 2>(ps, la, C.c + 8, gt[2], gp[2]);
+                    if constexpr (QR > 4)
+                        if (S.ry[3] >= 0) fs_unapply<QR, (QR > 4 ? 3 : 0), (QR > 4 ? 4 : 1)>(ps, la, C.c + 12, gt[3], gp[3]);
+                    q_red_fs<(QR > 4 ? 2 : 1)>(red, S.sy + 2, nwaves, wave, lane, gt + 2, gp + 2);
+                    if (S.ry[0] >= 0) fs_unapply<QR, 0, 1>(ps, la, C.c, gt[0], gp[0]);
+                    if (S.ry[1] >= 0) fs_unapply<QR, 2, 3>(ps, la, C.c + 4, gt[1], gp[1]);
                     q_red_fs<2>(red, S.sy, nwaves, wave, lane, gt, gp);
                     continue;
                 }
