@@ -1037,9 +1037,15 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl,
             const int s_end = F->step_end;
             for (int s = F->step_begin; s < s_end; ++s) {
                 const QCoef C = coef[s];
-                if constexpr (FS) {
-                    a = q_fs_round_a<false, QR>(a, C.c);
-                    a = q_fs_round_b<false, QR>(a, C.c);
+                if constexpr (FS) {   // absent gates skipped
+                    const QStep S = as_const(J.qsteps)[s];
+                    if (S.ry[0] >= 0) a = app_fsim<float, (1 << QR), 0, 1>(a, C.c[0], C.c[1], cx<float>{C.c[2], C.c[3]});
+                    if (S.ry[1] >= 0) a = app_fsim<float, (1 << QR), 2, 3>(a, C.c[4], C.c[5], cx<float>{C.c[6], C.c[7]});
+                    if (S.ry[2] >= 0) a = app_fsim<float, (1 << QR), 1, 2>(a, C.c[8], C.c[9], cx<float>{C.c[10], C.c[11]});
+                    if constexpr (QR > 4)
+                        if (S.ry[3] >= 0)
+                            a = app_fsim<float, (1 << QR), (QR > 4 ? 3 : 0), (QR > 4 ? 4 : 1)>(a, C.c[12], C.c[13],
+                                                                                          cx<float>{C.c[14], C.c[15]});
                 } else {
                     a = q_ry_round<false, QR>(a, C.c);
                     a = q_rz_round<false, QR>(a, C.c);
