@@ -55,18 +55,20 @@ KERNEL_SOURCES = {
     "plain": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_plain.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.6076e+09, "d7072ed679cc66aa"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.2981e+09, "d7072ed679cc66aa"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.7866e+09, "66d1390ee27fbd6c"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.2964e+09, "66d1390ee27fbd6c"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6865e+10, "66d1390ee27fbd6c"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0970e+08, "66d1390ee27fbd6c"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4651e+08, "66d1390ee27fbd6c"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7451e+08, "66d1390ee27fbd6c"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2843e+08, "66d1390ee27fbd6c"),
-    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5149e+10, "66d1390ee27fbd6c"),
-    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "68bfec6c64405833"),
-    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7187e+10, "d029f66455d0abfb"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.6047e+09, "38c831912626873b"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.2952e+09, "38c831912626873b"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.7868e+09, "c843121236b420f2"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.2963e+09, "c843121236b420f2"),
+    ("fsim_brickwork_n32_d20_tfim2d", "rev_tile"): (1.3745e+11, "38c831912626873b"),
+    ("fsim_brickwork_n32_d20_tfim2d", "fwd_tile"): (6.8719e+10, "38c831912626873b"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6865e+10, "c843121236b420f2"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0972e+08, "c843121236b420f2"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4650e+08, "c843121236b420f2"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7451e+08, "c843121236b420f2"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2844e+08, "c843121236b420f2"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5149e+10, "c843121236b420f2"),
+    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "02c6a18ba3a6bfbf"),
+    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7186e+10, "15da485875e46faa"),
 }
 
 
