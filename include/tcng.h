@@ -181,13 +181,15 @@ tcng_status tcng_circuit_get_config(const tcng_circuit* c, int32_t dtype, int32_
 /* The mode TCNG_MODE_AUTO runs for this circuit and dtype (after tuning, or
  * the default), resolved to the plan that exists (never TCNG_MODE_AUTO). */
 tcng_status tcng_circuit_get_mode(const tcng_circuit* c, int32_t dtype, int32_t* mode);
-/* Rotation rounds: a circuit whose gates are all RY, RZ and CNOT runs its
- * complex64 tiled passes (TCNG_MODE_TILED, and the tiled candidates of the
- * autotuner) as fixed rounds of rotations on 5 register bits per phase, with
- * each phase's CNOTs applied as a permutation of the tile's local index
- * (the paper's operator fusion of the "Foundations Recap" section, done on
- * the vector units).  *phases = the number of such phases of the current
- * plan, 0 when the circuit or dtype does not take this path. */
+/* Rounds: a complex64 tiled pass (TCNG_MODE_TILED, and the tiled candidates
+ * of the autotuner) whose gates are all RY, RZ and CNOT runs as fixed rounds
+ * of rotations on 5 register bits per phase, with each phase's CNOTs applied
+ * as a permutation of the tile's local index; one whose gates are all fSim
+ * and Hadamard runs as fixed rounds of fSim gates on register-bit pairs (the
+ * paper's operator fusion of the "Foundations Recap" section, done on the
+ * vector units).  Other passes of the same circuit run the generic tiled
+ * kernels.  *phases = the number of round phases of the current forward
+ * plan, 0 when no pass of the circuit or dtype takes this path. */
 tcng_status tcng_circuit_rounds(const tcng_circuit* c, int32_t dtype, int32_t* phases);
 
 /* Autotuner (the find-then-execute search of contraction strategies, Sec.
