@@ -397,10 +397,11 @@ WsLayout layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int dtype
     } else if (c) {
         if (tiled) {
             L.opm_bytes = size_t(batch) * c->gates.size() * 16 * (dtype == TCNG_C64 ? 8 : 16);
-            // rotation rounds: their coefficient blocks follow the members' matrix tables
+            // rounds: their coefficient blocks follow the members' matrix tables
             const CircuitPlan& H = c->tiled[dtype].host;
-            if (dtype == TCNG_C64 && H.rounds)
-                L.opm_bytes += size_t(batch) * rounds_coef_bytes(int(H.qsteps.size() + H.qrsteps.size()));
+            const int qs = int(H.qsteps.size() + H.qrsteps.size());
+            if (H.rounds)
+                L.opm_bytes += size_t(batch) * (dtype == TCNG_C64 ? rounds_coef_bytes<float>(qs) : rounds_coef_bytes<double>(qs));
         }
         L.total_slots = tiled ? c->tiled[dtype].host.total_slots : c->plain.total;
         L.rev_wgs = tiled ? rev_wgs_tiled(n, c->tiled[dtype].host.cfg.m_max, batch) : rev_wgs_plain(n, batch);
@@ -439,9 +440,9 @@ WsLayout grad_layout(const tcng_circuit* c, const tcng_pauli_sum* h, int n, int 
     return L;
 }
 
-// byte offset of the rotation rounds' coefficient blocks inside the op table
-size_t rounds_coef_offset(const tcng_circuit* c, int64_t batch) {
-    return size_t(batch) * c->gates.size() * 16 * sizeof(cx<float>);
+// byte offset of the rounds' coefficient blocks inside the op table
+size_t rounds_coef_offset(const tcng_circuit* c, int64_t batch, int dt) {
+    return size_t(batch) * c->gates.size() * 16 * (dt == TCNG_C64 ? sizeof(cx<float>) : sizeof(cx<double>));
 }
 
 // op matrix entries for the tiled passes (once per evaluation)
@@ -451,10 +452,10 @@ tcng_status build_ops(const tcng_circuit* c, const void* params, int64_t batch, 
     DevPlan dp{P.passes, P.phases, P.ops};
     PROF_TRY(F_FINISH, launch_build_ops<R>(dp, int(P.host.ops.size()), params, c->n_params, c->cm[dt], batch, opm, st));
     // (the forward plan lists every gate exactly once: the table is indexed by gate)
-    if (dt == TCNG_C64 && P.host.rounds)
-        PROF_TRY(F_FINISH, launch_rounds_coef(P.qsteps, int(P.host.qsteps.size()), P.qrsteps,
+    if (P.host.rounds)
+        PROF_TRY(F_FINISH, launch_rounds_coef<R>(P.qsteps, int(P.host.qsteps.size()), P.qrsteps,
                                               int(P.host.qrsteps.size()), opm, int(c->gates.size()), batch,
-                                              static_cast<char*>(opm) + rounds_coef_offset(c, batch), st));
+                                              static_cast<char*>(opm) + rounds_coef_offset(c, batch, dt), st));
     return TCNG_OK;
 }
 
@@ -471,14 +472,14 @@ Job make_job(const tcng_circuit* c, const tcng_pauli_sum* h, const tcng_state* s
         J.rpasses = P.rpasses;
         J.rphases = P.rphases;
         J.rops = P.rops;
-        if (dt == TCNG_C64 && P.host.rounds) {
+        if (P.host.rounds) {
             J.qpasses = P.qpasses;
             J.qphases = P.qphases;
             J.qsteps = P.qsteps;
             J.qrpasses = P.qrpasses;
             J.qrphases = P.qrphases;
             J.qrsteps = P.qrsteps;
-            J.qcoef = opm ? static_cast<const char*>(opm) + rounds_coef_offset(c, s->batch) : nullptr;
+            J.qcoef = opm ? static_cast<const char*>(opm) + rounds_coef_offset(c, s->batch, dt) : nullptr;
             J.qsteps_fwd = int32_t(P.host.qsteps.size());
             J.qsteps_all = int32_t(P.host.qsteps.size() + P.host.qrsteps.size());
         }
@@ -536,7 +537,7 @@ tcng_status run_forward(const tcng_circuit* c, const void* params, const tcng_st
             if (qk != QK_GENERIC) {
                 // a few tiles per workgroup, so each fetch overlaps a tile's phases
                 const int wgs = int(std::min<int64_t>(J.tiles, std::max<int64_t>(1, 2048 / J.batch)));
-                PROF_TRY(F_FWD_TILE, launch_rounds_fwd(jl, J, rb, qk == QK_FSIM, wgs, int64_t(wgs) * J.batch,
+                PROF_TRY(F_FWD_TILE, launch_rounds_fwd<R>(jl, J, rb, qk == QK_FSIM, wgs, int64_t(wgs) * J.batch,
                                                        1 << (m - rb), st));
             }
             else if (rb == RB)
@@ -604,7 +605,7 @@ tcng_status run_reverse(const tcng_circuit* c, const void* params, const tcng_st
             const int64_t blocks = int64_t(J.wgs) * J.batch;
             const int qk = (J.qrpasses && J.qcoef) ? P.host.qrpasses[np - 1 - k].kind : QK_GENERIC;
             if (qk != QK_GENERIC)
-                PROF_TRY(F_REV_TILE, launch_rounds_rev(jl, J, rb, qk == QK_FSIM, blocks, 1 << (m - rb), st));
+                PROF_TRY(F_REV_TILE, launch_rounds_rev<R>(jl, J, rb, qk == QK_FSIM, blocks, 1 << (m - rb), st));
             else if (rb == RB)
                 PROF_TRY(F_REV_TILE, (launch_tile_rev<R, RB>(jl, J, blocks, 1 << (m - RB), st)));
             else
@@ -2121,7 +2122,7 @@ tcng_status tcng_circuit_rounds(const tcng_circuit* c, int32_t dtype, int32_t* p
     if (!c || !phases) return fail(TCNG_E_INVALID, "null argument");
     if (dtype != TCNG_C64 && dtype != TCNG_C128) return fail(TCNG_E_INVALID, "bad dtype");
     const DevCircuitPlan& P = c->tiled[dtype];
-    *phases = (dtype == TCNG_C64 && P.valid && P.host.rounds) ? int32_t(P.host.qphases.size()) : 0;
+    *phases = (P.valid && P.host.rounds) ? int32_t(P.host.qphases.size()) : 0;
     return ok();
 }
 

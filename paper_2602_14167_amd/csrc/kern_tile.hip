@@ -708,7 +708,7 @@ k_tile_rev(const JobList jl, const Job single) {
 }
 
 // ---------------------------------------------------------------------------
-// rotation rounds (complex64, QR = 4 or 5 register bits; see QPhase)
+// rounds (complex64: QR = 4 or 5 register bits; complex128: QR = 3 or 4; see QPhase)
 // ---------------------------------------------------------------------------
 // `pin` passes a value through an empty asm statement: the compiler cannot
 // hoist what is computed from it out of the loop it sits in, nor share it
@@ -725,8 +725,17 @@ __device__ __forceinline__ uint32_t pin(uint32_t v) {
     return v;
 }
 
-template <int QR>
-using QBlk = Regs<float, (1 << QR)>;
+template <typename R, int QR>
+using QBlk = Regs<R, (1 << QR)>;
+
+// register bit B of a block of QR bits, clamped for the branches that only
+// blocks of more than B bits take
+template <int B, int QR>
+constexpr int qb() { return B < QR ? B : 0; }
+
+// tile bits of the rounds kernels (64 KiB of LDS): 13 (complex64), 12 (complex128)
+template <typename R>
+constexpr int q_tile_bits() { return sizeof(R) == 4 ? 13 : 12; }
 
 // a phase's register map: the thread's part of the local index, and the LDS
 // positions of its registers with and without the phase's permutation C
@@ -774,17 +783,17 @@ __device__ __forceinline__ uint32_t qaddr(const QMap<QR>& q, int j) {
 
 // (each call forms its addresses anew: shared between calls, the compiler
 // keeps them all live in registers across the sweep)
-template <bool MAPPED, int QR>
-__device__ __forceinline__ QBlk<QR> q_read(const cx<float>* lds, QMap<QR> q) {
+template <bool MAPPED, typename R, int QR>
+__device__ __forceinline__ QBlk<R, QR> q_read(const cx<R>* lds, QMap<QR> q) {
     q.tsw = pin(q.tsw);
     q.ctsw = pin(q.ctsw);
-    QBlk<QR> a;
+    QBlk<R, QR> a;
 #pragma unroll
     for (int j = 0; j < (1 << QR); ++j) a.v[j] = lds[qaddr<MAPPED>(q, j)];
     return a;
 }
-template <bool MAPPED, int QR>
-__device__ __forceinline__ void q_write(cx<float>* lds, const QBlk<QR>& a, QMap<QR> q) {
+template <bool MAPPED, typename R, int QR>
+__device__ __forceinline__ void q_write(cx<R>* lds, const QBlk<R, QR>& a, QMap<QR> q) {
     q.tsw = pin(q.tsw);
     q.ctsw = pin(q.ctsw);
 #pragma unroll
@@ -798,26 +807,26 @@ __device__ __forceinline__ void q_write(cx<float>* lds, const QBlk<QR>& a, QMap<
 // loads instead of one round trip per gate.
 constexpr int QCOEF = 24;
 
-template <bool INV, int QR>
-__device__ __forceinline__ QBlk<QR> q_ry_round(QBlk<QR> a, const float* c) {
+template <bool INV, int QR, typename R>
+__device__ __forceinline__ QBlk<R, QR> q_ry_round(QBlk<R, QR> a, const R* c) {
     constexpr int NB = 1 << QR;
-    const float sg = INV ? -1.f : 1.f;
-    a = app_ry_lift<float, NB, 0>(a, Lift<float>{sg * c[0], sg * c[5]});
-    a = app_ry_lift<float, NB, 1>(a, Lift<float>{sg * c[1], sg * c[6]});
-    a = app_ry_lift<float, NB, 2>(a, Lift<float>{sg * c[2], sg * c[7]});
-    a = app_ry_lift<float, NB, 3>(a, Lift<float>{sg * c[3], sg * c[8]});
-    if constexpr (QR > 4) a = app_ry_lift<float, NB, 4>(a, Lift<float>{sg * c[4], sg * c[9]});
+    const R sg = INV ? R(-1) : R(1);
+    a = app_ry_lift<R, NB, 0>(a, Lift<R>{sg * c[0], sg * c[5]});
+    a = app_ry_lift<R, NB, 1>(a, Lift<R>{sg * c[1], sg * c[6]});
+    a = app_ry_lift<R, NB, 2>(a, Lift<R>{sg * c[2], sg * c[7]});
+    if constexpr (QR > 3) a = app_ry_lift<R, NB, qb<3, QR>()>(a, Lift<R>{sg * c[3], sg * c[8]});
+    if constexpr (QR > 4) a = app_ry_lift<R, NB, qb<4, QR>()>(a, Lift<R>{sg * c[4], sg * c[9]});
     return a;
 }
-template <bool INV, int QR>
-__device__ __forceinline__ QBlk<QR> q_rz_round(QBlk<QR> a, const float* c) {
+template <bool INV, int QR, typename R>
+__device__ __forceinline__ QBlk<R, QR> q_rz_round(QBlk<R, QR> a, const R* c) {
     constexpr int NB = 1 << QR;
-    const float sg = INV ? -1.f : 1.f;
-    a = app_rz_lift<float, NB, 0>(a, Lift<float>{sg * c[10], sg * c[15]});
-    a = app_rz_lift<float, NB, 1>(a, Lift<float>{sg * c[11], sg * c[16]});
-    a = app_rz_lift<float, NB, 2>(a, Lift<float>{sg * c[12], sg * c[17]});
-    a = app_rz_lift<float, NB, 3>(a, Lift<float>{sg * c[13], sg * c[18]});
-    if constexpr (QR > 4) a = app_rz_lift<float, NB, 4>(a, Lift<float>{sg * c[14], sg * c[19]});
+    const R sg = INV ? R(-1) : R(1);
+    a = app_rz_lift<R, NB, 0>(a, Lift<R>{sg * c[10], sg * c[15]});
+    a = app_rz_lift<R, NB, 1>(a, Lift<R>{sg * c[11], sg * c[16]});
+    a = app_rz_lift<R, NB, 2>(a, Lift<R>{sg * c[12], sg * c[17]});
+    if constexpr (QR > 3) a = app_rz_lift<R, NB, qb<3, QR>()>(a, Lift<R>{sg * c[13], sg * c[18]});
+    if constexpr (QR > 4) a = app_rz_lift<R, NB, qb<4, QR>()>(a, Lift<R>{sg * c[14], sg * c[19]});
     return a;
 }
 
@@ -825,79 +834,85 @@ __device__ __forceinline__ QBlk<QR> q_rz_round(QBlk<QR> a, const float* c) {
 // in c[4k .. 4k + 3] (an absent gate: 1, 0, 1, 0, the identity); the inverse
 // negates sin t and Im e^{-ip}.  Round A: slots 0, 1 on register bits (0,1),
 // (2,3); round B: slots 2, 3 on (1,2), (3,4).
-template <bool INV, int QR>
-__device__ __forceinline__ QBlk<QR> q_fs_round_a(QBlk<QR> a, const float* c) {
+template <bool INV, int QR, typename R>
+__device__ __forceinline__ QBlk<R, QR> q_fs_round_a(QBlk<R, QR> a, const R* c) {
     constexpr int NB = 1 << QR;
-    const float sg = INV ? -1.f : 1.f;
-    a = app_fsim<float, NB, 0, 1>(a, c[0], sg * c[1], cx<float>{c[2], sg * c[3]});
-    a = app_fsim<float, NB, 2, 3>(a, c[4], sg * c[5], cx<float>{c[6], sg * c[7]});
+    const R sg = INV ? R(-1) : R(1);
+    a = app_fsim<R, NB, 0, 1>(a, c[0], sg * c[1], cx<R>{c[2], sg * c[3]});
+    if constexpr (QR > 3) a = app_fsim<R, NB, 2, qb<3, QR>()>(a, c[4], sg * c[5], cx<R>{c[6], sg * c[7]});
     return a;
 }
-template <bool INV, int QR>
-__device__ __forceinline__ QBlk<QR> q_fs_round_b(QBlk<QR> a, const float* c) {
+template <bool INV, int QR, typename R>
+__device__ __forceinline__ QBlk<R, QR> q_fs_round_b(QBlk<R, QR> a, const R* c) {
     constexpr int NB = 1 << QR;
-    const float sg = INV ? -1.f : 1.f;
-    a = app_fsim<float, NB, 1, 2>(a, c[8], sg * c[9], cx<float>{c[10], sg * c[11]});
-    if constexpr (QR > 4) a = app_fsim<float, NB, 3, 4>(a, c[12], sg * c[13], cx<float>{c[14], sg * c[15]});
+    const R sg = INV ? R(-1) : R(1);
+    a = app_fsim<R, NB, 1, 2>(a, c[8], sg * c[9], cx<R>{c[10], sg * c[11]});
+    if constexpr (QR > 4) a = app_fsim<R, NB, qb<3, QR>(), qb<4, QR>()>(a, c[12], sg * c[13], cx<R>{c[14], sg * c[15]});
     return a;
 }
 
 // reverse sweep, one fSim gate on register bits (B0, B1): its (theta, phi)
 // derivative partials at the current point, then the inverse on psi and lambda
-template <int QR, int B0, int B1>
-__device__ __forceinline__ void fs_unapply(QBlk<QR>& ps, QBlk<QR>& la, const float* c, float& gt, float& gp) {
+template <int QR, int B0, int B1, typename R, typename CP>
+__device__ __forceinline__ void fs_unapply(QBlk<R, QR>& ps, QBlk<R, QR>& la, CP c, R& gt, R& gp) {
     constexpr int NB = 1 << QR;
-    grad_fsim<float, NB, B0, B1>(la, ps, gt, gp);
-    ps = app_fsim<float, NB, B0, B1>(ps, c[0], -c[1], cx<float>{c[2], -c[3]});
-    la = app_fsim<float, NB, B0, B1>(la, c[0], -c[1], cx<float>{c[2], -c[3]});
+    grad_fsim<R, NB, B0, B1>(la, ps, gt, gp);
+    ps = app_fsim<R, NB, B0, B1>(ps, c[0], -c[1], cx<R>{c[2], -c[3]});
+    la = app_fsim<R, NB, B0, B1>(la, c[0], -c[1], cx<R>{c[2], -c[3]});
 }
 
 // Hadamard on the register bits set in mask (uniform), the others unchanged
-template <int QR>
-__device__ __forceinline__ QBlk<QR> q_h_round(QBlk<QR> a, uint32_t mask) {
+template <int QR, typename R>
+__device__ __forceinline__ QBlk<R, QR> q_h_round(QBlk<R, QR> a, uint32_t mask) {
     constexpr int NB = 1 << QR;
-    const float r = 0.70710678118654752f;
+    const R r = R(0.70710678118654752440);
 #pragma unroll
     for (int b = 0; b < QR; ++b) {
         const bool on = (mask >> b) & 1;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (j & (1 << b)) continue;
-            const cx<float> x0 = a.v[j], x1 = a.v[j | (1 << b)];
-            const cx<float> y0 = {r * (x0.re + x1.re), r * (x0.im + x1.im)};
-            const cx<float> y1 = {r * (x0.re - x1.re), r * (x0.im - x1.im)};
-            a.v[j] = on ? y0 : x0;
-            a.v[j | (1 << b)] = on ? y1 : x1;
+            const cx<R> x0 = a.v[j], x1 = a.v[j | (1 << b)];
+            const cx<R> y0 = {r * (x0.re + x1.re), r * (x0.im + x1.im)};
+            const cx<R> y1 = {r * (x0.re - x1.re), r * (x0.im - x1.im)};
+            // (per component: a select of whole complex values goes through scratch for double)
+            a.v[j].re = on ? y0.re : x0.re;
+            a.v[j].im = on ? y0.im : x0.im;
+            a.v[j | (1 << b)].re = on ? y1.re : x1.re;
+            a.v[j | (1 << b)].im = on ? y1.im : x1.im;
         }
     }
     return a;
 }
 
+template <typename R>
 struct QCoef {
-    float c[QCOEF];
+    R c[QCOEF];
 };
 
-// tile_load / tile_store of the rotation rounds (complex64, 2^QR amplitudes per
-// thread): element it of thread t is local index (it * nt + t) * 2 (+1)
-// Tile addressing of the rotation rounds.  Element it of thread t is local
-// index it * 2 nt + 2 t (+1): the bits of it are the top QR - 1 local bits, so
-// its global offset is a compile-time sum of their images hb[k] (per pass,
-// uniform), and the thread's part off_t is computed once (and pinned per use).
-
-template <int QR>
+// Tile addressing of the rounds.  A thread's 2^QR amplitudes are VN = 2
+// (complex64) or 1 (complex128) amplitudes per 16-byte access: element it of
+// thread t is local index it * VN nt + VN t (+ k, k < VN).  The bits of it are
+// the top EB = QR - log2(VN) local bits, so its global offset is a
+// compile-time sum of their images hb[k] (per pass, uniform), and the
+// thread's part off_t is computed once (and pinned per use).
+template <typename R, int QR>
 struct QTileAddr {
-    uint64_t hb[QR - 1];   // global offsets of the element-index bits (uniform)
+    static constexpr int VN = V16<R>::N;
+    static constexpr int EB = QR - (VN == 2 ? 1 : 0);
+    uint64_t hb[EB];       // global offsets of the element-index bits (uniform)
     uint64_t off_t;        // the thread's part
-    uint32_t lsw_t;        // swz(2 t)
-    uint32_t lhb[QR - 1];  // swz of the element-index bits (uniform)
+    uint32_t lsw_t;        // swz(VN t)
+    uint32_t lhb[EB];      // swz of the element-index bits (uniform)
 };
 
-template <int QR>
-__device__ __forceinline__ QTileAddr<QR> q_tile_addr(const PassInfo& pi, int t, int nt) {
-    QTileAddr<QR> A;
-    const int b0 = pi.m - (QR - 1);   // first local bit of the element index (2 nt = 2^b0)
+template <typename R, int QR>
+__device__ __forceinline__ QTileAddr<R, QR> q_tile_addr(const PassInfo& pi, int t) {
+    using A_t = QTileAddr<R, QR>;
+    A_t A;
+    const int b0 = pi.m - A_t::EB;   // first local bit of the element index
 #pragma unroll
-    for (int k = 0; k < QR - 1; ++k) {
+    for (int k = 0; k < A_t::EB; ++k) {
         int q = b0 + k;
 #pragma unroll
         for (int i = 0; i < MAX_TILE_BITS; ++i)
@@ -905,26 +920,25 @@ __device__ __forceinline__ QTileAddr<QR> q_tile_addr(const PassInfo& pi, int t, 
         A.hb[k] = uint64_t(1) << q;
         A.lhb[k] = swz(1u << (b0 + k));
     }
-    A.off_t = loc2glob(uint32_t(t * 2), pi.lo, pi.m, pi.lq);
-    A.lsw_t = swz(uint32_t(t * 2));
-    (void)nt;
+    A.off_t = loc2glob(uint32_t(t * A_t::VN), pi.lo, pi.m, pi.lq);
+    A.lsw_t = swz(uint32_t(t * A_t::VN));
     return A;
 }
 
 // (it is a constant once the loops over elements are unrolled: the selects fold)
-template <int QR>
-__device__ __forceinline__ uint64_t q_goff(const QTileAddr<QR>& A, int it) {
+template <typename R, int QR>
+__device__ __forceinline__ uint64_t q_goff(const QTileAddr<R, QR>& A, int it) {
     uint64_t g = 0;
 #pragma unroll
-    for (int k = 0; k < QR - 1; ++k)
+    for (int k = 0; k < QTileAddr<R, QR>::EB; ++k)
         if ((it >> k) & 1) g += A.hb[k];
     return g;
 }
-template <int QR>
-__device__ __forceinline__ uint32_t q_loff(const QTileAddr<QR>& A, int it) {
+template <typename R, int QR>
+__device__ __forceinline__ uint32_t q_loff(const QTileAddr<R, QR>& A, int it) {
     uint32_t a = 0;
 #pragma unroll
-    for (int k = 0; k < QR - 1; ++k)
+    for (int k = 0; k < QTileAddr<R, QR>::EB; ++k)
         if ((it >> k) & 1) a ^= A.lhb[k];
     return a;
 }
@@ -932,63 +946,68 @@ __device__ __forceinline__ uint32_t q_loff(const QTileAddr<QR>& A, int it) {
 // HBM -> registers (the loads stay in flight until the registers are used)
 // and registers -> LDS, separately, so that a tile can be fetched while
 // another one is processed
-template <int QR>
+template <typename R, int QR>
 struct QTileRegs {
-    cx<float> v[1 << QR];
+    cx<R> v[1 << QR];
 };
 
-template <int QR>
-__device__ __forceinline__ QTileRegs<QR> q_tile_fetch(gptr<const cx<float>> psi, uint64_t base,
-                                                      const QTileAddr<QR>& A) {
-    const gptr<const cx<float>> p = psi + pin(A.off_t);
-    QTileRegs<QR> r;
+template <typename R, int QR>
+__device__ __forceinline__ QTileRegs<R, QR> q_tile_fetch(gptr<const cx<R>> psi, uint64_t base,
+                                                         const QTileAddr<R, QR>& A) {
+    constexpr int VN = V16<R>::N;
+    const gptr<const cx<R>> p = psi + pin(A.off_t);
+    QTileRegs<R, QR> r;
 #pragma unroll
-    for (int it = 0; it < (1 << QR) / 2; ++it) V16<float>::load(p + (base + q_goff<QR>(A, it)), &r.v[it * 2]);
+    for (int it = 0; it < (1 << QR) / VN; ++it) V16<R>::load(p + (base + q_goff<R, QR>(A, it)), &r.v[it * VN]);
     return r;
 }
 
-template <int QR>
-__device__ __forceinline__ void q_tile_put(cx<float>* lds, const QTileRegs<QR>& r, const QTileAddr<QR>& A) {
+// (swz leaves bit 0 alone: the VN amplitudes of an access stay adjacent)
+template <typename R, int QR>
+__device__ __forceinline__ void q_tile_put(cx<R>* lds, const QTileRegs<R, QR>& r, const QTileAddr<R, QR>& A) {
+    constexpr int VN = V16<R>::N;
     const uint32_t lt = pin(A.lsw_t);
 #pragma unroll
-    for (int it = 0; it < (1 << QR) / 2; ++it) {
-        const uint32_t e = lt ^ q_loff<QR>(A, it);
-        lds[e] = r.v[it * 2];
-        lds[e ^ swz(1u)] = r.v[it * 2 + 1];
+    for (int it = 0; it < (1 << QR) / VN; ++it) {
+        const uint32_t e = lt ^ q_loff<R, QR>(A, it);
+#pragma unroll
+        for (int k = 0; k < VN; ++k) lds[e ^ uint32_t(k)] = r.v[it * VN + k];
     }
 }
 
-template <int QR>
-__device__ __forceinline__ void q_tile_store(const cx<float>* lds, gptr<cx<float>> psi, uint64_t base,
-                                             const QTileAddr<QR>& A, bool flip) {
-    const gptr<cx<float>> p = psi + pin(A.off_t);
+template <typename R, int QR>
+__device__ __forceinline__ void q_tile_store(const cx<R>* lds, gptr<cx<R>> psi, uint64_t base,
+                                             const QTileAddr<R, QR>& A, bool flip) {
+    constexpr int VN = V16<R>::N;
+    const gptr<cx<R>> p = psi + pin(A.off_t);
     const uint32_t lt = pin(A.lsw_t);
-    const float sg = flip ? -1.f : 1.f;
+    const R sg = flip ? R(-1) : R(1);
 #pragma unroll
-    for (int it = 0; it < (1 << QR) / 2; ++it) {
-        const uint32_t e = lt ^ q_loff<QR>(A, it);
-        cx<float> v[2] = {lds[e], lds[e ^ swz(1u)]};
-        if (flip) {
-            v[0] = {sg * v[0].re, sg * v[0].im};
-            v[1] = {sg * v[1].re, sg * v[1].im};
+    for (int it = 0; it < (1 << QR) / VN; ++it) {
+        const uint32_t e = lt ^ q_loff<R, QR>(A, it);
+        cx<R> v[VN];
+#pragma unroll
+        for (int k = 0; k < VN; ++k) {
+            v[k] = lds[e ^ uint32_t(k)];
+            if (flip) v[k] = {sg * v[k].re, sg * v[k].im};
         }
-        V16<float>::store(p + (base + q_goff<QR>(A, it)), v);
+        V16<R>::store(p + (base + q_goff<R, QR>(A, it)), v);
     }
 }
 
 // a round's derivative partials into their slots (absent gates have none)
-template <int QR>
+template <int QR, typename R>
 __device__ __forceinline__ void q_red(double* red, const int32_t* slot, int nwaves, int wave, int lane,
-                                      const float* g) {
+                                      const R* g) {
 #pragma unroll
     for (int i = 0; i < QR; ++i)
         if (slot[i] >= 0) red_add(red, slot[i] * nwaves + wave, g[i], lane);
 }
 
 // an fSim round's (theta, phi) partials into their slots (slot, slot + 1)
-template <int NS>
+template <int NS, typename R>
 __device__ __forceinline__ void q_red_fs(double* red, const int32_t* slot, int nwaves, int wave, int lane,
-                                         const float* gt, const float* gp) {
+                                         const R* gt, const R* gp) {
 #pragma unroll
     for (int i = 0; i < NS; ++i)
         if (slot[i] >= 0) {
@@ -999,9 +1018,10 @@ __device__ __forceinline__ void q_red_fs(double* red, const int32_t* slot, int n
 
 // forward: `wgs` workgroups per member loop over the tiles; the next tile's
 // loads are in flight while the current tile's phases run
-template <int QR, bool FS>
-__global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl, const Job single, int wgs) {
-    __shared__ cx<float> lds[Tile<float>::ELEMS];
+template <typename R, int QR, bool FS>
+__global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_fwd(const JobList jl, const Job single,
+                                                                           int wgs) {
+    __shared__ cx<R> lds[Tile<R>::ELEMS];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     cptr<Pass> P = as_const(J.passes) + jl.step;
@@ -1012,62 +1032,64 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_fwd(const JobList jl,
     const int t = threadIdx.x;
     const int64_t b = local / wgs;
     const int wg = int(local - b * wgs);
-    gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
+    gptr<cx<R>> psi = as_global(static_cast<cx<R>*>(J.state)) + b * J.stride;
     cptr<QPhase> phases = as_const(J.qphases);
-    cptr<QCoef> coef = as_const(reinterpret_cast<const QCoef*>(J.qcoef)) + size_t(b) * J.qsteps_all;
+    cptr<QCoef<R>> coef = as_const(reinterpret_cast<const QCoef<R>*>(J.qcoef)) + size_t(b) * J.qsteps_all;
 
-    const QTileAddr<QR> A = q_tile_addr<QR>(pi, t, nt);
-    QTileRegs<QR> nx;
-    if (wg < J.tiles) nx = q_tile_fetch<QR>(psi, tile_base(uint64_t(wg), pi.tmask, J.n), A);
+    const QTileAddr<R, QR> A = q_tile_addr<R, QR>(pi, t);
+    QTileRegs<R, QR> nx;
+    if (wg < J.tiles) nx = q_tile_fetch<R, QR>(psi, tile_base(uint64_t(wg), pi.tmask, J.n), A);
     for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), pi.tmask, J.n);
         __syncthreads();   // the previous tile's stores have read the LDS
-        q_tile_put<QR>(lds, nx, A);
-        if (tile + wgs < J.tiles) nx = q_tile_fetch<QR>(psi, tile_base(uint64_t(tile + wgs), pi.tmask, J.n), A);
+        q_tile_put<R, QR>(lds, nx, A);
+        if (tile + wgs < J.tiles) nx = q_tile_fetch<R, QR>(psi, tile_base(uint64_t(tile + wgs), pi.tmask, J.n), A);
         __syncthreads();
         bool flip = false;
         for (int f = Q.phase_begin; f < Q.phase_end; ++f) {
             cptr<QPhase> F = phases + f;
             const QMap<QR> q = qmap<QR>(F, t, pi.m);
-            QBlk<QR> a = q_read<false>(lds, q);
+            QBlk<R, QR> a = q_read<false>(lds, q);
             if constexpr (FS) {
                 const uint32_t hm = uint32_t(F->hmask);
                 if (hm) a = q_h_round<QR>(a, hm);
             }
             const int s_end = F->step_end;
             for (int s = F->step_begin; s < s_end; ++s) {
-                const QCoef C = coef[s];
-                if constexpr (FS) {   // absent gates skipped
+                if constexpr (FS) {   // absent gates skipped; coefficients read in place
                     const QStep S = as_const(J.qsteps)[s];
-                    if (S.ry[0] >= 0) a = app_fsim<float, (1 << QR), 0, 1>(a, C.c[0], C.c[1], cx<float>{C.c[2], C.c[3]});
-                    if (S.ry[1] >= 0) a = app_fsim<float, (1 << QR), 2, 3>(a, C.c[4], C.c[5], cx<float>{C.c[6], C.c[7]});
-                    if (S.ry[2] >= 0) a = app_fsim<float, (1 << QR), 1, 2>(a, C.c[8], C.c[9], cx<float>{C.c[10], C.c[11]});
+                    cptr<R> c = &coef[s].c[0];
+                    if (S.ry[0] >= 0) a = app_fsim<R, (1 << QR), 0, 1>(a, c[0], c[1], cx<R>{c[2], c[3]});
+                    if constexpr (QR > 3)
+                        if (S.ry[1] >= 0)
+                            a = app_fsim<R, (1 << QR), 2, qb<3, QR>()>(a, c[4], c[5], cx<R>{c[6], c[7]});
+                    if (S.ry[2] >= 0) a = app_fsim<R, (1 << QR), 1, 2>(a, c[8], c[9], cx<R>{c[10], c[11]});
                     if constexpr (QR > 4)
                         if (S.ry[3] >= 0)
-                            a = app_fsim<float, (1 << QR), (QR > 4 ? 3 : 0), (QR > 4 ? 4 : 1)>(a, C.c[12], C.c[13],
-                                                                                          cx<float>{C.c[14], C.c[15]});
+                            a = app_fsim<R, (1 << QR), qb<3, QR>(), qb<4, QR>()>(a, c[12], c[13], cx<R>{c[14], c[15]});
                 } else {
+                    const QCoef<R> C = coef[s];
                     a = q_ry_round<false, QR>(a, C.c);
                     a = q_rz_round<false, QR>(a, C.c);
-                    flip = flip != (C.c[20] < 0.f);
+                    flip = flip != (C.c[20] < R(0));
                 }
             }
             __syncthreads();   // the write permutes positions: every read first
             q_write<!FS>(lds, a, q);
             __syncthreads();
         }
-        q_tile_store<QR>(lds, psi, base, A, flip);
+        q_tile_store<R, QR>(lds, psi, base, A, flip);
     }
 }
 
 // reverse: phases and steps backwards; each phase reads through C, un-applies
 // its rounds (derivatives first: every rotation of a round at the round's
 // end point, where all of them commute) and writes without C
-template <int QR, bool FS>
-__global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl, const Job single) {
+template <typename R, int QR, bool FS>
+__global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_rev(const JobList jl, const Job single) {
     constexpr int NB = 1 << QR;
-    __shared__ cx<float> lds[Tile<float>::ELEMS];
-    __shared__ double red[RED_SLOTS * ((1 << (13 - QR)) / 64)];
+    __shared__ cx<R> lds[Tile<R>::ELEMS];
+    __shared__ double red[RED_SLOTS * ((1 << (q_tile_bits<R>() - QR)) / 64)];
     int64_t local;
     const Job J = load_job(jl, single, blockIdx.x, local);
     const int pidx = J.n_passes - 1 - jl.step;
@@ -1081,33 +1103,33 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
     const int wgs = J.wgs;
     const int64_t b = local / wgs;
     const int wg = int(local - b * wgs);
-    gptr<cx<float>> psi = as_global(static_cast<cx<float>*>(J.state)) + b * J.stride;
-    gptr<cx<float>> lam = as_global(static_cast<cx<float>*>(J.costate)) + b * J.stride;
+    gptr<cx<R>> psi = as_global(static_cast<cx<R>*>(J.state)) + b * J.stride;
+    gptr<cx<R>> lam = as_global(static_cast<cx<R>*>(J.costate)) + b * J.stride;
     cptr<QPhase> phases = as_const(J.qrphases);
     cptr<QStep> steps = as_const(J.qrsteps);
-    cptr<QCoef> coef = as_const(reinterpret_cast<const QCoef*>(J.qcoef)) + size_t(b) * J.qsteps_all + J.qsteps_fwd;
+    cptr<QCoef<R>> coef = as_const(reinterpret_cast<const QCoef<R>*>(J.qcoef)) + size_t(b) * J.qsteps_all + J.qsteps_fwd;
     const int nslots = P->n_slots;
 
     for (int i = t; i < nslots * nwaves; i += blockDim.x) red[i] = 0.0;
     // (the first __syncthreads below orders these writes before any accumulation)
-    const QTileAddr<QR> A = q_tile_addr<QR>(pi, t, nt);
+    const QTileAddr<R, QR> A = q_tile_addr<R, QR>(pi, t);
 
     for (int64_t tile = wg; tile < J.tiles; tile += wgs) {
         const uint64_t base = tile_base(uint64_t(tile), pi.tmask, J.n);
         int f = Q.phase_end - 1;
         QMap<QR> q = qmap<QR>(phases + f, t, pi.m);
-        QBlk<QR> ps, la;
+        QBlk<R, QR> ps, la;
         bool flip = false;   // psi and lambda see the same rotations: one sign for both
         {
             // both states' loads in flight together
-            const QTileRegs<QR> vp = q_tile_fetch<QR>(psi, base, A);
-            const QTileRegs<QR> vl = q_tile_fetch<QR>(lam, base, A);
+            const QTileRegs<R, QR> vp = q_tile_fetch<R, QR>(psi, base, A);
+            const QTileRegs<R, QR> vl = q_tile_fetch<R, QR>(lam, base, A);
             __syncthreads();
-            q_tile_put<QR>(lds, vp, A);
+            q_tile_put<R, QR>(lds, vp, A);
             __syncthreads();
             ps = q_read<!FS>(lds, q);
             __syncthreads();
-            q_tile_put<QR>(lds, vl, A);
+            q_tile_put<R, QR>(lds, vl, A);
             __syncthreads();
             la = q_read<!FS>(lds, q);
         }
@@ -1116,40 +1138,42 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
             const int s_begin = F->step_begin;
             for (int s = F->step_end - 1; s >= s_begin; --s) {
                 const QStep S = steps[s];
-                const QCoef C = coef[s];
                 if constexpr (FS) {
+                    cptr<R> c = &coef[s].c[0];
                     // round B, then round A, gate by gate (the gates of a round
                     // act on disjoint pairs and commute, so each one's derivative
                     // is taken just before it is un-applied); absent gates skipped
-                    float gt[4], gp[4];
-                    if (S.ry[2] >= 0) fs_unapply<QR, 1, 2>(ps, la, C.c + 8, gt[2], gp[2]);
+                    R gt[4], gp[4];
+                    if (S.ry[2] >= 0) fs_unapply<QR, 1, 2>(ps, la, c + 8, gt[2], gp[2]);
                     if constexpr (QR > 4)
-                        if (S.ry[3] >= 0) fs_unapply<QR, (QR > 4 ? 3 : 0), (QR > 4 ? 4 : 1)>(ps, la, C.c + 12, gt[3], gp[3]);
+                        if (S.ry[3] >= 0) fs_unapply<QR, qb<3, QR>(), qb<4, QR>()>(ps, la, c + 12, gt[3], gp[3]);
                     q_red_fs<(QR > 4 ? 2 : 1)>(red, S.sy + 2, nwaves, wave, lane, gt + 2, gp + 2);
-                    if (S.ry[0] >= 0) fs_unapply<QR, 0, 1>(ps, la, C.c, gt[0], gp[0]);
-                    if (S.ry[1] >= 0) fs_unapply<QR, 2, 3>(ps, la, C.c + 4, gt[1], gp[1]);
-                    q_red_fs<2>(red, S.sy, nwaves, wave, lane, gt, gp);
+                    if (S.ry[0] >= 0) fs_unapply<QR, 0, 1>(ps, la, c, gt[0], gp[0]);
+                    if constexpr (QR > 3)
+                        if (S.ry[1] >= 0) fs_unapply<QR, 2, qb<3, QR>()>(ps, la, c + 4, gt[1], gp[1]);
+                    q_red_fs<(QR > 3 ? 2 : 1)>(red, S.sy, nwaves, wave, lane, gt, gp);
                     continue;
                 }
+                const QCoef<R> C = coef[s];
                 // the round's derivatives first, then the un-apply, then their
                 // reductions (which leave the blocks alone)
-                float gz[QR], gy[QR];
-                gz[0] = grad_rz<float, NB, 0>(la, ps);
-                gz[1] = grad_rz<float, NB, 1>(la, ps);
-                gz[2] = grad_rz<float, NB, 2>(la, ps);
-                gz[3] = grad_rz<float, NB, 3>(la, ps);
-                if constexpr (QR > 4) gz[QR - 1] = grad_rz<float, NB, (QR > 4 ? 4 : 0)>(la, ps);
+                R gz[QR], gy[QR];
+                gz[0] = grad_rz<R, NB, 0>(la, ps);
+                gz[1] = grad_rz<R, NB, 1>(la, ps);
+                gz[2] = grad_rz<R, NB, 2>(la, ps);
+                if constexpr (QR > 3) gz[qb<3, QR>()] = grad_rz<R, NB, qb<3, QR>()>(la, ps);
+                if constexpr (QR > 4) gz[qb<4, QR>()] = grad_rz<R, NB, qb<4, QR>()>(la, ps);
                 ps = q_rz_round<true, QR>(ps, C.c);
                 la = q_rz_round<true, QR>(la, C.c);
                 q_red<QR>(red, S.sz, nwaves, wave, lane, gz);
-                gy[0] = grad_rot1<float, NB, 0>(K_RY, la, ps);
-                gy[1] = grad_rot1<float, NB, 1>(K_RY, la, ps);
-                gy[2] = grad_rot1<float, NB, 2>(K_RY, la, ps);
-                gy[3] = grad_rot1<float, NB, 3>(K_RY, la, ps);
-                if constexpr (QR > 4) gy[QR - 1] = grad_rot1<float, NB, (QR > 4 ? 4 : 0)>(K_RY, la, ps);
+                gy[0] = grad_rot1<R, NB, 0>(K_RY, la, ps);
+                gy[1] = grad_rot1<R, NB, 1>(K_RY, la, ps);
+                gy[2] = grad_rot1<R, NB, 2>(K_RY, la, ps);
+                if constexpr (QR > 3) gy[qb<3, QR>()] = grad_rot1<R, NB, qb<3, QR>()>(K_RY, la, ps);
+                if constexpr (QR > 4) gy[qb<4, QR>()] = grad_rot1<R, NB, qb<4, QR>()>(K_RY, la, ps);
                 ps = q_ry_round<true, QR>(ps, C.c);
                 la = q_ry_round<true, QR>(la, C.c);
-                flip = flip != (C.c[20] < 0.f);
+                flip = flip != (C.c[20] < R(0));
                 q_red<QR>(red, S.sy, nwaves, wave, lane, gy);
             }
             if constexpr (FS) {   // the phase's Hadamards (their own inverses) last
@@ -1177,11 +1201,11 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
         __syncthreads();
         q_write<false>(lds, ps, q);
         __syncthreads();
-        q_tile_store<QR>(lds, psi, base, A, flip);
+        q_tile_store<R, QR>(lds, psi, base, A, flip);
         __syncthreads();
         q_write<false>(lds, la, q);
         __syncthreads();
-        q_tile_store<QR>(lds, lam, base, A, flip);
+        q_tile_store<R, QR>(lds, lam, base, A, flip);
     }
     __syncthreads();
     double* part = J.part + size_t(b) * J.total_slots * wgs;
@@ -1194,40 +1218,41 @@ __global__ void __launch_bounds__(1 << (13 - QR)) k_rounds_rev(const JobList jl,
 
 // the shear-coefficient blocks of every (member, step): forward steps, then
 // reverse steps, from the ops' matrix tables (entries 4 and 5 of RY / RZ)
+template <typename R>
 __global__ void k_rounds_coef(const QStep* __restrict__ fsteps, int nf, const QStep* __restrict__ rsteps, int nr,
-                              const cx<float>* __restrict__ opm, int n_gates, int64_t batch, QCoef* __restrict__ out) {
+                              const cx<R>* __restrict__ opm, int n_gates, int64_t batch, QCoef<R>* __restrict__ out) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int per = nf + nr;
     if (i >= int64_t(per) * batch) return;
     const int64_t b = i / per;
     const int s = int(i - b * per);
     const QStep S = s < nf ? fsteps[s] : rsteps[s - nf];
-    const cx<float>* om = opm + size_t(b) * n_gates * 16;
-    QCoef C;
+    const cx<R>* om = opm + size_t(b) * n_gates * 16;
+    QCoef<R> C;
     if (S.kind == QK_FSIM) {   // the fSim matrix: entry 5 = cos t, entry 6 = -i sin t, entry 15 = e^{-ip}
         for (int k = 0; k < 4; ++k) {
             const int g = S.ry[k];
-            C.c[4 * k] = g >= 0 ? om[size_t(g) * 16 + 5].re : 1.f;
-            C.c[4 * k + 1] = g >= 0 ? -om[size_t(g) * 16 + 6].im : 0.f;
-            C.c[4 * k + 2] = g >= 0 ? om[size_t(g) * 16 + 15].re : 1.f;
-            C.c[4 * k + 3] = g >= 0 ? om[size_t(g) * 16 + 15].im : 0.f;
+            C.c[4 * k] = g >= 0 ? om[size_t(g) * 16 + 5].re : R(1);
+            C.c[4 * k + 1] = g >= 0 ? -om[size_t(g) * 16 + 6].im : R(0);
+            C.c[4 * k + 2] = g >= 0 ? om[size_t(g) * 16 + 15].re : R(1);
+            C.c[4 * k + 3] = g >= 0 ? om[size_t(g) * 16 + 15].im : R(0);
         }
-        for (int k = 16; k < QCOEF; ++k) C.c[k] = 0.f;
+        for (int k = 16; k < QCOEF; ++k) C.c[k] = R(0);
         out[i] = C;
         return;
     }
     bool odd = false;
     for (int k = 0; k < QREG; ++k) {
         const int gy = S.ry[k], gz = S.rz[k];
-        C.c[k] = gy >= 0 ? om[size_t(gy) * 16 + 4].re : 0.f;
-        C.c[5 + k] = gy >= 0 ? om[size_t(gy) * 16 + 4].im : 0.f;
-        C.c[10 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].re : 0.f;
-        C.c[15 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].im : 0.f;
-        if (gy >= 0 && om[size_t(gy) * 16 + 5].re < 0.f) odd = !odd;
-        if (gz >= 0 && om[size_t(gz) * 16 + 5].re < 0.f) odd = !odd;
+        C.c[k] = gy >= 0 ? om[size_t(gy) * 16 + 4].re : R(0);
+        C.c[5 + k] = gy >= 0 ? om[size_t(gy) * 16 + 4].im : R(0);
+        C.c[10 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].re : R(0);
+        C.c[15 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].im : R(0);
+        if (gy >= 0 && om[size_t(gy) * 16 + 5].re < R(0)) odd = !odd;
+        if (gz >= 0 && om[size_t(gz) * 16 + 5].re < R(0)) odd = !odd;
     }
-    C.c[20] = odd ? -1.f : 1.f;
-    C.c[21] = C.c[22] = C.c[23] = 0.f;
+    C.c[20] = odd ? R(-1) : R(1);
+    C.c[21] = C.c[22] = C.c[23] = R(0);
     out[i] = C;
 }
 
@@ -1259,42 +1284,74 @@ hipError_t launch_tile_rev(const JobList& jl, const Job& single, int64_t blocks,
 }
 
 // nthreads must be 2^(m - qr) for the launched pass's m (single jobs only)
+template <typename R>
 hipError_t launch_rounds_coef(const QStep* fsteps, int nf, const QStep* rsteps, int nr, const void* opm, int n_gates,
                               int64_t batch, void* out, hipStream_t st) {
     const int64_t work = int64_t(nf + nr) * batch;
     if (work == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rounds_coef, dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, fsteps, nf, rsteps, nr,
-                       static_cast<const cx<float>*>(opm), n_gates, batch, static_cast<QCoef*>(out));
+    hipLaunchKernelGGL((k_rounds_coef<R>), dim3(unsigned((work + 255) / 256)), dim3(256), 0, st, fsteps, nf, rsteps,
+                       nr, static_cast<const cx<R>*>(opm), n_gates, batch, static_cast<QCoef<R>*>(out));
     return hipGetLastError();
 }
 
-size_t rounds_coef_bytes(int steps) { return size_t(steps) * sizeof(QCoef); }
+template <typename R>
+size_t rounds_coef_bytes(int steps) { return size_t(steps) * sizeof(QCoef<R>); }
+
+// register bits per precision: 4 or 5 (complex64), 3 or 4 (complex128)
+template <typename R>
+bool rounds_qr_ok(int qr) { return sizeof(R) == 4 ? (qr == 4 || qr == 5) : (qr == 3 || qr == 4); }
 
 // forward: wgs workgroups per member (each loops over tiles), blocks = wgs * batch
+template <typename R>
 hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, bool fsim, int wgs, int64_t blocks,
                              int nthreads, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
-    if (jl.jobs || (qr != 4 && qr != 5) || nthreads > (1 << (13 - qr)) || nthreads < 64 || wgs < 1)
+    if (jl.jobs || !rounds_qr_ok<R>(qr) || nthreads > (1 << (q_tile_bits<R>() - qr)) || nthreads < 64 || wgs < 1)
         return hipErrorInvalidValue;
     const dim3 g = dim3(unsigned(blocks)), b = dim3(unsigned(nthreads));
-    if (qr == 5 && fsim) hipLaunchKernelGGL((k_rounds_fwd<5, true>), g, b, 0, st, jl, single, wgs);
-    else if (qr == 5) hipLaunchKernelGGL((k_rounds_fwd<5, false>), g, b, 0, st, jl, single, wgs);
-    else if (fsim) hipLaunchKernelGGL((k_rounds_fwd<4, true>), g, b, 0, st, jl, single, wgs);
-    else hipLaunchKernelGGL((k_rounds_fwd<4, false>), g, b, 0, st, jl, single, wgs);
+    if constexpr (sizeof(R) == 4) {
+        if (qr == 5 && fsim) hipLaunchKernelGGL((k_rounds_fwd<R, 5, true>), g, b, 0, st, jl, single, wgs);
+        else if (qr == 5) hipLaunchKernelGGL((k_rounds_fwd<R, 5, false>), g, b, 0, st, jl, single, wgs);
+        else if (fsim) hipLaunchKernelGGL((k_rounds_fwd<R, 4, true>), g, b, 0, st, jl, single, wgs);
+        else hipLaunchKernelGGL((k_rounds_fwd<R, 4, false>), g, b, 0, st, jl, single, wgs);
+    } else {
+        if (qr == 4 && fsim) hipLaunchKernelGGL((k_rounds_fwd<R, 4, true>), g, b, 0, st, jl, single, wgs);
+        else if (qr == 4) hipLaunchKernelGGL((k_rounds_fwd<R, 4, false>), g, b, 0, st, jl, single, wgs);
+        else if (fsim) hipLaunchKernelGGL((k_rounds_fwd<R, 3, true>), g, b, 0, st, jl, single, wgs);
+        else hipLaunchKernelGGL((k_rounds_fwd<R, 3, false>), g, b, 0, st, jl, single, wgs);
+    }
     return hipGetLastError();
 }
 
+template <typename R>
 hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, bool fsim, int64_t blocks, int nthreads,
                              hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
-    if (jl.jobs || (qr != 4 && qr != 5) || nthreads > (1 << (13 - qr)) || nthreads < 64) return hipErrorInvalidValue;
+    if (jl.jobs || !rounds_qr_ok<R>(qr) || nthreads > (1 << (q_tile_bits<R>() - qr)) || nthreads < 64)
+        return hipErrorInvalidValue;
     const dim3 g = dim3(unsigned(blocks)), b = dim3(unsigned(nthreads));
-    if (qr == 5 && fsim) hipLaunchKernelGGL((k_rounds_rev<5, true>), g, b, 0, st, jl, single);
-    else if (qr == 5) hipLaunchKernelGGL((k_rounds_rev<5, false>), g, b, 0, st, jl, single);
-    else if (fsim) hipLaunchKernelGGL((k_rounds_rev<4, true>), g, b, 0, st, jl, single);
-    else hipLaunchKernelGGL((k_rounds_rev<4, false>), g, b, 0, st, jl, single);
+    if constexpr (sizeof(R) == 4) {
+        if (qr == 5 && fsim) hipLaunchKernelGGL((k_rounds_rev<R, 5, true>), g, b, 0, st, jl, single);
+        else if (qr == 5) hipLaunchKernelGGL((k_rounds_rev<R, 5, false>), g, b, 0, st, jl, single);
+        else if (fsim) hipLaunchKernelGGL((k_rounds_rev<R, 4, true>), g, b, 0, st, jl, single);
+        else hipLaunchKernelGGL((k_rounds_rev<R, 4, false>), g, b, 0, st, jl, single);
+    } else {
+        if (qr == 4 && fsim) hipLaunchKernelGGL((k_rounds_rev<R, 4, true>), g, b, 0, st, jl, single);
+        else if (qr == 4) hipLaunchKernelGGL((k_rounds_rev<R, 4, false>), g, b, 0, st, jl, single);
+        else if (fsim) hipLaunchKernelGGL((k_rounds_rev<R, 3, true>), g, b, 0, st, jl, single);
+        else hipLaunchKernelGGL((k_rounds_rev<R, 3, false>), g, b, 0, st, jl, single);
+    }
     return hipGetLastError();
 }
+
+#define TCNG_INST_ROUNDS(R)                                                                                       \
+    template hipError_t launch_rounds_coef<R>(const QStep*, int, const QStep*, int, const void*, int, int64_t,   \
+                                              void*, hipStream_t);                                                \
+    template size_t rounds_coef_bytes<R>(int);                                                                    \
+    template hipError_t launch_rounds_fwd<R>(const JobList&, const Job&, int, bool, int, int64_t, int, hipStream_t); \
+    template hipError_t launch_rounds_rev<R>(const JobList&, const Job&, int, bool, int64_t, int, hipStream_t);
+TCNG_INST_ROUNDS(float)
+TCNG_INST_ROUNDS(double)
 
 template <typename R>
 hipError_t launch_build_ops_multi(const BuildJob* jobs, const int64_t* prefix, int njobs, int64_t total,

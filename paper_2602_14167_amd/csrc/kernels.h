@@ -85,15 +85,19 @@ hipError_t launch_build_ops(const DevPlan& dp, int n_ops, const void* params, in
 // nthreads: workgroup size (2^(m - RB) of the largest tile among the jobs)
 template <typename R, int RB>
 hipError_t launch_tile_fwd(const JobList& jl, const Job& single, int64_t blocks, int nthreads, hipStream_t st);
-// rotation rounds (complex64, qr = 4 or 5 register bits; the job's qpasses /
-// qrpasses are set).  launch_rounds_coef fills the coefficient blocks (after
-// launch_build_ops); rounds_coef_bytes: bytes per member for `steps` steps.
+// rounds (R = float: qr = 4 or 5 register bits; R = double: qr = 3 or 4; the job's
+// qpasses / qrpasses are set).  launch_rounds_coef fills the coefficient blocks
+// (after launch_build_ops); rounds_coef_bytes: bytes per member for `steps` steps.
+template <typename R>
 hipError_t launch_rounds_coef(const QStep* fsteps, int nf, const QStep* rsteps, int nr, const void* opm, int n_gates,
                               int64_t batch, void* out, hipStream_t st);
+template <typename R>
 size_t rounds_coef_bytes(int steps);
 // fsim: the pass's rounds are fSim rounds (QK_FSIM), else rotation rounds
+template <typename R>
 hipError_t launch_rounds_fwd(const JobList& jl, const Job& single, int qr, bool fsim, int wgs, int64_t blocks,
                              int nthreads, hipStream_t st);
+template <typename R>
 hipError_t launch_rounds_rev(const JobList& jl, const Job& single, int qr, bool fsim, int64_t blocks, int nthreads,
                              hipStream_t st);
 template <typename R, int RB>

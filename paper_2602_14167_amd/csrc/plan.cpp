@@ -351,7 +351,7 @@ std::string plan_circuit(int n, const std::vector<tcng_gate>& gates, int n_param
     std::vector<int> rem(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) rem[i] = int(i);
     // rounds: a wave's 64 lanes hold thread bits in both sweeps
-    const bool rounds_ok = m >= std::max(cfg.rb, cfg.rb_rev) + 6 && cfg.rb >= 4 && cfg.rb_rev >= 4;
+    const bool rounds_ok = m >= std::max(cfg.rb, cfg.rb_rev) + 6 && cfg.rb >= 3 && cfg.rb_rev >= 3;
     out.rounds = false;
 
     // per-gate slot assignment (global, in reverse-sweep order is not needed:

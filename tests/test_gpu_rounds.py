@@ -19,7 +19,9 @@ from tests.bars import assert_amps
 
 pytestmark = pytest.mark.gpu
 
-TOL_E, TOL_G = 1e-5, 1e-4
+TOL = {"c64": (1e-5, 1e-4), "c128": (1e-12, 1e-12)}
+TDT = {"c64": torch.complex64, "c128": torch.complex128}
+RDT = {"c64": torch.float32, "c128": torch.float64}
 
 
 @pytest.fixture(scope="module")
@@ -47,42 +49,43 @@ def ry_rz_cnot_circuit(n, n_gates, rng, low_bias=False):
     return W.as_gate_array(g), npar
 
 
-def check(P, oracle_mod, n, gates, n_params, codes, coeffs, pb, init, tiling=None, label=""):
+def check(P, oracle_mod, n, gates, n_params, codes, coeffs, pb, init, tiling=None, label="", dt="c64"):
     circ = P.Circuit(n, gates, n_params)
     if tiling:
-        circ.configure(torch.complex64, *tiling)
-    assert circ.rounds() > 0, "the circuit should run as rotation rounds"
+        circ.configure(TDT[dt], *tiling)
+    assert circ.rounds(TDT[dt]) > 0, "the circuit should run as rounds"
     H = P.PauliSum(n, codes, coeffs)
     B = pb.shape[0]
-    psi = torch.as_tensor(np.tile(init, (B, 1))).to(device="cuda", dtype=torch.complex64)
+    psi = torch.as_tensor(np.tile(init, (B, 1))).to(device="cuda", dtype=TDT[dt])
     psi0 = psi.clone()
-    p = torch.as_tensor(pb).to(device="cuda", dtype=torch.float32)
+    p = torch.as_tensor(pb).to(device="cuda", dtype=RDT[dt])
     E, g = P.expect_grad(circ, p, H, psi=psi, mode="tiled")[:2]
     E, g = E.cpu().numpy(), g.cpu().numpy()
     S = float(np.abs(coeffs).sum())
     worst_e = worst_g = 0.0
     for b in range(B):
-        ref = oracle_mod.expect_grad(n, gates, W.round_params(pb[b], "c64"), codes, coeffs, None, init=init)
+        ref = oracle_mod.expect_grad(n, gates, W.round_params(pb[b], dt), codes, coeffs, None, init=init)
         worst_e = max(worst_e, abs(E[b] - ref["E"]) / S)
         worst_g = max(worst_g, float(np.max(np.abs(g[b] - ref["grad"]))) / S)
-    print(f"rounds {label} n={n} gates={len(gates)} phases={circ.rounds()}: |dE|/S={worst_e:.2e} |dg|/S={worst_g:.2e}",
-          flush=True)
-    assert worst_e <= TOL_E and worst_g <= TOL_G, (worst_e, worst_g)
+    print(f"rounds {label} {dt} n={n} gates={len(gates)} phases={circ.rounds(TDT[dt])}: |dE|/S={worst_e:.2e} "
+          f"|dg|/S={worst_g:.2e}", flush=True)
+    te, tg = TOL[dt]
+    assert worst_e <= te and worst_g <= tg, (worst_e, worst_g)
     # the reverse sweep un-computes the states back to the input
-    assert_amps(psi.cpu().numpy(), psi0.cpu().numpy(), "c64", 8 * len(gates), f"rounds recomputed psi0 {label}")
+    assert_amps(psi.cpu().numpy(), psi0.cpu().numpy(), dt, 8 * len(gates), f"rounds recomputed psi0 {label}")
     # forward only: the final state
-    st = torch.empty((1, 2 ** n), dtype=torch.complex64, device="cuda")
+    st = torch.empty((1, 2 ** n), dtype=TDT[dt], device="cuda")
     st.copy_(torch.as_tensor(np.ascontiguousarray(init[None, :])))
     P.run_circuit(circ, p[:1].contiguous(), st, mode="tiled")
-    ref = oracle_mod.expect_grad(n, gates, W.round_params(pb[0], "c64"), codes, coeffs, None, init=init,
+    ref = oracle_mod.expect_grad(n, gates, W.round_params(pb[0], dt), codes, coeffs, None, init=init,
                                  want_state=True)
-    assert_amps(st.cpu().numpy()[0], ref["state"], "c64", len(gates), f"rounds final state {label}")
+    assert_amps(st.cpu().numpy()[0], ref["state"], dt, len(gates), f"rounds final state {label}")
 
 
 def test_rounds_taken_only_where_they_apply(P):
     w = W.cfg2(n=16, layers=3)
     c = P.Circuit(16, w["gates"], w["n_params"])
-    assert c.rounds() > 0 and c.rounds(torch.complex128) == 0
+    assert c.rounds() > 0 and c.rounds(torch.complex128) > 0
     r = np.random.default_rng(1)
     gates, params, mats = W.random_circuit(14, 40, r)   # every kind: not rotation rounds
     assert P.Circuit(14, gates, len(params), mats).rounds() == 0
@@ -190,3 +193,37 @@ def test_rounds_mixed_with_generic_passes(P, oracle_mod, n):
     pb = r.uniform(0, 2 * np.pi, (2, npar))
     init = W.random_state(n, r).astype(np.complex64).astype(np.complex128)
     check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, (11, 5, 4), "mixed")
+
+
+# ---------------------------------------------------------------------------
+# complex128 rounds (4 register bits in both sweeps, 12-bit tiles)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,layers", [(11, 2), (13, 3), (16, 3)])
+def test_rounds_hea_c128(P, oracle_mod, n, layers):
+    w = W.cfg2(n=n, layers=layers)
+    r = np.random.default_rng(500 + n)
+    pb = np.stack([w["params"], r.uniform(0, 2 * np.pi, w["n_params"])])
+    init = W.random_state(n, r)
+    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, None,
+          f"hea L={layers}", "c128")
+
+
+@pytest.mark.parametrize("n,n_gates,seed", [(11, 60, 1), (14, 150, 4)])
+def test_rounds_random_ry_rz_cnot_c128(P, oracle_mod, n, n_gates, seed):
+    r = np.random.default_rng(600 + seed)
+    gates, npar = ry_rz_cnot_circuit(n, n_gates, r, low_bias=(seed % 2 == 0))
+    codes, coeffs = W.random_pauli_sum(n, 12, r, max_weight=4)
+    pb = r.uniform(0, 2 * np.pi, (2, npar))
+    init = W.random_state(n, r)
+    check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, None, f"random seed={seed}", "c128")
+
+
+@pytest.mark.parametrize("rows,cols,depth", [(3, 4, 8), (4, 4, 10)])
+def test_fsim_rounds_c128(P, oracle_mod, rows, cols, depth):
+    w = W.cfg5(rows=rows, cols=cols, depth=depth)
+    n = w["n"]
+    r = np.random.default_rng(700 + n)
+    pb = np.stack([w["params"], r.uniform(0, 2 * np.pi, w["n_params"])])
+    init = W.random_state(n, r)
+    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, None,
+          f"fsim {rows}x{cols} d={depth}", "c128")
