@@ -258,6 +258,41 @@ __device__ __forceinline__ Regs<R, NB> app_phase_lift(Regs<R, NB> a, Lift<R> L) 
     return a;
 }
 
+// every amplitude j of a register block times its own phase (ph[2j], ph[2j + 1])
+// = (cos, sin), or by the conjugate (INV): a product of RZ rotations on the
+// block's bits is one phase per amplitude
+template <bool INV, typename R, int NB, typename CP>
+__device__ __forceinline__ Regs<R, NB> app_phases(Regs<R, NB> a, CP ph) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const R c = ph[2 * j], s = INV ? -ph[2 * j + 1] : ph[2 * j + 1];
+        const cx<R> x = a.v[j];
+        a.v[j] = {fmaR(x.re, c, -x.im * s), fmaR(x.re, s, x.im * c)};
+    }
+    return a;
+}
+
+// the RZ gradients of all QR bits of a block at once: with v_j = Im(conj(l_j) p_j),
+// g_b = sum_j (-1)^{j_b} v_j = T - 2 P_b, T = sum_j v_j, P_b = sum over j with bit b set
+template <typename R, int QR>
+__device__ __forceinline__ void grad_rz_all(const Regs<R, (1 << QR)>& l, const Regs<R, (1 << QR)>& p, R* g) {
+    constexpr int NB = 1 << QR;
+    R v[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v[j] = fmaR(l.v[j].re, p.v[j].im, -l.v[j].im * p.v[j].re);
+    R T = R(0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) T += v[j];
+#pragma unroll
+    for (int b = 0; b < QR; ++b) {
+        R P = R(0);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j & (1 << b)) P += v[j];
+        g[b] = fmaR(R(-2), P, T);
+    }
+}
+
 // RZ gradient on register bit B: sum_j (-1)^{j_B} Im(conj(l_j) p_j)
 template <typename R, int NB, int B>
 __device__ __forceinline__ R grad_rz(Regs<R, NB> l, Regs<R, NB> p) {

@@ -800,15 +800,18 @@ __device__ __forceinline__ void q_write(cx<R>* lds, const QBlk<R, QR>& a, QMap<Q
     for (int j = 0; j < (1 << QR); ++j) lds[qaddr<MAPPED>(q, j)] = a.v[j];
 }
 
-// Shear coefficients of a step, one block per (member, step) written once per
-// evaluation by k_rounds_coef: [RY t x5, RY s x5, RZ t x5, RZ s x5, sign, 0, 0, 0]
-// (an absent gate: t = s = 0; sign = -1 if an odd number of the step's
-// rotations are taken as -R(a - pi)).  A step reads its block with two scalar
-// loads instead of one round trip per gate.
-constexpr int QCOEF = 24;
+// Coefficients of a step, one block per (member, step) written once per
+// evaluation by k_rounds_coef, read in place with scalar loads (no round trip
+// per gate): c[0..9] = RY shear t x5, s x5 (an absent gate: t = s = 0);
+// c[10] = -1 if an odd number of the step's RY are taken as -R(a - pi), else 1;
+// c[16 + 2j], c[17 + 2j] = cos, sin of the phase of register amplitude j
+// (j < 2^QR) under the step's RZ round, the product over register bits b of
+// e^{-i a_b / 2} (bit b of j clear) or e^{+i a_b / 2} (set).
+constexpr int QCOEF = 16 + 2 * (1 << QREG);
+constexpr int QPH = 16;   // first phase entry
 
-template <bool INV, int QR, typename R>
-__device__ __forceinline__ QBlk<R, QR> q_ry_round(QBlk<R, QR> a, const R* c) {
+template <bool INV, int QR, typename R, typename CP>
+__device__ __forceinline__ QBlk<R, QR> q_ry_round(QBlk<R, QR> a, CP c) {
     constexpr int NB = 1 << QR;
     const R sg = INV ? R(-1) : R(1);
     a = app_ry_lift<R, NB, 0>(a, Lift<R>{sg * c[0], sg * c[5]});
@@ -818,18 +821,6 @@ __device__ __forceinline__ QBlk<R, QR> q_ry_round(QBlk<R, QR> a, const R* c) {
     if constexpr (QR > 4) a = app_ry_lift<R, NB, qb<4, QR>()>(a, Lift<R>{sg * c[4], sg * c[9]});
     return a;
 }
-template <bool INV, int QR, typename R>
-__device__ __forceinline__ QBlk<R, QR> q_rz_round(QBlk<R, QR> a, const R* c) {
-    constexpr int NB = 1 << QR;
-    const R sg = INV ? R(-1) : R(1);
-    a = app_rz_lift<R, NB, 0>(a, Lift<R>{sg * c[10], sg * c[15]});
-    a = app_rz_lift<R, NB, 1>(a, Lift<R>{sg * c[11], sg * c[16]});
-    a = app_rz_lift<R, NB, 2>(a, Lift<R>{sg * c[12], sg * c[17]});
-    if constexpr (QR > 3) a = app_rz_lift<R, NB, qb<3, QR>()>(a, Lift<R>{sg * c[13], sg * c[18]});
-    if constexpr (QR > 4) a = app_rz_lift<R, NB, qb<4, QR>()>(a, Lift<R>{sg * c[14], sg * c[19]});
-    return a;
-}
-
 // fSim rounds: pair slot k of a step has [cos t, sin t, Re e^{-ip}, Im e^{-ip}]
 // in c[4k .. 4k + 3] (an absent gate: 1, 0, 1, 0, the identity); the inverse
 // negates sin t and Im e^{-ip}.  Round A: slots 0, 1 on register bits (0,1),
@@ -1068,10 +1059,10 @@ __global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_fwd(con
                         if (S.ry[3] >= 0)
                             a = app_fsim<R, (1 << QR), qb<3, QR>(), qb<4, QR>()>(a, c[12], c[13], cx<R>{c[14], c[15]});
                 } else {
-                    const QCoef<R> C = coef[s];
-                    a = q_ry_round<false, QR>(a, C.c);
-                    a = q_rz_round<false, QR>(a, C.c);
-                    flip = flip != (C.c[20] < R(0));
+                    cptr<R> c = &coef[s].c[0];
+                    a = q_ry_round<false, QR>(a, c);
+                    a = app_phases<false, R, (1 << QR)>(a, c + QPH);
+                    flip = flip != (c[10] < R(0));
                 }
             }
             __syncthreads();   // the write permutes positions: every read first
@@ -1154,26 +1145,22 @@ __global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_rev(con
                     q_red_fs<(QR > 3 ? 2 : 1)>(red, S.sy, nwaves, wave, lane, gt, gp);
                     continue;
                 }
-                const QCoef<R> C = coef[s];
+                cptr<R> c = &coef[s].c[0];
                 // the round's derivatives first, then the un-apply, then their
                 // reductions (which leave the blocks alone)
                 R gz[QR], gy[QR];
-                gz[0] = grad_rz<R, NB, 0>(la, ps);
-                gz[1] = grad_rz<R, NB, 1>(la, ps);
-                gz[2] = grad_rz<R, NB, 2>(la, ps);
-                if constexpr (QR > 3) gz[qb<3, QR>()] = grad_rz<R, NB, qb<3, QR>()>(la, ps);
-                if constexpr (QR > 4) gz[qb<4, QR>()] = grad_rz<R, NB, qb<4, QR>()>(la, ps);
-                ps = q_rz_round<true, QR>(ps, C.c);
-                la = q_rz_round<true, QR>(la, C.c);
+                grad_rz_all<R, QR>(la, ps, gz);
+                ps = app_phases<true, R, NB>(ps, c + QPH);
+                la = app_phases<true, R, NB>(la, c + QPH);
                 q_red<QR>(red, S.sz, nwaves, wave, lane, gz);
                 gy[0] = grad_rot1<R, NB, 0>(K_RY, la, ps);
                 gy[1] = grad_rot1<R, NB, 1>(K_RY, la, ps);
                 gy[2] = grad_rot1<R, NB, 2>(K_RY, la, ps);
                 if constexpr (QR > 3) gy[qb<3, QR>()] = grad_rot1<R, NB, qb<3, QR>()>(K_RY, la, ps);
                 if constexpr (QR > 4) gy[qb<4, QR>()] = grad_rot1<R, NB, qb<4, QR>()>(K_RY, la, ps);
-                ps = q_ry_round<true, QR>(ps, C.c);
-                la = q_ry_round<true, QR>(la, C.c);
-                flip = flip != (C.c[20] < R(0));
+                ps = q_ry_round<true, QR>(ps, c);
+                la = q_ry_round<true, QR>(la, c);
+                flip = flip != (c[10] < R(0));
                 q_red<QR>(red, S.sy, nwaves, wave, lane, gy);
             }
             if constexpr (FS) {   // the phase's Hadamards (their own inverses) last
@@ -1243,16 +1230,23 @@ __global__ void k_rounds_coef(const QStep* __restrict__ fsteps, int nf, const QS
     }
     bool odd = false;
     for (int k = 0; k < QREG; ++k) {
-        const int gy = S.ry[k], gz = S.rz[k];
+        const int gy = S.ry[k];
         C.c[k] = gy >= 0 ? om[size_t(gy) * 16 + 4].re : R(0);
         C.c[5 + k] = gy >= 0 ? om[size_t(gy) * 16 + 4].im : R(0);
-        C.c[10 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].re : R(0);
-        C.c[15 + k] = gz >= 0 ? om[size_t(gz) * 16 + 4].im : R(0);
         if (gy >= 0 && om[size_t(gy) * 16 + 5].re < R(0)) odd = !odd;
-        if (gz >= 0 && om[size_t(gz) * 16 + 5].re < R(0)) odd = !odd;
     }
-    C.c[20] = odd ? R(-1) : R(1);
-    C.c[21] = C.c[22] = C.c[23] = R(0);
+    C.c[10] = odd ? R(-1) : R(1);
+    for (int k = 11; k < QPH; ++k) C.c[k] = R(0);
+    // the RZ round's phases: RZ matrix entries 0 = e^{-ia/2}, 1 = e^{+ia/2}
+    for (int j = 0; j < (1 << QREG); ++j) {
+        cx<R> ph = {R(1), R(0)};
+        for (int k = 0; k < QREG; ++k) {
+            const int gz = S.rz[k];
+            if (gz >= 0) ph = ph * om[size_t(gz) * 16 + ((j >> k) & 1)];
+        }
+        C.c[QPH + 2 * j] = ph.re;
+        C.c[QPH + 2 * j + 1] = ph.im;
+    }
     out[i] = C;
 }
 
