@@ -756,15 +756,19 @@ __device__ __forceinline__ QMap<QR> qmap(cptr<QPhase> F, int t, int m) {
         q.rsw[i] = swz(1u << l);
         q.crsw[i] = swz(uint32_t(F->cimg[l]));
     }
+    // the thread's bits fill the non-register local bits in increasing order:
+    // unrolled over the local bits, with uniform control and lane masks, so the
+    // images' scalar loads are independent (a loop with a lane-dependent branch
+    // around each load serialised them, a scalar load's latency per bit)
     uint32_t tp = 0, ct = 0;
-    int k = 0;
-    for (int b = 0; b < m; ++b) {
-        if ((rmask >> b) & 1) continue;
-        if ((t >> k) & 1) {
-            tp |= 1u << b;
-            ct ^= uint32_t(F->cimg[b]);
-        }
-        ++k;
+    const uint32_t tt = pin(uint32_t(t));   // (the masks are formed anew per phase, not kept live)
+#pragma unroll
+    for (int b = 0; b < MAX_TILE_BITS; ++b) {
+        if (b >= m || ((rmask >> b) & 1)) continue;
+        const int k = __popc(~rmask & ((1u << b) - 1u));   // the thread bit that fills local bit b
+        const uint32_t msk = 0u - ((tt >> k) & 1u);
+        tp |= (1u << b) & msk;
+        ct ^= uint32_t(F->cimg[b]) & msk;
     }
     q.tsw = swz(tp);
     q.ctsw = swz(ct);
