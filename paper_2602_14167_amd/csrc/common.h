@@ -147,7 +147,9 @@ struct QPhase {
     int32_t R[QREG];              // local bit of register bit i
     int32_t has_map;              // 0: C is the identity
     int32_t cimg[16];             // C(e_b) for local bits b < m
-    int32_t hmask, pad;           // fSim rounds: register bits taking a Hadamard before the steps
+    int32_t hmask;                // fSim rounds: register bits taking a Hadamard before the steps
+    int32_t rmask;                // local bits held in registers (bits R[i])
+    int32_t rimg[QREG];           // C(e_R[i]): the images of the register bits
 };
 
 struct QPass {

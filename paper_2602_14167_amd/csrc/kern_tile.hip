@@ -748,13 +748,11 @@ struct QMap {
 template <int QR>
 __device__ __forceinline__ QMap<QR> qmap(cptr<QPhase> F, int t, int m) {
     QMap<QR> q;
-    uint32_t rmask = 0;
+    const uint32_t rmask = uint32_t(F->rmask);
 #pragma unroll
     for (int i = 0; i < QR; ++i) {
-        const int l = F->R[i];
-        rmask |= 1u << l;
-        q.rsw[i] = swz(1u << l);
-        q.crsw[i] = swz(uint32_t(F->cimg[l]));
+        q.rsw[i] = swz(1u << F->R[i]);
+        q.crsw[i] = swz(uint32_t(F->rimg[i]));
     }
     // the thread's bits fill the non-register local bits in increasing order:
     // unrolled over the local bits, with uniform control and lane masks, so the

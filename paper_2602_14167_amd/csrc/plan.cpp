@@ -240,6 +240,10 @@ std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<i
             used |= 1u << l;
         }
         for (int b = qreg; b < QREG; ++b) F.R[b] = -1;
+        for (int b = 0; b < qreg; ++b) {
+            F.rmask |= 1 << F.R[b];
+            F.rimg[b] = F.cimg[F.R[b]];
+        }
         phases.push_back(F);
     }
     qp.phase_end = int(phases.size());
@@ -328,6 +332,10 @@ std::string plan_rounds_fsim(const std::vector<tcng_gate>& gates, const std::vec
             used |= 1u << l;
         }
         for (int b = qreg; b < QREG; ++b) F.R[b] = -1;
+        for (int b = 0; b < qreg; ++b) {
+            F.rmask |= 1 << F.R[b];
+            F.rimg[b] = F.cimg[F.R[b]];
+        }
         phases.push_back(F);
     }
     qp.phase_end = int(phases.size());
