@@ -55,20 +55,20 @@ KERNEL_SOURCES = {
     "plain": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_plain.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.6047e+09, "38c831912626873b"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.2952e+09, "38c831912626873b"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.7868e+09, "c843121236b420f2"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.2963e+09, "c843121236b420f2"),
-    ("fsim_brickwork_n32_d20_tfim2d", "rev_tile"): (1.3745e+11, "38c831912626873b"),
-    ("fsim_brickwork_n32_d20_tfim2d", "fwd_tile"): (6.8719e+10, "38c831912626873b"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6865e+10, "c843121236b420f2"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0972e+08, "c843121236b420f2"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4650e+08, "c843121236b420f2"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7451e+08, "c843121236b420f2"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2844e+08, "c843121236b420f2"),
-    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5149e+10, "c843121236b420f2"),
-    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "02c6a18ba3a6bfbf"),
-    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7186e+10, "15da485875e46faa"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.6046e+09, "a105e7ac5ed63f15"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.2952e+09, "a105e7ac5ed63f15"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.7870e+09, "53072dae2f1df073"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.2964e+09, "53072dae2f1df073"),
+    ("fsim_brickwork_n32_d20_tfim2d", "rev_tile"): (1.3745e+11, "a105e7ac5ed63f15"),
+    ("fsim_brickwork_n32_d20_tfim2d", "fwd_tile"): (6.8719e+10, "a105e7ac5ed63f15"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6865e+10, "53072dae2f1df073"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0971e+08, "53072dae2f1df073"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4651e+08, "53072dae2f1df073"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7453e+08, "53072dae2f1df073"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2844e+08, "53072dae2f1df073"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5150e+10, "53072dae2f1df073"),
+    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "b14607c6c840b485"),
+    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7186e+10, "794086836755462a"),
 }
 
 
