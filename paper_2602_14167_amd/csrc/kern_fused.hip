@@ -252,6 +252,15 @@ __device__ __forceinline__ FWork fwork(int m, int kb = FUSED_K) {
 template <int KB>
 constexpr int mats_stride() { return KB == 5 ? 8192 : 2048; }
 
+// XCD-aware block order of a single-job launch: workgroups are dealt to the
+// 8 XCDs round-robin, each with its own L2, so consecutive tiles (which share
+// the 128-byte lines of 64-byte runs when a tile has 3 low qubits) go to blocks
+// 8 apart, on one XCD; the tail past a multiple of 8 keeps its order
+__device__ __forceinline__ int64_t xcd_block(int64_t blk, int64_t grid) {
+    const int64_t g8 = grid & ~int64_t(7);
+    return blk < g8 ? (blk & 7) * (g8 >> 3) + (blk >> 3) : blk;
+}
+
 // MB: largest tile bits of the instantiation (LDS size, column tiles per wave);
 // KB: block bits of the plan
 template <int IT, int MB, int KB>
@@ -259,7 +268,7 @@ __global__ void __launch_bounds__(FTHREADS) k_fused_fwd(const JobList jl, const 
     constexpr int CT_MAX = KB == 5 ? 1 : ct_max<MB>();
     __shared__ float2 lds[1 << MB];
     int64_t local;
-    const Job J = load_job(jl, single, blockIdx.x, local);
+    const Job J = load_job(jl, single, jl.jobs ? int64_t(blockIdx.x) : xcd_block(blockIdx.x, gridDim.x), local);
     cptr<FPass> P = as_const(J.fpasses) + jl.step;
     const int m = P->m;
     const FWork K = fwork(m, KB);
