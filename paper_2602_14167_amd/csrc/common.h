@@ -120,7 +120,11 @@ struct Pass {
 // its rounds, form a GF(2)-linear permutation of the tile's local index:
 // amplitude y of the phase moves to C(y), which the phase applies by writing
 // register j at LDS position C(y) (the reverse sweep reads it from there).
-// C is given by cimg[b] = C(e_b), the image of local bit b.
+// Each boundary between two phases of a pass has its own LDS layout A (a
+// linear bijection of the local index): the phase reads y at A_before(y) and
+// writes C(y) at A_after(C(y)), so it keeps the images of the local bits in
+// both (uimg, cimg); the reverse sweep reads through cimg and writes through
+// uimg.  fSim phases have C = I.
 //
 // fSim rounds: the passes made of fSim gates and Hadamards only.  A phase holds a chain of
 // up to 5 qubits in register bits 0..4 and runs steps of two rounds on fixed
@@ -146,11 +150,19 @@ struct QPhase {
     int32_t step_begin, step_end;
     int32_t R[QREG];              // local bit of register bit i
     int32_t has_map;              // 0: C is the identity
-    int32_t cimg[16];             // C(e_b) for local bits b < m
+    int32_t cimg[16];             // LDS slot of C(e_b) (local bits b < m) in the layout after the phase
     int32_t hmask;                // fSim rounds: register bits taking a Hadamard before the steps
     int32_t rmask;                // local bits held in registers (bits R[i])
-    int32_t rimg[QREG];           // C(e_R[i]): the images of the register bits
+    int32_t rimg[QREG];           // cimg[R[i]]: the same for the register bits
+    int32_t uimg[16];             // LDS slot of e_b in the layout before the phase
+    int32_t ruimg[QREG];          // uimg[R[i]]
 };
+
+// The tiles' fixed LDS swizzle, a linear bijection of the local index that
+// leaves bit 0 alone (so pairs of amplitudes stay adjacent): bits 5..7 fold
+// onto bits 1..3.  The rounds' tile loads and stores use it; the planner
+// chooses the layouts between their phases.
+__host__ __device__ inline uint32_t tile_swz(uint32_t l) { return l ^ (((l >> 5) & 7u) << 1); }
 
 struct QPass {
     int32_t phase_begin, phase_end;
@@ -226,7 +238,7 @@ struct PClass {
 struct PGroup {
     int32_t x_local;     // X/Y bits (all inside the tile), local positions
     int32_t class_begin, class_end;
-    int32_t pad;
+    int32_t no_z;        // 1: no term has Z/Y bits, so the coefficient is cbr + i cbi for every element
     double cbr, cbi;     // sum over all its classes of c * n_terms
     float fbr, fbi;      // the same, rounded to float32
 };

@@ -229,6 +229,26 @@ k_pauli_tile(const JobList jl, const Job single) {
                 // the group's coefficient of psi_{l ^ x}: the element-independent
                 // sum c * n_terms, then -2 c * #odd parities per class
                 const R gbr = grp_re<R>(G), gbi = grp_im<R>(G);
+                if (G.no_z) {
+                    // X-only strings: one coefficient for every element (real
+                    // for the field terms of a spin model: two products, not four)
+                    if (gbi == R(0)) {
+#pragma unroll
+                        for (int i = 0; i < CH; ++i) {
+                            const cx<R> pp = partner<R>(lds, tb8, uint32_t((c0 + i) * nt), uint32_t(G.x_local));
+                            sr[i] = fma(gbr, pp.re, sr[i]);
+                            si[i] = fma(gbr, pp.im, si[i]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < CH; ++i) {
+                            const cx<R> pp = partner<R>(lds, tb8, uint32_t((c0 + i) * nt), uint32_t(G.x_local));
+                            sr[i] = fma(gbr, pp.re, fma(-gbi, pp.im, sr[i]));
+                            si[i] = fma(gbr, pp.im, fma(gbi, pp.re, si[i]));
+                        }
+                    }
+                    continue;
+                }
                 // (every group lists at least one class, possibly without terms)
                 int c = G.class_begin;
                 const int c_end = G.class_end;

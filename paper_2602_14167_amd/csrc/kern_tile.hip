@@ -61,7 +61,7 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t tile, uint64_t tmask, int
 // LDS position of local index l: XOR-swizzle bits 1..3 with bits 5..7 so that
 // strided register reads spread over banks; bit 0 is untouched so 16-byte
 // pairs of complex64 stay adjacent.
-__device__ __forceinline__ uint32_t swz(uint32_t l) { return l ^ (((l >> 5) & 7u) << 1); }
+__device__ __forceinline__ uint32_t swz(uint32_t l) { return tile_swz(l); }
 
 // 16-byte vector access of the state
 template <typename R>
@@ -737,12 +737,13 @@ constexpr int qb() { return B < QR ? B : 0; }
 template <typename R>
 constexpr int q_tile_bits() { return sizeof(R) == 4 ? 13 : 12; }
 
-// a phase's register map: the thread's part of the local index, and the LDS
-// positions of its registers with and without the phase's permutation C
+// a phase's register map: the LDS positions of the thread's part of the local
+// index and of its registers, in the layout before the phase (plain) and
+// after it (through the phase's permutation C)
 template <int QR>
 struct QMap {
-    uint32_t tsw, ctsw;              // swz(tpart), swz(C(tpart))
-    uint32_t rsw[QR], crsw[QR];      // swz(e_R[i]), swz(C(e_R[i])) (uniform)
+    uint32_t tsw, ctsw;              // A_before(tpart), A_after(C(tpart))
+    uint32_t rsw[QR], crsw[QR];      // A_before(e_R[i]), A_after(C(e_R[i])) (uniform)
 };
 
 template <int QR>
@@ -751,8 +752,8 @@ __device__ __forceinline__ QMap<QR> qmap(cptr<QPhase> F, int t, int m) {
     const uint32_t rmask = uint32_t(F->rmask);
 #pragma unroll
     for (int i = 0; i < QR; ++i) {
-        q.rsw[i] = swz(1u << F->R[i]);
-        q.crsw[i] = swz(uint32_t(F->rimg[i]));
+        q.rsw[i] = uint32_t(F->ruimg[i]);
+        q.crsw[i] = uint32_t(F->rimg[i]);
     }
     // the thread's bits fill the non-register local bits in increasing order:
     // unrolled over the local bits, with uniform control and lane masks, so the
@@ -765,11 +766,11 @@ __device__ __forceinline__ QMap<QR> qmap(cptr<QPhase> F, int t, int m) {
         if (b >= m || ((rmask >> b) & 1)) continue;
         const int k = __popc(~rmask & ((1u << b) - 1u));   // the thread bit that fills local bit b
         const uint32_t msk = 0u - ((tt >> k) & 1u);
-        tp |= (1u << b) & msk;
+        tp ^= uint32_t(F->uimg[b]) & msk;
         ct ^= uint32_t(F->cimg[b]) & msk;
     }
-    q.tsw = swz(tp);
-    q.ctsw = swz(ct);
+    q.tsw = tp;
+    q.ctsw = ct;
     return q;
 }
 
@@ -1068,7 +1069,7 @@ __global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_fwd(con
                 }
             }
             __syncthreads();   // the write permutes positions: every read first
-            q_write<!FS>(lds, a, q);
+            q_write<true>(lds, a, q);   // (into the next layout)
             __syncthreads();
         }
         q_tile_store<R, QR>(lds, psi, base, A, flip);
@@ -1120,11 +1121,11 @@ __global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_rev(con
             __syncthreads();
             q_tile_put<R, QR>(lds, vp, A);
             __syncthreads();
-            ps = q_read<!FS>(lds, q);
+            ps = q_read<true>(lds, q);
             __syncthreads();
             q_tile_put<R, QR>(lds, vl, A);
             __syncthreads();
-            la = q_read<!FS>(lds, q);
+            la = q_read<true>(lds, q);
         }
         for (;;) {
             cptr<QPhase> F = phases + f;
@@ -1179,11 +1180,11 @@ __global__ void __launch_bounds__(1 << (q_tile_bits<R>() - QR)) k_rounds_rev(con
             __syncthreads();
             q_write<false>(lds, ps, q);
             __syncthreads();
-            ps = q_read<!FS>(lds, qn);
+            ps = q_read<true>(lds, qn);
             __syncthreads();
             q_write<false>(lds, la, q);
             __syncthreads();
-            la = q_read<!FS>(lds, qn);
+            la = q_read<true>(lds, qn);
             q = qn;
             --f;
         }

@@ -12,6 +12,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <array>
 #include <map>
 
 namespace tcng {
@@ -149,6 +150,10 @@ std::string plan_phases(const std::vector<tcng_gate>& gates, const std::vector<i
     return "";
 }
 
+// the LDS layouts between the count phases of one rounds pass (QPhase::uimg,
+// cimg, rimg, ruimg; cimg holds C(e_b) on entry), below
+void rounds_lds_layouts(int m, QPhase* ph, int count, int qreg);
+
 // Rotation rounds of one pass (see QPhase).  A phase takes up to qreg qubits
 // whose first remaining gate is a rotation, then steps: each step applies, per
 // register qubit, its first remaining gate if that is an RY, then its next if
@@ -248,11 +253,125 @@ std::string plan_rounds(const std::vector<tcng_gate>& gates, const std::vector<i
     }
     qp.phase_end = int(phases.size());
     qp.kind = QK_ROT;
+    rounds_lds_layouts(m, phases.data() + qp.phase_begin, qp.phase_end - qp.phase_begin, qreg);
     size_t rots = 0;
     for (size_t k = first_step; k < steps.size(); ++k)
         for (int b = 0; b < QREG; ++b) rots += (steps[k].ry[b] >= 0) + (steps[k].rz[b] >= 0);
     if (rots + cnots != sel.size()) return "internal: rotation rounds lost a gate";
     return "";
+}
+
+// LDS layouts of the rounds (see QPhase).  The boundary between phases k - 1
+// and k of a pass is seen by the lanes of both: through C_{k-1} from phase
+// k - 1 (its lanes vary its 5 lowest non-register local bits) and plainly from
+// phase k, in the forward and in the reverse sweep alike.  Its layout A is
+// chosen so that, on both sides, the lanes' local-index vectors for lane bits
+// 0..s-1 map onto independent low s bits of the LDS slot, for s = 3, 4 and 5:
+// 8, 16 and 32 consecutive lanes then address distinct banks (amplitudes of
+// 16 and 8 bytes, 32 or 64 banks of 4 bytes).  The first and last boundaries
+// keep the tile load / store swizzle.  Deterministic (a fixed-seed search).
+namespace {
+
+int rank_of(std::vector<uint32_t> v) {
+    int r = 0;
+    for (int b = 0; b < 32; ++b) {
+        size_t p = size_t(r);
+        while (p < v.size() && !((v[p] >> b) & 1)) ++p;
+        if (p >= v.size()) continue;
+        std::swap(v[p], v[size_t(r)]);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (int(i) != r && ((v[i] >> b) & 1)) v[i] ^= v[size_t(r)];
+        ++r;
+    }
+    return r;
+}
+
+// rows[i]: bit i of the slot as a mask over the local index
+bool lanes_spread(const uint32_t* rows, const uint32_t* vec) {
+    for (int s = 3; s <= 5; ++s) {
+        std::vector<uint32_t> x(size_t(s), 0u);
+        for (int j = 0; j < s; ++j)
+            for (int i = 0; i < s; ++i) x[size_t(j)] |= uint32_t(popc(uint64_t(rows[i] & vec[j])) & 1) << i;
+        if (rank_of(x) != s) return false;
+    }
+    return true;
+}
+
+// images of the local bits under the layout whose low 5 slot bits are rows[0..4]
+// (the other slot bits: local bits, taken in increasing order while independent)
+void layout_images(int m, const uint32_t* low_rows, int32_t* img) {
+    std::vector<uint32_t> rows(low_rows, low_rows + 5);
+    for (int j = 0; j < m && int(rows.size()) < m; ++j) {
+        std::vector<uint32_t> t = rows;
+        t.push_back(1u << j);
+        if (rank_of(t) == int(t.size())) rows.push_back(1u << j);
+    }
+    for (int b = 0; b < 16; ++b) {
+        uint32_t v = 0;
+        if (b < m)
+            for (size_t i = 0; i < rows.size(); ++i) v |= ((rows[i] >> b) & 1u) << i;
+        img[b] = int32_t(v);
+    }
+}
+
+uint32_t apply_images(const int32_t* img, uint32_t v) {
+    uint32_t r = 0;
+    for (int b = 0; b < 16; ++b)
+        if ((v >> b) & 1) r ^= uint32_t(img[b]);
+    return r;
+}
+
+}  // namespace
+
+void rounds_lds_layouts(int m, QPhase* ph, int count, int qreg) {
+    if (count <= 0) return;
+    const uint32_t full = (1u << m) - 1u;
+    std::vector<std::array<int32_t, 16>> A(size_t(count) + 1);
+    for (int b = 0; b < 16; ++b) A[0][size_t(b)] = b < m ? int32_t(tile_swz(1u << b)) : 0;
+    A[size_t(count)] = A[0];
+    auto lanes = [&](const QPhase& F, bool mapped, uint32_t* vec) {
+        int k = 0;
+        for (int b = 0; b < m && k < 5; ++b)
+            if (!((F.rmask >> b) & 1)) vec[k++] = mapped ? uint32_t(F.cimg[b]) : (1u << b);
+    };
+    uint32_t swz_rows[5], id_rows[5];
+    for (int i = 0; i < 5; ++i) {
+        swz_rows[i] = 1u << i;
+        if (i >= 1 && i <= 3) swz_rows[i] |= 1u << (i + 4);
+        id_rows[i] = 1u << i;
+    }
+    uint64_t seed = 0x9E3779B97F4A7C15ull;
+    for (int k = 1; k < count; ++k) {
+        uint32_t w[5], r[5];
+        lanes(ph[k - 1], true, w);
+        lanes(ph[k], false, r);
+        const uint32_t* pick = nullptr;
+        uint32_t rows[5];
+        if (lanes_spread(swz_rows, w) && lanes_spread(swz_rows, r)) pick = swz_rows;
+        else if (lanes_spread(id_rows, w) && lanes_spread(id_rows, r)) pick = id_rows;
+        for (int tries = 0; !pick && tries < 200000; ++tries) {
+            for (int i = 0; i < 5; ++i) {
+                seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+                rows[i] = uint32_t(seed) & full;
+            }
+            if (lanes_spread(rows, w) && lanes_spread(rows, r)) pick = rows;
+        }
+        if (pick) layout_images(m, pick, A[size_t(k)].data());
+        else A[size_t(k)] = A[0];   // (not expected: the swizzle, with its conflicts)
+    }
+    for (int k = 0; k < count; ++k) {
+        QPhase& F = ph[k];
+        int32_t c[16];
+        for (int b = 0; b < 16; ++b) {
+            c[b] = b < m ? int32_t(apply_images(A[size_t(k) + 1].data(), uint32_t(F.cimg[b]))) : 0;
+            F.uimg[b] = A[size_t(k)][size_t(b)];
+        }
+        for (int b = 0; b < 16; ++b) F.cimg[b] = c[b];
+        for (int i = 0; i < QREG; ++i) {
+            F.rimg[i] = i < qreg ? F.cimg[F.R[i]] : 0;
+            F.ruimg[i] = i < qreg ? F.uimg[F.R[i]] : 0;
+        }
+    }
 }
 
 // fSim rounds of one pass (see QPhase).  A phase's register qubits form a
@@ -339,6 +458,7 @@ std::string plan_rounds_fsim(const std::vector<tcng_gate>& gates, const std::vec
         phases.push_back(F);
     }
     qp.phase_end = int(phases.size());
+    rounds_lds_layouts(m, phases.data() + qp.phase_begin, qp.phase_end - qp.phase_begin, qreg);
     if (taken_total != sel.size()) return "internal: fSim rounds lost a gate";
     return "";
 }
@@ -908,6 +1028,7 @@ std::string plan_pauli(int n, const std::vector<PauliTermHost>& terms, const Til
                 PClass pc{};
                 pc.term_begin = pc.term_end = int(out.terms.size());
                 out.classes.push_back(pc);
+                G.no_z = 1;
             }
             G.class_end = int(out.classes.size());
             G.fbr = float(G.cbr);
