@@ -55,20 +55,20 @@ KERNEL_SOURCES = {
     "plain": ["common.h", "devutil.h", "gates.h", "kernels.h", "kern_plain.hip"],
 }
 TRAFFIC = {
-    ("hea_n28_L12_tfim", "rev_tile"): (8.6046e+09, "a105e7ac5ed63f15"),
-    ("hea_n28_L12_tfim", "fwd_tile"): (4.2952e+09, "a105e7ac5ed63f15"),
-    ("hea_n28_L12_tfim", "fused_rev"): (8.7866e+09, "f076e651f73de446"),
-    ("hea_n28_L12_tfim", "fused_fwd"): (4.2966e+09, "f076e651f73de446"),
-    ("fsim_brickwork_n32_d20_tfim2d", "rev_tile"): (1.3745e+11, "a105e7ac5ed63f15"),
-    ("fsim_brickwork_n32_d20_tfim2d", "fwd_tile"): (6.8719e+10, "a105e7ac5ed63f15"),
-    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6976e+10, "f076e651f73de446"),
-    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0971e+08, "f076e651f73de446"),
-    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4651e+08, "f076e651f73de446"),
-    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7453e+08, "f076e651f73de446"),
-    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2844e+08, "f076e651f73de446"),
-    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5137e+10, "f076e651f73de446"),
-    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "b14607c6c840b485"),
-    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7186e+10, "794086836755462a"),
+    ("hea_n28_L12_tfim", "rev_tile"): (8.6047e+09, "34cae1f9856ca791"),
+    ("hea_n28_L12_tfim", "fwd_tile"): (4.2952e+09, "34cae1f9856ca791"),
+    ("hea_n28_L12_tfim", "fused_rev"): (8.7870e+09, "e6701c5affaf0dc5"),
+    ("hea_n28_L12_tfim", "fused_fwd"): (4.2968e+09, "e6701c5affaf0dc5"),
+    ("fsim_brickwork_n32_d20_tfim2d", "rev_tile"): (1.3745e+11, "34cae1f9856ca791"),
+    ("fsim_brickwork_n32_d20_tfim2d", "fwd_tile"): (6.8719e+10, "34cae1f9856ca791"),
+    ("mipt_haar_n20_d40_b1000_p0.2", "fused_fwd"): (1.6976e+10, "e6701c5affaf0dc5"),
+    ("qml_mnist_n10_l40_b15000", "fused_rev"): (5.0972e+08, "e6701c5affaf0dc5"),
+    ("qml_mnist_n10_l40_b15000", "fused_fwd"): (2.4651e+08, "e6701c5affaf0dc5"),
+    ("qml_cifar100_n12_l30_b5000", "fused_rev"): (6.7451e+08, "e6701c5affaf0dc5"),
+    ("qml_cifar100_n12_l30_b5000", "fused_fwd"): (3.2845e+08, "e6701c5affaf0dc5"),
+    ("haar_brickwork_uneven_1024", "fused_rev"): (1.5136e+10, "e6701c5affaf0dc5"),
+    ("tfim_coo_n24", "pauli_coo"): (1.3422e+10, "ba2bf1c0385a9695"),
+    ("single_gate_sweep_n30_c64", "plain_gate"): (1.7186e+10, "9295abc6ba4265a5"),
 }
 
 
