@@ -181,9 +181,10 @@ tcng_status tcng_circuit_get_config(const tcng_circuit* c, int32_t dtype, int32_
 /* The mode TCNG_MODE_AUTO runs for this circuit and dtype (after tuning, or
  * the default), resolved to the plan that exists (never TCNG_MODE_AUTO). */
 tcng_status tcng_circuit_get_mode(const tcng_circuit* c, int32_t dtype, int32_t* mode);
-/* Rounds: a complex64 tiled pass (TCNG_MODE_TILED, and the tiled candidates
- * of the autotuner) whose gates are all RY, RZ and CNOT runs as fixed rounds
- * of rotations on 5 register bits per phase, with each phase's CNOTs applied
+/* Rounds: a tiled pass (TCNG_MODE_TILED, and the tiled candidates of the
+ * autotuner; complex64 or complex128) whose gates are all RY, RZ and CNOT
+ * runs as fixed rounds of rotations on the tiling's register bits (reg_bits
+ * forward, reg_bits_rev reverse) per phase, with each phase's CNOTs applied
  * as a permutation of the tile's local index; one whose gates are all fSim
  * and Hadamard runs as fixed rounds of fSim gates on register-bit pairs (the
  * paper's operator fusion of the "Foundations Recap" section, done on the
@@ -347,6 +348,23 @@ tcng_status tcng_profile_end(void);
 tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
                               int32_t dtype, int32_t* order, int32_t* pass_of, uint64_t* tile_mask,
                               int32_t* n_passes);
+
+/* Host-only inspection of the rounds of a tiled plan (operator fusion of
+ * Sec. "Foundations Recap" on the vector units; no device is touched), for
+ * the tiling tile_bits (9..13), reg_bits (forward) and reg_bits_rev
+ * (reverse), each 3..5.  Outputs (host, any may be NULL):
+ *   n_round_passes  passes that run rotation or fSim rounds;
+ *   n_phases        round phases of the forward sweep;
+ *   bad_layouts     round phases (both sweeps) whose LDS layouts are not
+ *                   bijections of the tile, whose pass does not start from
+ *                   the tile load's layout, or whose reading lanes, or the
+ *                   writing lanes of the phase before, put two of 8, 16 or 32
+ *                   consecutive lanes on one bank (0 expected).
+ * Returns TCNG_E_INVALID for a tiling out of range and TCNG_E_UNSUPPORTED
+ * when the planner rejects it for this circuit. */
+tcng_status tcng_rounds_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
+                                     int32_t tile_bits, int32_t reg_bits, int32_t reg_bits_rev,
+                                     int32_t* n_round_passes, int32_t* n_phases, int32_t* bad_layouts);
 
 /* Graph capture of one evaluation: the trace-once, run-many JIT paradigm
  * (Sec. "Foundations Recap", JIT paragraph) done as a HIP graph:

@@ -22,7 +22,8 @@ from ._lib import (TCNG_C64, TCNG_C128, TCNG_MODE_AUTO, TCNG_MODE_FUSED, TCNG_MO
                    TcngError, TcngGate, TcngState, check, lib)
 
 __all__ = ["expect_grad_multi", "Multi", "expect_grad_noalloc", "autotune", "plan_inspect", "Circuit", "PauliSum", "state_init", "apply_gate", "run_circuit", "expect_pauli", "expect_grad",
-           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "Graph", "mipt_run",
+           "TcngEnergy", "new_state", "TcngError", "MODES", "fused_plan_inspect", "rounds_plan_inspect", "Graph",
+           "mipt_run",
            "apply_pauli", "pauli_coo", "shadow_layer", "shadow_snapshots", "qml_step"]
 
 MODES = {"tiled": TCNG_MODE_TILED, "plain": TCNG_MODE_PLAIN, "fused": TCNG_MODE_FUSED, "fused5": TCNG_MODE_FUSED5,
@@ -537,6 +538,17 @@ def fused_plan_inspect(n, gates, n_params, block_bits=4):
                                         block_of.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npass),
                                         ctypes.byref(nblk), ctypes.byref(bad)))
     return order[:G], pass_of[:G], block_of[:G], npass.value, nblk.value, bad.value
+
+
+def rounds_plan_inspect(n, gates, n_params, tiling=(13, 5, 4)):
+    """Host-only view of the rounds of the tiled plan for tiling (tile bits,
+    register bits forward, reverse): (n_round_passes, n_phases, bad_layouts)."""
+    g = np.ascontiguousarray(np.asarray(gates, dtype=np.int32).reshape(-1, 6))
+    rp, nph, bad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    m, rb, rbr = (int(x) for x in tiling)
+    check(lib().tcng_rounds_plan_inspect(int(n), g.ctypes.data_as(ctypes.c_void_p), g.shape[0], int(n_params), m, rb,
+                                         rbr, ctypes.byref(rp), ctypes.byref(nph), ctypes.byref(bad)))
+    return rp.value, nph.value, bad.value
 
 
 def mipt_run(step: Circuit, mats: torch.Tensor, psi: torch.Tensor, u: torch.Tensor, p: float, want_margin=False,

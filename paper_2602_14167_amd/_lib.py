@@ -22,7 +22,7 @@ EXPORTS = [
     "tcng_last_error", "tcng_version", "tcng_state_init", "tcng_apply_gate", "tcng_circuit_create",
     "tcng_circuit_destroy", "tcng_circuit_num_passes", "tcng_pauli_sum_create", "tcng_pauli_sum_destroy",
     "tcng_workspace_size", "tcng_run_circuit", "tcng_expect_pauli", "tcng_expect_grad", "tcng_plan_inspect",
-    "tcng_fused_plan_inspect", "tcng_graph_create", "tcng_graph_launch", "tcng_graph_destroy",
+    "tcng_fused_plan_inspect", "tcng_rounds_plan_inspect", "tcng_graph_create", "tcng_graph_launch", "tcng_graph_destroy",
     "tcng_profile_begin", "tcng_profile_query", "tcng_profile_end", "tcng_circuit_configure",
     "tcng_circuit_get_config", "tcng_autotune", "tcng_workspace_size_multi", "tcng_expect_grad_multi",
     "tcng_mipt_workspace_size", "tcng_mipt_run", "tcng_apply_pauli", "tcng_pauli_coo_info", "tcng_pauli_coo",
@@ -98,6 +98,8 @@ def lib():
     L.tcng_graph_destroy.argtypes = [P]
     L.tcng_fused_plan_inspect.argtypes = [i32, P, i32, i32, i32, P, P, P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+    L.tcng_rounds_plan_inspect.argtypes = [i32, P, i32, i32, i32, i32, i32, ctypes.POINTER(i32),
+                                           ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.tcng_apply_pauli.argtypes = [PS, P, PS, P, i32, P, sz, P]
     L.tcng_pauli_coo_info.argtypes = [P, ctypes.POINTER(i32)]
     L.tcng_pauli_coo.argtypes = [P, i64, i64, P, P, P, P]

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtcng.so")
-SOURCES = ["api.cpp", "plan.cpp", "kern_plain.hip", "kern_tile.hip", "kern_pauli.hip", "kern_fused.hip",
+SOURCES = ["api.cpp", "plan.cpp", "plan_check.cpp", "kern_plain.hip", "kern_tile.hip", "kern_pauli.hip", "kern_fused.hip",
            "kern_mipt.hip", "kern_shadow.hip", "kern_qml.hip"]
 ARCH = os.environ.get("TCNG_OFFLOAD_ARCH", "gfx950")
 

@@ -16,6 +16,7 @@
 #include "../../include/tcng.h"
 #include "kernels.h"
 #include "plan.h"
+#include "plan_check.h"
 
 using namespace tcng;
 
@@ -2334,6 +2335,38 @@ tcng_status tcng_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t 
             }
     }
     if (n_passes) *n_passes = int32_t(P.passes.size());
+    return ok();
+}
+
+tcng_status tcng_rounds_plan_inspect(int32_t n_qubits, const tcng_gate* gates, int32_t n_gates, int32_t n_params,
+                                     int32_t tile_bits, int32_t reg_bits, int32_t reg_bits_rev,
+                                     int32_t* n_round_passes, int32_t* n_phases, int32_t* bad_layouts) {
+    if (n_qubits < 1 || n_qubits > MAX_QUBITS) return fail(TCNG_E_UNSUPPORTED, "n_qubits out of range 1..34");
+    if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(TCNG_E_INVALID, "bad gate list");
+    for (int i = 0; i < n_gates; ++i) {
+        const tcng_gate& g = gates[i];
+        if (g.kind < 0 || g.kind >= K_COUNT || g.q0 < 0 || g.q0 >= n_qubits ||
+            (kind_arity(g.kind) == 2 && (g.q1 < 0 || g.q1 >= n_qubits || g.q1 == g.q0)))
+            return fail(TCNG_E_INVALID, "gate " + std::to_string(i) + ": bad kind or qubits");
+        const int np = kind_nparams(g.kind);
+        if ((np >= 1 && (g.p0 < 0 || g.p0 >= n_params)) || (np >= 2 && (g.p1 < 0 || g.p1 >= n_params)))
+            return fail(TCNG_E_INVALID, "gate " + std::to_string(i) + ": parameter index out of range");
+    }
+    if (tile_bits < 9 || tile_bits > 13 || reg_bits < 3 || reg_bits > 5 || reg_bits_rev < 3 || reg_bits_rev > 5)
+        return fail(TCNG_E_INVALID, "tiling out of range (tile bits 9..13, register bits 3..5)");
+    CircuitPlan P;
+    std::vector<tcng_gate> g(gates, gates + n_gates);
+    TileConfig cfg = tile_config(TCNG_C64);
+    cfg.m_max = tile_bits;
+    cfg.rb = reg_bits;
+    cfg.rb_rev = reg_bits_rev;
+    const std::string why = plan_circuit(n_qubits, g, n_params, cfg, P);
+    if (!why.empty()) return fail(TCNG_E_UNSUPPORTED, "planner: " + why);
+    int32_t rp = 0;
+    for (const QPass& Q : P.qpasses) rp += Q.kind != QK_GENERIC;
+    if (n_round_passes) *n_round_passes = rp;
+    if (n_phases) *n_phases = int32_t(P.qphases.size());
+    if (bad_layouts) *bad_layouts = check_rounds_layouts(P);
     return ok();
 }
 

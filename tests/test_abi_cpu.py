@@ -192,3 +192,43 @@ def test_fused_planner_rejects_small_tiles(P):
         P.fused_plan_inspect(11, gates, 1, 5)     # 5-qubit blocks need full 12-bit tiles
     with pytest.raises(P.TcngError):
         P.fused_plan_inspect(12, gates, 1, 6)
+
+
+def _ry_rz_cnot(n, n_gates, rng):
+    g, npar = [], 0
+    for _ in range(n_gates):
+        k = rng.integers(3)
+        if k == 2:
+            a, b = rng.choice(n, size=2, replace=False)
+            g.append(W.gate(W.CNOT, int(a), int(b)))
+        else:
+            g.append(W.gate(W.RY if k == 0 else W.RZ, int(rng.integers(n)), p0=npar))
+            npar += 1
+    return W.as_gate_array(g), npar
+
+
+@pytest.mark.parametrize("tiling", [(13, 5, 4), (13, 5, 5), (13, 4, 4), (12, 4, 3), (12, 4, 4), (11, 5, 4)])
+def test_rounds_planner_layouts(P, tiling):
+    """The LDS layouts between round phases: bijections of the tile, the tile
+    load's layout first, and at every inner phase boundary 8, 16 and 32
+    consecutive lanes of the reading phase, and of the writing phase through
+    its CNOT permutation, on distinct banks (rotation rounds on the HEA and
+    random RY/RZ/CNOT circuits, fSim rounds on the brick wall)."""
+    c = W.cfg2()
+    rp, nph, bad = P.rounds_plan_inspect(28, c["gates"], c["n_params"], tiling)
+    assert rp > 0 and nph > rp and bad == 0
+    f = W.cfg5()
+    rp, nph, bad = P.rounds_plan_inspect(32, f["gates"], f["n_params"], tiling)
+    assert rp > 0 and bad == 0
+    r = np.random.default_rng(70 + tiling[0] + tiling[2])
+    for n in (11, 14, 20):
+        gates, npar = _ry_rz_cnot(n, 300, r)
+        rp, nph, bad = P.rounds_plan_inspect(n, gates, npar, tiling)
+        assert rp > 0 and bad == 0, (n, rp, bad)
+
+
+def test_rounds_planner_rejects_bad_tilings(P):
+    c = W.cfg2(n=14, layers=2)
+    for tiling in ((14, 5, 4), (13, 6, 4), (13, 5, 2), (8, 4, 4)):
+        with pytest.raises(P.TcngError):
+            P.rounds_plan_inspect(14, c["gates"], c["n_params"], tiling)
