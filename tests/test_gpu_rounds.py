@@ -96,7 +96,8 @@ def test_rounds_taken_only_where_they_apply(P):
 
 @pytest.mark.parametrize("n,layers,tiling", [(11, 2, None), (13, 4, None), (16, 3, None), (16, 3, (12, 5, 5)),
                                              (18, 4, (13, 5, 4)), (18, 3, (13, 4, 4)), (16, 3, (13, 4, 5)),
-                                             (12, 3, (12, 4, 4)), (20, 2, None)])
+                                             (12, 3, (12, 4, 4)), (20, 2, None), (17, 3, (13, 5, 5)),
+                                             (15, 3, (12, 5, 4)), (15, 3, (12, 4, 5))])
 def test_rounds_hea(P, oracle_mod, n, layers, tiling):
     w = W.cfg2(n=n, layers=layers)
     r = np.random.default_rng(100 + n)
@@ -141,7 +142,8 @@ def fsim_h_circuit(n, n_gates, rng, nearest=False):
 
 @pytest.mark.parametrize("rows,cols,depth,tiling", [(3, 4, 8, None), (2, 7, 10, None), (4, 4, 12, None),
                                                     (4, 4, 12, (13, 4, 4)), (3, 6, 10, (13, 5, 4)),
-                                                    (3, 6, 10, (12, 5, 5)), (4, 5, 6, (12, 4, 4))])
+                                                    (3, 6, 10, (12, 5, 5)), (4, 5, 6, (12, 4, 4)),
+                                                    (4, 4, 12, (13, 5, 5)), (3, 5, 10, (12, 4, 5))])
 def test_fsim_rounds_brickwork(P, oracle_mod, rows, cols, depth, tiling):
     """The fSim brick-wall workload (Hadamard layer, depth-d fSim brick wall,
     2D TFIM) on small lattices."""
@@ -196,15 +198,16 @@ def test_rounds_mixed_with_generic_passes(P, oracle_mod, n):
 
 
 # ---------------------------------------------------------------------------
-# complex128 rounds (4 register bits in both sweeps, 12-bit tiles)
+# complex128 rounds (12- or 11-bit tiles, 3 or 4 register bits per sweep)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n,layers", [(11, 2), (13, 3), (16, 3)])
-def test_rounds_hea_c128(P, oracle_mod, n, layers):
+@pytest.mark.parametrize("n,layers,tiling", [(11, 2, None), (13, 3, None), (16, 3, None), (16, 3, (12, 4, 4)),
+                                             (15, 3, (11, 4, 4)), (14, 3, (12, 3, 3)), (14, 3, (11, 3, 4))])
+def test_rounds_hea_c128(P, oracle_mod, n, layers, tiling):
     w = W.cfg2(n=n, layers=layers)
     r = np.random.default_rng(500 + n)
     pb = np.stack([w["params"], r.uniform(0, 2 * np.pi, w["n_params"])])
     init = W.random_state(n, r)
-    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, None,
+    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, tiling,
           f"hea L={layers}", "c128")
 
 
@@ -218,12 +221,13 @@ def test_rounds_random_ry_rz_cnot_c128(P, oracle_mod, n, n_gates, seed):
     check(P, oracle_mod, n, gates, npar, codes, coeffs, pb, init, None, f"random seed={seed}", "c128")
 
 
-@pytest.mark.parametrize("rows,cols,depth", [(3, 4, 8), (4, 4, 10)])
-def test_fsim_rounds_c128(P, oracle_mod, rows, cols, depth):
+@pytest.mark.parametrize("rows,cols,depth,tiling", [(3, 4, 8, None), (4, 4, 10, None), (4, 4, 10, (12, 4, 4)),
+                                                    (3, 5, 8, (11, 3, 4))])
+def test_fsim_rounds_c128(P, oracle_mod, rows, cols, depth, tiling):
     w = W.cfg5(rows=rows, cols=cols, depth=depth)
     n = w["n"]
     r = np.random.default_rng(700 + n)
     pb = np.stack([w["params"], r.uniform(0, 2 * np.pi, w["n_params"])])
     init = W.random_state(n, r)
-    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, None,
+    check(P, oracle_mod, n, w["gates"], w["n_params"], w["codes"], w["coeffs"], pb, init, tiling,
           f"fsim {rows}x{cols} d={depth}", "c128")
